@@ -1,0 +1,726 @@
+/*
+ * pic_oracle.c -- plain FP64 CPU oracle of the PIC-MCC/PPPM step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see pic_oracle.h).  Written for a reader who
+ * checks it against the paper by eye: no blocking, no fusion, no reordering
+ * beyond what the method states.  Loops over particles use OpenMP only where
+ * the particles are independent of each other; every reduction is serial or
+ * integer, so results do not depend on the thread count.
+ */
+#include "pic_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* CODATA 2018 values */
+#define O_ECHARGE 1.602176634e-19
+#define O_EPS0    8.8541878128e-12
+#define O_KB      1.380649e-23
+#define O_ME      9.1093837015e-31
+#define O_AMU     1.66053906660e-27
+#define O_MAR     (39.948 * O_AMU)
+#define O_PI      3.14159265358979323846
+
+/* Philox counter word 2: what a draw is for */
+enum { PUR_INIT_POS = 1, PUR_INIT_VEL = 2, PUR_COLL = 3, PUR_NEUTRAL = 4 };
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32  */
+/* multiplies with the published multipliers; the key is bumped by the Weyl   */
+/* constants between rounds.                                                  */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(prod1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)prod1;
+    uint32_t y2 = (uint32_t)(prod0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)prod0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static void draw(const orc_config* c, uint32_t id, uint32_t step, uint32_t purpose,
+                 uint32_t species, uint32_t out[4])
+{
+  uint32_t ctr[4] = {id, step, purpose, species};
+  uint32_t key[2] = {(uint32_t)(c->seed & 0xffffffffu), (uint32_t)(c->seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+/* uniform on (0,1): (word + 1/2) 2^-32 */
+static double unif_open(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+/* two standard normals by Box-Muller from two words (cosine branch first) */
+static void box_muller(uint32_t wa, uint32_t wb, double* n0, double* n1)
+{
+  double ua = unif_open(wa), ub = unif_open(wb);
+  double r = sqrt(-2.0 * log(ua));
+  double th = 2.0 * O_PI * ub;
+  *n0 = r * cos(th);
+  *n1 = r * sin(th);
+}
+
+/* ------------------------------------------------------------------------ */
+/* derived constants                                                          */
+/* ------------------------------------------------------------------------ */
+int orc_derive(const orc_config* c, orc_derived* d)
+{
+  if (c->ppc_e <= 0 || c->ppc_e != c->ppc_i) return -1;
+  /* one super-particle weight for both species (Sec. III: super-particles) */
+  d->w = c->n0 * c->dx * c->dx * c->dx / (double)c->ppc_e;
+  d->Qp = llround(d->w * 4294967296.0);
+  /* neutral reservoir density from the gas pressure (ideal gas) */
+  d->n_gas = c->p_gas / (O_KB * c->T_gas);
+  d->q[0] = -O_ECHARGE;
+  d->q[1] = +O_ECHARGE;
+  d->m[0] = O_ME;
+  d->m[1] = O_MAR;
+  d->vth[0] = sqrt(c->Te_eV * O_ECHARGE / O_ME);
+  d->vth[1] = sqrt(c->Ti_eV * O_ECHARGE / O_MAR);
+  double sigma[2] = {c->sigma_e, c->sigma_i};
+  for (int s = 0; s < 2; ++s) {
+    d->g_cap[s] = sqrt(2.0 * c->E_cap_eV * O_ECHARGE / d->m[s]);
+    double nu_max = d->n_gas * sigma[s] * d->g_cap[s];
+    d->P_null[s] = -expm1(-nu_max * c->dt);
+    d->T_null[s] = (uint64_t)floor(d->P_null[s] * 4294967296.0);
+  }
+  d->vth_gas = sqrt(O_KB * c->T_gas / O_MAR);
+  return 0;
+}
+
+double orc_rf_voltage(const orc_config* c, uint32_t k)
+{
+  double t = (double)k * c->dt;
+  return c->V_dc + c->V_rf * sin(2.0 * O_PI * c->f_rf * t);
+}
+
+int64_t orc_n_nodes(const orc_config* c)
+{
+  return (int64_t)c->nx * c->ny * (c->nz + 1);
+}
+
+static int64_t node_index(const orc_config* c, int i, int j, int k)
+{
+  return (int64_t)i + (int64_t)c->nx * ((int64_t)j + (int64_t)c->ny * k);
+}
+
+static int wrap_index(int i, int n) { return ((i % n) + n) % n; }
+
+/* ------------------------------------------------------------------------ */
+/* loading: exactly ppc particles per cell, uniform offsets, Maxwellian v     */
+/* taken as v_{-1/2}                                                          */
+/* ------------------------------------------------------------------------ */
+int orc_init_particles(const orc_config* c, orc_state* s)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return -1;
+  int64_t ncell = (int64_t)c->nx * c->ny * c->nz;
+  for (int sp = 0; sp < 2; ++sp) {
+    int ppc = sp == 0 ? c->ppc_e : c->ppc_i;
+    if (s->n[sp] != ncell * ppc) return -2;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < s->n[sp]; ++p) {
+      int64_t cell = p / ppc;
+      int i = (int)(cell % c->nx);
+      int j = (int)((cell / c->nx) % c->ny);
+      int k = (int)(cell / ((int64_t)c->nx * c->ny));
+      uint32_t r[4];
+      draw(c, (uint32_t)p, 0, PUR_INIT_POS, (uint32_t)sp, r);
+      const double q24 = 1.0 / 16777216.0;
+      s->pos[sp][3 * p + 0] = (double)i + (double)(r[0] >> 8) * q24;
+      s->pos[sp][3 * p + 1] = (double)j + (double)(r[1] >> 8) * q24;
+      s->pos[sp][3 * p + 2] = (double)k + (double)(r[2] >> 8) * q24;
+      draw(c, (uint32_t)p, 0, PUR_INIT_VEL, (uint32_t)sp, r);
+      double n0, n1, n2, unused;
+      box_muller(r[0], r[1], &n0, &n1);
+      box_muller(r[2], r[3], &n2, &unused);
+      s->vel[sp][3 * p + 0] = d.vth[sp] * n0;
+      s->vel[sp][3 * p + 1] = d.vth[sp] * n1;
+      s->vel[sp][3 * p + 2] = d.vth[sp] * n2;
+      s->id[sp][p] = (uint32_t)p;
+      s->alive[sp][p] = 1;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* cloud-in-cell: the 8 corner nodes of the particle's cell, each weighted by */
+/* the product of the three 1-D linear weights (Sec. III, box-like shape)     */
+/* ------------------------------------------------------------------------ */
+typedef struct { int64_t node[8]; double w[8]; } cic8;
+
+static cic8 cic_weights(const orc_config* c, double X, double Y, double Z)
+{
+  cic8 r;
+  int i0 = (int)floor(X), j0 = (int)floor(Y), k0 = (int)floor(Z);
+  double fx = X - i0, fy = Y - j0, fz = Z - k0;
+  int t = 0;
+  for (int cc = 0; cc < 2; ++cc)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        double wx = a ? fx : 1.0 - fx;
+        double wy = b ? fy : 1.0 - fy;
+        double wz = cc ? fz : 1.0 - fz;
+        r.node[t] = node_index(c, wrap_index(i0 + a, c->nx), wrap_index(j0 + b, c->ny), k0 + cc);
+        r.w[t] = wx * wy * wz;
+        ++t;
+      }
+  return r;
+}
+
+/* grain charge in coulomb, taken at the start of a step */
+static double grain_charge(const orc_config* c, const orc_derived* d, const orc_state* s, int g)
+{
+  if (c->flags & ORC_FROZEN_Q) return c->Q_frozen_e * O_ECHARGE;
+  int64_t net = s->grain_count[2 * g + 1] - s->grain_count[2 * g + 0];
+  return (double)net * d->w * O_ECHARGE;
+}
+
+int orc_deposit(const orc_config* c, const orc_state* s, double* rho)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return -1;
+  int64_t nn = orc_n_nodes(c);
+  memset(rho, 0, sizeof(double) * nn);
+  double vol = c->dx * c->dx * c->dx;
+  for (int sp = 0; sp < 2; ++sp) {
+    double qw = d.q[sp] * d.w;
+    for (int64_t p = 0; p < s->n[sp]; ++p) {
+      if (!s->alive[sp][p]) continue;
+      const double* x = &s->pos[sp][3 * p];
+      cic8 W = cic_weights(c, x[0], x[1], x[2]);
+      for (int t = 0; t < 8; ++t) rho[W.node[t]] += qw * W.w[t];
+    }
+  }
+  /* grain charges act on the mesh through the same assignment */
+  for (int g = 0; g < c->n_grains; ++g) {
+    const double* xg = &c->grain_pos[3 * g];
+    double Q = grain_charge(c, &d, s, g);
+    cic8 W = cic_weights(c, xg[0], xg[1], xg[2]);
+    for (int t = 0; t < 8; ++t) rho[W.node[t]] += Q * W.w[t];
+  }
+  for (int64_t n = 0; n < nn; ++n) rho[n] /= vol;
+  return 0;
+}
+
+/* Fixed-point CIC: the macro charge Qp (2^-32 e) is split along x, then each */
+/* half along y, then each quarter along z, by q1 = (Q * f24) >> 24 and        */
+/* q0 = Q - q1, where f24 = floor(offset * 2^24).  The 8 parts sum to Qp.      */
+static void split_fixed(int64_t Q, double fx, double fy, double fz, int64_t part[8])
+{
+  int64_t qx = (int64_t)floor(fx * 16777216.0);
+  int64_t qy = (int64_t)floor(fy * 16777216.0);
+  int64_t qz = (int64_t)floor(fz * 16777216.0);
+  int64_t ax[2], axy[2][2];
+  ax[1] = (Q * qx) >> 24;
+  ax[0] = Q - ax[1];
+  for (int a = 0; a < 2; ++a) {
+    axy[a][1] = (ax[a] * qy) >> 24;
+    axy[a][0] = ax[a] - axy[a][1];
+  }
+  int t = 0;
+  for (int cc = 0; cc < 2; ++cc)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        int64_t z1 = (axy[a][b] * qz) >> 24;
+        part[t++] = cc ? z1 : axy[a][b] - z1;
+      }
+}
+
+int orc_deposit_fixed(const orc_config* c, const orc_state* s, int64_t* rho_fixed)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return -1;
+  if (c->flags & ORC_FROZEN_Q) return -3;
+  int64_t nn = orc_n_nodes(c);
+  memset(rho_fixed, 0, sizeof(int64_t) * nn);
+  for (int sp = 0; sp < 2; ++sp) {
+    int64_t sign = sp == 0 ? -1 : 1;
+    for (int64_t p = 0; p < s->n[sp]; ++p) {
+      if (!s->alive[sp][p]) continue;
+      const double* x = &s->pos[sp][3 * p];
+      cic8 W = cic_weights(c, x[0], x[1], x[2]);
+      int64_t part[8];
+      split_fixed(d.Qp, x[0] - floor(x[0]), x[1] - floor(x[1]), x[2] - floor(x[2]), part);
+      for (int t = 0; t < 8; ++t) rho_fixed[W.node[t]] += sign * part[t];
+    }
+  }
+  for (int g = 0; g < c->n_grains; ++g) {
+    const double* xg = &c->grain_pos[3 * g];
+    int64_t net = s->grain_count[2 * g + 1] - s->grain_count[2 * g + 0];
+    cic8 W = cic_weights(c, xg[0], xg[1], xg[2]);
+    int64_t part[8];
+    split_fixed(d.Qp, xg[0] - floor(xg[0]), xg[1] - floor(xg[1]), xg[2] - floor(xg[2]), part);
+    for (int t = 0; t < 8; ++t) rho_fixed[W.node[t]] += net * part[t];
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Poisson, Eq. (3), in the 7-point finite-difference form on the nodes:      */
+/*   sum of 6 neighbours - 6 phi = -dx^2 rho / eps0  on interior z nodes,     */
+/*   periodic in x,y, phi = 0 on the grounded wall, phi = V on the rf wall.   */
+/* phi = V k / nz + psi (the linear lift is discrete-harmonic); psi is found  */
+/* by a plain DFT in x and y and, for every Fourier mode, a tridiagonal solve */
+/* along z.                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* plain O(n^2) DFT of `count` lines of length n: out[m] = sum_j in[j] e^{sign 2 pi i m j / n} */
+static void dft_lines(double complex* buf, int n, int64_t count, int64_t elem_stride,
+                      int64_t line_stride, int sign, double complex* scratch)
+{
+  double complex* tw = (double complex*)malloc(sizeof(double complex) * n);
+  for (int t = 0; t < n; ++t) {
+    double a = 2.0 * O_PI * (double)t / (double)n;
+    tw[t] = cos(a) + sign * sin(a) * I;
+  }
+  for (int64_t l = 0; l < count; ++l) {
+    double complex* line = buf + l * line_stride;
+    for (int m = 0; m < n; ++m) {
+      double complex acc = 0;
+      for (int j = 0; j < n; ++j) acc += line[j * elem_stride] * tw[((int64_t)m * j) % n];
+      scratch[m] = acc;
+    }
+    for (int m = 0; m < n; ++m) line[m * elem_stride] = scratch[m];
+  }
+  free(tw);
+}
+
+/* forward (sign -1) or inverse (sign +1, unnormalised) 2-D DFT of one plane */
+static void dft2_plane(double complex* plane, int nx, int ny, int sign, double complex* scratch)
+{
+  dft_lines(plane, nx, ny, 1, nx, sign, scratch);   /* rows: along x */
+  dft_lines(plane, ny, nx, nx, 1, sign, scratch);   /* columns: along y */
+}
+
+/* tridiagonal with unit off-diagonals and diagonal `diag`, Dirichlet zeros at both ends */
+static void thomas_unit(double diag, double complex* d, int K, double* cp)
+{
+  /* forward elimination */
+  cp[0] = 1.0 / diag;
+  d[0] = d[0] / diag;
+  for (int k = 1; k < K; ++k) {
+    double den = diag - cp[k - 1];
+    cp[k] = 1.0 / den;
+    d[k] = (d[k] - d[k - 1]) / den;
+  }
+  /* back substitution */
+  for (int k = K - 2; k >= 0; --k) d[k] = d[k] - cp[k] * d[k + 1];
+}
+
+int orc_poisson(const orc_config* c, const double* rho, double V, double* phi)
+{
+  int nx = c->nx, ny = c->ny, nz = c->nz;
+  int64_t plane = (int64_t)nx * ny;
+  int K = nz - 1; /* interior planes k = 1 .. nz-1 */
+  if (K < 1) return -1;
+  double complex* hat = (double complex*)malloc(sizeof(double complex) * plane * K);
+  if (!hat) return -2;
+  double scale = -c->dx * c->dx / O_EPS0;
+#pragma omp parallel
+  {
+    double complex* scratch = (double complex*)malloc(sizeof(double complex) * (nx > ny ? nx : ny));
+#pragma omp for schedule(static)
+    for (int k = 1; k <= K; ++k) {
+      double complex* h = hat + (int64_t)(k - 1) * plane;
+      for (int64_t n = 0; n < plane; ++n) h[n] = scale * rho[k * plane + n];
+      dft2_plane(h, nx, ny, -1, scratch);
+    }
+    free(scratch);
+  }
+  /* one tridiagonal system per mode (m, n) */
+#pragma omp parallel
+  {
+    double complex* col = (double complex*)malloc(sizeof(double complex) * K);
+    double* cp = (double*)malloc(sizeof(double) * K);
+#pragma omp for schedule(static)
+    for (int64_t mn = 0; mn < plane; ++mn) {
+      int m = (int)(mn % nx), n = (int)(mn / nx);
+      double sx = sin(O_PI * m / nx), sy = sin(O_PI * n / ny);
+      double diag = -(2.0 + 4.0 * (sx * sx + sy * sy));
+      for (int k = 0; k < K; ++k) col[k] = hat[(int64_t)k * plane + mn];
+      thomas_unit(diag, col, K, cp);
+      for (int k = 0; k < K; ++k) hat[(int64_t)k * plane + mn] = col[k];
+    }
+    free(col);
+    free(cp);
+  }
+#pragma omp parallel
+  {
+    double complex* scratch = (double complex*)malloc(sizeof(double complex) * (nx > ny ? nx : ny));
+#pragma omp for schedule(static)
+    for (int k = 1; k <= K; ++k) {
+      double complex* h = hat + (int64_t)(k - 1) * plane;
+      dft2_plane(h, nx, ny, +1, scratch);
+      for (int64_t n = 0; n < plane; ++n)
+        phi[k * plane + n] = creal(h[n]) / (double)plane + V * (double)k / (double)nz;
+    }
+    free(scratch);
+  }
+  for (int64_t n = 0; n < plane; ++n) {
+    phi[n] = 0.0;
+    phi[(int64_t)nz * plane + n] = V;
+  }
+  free(hat);
+  return 0;
+}
+
+/* E = -grad phi, Eq. (4): central differences; one-sided along z on the two  */
+/* electrode planes                                                            */
+int orc_efield(const orc_config* c, const double* phi, double* E)
+{
+  int nx = c->nx, ny = c->ny, nz = c->nz;
+  int64_t nn = orc_n_nodes(c);
+  double* Ex = E;
+  double* Ey = E + nn;
+  double* Ez = E + 2 * nn;
+  for (int k = 0; k <= nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        int64_t n = node_index(c, i, j, k);
+        Ex[n] = -(phi[node_index(c, wrap_index(i + 1, nx), j, k)] -
+                  phi[node_index(c, wrap_index(i - 1, nx), j, k)]) / (2.0 * c->dx);
+        Ey[n] = -(phi[node_index(c, i, wrap_index(j + 1, ny), k)] -
+                  phi[node_index(c, i, wrap_index(j - 1, ny), k)]) / (2.0 * c->dx);
+        if (k == 0)
+          Ez[n] = -(phi[node_index(c, i, j, 1)] - phi[n]) / c->dx;
+        else if (k == nz)
+          Ez[n] = -(phi[n] - phi[node_index(c, i, j, nz - 1)]) / c->dx;
+        else
+          Ez[n] = -(phi[node_index(c, i, j, k + 1)] - phi[node_index(c, i, j, k - 1)]) / (2.0 * c->dx);
+      }
+  return 0;
+}
+
+int orc_fields(const orc_config* c, const orc_state* s, double* rho, int64_t* rho_fixed,
+               double* phi, double* E)
+{
+  int rc;
+  if (rho_fixed) {
+    if ((rc = orc_deposit_fixed(c, s, rho_fixed))) return rc;
+    double conv = O_ECHARGE / 4294967296.0 / (c->dx * c->dx * c->dx);
+    for (int64_t n = 0; n < orc_n_nodes(c); ++n) rho[n] = (double)rho_fixed[n] * conv;
+  } else if ((rc = orc_deposit(c, s, rho))) {
+    return rc;
+  }
+  if ((rc = orc_poisson(c, rho, orc_rf_voltage(c, s->step), phi))) return rc;
+  return orc_efield(c, phi, E);
+}
+
+/* ------------------------------------------------------------------------ */
+/* MD region: the cube of (2c+1)^3 cells centred on the grain's cell,         */
+/* periodic in x,y (c = 1 is the grain's cell plus its direct neighbours)     */
+/* ------------------------------------------------------------------------ */
+static int periodic_delta(int a, int b, int n)
+{
+  int d = wrap_index(a - b, n);
+  if (d > n / 2) d -= n;
+  return d;
+}
+
+int orc_md_grains(const orc_config* c, int i, int j, int k, int* out, int cap)
+{
+  int cnt = 0;
+  for (int g = 0; g < c->n_grains; ++g) {
+    const double* xg = &c->grain_pos[3 * g];
+    int gi = (int)floor(xg[0]), gj = (int)floor(xg[1]), gk = (int)floor(xg[2]);
+    if (abs(periodic_delta(i, gi, c->nx)) <= c->cutoff &&
+        abs(periodic_delta(j, gj, c->ny)) <= c->cutoff && abs(k - gk) <= c->cutoff) {
+      if (cnt < cap) out[cnt] = g;
+      ++cnt;
+    }
+  }
+  return cnt;
+}
+
+static int cube_side(const orc_config* c) { return 2 * c->cutoff + 2; }
+
+/* E_PIC^dust of a unit (1 C) grain charge: the same deposit, solver and      */
+/* stencil as the plasma field, kept on the nodes of the grain's MD cube      */
+int orc_unit_fields(const orc_config* c, double* U)
+{
+  int64_t nn = orc_n_nodes(c);
+  int side = cube_side(c);
+  int64_t cube = (int64_t)side * side * side;
+  double* rho = (double*)malloc(sizeof(double) * nn);
+  double* phi = (double*)malloc(sizeof(double) * nn);
+  double* E = (double*)malloc(sizeof(double) * nn * 3);
+  if (!rho || !phi || !E) return -2;
+  double vol = c->dx * c->dx * c->dx;
+  int rc = 0;
+  for (int g = 0; g < c->n_grains && !rc; ++g) {
+    const double* xg = &c->grain_pos[3 * g];
+    int gi = (int)floor(xg[0]), gj = (int)floor(xg[1]), gk = (int)floor(xg[2]);
+    if (gk - c->cutoff < 0 || gk + c->cutoff + 1 > c->nz) { rc = -4; break; }
+    memset(rho, 0, sizeof(double) * nn);
+    cic8 W = cic_weights(c, xg[0], xg[1], xg[2]);
+    for (int t = 0; t < 8; ++t) rho[W.node[t]] += W.w[t] / vol;
+    if ((rc = orc_poisson(c, rho, 0.0, phi))) break;
+    orc_efield(c, phi, E);
+    for (int comp = 0; comp < 3; ++comp)
+      for (int cz = 0; cz < side; ++cz)
+        for (int cy = 0; cy < side; ++cy)
+          for (int cx = 0; cx < side; ++cx) {
+            int64_t n = node_index(c, wrap_index(gi - c->cutoff + cx, c->nx),
+                                   wrap_index(gj - c->cutoff + cy, c->ny), gk - c->cutoff + cz);
+            U[(int64_t)g * 3 * cube + comp * cube + ((int64_t)cz * side + cy) * side + cx] =
+                E[comp * nn + n];
+          }
+  }
+  free(rho);
+  free(phi);
+  free(E);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* particle motion                                                            */
+/* ------------------------------------------------------------------------ */
+static void gather_mesh(const orc_config* c, const double* E, double X, double Y, double Z,
+                        double out[3])
+{
+  out[0] = out[1] = out[2] = 0.0;
+  if (!E) return;
+  int64_t nn = orc_n_nodes(c);
+  cic8 W = cic_weights(c, X, Y, Z);
+  for (int t = 0; t < 8; ++t)
+    for (int comp = 0; comp < 3; ++comp) out[comp] += W.w[t] * E[comp * nn + W.node[t]];
+}
+
+/* the same CIC weights applied to a grain's unit field on its cube */
+static void gather_unit(const orc_config* c, const double* U, int g, double X, double Y,
+                        double Z, double out[3])
+{
+  int side = cube_side(c);
+  int64_t cube = (int64_t)side * side * side;
+  const double* xg = &c->grain_pos[3 * g];
+  int gi = (int)floor(xg[0]), gj = (int)floor(xg[1]), gk = (int)floor(xg[2]);
+  int i0 = (int)floor(X), j0 = (int)floor(Y), k0 = (int)floor(Z);
+  double fx = X - i0, fy = Y - j0, fz = Z - k0;
+  out[0] = out[1] = out[2] = 0.0;
+  for (int cc = 0; cc < 2; ++cc)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        double w = (a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy) * (cc ? fz : 1.0 - fz);
+        int lx = wrap_index(i0 + a - (gi - c->cutoff), c->nx);
+        int ly = wrap_index(j0 + b - (gj - c->cutoff), c->ny);
+        int lz = k0 + cc - (gk - c->cutoff);
+        int64_t l = ((int64_t)lz * side + ly) * side + lx;
+        for (int comp = 0; comp < 3; ++comp) out[comp] += w * U[(int64_t)g * 3 * cube + comp * cube + l];
+      }
+}
+
+/* minimum-image separation x - x_g in cell units */
+static void separation(const orc_config* c, int g, double X, double Y, double Z, double r[3])
+{
+  const double* xg = &c->grain_pos[3 * g];
+  r[0] = X - xg[0];
+  r[1] = Y - xg[1];
+  r[2] = Z - xg[2];
+  if (r[0] > 0.5 * c->nx) r[0] -= c->nx;
+  else if (r[0] < -0.5 * c->nx) r[0] += c->nx;
+  if (r[1] > 0.5 * c->ny) r[1] -= c->ny;
+  else if (r[1] < -0.5 * c->ny) r[1] += c->ny;
+}
+
+static double wrap_coord(double X, int n)
+{
+  X = X - (double)n * floor(X / (double)n);
+  if (X >= (double)n) X -= (double)n;
+  return X;
+}
+
+enum { MV_ALIVE = 0, MV_WALL0 = 1, MV_WALL1 = 2, MV_GRAIN = 3 };
+
+static double dmin(double a, double b) { return a < b ? a : b; }
+
+/* plain PIC particle: gather, Eq. (2) kick, Eq. (1) drift, wrap, electrodes */
+static int move_plain(const orc_config* c, const double* E, double qm, double* x, double* v,
+                      double* margin)
+{
+  double Ep[3];
+  gather_mesh(c, E, x[0], x[1], x[2], Ep);
+  for (int a = 0; a < 3; ++a) v[a] += qm * Ep[a] * c->dt;
+  for (int a = 0; a < 3; ++a) x[a] += v[a] * c->dt / c->dx;
+  x[0] = wrap_coord(x[0], c->nx);
+  x[1] = wrap_coord(x[1], c->ny);
+  *margin = dmin(*margin, dmin(fabs(x[2]), fabs(x[2] - c->nz)));
+  if (x[2] < 0.0) return MV_WALL0;
+  if (x[2] >= (double)c->nz) return MV_WALL1;
+  return MV_ALIVE;
+}
+
+/* MD particle: md_sub sub-steps of dt/md_sub with the PPPM field of Eq. (5)-(6) */
+static int move_md(const orc_config* c, const double* E, const double* U, const double* Q,
+                   double qm, double* x, double* v, double* margin, int* hit_grain)
+{
+  double h = c->dt / (double)c->md_sub;
+  double a2 = c->grain_radius * c->grain_radius;
+  int G[64];
+  for (int sub = 0; sub < c->md_sub; ++sub) {
+    double Ep[3];
+    gather_mesh(c, E, x[0], x[1], x[2], Ep);
+    int nG = orc_md_grains(c, (int)floor(x[0]), (int)floor(x[1]), (int)floor(x[2]), G, 64);
+    for (int t = 0; t < nG && t < 64; ++t) {
+      int g = G[t];
+      if (Q[g] == 0.0) continue;
+      double r[3];
+      separation(c, g, x[0], x[1], x[2], r);
+      for (int a = 0; a < 3; ++a) r[a] *= c->dx;
+      double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      double inv = 1.0 / (4.0 * O_PI * O_EPS0 * r2 * sqrt(r2));
+      double Um[3] = {0.0, 0.0, 0.0};
+      if (U) gather_unit(c, U, g, x[0], x[1], x[2], Um);
+      for (int a = 0; a < 3; ++a) Ep[a] += Q[g] * (r[a] * inv - Um[a]);
+    }
+    for (int a = 0; a < 3; ++a) v[a] += qm * Ep[a] * h;
+    for (int a = 0; a < 3; ++a) x[a] += v[a] * h / c->dx;
+    x[0] = wrap_coord(x[0], c->nx);
+    x[1] = wrap_coord(x[1], c->ny);
+    *margin = dmin(*margin, dmin(fabs(x[2]), fabs(x[2] - c->nz)));
+    if (x[2] < 0.0) return MV_WALL0;
+    if (x[2] >= (double)c->nz) return MV_WALL1;
+    nG = orc_md_grains(c, (int)floor(x[0]), (int)floor(x[1]), (int)floor(x[2]), G, 64);
+    for (int t = 0; t < nG && t < 64; ++t) {
+      int g = G[t];
+      double r[3];
+      separation(c, g, x[0], x[1], x[2], r);
+      for (int a = 0; a < 3; ++a) r[a] *= c->dx;
+      double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      *margin = dmin(*margin, fabs(sqrt(r2) - c->grain_radius) / c->grain_radius);
+      if (r2 <= a2) {
+        *hit_grain = g;
+        return MV_GRAIN;
+      }
+    }
+  }
+  return MV_ALIVE;
+}
+
+/* binary collision with a neutral drawn from the reservoir, null-collision form */
+static void collide(const orc_config* c, const orc_derived* d, int sp, uint32_t id, uint32_t k,
+                    double* v, double* margin, int64_t* cap_viol, int64_t* ncoll)
+{
+  uint32_t r[4];
+  draw(c, id, k, PUR_COLL, (uint32_t)sp, r);
+  if ((uint64_t)r[0] >= d->T_null[sp]) return; /* not a candidate */
+  double vn[3] = {0.0, 0.0, 0.0};
+  if (sp == 1) {
+    uint32_t rn[4];
+    double unused;
+    draw(c, id, k, PUR_NEUTRAL, (uint32_t)sp, rn);
+    box_muller(rn[0], rn[1], &vn[0], &vn[1]);
+    box_muller(rn[2], rn[3], &vn[2], &unused);
+    for (int a = 0; a < 3; ++a) vn[a] *= d->vth_gas;
+  }
+  double gv[3] = {v[0] - vn[0], v[1] - vn[1], v[2] - vn[2]};
+  double g = sqrt(gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2]);
+  double u1 = unif_open(r[1]);
+  double ratio = g / d->g_cap[sp];
+  int accept;
+  if (ratio > 1.0) {
+#pragma omp atomic
+    cap_viol[sp] += 1;
+    accept = 1;
+  } else {
+    *margin = dmin(*margin, fabs(u1 - ratio));
+    accept = u1 < ratio;
+  }
+  if (!accept) return;
+#pragma omp atomic
+  ncoll[sp] += 1;
+  if (sp == 0) {
+    /* e-Ar elastic: isotropic in the centre-of-mass frame, neutral at rest */
+    double cost = 1.0 - 2.0 * unif_open(r[2]);
+    double sint = sqrt(fmax(0.0, 1.0 - cost * cost));
+    double ph = 2.0 * O_PI * unif_open(r[3]);
+    double nh[3] = {sint * cos(ph), sint * sin(ph), cost};
+    double mt = d->m[0] + d->m[1];
+    for (int a = 0; a < 3; ++a) v[a] = (d->m[0] / mt) * v[a] + (d->m[1] / mt) * g * nh[a];
+  } else {
+    /* Ar+-Ar charge exchange: the ion leaves with the neutral's velocity */
+    for (int a = 0; a < 3; ++a) v[a] = vn[a];
+  }
+}
+
+static int move_all(const orc_config* c, orc_state* s, const double* E, const double* U)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return -1;
+  if (c->n_grains > 64) return -5;
+  double Q[64];
+  for (int g = 0; g < c->n_grains; ++g) Q[g] = grain_charge(c, &d, s, g);
+  const double* Uuse = (c->flags & ORC_NO_MESH) ? NULL : U;
+  const double* Euse = (c->flags & ORC_NO_MESH) ? NULL : E;
+  uint32_t k = s->step;
+  for (int sp = 0; sp < 2; ++sp) {
+    double qm = d.q[sp] / d.m[sp];
+    int64_t wall[2] = {0, 0};
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : wall[:2])
+    for (int64_t p = 0; p < s->n[sp]; ++p) {
+      if (!s->alive[sp][p]) continue;
+      double* x = &s->pos[sp][3 * p];
+      double* v = &s->vel[sp][3 * p];
+      double margin = INFINITY;
+      int G[1];
+      int nG = orc_md_grains(c, (int)floor(x[0]), (int)floor(x[1]), (int)floor(x[2]), G, 1);
+      int hit = -1, st;
+      if (nG == 0)
+        st = move_plain(c, Euse, qm, x, v, &margin);
+      else
+        st = move_md(c, Euse, Uuse, Q, qm, x, v, &margin, &hit);
+      if (st == MV_WALL0 || st == MV_WALL1) {
+        wall[st - 1] += 1;
+        s->alive[sp][p] = 0;
+      } else if (st == MV_GRAIN) {
+#pragma omp atomic
+        s->grain_count[2 * hit + sp] += 1;
+        s->alive[sp][p] = 0;
+      } else if (!(c->flags & ORC_NO_MCC)) {
+        collide(c, &d, sp, s->id[sp][p], k, v, &margin, s->cap_violation, s->n_collisions);
+      }
+      if (s->margin[sp]) s->margin[sp][p] = margin;
+    }
+    s->wall_count[0][sp] += wall[0];
+    s->wall_count[1][sp] += wall[1];
+  }
+  s->step = k + 1;
+  return 0;
+}
+
+int orc_step_in_field(const orc_config* c, orc_state* s, const double* E, const double* U)
+{
+  return move_all(c, s, E, U);
+}
+
+int orc_step(const orc_config* c, orc_state* s, const double* U)
+{
+  if (c->flags & ORC_NO_MESH) return move_all(c, s, NULL, NULL);
+  int64_t nn = orc_n_nodes(c);
+  double* rho = (double*)malloc(sizeof(double) * nn);
+  double* phi = (double*)malloc(sizeof(double) * nn);
+  double* E = (double*)malloc(sizeof(double) * nn * 3);
+  int64_t* rf = (c->flags & ORC_FIXED_POINT) ? (int64_t*)malloc(sizeof(int64_t) * nn) : NULL;
+  int rc = -2;
+  if (rho && phi && E)
+    rc = orc_fields(c, s, rho, rf, phi, E);
+  if (!rc) rc = move_all(c, s, E, U);
+  free(rho);
+  free(phi);
+  free(E);
+  free(rf);
+  return rc;
+}

@@ -1,0 +1,126 @@
+/*
+ * pic_oracle.h -- plain FP64 CPU oracle of the PIC-MCC/PPPM time step of
+ * Schleede et al., "Plasma flow around and charge distribution of a dust
+ * cluster in a rf discharge" (arXiv:1801.00972).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source, header, table or constant
+ * generator with the HIP path.
+ *
+ * Every function follows the method section of the paper (Sec. III):
+ *   - super-particles, kinetic e- and Ar+, neutral Ar reservoir (Sec. III, first paragraphs)
+ *   - leapfrog push, Eq. (1)-(2)
+ *   - Poisson on cell corners, Eq. (3)-(4), CIC charge assignment and field gather
+ *   - PPPM near-grain field, Eq. (5)-(6), with dt_MD = dt/40
+ *   - perfect absorbers: electrodes and grains; grain charge in quanta of the
+ *     super-particle charge (Sec. IV.B)
+ *   - binary Monte-Carlo collisions against the neutral reservoir (Table I), in
+ *     the null-collision form with constant cross sections.
+ * Where the paper is silent, the reading taken is the one listed in the
+ * design notes of the repository (leapfrog start, step order, Philox usage,
+ * wall-node stencil, MD-region extent, ...).
+ *
+ * Units: SI, except particle positions which are in cell units (x / dx).
+ * Species index: 0 = electron, 1 = Ar+.
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* test-mode flags */
+#define ORC_NO_MESH      1  /* no deposit / Poisson: mesh field identically 0 */
+#define ORC_NO_MCC       2  /* no collisions */
+#define ORC_FIXED_POINT  4  /* CIC deposit in int64 fixed point (2^-32 e units) */
+#define ORC_FROZEN_Q     8  /* grain charges do not change when particles hit */
+
+typedef struct orc_config {
+  int32_t nx, ny, nz;        /* cells; x,y periodic, z bounded by two electrodes */
+  int32_t ppc_e, ppc_i;      /* macro-particles per cell at load */
+  int32_t n_grains;
+  int32_t cutoff;            /* MD cube half-width c, in cells */
+  int32_t md_sub;            /* sub-steps per step in the MD region (40) */
+  int32_t flags;             /* ORC_* test modes */
+  int32_t pad0;
+  double dx, dt;             /* m, s */
+  double n0;                 /* plasma density setting the macro-particle weight */
+  double Te_eV, Ti_eV;       /* load temperatures, kT in eV */
+  double p_gas, T_gas;       /* neutral reservoir: Pa, K */
+  double sigma_e, sigma_i;   /* e-Ar elastic, Ar+-Ar charge exchange, m^2 */
+  double V_dc, V_rf, f_rf;   /* phi(z=L_z, t) = V_dc + V_rf sin(2 pi f_rf t) */
+  double grain_radius;       /* m */
+  double E_cap_eV;           /* null-collision cap on the relative kinetic energy */
+  double Q_frozen_e;         /* grain charge in e when ORC_FROZEN_Q is set */
+  uint64_t seed;             /* Philox key */
+  const double* grain_pos;   /* [n_grains][3], cell units */
+} orc_config;
+
+typedef struct orc_derived {
+  double w;                  /* real particles per macro-particle */
+  int64_t Qp;                /* macro-particle charge in units of 2^-32 e */
+  double n_gas;              /* neutral density */
+  double q[2], m[2];
+  double vth[2];             /* per-component thermal speed sqrt(kT/m) at load */
+  double g_cap[2];           /* relative-speed cap of the null-collision method */
+  double P_null[2];          /* candidate probability per step */
+  uint64_t T_null[2];        /* integer candidate threshold floor(P * 2^32) */
+  double vth_gas;            /* sqrt(kB T_gas / M_Ar) */
+} orc_derived;
+
+typedef struct orc_state {
+  int64_t n[2];              /* particles per species (array lengths) */
+  double* pos[2];            /* [n][3] cell units */
+  double* vel[2];            /* [n][3] m/s, at the half step k-1/2 */
+  uint32_t* id[2];           /* Philox counter word 0 */
+  uint8_t* alive[2];         /* 1 alive, 0 removed */
+  double* margin[2];         /* nullable: smallest margin of a discrete decision */
+  int64_t* grain_count;      /* [n_grains][2] absorbed macro-particles */
+  int64_t wall_count[2][2];  /* [wall: 0 grounded z=0, 1 rf z=L_z][species] */
+  int64_t cap_violation[2];  /* relative speed above g_cap */
+  int64_t n_collisions[2];   /* accepted collisions */
+  uint32_t step;             /* k: the state holds x_k and v_{k-1/2} */
+  uint32_t pad0;
+} orc_state;
+
+/* ---- building blocks (exposed for the pins) ---- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+int  orc_derive(const orc_config* c, orc_derived* d);
+double orc_rf_voltage(const orc_config* c, uint32_t k);
+int64_t orc_n_nodes(const orc_config* c);
+
+/* particle loading: fills pos/vel/id for n = nx*ny*nz*ppc particles per species */
+int orc_init_particles(const orc_config* c, orc_state* s);
+
+/* CIC deposit of the alive particles and of the grain charges.
+ * FP64 mode: rho in C/m^3.  Fixed-point mode: rho_fixed in 2^-32 e per node. */
+int orc_deposit(const orc_config* c, const orc_state* s, double* rho);
+int orc_deposit_fixed(const orc_config* c, const orc_state* s, int64_t* rho_fixed);
+
+/* Poisson: phi on all nodes, Dirichlet phi(k=0)=0, phi(k=nz)=V */
+int orc_poisson(const orc_config* c, const double* rho, double V, double* phi);
+/* E = -grad phi; E is [3][nodes] */
+int orc_efield(const orc_config* c, const double* phi, double* E);
+/* fields at the state's step: rho (C/m^3), phi, E; rho_fixed nullable */
+int orc_fields(const orc_config* c, const orc_state* s, double* rho, int64_t* rho_fixed,
+               double* phi, double* E);
+/* unit-charge mesh field of each grain on its (2c+2)^3 node cube: [g][3][(2c+2)^3] */
+int orc_unit_fields(const orc_config* c, double* U);
+/* grains whose MD cube contains cell (i,j,k): writes indices, returns the count */
+int orc_md_grains(const orc_config* c, int i, int j, int k, int* out, int cap);
+
+/* one full time step k -> k+1 (deposit, solve, field, move, absorb, collide);
+ * U: the grains' unit fields from orc_unit_fields (nullable without grains) */
+int orc_step(const orc_config* c, orc_state* s, const double* U);
+/* move particles through a given mesh field E_k ([3][nodes], nullable = 0)
+ * without solving, then collide; grains and walls as in orc_step. */
+int orc_step_in_field(const orc_config* c, orc_state* s, const double* E, const double* U);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
