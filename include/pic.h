@@ -1,0 +1,210 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) PIC-MCC/PPPM hot path.
+ *
+ * The library advances electrons and Ar+ ions of a capacitively coupled rf
+ * argon discharge around a fixed cluster of absorbing dust grains, following
+ * the method of Schleede et al., "Plasma flow around and charge distribution
+ * of a dust cluster in a rf discharge" (arXiv:1801.00972), Sec. III:
+ *   - super-particles of one weight for both kinetic species (Sec. III);
+ *   - CIC (box-shape) charge assignment on the cell corners, Poisson's
+ *     equation Eq. (3) in 7-point finite-difference form, E = -grad phi by
+ *     finite differences, Eq. (4), and the field at the particle by the same
+ *     weights (Sec. III);
+ *   - leapfrog, Eq. (1)-(2), electric field only;
+ *   - PPPM correction near the grains, Eq. (5)-(6), with dt_MD = dt/40;
+ *   - electrodes and grains as perfect absorbers, the grain charge changing in
+ *     quanta of the super-particle charge (Sec. III end, Sec. IV.B);
+ *   - binary Monte-Carlo collisions against a neutral argon reservoir
+ *     (Table I: e-Ar elastic, Ar+-Ar charge exchange), null-collision form.
+ * Geometry: x,y periodic; z from a grounded electrode (z = 0, phi = 0) to the
+ * rf electrode (z = L_z, phi = V_dc + V_rf sin(2 pi f_rf t)) -- the paper's
+ * discharge axis y is called z here.
+ *
+ * Conventions of every call:
+ *   - returns PIC_OK (0) or a negative PIC_E* code; no exception or abort
+ *     crosses the ABI; pic_last_error() describes the last failure;
+ *   - an asynchronous device fault becomes a sticky PIC_EDEVICE;
+ *   - the context owns all device memory; callers own every buffer they pass;
+ *   - all device work is ordered on the stream given to pic_init (NULL: the
+ *     default stream); calls that return host data synchronise that stream;
+ *   - a context is not thread-safe; several contexts may coexist;
+ *   - SI units; temperatures as kT in eV; particle positions in cell units
+ *     (x / dx); node arrays are x-fastest: n = i + nx (j + ny k), k = 0..nz.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_OK        0
+#define PIC_EINVAL   -1  /* bad argument or configuration value */
+#define PIC_ECONFIG  -2  /* configuration that cannot be realised (grain placement, sizes) */
+#define PIC_ENOMEM   -3  /* device or host allocation failed */
+#define PIC_EDEVICE  -4  /* HIP runtime or kernel fault (sticky) */
+#define PIC_ENUMERIC -5  /* non-finite or out-of-range particle data */
+#define PIC_ESTATE   -6  /* call not valid in the context's state */
+
+/* arithmetic forms */
+#define PIC_FP64  0  /* FP64 positions (cell units), velocities, fields and deposit */
+#define PIC_FP32R 1  /* int32 cell + FP32 offset, FP32 velocity and field, int64
+                        fixed-point deposit (2^-32 e), FP32 Poisson solve with FP64
+                        residual refinement */
+
+/* pic_fields selection bits */
+#define PIC_PHI       1u  /* double [nodes]                     V        */
+#define PIC_E         2u  /* double [3][nodes]                  V/m      */
+#define PIC_RHO       4u  /* double [nodes]  plasma + grains    C/m^3    */
+#define PIC_RHO_FIXED 8u  /* int64  [nodes]  PIC_FP32R only     2^-32 e  */
+
+/*
+ * One replica.  Read-only; copied by pic_init.
+ *   weight w = n0 dx^3 / ppc real particles per macro-particle (both species);
+ *   phi(z = nz dx, t_k) = V_dc + V_rf sin(2 pi f_rf k dt), phi(z = 0) = 0;
+ *   grain_pos: [n_grains][3] in cell units, each at least cutoff+1 cells from
+ *   both electrodes; the MD region of a grain is the cube of (2 cutoff + 1)^3
+ *   cells centred on its cell (cutoff 1: the grain's cell and its direct
+ *   neighbours, Sec. III);  md_subcycles sub-steps of dt / md_subcycles are taken
+ *   inside it (40 in the paper);
+ *   E_cap_eV caps the relative kinetic energy used by the null-collision
+ *   method (a particle above the cap collides and is counted).
+ */
+typedef struct pic_config {
+  int32_t nx, ny, nz;
+  int32_t ppc;                 /* macro-particles per cell per species at load */
+  int32_t n_grains;
+  int32_t pp_cutoff_cells;
+  int32_t md_subcycles;
+  int32_t precision;           /* PIC_FP64 or PIC_FP32R */
+  int32_t max_refine;          /* FP32R: residual-refinement sweeps per solve (>= 1) */
+  int32_t sort_interval;       /* steps between full cell sorts of the particles (>= 1) */
+  double dx, dt;
+  double n0;
+  double Te_eV, Ti_eV;
+  double p_gas_Pa, T_gas_K;
+  double sigma_e_el, sigma_i_cx;
+  double V_dc, V_rf, f_rf;
+  double grain_radius;
+  double E_cap_eV;
+  double refine_tol;           /* FP32R: target ||b - A phi|| / ||b|| (diagnostic) */
+  uint64_t seed;               /* Philox key of the replica */
+  const double* grain_pos;     /* host pointer, [n_grains][3], cell units */
+} pic_config;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Host view of one replica's particle state (for pic_get_state/pic_set_state). */
+typedef struct pic_state_view {
+  int64_t capacity[2];   /* get: length of the arrays below per species */
+  int64_t n[2];          /* get: particles written; set: particles given */
+  double* pos[2];        /* [n][3] cell units, x,y in [0,n), z in [0,nz) */
+  double* vel[2];        /* [n][3] m/s at the half step k - 1/2 */
+  uint32_t* id[2];       /* Philox particle ids, unique per species */
+  int64_t* grain_count;  /* [n_grains][2] absorbed (electrons, ions); nullable */
+  int64_t wall_count[2][2]; /* [wall 0: z=0, 1: z=L_z][species] */
+  uint32_t step;         /* k */
+  uint32_t pad0;
+} pic_state_view;
+
+typedef struct pic_counters {
+  int64_t n_alive[2];
+  int64_t wall_count[2][2];
+  int64_t cap_violation[2];   /* collisions whose relative speed exceeded g_cap */
+  int64_t n_collisions[2];    /* accepted collisions */
+  int64_t md_particles[2];    /* particle-steps moved by the sub-cycled MD path */
+  uint32_t step;
+  int32_t refine_sweeps;      /* FP32R: sweeps in the last solve */
+  double refine_residual;     /* FP32R: ||b - A phi|| / ||b|| after the last solve */
+} pic_counters;
+
+/*
+ * pic_init -- validate and copy n_replicas configurations (n_replicas > 1 is
+ * the batched ensemble form), allocate every device buffer, load the
+ * particles (ppc per cell, uniform offsets, Maxwellian velocities taken as
+ * v_{-1/2}, Philox keyed by the seed), precompute the tridiagonal factors
+ * and each grain's unit-charge mesh field, and deposit rho_0.
+ * hip_stream: a hipStream_t (NULL: default stream).  *out receives the
+ * context (NULL on failure; pic_last_error(NULL) then describes it).
+ * Errors: PIC_EINVAL (bad values), PIC_ECONFIG (grains too close to an
+ * electrode or cube wider than the box), PIC_ENOMEM, PIC_EDEVICE.
+ */
+int pic_init(const pic_config* cfgs, int n_replicas, void* hip_stream, pic_ctx** out);
+
+/*
+ * pic_step -- advance every replica by n_steps time steps, asynchronously on
+ * the context's stream.  One step k -> k+1: solve Eq. (3) for phi_k with the
+ * grains' charges on the mesh and phi(L_z) = V(t_k), E_k by Eq. (4), move
+ * every particle (Eq. (1)-(2) or the sub-cycled PPPM path of Eq. (5)-(6)),
+ * absorb at electrodes and grains, collide with the neutral gas, deposit
+ * rho_{k+1}.  Errors: PIC_EINVAL (n_steps < 0), PIC_EDEVICE.
+ */
+int pic_step(pic_ctx* ctx, int n_steps);
+
+/*
+ * pic_grain_charges -- exact absorbed macro-particle counts per grain,
+ * counts[g][0] electrons, counts[g][1] ions (host buffer of 2 n_grains
+ * int64), and, if Q_C is not NULL, the grain charges Q_g = (C_i - C_e) w e in
+ * coulomb (host buffer of n_grains doubles).  Synchronises the stream.
+ */
+int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C);
+
+/*
+ * pic_fields -- the mesh quantities at the current step k for the current
+ * particle state (solving if needed): out[b] receives the quantity of the
+ * b-th set bit of `what`, in the order PHI, E, RHO, RHO_FIXED.  Buffers are
+ * host pointers (out_on_device = 0, the call synchronises) or device
+ * pointers on the context's device (out_on_device = 1, stream-ordered).
+ * Errors: PIC_EINVAL (bad replica, NULL buffer, RHO_FIXED without FP32R).
+ */
+int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int out_on_device);
+
+/* pic_destroy -- free the context and all its device memory (NULL is a no-op). */
+void pic_destroy(pic_ctx* ctx);
+
+/* pic_last_error -- text of the last failure on ctx (or of the last failed
+ * pic_init when ctx is NULL); owned by the library, valid until the next call. */
+const char* pic_last_error(const pic_ctx* ctx);
+
+/*
+ * Test and checkpoint hooks.
+ * pic_get_state copies one replica's particles (device order, not sorted by
+ * id), counts and step to host arrays of the given capacities; PIC_EINVAL if
+ * a capacity is too small.  pic_set_state replaces them (FP32R: positions are
+ * split into cell + FP32 offset and velocities rounded to FP32) and deposits
+ * rho for the new state; PIC_ENUMERIC for non-finite data or positions
+ * outside the box; PIC_EINVAL if n exceeds the replica's particle capacity.
+ */
+int pic_get_state(pic_ctx* ctx, int replica, pic_state_view* view);
+int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* view);
+
+/* pic_get_counters -- per-replica diagnostics; synchronises the stream. */
+int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out);
+
+/* pic_derived -- constants the library derived for a replica, for checking:
+ * out[0] weight w, out[1] Qp (2^-32 e, as double), out[2] n_gas,
+ * out[3..4] g_cap e/i, out[5..6] candidate thresholds e/i (as double). */
+int pic_derived(pic_ctx* ctx, int replica, double out[7]);
+
+/*
+ * Kernel timing.  pic_profile_enable(ctx, 1) clears the record and brackets
+ * every following launch of the selected kernel class with HIP events on the
+ * context's stream; pic_profile_read synchronises and returns the summed
+ * elapsed time (ms) and the number of launches measured since enabling.
+ *   PIC_PROF_PUSH   the fused gather / push / absorb / collide / deposit kernel
+ *                   (one launch per species and step)
+ *   PIC_PROF_FIELD  the whole field stage of a step (RHS, Poisson, E)
+ *   PIC_PROF_SORT   the periodic cell sort of both species
+ */
+#define PIC_PROF_PUSH  0
+#define PIC_PROF_FIELD 1
+#define PIC_PROF_SORT  2
+int pic_profile_enable(pic_ctx* ctx, int on);
+int pic_profile_read(pic_ctx* ctx, int kernel_class, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

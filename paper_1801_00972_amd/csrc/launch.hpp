@@ -1,0 +1,71 @@
+// launch.hpp -- host-side entry points of the library's kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pic_types.hpp"
+
+namespace pic {
+
+// factorisation of the FFT line lengths and lines per block
+struct FftPlanHost {
+  int nfac_x, fac_x[12];
+  int nfac_y, fac_y[12];
+  int L_x, L_y;
+};
+
+// particles
+void launch_push_f64(const PartF64& in, const PartF64& out, const int* n_in, int* n_out,
+                     const double* E, double* rho_next, const MdTables& md, const SpeciesStep& S,
+                     Tallies* T, unsigned long long* gc, int do_mcc, long capacity, hipStream_t st);
+void launch_push_f32r(const PartF32R& in, const PartF32R& out, const int* n_in, int* n_out,
+                      const float* E, long long* rho_next, const MdTables& md,
+                      const SpeciesStep& S, Tallies* T, unsigned long long* gc, int do_mcc,
+                      long capacity, hipStream_t st);
+void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
+                     uint32_t k1, double vth, hipStream_t st);
+void launch_init_f32r(const PartF32R& P, int n, int ppc, int sp, uint32_t k0, uint32_t k1,
+                      double vth, hipStream_t st);
+void launch_deposit_f64(const PartF64& P, const int* n_in, double* rho, const SpeciesStep& S,
+                        long capacity, hipStream_t st);
+void launch_deposit_f32r(const PartF32R& P, const int* n_in, long long* rho, const SpeciesStep& S,
+                         long capacity, hipStream_t st);
+void launch_sort_f64(const PartF64& src, const PartF64& dst, const int* n_in, int* hist, int* sums,
+                     long ncell, int nx, int ny, long capacity, hipStream_t st);
+void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const int* n_in, int* hist,
+                      int* sums, long ncell, int nx, int ny, long capacity, hipStream_t st);
+void launch_fill_int(int* a, long n, int v, hipStream_t st);
+
+// mesh
+void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double* b, void* work,
+                      const void* tw_x, const void* tw_y, const void* inv, double* phi, double V,
+                      hipStream_t st);
+void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
+                          double* psi, double* r, void* work32, const void* tw_x32,
+                          const void* tw_y32, const void* inv32, double* phi, double V,
+                          int sweeps, double* norms, hipStream_t st);
+void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
+                    hipStream_t st);
+void launch_rhs_fixed(const long long* rho, double scale, double* b, int nx, int ny, int nz,
+                      hipStream_t st);
+void launch_grain_rhs(const unsigned long long* counts, const double* gpos, int ng, int nx, int ny,
+                      int nz, double we, double* Q, double* b, double scale, int mode,
+                      long long Qp, hipStream_t st);
+void launch_unit_rhs(const double* gpos, int g, int nx, int ny, int nz, double scale, double* b,
+                     hipStream_t st);
+void launch_extract_cube(const double* E, const int* gcell, int g, int c, int nx, int ny, double* U,
+                         hipStream_t st);
+void launch_efield_f64(const double* phi, double* E, int nx, int ny, int nz, double dx,
+                       hipStream_t st);
+void launch_efield_f32(const double* phi, float* E, int nx, int ny, int nz, double dx,
+                       hipStream_t st);
+void launch_e_out(const double* E64, const float* E32, double* out, long nn, hipStream_t st);
+void launch_rho_total(const double* acc64, const long long* accfx, double* tot64, long long* totfx,
+                      const unsigned long long* counts, const double* gpos, int ng, int nx, int ny,
+                      long nn, long long Qp, hipStream_t st);
+void launch_scale(const double* in, const long long* infx, double conv, double* out, long nn,
+                  hipStream_t st);
+void launch_zero_f64(double* a, long n, hipStream_t st);
+void launch_zero_i64(long long* a, long n, hipStream_t st);
+void launch_zero_i32(int* a, long n, hipStream_t st);
+
+}  // namespace pic

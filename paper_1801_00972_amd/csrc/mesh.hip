@@ -1,0 +1,664 @@
+// mesh.hip -- mesh kernels of the hot path (gfx950): the Poisson solve of
+// Eq. (3) in 7-point finite-difference form (FFT along the periodic x,y,
+// tridiagonal along z between the electrodes), the FP64 residual used to
+// refine an FP32 solve, the field of Eq. (4) and the grains' charge on the mesh.
+//
+// Poisson: phi = V(t) k / nz + psi, psi = 0 on both electrodes; per interior
+// plane the RHS b = -dx^2 rho / eps0 is transformed along x then y, each
+// Fourier mode (m, n) solves psi_{k-1} - (2 + lambda_mn) psi_k + psi_{k+1} = b_k,
+// lambda_mn = 4 sin^2(pi m / nx) + 4 sin^2(pi n / ny), and the inverse
+// transform returns psi.  The tridiagonal factors are computed once per run.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace pic {
+
+template <typename T>
+using cplx = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) {
+  C r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) {
+  C r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
+}
+// multiply by -i (fwd = true) or +i
+template <typename C>
+__device__ __forceinline__ C cmi(C a, bool fwd) {
+  C r;
+  if (fwd) {
+    r.x = a.y;
+    r.y = -a.x;
+  } else {
+    r.x = -a.y;
+    r.y = a.x;
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------- FFT lines
+// One block transforms L lines of length N held in LDS, ping-ponging between
+// two buffers through the Stockham stages (decimation in frequency):
+//   y[q + s (r p + j)] = w_n^{j p} sum_k x[q + s (p + k m)] w_r^{j k},  m = n / r,
+// then n <- m, s <- s r; the output ends in natural order.  Every twiddle is
+// w_N^t from one table of the N-th roots of unity.
+struct FftGeom {
+  int N;             // line length
+  int nfac;
+  int fac[12];       // radices, each 2, 3, 4 or 5
+  int L;             // lines per block
+  int lines_per_plane;
+  long elem_stride, line_stride, plane_stride;  // in elements of the work array
+  long real_plane_offset;  // added to the real array offset (phi: one wall plane)
+};
+
+enum { IN_COMPLEX = 0, IN_REAL = 1 };
+enum { OUT_COMPLEX = 0, OUT_REAL_LIFT = 1, OUT_REAL_ACCUM = 2 };
+
+template <typename T, int IN, int OUT>
+__global__ __launch_bounds__(256) void fft_lines_kernel(FftGeom g, const cplx<T>* __restrict__ tw,
+                                                        int forward, cplx<T>* __restrict__ work,
+                                                        const double* __restrict__ rin,
+                                                        double in_scale, double* __restrict__ rout,
+                                                        double out_scale, double V, int nz) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* buf0 = reinterpret_cast<C*>(smem_raw);
+  C* buf1 = buf0 + g.L * g.N;
+  const int N = g.N, L = g.L;
+  const int blocks_per_plane = g.lines_per_plane / L;
+  const int plane = blockIdx.x / blocks_per_plane;
+  const int l0 = (blockIdx.x % blocks_per_plane) * L;
+  const long pbase = (long)plane * g.plane_stride;
+  const bool e_fast = g.elem_stride == 1;
+
+  for (int idx = threadIdx.x; idx < L * N; idx += blockDim.x) {
+    const int l = e_fast ? idx / N : idx % L;
+    const int e = e_fast ? idx % N : idx / L;
+    const long off = pbase + (long)(l0 + l) * g.line_stride + (long)e * g.elem_stride;
+    C v;
+    if (IN == IN_REAL) {
+      v.x = (T)(rin[off] * in_scale);
+      v.y = (T)0;
+    } else {
+      v = work[off];
+    }
+    buf0[l * N + e] = v;
+  }
+  __syncthreads();
+
+  C* src = buf0;
+  C* dst = buf1;
+  int n = N, s = 1;
+  for (int f = 0; f < g.nfac; ++f) {
+    const int r = g.fac[f];
+    const int m = n / r;
+    const int per_line = N / r;  // = m * s butterflies per line
+    for (int b = threadIdx.x; b < L * per_line; b += blockDim.x) {
+      const int l = b / per_line;
+      const int t = b - l * per_line;
+      const int p = t / s, q = t - p * s;
+      const C* x = src + l * N + q + s * p;
+      C* y = dst + l * N + q + s * r * p;
+      C a[5];
+      for (int k = 0; k < r; ++k) a[k] = x[s * k * m];
+      C out[5];
+      if (r == 2) {
+        out[0] = cadd(a[0], a[1]);
+        out[1] = csub(a[0], a[1]);
+      } else if (r == 4) {
+        const C t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+        const C t2 = cadd(a[1], a[3]), t3 = cmi(csub(a[1], a[3]), forward != 0);
+        out[0] = cadd(t0, t2);
+        out[1] = cadd(t1, t3);
+        out[2] = csub(t0, t2);
+        out[3] = csub(t1, t3);
+      } else {
+        for (int j = 0; j < r; ++j) {
+          C acc = a[0];
+          for (int k = 1; k < r; ++k) {
+            C w = tw[((j * k) % r) * (N / r)];
+            if (forward) w.y = -w.y;
+            acc = cadd(acc, cmul(a[k], w));
+          }
+          out[j] = acc;
+        }
+      }
+      y[0] = out[0];
+      for (int j = 1; j < r; ++j) {
+        C w = tw[(long)j * p * s % N];
+        if (forward) w.y = -w.y;
+        y[s * j] = cmul(out[j], w);
+      }
+    }
+    __syncthreads();
+    C* tmp = src;
+    src = dst;
+    dst = tmp;
+    n = m;
+    s *= r;
+  }
+
+  for (int idx = threadIdx.x; idx < L * N; idx += blockDim.x) {
+    const int l = e_fast ? idx / N : idx % L;
+    const int e = e_fast ? idx % N : idx / L;
+    const long off = pbase + (long)(l0 + l) * g.line_stride + (long)e * g.elem_stride;
+    const C v = src[l * N + e];
+    if (OUT == OUT_COMPLEX) {
+      work[off] = v;
+    } else if (OUT == OUT_REAL_LIFT) {
+      // interior plane k = plane + 1 of phi
+      rout[off + g.real_plane_offset] = (double)v.x * out_scale + V * (double)(plane + 1) / (double)nz;
+    } else {
+      rout[off] += (double)v.x * out_scale;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- tridiagonal
+// one thread per Fourier mode; inv[k][mode] = 1 / (diag - inv[k-1][mode]) is
+// the factorisation, computed once per run
+template <typename T>
+__global__ void thomas_kernel(cplx<T>* __restrict__ d, const T* __restrict__ inv, int K,
+                              long modes) {
+  using C = cplx<T>;
+  const long mn = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (mn >= modes) return;
+  C prev = d[mn];
+  T f = inv[mn];
+  prev.x *= f;
+  prev.y *= f;
+  d[mn] = prev;
+  for (int k = 1; k < K; ++k) {
+    C cur = d[(long)k * modes + mn];
+    f = inv[(long)k * modes + mn];
+    cur.x = (cur.x - prev.x) * f;
+    cur.y = (cur.y - prev.y) * f;
+    d[(long)k * modes + mn] = cur;
+    prev = cur;
+  }
+  for (int k = K - 2; k >= 0; --k) {
+    C cur = d[(long)k * modes + mn];
+    f = inv[(long)k * modes + mn];
+    cur.x -= f * prev.x;
+    cur.y -= f * prev.y;
+    d[(long)k * modes + mn] = cur;
+    prev = cur;
+  }
+}
+
+// ---------------------------------------------------------------- RHS
+// b (interior planes) = scale * rho (all nodes); FP64 form rho in units of w e
+__global__ void rhs_f64_kernel(const double* __restrict__ rho, double scale, double* __restrict__ b,
+                               long plane, long n_int) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_int) b[i] = scale * rho[i + plane];
+}
+__global__ void rhs_fixed_kernel(const long long* __restrict__ rho, double scale,
+                                 double* __restrict__ b, long plane, long n_int) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_int) b[i] = scale * (double)rho[i + plane];
+}
+
+// CIC nodes and weights of a grain (its position is at least one cell inside)
+__device__ __forceinline__ void grain_nodes(const double* gpos, int g, int nx, int ny, long n[8],
+                                            double w[8], float off[3], int cell[3]) {
+  const double X = gpos[3 * g], Y = gpos[3 * g + 1], Z = gpos[3 * g + 2];
+  const int i0 = (int)floor(X), j0 = (int)floor(Y), k0 = (int)floor(Z);
+  const double fx = X - i0, fy = Y - j0, fz = Z - k0;
+  const int i1 = i0 + 1 == nx ? 0 : i0 + 1, j1 = j0 + 1 == ny ? 0 : j0 + 1;
+  const int ii[2] = {i0, i1}, jj[2] = {j0, j1};
+  for (int t = 0; t < 8; ++t) {
+    const int a = t & 1, b = (t >> 1) & 1, c = t >> 2;
+    n[t] = ii[a] + (long)nx * (jj[b] + (long)ny * (k0 + c));
+    w[t] = (a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy) * (c ? fz : 1.0 - fz);
+  }
+  off[0] = (float)fx;
+  off[1] = (float)fy;
+  off[2] = (float)fz;
+  cell[0] = i0;
+  cell[1] = j0;
+  cell[2] = k0;
+}
+
+// the same exact split of the macro charge as the particle deposit (FP32R)
+__device__ __forceinline__ void grain_split(long long Q, double fx, double fy, double fz,
+                                            long long part[8]) {
+  const long long qx = (long long)floor(fx * 16777216.0);
+  const long long qy = (long long)floor(fy * 16777216.0);
+  const long long qz = (long long)floor(fz * 16777216.0);
+  long long ax[2];
+  ax[1] = (Q * qx) >> 24;
+  ax[0] = Q - ax[1];
+  for (int a = 0; a < 2; ++a) {
+    const long long y1 = (ax[a] * qy) >> 24;
+    const long long yy[2] = {ax[a] - y1, y1};
+    for (int b = 0; b < 2; ++b) {
+      const long long z1 = (yy[b] * qz) >> 24;
+      part[a + 2 * b] = yy[b] - z1;
+      part[a + 2 * b + 4] = z1;
+    }
+  }
+}
+
+// Grain charges at the start of the step: Q_g = (C_i - C_e) w e is frozen for
+// the step's MD kernel, and the grains' CIC charge is added to the RHS.
+// mode 0: FP64 (b += scale_w * net * W); mode 1: FP32R (b += scale_fixed * net * part)
+__global__ void grain_rhs_kernel(const unsigned long long* __restrict__ counts, const double* gpos,
+                                 int ng, int nx, int ny, int nz, double we, double* __restrict__ Q,
+                                 double* __restrict__ b, double scale, int mode, long long Qp) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const long plane = (long)nx * ny;
+  for (int g = 0; g < ng; ++g) {
+    const long long net = (long long)counts[2 * g + 1] - (long long)counts[2 * g + 0];
+    Q[g] = (double)net * we;
+    if (!b || net == 0) continue;
+    long n[8];
+    double w[8];
+    float off[3];
+    int cell[3];
+    grain_nodes(gpos, g, nx, ny, n, w, off, cell);
+    long long part[8];
+    if (mode == 1) {
+      const double X = gpos[3 * g], Y = gpos[3 * g + 1], Z = gpos[3 * g + 2];
+      grain_split(Qp, X - floor(X), Y - floor(Y), Z - floor(Z), part);
+    }
+    for (int t = 0; t < 8; ++t) {
+      const long k = n[t] / plane;
+      if (k < 1 || k > nz - 1) continue;
+      const double add = mode == 1 ? scale * (double)(net * part[t]) : scale * (double)net * w[t];
+      b[n[t] - plane] += add;
+    }
+  }
+}
+
+// unit (1 C) charge of grain g on the RHS, for its unit field
+__global__ void unit_rhs_kernel(const double* gpos, int g, int nx, int ny, int nz, double scale,
+                                double* __restrict__ b) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const long plane = (long)nx * ny;
+  long n[8];
+  double w[8];
+  float off[3];
+  int cell[3];
+  grain_nodes(gpos, g, nx, ny, n, w, off, cell);
+  for (int t = 0; t < 8; ++t) {
+    const long k = n[t] / plane;
+    if (k >= 1 && k <= nz - 1) b[n[t] - plane] += scale * w[t];
+  }
+}
+
+// copy grain g's field (interleaved double pairs) on its cube into U[g][3][side^3]
+__global__ void extract_cube_kernel(const double2* __restrict__ E, const int* gcell, int g, int c,
+                                    int nx, int ny, double* __restrict__ U) {
+  const int side = 2 * c + 2;
+  const long cube = (long)side * side * side;
+  const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= cube) return;
+  const int cx = (int)(l % side), cy = (int)((l / side) % side), cz = (int)(l / (side * side));
+  int i = gcell[3 * g] - c + cx, j = gcell[3 * g + 1] - c + cy;
+  const int k = gcell[3 * g + 2] - c + cz;
+  i = ((i % nx) + nx) % nx;
+  j = ((j % ny) + ny) % ny;
+  const long n = i + (long)nx * (j + (long)ny * k);
+  const double2 a = E[2 * n], bz = E[2 * n + 1];
+  double* Ug = U + (long)g * 3 * cube;
+  Ug[l] = a.x;
+  Ug[cube + l] = a.y;
+  Ug[2 * cube + l] = bz.x;
+}
+
+// ---------------------------------------------------------------- refinement
+// r = b - A psi on the interior nodes (psi = 0 on the electrodes), FP64;
+// accumulates ||r||^2 and ||b||^2
+__global__ __launch_bounds__(256) void residual_kernel(const double* __restrict__ psi,
+                                                       const double* __restrict__ b,
+                                                       double* __restrict__ r, int nx, int ny,
+                                                       int K, double* __restrict__ norms) {
+  __shared__ double s_r[256], s_b[256];
+  const long plane = (long)nx * ny;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double rr = 0.0, bb = 0.0;
+  if (i < plane * K) {
+    const int x = (int)(i % nx), y = (int)((i / nx) % ny), k = (int)(i / plane);
+    const long row = i - x, pl = i - (long)y * nx - x;
+    const double c = psi[i];
+    const double xp = psi[row + (x + 1 == nx ? 0 : x + 1)];
+    const double xm = psi[row + (x == 0 ? nx - 1 : x - 1)];
+    const double yp = psi[pl + (long)(y + 1 == ny ? 0 : y + 1) * nx + x];
+    const double ym = psi[pl + (long)(y == 0 ? ny - 1 : y - 1) * nx + x];
+    const double zp = k + 1 < K ? psi[i + plane] : 0.0;
+    const double zm = k > 0 ? psi[i - plane] : 0.0;
+    const double Ax = xp + xm + yp + ym + zp + zm - 6.0 * c;
+    const double bi = b[i];
+    const double ri = bi - Ax;
+    r[i] = ri;
+    rr = ri * ri;
+    bb = bi * bi;
+  }
+  s_r[threadIdx.x] = rr;
+  s_b[threadIdx.x] = bb;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s_r[threadIdx.x] += s_r[threadIdx.x + off];
+      s_b[threadIdx.x] += s_b[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&norms[0], s_r[0]);
+    atomicAdd(&norms[1], s_b[0]);
+  }
+}
+
+// phi = psi + V k / nz on the interior, 0 and V on the electrodes
+__global__ void lift_kernel(const double* __restrict__ psi, double* __restrict__ phi, int nx,
+                            int ny, int nz, double V) {
+  const long plane = (long)nx * ny;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= plane * (nz + 1)) return;
+  const int k = (int)(n / plane);
+  if (k == 0) phi[n] = 0.0;
+  else if (k == nz) phi[n] = V;
+  else phi[n] = psi[n - plane] + V * (double)k / (double)nz;
+}
+
+__global__ void walls_kernel(double* __restrict__ phi, long plane, int nz, double V) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= plane) return;
+  phi[n] = 0.0;
+  phi[(long)nz * plane + n] = V;
+}
+
+// ---------------------------------------------------------------- field
+// E = -grad phi: central differences, periodic in x,y; one-sided along z on
+// the electrode planes.  Stored interleaved per node: FP64 as two double pairs
+// (Ex,Ey),(Ez,0); FP32 as one float4 (Ex,Ey,Ez,0).
+template <typename OutT>
+__global__ void efield_kernel(const double* __restrict__ phi, OutT* __restrict__ E, int nx, int ny,
+                              int nz, double dx) {
+  const long plane = (long)nx * ny;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= plane * (nz + 1)) return;
+  const int x = (int)(n % nx), y = (int)((n / nx) % ny), k = (int)(n / plane);
+  const long row = n - x, pl = n - (long)y * nx - x;
+  const double ex = -(phi[row + (x + 1 == nx ? 0 : x + 1)] - phi[row + (x == 0 ? nx - 1 : x - 1)]) /
+                    (2.0 * dx);
+  const double ey = -(phi[pl + (long)(y + 1 == ny ? 0 : y + 1) * nx + x] -
+                      phi[pl + (long)(y == 0 ? ny - 1 : y - 1) * nx + x]) /
+                    (2.0 * dx);
+  double ez;
+  if (k == 0) ez = -(phi[n + plane] - phi[n]) / dx;
+  else if (k == nz) ez = -(phi[n] - phi[n - plane]) / dx;
+  else ez = -(phi[n + plane] - phi[n - plane]) / (2.0 * dx);
+  if constexpr (std::is_same<OutT, double2>::value) {
+    E[2 * n] = make_double2(ex, ey);
+    E[2 * n + 1] = make_double2(ez, 0.0);
+  } else {
+    E[n] = make_float4((float)ex, (float)ey, (float)ez, 0.0f);
+  }
+}
+
+// ---------------------------------------------------------------- readouts
+__global__ void e_out_kernel(const double2* __restrict__ E2, const float4* __restrict__ E4,
+                             double* __restrict__ out, long nn) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  if (E2) {
+    const double2 a = E2[2 * n], b = E2[2 * n + 1];
+    out[n] = a.x;
+    out[nn + n] = a.y;
+    out[2 * nn + n] = b.x;
+  } else {
+    const float4 a = E4[n];
+    out[n] = a.x;
+    out[nn + n] = a.y;
+    out[2 * nn + n] = a.z;
+  }
+}
+
+// total rho: plasma accumulator plus grains.  FP64 form: out = conv * (acc + net W);
+// FP32R: fixed = acc + net * part (exact), out = conv * fixed.
+__global__ void rho_out_kernel(const double* __restrict__ acc64, const long long* __restrict__ accfx,
+                               double conv, double* __restrict__ out, long long* __restrict__ outfx,
+                               long nn) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  if (acc64) {
+    out[n] = acc64[n];
+  } else {
+    outfx[n] = accfx[n];
+  }
+}
+
+__global__ void rho_grains_kernel(const unsigned long long* __restrict__ counts, const double* gpos,
+                                  int ng, int nx, int ny, double* __restrict__ acc,
+                                  long long* __restrict__ fx, long long Qp) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int g = 0; g < ng; ++g) {
+    const long long net = (long long)counts[2 * g + 1] - (long long)counts[2 * g + 0];
+    long n[8];
+    double w[8];
+    float off[3];
+    int cell[3];
+    grain_nodes(gpos, g, nx, ny, n, w, off, cell);
+    long long part[8];
+    const double X = gpos[3 * g], Y = gpos[3 * g + 1], Z = gpos[3 * g + 2];
+    grain_split(Qp, X - floor(X), Y - floor(Y), Z - floor(Z), part);
+    for (int t = 0; t < 8; ++t) {
+      if (acc) acc[n[t]] += (double)net * w[t];
+      if (fx) fx[n[t]] += net * part[t];
+    }
+  }
+}
+
+__global__ void scale_kernel(const double* __restrict__ in, const long long* __restrict__ infx,
+                             double conv, double* __restrict__ out, long nn) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  out[n] = conv * (in ? in[n] : (double)infx[n]);
+}
+
+__global__ void zero_f64_kernel(double* a, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+__global__ void zero_i64_kernel(long long* a, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+__global__ void zero_i32_kernel(int* a, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+// ---------------------------------------------------------------- launchers
+static inline int nb256(long n) { return (int)((n + 255) / 256); }
+
+static FftGeom make_geom(const FftPlanHost& P, bool along_x, int nx, int ny, long plane) {
+  FftGeom g{};
+  g.N = along_x ? nx : ny;
+  const int* f = along_x ? P.fac_x : P.fac_y;
+  g.nfac = along_x ? P.nfac_x : P.nfac_y;
+  for (int i = 0; i < g.nfac; ++i) g.fac[i] = f[i];
+  g.lines_per_plane = along_x ? ny : nx;
+  g.L = along_x ? P.L_x : P.L_y;
+  g.elem_stride = along_x ? 1 : nx;
+  g.line_stride = along_x ? nx : 1;
+  g.plane_stride = plane;
+  g.real_plane_offset = plane;
+  return g;
+}
+
+template <typename T>
+static void fft_launch(const FftGeom& g, int planes, const void* tw, int forward, int in_mode,
+                       int out_mode, void* work, const double* rin, double in_scale, double* rout,
+                       double out_scale, double V, int nz, hipStream_t st) {
+  using C = cplx<T>;
+  const int blocks = planes * (g.lines_per_plane / g.L);
+  const size_t lds = 2 * sizeof(C) * g.L * g.N;
+  const C* t = (const C*)tw;
+  C* w = (C*)work;
+  if (in_mode == IN_REAL && out_mode == OUT_COMPLEX)
+    hipLaunchKernelGGL((fft_lines_kernel<T, IN_REAL, OUT_COMPLEX>), dim3(blocks), dim3(256), lds, st,
+                       g, t, forward, w, rin, in_scale, rout, out_scale, V, nz);
+  else if (in_mode == IN_COMPLEX && out_mode == OUT_COMPLEX)
+    hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_COMPLEX>), dim3(blocks), dim3(256), lds,
+                       st, g, t, forward, w, rin, in_scale, rout, out_scale, V, nz);
+  else if (out_mode == OUT_REAL_LIFT)
+    hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_LIFT>), dim3(blocks), dim3(256), lds,
+                       st, g, t, forward, w, rin, in_scale, rout, out_scale, V, nz);
+  else
+    hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_ACCUM>), dim3(blocks), dim3(256),
+                       lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, V, nz);
+}
+
+// one FFT + tridiagonal + inverse FFT solve of A psi = b (T = double or float);
+// out_mode OUT_REAL_LIFT writes phi (with the lift), OUT_REAL_ACCUM adds to psi
+template <typename T>
+static void solve_once(const FftPlanHost& P, int nx, int ny, int nz, const double* b, void* work,
+                       const void* tw_x, const void* tw_y, const void* inv, int out_mode,
+                       double* out, double V, hipStream_t st) {
+  const long plane = (long)nx * ny;
+  const int K = nz - 1;
+  const FftGeom gx = make_geom(P, true, nx, ny, plane);
+  const FftGeom gy = make_geom(P, false, nx, ny, plane);
+  fft_launch<T>(gx, K, tw_x, 1, IN_REAL, OUT_COMPLEX, work, b, 1.0, nullptr, 0.0, 0.0, nz, st);
+  fft_launch<T>(gy, K, tw_y, 1, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, 0.0, nz,
+                st);
+  hipLaunchKernelGGL(thomas_kernel<T>, dim3(nb256(plane)), dim3(256), 0, st, (cplx<T>*)work,
+                     (const T*)inv, K, plane);
+  fft_launch<T>(gy, K, tw_y, 0, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, 0.0, nz,
+                st);
+  fft_launch<T>(gx, K, tw_x, 0, IN_COMPLEX, out_mode, work, nullptr, 0.0, out,
+                1.0 / (double)plane, V, nz, st);
+}
+
+void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double* b, void* work,
+                      const void* tw_x, const void* tw_y, const void* inv, double* phi, double V,
+                      hipStream_t st) {
+  solve_once<double>(P, nx, ny, nz, b, work, tw_x, tw_y, inv, OUT_REAL_LIFT, phi, V, st);
+  hipLaunchKernelGGL(walls_kernel, dim3(nb256((long)nx * ny)), dim3(256), 0, st, phi,
+                     (long)nx * ny, nz, V);
+}
+
+// FP32 solves refined in FP64: psi = 0, r = b; repeat sweeps times
+// { psi += solve32(r); r = b - A psi }; phi = psi + lift.  norms receives
+// ||r||^2, ||b||^2 of the last sweep.
+void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
+                          double* psi, double* r, void* work32, const void* tw_x32,
+                          const void* tw_y32, const void* inv32, double* phi, double V,
+                          int sweeps, double* norms, hipStream_t st) {
+  const long plane = (long)nx * ny;
+  const long n_int = plane * (nz - 1);
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(nb256(n_int)), dim3(256), 0, st, psi, n_int);
+  const double* rhs = b;
+  for (int it = 0; it < sweeps; ++it) {
+    solve_once<float>(P, nx, ny, nz, rhs, work32, tw_x32, tw_y32, inv32, OUT_REAL_ACCUM, psi, 0.0,
+                      st);
+    hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(2), 0, st, norms, 2L);
+    hipLaunchKernelGGL(residual_kernel, dim3(nb256(n_int)), dim3(256), 0, st, psi, b, r, nx, ny,
+                       nz - 1, norms);
+    rhs = r;
+  }
+  hipLaunchKernelGGL(lift_kernel, dim3(nb256(plane * (nz + 1))), dim3(256), 0, st, psi, phi, nx, ny,
+                     nz, V);
+}
+
+void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
+                    hipStream_t st) {
+  const long plane = (long)nx * ny, n_int = plane * (nz - 1);
+  hipLaunchKernelGGL(rhs_f64_kernel, dim3(nb256(n_int)), dim3(256), 0, st, rho, scale, b, plane,
+                     n_int);
+}
+void launch_rhs_fixed(const long long* rho, double scale, double* b, int nx, int ny, int nz,
+                      hipStream_t st) {
+  const long plane = (long)nx * ny, n_int = plane * (nz - 1);
+  hipLaunchKernelGGL(rhs_fixed_kernel, dim3(nb256(n_int)), dim3(256), 0, st, rho, scale, b, plane,
+                     n_int);
+}
+
+void launch_grain_rhs(const unsigned long long* counts, const double* gpos, int ng, int nx, int ny,
+                      int nz, double we, double* Q, double* b, double scale, int mode,
+                      long long Qp, hipStream_t st) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(grain_rhs_kernel, dim3(1), dim3(64), 0, st, counts, gpos, ng, nx, ny, nz, we,
+                     Q, b, scale, mode, Qp);
+}
+
+void launch_unit_rhs(const double* gpos, int g, int nx, int ny, int nz, double scale, double* b,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(unit_rhs_kernel, dim3(1), dim3(64), 0, st, gpos, g, nx, ny, nz, scale, b);
+}
+
+void launch_extract_cube(const double* E, const int* gcell, int g, int c, int nx, int ny, double* U,
+                         hipStream_t st) {
+  const long side = 2 * c + 2, cube = side * side * side;
+  hipLaunchKernelGGL(extract_cube_kernel, dim3(nb256(cube)), dim3(256), 0, st, (const double2*)E,
+                     gcell, g, c, nx, ny, U);
+}
+
+void launch_efield_f64(const double* phi, double* E, int nx, int ny, int nz, double dx,
+                       hipStream_t st) {
+  const long nn = (long)nx * ny * (nz + 1);
+  hipLaunchKernelGGL(efield_kernel<double2>, dim3(nb256(nn)), dim3(256), 0, st, phi, (double2*)E,
+                     nx, ny, nz, dx);
+}
+void launch_efield_f32(const double* phi, float* E, int nx, int ny, int nz, double dx,
+                       hipStream_t st) {
+  const long nn = (long)nx * ny * (nz + 1);
+  hipLaunchKernelGGL(efield_kernel<float4>, dim3(nb256(nn)), dim3(256), 0, st, phi, (float4*)E, nx,
+                     ny, nz, dx);
+}
+
+void launch_e_out(const double* E64, const float* E32, double* out, long nn, hipStream_t st) {
+  hipLaunchKernelGGL(e_out_kernel, dim3(nb256(nn)), dim3(256), 0, st, (const double2*)E64,
+                     (const float4*)E32, out, nn);
+}
+
+void launch_rho_total(const double* acc64, const long long* accfx, double* tot64,
+                      long long* totfx, const unsigned long long* counts, const double* gpos,
+                      int ng, int nx, int ny, long nn, long long Qp, hipStream_t st) {
+  hipLaunchKernelGGL(rho_out_kernel, dim3(nb256(nn)), dim3(256), 0, st, acc64, accfx, 0.0, tot64,
+                     totfx, nn);
+  if (ng > 0)
+    hipLaunchKernelGGL(rho_grains_kernel, dim3(1), dim3(64), 0, st, counts, gpos, ng, nx, ny,
+                       acc64 ? tot64 : nullptr, acc64 ? nullptr : totfx, Qp);
+}
+
+void launch_scale(const double* in, const long long* infx, double conv, double* out, long nn,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(scale_kernel, dim3(nb256(nn)), dim3(256), 0, st, in, infx, conv, out, nn);
+}
+
+void launch_zero_f64(double* a, long n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(zero_f64_kernel, dim3(nb256(n)), dim3(256), 0, st, a, n);
+}
+void launch_zero_i64(long long* a, long n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(zero_i64_kernel, dim3(nb256(n)), dim3(256), 0, st, a, n);
+}
+void launch_zero_i32(int* a, long n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(zero_i32_kernel, dim3(nb256(n)), dim3(256), 0, st, a, n);
+}
+
+}  // namespace pic

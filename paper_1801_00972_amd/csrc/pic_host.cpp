@@ -1,0 +1,950 @@
+// pic_host.cpp -- the C ABI of include/pic.h: configuration checks, derived
+// constants, device memory, the per-step launch sequence, readouts and the
+// state hooks.  All arithmetic of the step runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "pic.h"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct DevMem {
+  std::vector<void*> blocks;
+  ~DevMem() {
+    for (void* p : blocks) (void)hipFree(p);
+  }
+};
+
+struct Replica {
+  pic_config cfg{};
+  std::vector<double> gpos;  // [g][3] cell units
+  int nx = 0, ny = 0, nz = 0;
+  long nxy = 0, ncell = 0, nn = 0, n_int = 0;
+  int prec = PIC_FP64;
+  // derived constants
+  double w = 0, n_gas = 0, we = 0;
+  long long Qp = 0;
+  double q[2]{}, m[2]{}, vth[2]{}, g_cap[2]{}, P_null[2]{};
+  uint64_t T_null[2]{};
+  double vth_gas = 0;
+  long cap[2]{};
+  // particles: [species][buffer]
+  PartF64 p64[2][2]{};
+  PartF32R p32[2][2]{};
+  int cur = 0;
+  int* d_n = nullptr;  // [species * 2 + buffer]
+  // mesh
+  void* rho[2]{};      // accumulators: double (units w e) or int64 (2^-32 e)
+  int rho_cur = 0;
+  double* b = nullptr;
+  double* phi = nullptr;
+  void* E = nullptr;   // double pairs (FP64) or float4 (FP32R)
+  double* psi = nullptr;
+  double* r = nullptr;
+  void* work = nullptr;
+  void* tw_x = nullptr;
+  void* tw_y = nullptr;
+  void* inv = nullptr;
+  FftPlanHost fft{};
+  double* norms = nullptr;
+  double* tot64 = nullptr;
+  long long* totfx = nullptr;
+  double* eout = nullptr;
+  // near-grain tables
+  MdTables md{};
+  double* d_Q = nullptr;
+  // tallies
+  Tallies* d_T = nullptr;
+  unsigned long long* d_gc = nullptr;
+  // sort
+  int* d_hist = nullptr;
+  int* d_sums = nullptr;
+  uint32_t step = 0;
+  int since_sort = 0;
+  DevMem mem;
+};
+
+}  // namespace
+
+struct pic_ctx {
+  std::vector<std::unique_ptr<Replica>> reps;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int sticky = 0;
+  // kernel timing: event pairs per kernel class
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[3];
+  ~pic_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int fail(pic_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) {
+    ctx->err = msg;
+    if (code == PIC_EDEVICE) ctx->sticky = PIC_EDEVICE;
+  } else {
+    g_init_error = msg;
+  }
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EDEVICE,             \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+#define CHECK_LAUNCH(ctx) HIPCHK(ctx, hipGetLastError())
+
+template <typename T>
+int dalloc(pic_ctx* ctx, Replica& R, T** p, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, PIC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  R.mem.blocks.push_back(q);
+  *p = static_cast<T*>(q);
+  return PIC_OK;
+}
+
+#define TRY(x)               \
+  do {                       \
+    int rc_ = (x);           \
+    if (rc_ != PIC_OK) return rc_; \
+  } while (0)
+
+bool factor_len(int N, int* fac, int* nfac) {
+  int n = N, k = 0;
+  while (n % 4 == 0 && k < 12) { fac[k++] = 4; n /= 4; }
+  while (n % 2 == 0 && k < 12) { fac[k++] = 2; n /= 2; }
+  while (n % 3 == 0 && k < 12) { fac[k++] = 3; n /= 3; }
+  while (n % 5 == 0 && k < 12) { fac[k++] = 5; n /= 5; }
+  *nfac = k;
+  return n == 1;
+}
+
+int lines_per_block(int N, int lines) {
+  int L = 1;
+  while (L * 2 * N <= 1024 && lines % (L * 2) == 0) L *= 2;
+  return L;
+}
+
+double rf_voltage(const pic_config& c, uint32_t k) {
+  const double t = (double)k * c.dt;
+  return c.V_dc + c.V_rf * std::sin(2.0 * kPi * c.f_rf * t);
+}
+
+int periodic_delta(int a, int b, int n) {
+  int d = ((a - b) % n + n) % n;
+  if (d > n / 2) d -= n;
+  return d;
+}
+
+// smallest periodic interval [origin, origin + size) covering every marked cell
+void periodic_bbox(const std::vector<char>& cov, int n, int* origin, int* size) {
+  int best_len = 0, best_end = 0;
+  bool any = false;
+  for (int i = 0; i < n; ++i) any |= cov[i] != 0;
+  if (!any) { *origin = 0; *size = 0; return; }
+  // longest circular run of uncovered cells
+  for (int s = 0; s < n; ++s) {
+    if (cov[s] || !cov[(s - 1 + n) % n]) continue;  // run starts right after a covered cell
+    int len = 0;
+    while (len < n && !cov[(s + len) % n]) ++len;
+    if (len > best_len) { best_len = len; best_end = (s + len) % n; }
+  }
+  *origin = best_len ? best_end : 0;
+  *size = n - best_len;
+}
+
+int validate(const pic_config& c, std::string& why) {
+  auto bad = [&](const std::string& s) { why = s; return PIC_EINVAL; };
+  if (c.nx < 2 || c.ny < 2 || c.nz < 2) return bad("nx, ny, nz must be >= 2");
+  int f[12], nf;
+  if (!factor_len(c.nx, f, &nf) || !factor_len(c.ny, f, &nf))
+    return bad("nx and ny must factor into 2, 3 and 5");
+  if (c.ppc < 1) return bad("ppc must be >= 1");
+  const double np = (double)c.nx * c.ny * c.nz * c.ppc;
+  if (np > 2147483647.0) return bad("more than 2^31-1 particles per species");
+  if (!(c.dx > 0) || !(c.dt > 0) || !(c.n0 > 0)) return bad("dx, dt and n0 must be > 0");
+  if (!(c.Te_eV >= 0) || !(c.Ti_eV >= 0) || !(c.p_gas_Pa >= 0) || !(c.T_gas_K > 0))
+    return bad("temperatures and pressure out of range");
+  if (!(c.sigma_e_el >= 0) || !(c.sigma_i_cx >= 0) || !(c.E_cap_eV > 0))
+    return bad("cross sections must be >= 0 and E_cap > 0");
+  if (!std::isfinite(c.V_dc) || !std::isfinite(c.V_rf) || !std::isfinite(c.f_rf))
+    return bad("rf drive must be finite");
+  if (c.precision != PIC_FP64 && c.precision != PIC_FP32R) return bad("unknown precision");
+  if (c.precision == PIC_FP32R && c.max_refine < 1) return bad("max_refine must be >= 1");
+  if (c.md_subcycles < 1) return bad("md_subcycles must be >= 1");
+  if (c.pp_cutoff_cells < 0) return bad("pp_cutoff_cells must be >= 0");
+  if (c.n_grains < 0 || c.n_grains > 4096) return bad("n_grains out of range");
+  if (c.n_grains > 0 && !c.grain_pos) return bad("grain_pos is NULL");
+  if (c.n_grains > 0 && !(c.grain_radius > 0)) return bad("grain_radius must be > 0");
+  if (c.sort_interval < 0) return bad("sort_interval must be >= 0");
+  return PIC_OK;
+}
+
+int setup_md(pic_ctx* ctx, Replica& R) {
+  const pic_config& c = R.cfg;
+  const int ng = c.n_grains, cc = c.pp_cutoff_cells;
+  MdTables& md = R.md;
+  md.n_grains = ng;
+  md.cutoff = cc;
+  md.side = 2 * cc + 2;
+  md.a2 = c.grain_radius * c.grain_radius;
+  TRY(dalloc(ctx, R, &R.d_Q, std::max(ng, 1)));
+  md.Q = R.d_Q;
+  if (ng == 0) return PIC_OK;
+  if (2 * cc + 1 > R.nx || 2 * cc + 1 > R.ny)
+    return fail(ctx, PIC_ECONFIG, "MD cube wider than the periodic box");
+  std::vector<int> gcell(3 * ng);
+  std::vector<char> covx(R.nx, 0), covy(R.ny, 0);
+  int zmin = R.nz, zmax = -1;
+  for (int g = 0; g < ng; ++g) {
+    const double* x = &R.gpos[3 * g];
+    if (!(x[0] >= 0 && x[0] < R.nx && x[1] >= 0 && x[1] < R.ny && x[2] >= 0 && x[2] < R.nz))
+      return fail(ctx, PIC_ECONFIG, "grain " + std::to_string(g) + " outside the box");
+    for (int a = 0; a < 3; ++a) gcell[3 * g + a] = (int)std::floor(x[a]);
+    const int gk = gcell[3 * g + 2];
+    if (gk - cc < 0 || gk + cc + 1 > R.nz || gk < 1 || gk > R.nz - 2)
+      return fail(ctx, PIC_ECONFIG, "grain " + std::to_string(g) + " too close to an electrode");
+    for (int d = -cc; d <= cc; ++d) {
+      covx[((gcell[3 * g] + d) % R.nx + R.nx) % R.nx] = 1;
+      covy[((gcell[3 * g + 1] + d) % R.ny + R.ny) % R.ny] = 1;
+    }
+    zmin = std::min(zmin, gk - cc);
+    zmax = std::max(zmax, gk + cc);
+  }
+  periodic_bbox(covx, R.nx, &md.bx0, &md.bsx);
+  periodic_bbox(covy, R.ny, &md.by0, &md.bsy);
+  md.bz0 = zmin;
+  md.bsz = zmax - zmin + 1;
+  std::vector<uint32_t> cell_list((size_t)md.bsx * md.bsy * md.bsz, 0u);
+  std::vector<int32_t> idx;
+  for (int z = 0; z < md.bsz; ++z)
+    for (int y = 0; y < md.bsy; ++y)
+      for (int x = 0; x < md.bsx; ++x) {
+        const int i = (md.bx0 + x) % R.nx, j = (md.by0 + y) % R.ny, k = md.bz0 + z;
+        const size_t start = idx.size();
+        for (int g = 0; g < ng; ++g)
+          if (std::abs(periodic_delta(i, gcell[3 * g], R.nx)) <= cc &&
+              std::abs(periodic_delta(j, gcell[3 * g + 1], R.ny)) <= cc &&
+              std::abs(k - gcell[3 * g + 2]) <= cc)
+            idx.push_back(g);
+        const size_t cnt = idx.size() - start;
+        if (cnt > 255) return fail(ctx, PIC_ECONFIG, "more than 255 grains share an MD cell");
+        if (start >= (1u << 24)) return fail(ctx, PIC_ECONFIG, "MD tables too large");
+        cell_list[((size_t)z * md.bsy + y) * md.bsx + x] = (uint32_t)(start << 8) | (uint32_t)cnt;
+      }
+  uint32_t* d_cl;
+  int32_t* d_idx;
+  double* d_gpos;
+  int32_t* d_gcell;
+  double* d_U;
+  const long cube = (long)md.side * md.side * md.side;
+  TRY(dalloc(ctx, R, &d_cl, cell_list.size()));
+  TRY(dalloc(ctx, R, &d_idx, std::max<size_t>(idx.size(), 1)));
+  TRY(dalloc(ctx, R, &d_gpos, 3 * ng));
+  TRY(dalloc(ctx, R, &d_gcell, 3 * ng));
+  TRY(dalloc(ctx, R, &d_U, (size_t)ng * 3 * cube));
+  HIPCHK(ctx, hipMemcpy(d_cl, cell_list.data(), cell_list.size() * 4, hipMemcpyHostToDevice));
+  if (!idx.empty())
+    HIPCHK(ctx, hipMemcpy(d_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(d_gpos, R.gpos.data(), 3 * ng * 8, hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(d_gcell, gcell.data(), 3 * ng * 4, hipMemcpyHostToDevice));
+  md.cell_list = d_cl;
+  md.grain_idx = d_idx;
+  md.gpos = d_gpos;
+  md.gcell = d_gcell;
+  md.U = d_U;
+  return PIC_OK;
+}
+
+// FFT twiddles and tridiagonal factors of one precision
+template <typename T>
+int setup_solver_tables(pic_ctx* ctx, Replica& R, void** tw_x, void** tw_y, void** inv) {
+  auto twiddles = [&](int N, void** out) -> int {
+    std::vector<T> h(2 * N);
+    for (int t = 0; t < N; ++t) {
+      const double a = 2.0 * kPi * (double)t / (double)N;
+      h[2 * t] = (T)std::cos(a);
+      h[2 * t + 1] = (T)std::sin(a);
+    }
+    T* d;
+    TRY(dalloc(ctx, R, &d, 2 * N));
+    HIPCHK(ctx, hipMemcpy(d, h.data(), 2 * N * sizeof(T), hipMemcpyHostToDevice));
+    *out = d;
+    return PIC_OK;
+  };
+  TRY(twiddles(R.nx, tw_x));
+  TRY(twiddles(R.ny, tw_y));
+  const int K = R.nz - 1;
+  std::vector<T> h((size_t)K * R.nxy);
+  for (long mn = 0; mn < R.nxy; ++mn) {
+    const int m = (int)(mn % R.nx), n = (int)(mn / R.nx);
+    const double sx = std::sin(kPi * m / R.nx), sy = std::sin(kPi * n / R.ny);
+    const double diag = -(2.0 + 4.0 * (sx * sx + sy * sy));
+    double cprev = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double f = 1.0 / (diag - cprev);
+      h[(size_t)k * R.nxy + mn] = (T)f;
+      cprev = f;
+    }
+  }
+  T* d;
+  TRY(dalloc(ctx, R, &d, h.size()));
+  HIPCHK(ctx, hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *inv = d;
+  return PIC_OK;
+}
+
+SpeciesStep species_step(const Replica& R, int sp) {
+  SpeciesStep S{};
+  const pic_config& c = R.cfg;
+  S.nx = R.nx;
+  S.ny = R.ny;
+  S.nz = R.nz;
+  S.nxy = (int)R.nxy;
+  S.sp = sp;
+  S.md_sub = c.md_subcycles;
+  S.dx = c.dx;
+  const double qm = R.q[sp] / R.m[sp];
+  const double h = c.dt / (double)c.md_subcycles;
+  S.qm = qm;
+  S.qm_dt = qm * c.dt;
+  S.dt_dx = c.dt / c.dx;
+  S.qm_h = qm * h;
+  S.h_dx = h / c.dx;
+  S.qm_dt_f = (float)S.qm_dt;
+  S.dt_dx_f = (float)S.dt_dx;
+  S.T_null = R.T_null[sp];
+  S.inv_g_cap = 1.0 / R.g_cap[sp];
+  S.vth_gas = R.vth_gas;
+  S.mass_ratio_e = R.m[0] / (R.m[0] + R.m[1]);
+  S.mass_ratio_n = R.m[1] / (R.m[0] + R.m[1]);
+  S.key0 = (uint32_t)(c.seed & 0xffffffffu);
+  S.key1 = (uint32_t)(c.seed >> 32);
+  S.step = R.step;
+  S.Qp = R.Qp;
+  S.sign = sp == 0 ? -1.0 : 1.0;
+  S.isign = sp == 0 ? -1 : 1;
+  return S;
+}
+
+int alloc_particles(pic_ctx* ctx, Replica& R) {
+  for (int sp = 0; sp < 2; ++sp)
+    for (int bsel = 0; bsel < 2; ++bsel) {
+      const long n = R.cap[sp];
+      if (R.prec == PIC_FP64) {
+        PartF64& P = R.p64[sp][bsel];
+        TRY(dalloc(ctx, R, &P.x, n));
+        TRY(dalloc(ctx, R, &P.y, n));
+        TRY(dalloc(ctx, R, &P.z, n));
+        TRY(dalloc(ctx, R, &P.vx, n));
+        TRY(dalloc(ctx, R, &P.vy, n));
+        TRY(dalloc(ctx, R, &P.vz, n));
+        TRY(dalloc(ctx, R, &P.id, n));
+      } else {
+        PartF32R& P = R.p32[sp][bsel];
+        TRY(dalloc(ctx, R, &P.cell, n));
+        TRY(dalloc(ctx, R, &P.ox, n));
+        TRY(dalloc(ctx, R, &P.oy, n));
+        TRY(dalloc(ctx, R, &P.oz, n));
+        TRY(dalloc(ctx, R, &P.vx, n));
+        TRY(dalloc(ctx, R, &P.vy, n));
+        TRY(dalloc(ctx, R, &P.vz, n));
+        TRY(dalloc(ctx, R, &P.id, n));
+      }
+    }
+  TRY(dalloc(ctx, R, &R.d_n, 4));
+  return PIC_OK;
+}
+
+// records an event on the stream when profiling (nullptr otherwise)
+hipEvent_t prof_event(pic_ctx* ctx) {
+  if (!ctx->prof) return nullptr;
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+  }
+  hipEvent_t e = ctx->ev_pool[ctx->ev_used++];
+  if (hipEventRecord(e, ctx->stream) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_pair(pic_ctx* ctx, int cls, hipEvent_t a, hipEvent_t b) {
+  if (a && b) ctx->ev_pairs[cls].push_back({a, b});
+}
+
+// rho_cur <- deposit of the current particles (used after loading or set_state)
+int deposit_current(pic_ctx* ctx, Replica& R) {
+  hipStream_t st = ctx->stream;
+  if (R.prec == PIC_FP64) {
+    launch_zero_f64((double*)R.rho[R.rho_cur], R.nn, st);
+    for (int sp = 0; sp < 2; ++sp)
+      launch_deposit_f64(R.p64[sp][R.cur], R.d_n + 2 * sp + R.cur, (double*)R.rho[R.rho_cur],
+                         species_step(R, sp), R.cap[sp], st);
+  } else {
+    launch_zero_i64((long long*)R.rho[R.rho_cur], R.nn, st);
+    for (int sp = 0; sp < 2; ++sp)
+      launch_deposit_f32r(R.p32[sp][R.cur], R.d_n + 2 * sp + R.cur, (long long*)R.rho[R.rho_cur],
+                          species_step(R, sp), R.cap[sp], st);
+  }
+  CHECK_LAUNCH(ctx);
+  return PIC_OK;
+}
+
+// phi_k and E_k from rho_k, the grains' charges and V(t_k); also freezes Q_g
+int solve_fields(pic_ctx* ctx, Replica& R) {
+  hipStream_t st = ctx->stream;
+  const pic_config& c = R.cfg;
+  const double V = rf_voltage(c, R.step);
+  const double vol = c.dx * c.dx * c.dx;
+  if (R.prec == PIC_FP64) {
+    const double scale = -c.dx * c.dx / kEps0 * (R.we / vol);
+    launch_rhs_f64((const double*)R.rho[R.rho_cur], scale, R.b, R.nx, R.ny, R.nz, st);
+    launch_grain_rhs(R.d_gc, R.md.gpos, c.n_grains, R.nx, R.ny, R.nz, R.we, R.d_Q, R.b, scale, 0,
+                     R.Qp, st);
+    launch_solve_f64(R.fft, R.nx, R.ny, R.nz, R.b, R.work, R.tw_x, R.tw_y, R.inv, R.phi, V, st);
+    launch_efield_f64(R.phi, (double*)R.E, R.nx, R.ny, R.nz, c.dx, st);
+  } else {
+    const double scale = -c.dx * c.dx / kEps0 * (kCharge / 4294967296.0 / vol);
+    launch_rhs_fixed((const long long*)R.rho[R.rho_cur], scale, R.b, R.nx, R.ny, R.nz, st);
+    launch_grain_rhs(R.d_gc, R.md.gpos, c.n_grains, R.nx, R.ny, R.nz, R.we, R.d_Q, R.b, scale, 1,
+                     R.Qp, st);
+    launch_solve_refined(R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y, R.inv,
+                         R.phi, V, c.max_refine, R.norms, st);
+    launch_efield_f32(R.phi, (float*)R.E, R.nx, R.ny, R.nz, c.dx, st);
+  }
+  CHECK_LAUNCH(ctx);
+  return PIC_OK;
+}
+
+int step_replica(pic_ctx* ctx, Replica& R) {
+  hipStream_t st = ctx->stream;
+  hipEvent_t f0 = prof_event(ctx);
+  TRY(solve_fields(ctx, R));
+  prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
+  const int nxt = 1 - R.cur, rnx = 1 - R.rho_cur;
+  for (int sp = 0; sp < 2; ++sp) launch_zero_i32(R.d_n + 2 * sp + nxt, 1, st);
+  const int do_mcc = 1;
+  if (R.prec == PIC_FP64) {
+    launch_zero_f64((double*)R.rho[rnx], R.nn, st);
+    for (int sp = 0; sp < 2; ++sp) {
+      hipEvent_t a = prof_event(ctx);
+      launch_push_f64(R.p64[sp][R.cur], R.p64[sp][nxt], R.d_n + 2 * sp + R.cur,
+                      R.d_n + 2 * sp + nxt, (const double*)R.E, (double*)R.rho[rnx], R.md,
+                      species_step(R, sp), R.d_T, R.d_gc, do_mcc, R.cap[sp], st);
+      prof_pair(ctx, PIC_PROF_PUSH, a, prof_event(ctx));
+    }
+  } else {
+    launch_zero_i64((long long*)R.rho[rnx], R.nn, st);
+    for (int sp = 0; sp < 2; ++sp) {
+      hipEvent_t a = prof_event(ctx);
+      launch_push_f32r(R.p32[sp][R.cur], R.p32[sp][nxt], R.d_n + 2 * sp + R.cur,
+                       R.d_n + 2 * sp + nxt, (const float*)R.E, (long long*)R.rho[rnx], R.md,
+                       species_step(R, sp), R.d_T, R.d_gc, do_mcc, R.cap[sp], st);
+      prof_pair(ctx, PIC_PROF_PUSH, a, prof_event(ctx));
+    }
+  }
+  CHECK_LAUNCH(ctx);
+  R.cur = nxt;
+  R.rho_cur = rnx;
+  R.step += 1;
+  if (R.cfg.sort_interval > 0 && ++R.since_sort >= R.cfg.sort_interval) {
+    R.since_sort = 0;
+    const int o = 1 - R.cur;
+    hipEvent_t s0 = prof_event(ctx);
+    for (int sp = 0; sp < 2; ++sp) {
+      HIPCHK(ctx, hipMemcpyAsync(R.d_n + 2 * sp + o, R.d_n + 2 * sp + R.cur, sizeof(int),
+                                 hipMemcpyDeviceToDevice, st));
+      if (R.prec == PIC_FP64)
+        launch_sort_f64(R.p64[sp][R.cur], R.p64[sp][o], R.d_n + 2 * sp + R.cur, R.d_hist,
+                        R.d_sums, R.ncell, R.nx, R.ny, R.cap[sp], st);
+      else
+        launch_sort_f32r(R.p32[sp][R.cur], R.p32[sp][o], R.d_n + 2 * sp + R.cur, R.d_hist,
+                         R.d_sums, R.ncell, R.nx, R.ny, R.cap[sp], st);
+    }
+    CHECK_LAUNCH(ctx);
+    prof_pair(ctx, PIC_PROF_SORT, s0, prof_event(ctx));
+    R.cur = o;
+  }
+  return PIC_OK;
+}
+
+int unit_fields(pic_ctx* ctx, Replica& R) {
+  const pic_config& c = R.cfg;
+  const int ng = c.n_grains;
+  if (ng == 0) return PIC_OK;
+  hipStream_t st = ctx->stream;
+  // FP64 solver resources for the unit-charge solves (the FP32R form uses them only here)
+  void *tw_x = R.tw_x, *tw_y = R.tw_y, *inv = R.inv, *work = R.work;
+  double* E = (double*)R.E;
+  if (R.prec != PIC_FP64) {
+    TRY(setup_solver_tables<double>(ctx, R, &tw_x, &tw_y, &inv));
+    double2* w2;
+    TRY(dalloc(ctx, R, &w2, R.n_int));
+    work = w2;
+    TRY(dalloc(ctx, R, &E, 2 * 2 * R.nn));
+  }
+  const double scale = -c.dx * c.dx / kEps0 / (c.dx * c.dx * c.dx);
+  for (int g = 0; g < ng; ++g) {
+    launch_zero_f64(R.b, R.n_int, st);
+    launch_unit_rhs(R.md.gpos, g, R.nx, R.ny, R.nz, scale, R.b, st);
+    launch_solve_f64(R.fft, R.nx, R.ny, R.nz, R.b, work, tw_x, tw_y, inv, R.phi, 0.0, st);
+    launch_efield_f64(R.phi, E, R.nx, R.ny, R.nz, c.dx, st);
+    launch_extract_cube(E, R.md.gcell, g, c.pp_cutoff_cells, R.nx, R.ny,
+                        const_cast<double*>(R.md.U), st);
+  }
+  CHECK_LAUNCH(ctx);
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return PIC_OK;
+}
+
+int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
+  std::string why;
+  if (validate(cin, why) != PIC_OK) return fail(ctx, PIC_EINVAL, why);
+  R.cfg = cin;
+  R.gpos.assign(cin.grain_pos, cin.grain_pos + 3 * (size_t)cin.n_grains);
+  R.cfg.grain_pos = nullptr;
+  pic_config& c = R.cfg;
+  R.nx = c.nx;
+  R.ny = c.ny;
+  R.nz = c.nz;
+  R.nxy = (long)c.nx * c.ny;
+  R.ncell = R.nxy * c.nz;
+  R.nn = R.nxy * (c.nz + 1);
+  R.n_int = R.nxy * (c.nz - 1);
+  R.prec = c.precision;
+  // derived constants (Sec. III: one super-particle weight for both species)
+  R.w = c.n0 * c.dx * c.dx * c.dx / (double)c.ppc;
+  R.Qp = std::llround(R.w * 4294967296.0);
+  R.we = R.w * kCharge;
+  R.n_gas = c.p_gas_Pa / (kBoltz * c.T_gas_K);
+  R.q[0] = -kCharge;
+  R.q[1] = kCharge;
+  R.m[0] = kMassE;
+  R.m[1] = kMassAr;
+  R.vth[0] = std::sqrt(c.Te_eV * kCharge / kMassE);
+  R.vth[1] = std::sqrt(c.Ti_eV * kCharge / kMassAr);
+  const double sigma[2] = {c.sigma_e_el, c.sigma_i_cx};
+  for (int s = 0; s < 2; ++s) {
+    R.g_cap[s] = std::sqrt(2.0 * c.E_cap_eV * kCharge / R.m[s]);
+    const double nu_max = R.n_gas * sigma[s] * R.g_cap[s];
+    R.P_null[s] = -std::expm1(-nu_max * c.dt);
+    R.T_null[s] = (uint64_t)std::floor(R.P_null[s] * 4294967296.0);
+  }
+  R.vth_gas = std::sqrt(kBoltz * c.T_gas_K / kMassAr);
+  R.cap[0] = R.cap[1] = R.ncell * c.ppc;
+  if (!factor_len(R.nx, R.fft.fac_x, &R.fft.nfac_x) || !factor_len(R.ny, R.fft.fac_y, &R.fft.nfac_y))
+    return fail(ctx, PIC_EINVAL, "FFT length not supported");
+  R.fft.L_x = lines_per_block(R.nx, R.ny);
+  R.fft.L_y = lines_per_block(R.ny, R.nx);
+
+  hipStream_t st = ctx->stream;
+  TRY(alloc_particles(ctx, R));
+  if (R.prec == PIC_FP64) {
+    double *r0, *r1;
+    TRY(dalloc(ctx, R, &r0, R.nn));
+    TRY(dalloc(ctx, R, &r1, R.nn));
+    R.rho[0] = r0;
+    R.rho[1] = r1;
+    double* E;
+    TRY(dalloc(ctx, R, &E, 4 * R.nn));
+    R.E = E;
+    double2* w;
+    TRY(dalloc(ctx, R, &w, R.n_int));
+    R.work = w;
+    TRY(setup_solver_tables<double>(ctx, R, &R.tw_x, &R.tw_y, &R.inv));
+  } else {
+    long long *r0, *r1;
+    TRY(dalloc(ctx, R, &r0, R.nn));
+    TRY(dalloc(ctx, R, &r1, R.nn));
+    R.rho[0] = r0;
+    R.rho[1] = r1;
+    float* E;
+    TRY(dalloc(ctx, R, &E, 4 * R.nn));
+    R.E = E;
+    float2* w;
+    TRY(dalloc(ctx, R, &w, R.n_int));
+    R.work = w;
+    TRY(setup_solver_tables<float>(ctx, R, &R.tw_x, &R.tw_y, &R.inv));
+    TRY(dalloc(ctx, R, &R.psi, R.n_int));
+    TRY(dalloc(ctx, R, &R.r, R.n_int));
+  }
+  TRY(dalloc(ctx, R, &R.b, R.n_int));
+  TRY(dalloc(ctx, R, &R.phi, R.nn));
+  TRY(dalloc(ctx, R, &R.norms, 2));
+  TRY(dalloc(ctx, R, &R.d_T, 1));
+  TRY(dalloc(ctx, R, &R.d_gc, 2 * std::max(c.n_grains, 1)));
+  TRY(dalloc(ctx, R, &R.d_hist, R.ncell));
+  TRY(dalloc(ctx, R, &R.d_sums, (R.ncell + 1023) / 1024 + 1));
+  HIPCHK(ctx, hipMemsetAsync(R.d_T, 0, sizeof(Tallies), st));
+  HIPCHK(ctx, hipMemsetAsync(R.d_gc, 0, 16 * std::max(c.n_grains, 1), st));
+  HIPCHK(ctx, hipMemsetAsync(R.norms, 0, 16, st));
+  TRY(setup_md(ctx, R));
+  TRY(unit_fields(ctx, R));
+
+  // load: ppc particles per cell, Maxwellian, Philox keyed by the seed
+  const uint32_t k0 = (uint32_t)(c.seed & 0xffffffffu), k1 = (uint32_t)(c.seed >> 32);
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = (int)R.cap[sp];
+    if (R.prec == PIC_FP64)
+      launch_init_f64(R.p64[sp][0], n, c.ppc, R.nx, R.ny, sp, k0, k1, R.vth[sp], st);
+    else
+      launch_init_f32r(R.p32[sp][0], n, c.ppc, sp, k0, k1, R.vth[sp], st);
+  }
+  CHECK_LAUNCH(ctx);
+  const int counts[4] = {(int)R.cap[0], 0, (int)R.cap[1], 0};
+  HIPCHK(ctx, hipMemcpyAsync(R.d_n, counts, sizeof(counts), hipMemcpyHostToDevice, st));
+  R.cur = 0;
+  R.rho_cur = 0;
+  R.step = 0;
+  TRY(deposit_current(ctx, R));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return PIC_OK;
+}
+
+Replica* get_rep(pic_ctx* ctx, int replica) {
+  if (!ctx || replica < 0 || replica >= (int)ctx->reps.size()) return nullptr;
+  return ctx->reps[replica].get();
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+int pic_init(const pic_config* cfgs, int n_replicas, void* hip_stream, pic_ctx** out) {
+  if (!out) return fail(nullptr, PIC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfgs || n_replicas < 1) return fail(nullptr, PIC_EINVAL, "no configuration given");
+  std::unique_ptr<pic_ctx> ctx(new (std::nothrow) pic_ctx());
+  if (!ctx) return fail(nullptr, PIC_ENOMEM, "host allocation failed");
+  ctx->stream = (hipStream_t)hip_stream;
+  for (int r = 0; r < n_replicas; ++r) {
+    std::unique_ptr<Replica> R(new (std::nothrow) Replica());
+    if (!R) return fail(nullptr, PIC_ENOMEM, "host allocation failed");
+    int rc = init_replica(ctx.get(), *R, cfgs[r]);
+    if (rc != PIC_OK) {
+      g_init_error = "replica " + std::to_string(r) + ": " + ctx->err;
+      return rc;
+    }
+    ctx->reps.push_back(std::move(R));
+  }
+  *out = ctx.release();
+  return PIC_OK;
+}
+
+int pic_step(pic_ctx* ctx, int n_steps) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  if (n_steps < 0) return fail(ctx, PIC_EINVAL, "n_steps < 0");
+  for (int s = 0; s < n_steps; ++s)
+    for (auto& R : ctx->reps) TRY(step_replica(ctx, *R));
+  return PIC_OK;
+}
+
+int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
+  const int ng = R->cfg.n_grains;
+  if (ng == 0) return PIC_OK;
+  if (!counts) return fail(ctx, PIC_EINVAL, "counts is NULL");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(counts, R->d_gc, 16 * ng, hipMemcpyDeviceToHost));
+  if (Q_C)
+    for (int g = 0; g < ng; ++g) Q_C[g] = (double)(counts[2 * g + 1] - counts[2 * g]) * R->we;
+  return PIC_OK;
+}
+
+int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int out_on_device) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
+  if (!out || (what & ~15u)) return fail(ctx, PIC_EINVAL, "bad selection or out");
+  if ((what & PIC_RHO_FIXED) && R->prec != PIC_FP32R)
+    return fail(ctx, PIC_EINVAL, "PIC_RHO_FIXED needs the FP32R form");
+  hipStream_t st = ctx->stream;
+  TRY(solve_fields(ctx, *R));
+  const long nn = R->nn;
+  if (!R->tot64) TRY(dalloc(ctx, *R, &R->tot64, nn));
+  if (!R->totfx) TRY(dalloc(ctx, *R, &R->totfx, nn));
+  if (!R->eout) TRY(dalloc(ctx, *R, &R->eout, 3 * nn));
+  const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  int slot = 0;
+  const double vol = R->cfg.dx * R->cfg.dx * R->cfg.dx;
+  for (unsigned bit = 1; bit <= PIC_RHO_FIXED; bit <<= 1) {
+    if (!(what & bit)) continue;
+    void* dst = out[slot++];
+    if (!dst) return fail(ctx, PIC_EINVAL, "NULL output buffer");
+    if (bit == PIC_PHI) {
+      HIPCHK(ctx, hipMemcpyAsync(dst, R->phi, nn * 8, kind, st));
+    } else if (bit == PIC_E) {
+      launch_e_out(R->prec == PIC_FP64 ? (const double*)R->E : nullptr,
+                   R->prec == PIC_FP64 ? nullptr : (const float*)R->E, R->eout, nn, st);
+      HIPCHK(ctx, hipMemcpyAsync(dst, R->eout, 3 * nn * 8, kind, st));
+    } else {
+      if (R->prec == PIC_FP64) {
+        launch_rho_total((const double*)R->rho[R->rho_cur], nullptr, R->tot64, nullptr, R->d_gc,
+                         R->md.gpos, R->cfg.n_grains, R->nx, R->ny, nn, R->Qp, st);
+        launch_scale(R->tot64, nullptr, R->we / vol, R->tot64, nn, st);
+      } else {
+        launch_rho_total(nullptr, (const long long*)R->rho[R->rho_cur], nullptr, R->totfx,
+                         R->d_gc, R->md.gpos, R->cfg.n_grains, R->nx, R->ny, nn, R->Qp, st);
+        launch_scale(nullptr, R->totfx, kCharge / 4294967296.0 / vol, R->tot64, nn, st);
+      }
+      if (bit == PIC_RHO)
+        HIPCHK(ctx, hipMemcpyAsync(dst, R->tot64, nn * 8, kind, st));
+      else
+        HIPCHK(ctx, hipMemcpyAsync(dst, R->totfx, nn * 8, kind, st));
+    }
+    CHECK_LAUNCH(ctx);
+  }
+  if (!out_on_device) HIPCHK(ctx, hipStreamSynchronize(st));
+  return PIC_OK;
+}
+
+void pic_destroy(pic_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+const char* pic_last_error(const pic_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+int pic_get_state(pic_ctx* ctx, int replica, pic_state_view* v) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R || !v) return fail(ctx, PIC_EINVAL, "bad replica or view");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  int n[4];
+  HIPCHK(ctx, hipMemcpy(n, R->d_n, sizeof(n), hipMemcpyDeviceToHost));
+  for (int sp = 0; sp < 2; ++sp) {
+    const long cnt = n[2 * sp + R->cur];
+    if (cnt > v->capacity[sp]) return fail(ctx, PIC_EINVAL, "view capacity too small");
+    if (cnt > 0 && (!v->pos[sp] || !v->vel[sp] || !v->id[sp]))
+      return fail(ctx, PIC_EINVAL, "NULL view array");
+    v->n[sp] = cnt;
+    if (cnt == 0) continue;
+    HIPCHK(ctx, hipMemcpy(v->id[sp], R->prec == PIC_FP64 ? R->p64[sp][R->cur].id
+                                                          : R->p32[sp][R->cur].id,
+                          cnt * 4, hipMemcpyDeviceToHost));
+    if (R->prec == PIC_FP64) {
+      const PartF64& P = R->p64[sp][R->cur];
+      std::vector<double> a(cnt);
+      double* src[6] = {P.x, P.y, P.z, P.vx, P.vy, P.vz};
+      for (int q = 0; q < 6; ++q) {
+        HIPCHK(ctx, hipMemcpy(a.data(), src[q], cnt * 8, hipMemcpyDeviceToHost));
+        double* dst = q < 3 ? v->pos[sp] : v->vel[sp];
+        for (long i = 0; i < cnt; ++i) dst[3 * i + q % 3] = a[i];
+      }
+    } else {
+      const PartF32R& P = R->p32[sp][R->cur];
+      std::vector<int32_t> cell(cnt);
+      std::vector<float> a(cnt);
+      HIPCHK(ctx, hipMemcpy(cell.data(), P.cell, cnt * 4, hipMemcpyDeviceToHost));
+      for (long i = 0; i < cnt; ++i) {
+        const int k = (int)(cell[i] / R->nxy), rem = (int)(cell[i] - k * R->nxy);
+        v->pos[sp][3 * i + 0] = rem % R->nx;
+        v->pos[sp][3 * i + 1] = rem / R->nx;
+        v->pos[sp][3 * i + 2] = k;
+      }
+      float* src[6] = {P.ox, P.oy, P.oz, P.vx, P.vy, P.vz};
+      for (int q = 0; q < 6; ++q) {
+        HIPCHK(ctx, hipMemcpy(a.data(), src[q], cnt * 4, hipMemcpyDeviceToHost));
+        for (long i = 0; i < cnt; ++i) {
+          if (q < 3) v->pos[sp][3 * i + q] += (double)a[i];
+          else v->vel[sp][3 * i + q - 3] = (double)a[i];
+        }
+      }
+    }
+  }
+  Tallies T;
+  HIPCHK(ctx, hipMemcpy(&T, R->d_T, sizeof(T), hipMemcpyDeviceToHost));
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) v->wall_count[a][b] = (int64_t)T.wall[a][b];
+  if (v->grain_count && R->cfg.n_grains > 0)
+    HIPCHK(ctx, hipMemcpy(v->grain_count, R->d_gc, 16 * R->cfg.n_grains, hipMemcpyDeviceToHost));
+  v->step = R->step;
+  return PIC_OK;
+}
+
+int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R || !v) return fail(ctx, PIC_EINVAL, "bad replica or view");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (int sp = 0; sp < 2; ++sp) {
+    const long cnt = v->n[sp];
+    if (cnt < 0 || cnt > R->cap[sp]) return fail(ctx, PIC_EINVAL, "n exceeds the capacity");
+    if (cnt > 0 && (!v->pos[sp] || !v->vel[sp] || !v->id[sp]))
+      return fail(ctx, PIC_EINVAL, "NULL view array");
+    for (long i = 0; i < cnt; ++i) {
+      const double* x = &v->pos[sp][3 * i];
+      const double* u = &v->vel[sp][3 * i];
+      const bool ok = x[0] >= 0 && x[0] < R->nx && x[1] >= 0 && x[1] < R->ny && x[2] >= 0 &&
+                      x[2] < R->nz && std::isfinite(u[0]) && std::isfinite(u[1]) &&
+                      std::isfinite(u[2]);
+      if (!ok) return fail(ctx, PIC_ENUMERIC, "particle outside the box or not finite");
+    }
+  }
+  R->cur = 0;
+  R->rho_cur = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const long cnt = v->n[sp];
+    if (cnt == 0) continue;
+    if (R->prec == PIC_FP64) {
+      const PartF64& P = R->p64[sp][0];
+      std::vector<double> a(cnt);
+      double* dst[6] = {P.x, P.y, P.z, P.vx, P.vy, P.vz};
+      for (int q = 0; q < 6; ++q) {
+        const double* src = q < 3 ? v->pos[sp] : v->vel[sp];
+        for (long i = 0; i < cnt; ++i) a[i] = src[3 * i + q % 3];
+        HIPCHK(ctx, hipMemcpy(dst[q], a.data(), cnt * 8, hipMemcpyHostToDevice));
+      }
+      HIPCHK(ctx, hipMemcpy(P.id, v->id[sp], cnt * 4, hipMemcpyHostToDevice));
+    } else {
+      const PartF32R& P = R->p32[sp][0];
+      std::vector<int32_t> cell(cnt);
+      std::vector<float> a(6 * cnt);
+      for (long i = 0; i < cnt; ++i) {
+        int c3[3];
+        for (int q = 0; q < 3; ++q) {
+          const double x = v->pos[sp][3 * i + q];
+          int ci = (int)std::floor(x);
+          float f = (float)(x - ci);
+          const int nq = q == 0 ? R->nx : (q == 1 ? R->ny : R->nz);
+          if (f >= 1.0f) {  // rounding up to the next cell
+            f = 0.0f;
+            ci += 1;
+            if (q < 2 && ci == nq) ci = 0;
+            if (q == 2 && ci == nq) return fail(ctx, PIC_ENUMERIC, "particle rounds onto z = L_z");
+          }
+          c3[q] = ci;
+          a[q * cnt + i] = f;
+          a[(3 + q) * cnt + i] = (float)v->vel[sp][3 * i + q];
+        }
+        cell[i] = c3[0] + R->nx * (c3[1] + R->ny * c3[2]);
+      }
+      HIPCHK(ctx, hipMemcpy(P.cell, cell.data(), cnt * 4, hipMemcpyHostToDevice));
+      float* dst[6] = {P.ox, P.oy, P.oz, P.vx, P.vy, P.vz};
+      for (int q = 0; q < 6; ++q)
+        HIPCHK(ctx, hipMemcpy(dst[q], a.data() + q * cnt, cnt * 4, hipMemcpyHostToDevice));
+      HIPCHK(ctx, hipMemcpy(P.id, v->id[sp], cnt * 4, hipMemcpyHostToDevice));
+    }
+  }
+  const int counts[4] = {(int)v->n[0], 0, (int)v->n[1], 0};
+  HIPCHK(ctx, hipMemcpy(R->d_n, counts, sizeof(counts), hipMemcpyHostToDevice));
+  Tallies T{};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) T.wall[a][b] = (unsigned long long)v->wall_count[a][b];
+  HIPCHK(ctx, hipMemcpy(R->d_T, &T, sizeof(T), hipMemcpyHostToDevice));
+  const int ng = R->cfg.n_grains;
+  if (ng > 0) {
+    std::vector<int64_t> gc(2 * ng, 0);
+    if (v->grain_count) std::copy(v->grain_count, v->grain_count + 2 * ng, gc.begin());
+    HIPCHK(ctx, hipMemcpy(R->d_gc, gc.data(), 16 * ng, hipMemcpyHostToDevice));
+  }
+  R->step = v->step;
+  R->since_sort = 0;
+  TRY(deposit_current(ctx, *R));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return PIC_OK;
+}
+
+int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R || !out) return fail(ctx, PIC_EINVAL, "bad replica or out");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  int n[4];
+  Tallies T;
+  double norms[2] = {0, 0};
+  HIPCHK(ctx, hipMemcpy(n, R->d_n, sizeof(n), hipMemcpyDeviceToHost));
+  HIPCHK(ctx, hipMemcpy(&T, R->d_T, sizeof(T), hipMemcpyDeviceToHost));
+  HIPCHK(ctx, hipMemcpy(norms, R->norms, sizeof(norms), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  for (int sp = 0; sp < 2; ++sp) {
+    out->n_alive[sp] = n[2 * sp + R->cur];
+    out->cap_violation[sp] = (int64_t)T.cap_viol[sp];
+    out->n_collisions[sp] = (int64_t)T.n_coll[sp];
+    out->md_particles[sp] = (int64_t)T.md[sp];
+    for (int a = 0; a < 2; ++a) out->wall_count[a][sp] = (int64_t)T.wall[a][sp];
+  }
+  out->step = R->step;
+  out->refine_sweeps = R->prec == PIC_FP32R ? R->cfg.max_refine : 0;
+  out->refine_residual = norms[1] > 0 ? std::sqrt(norms[0] / norms[1]) : std::sqrt(norms[0]);
+  return PIC_OK;
+}
+
+int pic_profile_enable(pic_ctx* ctx, int on) {
+  if (!ctx) return PIC_EINVAL;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->prof = on != 0;
+  ctx->ev_used = 0;
+  for (auto& v : ctx->ev_pairs) v.clear();
+  return PIC_OK;
+}
+
+int pic_profile_read(pic_ctx* ctx, int cls, double* total_ms, int64_t* launches) {
+  if (!ctx) return PIC_EINVAL;
+  if (cls < 0 || cls > 2 || !total_ms || !launches) return fail(ctx, PIC_EINVAL, "bad arguments");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  for (auto& p : ctx->ev_pairs[cls]) {
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, p.first, p.second));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)ctx->ev_pairs[cls].size();
+  return PIC_OK;
+}
+
+int pic_derived(pic_ctx* ctx, int replica, double out[7]) {
+  if (!ctx) return PIC_EINVAL;
+  Replica* R = get_rep(ctx, replica);
+  if (!R || !out) return fail(ctx, PIC_EINVAL, "bad replica or out");
+  out[0] = R->w;
+  out[1] = (double)R->Qp;
+  out[2] = R->n_gas;
+  out[3] = R->g_cap[0];
+  out[4] = R->g_cap[1];
+  out[5] = (double)R->T_null[0];
+  out[6] = (double)R->T_null[1];
+  return PIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// pic_types.hpp -- plain-data structures shared by the library's host code and
+// its HIP kernels (passed to kernels by value).
+#pragma once
+#include <cstdint>
+
+namespace pic {
+
+// CODATA 2018
+constexpr double kCharge = 1.602176634e-19;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kBoltz = 1.380649e-23;
+constexpr double kMassE = 9.1093837015e-31;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kMassAr = 39.948 * kAmu;
+constexpr double kPi = 3.14159265358979323846;
+
+// Philox counter word 2: what a draw is for
+enum Purpose : uint32_t { kInitPos = 1, kInitVel = 2, kColl = 3, kNeutral = 4 };
+
+// particle arrays of one species, structure of arrays
+struct PartF64 {
+  double *x, *y, *z;      // cell units
+  double *vx, *vy, *vz;   // m/s
+  uint32_t* id;
+};
+struct PartF32R {
+  int32_t* cell;          // i + nx (j + ny k)
+  float *ox, *oy, *oz;    // offsets in [0, 1)
+  float *vx, *vy, *vz;    // m/s
+  uint32_t* id;
+};
+
+// tallies of one replica (device, int64 so atomics are exact)
+struct Tallies {
+  unsigned long long wall[2][2];     // [wall][species]
+  unsigned long long cap_viol[2];
+  unsigned long long n_coll[2];
+  unsigned long long md[2];
+  unsigned long long numeric_bad;
+};
+
+// near-grain (MD) tables of one replica
+struct MdTables {
+  int n_grains;
+  int cutoff;
+  int side;                // 2 cutoff + 2 nodes per cube edge
+  int bx0, by0, bz0;       // periodic bounding box of all MD cubes (cells)
+  int bsx, bsy, bsz;
+  const uint32_t* cell_list;  // [bsz][bsy][bsx]: (start << 8) | count
+  const int32_t* grain_idx;   // grain indices referenced by cell_list
+  const double* gpos;         // [g][3] cell units
+  const int32_t* gcell;       // [g][3] floor of gpos
+  const double* Q;            // [g] grain charge (C) frozen at the start of the step
+  const double* U;            // [g][3][side^3] unit-charge mesh field on the cube
+  double a2;                  // grain radius^2 (m^2)
+};
+
+// everything the particle kernels need for one species of one replica
+struct SpeciesStep {
+  int nx, ny, nz, nxy;
+  int sp;                  // 0 electron, 1 ion
+  int md_sub;
+  double dx;
+  double qm_dt, dt_dx;     // (q/m) dt, dt/dx
+  double qm_h, h_dx;       // the same for the MD sub-step h = dt / md_sub
+  double qm;               // q/m
+  float qm_dt_f, dt_dx_f;
+  // null-collision MCC
+  uint64_t T_null;         // candidate iff Philox word 0 < T_null
+  double inv_g_cap;
+  double vth_gas;
+  double mass_ratio_e;     // m_e / (m_e + M)
+  double mass_ratio_n;     // M / (m_e + M)
+  uint32_t key0, key1, step;
+  // deposit
+  int64_t Qp;              // macro charge, 2^-32 e
+  double sign;             // -1 electrons, +1 ions
+  long long isign;
+};
+
+}  // namespace pic

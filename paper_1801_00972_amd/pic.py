@@ -1,0 +1,314 @@
+"""ctypes binding of include/pic.h (argument marshalling only).
+
+Every function named pic_* here calls the C function of the same name in the
+in-tree HIP library libpic.so; all arithmetic runs in its kernels.  There is no
+fallback: if the library is missing this module raises on first use.
+PyTorch supplies the HIP stream and, optionally, device output tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpic.so")
+
+PIC_OK, PIC_EINVAL, PIC_ECONFIG, PIC_ENOMEM, PIC_EDEVICE, PIC_ENUMERIC, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PIC_FP64, PIC_FP32R = 0, 1
+PIC_PHI, PIC_E, PIC_RHO, PIC_RHO_FIXED = 1, 2, 4, 8
+
+SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destroy",
+           "pic_last_error", "pic_get_state", "pic_set_state", "pic_get_counters", "pic_derived",
+           "pic_profile_enable", "pic_profile_read")
+PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT = 0, 1, 2
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class pic_config(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("ppc", C.c_int32), ("n_grains", C.c_int32), ("pp_cutoff_cells", C.c_int32),
+        ("md_subcycles", C.c_int32), ("precision", C.c_int32), ("max_refine", C.c_int32),
+        ("sort_interval", C.c_int32),
+        ("dx", C.c_double), ("dt", C.c_double), ("n0", C.c_double),
+        ("Te_eV", C.c_double), ("Ti_eV", C.c_double),
+        ("p_gas_Pa", C.c_double), ("T_gas_K", C.c_double),
+        ("sigma_e_el", C.c_double), ("sigma_i_cx", C.c_double),
+        ("V_dc", C.c_double), ("V_rf", C.c_double), ("f_rf", C.c_double),
+        ("grain_radius", C.c_double), ("E_cap_eV", C.c_double), ("refine_tol", C.c_double),
+        ("seed", C.c_uint64),
+        ("grain_pos", C.POINTER(C.c_double)),
+    ]
+
+
+class pic_state_view(C.Structure):
+    _fields_ = [
+        ("capacity", C.c_int64 * 2), ("n", C.c_int64 * 2),
+        ("pos", C.POINTER(C.c_double) * 2), ("vel", C.POINTER(C.c_double) * 2),
+        ("id", C.POINTER(C.c_uint32) * 2),
+        ("grain_count", C.POINTER(C.c_int64)),
+        ("wall_count", (C.c_int64 * 2) * 2),
+        ("step", C.c_uint32), ("pad0", C.c_uint32),
+    ]
+
+
+class pic_counters(C.Structure):
+    _fields_ = [
+        ("n_alive", C.c_int64 * 2), ("wall_count", (C.c_int64 * 2) * 2),
+        ("cap_violation", C.c_int64 * 2), ("n_collisions", C.c_int64 * 2),
+        ("md_particles", C.c_int64 * 2),
+        ("step", C.c_uint32), ("refine_sweeps", C.c_int32), ("refine_residual", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.pic_init.argtypes = [C.POINTER(pic_config), C.c_int, P, C.POINTER(P)]
+        L.pic_step.argtypes = [P, C.c_int]
+        L.pic_grain_charges.argtypes = [P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.pic_fields.argtypes = [P, C.c_int, C.c_uint, C.POINTER(P), C.c_int]
+        L.pic_destroy.argtypes = [P]
+        L.pic_destroy.restype = None
+        L.pic_last_error.argtypes = [P]
+        L.pic_last_error.restype = C.c_char_p
+        L.pic_get_state.argtypes = [P, C.c_int, C.POINTER(pic_state_view)]
+        L.pic_set_state.argtypes = [P, C.c_int, C.POINTER(pic_state_view)]
+        L.pic_get_counters.argtypes = [P, C.c_int, C.POINTER(pic_counters)]
+        L.pic_derived.argtypes = [P, C.c_int, C.POINTER(C.c_double)]
+        L.pic_profile_enable.argtypes = [P, C.c_int]
+        L.pic_profile_read.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        for name in ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_get_state",
+                     "pic_set_state", "pic_get_counters", "pic_derived", "pic_profile_enable",
+                     "pic_profile_read"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != PIC_OK:
+        msg = lib().pic_last_error(ctx)
+        raise PicError(rc, msg.decode() if msg else "error")
+
+
+def make_config(wl: dict, sort_interval: int = 16, max_refine: int = 2):
+    """pic_config from a workload dict; returns (config, keep-alive arrays)."""
+    g = np.ascontiguousarray(np.asarray(wl.get("grain_pos", np.zeros((0, 3))), np.float64).reshape(-1, 3))
+    c = pic_config()
+    c.nx, c.ny, c.nz = int(wl["nx"]), int(wl["ny"]), int(wl["nz"])
+    c.ppc = int(wl["ppc"])
+    c.n_grains = g.shape[0]
+    c.pp_cutoff_cells = int(wl.get("cutoff", 3))
+    c.md_subcycles = int(wl.get("md_sub", 40))
+    prec = wl.get("precision", "fp64")
+    c.precision = PIC_FP32R if prec == "fp32r" else PIC_FP64
+    c.max_refine = int(wl.get("max_refine", max_refine))
+    c.sort_interval = int(wl.get("sort_interval", sort_interval))
+    c.dx, c.dt, c.n0 = float(wl["dx"]), float(wl["dt"]), float(wl["n0"])
+    c.Te_eV, c.Ti_eV = float(wl["Te_eV"]), float(wl["Ti_eV"])
+    c.p_gas_Pa, c.T_gas_K = float(wl["p_gas"]), float(wl["T_gas"])
+    c.sigma_e_el, c.sigma_i_cx = float(wl["sigma_e"]), float(wl["sigma_i"])
+    c.V_dc, c.V_rf, c.f_rf = float(wl["V_dc"]), float(wl["V_rf"]), float(wl["f_rf"])
+    c.grain_radius = float(wl["grain_radius"])
+    c.E_cap_eV = float(wl["E_cap_eV"])
+    c.refine_tol = float(wl.get("refine_tol", 1e-10))
+    c.seed = int(wl.get("seed", 0))
+    c.grain_pos = g.ctypes.data_as(C.POINTER(C.c_double))
+    return c, g
+
+
+def current_stream():
+    """The torch current HIP stream handle (None without a GPU)."""
+    import torch
+    if torch.cuda.is_available():
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return None
+
+
+# ---------------------------------------------------------------- C names
+def pic_init(cfgs, n_replicas, hip_stream=None):
+    arr = (pic_config * n_replicas)(*cfgs)
+    out = C.c_void_p()
+    rc = lib().pic_init(arr, n_replicas, hip_stream, C.byref(out))
+    _check(rc, None)
+    return out
+
+
+def pic_step(ctx, n_steps):
+    _check(lib().pic_step(ctx, int(n_steps)), ctx)
+
+
+def pic_grain_charges(ctx, replica, n_grains):
+    counts = np.zeros((n_grains, 2), np.int64)
+    Q = np.zeros(n_grains)
+    _check(lib().pic_grain_charges(ctx, replica, counts.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   Q.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+    return counts, Q
+
+
+def pic_fields(ctx, replica, what, outs, out_on_device=False):
+    """outs: list of buffers (numpy arrays or torch tensors) in PHI, E, RHO, RHO_FIXED order."""
+    ptrs = (C.c_void_p * len(outs))()
+    for i, o in enumerate(outs):
+        ptrs[i] = o.data_ptr() if hasattr(o, "data_ptr") else o.ctypes.data
+    _check(lib().pic_fields(ctx, replica, what, ptrs, 1 if out_on_device else 0), ctx)
+
+
+def pic_destroy(ctx):
+    lib().pic_destroy(ctx)
+
+
+def pic_last_error(ctx=None):
+    m = lib().pic_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def pic_get_state(ctx, replica, capacity, n_grains):
+    st = {}
+    v = pic_state_view()
+    bufs = []
+    for s in range(2):
+        pos = np.zeros((capacity[s], 3))
+        vel = np.zeros((capacity[s], 3))
+        ids = np.zeros(capacity[s], np.uint32)
+        bufs.append((pos, vel, ids))
+        v.capacity[s] = capacity[s]
+        v.pos[s] = pos.ctypes.data_as(C.POINTER(C.c_double))
+        v.vel[s] = vel.ctypes.data_as(C.POINTER(C.c_double))
+        v.id[s] = ids.ctypes.data_as(C.POINTER(C.c_uint32))
+    gc = np.zeros((max(n_grains, 1), 2), np.int64)
+    v.grain_count = gc.ctypes.data_as(C.POINTER(C.c_int64))
+    _check(lib().pic_get_state(ctx, replica, C.byref(v)), ctx)
+    for s in range(2):
+        n = v.n[s]
+        st[s] = dict(pos=bufs[s][0][:n].copy(), vel=bufs[s][1][:n].copy(), id=bufs[s][2][:n].copy())
+    st["grain_count"] = gc[:n_grains].copy()
+    st["wall_count"] = np.array([[v.wall_count[a][b] for b in range(2)] for a in range(2)])
+    st["step"] = int(v.step)
+    return st
+
+
+def pic_set_state(ctx, replica, state, n_grains):
+    v = pic_state_view()
+    keep = []
+    for s in range(2):
+        pos = np.ascontiguousarray(state[s]["pos"], np.float64).reshape(-1, 3)
+        vel = np.ascontiguousarray(state[s]["vel"], np.float64).reshape(-1, 3)
+        ids = np.ascontiguousarray(state[s]["id"], np.uint32)
+        keep += [pos, vel, ids]
+        v.n[s] = v.capacity[s] = len(ids)
+        v.pos[s] = pos.ctypes.data_as(C.POINTER(C.c_double))
+        v.vel[s] = vel.ctypes.data_as(C.POINTER(C.c_double))
+        v.id[s] = ids.ctypes.data_as(C.POINTER(C.c_uint32))
+    gc = np.ascontiguousarray(state.get("grain_count", np.zeros((n_grains, 2))), np.int64).reshape(-1)
+    if n_grains:
+        v.grain_count = gc.ctypes.data_as(C.POINTER(C.c_int64))
+    wc = np.asarray(state.get("wall_count", np.zeros((2, 2))), np.int64)
+    for a in range(2):
+        for b in range(2):
+            v.wall_count[a][b] = int(wc[a, b])
+    v.step = int(state.get("step", 0))
+    _check(lib().pic_set_state(ctx, replica, C.byref(v)), ctx)
+
+
+def pic_get_counters(ctx, replica):
+    c = pic_counters()
+    _check(lib().pic_get_counters(ctx, replica, C.byref(c)), ctx)
+    return dict(n_alive=list(c.n_alive), wall_count=[[c.wall_count[a][b] for b in range(2)] for a in range(2)],
+                cap_violation=list(c.cap_violation), n_collisions=list(c.n_collisions),
+                md_particles=list(c.md_particles), step=int(c.step),
+                refine_sweeps=int(c.refine_sweeps), refine_residual=float(c.refine_residual))
+
+
+def pic_derived(ctx, replica):
+    out = (C.c_double * 7)()
+    _check(lib().pic_derived(ctx, replica, out), ctx)
+    return dict(w=out[0], Qp=int(out[1]), n_gas=out[2], g_cap=[out[3], out[4]],
+                T_null=[int(out[5]), int(out[6])])
+
+
+def pic_profile_enable(ctx, on=True):
+    _check(lib().pic_profile_enable(ctx, 1 if on else 0), ctx)
+
+
+def pic_profile_read(ctx, kernel_class):
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(lib().pic_profile_read(ctx, kernel_class, C.byref(ms), C.byref(n)), ctx)
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------- convenience
+class Simulation:
+    """One context over one or more replicas (workload dicts)."""
+
+    def __init__(self, workloads, stream=None, sort_interval=16, max_refine=2):
+        if isinstance(workloads, dict):
+            workloads = [workloads]
+        self.wls = list(workloads)
+        made = [make_config(w, sort_interval=sort_interval, max_refine=max_refine) for w in self.wls]
+        self._keep = [m[1] for m in made]
+        self.ctx = pic_init([m[0] for m in made], len(made),
+                            stream if stream is not None else current_stream())
+        self.n_nodes = [w["nx"] * w["ny"] * (w["nz"] + 1) for w in self.wls]
+        self.n_grains = [m[1].shape[0] for m in made]
+        self.capacity = [w["nx"] * w["ny"] * w["nz"] * w["ppc"] for w in self.wls]
+
+    def step(self, n=1):
+        pic_step(self.ctx, n)
+
+    def fields(self, replica=0, what=PIC_PHI | PIC_E | PIC_RHO):
+        nn = self.n_nodes[replica]
+        outs, names = [], []
+        for bit, name, shape, dt in ((PIC_PHI, "phi", (nn,), np.float64), (PIC_E, "E", (3, nn), np.float64),
+                                     (PIC_RHO, "rho", (nn,), np.float64),
+                                     (PIC_RHO_FIXED, "rho_fixed", (nn,), np.int64)):
+            if what & bit:
+                outs.append(np.zeros(shape, dt))
+                names.append(name)
+        pic_fields(self.ctx, replica, what, outs, False)
+        return dict(zip(names, outs))
+
+    def get_state(self, replica=0):
+        cap = [self.capacity[replica]] * 2
+        return pic_get_state(self.ctx, replica, cap, self.n_grains[replica])
+
+    def set_state(self, state, replica=0):
+        pic_set_state(self.ctx, replica, state, self.n_grains[replica])
+
+    def counters(self, replica=0):
+        return pic_get_counters(self.ctx, replica)
+
+    def grain_charges(self, replica=0):
+        return pic_grain_charges(self.ctx, replica, self.n_grains[replica])
+
+    def derived(self, replica=0):
+        return pic_derived(self.ctx, replica)
+
+    def close(self):
+        if self.ctx:
+            pic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

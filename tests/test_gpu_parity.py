@@ -1,0 +1,217 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Same particle state on both sides (pic_set_state / the oracle's arrays), then
+ - the mesh quantities at step k: rho bit-exact in fixed point (FP32R) or to
+   1e-12 (FP64); phi and E to 1e-12 (FP64) or 1e-5 (FP32R), relative to the
+   largest value (phi: to max(|phi|, |V|));
+ - one full step: positions to 1e-12 / 1e-5 cells, velocities to 1e-12 /
+   1e-5 of max(|v|, v_th), survivors, electrode and grain tallies exact, except
+   where a discrete decision sits within the oracle's recorded margin.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_00972_amd import workloads as W
+from tests.parity_util import compare_step, oracle_from_state, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": dict(field=1e-12, pos=1e-12, vel=1e-12, margin=1e-12),
+       "fp32r": dict(field=1e-5, pos=1e-5, vel=1e-5, margin=1e-5)}
+
+
+def _sim(wl, **kw):
+    from paper_1801_00972_amd.pic import Simulation
+    print(f"[case] {wl['name']} {wl['precision']} {wl['nx']}x{wl['ny']}x{wl['nz']} ppc={wl['ppc']}",
+          flush=True)
+    return Simulation(wl, **kw)
+
+
+def _random_state(wl, n_e, n_i, seed, grain_count=None, step=0, near_grain=0):
+    """Seeded synthetic state: uniform positions, Maxwellian velocities, some
+    particles placed inside MD cubes and next to the electrodes."""
+    rng = np.random.default_rng(seed)
+    box = np.array([wl["nx"], wl["ny"], wl["nz"]], float)
+    e, me, mi = 1.602176634e-19, 9.1093837015e-31, 39.948 * 1.66053906660e-27
+    st = {}
+    for s, (n, T, m) in enumerate(((n_e, wl["Te_eV"], me), (n_i, wl["Ti_eV"], mi))):
+        pos = rng.random((n, 3)) * box
+        g = np.asarray(wl["grain_pos"]).reshape(-1, 3)
+        if near_grain and len(g):
+            k = min(near_grain, n)
+            pos[:k] = g[rng.integers(0, len(g), k)] + rng.uniform(-2.5, 2.5, (k, 3))
+            pos[:k, 0] %= box[0]
+            pos[:k, 1] %= box[1]
+        pos[-max(n // 20, 1):, 2] = rng.random(max(n // 20, 1)) * 0.2  # close to z = 0
+        if wl["precision"] == "fp32r":  # positions exactly representable as cell + float32 offset
+            c = np.floor(pos)
+            pos = c + (pos - c).astype(np.float32).astype(np.float64)
+            pos = np.where(pos >= box, c, pos)
+        vel = np.sqrt(T * e / m) * rng.standard_normal((n, 3))
+        if wl["precision"] == "fp32r":
+            vel = vel.astype(np.float32).astype(np.float64)
+        st[s] = dict(pos=pos, vel=vel, id=rng.permutation(n).astype(np.uint32) + 7)
+    ng = len(np.asarray(wl["grain_pos"]).reshape(-1, 3))
+    st["grain_count"] = np.zeros((ng, 2), np.int64) if grain_count is None else np.asarray(grain_count)
+    st["wall_count"] = np.zeros((2, 2), np.int64)
+    st["step"] = step
+    return st
+
+
+def _check_fields(wl, sim, orc):
+    tol = TOL[wl["precision"]]
+    fixed = wl["precision"] == "fp32r"
+    from paper_1801_00972_amd.pic import PIC_E, PIC_PHI, PIC_RHO, PIC_RHO_FIXED
+    what = PIC_PHI | PIC_E | PIC_RHO | (PIC_RHO_FIXED if fixed else 0)
+    g = sim.fields(0, what)
+    o = orc.fields(fixed_point=fixed)
+    if fixed:
+        assert np.array_equal(g["rho_fixed"], o["rho_fixed"]), "fixed-point deposit is not bit-exact"
+    assert rel_inf(g["rho"], o["rho"]) <= (1e-12 if not fixed else 1e-15)
+    V = abs(orc.rf_voltage(orc.step_index))
+    e_phi = rel_inf(g["phi"], o["phi"], floor=V)
+    e_E = rel_inf(g["E"], o["E"])
+    print(f"  fields: phi {e_phi:.2e}  E {e_E:.2e}", flush=True)
+    assert e_phi <= tol["field"]
+    assert e_E <= tol["field"]
+    return g, o
+
+
+CASES = [
+    # (workload factory, n_e, n_i, grain counts, step)
+    ("small", lambda p: dict(W.small_fp64(), precision=p), 3000, 2500, [[40, 7]], 123),
+    ("ragged", lambda p: W.tiny(nx=12, ny=10, nz=17, ppc=2, grains=[[0.3, 9.6, 8.5]], cutoff=2,
+                                precision=p), 1001, 777, [[3, 11]], 5),
+    ("no_grains", lambda p: W.tiny(nx=16, ny=48, nz=9, ppc=1, precision=p), 4097, 255, None, 0),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32r"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_fields_and_one_step(case, prec):
+    name, make, n_e, n_i, gc, step = case
+    wl = make(prec)
+    sim = _sim(wl)
+    st = _random_state(wl, n_e, n_i, seed=sum(map(ord, name)), grain_count=gc, step=step,
+                       near_grain=400)
+    sim.set_state(st)
+    back = sim.get_state()
+    # FP32R: the state the library actually holds (cell + float32 offset) is exact in FP64
+    orc = oracle_from_state(wl, back)
+    _check_fields(wl, sim, orc)
+    sim.step(1)
+    orc.step(1)
+    after = sim.get_state()
+    tol = TOL[prec]
+    rep = compare_step(wl, after, orc, tol["pos"], tol["vel"], tol["margin"])
+    print(f"  step: n={rep['n']} flips={rep['flips']} dpos={rep['max_dpos']:.2e} "
+          f"dvel={rep['max_dvel']:.2e}", flush=True)
+    assert rep["flips"] <= 2
+    assert np.abs(after["wall_count"] - orc.wall_count).sum() <= rep["flips"]
+    assert np.abs(after["grain_count"] - orc.grain_count).sum() <= rep["flips"]
+    assert after["step"] == orc.step_index
+    c = sim.counters()
+    assert c["md_particles"][0] + c["md_particles"][1] > 0 or not len(wl["grain_pos"])
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32r"])
+def test_loading_matches_oracle(prec):
+    wl = dict(W.small_fp64(), precision=prec)
+    sim = _sim(wl, sort_interval=0)
+    g = sim.get_state()
+    o = oracle.Oracle(wl)
+    o.init_particles()
+    for s in range(2):
+        order = np.argsort(g[s]["id"])
+        assert np.array_equal(g[s]["id"][order], o.id[s])
+        # offsets are 24-bit multiples: exact in both forms
+        assert np.array_equal(g[s]["pos"][order], o.pos[s])
+        v, ov = g[s]["vel"][order], o.vel[s]
+        if prec == "fp64":
+            assert np.max(np.abs(v - ov) / np.abs(ov).max()) < 1e-14
+        else:
+            assert np.max(np.abs(v - ov.astype(np.float32))) <= np.max(np.spacing(np.abs(ov).astype(np.float32)))
+    d_g, d_o = sim.derived(), o.derived()
+    assert d_g["Qp"] == d_o["Qp"] and d_g["T_null"] == d_o["T_null"]
+    assert d_g["w"] == d_o["w"]
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32r"])
+def test_ten_steps_from_loading(prec):
+    """Ten coupled steps from the same loaded state (rho, phi, push feed back)."""
+    wl = dict(W.small_fp64(), precision=prec)
+    sim = _sim(wl)
+    st = sim.get_state()
+    orc = oracle_from_state(wl, st)
+    tol = TOL[prec]
+    for k in range(10):
+        sim.step(1)
+        orc.step(1)
+        after = sim.get_state()
+        # the FP32R state is re-read each step so both sides stay on the same state
+        rep = compare_step(wl, after, orc, tol["pos"] * (10 if prec == "fp64" else 1), tol["vel"] * 10,
+                           tol["margin"] * 10)
+        assert rep["flips"] <= 3
+        orc = oracle_from_state(wl, after)
+    c = sim.counters()
+    n0 = 16 * 16 * 32 * 8
+    for s in range(2):
+        tot = c["n_alive"][s] + c["wall_count"][0][s] + c["wall_count"][1][s]
+        counts, _ = sim.grain_charges()
+        assert tot + counts[:, s].sum() == n0
+    sim.close()
+
+
+def test_fixed_point_total_charge_is_exact():
+    wl = W.small_fp32r()
+    sim = _sim(wl)
+    sim.step(20)
+    from paper_1801_00972_amd.pic import PIC_RHO_FIXED
+    f = sim.fields(0, PIC_RHO_FIXED)
+    c = sim.counters()
+    Qp = sim.derived()["Qp"]
+    lost = c["wall_count"][0][1] + c["wall_count"][1][1] - c["wall_count"][0][0] - c["wall_count"][1][0]
+    assert int(f["rho_fixed"].sum()) == -lost * Qp
+    sim.close()
+
+
+def test_fp32r_refinement_reaches_tolerance():
+    wl = W.small_fp32r()
+    sim = _sim(wl, max_refine=2)
+    sim.step(3)
+    c = sim.counters()
+    print("  refine residual", c["refine_residual"])
+    assert c["refine_residual"] <= 1e-10
+    sim.close()
+
+
+def test_determinism_fp32r_bitwise():
+    wl = W.small_fp32r()
+    a, b = _sim(wl), _sim(wl)
+    a.step(15)
+    b.step(15)
+    sa, sb = a.get_state(), b.get_state()
+    for s in range(2):
+        oa, ob = np.argsort(sa[s]["id"]), np.argsort(sb[s]["id"])
+        assert np.array_equal(sa[s]["pos"][oa], sb[s]["pos"][ob])
+        assert np.array_equal(sa[s]["vel"][oa], sb[s]["vel"][ob])
+    a.close()
+    b.close()
+
+
+def test_empty_species_and_bad_inputs():
+    from paper_1801_00972_amd.pic import PicError
+    wl = W.tiny(nx=8, ny=8, nz=10, ppc=1)
+    sim = _sim(wl)
+    st = _random_state(wl, 0, 5, seed=1)
+    sim.set_state(st)
+    sim.step(2)
+    assert sim.counters()["n_alive"][0] == 0
+    bad = _random_state(wl, 3, 0, seed=2)
+    bad[0]["pos"][1, 2] = wl["nz"] + 0.5
+    with pytest.raises(PicError):
+        sim.set_state(bad)
+    sim.close()
