@@ -35,14 +35,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(wl, steps, warmup):
+def run_form(wl, steps, warmup, sort_interval=16):
     import torch
 
-    from paper_1801_00972_amd.pic import (PIC_PROF_FIELD, PIC_PROF_PUSH, PIC_PROF_SORT,
-                                          Simulation, pic_profile_enable, pic_profile_read)
+    from paper_1801_00972_amd.pic import (PIC_PROF_FIELD, PIC_PROF_LISTS, PIC_PROF_PUSH,
+                                          PIC_PROF_SORT, Simulation, pic_profile_enable,
+                                          pic_profile_read)
 
     log(f"[bench] init {wl['name']}")
-    sim = Simulation(wl)
+    sim = Simulation(wl, sort_interval=sort_interval)
     torch.cuda.synchronize()
     log(f"[bench] warmup {warmup} steps")
     sim.step(warmup)
@@ -59,6 +60,7 @@ def run_form(wl, steps, warmup):
     push_ms, push_n = pic_profile_read(sim.ctx, PIC_PROF_PUSH)
     field_ms, _ = pic_profile_read(sim.ctx, PIC_PROF_FIELD)
     sort_ms, sort_n = pic_profile_read(sim.ctx, PIC_PROF_SORT)
+    lists_ms, _ = pic_profile_read(sim.ctx, PIC_PROF_LISTS)
     pic_profile_enable(sim.ctx, False)
     n_start, n_end = sum(c0["n_alive"]), sum(c1["n_alive"])
     particle_steps = 0.5 * (n_start + n_end) * steps
@@ -74,16 +76,41 @@ def run_form(wl, steps, warmup):
         push_ms_per_launch=push_ms / max(push_n, 1),
         push_launches=push_n,
         field_ms_per_step=field_ms / steps,
+        lists_ms_per_step=lists_ms / steps,
         sort_ms_total=sort_ms, sort_launches=sort_n,
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                       kernel="push_" + prec, bytes_per_launch=alg_bytes / max(push_n, 1)),
         refine_residual=c1["refine_residual"] if prec == "fp32r" else None,
+        tile_fallback_blocks=c1["tile_fallback"] - c0["tile_fallback"],
+        md_particle_steps=sum(c1["md_particles"]) - sum(c0["md_particles"]),
+        collisions=sum(c1["n_collisions"]) - sum(c0["n_collisions"]),
     )
     log(f"[bench] {prec}: {res['value']:.3e} particle-steps/s, {res['ms_per_step']:.3f} ms/step, "
         f"push {res['push_ms_per_launch']:.3f} ms/launch, {achieved:.0f} GB/s")
     sim.close()
     return res
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of nbytes (read nbytes + write nbytes),
+    timed with HIP events: the HBM bandwidth this machine reaches, and the
+    known-size kernel that calibrates the HBM byte counters."""
+    import torch
+
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return dict(bytes_per_copy=2 * nbytes, ms=ms, GBs=2 * nbytes / (ms * 1e-3) / 1e9)
 
 
 def cpu_baseline(wl, steps=2):
@@ -115,6 +142,7 @@ def main():
     ap.add_argument("--workload", choices=["full", "small"], default="full")
     ap.add_argument("--forms", default="fp32r,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sort-interval", type=int, default=16)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -132,7 +160,7 @@ def main():
     results = {}
     for form in forms:
         wl = W.full_fp64(form) if args.workload == "full" else dict(W.small_fp64(), precision=form)
-        results[form] = run_form(wl, args.steps, args.warmup)
+        results[form] = run_form(wl, args.steps, args.warmup, args.sort_interval)
     head = "fp32r" if "fp32r" in results else forms[0]
     wl = W.full_fp64(head) if args.workload == "full" else dict(W.small_fp64(), precision=head)
     R = results[head]
@@ -158,6 +186,7 @@ def main():
             "grains": int(len(wl["grain_pos"])),
             "pp_cutoff_cells": wl["cutoff"],
             "stated_err": {"fp32r": 1e-5, "fp64": 1e-12},
+            "sort_interval": args.sort_interval,
         },
         "roofline": R["roofline"],
         "forms": {k: {kk: v for kk, v in r.items() if kk != "roofline"} | {"roofline": r["roofline"]}
@@ -165,6 +194,9 @@ def main():
     }
     if "fp64" in results and "fp32r" in results:
         line["speedup_fp32r_vs_fp64"] = results["fp32r"]["value"] / results["fp64"]["value"]
+    cb = copy_bandwidth()
+    line["copy_bandwidth"] = cb
+    line["roofline"]["frac_of_measured_copy"] = round(R["roofline"]["achieved"] / cb["GBs"], 4)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(W.full_fp64("fp64") if args.workload == "full" else W.small_fp64())
         line["cpu_baseline"] = cb

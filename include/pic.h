@@ -118,6 +118,8 @@ typedef struct pic_counters {
   uint32_t step;
   int32_t refine_sweeps;      /* FP32R: sweeps in the last solve */
   double refine_residual;     /* FP32R: ||b - A phi|| / ||b|| after the last solve */
+  int64_t numeric_bad;        /* particles removed for a non-finite position (0 for valid input) */
+  int64_t tile_fallback;      /* push blocks whose deposit tile exceeded LDS (global atomics) */
 } pic_counters;
 
 /*
@@ -193,14 +195,17 @@ int pic_derived(pic_ctx* ctx, int replica, double out[7]);
  * every following launch of the selected kernel class with HIP events on the
  * context's stream; pic_profile_read synchronises and returns the summed
  * elapsed time (ms) and the number of launches measured since enabling.
- *   PIC_PROF_PUSH   the fused gather / push / absorb / collide / deposit kernel
- *                   (one launch per species and step)
+ *   PIC_PROF_PUSH   the streaming gather / push / electrode / candidate / deposit
+ *                   kernel (one launch per species and step)
  *   PIC_PROF_FIELD  the whole field stage of a step (RHS, Poisson, E)
  *   PIC_PROF_SORT   the periodic cell sort of both species
+ *   PIC_PROF_LISTS  the listed particles of one species: sub-cycled near-grain
+ *                   motion and the collisions of the candidates
  */
 #define PIC_PROF_PUSH  0
 #define PIC_PROF_FIELD 1
 #define PIC_PROF_SORT  2
+#define PIC_PROF_LISTS 3
 int pic_profile_enable(pic_ctx* ctx, int on);
 int pic_profile_read(pic_ctx* ctx, int kernel_class, double* total_ms, int64_t* launches);
 

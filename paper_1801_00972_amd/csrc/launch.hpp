@@ -13,26 +13,36 @@ struct FftPlanHost {
   int L_x, L_y;
 };
 
-// particles
-void launch_push_f64(const PartF64& in, const PartF64& out, const int* n_in, int* n_out,
-                     const double* E, double* rho_next, const MdTables& md, const SpeciesStep& S,
-                     Tallies* T, unsigned long long* gc, int do_mcc, long capacity, hipStream_t st);
-void launch_push_f32r(const PartF32R& in, const PartF32R& out, const int* n_in, int* n_out,
-                      const float* E, long long* rho_next, const MdTables& md,
-                      const SpeciesStep& S, Tallies* T, unsigned long long* gc, int do_mcc,
+// particles: arrays updated in place, WorkLists.cnt[0] slots in use, work
+// lists and tallies segmented by 1024-slot chunk
+int push_chunks(long capacity);             // chunks (push blocks) for a capacity
+long sort_keys(int nx, int ny, int nz);     // size of the sort histogram
+// the streaming kernel of one species (gather, push, walls, candidate test, deposit)
+void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
+                     const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st);
+void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
+                      const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st);
+// the listed particles: sub-cycled MD motion (with its collision and deposit), then collisions
+void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
+                      const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
                       long capacity, hipStream_t st);
+void launch_lists_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
+                       const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
+                       long capacity, hipStream_t st);
 void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
                      uint32_t k1, double vth, hipStream_t st);
-void launch_init_f32r(const PartF32R& P, int n, int ppc, int sp, uint32_t k0, uint32_t k1,
-                      double vth, hipStream_t st);
-void launch_deposit_f64(const PartF64& P, const int* n_in, double* rho, const SpeciesStep& S,
-                        long capacity, hipStream_t st);
-void launch_deposit_f32r(const PartF32R& P, const int* n_in, long long* rho, const SpeciesStep& S,
-                         long capacity, hipStream_t st);
-void launch_sort_f64(const PartF64& src, const PartF64& dst, const int* n_in, int* hist, int* sums,
-                     long ncell, int nx, int ny, long capacity, hipStream_t st);
-void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const int* n_in, int* hist,
-                      int* sums, long ncell, int nx, int ny, long capacity, hipStream_t st);
+void launch_init_f32r(const PartF32R& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
+                      uint32_t k1, double vth, hipStream_t st);
+// deposit of the current positions through the chunk tiles (arrays freshly sorted)
+void launch_deposit_f64(const PartF64& P, double* rho, const MdTables& md, const SpeciesStep& S,
+                        const WorkLists& L, long capacity, hipStream_t st);
+void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
+                         const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st);
+// counting sort into dst (dropping empty slots), then the chunk boxes of dst
+void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L, int* hist,
+                     int* sums, int nx, int ny, int nz, long capacity, hipStream_t st);
+void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const WorkLists& L, int* hist,
+                      int* sums, int nx, int ny, int nz, long capacity, hipStream_t st);
 void launch_fill_int(int* a, long n, int v, hipStream_t st);
 
 // mesh

@@ -180,29 +180,56 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(FftGeom g, const cplx<T>
 template <typename T>
 __global__ void thomas_kernel(cplx<T>* __restrict__ d, const T* __restrict__ inv, int K,
                               long modes) {
+  // the loads of a batch of planes are issued together: the recursion only
+  // waits on arithmetic, not on one memory round trip per plane
   using C = cplx<T>;
+  constexpr int B = 8;
   const long mn = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (mn >= modes) return;
-  C prev = d[mn];
-  T f = inv[mn];
-  prev.x *= f;
-  prev.y *= f;
-  d[mn] = prev;
-  for (int k = 1; k < K; ++k) {
-    C cur = d[(long)k * modes + mn];
-    f = inv[(long)k * modes + mn];
-    cur.x = (cur.x - prev.x) * f;
-    cur.y = (cur.y - prev.y) * f;
-    d[(long)k * modes + mn] = cur;
-    prev = cur;
+  C prev;
+  prev.x = prev.y = (T)0;
+  for (int k0 = 0; k0 < K; k0 += B) {
+    C cur[B];
+    T f[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (k0 + b < K) {
+        cur[b] = d[(long)(k0 + b) * modes + mn];
+        f[b] = inv[(long)(k0 + b) * modes + mn];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (k0 + b < K) {
+        cur[b].x = (cur[b].x - prev.x) * f[b];
+        cur[b].y = (cur[b].y - prev.y) * f[b];
+        prev = cur[b];
+        d[(long)(k0 + b) * modes + mn] = cur[b];
+      }
+    }
   }
-  for (int k = K - 2; k >= 0; --k) {
-    C cur = d[(long)k * modes + mn];
-    f = inv[(long)k * modes + mn];
-    cur.x -= f * prev.x;
-    cur.y -= f * prev.y;
-    d[(long)k * modes + mn] = cur;
-    prev = cur;
+  // back substitution from the last plane: x_k = d'_k - inv_k x_{k+1}
+  C next;
+  next.x = next.y = (T)0;
+  for (int k1 = K - 1; k1 >= 0; k1 -= B) {
+    C cur[B];
+    T f[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (k1 - b >= 0) {
+        cur[b] = d[(long)(k1 - b) * modes + mn];
+        f[b] = inv[(long)(k1 - b) * modes + mn];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (k1 - b >= 0) {
+        cur[b].x -= f[b] * next.x;
+        cur[b].y -= f[b] * next.y;
+        next = cur[b];
+        d[(long)(k1 - b) * modes + mn] = cur[b];
+      }
+    }
   }
 }
 

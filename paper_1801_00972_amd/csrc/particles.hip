@@ -9,12 +9,15 @@
 // collisions with the neutral reservoir (Table I) in null-collision form.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
 namespace pic {
 
-enum { ST_ALIVE = 0, ST_WALL0 = 1, ST_WALL1 = 2, ST_GRAIN = 3, ST_NONE = 4, ST_BAD = 5 };
+enum { ST_ALIVE = 0, ST_WALL0 = 1, ST_WALL1 = 2, ST_GRAIN = 3, ST_NONE = 4, ST_BAD = 5, ST_MD = 6, ST_OUT = 7 };
 
 // electrode test of a position already wrapped in x,y; a non-finite or
 // out-of-range coordinate (which no valid input produces) removes the particle
@@ -30,6 +33,22 @@ __device__ __forceinline__ int z_status(const double x[3], const SpeciesStep& S)
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kPPT = 4;                   // consecutive particles per thread
+constexpr int kChunk = kBlock * kPPT;     // particles per block
+constexpr int kTileNodes = 1024;          // LDS field and deposit tile capacity (nodes)
+constexpr int kMargin = 2;                // cells of drift allowed around a chunk's box
+
+// int32 cell index of the FP32R form: i | j << 10 | k << 20 (nx, ny <= 1024, nz < 2048);
+// -1 marks an empty slot
+__device__ __forceinline__ int cell_i(int c) { return c & 1023; }
+__device__ __forceinline__ int cell_j(int c) { return (c >> 10) & 1023; }
+__device__ __forceinline__ int cell_k(int c) { return c >> 20; }
+__device__ __forceinline__ int pack_cell(int i, int j, int k) { return i | (j << 10) | (k << 20); }
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD one contiguous
+// run of chunks so neighbouring chunks share that XCD's L2.  nb is a multiple
+// of 8, so this is a permutation of [0, nb).
+__device__ __forceinline__ long xcd_chunk(long b, long nb) { return (b % 8) * (nb / 8) + b / 8; }
 
 // ---------------------------------------------------------------- field loads
 __device__ __forceinline__ void load_node(const double2* __restrict__ E, long n, double& ex,
@@ -87,7 +106,8 @@ __device__ __forceinline__ uint32_t md_lookup(const MdTables& md, int nx, int ny
   if (b >= md.bsy) return 0u;
   const int c = k - md.bz0;
   if (c < 0 || c >= md.bsz) return 0u;
-  return md.cell_list[((long)c * md.bsy + b) * md.bsx + a];
+  const uint32_t cl = md.cell_list[((long)c * md.bsy + b) * md.bsx + a];
+  return (cl & 255u) ? cl : 0u;  // a cell of the box outside every cube has no grains
 }
 
 // separation x - x_g (cell units), minimum image across the periodic x,y
@@ -213,7 +233,7 @@ __device__ __forceinline__ void collide(const SpeciesStep& S, uint32_t id, doubl
   }
   const double gx = v[0] - vn[0], gy = v[1] - vn[1], gz = v[2] - vn[2];
   const double g = sqrt(gx * gx + gy * gy + gz * gz);
-  const double ratio = g * S.inv_g_cap;
+  const double ratio = g / S.g_cap;
   bool accept;
   if (ratio > 1.0) {
     capv = true;
@@ -281,249 +301,988 @@ __device__ __forceinline__ void split8(long long Q, float ox, float oy, float oz
   }
 }
 
-__device__ __forceinline__ void deposit_fixed(long long* __restrict__ rho, const SpeciesStep& S,
-                                              int i0, int j0, int k0, float ox, float oy,
-                                              float oz) {
-  long long part[8];
-  split8(S.Qp, ox, oy, oz, part);
-  const int i1 = i0 + 1 == S.nx ? 0 : i0 + 1;
-  const int j1 = j0 + 1 == S.ny ? 0 : j0 + 1;
-  const int ii[2] = {i0, i1}, jj[2] = {j0, j1};
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int a = t & 1, b = (t >> 1) & 1, c = t >> 2;
-    const long n = ii[a] + (long)S.nx * jj[b] + (long)S.nxy * (k0 + c);
-    atomicAdd((unsigned long long*)&rho[n], (unsigned long long)(S.isign * part[t]));
-  }
-}
-
-// ---------------------------------------------------------------- helpers
-// Block-wide stream compaction: each kept thread gets a slot in the output;
-// the block reserves its range with one atomic.
-__device__ __forceinline__ int compact_slot(bool keep, int* n_out, int* s_wave, int* s_base) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const unsigned long long m = __ballot(keep);
-  const int before = __popcll(m & ((1ull << lane) - 1ull));
-  if (lane == 0) s_wave[wave] = __popcll(m);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int tot = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      const int cnt = s_wave[w];
-      s_wave[w] = tot;
-      tot += cnt;
-    }
-    *s_base = tot ? atomicAdd(n_out, tot) : 0;
-  }
-  __syncthreads();
-  return *s_base + s_wave[wave] + before;
-}
-
+// ---------------------------------------------------------------- wave helpers
 __device__ __forceinline__ void wave_count(bool flag, unsigned long long* dst) {
   const unsigned long long m = __ballot(flag);
   if ((threadIdx.x & 63) == 0 && m) atomicAdd(dst, (unsigned long long)__popcll(m));
 }
 
-// ---------------------------------------------------------------- push, FP64
-__global__ __launch_bounds__(kBlock) void push_f64_kernel(
-    PartF64 in, PartF64 out, const int* __restrict__ n_in, int* __restrict__ n_out,
-    const double2* __restrict__ E, double* __restrict__ rho_next, MdTables md, SpeciesStep S,
-    Tallies* __restrict__ T, unsigned long long* __restrict__ grain_count, int do_mcc) {
-  __shared__ int s_wave[kWaves];
-  __shared__ int s_base;
-  const int n = *n_in;
-  if ((long)blockIdx.x * kBlock >= n) return;
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  int st = ST_NONE;
-  double x[3], v[3];
-  uint32_t id = 0;
-  bool coll = false, capv = false, is_md = false;
-  if (p < n) {
-    x[0] = in.x[p];
-    x[1] = in.y[p];
-    x[2] = in.z[p];
-    v[0] = in.vx[p];
-    v[1] = in.vy[p];
-    v[2] = in.vz[p];
-    id = in.id[p];
-    const int i0 = (int)floor(x[0]), j0 = (int)floor(x[1]), k0 = (int)floor(x[2]);
-    if (md_lookup(md, S.nx, S.ny, i0, j0, k0) == 0u) {
-      // plain PIC particle: gather, kick Eq. (2), drift Eq. (1)
-      double Ep[3];
-      gather_d(E, S, i0, j0, k0, x[0] - i0, x[1] - j0, x[2] - k0, Ep);
-      v[0] += S.qm_dt * Ep[0];
-      v[1] += S.qm_dt * Ep[1];
-      v[2] += S.qm_dt * Ep[2];
-      x[0] = wrap_coord(x[0] + v[0] * S.dt_dx, S.nx);
-      x[1] = wrap_coord(x[1] + v[1] * S.dt_dx, S.ny);
-      x[2] += v[2] * S.dt_dx;
-      st = z_status(x, S);
-    } else {
-      is_md = true;
-      int hit = -1;
-      st = md_move(E, md, S, x, v, hit);
-      if (st == ST_GRAIN) atomicAdd(&grain_count[2 * hit + S.sp], 1ull);
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ void wave_add_count(int v, unsigned long long* dst) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
+}
+
+// ---------------------------------------------------------------- one particle
+// FP32R: gather from the 8 node fields ec, kick Eq. (2), drift Eq. (1) in cell +
+// offset form, periodic wrap; returns the electrode status
+__device__ __forceinline__ int push_one_f32(const SpeciesStep& S, const float ec[8][3], float o[3],
+                                            float v[3], int& ci, int& cj, int& ck) {
+  const float wx[2] = {1.0f - o[0], o[0]};
+  const float wy[2] = {1.0f - o[1], o[1]};
+  const float wz[2] = {1.0f - o[2], o[2]};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float e = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) e += wx[t & 1] * wy[(t >> 1) & 1] * wz[t >> 2] * ec[t][a];
+    v[a] += S.qm_dt_f * e;
+  }
+  int d[3];
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float f = o[a] + v[a] * S.dt_dx_f;
+    const float fl = floorf(f);
+    f -= fl;
+    d[a] = (int)fl;
+    if (f >= 1.0f) {  // -tiny + 1 rounds to 1
+      f = 0.0f;
+      d[a] += 1;
     }
-    if (st == ST_ALIVE && do_mcc) collide(S, id, v, coll, capv);
+    ok = ok && (f >= 0.0f && f < 1.0f);
+    o[a] = f;
   }
-  const bool keep = st == ST_ALIVE;
-  const int dst = compact_slot(keep, n_out, s_wave, &s_base);
-  if (keep) {
-    out.x[dst] = x[0];
-    out.y[dst] = x[1];
-    out.z[dst] = x[2];
-    out.vx[dst] = v[0];
-    out.vy[dst] = v[1];
-    out.vz[dst] = v[2];
-    out.id[dst] = id;
-    deposit_f64(rho_next, S, x[0], x[1], x[2]);
+  ci += d[0];
+  cj += d[1];
+  ck += d[2];
+  if (ci < 0 || ci >= S.nx) ci = ((ci % S.nx) + S.nx) % S.nx;
+  if (cj < 0 || cj >= S.ny) cj = ((cj % S.ny) + S.ny) % S.ny;
+  return !ok ? ST_BAD : (ck < 0 ? ST_WALL0 : (ck >= S.nz ? ST_WALL1 : ST_ALIVE));
+}
+
+// FP64: kick with the gathered field, drift, wrap; returns the electrode status
+__device__ __forceinline__ int push_one_f64(const SpeciesStep& S, const double Ep[3], double x[3],
+                                            double v[3]) {
+  v[0] += S.qm_dt * Ep[0];
+  v[1] += S.qm_dt * Ep[1];
+  v[2] += S.qm_dt * Ep[2];
+  x[0] = wrap_coord(x[0] + v[0] * S.dt_dx, S.nx);
+  x[1] = wrap_coord(x[1] + v[1] * S.dt_dx, S.ny);
+  x[2] += v[2] * S.dt_dx;
+  return z_status(x, S);
+}
+
+// ---------------------------------------------------------------- chunk tiles
+// The arrays are kept sorted by 4x4x4 cell tiles, so the 1024 particles of a
+// chunk (the slots one push block streams) sit in a small box of cells.  The
+// box is taken exactly right after each sort; the push block stages the field
+// on that box plus kMargin cells in LDS and accumulates its deposit there.
+// Particles that have drifted outside it (fast electrons) gather and deposit
+// through global memory instead.  Along the periodic x,y the box is the raw
+// range of the index or the range shifted by n/2, whichever is shorter.
+struct Tile {
+  int x0, y0, k0;  // first node (x0, y0 may be negative: periodic)
+  int tx, ty, tz;  // nodes per edge
+  bool on;
+};
+
+__device__ __forceinline__ void box_update(int v[10], int i, int j, int k, int nx, int ny) {
+  const int si = i + (nx >> 1) >= nx ? i + (nx >> 1) - nx : i + (nx >> 1);
+  const int sj = j + (ny >> 1) >= ny ? j + (ny >> 1) - ny : j + (ny >> 1);
+  v[0] = min(v[0], i);
+  v[1] = max(v[1], i);
+  v[2] = min(v[2], si);
+  v[3] = max(v[3], si);
+  v[4] = min(v[4], j);
+  v[5] = max(v[5], j);
+  v[6] = min(v[6], sj);
+  v[7] = max(v[7], sj);
+  v[8] = min(v[8], k);
+  v[9] = max(v[9], k);
+}
+
+// cells [c0, c0 + nc) along a periodic axis covering the raw or shifted range
+__device__ __forceinline__ void axis_cells(int lo, int hi, int slo, int shi, int n, int& c0,
+                                           int& nc) {
+  if (hi - lo <= shi - slo) {
+    c0 = lo;
+    nc = hi - lo + 1;
+  } else {
+    c0 = slo - (n >> 1);
+    nc = shi - slo + 1;
   }
-  wave_count(st == ST_WALL0, &T->wall[0][S.sp]);
-  wave_count(st == ST_WALL1, &T->wall[1][S.sp]);
-  wave_count(coll, &T->n_coll[S.sp]);
-  wave_count(capv, &T->cap_viol[S.sp]);
-  wave_count(is_md, &T->md[S.sp]);
-  wave_count(st == ST_BAD, &T->numeric_bad);
+}
+
+// block-wide min/max of the 10 box values (every thread gets the result)
+__device__ __forceinline__ void block_minmax(int v[10], int (*s_red)[10]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 10; ++t) v[t] = (t & 1) ? wave_max(v[t]) : wave_min(v[t]);
+  if (lane == 0)
+    for (int t = 0; t < 10; ++t) s_red[wave][t] = v[t];
+  __syncthreads();
+  for (int t = 0; t < 10; ++t) {
+    int r = s_red[0][t];
+    for (int w = 1; w < kWaves; ++w) r = (t & 1) ? max(r, s_red[w][t]) : min(r, s_red[w][t]);
+    v[t] = r;
+  }
+}
+
+// the chunk box plus m cells, in nodes; shrinks the margin until it fits in LDS
+__device__ __forceinline__ Tile make_tile(const int32_t* __restrict__ box, int nx, int ny, int nz) {
+  Tile t;
+  t.on = false;
+  t.x0 = t.y0 = t.k0 = 0;
+  t.tx = t.ty = t.tz = 0;
+  const int i0 = box[0], ni = box[1], j0 = box[2], nj = box[3], k0 = box[4], nk = box[5];
+  if (ni <= 0) return t;
+  for (int m = kMargin; m >= 0; --m) {
+    int x0 = i0 - m, tx = ni + 2 * m + 1;
+    if (ni + 2 * m >= nx) {
+      x0 = 0;
+      tx = nx + 1;
+    }
+    int y0 = j0 - m, ty = nj + 2 * m + 1;
+    if (nj + 2 * m >= ny) {
+      y0 = 0;
+      ty = ny + 1;
+    }
+    const int klo = max(0, k0 - m), khi = min(nz - 1, k0 + nk - 1 + m);
+    const int tz = khi - klo + 2;
+    if (tx * ty * tz <= kTileNodes) {
+      t.x0 = x0;
+      t.y0 = y0;
+      t.k0 = klo;
+      t.tx = tx;
+      t.ty = ty;
+      t.tz = tz;
+      t.on = true;
+      return t;
+    }
+  }
+  return t;
+}
+
+// tile-local index of the cell's lower corner node, or -1 if the cell's 8
+// nodes are not all in the tile
+__device__ __forceinline__ int tile_cell(const Tile& t, int i, int j, int k, int nx, int ny) {
+  if (!t.on) return -1;
+  int lx = i - t.x0;
+  if (lx >= nx) lx -= nx;
+  else if (lx < 0) lx += nx;
+  int ly = j - t.y0;
+  if (ly >= ny) ly -= ny;
+  else if (ly < 0) ly += ny;
+  const int lz = k - t.k0;
+  if (lx > t.tx - 2 || ly > t.ty - 2 || lz < 0 || lz > t.tz - 2) return -1;
+  return (lz * t.ty + ly) * t.tx + lx;
+}
+
+// a / b for 0 <= a < 2^24 without an integer divide (rb = 1/b)
+__device__ __forceinline__ int qdiv(int a, int b, float rb) {
+  int q = (int)((float)a * rb);
+  if (q * b > a) --q;
+  else if ((q + 1) * b <= a) ++q;
+  return q;
+}
+
+// global node of tile entry t
+__device__ __forceinline__ long tile_node(const Tile& T, int t, float rtx, float rtxy, int nx,
+                                          int ny, long nxy) {
+  const int lz = qdiv(t, T.tx * T.ty, rtxy);
+  const int r = t - lz * T.tx * T.ty;
+  const int ly = qdiv(r, T.tx, rtx);
+  const int lx = r - ly * T.tx;
+  int gi = T.x0 + lx;
+  if (gi < 0) gi += nx;
+  else if (gi >= nx) gi -= nx;
+  if (gi < 0 || gi >= nx) gi = ((gi % nx) + nx) % nx;
+  int gj = T.y0 + ly;
+  if (gj < 0) gj += ny;
+  else if (gj >= ny) gj -= ny;
+  if (gj < 0 || gj >= ny) gj = ((gj % ny) + ny) % ny;
+  return gi + (long)nx * gj + nxy * (T.k0 + lz);
+}
+
+template <typename A>
+__device__ __forceinline__ void atomic_add_acc(A* p, A v) {
+  if constexpr (std::is_same<A, long long>::value)
+    atomicAdd((unsigned long long*)p, (unsigned long long)v);
+  else
+    unsafeAtomicAdd(p, v);
+}
+
+// the 8 corner contributions of one cell into the tile (lbase >= 0) or to global
+template <typename A>
+__device__ __forceinline__ void corner_add(const Tile& T, int lbase, A* s_rho, A* __restrict__ rho,
+                                           const SpeciesStep& S, int i, int j, int k,
+                                           const A acc[8]) {
+  if (lbase >= 0) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int off = (t & 1) + T.tx * (((t >> 1) & 1) + T.ty * (t >> 2));
+      if constexpr (std::is_same<A, long long>::value)
+        atomicAdd((unsigned long long*)&s_rho[lbase + off], (unsigned long long)acc[t]);
+      else
+        atomicAdd(&s_rho[lbase + off], acc[t]);
+    }
+  } else {
+    const int i1 = i + 1 == S.nx ? 0 : i + 1;
+    const int j1 = j + 1 == S.ny ? 0 : j + 1;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const long node = ((t & 1) ? i1 : i) + (long)S.nx * (((t >> 1) & 1) ? j1 : j) +
+                        (long)S.nxy * (k + (t >> 2));
+      atomic_add_acc(&rho[node], acc[t]);
+    }
+  }
+}
+
+// one particle's CIC charge straight to the global mesh (loading, MD particles)
+__device__ __forceinline__ void deposit_global_fixed(long long* __restrict__ rho,
+                                                     const SpeciesStep& S, int i, int j, int k,
+                                                     float ox, float oy, float oz) {
+  long long part[8];
+  split8(S.Qp, ox, oy, oz, part);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) part[t] *= S.isign;
+  Tile none{};
+  corner_add<long long>(none, -1, nullptr, rho, S, i, j, k, part);
+}
+
+__device__ __forceinline__ void cic_weights_d(double fx, double fy, double fz, double s,
+                                              double w[8]) {
+  const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+#pragma unroll
+  for (int t = 0; t < 8; ++t) w[t] = s * wx[t & 1] * wy[(t >> 1) & 1] * wz[t >> 2];
+}
+
+__device__ __forceinline__ void deposit_global_f64(double* __restrict__ rho, const SpeciesStep& S,
+                                                   double X, double Y, double Z) {
+  const int i = (int)floor(X), j = (int)floor(Y), k = (int)floor(Z);
+  double w[8];
+  cic_weights_d(X - i, Y - j, Z - k, S.sign, w);
+  Tile none{};
+  corner_add<double>(none, -1, nullptr, rho, S, i, j, k, w);
+}
+
+// append to the chunk's list segment: one LDS atomic per wave
+__device__ __forceinline__ void chunk_append(bool flag, int32_t* seg, int* s_n, int value) {
+  const unsigned long long m = __ballot(flag);
+  if (!m) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(s_n, __popcll(m));
+  base = __shfl(base, leader, 64);
+  if (flag) seg[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
+}
+
+// block-level tallies: wave sums into LDS; thread 0 then adds them to the
+// chunk's own accumulators (each chunk has one writer per kernel: no atomics)
+__device__ __forceinline__ void tally_add(unsigned* s_t, int which, int v) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(&s_t[which], (unsigned)v);
+}
+__device__ __forceinline__ void tally_store(const unsigned* s_t, unsigned long long* tally) {
+  if (threadIdx.x != 0) return;
+  for (int w = 0; w < TL_N; ++w)
+    if (s_t[w]) tally[w] += s_t[w];
 }
 
 // ---------------------------------------------------------------- push, FP32R
-__device__ __forceinline__ float gather1(const float4 e, int comp) {
-  return comp == 0 ? e.x : (comp == 1 ? e.y : e.z);
+// One block streams the kChunk consecutive slots of its chunk, four per thread
+// with 16-byte loads and stores, and updates them in place: gather from the
+// LDS field tile (the 8 node fields are reused while consecutive particles
+// share a cell), kick Eq. (2), drift Eq. (1) in cell + offset form, periodic
+// wrap, electrode absorption, collision candidate test; the new positions are
+// deposited into the LDS tile (per-thread sums over a run of particles in one
+// cell first), whose occupied nodes are then added to rho.  Particles starting
+// inside an MD cube are left untouched and listed for the sub-cycled kernel;
+// candidates are listed for the collision kernel.
+template <bool kMove>
+__global__ __launch_bounds__(kBlock) void push_f32r_kernel(PartF32R P,
+                                                           const float4* __restrict__ E,
+                                                           long long* __restrict__ rho, MdTables md,
+                                                           SpeciesStep S, WorkLists L) {
+  __shared__ float4 s_E[kTileNodes];
+  __shared__ long long s_rho[kTileNodes];
+  __shared__ unsigned s_tally[TL_N];
+  __shared__ int s_nmd, s_ncoll, s_nout, s_mdbase;
+  __shared__ int32_t s_md[kChunk];
+  const int n = L.cnt[0];
+  const long chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  const long chunk0 = chunk * kChunk;
+  if (chunk0 >= n) {
+    if (kMove && threadIdx.x == 0) {
+      L.coll_cnt[chunk] = 0;
+      L.out_cnt[chunk] = 0;
+    }
+    return;
+  }
+  const Tile tile = make_tile(L.box + 6 * chunk, S.nx, S.ny, S.nz);
+  const int vol = tile.on ? tile.tx * tile.ty * tile.tz : 0;
+  const float rtx = 1.0f / (float)max(tile.tx, 1), rtxy = 1.0f / (float)max(tile.tx * tile.ty, 1);
+  for (int t = threadIdx.x; t < vol; t += kBlock) {
+    if (kMove) s_E[t] = E[tile_node(tile, t, rtx, rtxy, S.nx, S.ny, S.nxy)];
+    s_rho[t] = 0;
+  }
+  if (threadIdx.x < TL_N) s_tally[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    s_nmd = 0;
+    s_ncoll = 0;
+    s_nout = 0;
+  }
+  const long g4 = chunk0 / kPPT + threadIdx.x;
+  const long p0 = g4 * kPPT;
+  const int4 c4 = reinterpret_cast<const int4*>(P.cell)[g4];
+  const float4 X4 = reinterpret_cast<const float4*>(P.ox)[g4];
+  const float4 Y4 = reinterpret_cast<const float4*>(P.oy)[g4];
+  const float4 Z4 = reinterpret_cast<const float4*>(P.oz)[g4];
+  const float4 U4 = reinterpret_cast<const float4*>(P.vx)[g4];
+  const float4 V4 = reinterpret_cast<const float4*>(P.vy)[g4];
+  const float4 W4 = reinterpret_cast<const float4*>(P.vz)[g4];
+  const uint4 I4 = reinterpret_cast<const uint4*>(P.id)[g4];
+  __syncthreads();
+  int cell[kPPT] = {c4.x, c4.y, c4.z, c4.w};
+  float o[kPPT][3] = {{X4.x, Y4.x, Z4.x}, {X4.y, Y4.y, Z4.y}, {X4.z, Y4.z, Z4.z}, {X4.w, Y4.w, Z4.w}};
+  float v[kPPT][3] = {{U4.x, V4.x, W4.x}, {U4.y, V4.y, W4.y}, {U4.z, V4.z, W4.z}, {U4.w, V4.w, W4.w}};
+  const uint32_t id[kPPT] = {I4.x, I4.y, I4.z, I4.w};
+  int st[kPPT];
+  bool cand[kPPT];
+  int cached = -1;
+  float ec[8][3];
+  int n_out = 0;
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    st[q] = ST_NONE;
+    cand[q] = false;
+    if (!kMove) {
+      if (p0 + q < n && cell[q] >= 0) st[q] = ST_ALIVE;
+      continue;
+    }
+    if (p0 + q < n && cell[q] >= 0) {
+      int ci = cell_i(cell[q]), cj = cell_j(cell[q]), ck = cell_k(cell[q]);
+      if (md_lookup(md, S.nx, S.ny, ci, cj, ck) != 0u) {
+        st[q] = ST_MD;
+      } else {
+        const int lb = cell[q] == cached ? 0 : tile_cell(tile, ci, cj, ck, S.nx, S.ny);
+        if (lb < 0) {
+          // outside the chunk's tile: left for the outlier kernel (no global
+          // gather here, so no wave waits on a dependent memory round trip)
+          st[q] = ST_OUT;
+          continue;
+        }
+        if (cell[q] != cached) {
+          cached = cell[q];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const float4 e = s_E[lb + (t & 1) + tile.tx * (((t >> 1) & 1) + tile.ty * (t >> 2))];
+            ec[t][0] = e.x;
+            ec[t][1] = e.y;
+            ec[t][2] = e.z;
+          }
+        }
+        st[q] = push_one_f32(S, ec, o[q], v[q], ci, cj, ck);
+        if (st[q] == ST_ALIVE) {
+          cell[q] = pack_cell(ci, cj, ck);
+          const uint4 r = philox4x32_10(id[q], S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+          cand[q] = (uint64_t)r.x < S.T_null;
+        } else {
+          cell[q] = -1;
+        }
+      }
+    }
+  }
+  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0;
+  if (kMove) {
+#pragma unroll
+    for (int q = 0; q < kPPT; ++q) {
+      chunk_append(st[q] == ST_MD, s_md, &s_nmd, (int)(p0 + q));
+      chunk_append(cand[q], L.coll + chunk0, &s_ncoll, (int)(p0 + q));
+      chunk_append(st[q] == ST_OUT, L.out + chunk0, &s_nout, (int)(p0 + q));
+      n_out += st[q] == ST_OUT;
+      n_w0 += st[q] == ST_WALL0;
+      n_w1 += st[q] == ST_WALL1;
+      n_bad += st[q] == ST_BAD;
+      n_md += st[q] == ST_MD;
+    }
+  }
+  if (kMove) {
+  reinterpret_cast<int4*>(P.cell)[g4] = make_int4(cell[0], cell[1], cell[2], cell[3]);
+  reinterpret_cast<float4*>(P.ox)[g4] = make_float4(o[0][0], o[1][0], o[2][0], o[3][0]);
+  reinterpret_cast<float4*>(P.oy)[g4] = make_float4(o[0][1], o[1][1], o[2][1], o[3][1]);
+  reinterpret_cast<float4*>(P.oz)[g4] = make_float4(o[0][2], o[1][2], o[2][2], o[3][2]);
+  reinterpret_cast<float4*>(P.vx)[g4] = make_float4(v[0][0], v[1][0], v[2][0], v[3][0]);
+  reinterpret_cast<float4*>(P.vy)[g4] = make_float4(v[0][1], v[1][1], v[2][1], v[3][1]);
+  reinterpret_cast<float4*>(P.vz)[g4] = make_float4(v[0][2], v[1][2], v[2][2], v[3][2]);
+  }
+
+  // deposit of rho_{k+1}
+  long long acc[8];
+  int acc_cell = -1;
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    if (st[q] != ST_ALIVE) continue;
+    long long part[8];
+    split8(S.Qp, o[q][0], o[q][1], o[q][2], part);
+    if (cell[q] == acc_cell) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t] += part[t];
+    } else {
+      if (acc_cell >= 0) {
+        const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] *= S.isign;
+        corner_add<long long>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj,
+                              ak, acc);
+      }
+      acc_cell = cell[q];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t] = part[t];
+    }
+  }
+  if (acc_cell >= 0) {
+    const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] *= S.isign;
+    corner_add<long long>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj, ak,
+                          acc);
+  }
+  tally_add(s_tally, TL_W0, n_w0);
+  tally_add(s_tally, TL_W1, n_w1);
+  tally_add(s_tally, TL_BAD, n_bad);
+  tally_add(s_tally, TL_MD, n_md);
+  tally_add(s_tally, TL_DEAD, n_w0 + n_w1 + n_bad);
+  tally_add(s_tally, TL_FALL, n_out);
+  __syncthreads();
+  for (int t = threadIdx.x; t < vol; t += kBlock) {
+    const long long val = s_rho[t];
+    if (val != 0)
+      atomicAdd((unsigned long long*)&rho[tile_node(tile, t, rtx, rtxy, S.nx, S.ny, S.nxy)],
+                (unsigned long long)val);
+  }
+  if (kMove) {
+    // the MD particles join one dense list: one reservation per block that has any
+    if (threadIdx.x == 0) {
+      L.coll_cnt[chunk] = s_ncoll;
+      L.out_cnt[chunk] = s_nout;
+      if (s_nmd) s_mdbase = atomicAdd(&L.cnt[2], s_nmd);
+    }
+    tally_store(s_tally, L.tally + TL_N * chunk);
+    __syncthreads();
+    for (int t = threadIdx.x; t < s_nmd; t += kBlock) L.md[s_mdbase + t] = s_md[t];
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void push_f32r_kernel(
-    PartF32R in, PartF32R out, const int* __restrict__ n_in, int* __restrict__ n_out,
-    const float4* __restrict__ E, long long* __restrict__ rho_next, MdTables md, SpeciesStep S,
-    Tallies* __restrict__ T, unsigned long long* __restrict__ grain_count, int do_mcc) {
-  __shared__ int s_wave[kWaves];
-  __shared__ int s_base;
-  const int n = *n_in;
-  if ((long)blockIdx.x * kBlock >= n) return;
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  int st = ST_NONE;
-  int ci = 0, cj = 0, ck = 0;
-  float o[3] = {0.f, 0.f, 0.f}, vf[3] = {0.f, 0.f, 0.f};
-  uint32_t id = 0;
-  bool coll = false, capv = false, is_md = false;
-  if (p < n) {
-    const int cell = in.cell[p];
-    o[0] = in.ox[p];
-    o[1] = in.oy[p];
-    o[2] = in.oz[p];
-    vf[0] = in.vx[p];
-    vf[1] = in.vy[p];
-    vf[2] = in.vz[p];
-    id = in.id[p];
-    ck = cell / S.nxy;
-    const int rem = cell - ck * S.nxy;
-    cj = rem / S.nx;
-    ci = rem - cj * S.nx;
-    if (md_lookup(md, S.nx, S.ny, ci, cj, ck) == 0u) {
-      // gather in FP32 from the FP32 field
-      const int i1 = ci + 1 == S.nx ? 0 : ci + 1;
-      const int j1 = cj + 1 == S.ny ? 0 : cj + 1;
-      const long r00 = (long)S.nx * cj + (long)S.nxy * ck;
-      const long r10 = (long)S.nx * j1 + (long)S.nxy * ck;
-      const long base[4] = {r00, r10, r00 + S.nxy, r10 + S.nxy};
-      const float wx0 = 1.0f - o[0], wx1 = o[0];
-      const float wy[2] = {1.0f - o[1], o[1]}, wz[2] = {1.0f - o[2], o[2]};
-      float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+// ---------------------------------------------------------------- push, FP64
+// The same kernel on FP64 records: positions in cell units, velocities in m/s;
+// an empty slot has z = -1.  The field tile holds (Ex,Ey),(Ez,0) pairs.
+template <bool kMove>
+__global__ __launch_bounds__(kBlock) void push_f64_kernel(PartF64 P, const double2* __restrict__ E,
+                                                          double* __restrict__ rho, MdTables md,
+                                                          SpeciesStep S, WorkLists L) {
+  __shared__ double2 s_E[2 * kTileNodes];
+  __shared__ double s_rho[kTileNodes];
+  __shared__ unsigned s_tally[TL_N];
+  __shared__ int s_nmd, s_ncoll, s_nout, s_mdbase;
+  __shared__ int32_t s_md[kChunk];
+  const int n = L.cnt[0];
+  const long chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  const long chunk0 = chunk * kChunk;
+  if (chunk0 >= n) {
+    if (kMove && threadIdx.x == 0) {
+      L.coll_cnt[chunk] = 0;
+      L.out_cnt[chunk] = 0;
+    }
+    return;
+  }
+  const Tile tile = make_tile(L.box + 6 * chunk, S.nx, S.ny, S.nz);
+  const int vol = tile.on ? tile.tx * tile.ty * tile.tz : 0;
+  const float rtx = 1.0f / (float)max(tile.tx, 1), rtxy = 1.0f / (float)max(tile.tx * tile.ty, 1);
+  for (int t = threadIdx.x; t < vol; t += kBlock) {
+    if (kMove) {
+      const long node = tile_node(tile, t, rtx, rtxy, S.nx, S.ny, S.nxy);
+      s_E[2 * t] = E[2 * node];
+      s_E[2 * t + 1] = E[2 * node + 1];
+    }
+    s_rho[t] = 0.0;
+  }
+  if (threadIdx.x < TL_N) s_tally[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    s_nmd = 0;
+    s_ncoll = 0;
+    s_nout = 0;
+  }
+  const long g4 = chunk0 / kPPT + threadIdx.x;
+  const long p0 = g4 * kPPT;
+  double x[kPPT][3], v[kPPT][3];
+#define PIC_LOAD4(arr, dst, a)                                            \
+  {                                                                       \
+    const double2 lo = reinterpret_cast<const double2*>(arr)[2 * g4];     \
+    const double2 hi = reinterpret_cast<const double2*>(arr)[2 * g4 + 1]; \
+    dst[0][a] = lo.x;                                                     \
+    dst[1][a] = lo.y;                                                     \
+    dst[2][a] = hi.x;                                                     \
+    dst[3][a] = hi.y;                                                     \
+  }
+  PIC_LOAD4(P.x, x, 0)
+  PIC_LOAD4(P.y, x, 1)
+  PIC_LOAD4(P.z, x, 2)
+  PIC_LOAD4(P.vx, v, 0)
+  PIC_LOAD4(P.vy, v, 1)
+  PIC_LOAD4(P.vz, v, 2)
+#undef PIC_LOAD4
+  const uint4 I4 = reinterpret_cast<const uint4*>(P.id)[g4];
+  const uint32_t id[kPPT] = {I4.x, I4.y, I4.z, I4.w};
+  __syncthreads();
+  int st[kPPT], cell[kPPT];
+  bool cand[kPPT];
+  int n_out = 0;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const float wyz = wy[t & 1] * wz[t >> 1];
-        const float4 a = E[base[t] + ci];
-        const float4 b = E[base[t] + i1];
-        e0 += wyz * (wx0 * a.x + wx1 * b.x);
-        e1 += wyz * (wx0 * a.y + wx1 * b.y);
-        e2 += wyz * (wx0 * a.z + wx1 * b.z);
+  for (int q = 0; q < kPPT; ++q) {
+    st[q] = ST_NONE;
+    cand[q] = false;
+    cell[q] = -1;
+    if (!kMove) {
+      if (p0 + q < n && x[q][2] >= 0.0) {
+        st[q] = ST_ALIVE;
+        cell[q] = pack_cell((int)floor(x[q][0]), (int)floor(x[q][1]), (int)floor(x[q][2]));
       }
-      vf[0] += S.qm_dt_f * e0;
-      vf[1] += S.qm_dt_f * e1;
-      vf[2] += S.qm_dt_f * e2;
-      int d[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        float f = o[a] + vf[a] * S.dt_dx_f;
-        const float fl = floorf(f);
-        f -= fl;
-        d[a] = (int)fl;
-        if (f >= 1.0f) {  // -tiny + 1 rounds to 1
-          f = 0.0f;
-          d[a] += 1;
+      continue;
+    }
+    if (p0 + q < n && x[q][2] >= 0.0) {
+      const int i0 = (int)floor(x[q][0]), j0 = (int)floor(x[q][1]), k0 = (int)floor(x[q][2]);
+      if (md_lookup(md, S.nx, S.ny, i0, j0, k0) != 0u) {
+        st[q] = ST_MD;
+      } else {
+        double Ep[3];
+        const double fx = x[q][0] - i0, fy = x[q][1] - j0, fz = x[q][2] - k0;
+        const int lb = tile_cell(tile, i0, j0, k0, S.nx, S.ny);
+        if (lb < 0) {
+          st[q] = ST_OUT;  // left for the outlier kernel
+          continue;
         }
-        o[a] = f;
+        {
+          const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+          Ep[0] = Ep[1] = Ep[2] = 0.0;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int l = lb + (t & 1) + tile.tx * (((t >> 1) & 1) + tile.ty * (t >> 2));
+            const double w = wx[t & 1] * wy[(t >> 1) & 1] * wz[t >> 2];
+            const double2 a = s_E[2 * l], b2 = s_E[2 * l + 1];
+            Ep[0] += w * a.x;
+            Ep[1] += w * a.y;
+            Ep[2] += w * b2.x;
+          }
+        }
+        st[q] = push_one_f64(S, Ep, x[q], v[q]);
+        if (st[q] == ST_ALIVE) {
+          cell[q] = pack_cell((int)floor(x[q][0]), (int)floor(x[q][1]), (int)floor(x[q][2]));
+          const uint4 r = philox4x32_10(id[q], S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+          cand[q] = (uint64_t)r.x < S.T_null;
+        } else {
+          x[q][2] = -1.0;
+        }
       }
-      ci += d[0];
-      cj += d[1];
-      ck += d[2];
-      if (ci < 0 || ci >= S.nx) ci = ((ci % S.nx) + S.nx) % S.nx;
-      if (cj < 0 || cj >= S.ny) cj = ((cj % S.ny) + S.ny) % S.ny;
-      st = ck < 0 ? ST_WALL0 : (ck >= S.nz ? ST_WALL1 : ST_ALIVE);
-      if (!(o[0] >= 0.0f && o[0] < 1.0f && o[1] >= 0.0f && o[1] < 1.0f && o[2] >= 0.0f &&
-            o[2] < 1.0f && vf[0] == vf[0] && vf[1] == vf[1] && vf[2] == vf[2]))
-        st = ST_BAD;
+    }
+  }
+  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0;
+  if (kMove) {
+#pragma unroll
+    for (int q = 0; q < kPPT; ++q) {
+      chunk_append(st[q] == ST_MD, s_md, &s_nmd, (int)(p0 + q));
+      chunk_append(cand[q], L.coll + chunk0, &s_ncoll, (int)(p0 + q));
+      chunk_append(st[q] == ST_OUT, L.out + chunk0, &s_nout, (int)(p0 + q));
+      n_out += st[q] == ST_OUT;
+      n_w0 += st[q] == ST_WALL0;
+      n_w1 += st[q] == ST_WALL1;
+      n_bad += st[q] == ST_BAD;
+      n_md += st[q] == ST_MD;
+    }
+  }
+  if (kMove) {
+#define PIC_STORE4(arr, srcv, a)                                                          \
+  {                                                                                       \
+    reinterpret_cast<double2*>(arr)[2 * g4] = make_double2(srcv[0][a], srcv[1][a]);     \
+    reinterpret_cast<double2*>(arr)[2 * g4 + 1] = make_double2(srcv[2][a], srcv[3][a]); \
+  }
+  PIC_STORE4(P.x, x, 0)
+  PIC_STORE4(P.y, x, 1)
+  PIC_STORE4(P.z, x, 2)
+  PIC_STORE4(P.vx, v, 0)
+  PIC_STORE4(P.vy, v, 1)
+  PIC_STORE4(P.vz, v, 2)
+#undef PIC_STORE4
+  }
+
+  double acc[8];
+  int acc_cell = -1;
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    if (st[q] != ST_ALIVE) continue;
+    double w[8];
+    const int i = cell_i(cell[q]), j = cell_j(cell[q]), k = cell_k(cell[q]);
+    cic_weights_d(x[q][0] - i, x[q][1] - j, x[q][2] - k, S.sign, w);
+    if (cell[q] == acc_cell) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t] += w[t];
     } else {
-      // near a grain: the sub-cycled path runs in FP64 on the exact position
-      is_md = true;
-      double x[3] = {(double)ci + (double)o[0], (double)cj + (double)o[1],
-                     (double)ck + (double)o[2]};
-      double v[3] = {vf[0], vf[1], vf[2]};
+      if (acc_cell >= 0) {
+        const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
+        corner_add<double>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj, ak,
+                           acc);
+      }
+      acc_cell = cell[q];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t] = w[t];
+    }
+  }
+  if (acc_cell >= 0) {
+    const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
+    corner_add<double>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj, ak, acc);
+  }
+  tally_add(s_tally, TL_W0, n_w0);
+  tally_add(s_tally, TL_W1, n_w1);
+  tally_add(s_tally, TL_BAD, n_bad);
+  tally_add(s_tally, TL_MD, n_md);
+  tally_add(s_tally, TL_DEAD, n_w0 + n_w1 + n_bad);
+  tally_add(s_tally, TL_FALL, n_out);
+  __syncthreads();
+  for (int t = threadIdx.x; t < vol; t += kBlock) {
+    const double val = s_rho[t];
+    if (val != 0.0) unsafeAtomicAdd(&rho[tile_node(tile, t, rtx, rtxy, S.nx, S.ny, S.nxy)], val);
+  }
+  if (kMove) {
+    // the MD particles join one dense list: one reservation per block that has any
+    if (threadIdx.x == 0) {
+      L.coll_cnt[chunk] = s_ncoll;
+      L.out_cnt[chunk] = s_nout;
+      if (s_nmd) s_mdbase = atomicAdd(&L.cnt[2], s_nmd);
+    }
+    tally_store(s_tally, L.tally + TL_N * chunk);
+    __syncthreads();
+    for (int t = threadIdx.x; t < s_nmd; t += kBlock) L.md[s_mdbase + t] = s_md[t];
+  }
+}
+
+// ---------------------------------------------------------------- chunk boxes
+// After a sort: the exact cell box of each chunk's particles.
+__device__ __forceinline__ bool slot_cell(const PartF64& P, long p, int& i, int& j, int& k) {
+  if (!(P.z[p] >= 0.0)) return false;
+  i = (int)floor(P.x[p]);
+  j = (int)floor(P.y[p]);
+  k = (int)floor(P.z[p]);
+  return true;
+}
+__device__ __forceinline__ bool slot_cell(const PartF32R& P, long p, int& i, int& j, int& k) {
+  const int c = P.cell[p];
+  if (c < 0) return false;
+  i = cell_i(c);
+  j = cell_j(c);
+  k = cell_k(c);
+  return true;
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void chunk_box_kernel(PT P, WorkLists L, int nx, int ny) {
+  __shared__ int s_red[kWaves][10];
+  const int n = L.cnt[0];
+  const long chunk = blockIdx.x;
+  const long chunk0 = chunk * kChunk;
+  int v[10] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+  for (int q = 0; q < kPPT; ++q) {
+    const long p = chunk0 + q * kBlock + threadIdx.x;
+    int i, j, k;
+    if (p < n && slot_cell(P, p, i, j, k)) box_update(v, i, j, k, nx, ny);
+  }
+  block_minmax(v, s_red);
+  if (threadIdx.x != 0) return;
+  int32_t* b = L.box + 6 * chunk;
+  if (v[0] > v[1]) {
+    for (int t = 0; t < 6; ++t) b[t] = 0;
+    return;
+  }
+  int c0, nc;
+  axis_cells(v[0], v[1], v[2], v[3], nx, c0, nc);
+  b[0] = c0;
+  b[1] = nc;
+  axis_cells(v[4], v[5], v[6], v[7], ny, c0, nc);
+  b[2] = c0;
+  b[3] = nc;
+  b[4] = v[8];
+  b[5] = v[9] - v[8] + 1;
+}
+
+// ---------------------------------------------------------------- MD particles
+// The particles that started the step inside an MD cube: the sub-cycled PPPM
+// motion in FP64, grain and electrode absorption, the collision, the deposit.
+// One block per chunk list segment.
+__device__ __forceinline__ void load_d(const PartF64& P, long p, double x[3], double v[3]) {
+  x[0] = P.x[p];
+  x[1] = P.y[p];
+  x[2] = P.z[p];
+  v[0] = P.vx[p];
+  v[1] = P.vy[p];
+  v[2] = P.vz[p];
+}
+__device__ __forceinline__ void load_d(const PartF32R& P, long p, double x[3], double v[3]) {
+  const int c = P.cell[p];
+  x[0] = (double)cell_i(c) + (double)P.ox[p];
+  x[1] = (double)cell_j(c) + (double)P.oy[p];
+  x[2] = (double)cell_k(c) + (double)P.oz[p];
+  v[0] = P.vx[p];
+  v[1] = P.vy[p];
+  v[2] = P.vz[p];
+}
+
+// store the survivor (returns false if rounding put it on the rf electrode)
+__device__ __forceinline__ bool store_d(const PartF64& P, long p, const double x[3],
+                                        const double v[3], double* rho, const SpeciesStep& S) {
+  P.x[p] = x[0];
+  P.y[p] = x[1];
+  P.z[p] = x[2];
+  P.vx[p] = v[0];
+  P.vy[p] = v[1];
+  P.vz[p] = v[2];
+  deposit_global_f64(rho, S, x[0], x[1], x[2]);
+  return true;
+}
+__device__ __forceinline__ bool store_d(const PartF32R& P, long p, const double x[3],
+                                        const double v[3], long long* rho, const SpeciesStep& S) {
+  int c[3];
+  float f[3];
+  const int n3[3] = {S.nx, S.ny, S.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    c[a] = (int)floor(x[a]);
+    f[a] = (float)(x[a] - (double)c[a]);
+    if (f[a] >= 1.0f) {
+      f[a] = 0.0f;
+      c[a] += 1;
+      if (a < 2 && c[a] == n3[a]) c[a] = 0;
+    }
+  }
+  P.vx[p] = (float)v[0];
+  P.vy[p] = (float)v[1];
+  P.vz[p] = (float)v[2];
+  if (c[2] >= S.nz) {
+    P.cell[p] = -1;
+    return false;
+  }
+  P.cell[p] = pack_cell(c[0], c[1], c[2]);
+  P.ox[p] = f[0];
+  P.oy[p] = f[1];
+  P.oz[p] = f[2];
+  deposit_global_fixed(rho, S, c[0], c[1], c[2], f[0], f[1], f[2]);
+  return true;
+}
+__device__ __forceinline__ void kill(const PartF64& P, long p) { P.z[p] = -1.0; }
+__device__ __forceinline__ void kill(const PartF32R& P, long p) { P.cell[p] = -1; }
+
+// one MD particle per thread over the dense list of this step
+template <typename PT, typename ET, typename RT>
+__global__ __launch_bounds__(64) void md_kernel(PT P, const ET* __restrict__ E, RT* __restrict__ rho,
+                                                MdTables md, SpeciesStep S,
+                                                unsigned long long* __restrict__ grain_count,
+                                                WorkLists L, int nchunks, int do_mcc) {
+  const int total = L.cnt[2];
+  unsigned long long* tally = L.tally + (long)TL_N * nchunks;  // the MD row
+  for (long base = (long)blockIdx.x * 64; base < total; base += (long)gridDim.x * 64) {
+    const int idx = (int)base + threadIdx.x;
+    int st = ST_NONE;
+    bool coll = false, capv = false;
+    if (idx < total) {
+      const long p = L.md[idx];
+      double x[3], v[3];
+      load_d(P, p, x, v);
       int hit = -1;
       st = md_move(E, md, S, x, v, hit);
       if (st == ST_GRAIN) atomicAdd(&grain_count[2 * hit + S.sp], 1ull);
+      if (st == ST_ALIVE && do_mcc) collide(S, P.id[p], v, coll, capv);
       if (st == ST_ALIVE) {
-        ci = (int)floor(x[0]);
-        cj = (int)floor(x[1]);
-        ck = (int)floor(x[2]);
+        if (!store_d(P, p, x, v, rho, S)) st = ST_WALL1;
+      } else {
+        kill(P, p);
+      }
+    }
+    wave_count(st == ST_WALL0, &tally[TL_W0]);
+    wave_count(st == ST_WALL1, &tally[TL_W1]);
+    wave_count(st == ST_BAD, &tally[TL_BAD]);
+    wave_count(coll, &tally[TL_COLL]);
+    wave_count(capv, &tally[TL_CAP]);
+    wave_count(st == ST_WALL0 || st == ST_WALL1 || st == ST_BAD || st == ST_GRAIN, &tally[TL_DEAD]);
+  }
+}
+
+// the dense MD list starts empty for the next step
+__global__ void md_reset_kernel(int32_t* cnt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) cnt[2] = 0;
+}
+
+// ---------------------------------------------------------------- outliers
+// Particles that started outside their chunk's tile (they drifted since the
+// last sort): the same push with the field gathered from global memory and the
+// charge deposited with global atomics, the collision done in place.  One wave
+// per chunk segment.
+__global__ __launch_bounds__(64) void outlier_f32r_kernel(PartF32R P, const float4* __restrict__ E,
+                                                          long long* __restrict__ rho,
+                                                          SpeciesStep S, WorkLists L, int do_mcc) {
+  const long chunk = blockIdx.x;
+  const int count = L.out_cnt[chunk];
+  if (count == 0) return;
+  const int32_t* seg = L.out + chunk * kChunk;
+  int t_w0 = 0, t_w1 = 0, t_bad = 0, t_coll = 0, t_cap = 0;
+  for (int idx = threadIdx.x; idx < count; idx += 64) {
+    const long p = seg[idx];
+    const int c = P.cell[p];
+    int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
+    float o[3] = {P.ox[p], P.oy[p], P.oz[p]};
+    float v[3] = {P.vx[p], P.vy[p], P.vz[p]};
+    float ec[8][3];
+    const int i1 = ci + 1 == S.nx ? 0 : ci + 1;
+    const int j1 = cj + 1 == S.ny ? 0 : cj + 1;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int c = a == 0 ? ci : (a == 1 ? cj : ck);
-          float f = (float)(x[a] - (double)c);
-          if (f >= 1.0f) {
-            f = 0.0f;
-            if (a == 0) ci = ci + 1 == S.nx ? 0 : ci + 1;
-            if (a == 1) cj = cj + 1 == S.ny ? 0 : cj + 1;
-            if (a == 2) ck += 1;
-          }
-          o[a] = f;
+    for (int t = 0; t < 8; ++t) {
+      const float4 e = E[((t & 1) ? i1 : ci) + (long)S.nx * (((t >> 1) & 1) ? j1 : cj) +
+                         (long)S.nxy * (ck + (t >> 2))];
+      ec[t][0] = e.x;
+      ec[t][1] = e.y;
+      ec[t][2] = e.z;
+    }
+    const int st = push_one_f32(S, ec, o, v, ci, cj, ck);
+    if (st == ST_ALIVE) {
+      bool coll = false, capv = false;
+      if (do_mcc) {
+        const uint32_t id = P.id[p];
+        const uint4 r = philox4x32_10(id, S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+        if ((uint64_t)r.x < S.T_null) {
+          double vd[3] = {v[0], v[1], v[2]};
+          collide(S, id, vd, coll, capv);
+          v[0] = (float)vd[0];
+          v[1] = (float)vd[1];
+          v[2] = (float)vd[2];
         }
-        if (ck >= S.nz) st = ST_WALL1;
       }
-      vf[0] = (float)v[0];
-      vf[1] = (float)v[1];
-      vf[2] = (float)v[2];
+      t_coll += coll;
+      t_cap += capv;
+      P.cell[p] = pack_cell(ci, cj, ck);
+      P.ox[p] = o[0];
+      P.oy[p] = o[1];
+      P.oz[p] = o[2];
+      deposit_global_fixed(rho, S, ci, cj, ck, o[0], o[1], o[2]);
+    } else {
+      P.cell[p] = -1;
     }
-    if (st == ST_ALIVE && do_mcc) {
-      // the candidate test is integer; the kinematics of the few candidates run in FP64
-      const uint4 r = philox4x32_10(id, S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
-      if ((uint64_t)r.x < S.T_null) {
-        double v[3] = {vf[0], vf[1], vf[2]};
-        collide(S, id, v, coll, capv);
-        vf[0] = (float)v[0];
-        vf[1] = (float)v[1];
-        vf[2] = (float)v[2];
+    P.vx[p] = v[0];
+    P.vy[p] = v[1];
+    P.vz[p] = v[2];
+    t_w0 += st == ST_WALL0;
+    t_w1 += st == ST_WALL1;
+    t_bad += st == ST_BAD;
+  }
+  t_w0 = wave_sum(t_w0);
+  t_w1 = wave_sum(t_w1);
+  t_bad = wave_sum(t_bad);
+  t_coll = wave_sum(t_coll);
+  t_cap = wave_sum(t_cap);
+  if (threadIdx.x == 0) {
+    unsigned long long* tl = L.tally + TL_N * chunk;
+    tl[TL_W0] += t_w0;
+    tl[TL_W1] += t_w1;
+    tl[TL_BAD] += t_bad;
+    tl[TL_COLL] += t_coll;
+    tl[TL_CAP] += t_cap;
+    tl[TL_DEAD] += t_w0 + t_w1 + t_bad;
+  }
+}
+
+__global__ __launch_bounds__(64) void outlier_f64_kernel(PartF64 P, const double2* __restrict__ E,
+                                                         double* __restrict__ rho, SpeciesStep S,
+                                                         WorkLists L, int do_mcc) {
+  const long chunk = blockIdx.x;
+  const int count = L.out_cnt[chunk];
+  if (count == 0) return;
+  const int32_t* seg = L.out + chunk * kChunk;
+  int t_w0 = 0, t_w1 = 0, t_bad = 0, t_coll = 0, t_cap = 0;
+  for (int idx = threadIdx.x; idx < count; idx += 64) {
+    const long p = seg[idx];
+    double x[3], v[3];
+    load_d(P, p, x, v);
+    const int i0 = (int)floor(x[0]), j0 = (int)floor(x[1]), k0 = (int)floor(x[2]);
+    double Ep[3];
+    gather_d(E, S, i0, j0, k0, x[0] - i0, x[1] - j0, x[2] - k0, Ep);
+    const int st = push_one_f64(S, Ep, x, v);
+    if (st == ST_ALIVE) {
+      bool coll = false, capv = false;
+      if (do_mcc) {
+        const uint32_t id = P.id[p];
+        const uint4 r = philox4x32_10(id, S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+        if ((uint64_t)r.x < S.T_null) collide(S, id, v, coll, capv);
       }
+      t_coll += coll;
+      t_cap += capv;
+      store_d(P, p, x, v, rho, S);
+    } else {
+      kill(P, p);
+      P.vx[p] = v[0];
+      P.vy[p] = v[1];
+      P.vz[p] = v[2];
     }
+    t_w0 += st == ST_WALL0;
+    t_w1 += st == ST_WALL1;
+    t_bad += st == ST_BAD;
   }
-  const bool keep = st == ST_ALIVE;
-  const int dst = compact_slot(keep, n_out, s_wave, &s_base);
-  if (keep) {
-    out.cell[dst] = ci + S.nx * (cj + S.ny * ck);
-    out.ox[dst] = o[0];
-    out.oy[dst] = o[1];
-    out.oz[dst] = o[2];
-    out.vx[dst] = vf[0];
-    out.vy[dst] = vf[1];
-    out.vz[dst] = vf[2];
-    out.id[dst] = id;
-    deposit_fixed(rho_next, S, ci, cj, ck, o[0], o[1], o[2]);
+  t_w0 = wave_sum(t_w0);
+  t_w1 = wave_sum(t_w1);
+  t_bad = wave_sum(t_bad);
+  t_coll = wave_sum(t_coll);
+  t_cap = wave_sum(t_cap);
+  if (threadIdx.x == 0) {
+    unsigned long long* tl = L.tally + TL_N * chunk;
+    tl[TL_W0] += t_w0;
+    tl[TL_W1] += t_w1;
+    tl[TL_BAD] += t_bad;
+    tl[TL_COLL] += t_coll;
+    tl[TL_CAP] += t_cap;
+    tl[TL_DEAD] += t_w0 + t_w1 + t_bad;
   }
-  wave_count(st == ST_WALL0, &T->wall[0][S.sp]);
-  wave_count(st == ST_WALL1, &T->wall[1][S.sp]);
-  wave_count(coll, &T->n_coll[S.sp]);
-  wave_count(capv, &T->cap_viol[S.sp]);
-  wave_count(is_md, &T->md[S.sp]);
-  wave_count(st == ST_BAD, &T->numeric_bad);
+}
+
+// ---------------------------------------------------------------- collisions
+// One wave per chunk list segment of collision candidates.
+template <typename PT>
+__global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLists L) {
+  const long chunk = blockIdx.x;
+  const int count = L.coll_cnt[chunk];
+  if (count == 0) return;
+  const int32_t* seg = L.coll + chunk * kChunk;
+  int n_coll = 0, n_cap = 0;
+  for (int idx = threadIdx.x; idx < count; idx += 64) {
+    const long p = seg[idx];
+    bool coll = false, capv = false;
+    double v[3] = {(double)P.vx[p], (double)P.vy[p], (double)P.vz[p]};
+    collide(S, P.id[p], v, coll, capv);
+    if (coll) {
+      P.vx[p] = v[0];
+      P.vy[p] = v[1];
+      P.vz[p] = v[2];
+    }
+    n_coll += coll;
+    n_cap += capv;
+  }
+  n_coll = wave_sum(n_coll);
+  n_cap = wave_sum(n_cap);
+  if (threadIdx.x == 0) {
+    L.tally[TL_N * chunk + TL_COLL] += (unsigned long long)n_coll;
+    L.tally[TL_N * chunk + TL_CAP] += (unsigned long long)n_cap;
+  }
 }
 
 // ---------------------------------------------------------------- loading
@@ -562,13 +1321,14 @@ __global__ void init_f64_kernel(PartF64 P, int n, int ppc, int nx, int ny, int s
   P.id[p] = (uint32_t)p;
 }
 
-__global__ void init_f32r_kernel(PartF32R P, int n, int ppc, int sp, uint32_t k0, uint32_t k1,
-                                 double vth) {
+__global__ void init_f32r_kernel(PartF32R P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
+                                 uint32_t k1, double vth) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
+  const int cell = p / ppc;
   double off[3], vel[3];
   load_draws((uint32_t)p, sp, k0, k1, vth, off, vel);
-  P.cell[p] = p / ppc;
+  P.cell[p] = pack_cell(cell % nx, (cell / nx) % ny, cell / (nx * ny));
   P.ox[p] = (float)off[0];
   P.oy[p] = (float)off[1];
   P.oz[p] = (float)off[2];
@@ -578,35 +1338,53 @@ __global__ void init_f32r_kernel(PartF32R P, int n, int ppc, int sp, uint32_t k0
   P.id[p] = (uint32_t)p;
 }
 
-// ---------------------------------------------------------------- deposit only
-__global__ void deposit_f64_kernel(PartF64 P, const int* __restrict__ n_in,
-                                   double* __restrict__ rho, SpeciesStep S) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= *n_in) return;
-  deposit_f64(rho, S, P.x[p], P.y[p], P.z[p]);
-}
-
-__global__ void deposit_f32r_kernel(PartF32R P, const int* __restrict__ n_in,
-                                    long long* __restrict__ rho, SpeciesStep S) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= *n_in) return;
-  const int cell = P.cell[p];
-  const int k = cell / S.nxy, rem = cell - k * S.nxy, j = rem / S.nx, i = rem - j * S.nx;
-  deposit_fixed(rho, S, i, j, k, P.ox[p], P.oy[p], P.oz[p]);
-}
-
 // ---------------------------------------------------------------- cell sort
-__device__ __forceinline__ int cell_of(const PartF64& P, int p, int nx, int ny) {
-  return (int)floor(P.x[p]) + nx * ((int)floor(P.y[p]) + ny * (int)floor(P.z[p]));
+// Counting sort of one species by linear cell index (x fastest), dropping the
+// empty slots: histogram, exclusive scan, scatter into the other buffer.
+// key of a cell in 4x4x4-tile order (tiles x fastest, cells x fastest inside a tile)
+struct TileOrder {
+  int ntx, nty;  // tiles along x, y
+};
+__device__ __forceinline__ int tiled_key(int i, int j, int k, TileOrder o) {
+  return (((k >> 2) * o.nty + (j >> 2)) * o.ntx + (i >> 2)) * 64 + ((k & 3) * 4 + (j & 3)) * 4 +
+         (i & 3);
 }
-__device__ __forceinline__ int cell_of(const PartF32R& P, int p, int, int) { return P.cell[p]; }
+__device__ __forceinline__ int sort_key(const PartF64& P, int p, TileOrder o) {
+  if (!(P.z[p] >= 0.0)) return -1;
+  return tiled_key((int)floor(P.x[p]), (int)floor(P.y[p]), (int)floor(P.z[p]), o);
+}
+__device__ __forceinline__ int sort_key(const PartF32R& P, int p, TileOrder o) {
+  const int c = P.cell[p];
+  if (c < 0) return -1;
+  return tiled_key(cell_i(c), cell_j(c), cell_k(c), o);
+}
+
+// Runs of equal keys in neighbouring lanes (the input is nearly sorted): each
+// lane learns the lane that heads its run, its rank in the run and, for the
+// head, the run length, so one atomic serves the whole run.
+struct Run {
+  int head, rank, len;
+};
+__device__ __forceinline__ Run lane_run(int key) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  const bool is_head = lane == 0 || key != prev;
+  const unsigned long long heads = __ballot(is_head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  Run r;
+  r.head = 63 - __clzll((long long)(heads & upto));
+  r.rank = lane - r.head;
+  const unsigned long long above = lane == 63 ? 0ull : (heads & ~upto);
+  r.len = (above ? __ffsll((long long)above) - 1 : 64) - lane;
+  return r;
+}
 
 template <typename PT>
-__global__ void sort_hist_kernel(PT P, const int* __restrict__ n_in, int* __restrict__ hist,
-                                 int nx, int ny) {
+__global__ void sort_hist_kernel(PT P, int* __restrict__ cnt, int* __restrict__ hist, TileOrder o) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= *n_in) return;
-  atomicAdd(&hist[cell_of(P, p, nx, ny)], 1);
+  const int key = p < cnt[0] ? sort_key(P, p, o) : -1;
+  const Run r = lane_run(key);
+  if (key >= 0 && r.rank == 0) atomicAdd(&hist[key], r.len);
 }
 
 __device__ __forceinline__ void copy_particle(const PartF64& a, int i, const PartF64& b, int j) {
@@ -630,12 +1408,26 @@ __device__ __forceinline__ void copy_particle(const PartF32R& a, int i, const Pa
 }
 
 template <typename PT>
-__global__ void sort_scatter_kernel(PT src, PT dst, const int* __restrict__ n_in,
-                                    int* __restrict__ cursor, int nx, int ny) {
+__global__ void sort_scatter_kernel(PT src, PT dst, const int* __restrict__ cnt,
+                                    int* __restrict__ cursor, TileOrder o) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= *n_in) return;
-  const int d = atomicAdd(&cursor[cell_of(src, p, nx, ny)], 1);
-  copy_particle(src, p, dst, d);
+  const int key = p < cnt[0] ? sort_key(src, p, o) : -1;
+  const Run r = lane_run(key);
+  int base = 0;
+  if (key >= 0 && r.rank == 0) base = atomicAdd(&cursor[key], r.len);
+  base = __shfl(base, r.head, 64);
+  if (key >= 0) copy_particle(src, p, dst, base + r.rank);
+}
+
+// after the scatter the survivors fill [0, cnt[4]) of the other buffer; the
+// empty-slot counts start again from zero
+__global__ void sort_finish_kernel(int* cnt, unsigned long long* tally, int nchunks) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c <= nchunks) tally[TL_N * c + TL_DEAD] = 0;  // row nchunks: the MD kernel
+  if (c == 0) {
+    cnt[0] = cnt[4];
+    cnt[4] = 0;
+  }
 }
 
 // exclusive scan of an int array: per-block sums, scan of the sums, per-block scan
@@ -652,8 +1444,7 @@ __global__ void scan_block_sums(const int* __restrict__ a, int n, int* __restric
   if (threadIdx.x == 0) sums[blockIdx.x] = s[0];
 }
 
-__global__ void scan_sums_serial(int* __restrict__ sums, int nb) {
-  // one block: exclusive scan of the block sums, chunk by chunk
+__global__ void scan_sums_serial(int* __restrict__ sums, int nb, int* __restrict__ total) {
   __shared__ int s[kScanBlock];
   __shared__ int carry;
   if (threadIdx.x == 0) carry = 0;
@@ -674,6 +1465,7 @@ __global__ void scan_sums_serial(int* __restrict__ sums, int nb) {
     if (threadIdx.x == kScanBlock - 1) carry += s[threadIdx.x];
     __syncthreads();
   }
+  if (threadIdx.x == 0 && total) *total = carry;
 }
 
 __global__ void scan_apply(const int* __restrict__ a, int n, const int* __restrict__ sums,
@@ -700,22 +1492,50 @@ __global__ void fill_int_kernel(int* a, long n, int v) {
 // ---------------------------------------------------------------- launchers
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
-void launch_push_f64(const PartF64& in, const PartF64& out, const int* n_in, int* n_out,
-                     const double* E, double* rho_next, const MdTables& md,
-                     const SpeciesStep& S, Tallies* T, unsigned long long* gc, int do_mcc,
-                     long capacity, hipStream_t st) {
+int push_chunks(long capacity) { return (nblk(capacity, kChunk) + 7) / 8 * 8; }
+
+void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
+                     const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st) {
   if (capacity <= 0) return;
-  hipLaunchKernelGGL(push_f64_kernel, dim3(nblk(capacity, kBlock)), dim3(kBlock), 0, st, in, out,
-                     n_in, n_out, (const double2*)E, rho_next, md, S, T, gc, do_mcc);
+  hipLaunchKernelGGL(push_f64_kernel<true>, dim3(push_chunks(capacity)), dim3(kBlock), 0, st, P,
+                     (const double2*)E, rho, md, S, L);
 }
 
-void launch_push_f32r(const PartF32R& in, const PartF32R& out, const int* n_in, int* n_out,
-                      const float* E, long long* rho_next, const MdTables& md,
-                      const SpeciesStep& S, Tallies* T, unsigned long long* gc, int do_mcc,
+void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
+                      const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st) {
+  if (capacity <= 0) return;
+  hipLaunchKernelGGL(push_f32r_kernel<true>, dim3(push_chunks(capacity)), dim3(kBlock), 0, st, P,
+                     (const float4*)E, rho, md, S, L);
+}
+
+constexpr int kMdBlocks = 2048;
+
+void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
+                      const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
                       long capacity, hipStream_t st) {
   if (capacity <= 0) return;
-  hipLaunchKernelGGL(push_f32r_kernel, dim3(nblk(capacity, kBlock)), dim3(kBlock), 0, st, in,
-                     out, n_in, n_out, (const float4*)E, rho_next, md, S, T, gc, do_mcc);
+  const int nc = push_chunks(capacity);
+  hipLaunchKernelGGL(outlier_f64_kernel, dim3(nc), dim3(64), 0, st, P, (const double2*)E, rho, S, L,
+                     do_mcc);
+  if (md.n_grains > 0)
+    hipLaunchKernelGGL((md_kernel<PartF64, double2, double>), dim3(kMdBlocks), dim3(64), 0, st, P,
+                       (const double2*)E, rho, md, S, gc, L, nc, do_mcc);
+  hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L.cnt);
+  if (do_mcc) hipLaunchKernelGGL(collide_kernel<PartF64>, dim3(nc), dim3(64), 0, st, P, S, L);
+}
+
+void launch_lists_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
+                       const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
+                       long capacity, hipStream_t st) {
+  if (capacity <= 0) return;
+  const int nc = push_chunks(capacity);
+  hipLaunchKernelGGL(outlier_f32r_kernel, dim3(nc), dim3(64), 0, st, P, (const float4*)E, rho, S,
+                     L, do_mcc);
+  if (md.n_grains > 0)
+    hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(kMdBlocks), dim3(64), 0, st,
+                       P, (const float4*)E, rho, md, S, gc, L, nc, do_mcc);
+  hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L.cnt);
+  if (do_mcc) hipLaunchKernelGGL(collide_kernel<PartF32R>, dim3(nc), dim3(64), 0, st, P, S, L);
 }
 
 void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
@@ -725,25 +1545,25 @@ void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, u
                      k0, k1, vth);
 }
 
-void launch_init_f32r(const PartF32R& P, int n, int ppc, int sp, uint32_t k0, uint32_t k1,
-                      double vth, hipStream_t st) {
+void launch_init_f32r(const PartF32R& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
+                      uint32_t k1, double vth, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(init_f32r_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, P, n, ppc, sp, k0,
-                     k1, vth);
+  hipLaunchKernelGGL(init_f32r_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, P, n, ppc, nx, ny, sp,
+                     k0, k1, vth);
 }
 
-void launch_deposit_f64(const PartF64& P, const int* n_in, double* rho, const SpeciesStep& S,
-                        long capacity, hipStream_t st) {
+void launch_deposit_f64(const PartF64& P, double* rho, const MdTables& md, const SpeciesStep& S,
+                        const WorkLists& L, long capacity, hipStream_t st) {
   if (capacity <= 0) return;
-  hipLaunchKernelGGL(deposit_f64_kernel, dim3(nblk(capacity, 256)), dim3(256), 0, st, P, n_in,
-                     rho, S);
+  hipLaunchKernelGGL(push_f64_kernel<false>, dim3(push_chunks(capacity)), dim3(kBlock), 0, st, P,
+                     nullptr, rho, md, S, L);
 }
 
-void launch_deposit_f32r(const PartF32R& P, const int* n_in, long long* rho,
-                         const SpeciesStep& S, long capacity, hipStream_t st) {
+void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
+                         const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st) {
   if (capacity <= 0) return;
-  hipLaunchKernelGGL(deposit_f32r_kernel, dim3(nblk(capacity, 256)), dim3(256), 0, st, P, n_in,
-                     rho, S);
+  hipLaunchKernelGGL(push_f32r_kernel<false>, dim3(push_chunks(capacity)), dim3(kBlock), 0, st, P,
+                     nullptr, rho, md, S, L);
 }
 
 void launch_fill_int(int* a, long n, int v, hipStream_t st) {
@@ -751,30 +1571,40 @@ void launch_fill_int(int* a, long n, int v, hipStream_t st) {
   hipLaunchKernelGGL(fill_int_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a, n, v);
 }
 
+long sort_keys(int nx, int ny, int nz) {
+  return (long)((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) * 64;
+}
+
 template <typename PT>
-static void sort_impl(const PT& src, const PT& dst, const int* n_in, int* hist, int* sums,
-                      long ncell, int nx, int ny, long capacity, hipStream_t st) {
-  launch_fill_int(hist, ncell, 0, st);
-  hipLaunchKernelGGL(sort_hist_kernel<PT>, dim3(nblk(capacity, 256)), dim3(256), 0, st, src, n_in,
-                     hist, nx, ny);
-  const int nb = nblk(ncell, kScanBlock);
-  hipLaunchKernelGGL(scan_block_sums, dim3(nb), dim3(kScanBlock), 0, st, hist, (int)ncell, sums);
-  hipLaunchKernelGGL(scan_sums_serial, dim3(1), dim3(kScanBlock), 0, st, sums, nb);
-  hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kScanBlock), 0, st, hist, (int)ncell, sums, hist);
+static void sort_impl(const PT& src, const PT& dst, const WorkLists& L, int* hist, int* sums, int nx,
+                      int ny, int nz, long capacity, hipStream_t st) {
+  const TileOrder o{(nx + 3) / 4, (ny + 3) / 4};
+  const long nkey = sort_keys(nx, ny, nz);
+  launch_fill_int(hist, nkey, 0, st);
+  hipLaunchKernelGGL(sort_hist_kernel<PT>, dim3(nblk(capacity, 256)), dim3(256), 0, st, src, L.cnt,
+                     hist, o);
+  const int nb = nblk(nkey, kScanBlock);
+  hipLaunchKernelGGL(scan_block_sums, dim3(nb), dim3(kScanBlock), 0, st, hist, (int)nkey, sums);
+  hipLaunchKernelGGL(scan_sums_serial, dim3(1), dim3(kScanBlock), 0, st, sums, nb, L.cnt + 4);
+  hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kScanBlock), 0, st, hist, (int)nkey, sums, hist);
   hipLaunchKernelGGL(sort_scatter_kernel<PT>, dim3(nblk(capacity, 256)), dim3(256), 0, st, src,
-                     dst, n_in, hist, nx, ny);
+                     dst, L.cnt, hist, o);
+  const int nc = push_chunks(capacity);
+  hipLaunchKernelGGL(sort_finish_kernel, dim3(nblk(nc + 1, 256)), dim3(256), 0, st, L.cnt, L.tally,
+                     nc);
+  hipLaunchKernelGGL(chunk_box_kernel<PT>, dim3(nc), dim3(kBlock), 0, st, dst, L, nx, ny);
 }
 
-void launch_sort_f64(const PartF64& src, const PartF64& dst, const int* n_in, int* hist,
-                     int* sums, long ncell, int nx, int ny, long capacity, hipStream_t st) {
+void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L, int* hist,
+                     int* sums, int nx, int ny, int nz, long capacity, hipStream_t st) {
   if (capacity <= 0) return;
-  sort_impl(src, dst, n_in, hist, sums, ncell, nx, ny, capacity, st);
+  sort_impl(src, dst, L, hist, sums, nx, ny, nz, capacity, st);
 }
 
-void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const int* n_in, int* hist,
-                      int* sums, long ncell, int nx, int ny, long capacity, hipStream_t st) {
+void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const WorkLists& L, int* hist,
+                      int* sums, int nx, int ny, int nz, long capacity, hipStream_t st) {
   if (capacity <= 0) return;
-  sort_impl(src, dst, n_in, hist, sums, ncell, nx, ny, capacity, st);
+  sort_impl(src, dst, L, hist, sums, nx, ny, nz, capacity, st);
 }
 
 }  // namespace pic

@@ -39,12 +39,14 @@ struct Replica {
   double q[2]{}, m[2]{}, vth[2]{}, g_cap[2]{}, P_null[2]{};
   uint64_t T_null[2]{};
   double vth_gas = 0;
-  long cap[2]{};
-  // particles: [species][buffer]
+  long n_load = 0;     // particles per species at load
+  long cap[2]{};       // slots per species buffer (a multiple of 1024)
+  // particles: [species][buffer]; updated in place, the other buffer receives the sort
   PartF64 p64[2][2]{};
   PartF32R p32[2][2]{};
   int cur = 0;
-  int* d_n = nullptr;  // [species * 2 + buffer]
+  int* d_cnt = nullptr;  // [species][8]: see WorkLists
+  WorkLists lists[2]{};
   // mesh
   void* rho[2]{};      // accumulators: double (units w e) or int64 (2^-32 e)
   int rho_cur = 0;
@@ -65,9 +67,10 @@ struct Replica {
   // near-grain tables
   MdTables md{};
   double* d_Q = nullptr;
-  // tallies
-  Tallies* d_T = nullptr;
+  // grain counts; event tallies live per chunk in lists[sp].tally
   unsigned long long* d_gc = nullptr;
+  long nchunks = 0;
+  int64_t wall_base[2][2]{};  // electrode counts handed over by pic_set_state
   // sort
   int* d_hist = nullptr;
   int* d_sums = nullptr;
@@ -87,7 +90,7 @@ struct pic_ctx {
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[3];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[4];
   ~pic_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
@@ -182,6 +185,7 @@ void periodic_bbox(const std::vector<char>& cov, int n, int* origin, int* size) 
 int validate(const pic_config& c, std::string& why) {
   auto bad = [&](const std::string& s) { why = s; return PIC_EINVAL; };
   if (c.nx < 2 || c.ny < 2 || c.nz < 2) return bad("nx, ny, nz must be >= 2");
+  if (c.nx > 1024 || c.ny > 1024 || c.nz > 2047) return bad("nx, ny <= 1024 and nz <= 2047");
   int f[12], nf;
   if (!factor_len(c.nx, f, &nf) || !factor_len(c.ny, f, &nf))
     return bad("nx and ny must factor into 2, 3 and 5");
@@ -340,7 +344,7 @@ SpeciesStep species_step(const Replica& R, int sp) {
   S.qm_dt_f = (float)S.qm_dt;
   S.dt_dx_f = (float)S.dt_dx;
   S.T_null = R.T_null[sp];
-  S.inv_g_cap = 1.0 / R.g_cap[sp];
+  S.g_cap = R.g_cap[sp];
   S.vth_gas = R.vth_gas;
   S.mass_ratio_e = R.m[0] / (R.m[0] + R.m[1]);
   S.mass_ratio_n = R.m[1] / (R.m[0] + R.m[1]);
@@ -378,7 +382,21 @@ int alloc_particles(pic_ctx* ctx, Replica& R) {
         TRY(dalloc(ctx, R, &P.id, n));
       }
     }
-  TRY(dalloc(ctx, R, &R.d_n, 4));
+  TRY(dalloc(ctx, R, &R.d_cnt, 16));
+  R.nchunks = push_chunks(R.cap[0]);
+  for (int sp = 0; sp < 2; ++sp) {
+    WorkLists& L = R.lists[sp];
+    TRY(dalloc(ctx, R, &L.md, R.cap[sp]));
+    TRY(dalloc(ctx, R, &L.coll, R.cap[sp]));
+    TRY(dalloc(ctx, R, &L.out, R.cap[sp]));
+    TRY(dalloc(ctx, R, &L.coll_cnt, R.nchunks));
+    TRY(dalloc(ctx, R, &L.out_cnt, R.nchunks));
+    TRY(dalloc(ctx, R, &L.box, 6 * R.nchunks));
+    TRY(dalloc(ctx, R, &L.tally, TL_N * (R.nchunks + 1)));
+    L.cnt = R.d_cnt + 8 * sp;
+    HIPCHK(ctx, hipMemsetAsync(L.tally, 0, 8 * TL_N * (R.nchunks + 1), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(L.box, 0, 4 * 6 * R.nchunks, ctx->stream));
+  }
   return PIC_OK;
 }
 
@@ -405,13 +423,13 @@ int deposit_current(pic_ctx* ctx, Replica& R) {
   if (R.prec == PIC_FP64) {
     launch_zero_f64((double*)R.rho[R.rho_cur], R.nn, st);
     for (int sp = 0; sp < 2; ++sp)
-      launch_deposit_f64(R.p64[sp][R.cur], R.d_n + 2 * sp + R.cur, (double*)R.rho[R.rho_cur],
-                         species_step(R, sp), R.cap[sp], st);
+      launch_deposit_f64(R.p64[sp][R.cur], (double*)R.rho[R.rho_cur], R.md, species_step(R, sp),
+                         R.lists[sp], R.cap[sp], st);
   } else {
     launch_zero_i64((long long*)R.rho[R.rho_cur], R.nn, st);
     for (int sp = 0; sp < 2; ++sp)
-      launch_deposit_f32r(R.p32[sp][R.cur], R.d_n + 2 * sp + R.cur, (long long*)R.rho[R.rho_cur],
-                          species_step(R, sp), R.cap[sp], st);
+      launch_deposit_f32r(R.p32[sp][R.cur], (long long*)R.rho[R.rho_cur], R.md,
+                          species_step(R, sp), R.lists[sp], R.cap[sp], st);
   }
   CHECK_LAUNCH(ctx);
   return PIC_OK;
@@ -443,54 +461,75 @@ int solve_fields(pic_ctx* ctx, Replica& R) {
   return PIC_OK;
 }
 
+// counting sort of both species into the other buffer (drops empty slots,
+// restores the tile order) and the chunk boxes of the sorted arrays
+int resort(pic_ctx* ctx, Replica& R) {
+  const int o = 1 - R.cur;
+  for (int sp = 0; sp < 2; ++sp) {
+    if (R.prec == PIC_FP64)
+      launch_sort_f64(R.p64[sp][R.cur], R.p64[sp][o], R.lists[sp], R.d_hist, R.d_sums, R.nx, R.ny,
+                      R.nz, R.cap[sp], ctx->stream);
+    else
+      launch_sort_f32r(R.p32[sp][R.cur], R.p32[sp][o], R.lists[sp], R.d_hist, R.d_sums, R.nx,
+                       R.ny, R.nz, R.cap[sp], ctx->stream);
+  }
+  CHECK_LAUNCH(ctx);
+  R.cur = o;
+  return PIC_OK;
+}
+
+// event tallies of one species summed over the chunks
+int read_tallies(pic_ctx* ctx, Replica& R, int sp, unsigned long long out[TL_N]) {
+  std::vector<unsigned long long> h((size_t)TL_N * (R.nchunks + 1));
+  HIPCHK(ctx, hipMemcpy(h.data(), R.lists[sp].tally, h.size() * 8, hipMemcpyDeviceToHost));
+  for (int w = 0; w < TL_N; ++w) out[w] = 0;
+  for (long c = 0; c <= R.nchunks; ++c)
+    for (int w = 0; w < TL_N; ++w) out[w] += h[(size_t)TL_N * c + w];
+  return PIC_OK;
+}
+
 int step_replica(pic_ctx* ctx, Replica& R) {
   hipStream_t st = ctx->stream;
   hipEvent_t f0 = prof_event(ctx);
   TRY(solve_fields(ctx, R));
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
-  const int nxt = 1 - R.cur, rnx = 1 - R.rho_cur;
-  for (int sp = 0; sp < 2; ++sp) launch_zero_i32(R.d_n + 2 * sp + nxt, 1, st);
+  const int rnx = 1 - R.rho_cur;
   const int do_mcc = 1;
   if (R.prec == PIC_FP64) {
     launch_zero_f64((double*)R.rho[rnx], R.nn, st);
     for (int sp = 0; sp < 2; ++sp) {
+      const SpeciesStep S = species_step(R, sp);
       hipEvent_t a = prof_event(ctx);
-      launch_push_f64(R.p64[sp][R.cur], R.p64[sp][nxt], R.d_n + 2 * sp + R.cur,
-                      R.d_n + 2 * sp + nxt, (const double*)R.E, (double*)R.rho[rnx], R.md,
-                      species_step(R, sp), R.d_T, R.d_gc, do_mcc, R.cap[sp], st);
-      prof_pair(ctx, PIC_PROF_PUSH, a, prof_event(ctx));
+      launch_push_f64(R.p64[sp][R.cur], (const double*)R.E, (double*)R.rho[rnx], R.md, S,
+                      R.lists[sp], R.cap[sp], st);
+      hipEvent_t b = prof_event(ctx);
+      launch_lists_f64(R.p64[sp][R.cur], (const double*)R.E, (double*)R.rho[rnx], R.md, S,
+                       R.d_gc, R.lists[sp], do_mcc, R.cap[sp], st);
+      prof_pair(ctx, PIC_PROF_PUSH, a, b);
+      prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
   } else {
     launch_zero_i64((long long*)R.rho[rnx], R.nn, st);
     for (int sp = 0; sp < 2; ++sp) {
+      const SpeciesStep S = species_step(R, sp);
       hipEvent_t a = prof_event(ctx);
-      launch_push_f32r(R.p32[sp][R.cur], R.p32[sp][nxt], R.d_n + 2 * sp + R.cur,
-                       R.d_n + 2 * sp + nxt, (const float*)R.E, (long long*)R.rho[rnx], R.md,
-                       species_step(R, sp), R.d_T, R.d_gc, do_mcc, R.cap[sp], st);
-      prof_pair(ctx, PIC_PROF_PUSH, a, prof_event(ctx));
+      launch_push_f32r(R.p32[sp][R.cur], (const float*)R.E, (long long*)R.rho[rnx], R.md, S,
+                       R.lists[sp], R.cap[sp], st);
+      hipEvent_t b = prof_event(ctx);
+      launch_lists_f32r(R.p32[sp][R.cur], (const float*)R.E, (long long*)R.rho[rnx], R.md, S,
+                        R.d_gc, R.lists[sp], do_mcc, R.cap[sp], st);
+      prof_pair(ctx, PIC_PROF_PUSH, a, b);
+      prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
   }
   CHECK_LAUNCH(ctx);
-  R.cur = nxt;
   R.rho_cur = rnx;
   R.step += 1;
   if (R.cfg.sort_interval > 0 && ++R.since_sort >= R.cfg.sort_interval) {
     R.since_sort = 0;
-    const int o = 1 - R.cur;
     hipEvent_t s0 = prof_event(ctx);
-    for (int sp = 0; sp < 2; ++sp) {
-      HIPCHK(ctx, hipMemcpyAsync(R.d_n + 2 * sp + o, R.d_n + 2 * sp + R.cur, sizeof(int),
-                                 hipMemcpyDeviceToDevice, st));
-      if (R.prec == PIC_FP64)
-        launch_sort_f64(R.p64[sp][R.cur], R.p64[sp][o], R.d_n + 2 * sp + R.cur, R.d_hist,
-                        R.d_sums, R.ncell, R.nx, R.ny, R.cap[sp], st);
-      else
-        launch_sort_f32r(R.p32[sp][R.cur], R.p32[sp][o], R.d_n + 2 * sp + R.cur, R.d_hist,
-                         R.d_sums, R.ncell, R.nx, R.ny, R.cap[sp], st);
-    }
-    CHECK_LAUNCH(ctx);
+    TRY(resort(ctx, R));
     prof_pair(ctx, PIC_PROF_SORT, s0, prof_event(ctx));
-    R.cur = o;
   }
   return PIC_OK;
 }
@@ -558,7 +597,8 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
     R.T_null[s] = (uint64_t)std::floor(R.P_null[s] * 4294967296.0);
   }
   R.vth_gas = std::sqrt(kBoltz * c.T_gas_K / kMassAr);
-  R.cap[0] = R.cap[1] = R.ncell * c.ppc;
+  R.n_load = R.ncell * c.ppc;
+  R.cap[0] = R.cap[1] = (R.n_load + 1023) / 1024 * 1024;
   if (!factor_len(R.nx, R.fft.fac_x, &R.fft.nfac_x) || !factor_len(R.ny, R.fft.fac_y, &R.fft.nfac_y))
     return fail(ctx, PIC_EINVAL, "FFT length not supported");
   R.fft.L_x = lines_per_block(R.nx, R.ny);
@@ -598,11 +638,10 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   TRY(dalloc(ctx, R, &R.b, R.n_int));
   TRY(dalloc(ctx, R, &R.phi, R.nn));
   TRY(dalloc(ctx, R, &R.norms, 2));
-  TRY(dalloc(ctx, R, &R.d_T, 1));
   TRY(dalloc(ctx, R, &R.d_gc, 2 * std::max(c.n_grains, 1)));
-  TRY(dalloc(ctx, R, &R.d_hist, R.ncell));
-  TRY(dalloc(ctx, R, &R.d_sums, (R.ncell + 1023) / 1024 + 1));
-  HIPCHK(ctx, hipMemsetAsync(R.d_T, 0, sizeof(Tallies), st));
+  const long nkey = sort_keys(R.nx, R.ny, R.nz);
+  TRY(dalloc(ctx, R, &R.d_hist, nkey));
+  TRY(dalloc(ctx, R, &R.d_sums, (nkey + 1023) / 1024 + 1));
   HIPCHK(ctx, hipMemsetAsync(R.d_gc, 0, 16 * std::max(c.n_grains, 1), st));
   HIPCHK(ctx, hipMemsetAsync(R.norms, 0, 16, st));
   TRY(setup_md(ctx, R));
@@ -611,18 +650,20 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   // load: ppc particles per cell, Maxwellian, Philox keyed by the seed
   const uint32_t k0 = (uint32_t)(c.seed & 0xffffffffu), k1 = (uint32_t)(c.seed >> 32);
   for (int sp = 0; sp < 2; ++sp) {
-    const int n = (int)R.cap[sp];
+    const int n = (int)R.n_load;
     if (R.prec == PIC_FP64)
       launch_init_f64(R.p64[sp][0], n, c.ppc, R.nx, R.ny, sp, k0, k1, R.vth[sp], st);
     else
-      launch_init_f32r(R.p32[sp][0], n, c.ppc, sp, k0, k1, R.vth[sp], st);
+      launch_init_f32r(R.p32[sp][0], n, c.ppc, R.nx, R.ny, sp, k0, k1, R.vth[sp], st);
   }
   CHECK_LAUNCH(ctx);
-  const int counts[4] = {(int)R.cap[0], 0, (int)R.cap[1], 0};
-  HIPCHK(ctx, hipMemcpyAsync(R.d_n, counts, sizeof(counts), hipMemcpyHostToDevice, st));
+  int counts[16] = {0};
+  counts[0] = counts[8] = (int)R.n_load;
+  HIPCHK(ctx, hipMemcpyAsync(R.d_cnt, counts, sizeof(counts), hipMemcpyHostToDevice, st));
   R.cur = 0;
   R.rho_cur = 0;
   R.step = 0;
+  TRY(resort(ctx, R));
   TRY(deposit_current(ctx, R));
   HIPCHK(ctx, hipStreamSynchronize(st));
   return PIC_OK;
@@ -747,52 +788,68 @@ int pic_get_state(pic_ctx* ctx, int replica, pic_state_view* v) {
   Replica* R = get_rep(ctx, replica);
   if (!R || !v) return fail(ctx, PIC_EINVAL, "bad replica or view");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  int n[4];
-  HIPCHK(ctx, hipMemcpy(n, R->d_n, sizeof(n), hipMemcpyDeviceToHost));
+  int cnts[16];
+  HIPCHK(ctx, hipMemcpy(cnts, R->d_cnt, sizeof(cnts), hipMemcpyDeviceToHost));
   for (int sp = 0; sp < 2; ++sp) {
-    const long cnt = n[2 * sp + R->cur];
-    if (cnt > v->capacity[sp]) return fail(ctx, PIC_EINVAL, "view capacity too small");
-    if (cnt > 0 && (!v->pos[sp] || !v->vel[sp] || !v->id[sp]))
-      return fail(ctx, PIC_EINVAL, "NULL view array");
-    v->n[sp] = cnt;
-    if (cnt == 0) continue;
-    HIPCHK(ctx, hipMemcpy(v->id[sp], R->prec == PIC_FP64 ? R->p64[sp][R->cur].id
-                                                          : R->p32[sp][R->cur].id,
-                          cnt * 4, hipMemcpyDeviceToHost));
-    if (R->prec == PIC_FP64) {
-      const PartF64& P = R->p64[sp][R->cur];
-      std::vector<double> a(cnt);
-      double* src[6] = {P.x, P.y, P.z, P.vx, P.vy, P.vz};
-      for (int q = 0; q < 6; ++q) {
-        HIPCHK(ctx, hipMemcpy(a.data(), src[q], cnt * 8, hipMemcpyDeviceToHost));
-        double* dst = q < 3 ? v->pos[sp] : v->vel[sp];
-        for (long i = 0; i < cnt; ++i) dst[3 * i + q % 3] = a[i];
-      }
-    } else {
-      const PartF32R& P = R->p32[sp][R->cur];
-      std::vector<int32_t> cell(cnt);
-      std::vector<float> a(cnt);
-      HIPCHK(ctx, hipMemcpy(cell.data(), P.cell, cnt * 4, hipMemcpyDeviceToHost));
-      for (long i = 0; i < cnt; ++i) {
-        const int k = (int)(cell[i] / R->nxy), rem = (int)(cell[i] - k * R->nxy);
-        v->pos[sp][3 * i + 0] = rem % R->nx;
-        v->pos[sp][3 * i + 1] = rem / R->nx;
-        v->pos[sp][3 * i + 2] = k;
-      }
-      float* src[6] = {P.ox, P.oy, P.oz, P.vx, P.vy, P.vz};
-      for (int q = 0; q < 6; ++q) {
-        HIPCHK(ctx, hipMemcpy(a.data(), src[q], cnt * 4, hipMemcpyDeviceToHost));
-        for (long i = 0; i < cnt; ++i) {
-          if (q < 3) v->pos[sp][3 * i + q] += (double)a[i];
-          else v->vel[sp][3 * i + q - 3] = (double)a[i];
+    const long slots = cnts[8 * sp];
+    // copy every slot in use, then keep the occupied ones
+    std::vector<uint32_t> ids(slots);
+    std::vector<double> a[6];
+    std::vector<char> alive(slots, 0);
+    if (slots > 0) {
+      HIPCHK(ctx, hipMemcpy(ids.data(), R->prec == PIC_FP64 ? R->p64[sp][R->cur].id
+                                                             : R->p32[sp][R->cur].id,
+                            slots * 4, hipMemcpyDeviceToHost));
+      for (auto& x : a) x.resize(slots);
+      if (R->prec == PIC_FP64) {
+        const PartF64& P = R->p64[sp][R->cur];
+        double* src[6] = {P.x, P.y, P.z, P.vx, P.vy, P.vz};
+        for (int q = 0; q < 6; ++q)
+          HIPCHK(ctx, hipMemcpy(a[q].data(), src[q], slots * 8, hipMemcpyDeviceToHost));
+        for (long i = 0; i < slots; ++i) alive[i] = a[2][i] >= 0.0;
+      } else {
+        const PartF32R& P = R->p32[sp][R->cur];
+        std::vector<int32_t> cell(slots);
+        std::vector<float> f(slots);
+        HIPCHK(ctx, hipMemcpy(cell.data(), P.cell, slots * 4, hipMemcpyDeviceToHost));
+        float* src[6] = {P.ox, P.oy, P.oz, P.vx, P.vy, P.vz};
+        for (int q = 0; q < 6; ++q) {
+          HIPCHK(ctx, hipMemcpy(f.data(), src[q], slots * 4, hipMemcpyDeviceToHost));
+          for (long i = 0; i < slots; ++i) a[q][i] = (double)f[i];
+        }
+        for (long i = 0; i < slots; ++i) {
+          const int c = cell[i];
+          alive[i] = c >= 0;
+          if (c < 0) continue;
+          a[0][i] += (double)(c & 1023);
+          a[1][i] += (double)((c >> 10) & 1023);
+          a[2][i] += (double)(c >> 20);
         }
       }
     }
+    long cnt = 0;
+    for (long i = 0; i < slots; ++i) cnt += alive[i];
+    if (cnt > v->capacity[sp]) return fail(ctx, PIC_EINVAL, "view capacity too small");
+    if (cnt > 0 && (!v->pos[sp] || !v->vel[sp] || !v->id[sp]))
+      return fail(ctx, PIC_EINVAL, "NULL view array");
+    long o = 0;
+    for (long i = 0; i < slots; ++i) {
+      if (!alive[i]) continue;
+      for (int q = 0; q < 3; ++q) {
+        v->pos[sp][3 * o + q] = a[q][i];
+        v->vel[sp][3 * o + q] = a[3 + q][i];
+      }
+      v->id[sp][o] = ids[i];
+      ++o;
+    }
+    v->n[sp] = cnt;
   }
-  Tallies T;
-  HIPCHK(ctx, hipMemcpy(&T, R->d_T, sizeof(T), hipMemcpyDeviceToHost));
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) v->wall_count[a][b] = (int64_t)T.wall[a][b];
+  for (int sp = 0; sp < 2; ++sp) {
+    unsigned long long t[TL_N];
+    TRY(read_tallies(ctx, *R, sp, t));
+    v->wall_count[0][sp] = R->wall_base[0][sp] + (int64_t)t[TL_W0];
+    v->wall_count[1][sp] = R->wall_base[1][sp] + (int64_t)t[TL_W1];
+  }
   if (v->grain_count && R->cfg.n_grains > 0)
     HIPCHK(ctx, hipMemcpy(v->grain_count, R->d_gc, 16 * R->cfg.n_grains, hipMemcpyDeviceToHost));
   v->step = R->step;
@@ -855,7 +912,7 @@ int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
           a[q * cnt + i] = f;
           a[(3 + q) * cnt + i] = (float)v->vel[sp][3 * i + q];
         }
-        cell[i] = c3[0] + R->nx * (c3[1] + R->ny * c3[2]);
+        cell[i] = c3[0] | (c3[1] << 10) | (c3[2] << 20);
       }
       HIPCHK(ctx, hipMemcpy(P.cell, cell.data(), cnt * 4, hipMemcpyHostToDevice));
       float* dst[6] = {P.ox, P.oy, P.oz, P.vx, P.vy, P.vz};
@@ -864,12 +921,14 @@ int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
       HIPCHK(ctx, hipMemcpy(P.id, v->id[sp], cnt * 4, hipMemcpyHostToDevice));
     }
   }
-  const int counts[4] = {(int)v->n[0], 0, (int)v->n[1], 0};
-  HIPCHK(ctx, hipMemcpy(R->d_n, counts, sizeof(counts), hipMemcpyHostToDevice));
-  Tallies T{};
+  int counts[16] = {0};
+  counts[0] = (int)v->n[0];
+  counts[8] = (int)v->n[1];
+  HIPCHK(ctx, hipMemcpy(R->d_cnt, counts, sizeof(counts), hipMemcpyHostToDevice));
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) T.wall[a][b] = (unsigned long long)v->wall_count[a][b];
-  HIPCHK(ctx, hipMemcpy(R->d_T, &T, sizeof(T), hipMemcpyHostToDevice));
+    for (int b = 0; b < 2; ++b) R->wall_base[a][b] = v->wall_count[a][b];
+  for (int sp = 0; sp < 2; ++sp)
+    HIPCHK(ctx, hipMemset(R->lists[sp].tally, 0, 8 * TL_N * (R->nchunks + 1)));
   const int ng = R->cfg.n_grains;
   if (ng > 0) {
     std::vector<int64_t> gc(2 * ng, 0);
@@ -878,6 +937,7 @@ int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
   }
   R->step = v->step;
   R->since_sort = 0;
+  TRY(resort(ctx, *R));
   TRY(deposit_current(ctx, *R));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   return PIC_OK;
@@ -889,19 +949,22 @@ int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out) {
   Replica* R = get_rep(ctx, replica);
   if (!R || !out) return fail(ctx, PIC_EINVAL, "bad replica or out");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  int n[4];
-  Tallies T;
+  int n[16];
   double norms[2] = {0, 0};
-  HIPCHK(ctx, hipMemcpy(n, R->d_n, sizeof(n), hipMemcpyDeviceToHost));
-  HIPCHK(ctx, hipMemcpy(&T, R->d_T, sizeof(T), hipMemcpyDeviceToHost));
+  HIPCHK(ctx, hipMemcpy(n, R->d_cnt, sizeof(n), hipMemcpyDeviceToHost));
   HIPCHK(ctx, hipMemcpy(norms, R->norms, sizeof(norms), hipMemcpyDeviceToHost));
   std::memset(out, 0, sizeof(*out));
   for (int sp = 0; sp < 2; ++sp) {
-    out->n_alive[sp] = n[2 * sp + R->cur];
-    out->cap_violation[sp] = (int64_t)T.cap_viol[sp];
-    out->n_collisions[sp] = (int64_t)T.n_coll[sp];
-    out->md_particles[sp] = (int64_t)T.md[sp];
-    for (int a = 0; a < 2; ++a) out->wall_count[a][sp] = (int64_t)T.wall[a][sp];
+    unsigned long long t[TL_N];
+    TRY(read_tallies(ctx, *R, sp, t));
+    out->n_alive[sp] = n[8 * sp] - (int64_t)t[TL_DEAD];
+    out->cap_violation[sp] = (int64_t)t[TL_CAP];
+    out->n_collisions[sp] = (int64_t)t[TL_COLL];
+    out->md_particles[sp] = (int64_t)t[TL_MD];
+    out->wall_count[0][sp] = R->wall_base[0][sp] + (int64_t)t[TL_W0];
+    out->wall_count[1][sp] = R->wall_base[1][sp] + (int64_t)t[TL_W1];
+    out->numeric_bad += (int64_t)t[TL_BAD];
+    out->tile_fallback += (int64_t)t[TL_FALL];
   }
   out->step = R->step;
   out->refine_sweeps = R->prec == PIC_FP32R ? R->cfg.max_refine : 0;
@@ -920,7 +983,7 @@ int pic_profile_enable(pic_ctx* ctx, int on) {
 
 int pic_profile_read(pic_ctx* ctx, int cls, double* total_ms, int64_t* launches) {
   if (!ctx) return PIC_EINVAL;
-  if (cls < 0 || cls > 2 || !total_ms || !launches) return fail(ctx, PIC_EINVAL, "bad arguments");
+  if (cls < 0 || cls > 3 || !total_ms || !launches) return fail(ctx, PIC_EINVAL, "bad arguments");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   double tot = 0.0;
   for (auto& p : ctx->ev_pairs[cls]) {

@@ -30,14 +30,23 @@ struct PartF32R {
   uint32_t* id;
 };
 
-// tallies of one replica (device, int64 so atomics are exact)
-struct Tallies {
-  unsigned long long wall[2][2];     // [wall][species]
-  unsigned long long cap_viol[2];
-  unsigned long long n_coll[2];
-  unsigned long long md[2];
-  unsigned long long numeric_bad;
+// per-species work lists and counters of one step (device)
+// coll and out are segmented by chunk (the 1024 consecutive slots one push
+// block streams): chunk c owns entries [1024 c, 1024 c + count[c]).
+struct WorkLists {
+  int32_t* md;        // dense list: slots of particles that start the step in an MD cube
+  int32_t* coll;      // slots of collision candidates (chunk segments)
+  int32_t* out;       // slots of particles outside their chunk's tile (chunk segments)
+  int32_t* coll_cnt;  // [chunk] entries in coll
+  int32_t* out_cnt;   // [chunk] entries in out
+  int32_t* box;       // [chunk][6] cell box of the chunk at the last sort: i0, ni, j0, nj, k0, nk
+  unsigned long long* tally;  // [chunk + 1][TL_N] accumulated event counts (see TallyKind);
+                              // the last row collects the MD kernel's events
+  int32_t* cnt;       // [0] slots in use, [2] entries in md, [4] survivors of the sort
 };
+
+// per-chunk event counts; TL_DEAD counts empty slots since the last sort
+enum TallyKind { TL_W0 = 0, TL_W1, TL_BAD, TL_MD, TL_FALL, TL_COLL, TL_CAP, TL_DEAD, TL_N };
 
 // near-grain (MD) tables of one replica
 struct MdTables {
@@ -67,7 +76,7 @@ struct SpeciesStep {
   float qm_dt_f, dt_dx_f;
   // null-collision MCC
   uint64_t T_null;         // candidate iff Philox word 0 < T_null
-  double inv_g_cap;
+  double g_cap;            // relative-speed cap
   double vth_gas;
   double mass_ratio_e;     // m_e / (m_e + M)
   double mass_ratio_n;     // M / (m_e + M)

@@ -22,7 +22,7 @@ PIC_PHI, PIC_E, PIC_RHO, PIC_RHO_FIXED = 1, 2, 4, 8
 SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destroy",
            "pic_last_error", "pic_get_state", "pic_set_state", "pic_get_counters", "pic_derived",
            "pic_profile_enable", "pic_profile_read")
-PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT = 0, 1, 2
+PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT, PIC_PROF_LISTS = 0, 1, 2, 3
 
 
 class PicError(RuntimeError):
@@ -65,6 +65,7 @@ class pic_counters(C.Structure):
         ("cap_violation", C.c_int64 * 2), ("n_collisions", C.c_int64 * 2),
         ("md_particles", C.c_int64 * 2),
         ("step", C.c_uint32), ("refine_sweeps", C.c_int32), ("refine_residual", C.c_double),
+        ("numeric_bad", C.c_int64), ("tile_fallback", C.c_int64),
     ]
 
 
@@ -234,7 +235,8 @@ def pic_get_counters(ctx, replica):
     return dict(n_alive=list(c.n_alive), wall_count=[[c.wall_count[a][b] for b in range(2)] for a in range(2)],
                 cap_violation=list(c.cap_violation), n_collisions=list(c.n_collisions),
                 md_particles=list(c.md_particles), step=int(c.step),
-                refine_sweeps=int(c.refine_sweeps), refine_residual=float(c.refine_residual))
+                refine_sweeps=int(c.refine_sweeps), refine_residual=float(c.refine_residual),
+                numeric_bad=int(c.numeric_bad), tile_fallback=int(c.tile_fallback))
 
 
 def pic_derived(ctx, replica):

@@ -84,6 +84,10 @@ CASES = [
     ("ragged", lambda p: W.tiny(nx=12, ny=10, nz=17, ppc=2, grains=[[0.3, 9.6, 8.5]], cutoff=2,
                                 precision=p), 1001, 777, [[3, 11]], 5),
     ("no_grains", lambda p: W.tiny(nx=16, ny=48, nz=9, ppc=1, precision=p), 4097, 255, None, 0),
+    # three separated grains: the near-grain lookup box has cells outside every cube
+    ("gaps", lambda p: W.tiny(nx=24, ny=24, nz=20, ppc=2, cutoff=1, precision=p,
+                              grains=[[4.5, 4.5, 6.2], [16.5, 18.3, 12.7], [12.1, 5.5, 9.9]]),
+     6000, 5000, [[5, 1], [0, 2], [9, 9]], 77),
 ]
 
 
