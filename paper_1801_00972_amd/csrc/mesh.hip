@@ -360,7 +360,7 @@ __global__ void extract_cube_kernel(const double2* __restrict__ E, const int* gc
 __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict__ psi,
                                                        const double* __restrict__ b,
                                                        double* __restrict__ r, int nx, int ny,
-                                                       int K, double* __restrict__ norms) {
+                                                       int K, double* __restrict__ partials) {
   __shared__ double s_r[256], s_b[256];
   const long plane = (long)nx * ny;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -393,8 +393,33 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    atomicAdd(&norms[0], s_r[0]);
-    atomicAdd(&norms[1], s_b[0]);
+    partials[2 * blockIdx.x] = s_r[0];
+    partials[2 * blockIdx.x + 1] = s_b[0];
+  }
+}
+
+// sum of the per-block partial norms (one block)
+__global__ __launch_bounds__(1024) void norm_reduce_kernel(const double* __restrict__ partials,
+                                                           int nb, double* __restrict__ norms) {
+  __shared__ double s_r[1024], s_b[1024];
+  double rr = 0.0, bb = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 1024) {
+    rr += partials[2 * i];
+    bb += partials[2 * i + 1];
+  }
+  s_r[threadIdx.x] = rr;
+  s_b[threadIdx.x] = bb;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s_r[threadIdx.x] += s_r[threadIdx.x + off];
+      s_b[threadIdx.x] += s_b[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    norms[0] = s_r[0];
+    norms[1] = s_b[0];
   }
 }
 
@@ -590,8 +615,9 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
 }
 
 // FP32 solves refined in FP64: psi = 0, r = b; repeat sweeps times
-// { psi += solve32(r); r = b - A psi }; phi = psi + lift.  norms receives
-// ||r||^2, ||b||^2 of the last sweep.
+// { psi += solve32(r); r = b - A psi }; phi = psi + lift.  norms[0..1] receive
+// ||r||^2, ||b||^2 of the last sweep; norms[2..] hold 2 per-block partials per
+// 256 interior nodes.
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
                           const void* tw_y32, const void* inv32, double* phi, double V,
@@ -603,9 +629,10 @@ void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const do
   for (int it = 0; it < sweeps; ++it) {
     solve_once<float>(P, nx, ny, nz, rhs, work32, tw_x32, tw_y32, inv32, OUT_REAL_ACCUM, psi, 0.0,
                       st);
-    hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(2), 0, st, norms, 2L);
     hipLaunchKernelGGL(residual_kernel, dim3(nb256(n_int)), dim3(256), 0, st, psi, b, r, nx, ny,
-                       nz - 1, norms);
+                       nz - 1, norms + 2);
+    hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb256(n_int),
+                       norms);
     rhs = r;
   }
   hipLaunchKernelGGL(lift_kernel, dim3(nb256(plane * (nz + 1))), dim3(256), 0, st, psi, phi, nx, ny,

@@ -110,12 +110,19 @@ __device__ __forceinline__ uint32_t md_lookup(const MdTables& md, int nx, int ny
   return (cl & 255u) ? cl : 0u;  // a cell of the box outside every cube has no grains
 }
 
+// per-grain data the sub-stepping reads every sub-step (staged in LDS when few)
+struct GrainView {
+  const double* gpos;   // [g][3] cell units
+  const int32_t* gcell; // [g][3]
+  const double* Q;      // [g] coulomb, frozen for the step
+};
+
 // separation x - x_g (cell units), minimum image across the periodic x,y
-__device__ __forceinline__ void grain_sep(const MdTables& md, const SpeciesStep& S, int g,
+__device__ __forceinline__ void grain_sep(const GrainView& G, const SpeciesStep& S, int g,
                                           const double x[3], double r[3]) {
-  r[0] = x[0] - md.gpos[3 * g + 0];
-  r[1] = x[1] - md.gpos[3 * g + 1];
-  r[2] = x[2] - md.gpos[3 * g + 2];
+  r[0] = x[0] - G.gpos[3 * g + 0];
+  r[1] = x[1] - G.gpos[3 * g + 1];
+  r[2] = x[2] - G.gpos[3 * g + 2];
   if (r[0] > 0.5 * S.nx) r[0] -= S.nx;
   else if (r[0] < -0.5 * S.nx) r[0] += S.nx;
   if (r[1] > 0.5 * S.ny) r[1] -= S.ny;
@@ -123,16 +130,16 @@ __device__ __forceinline__ void grain_sep(const MdTables& md, const SpeciesStep&
 }
 
 // CIC gather of grain g's unit-charge field from its cube of nodes
-__device__ __forceinline__ void gather_unit(const MdTables& md, const SpeciesStep& S, int g,
-                                            int i0, int j0, int k0, double fx, double fy,
-                                            double fz, double out[3]) {
+__device__ __forceinline__ void gather_unit(const MdTables& md, const GrainView& G,
+                                            const SpeciesStep& S, int g, int i0, int j0, int k0,
+                                            double fx, double fy, double fz, double out[3]) {
   const int c = md.cutoff, side = md.side;
   const long cube = (long)side * side * side;
-  int lx = i0 - (md.gcell[3 * g + 0] - c);
+  int lx = i0 - (G.gcell[3 * g + 0] - c);
   lx = ((lx % S.nx) + S.nx) % S.nx;
-  int ly = j0 - (md.gcell[3 * g + 1] - c);
+  int ly = j0 - (G.gcell[3 * g + 1] - c);
   ly = ((ly % S.ny) + S.ny) % S.ny;
-  const int lz = k0 - (md.gcell[3 * g + 2] - c);
+  const int lz = k0 - (G.gcell[3 * g + 2] - c);
   const double* U = md.U + (long)g * 3 * cube;
   out[0] = out[1] = out[2] = 0.0;
 #pragma unroll
@@ -154,31 +161,74 @@ __device__ __forceinline__ double wrap_coord(double X, int n) {
   return X;
 }
 
+constexpr int kMdCache = 8;  // grains of the current cell kept in registers
+
 // Sub-cycled PPPM motion near grains, Eq. (5)-(6): md_sub sub-steps of
 // h = dt/md_sub with E = E_mesh - sum_g Q_g U_g + sum_g Q_g r / (4 pi eps0 r^3)
 // over the grains whose cube holds the current cell; hit when |r| <= a.
+// A particle crosses a cell boundary in only a few of its sub-steps, so the
+// cell's 8 node fields and grain list are kept until the cell changes.
 template <typename ET>
-__device__ int md_move(const ET* __restrict__ E, const MdTables& md, const SpeciesStep& S,
-                       double x[3], double v[3], int& hit) {
+__device__ int md_move(const ET* __restrict__ E, const MdTables& md, const GrainView& G,
+                       const SpeciesStep& S, double x[3], double v[3], int& hit) {
+  int e_cell = -1, l_cell = -1;
+  double ec[8][3];
+  uint32_t cl = 0u;
+  int gl[kMdCache];
+  auto load_list = [&](int cell, int i0, int j0, int k0) {
+    if (cell == l_cell) return;
+    l_cell = cell;
+    cl = md_lookup(md, S.nx, S.ny, i0, j0, k0);
+#pragma unroll
+    for (int t = 0; t < kMdCache; ++t)
+      gl[t] = t < (int)(cl & 255u) ? md.grain_idx[(cl >> 8) + t] : 0;
+  };
+  auto grain_at = [&](int t) -> int {
+    int g = 0;
+#pragma unroll
+    for (int u = 0; u < kMdCache; ++u)
+      if (u == t) g = gl[u];
+    return t < kMdCache ? g : md.grain_idx[(cl >> 8) + t];
+  };
   for (int sub = 0; sub < S.md_sub; ++sub) {
     int i0 = (int)floor(x[0]), j0 = (int)floor(x[1]), k0 = (int)floor(x[2]);
-    double fx = x[0] - i0, fy = x[1] - j0, fz = x[2] - k0;
-    double Ep[3];
-    gather_d(E, S, i0, j0, k0, fx, fy, fz, Ep);
-    uint32_t cl = md_lookup(md, S.nx, S.ny, i0, j0, k0);
-    for (uint32_t t = 0; t < (cl & 255u); ++t) {
-      const int g = md.grain_idx[(cl >> 8) + t];
-      const double Q = md.Q[g];
+    const double fx = x[0] - i0, fy = x[1] - j0, fz = x[2] - k0;
+    int cell = pack_cell(i0, j0, k0);
+    if (cell != e_cell) {
+      e_cell = cell;
+      const int i1 = i0 + 1 == S.nx ? 0 : i0 + 1;
+      const int j1 = j0 + 1 == S.ny ? 0 : j0 + 1;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        load_node(E, ((t & 1) ? i1 : i0) + (long)S.nx * (((t >> 1) & 1) ? j1 : j0) +
+                         (long)S.nxy * (k0 + (t >> 2)),
+                  ec[t][0], ec[t][1], ec[t][2]);
+    }
+    load_list(cell, i0, j0, k0);
+    double Ep[3] = {0.0, 0.0, 0.0};
+    {
+      const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const double w = wx[t & 1] * wy[(t >> 1) & 1] * wz[t >> 2];
+        Ep[0] += w * ec[t][0];
+        Ep[1] += w * ec[t][1];
+        Ep[2] += w * ec[t][2];
+      }
+    }
+    for (int t = 0; t < (int)(cl & 255u); ++t) {
+      const int g = grain_at(t);
+      const double Q = G.Q[g];
       if (Q == 0.0) continue;
       double r[3];
-      grain_sep(md, S, g, x, r);
+      grain_sep(G, S, g, x, r);
       r[0] *= S.dx;
       r[1] *= S.dx;
       r[2] *= S.dx;
       const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
       const double inv = 1.0 / (4.0 * kPi * kEps0 * r2 * sqrt(r2));
       double Um[3];
-      gather_unit(md, S, g, i0, j0, k0, fx, fy, fz, Um);
+      gather_unit(md, G, S, g, i0, j0, k0, fx, fy, fz, Um);
       Ep[0] += Q * (r[0] * inv - Um[0]);
       Ep[1] += Q * (r[1] * inv - Um[1]);
       Ep[2] += Q * (r[2] * inv - Um[2]);
@@ -194,11 +244,12 @@ __device__ int md_move(const ET* __restrict__ E, const MdTables& md, const Speci
     i0 = (int)floor(x[0]);
     j0 = (int)floor(x[1]);
     k0 = (int)floor(x[2]);
-    cl = md_lookup(md, S.nx, S.ny, i0, j0, k0);
-    for (uint32_t t = 0; t < (cl & 255u); ++t) {
-      const int g = md.grain_idx[(cl >> 8) + t];
+    cell = pack_cell(i0, j0, k0);
+    load_list(cell, i0, j0, k0);
+    for (int t = 0; t < (int)(cl & 255u); ++t) {
+      const int g = grain_at(t);
       double r[3];
-      grain_sep(md, S, g, x, r);
+      grain_sep(G, S, g, x, r);
       r[0] *= S.dx;
       r[1] *= S.dx;
       r[2] *= S.dx;
@@ -1093,6 +1144,22 @@ __global__ __launch_bounds__(64) void md_kernel(PT P, const ET* __restrict__ E, 
                                                 unsigned long long* __restrict__ grain_count,
                                                 WorkLists L, int nchunks, int do_mcc) {
   const int total = L.cnt[2];
+  if ((long)blockIdx.x * 64 >= total) return;
+  constexpr int kStage = 256;
+  __shared__ double s_gpos[3 * kStage], s_Q[kStage];
+  __shared__ int32_t s_gcell[3 * kStage];
+  GrainView G{md.gpos, md.gcell, md.Q};
+  if (md.n_grains <= kStage) {
+    for (int t = threadIdx.x; t < md.n_grains; t += blockDim.x) {
+      s_Q[t] = md.Q[t];
+      for (int a = 0; a < 3; ++a) {
+        s_gpos[3 * t + a] = md.gpos[3 * t + a];
+        s_gcell[3 * t + a] = md.gcell[3 * t + a];
+      }
+    }
+    __syncthreads();
+    G = GrainView{s_gpos, s_gcell, s_Q};
+  }
   unsigned long long* tally = L.tally + (long)TL_N * nchunks;  // the MD row
   for (long base = (long)blockIdx.x * 64; base < total; base += (long)gridDim.x * 64) {
     const int idx = (int)base + threadIdx.x;
@@ -1103,7 +1170,7 @@ __global__ __launch_bounds__(64) void md_kernel(PT P, const ET* __restrict__ E, 
       double x[3], v[3];
       load_d(P, p, x, v);
       int hit = -1;
-      st = md_move(E, md, S, x, v, hit);
+      st = md_move(E, md, G, S, x, v, hit);
       if (st == ST_GRAIN) atomicAdd(&grain_count[2 * hit + S.sp], 1ull);
       if (st == ST_ALIVE && do_mcc) collide(S, P.id[p], v, coll, capv);
       if (st == ST_ALIVE) {
