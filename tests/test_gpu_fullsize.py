@@ -1,0 +1,83 @@
+"""Parity at the benchmark's full size (64x64x256 cells, 32 ppc, 8 grains, the
+launch configuration bench.py times), on outputs the oracle can compute one by
+one: all mesh quantities of a state the GPU produced after a few steps, and one
+step of a sample of particles (uniform, near grains, near the electrodes)
+moved by the oracle in its own field.  Plus exact particle conservation."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_00972_amd import workloads as W
+from tests.parity_util import compare_step, rel_inf
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+TOL = {"fp64": 1e-12, "fp32r": 1e-5}
+
+
+def _select(pos, grains, nz, rng, n_uniform=2000, n_grain=1500, n_wall=500):
+    n = len(pos)
+    pick = [rng.choice(n, size=min(n_uniform, n), replace=False)]
+    d2 = np.full(n, np.inf)
+    for g in grains:
+        d = pos - g
+        d2 = np.minimum(d2, np.sum(d * d, axis=1))
+    near = np.flatnonzero(d2 < 3.5 ** 2)
+    if len(near):
+        pick.append(rng.choice(near, size=min(n_grain, len(near)), replace=False))
+    wall = np.flatnonzero((pos[:, 2] < 0.3) | (pos[:, 2] > nz - 0.3))
+    if len(wall):
+        pick.append(rng.choice(wall, size=min(n_wall, len(wall)), replace=False))
+    return np.unique(np.concatenate(pick))
+
+
+@pytest.mark.parametrize("prec", ["fp32r", "fp64"])
+def test_fullsize_fields_and_sampled_step(prec):
+    from paper_1801_00972_amd.pic import PIC_E, PIC_PHI, PIC_RHO, PIC_RHO_FIXED, Simulation
+    wl = W.full_fp64(prec)
+    print(f"[case] {wl['name']}", flush=True)
+    sim = Simulation(wl)  # the benchmark's configuration (sort every 16 steps)
+    sim.step(3)
+    st = sim.get_state()
+    n0 = 64 * 64 * 256 * 32
+    c = sim.counters()
+    counts, _ = sim.grain_charges()
+    for s in range(2):
+        assert len(st[s]["id"]) == c["n_alive"][s]
+        assert c["n_alive"][s] + sum(c["wall_count"][w][s] for w in range(2)) + counts[:, s].sum() == n0
+    # all mesh quantities of this state
+    fixed = prec == "fp32r"
+    orc = oracle.Oracle(wl)
+    for s in range(2):
+        orc.set_particles(s, st[s]["pos"], st[s]["vel"], st[s]["id"])
+    orc.set_counts(grain_count=st["grain_count"], wall_count=st["wall_count"], step=st["step"])
+    g = sim.fields(0, PIC_PHI | PIC_E | PIC_RHO | (PIC_RHO_FIXED if fixed else 0))
+    o = orc.fields(fixed_point=fixed)
+    if fixed:
+        assert np.array_equal(g["rho_fixed"], o["rho_fixed"])
+    else:
+        assert rel_inf(g["rho"], o["rho"]) <= 1e-12
+    e_phi = rel_inf(g["phi"], o["phi"], floor=abs(orc.rf_voltage(st["step"])))
+    e_E = rel_inf(g["E"], o["E"])
+    print(f"  fields: phi {e_phi:.2e} E {e_E:.2e}", flush=True)
+    assert e_phi <= TOL[prec] and e_E <= TOL[prec]
+    # one step of a sample, moved by the oracle in its own field
+    rng = np.random.default_rng(11)
+    small = oracle.Oracle(wl)
+    for s in range(2):
+        idx = _select(st[s]["pos"], wl["grain_pos"], wl["nz"], rng)
+        small.set_particles(s, st[s]["pos"][idx], st[s]["vel"][idx], st[s]["id"][idx])
+    small.set_counts(grain_count=st["grain_count"], step=st["step"])
+    small.step_in_field(o["E"])
+    sim.step(1)
+    after = sim.get_state()
+    # restrict the GPU state to the sampled ids
+    sub = {}
+    for s in range(2):
+        keep = np.isin(after[s]["id"], small.id[s])
+        sub[s] = {k: after[s][k][keep] for k in ("pos", "vel", "id")}
+    rep = compare_step(wl, sub, small, TOL[prec], TOL[prec], TOL[prec])
+    print(f"  sampled step: n={rep['n']} flips={rep['flips']} dpos={rep['max_dpos']:.2e} "
+          f"dvel={rep['max_dvel']:.2e}", flush=True)
+    assert rep["n"] > 4000 and rep["flips"] <= 3
+    sim.close()
