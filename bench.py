@@ -35,44 +35,83 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(wl, steps, warmup, sort_interval=16):
+def _alive(sim):
+    return sum(sum(sim.counters(r)["n_alive"]) for r in range(len(sim.wls)))
+
+
+def _counter_sum(sim, key):
+    return sum(sum(sim.counters(r)[key]) for r in range(len(sim.wls)))
+
+
+def run_form(wls, steps, warmup, sort_interval=16, autotune=True, label=None):
+    """Times one arithmetic form on one context (a list of replica workloads:
+    one for the single-run forms, several for the batched ensemble)."""
     import torch
 
     from paper_1801_00972_amd.pic import (PIC_PROF_FIELD, PIC_PROF_LISTS, PIC_PROF_PUSH,
                                           PIC_PROF_SORT, Simulation, pic_profile_enable,
                                           pic_profile_read)
 
-    log(f"[bench] init {wl['name']}")
-    sim = Simulation(wl, sort_interval=sort_interval)
+    label = label or wls[0]["name"]
+    log(f"[bench] init {label} ({len(wls)} replica(s))")
+    t_init = time.perf_counter()
+    sim = Simulation(wls, sort_interval=sort_interval)
     torch.cuda.synchronize()
+    log(f"[bench] init took {time.perf_counter() - t_init:.1f} s")
+    tuning, trials = sim.tuning(), []
+    if autotune:
+        log("[bench] autotune (live steps)")
+        tuning, trials = sim.autotune(trial_steps=32)
+        log(f"[bench] settings {tuning} after {len(trials)} trials")
     log(f"[bench] warmup {warmup} steps")
     sim.step(warmup)
     torch.cuda.synchronize()
-    c0 = sim.counters()
+    steps_before = sim.counters(0)["step"]
+    # timed window 1: direct launches with every kernel class bracketed by events
+    n_start = _alive(sim)
+    md0, coll0 = _counter_sum(sim, "md_particles"), _counter_sum(sim, "n_collisions")
+    fall0 = sum(sim.counters(r)["tile_fallback"] for r in range(len(wls)))
     pic_profile_enable(sim.ctx, True)
     torch.cuda.synchronize()
-    log(f"[bench] timing {steps} steps")
+    log(f"[bench] timing {steps} steps (direct launches, kernel events)")
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    c1 = sim.counters()
+    n_end = _alive(sim)
     push_ms, push_n = pic_profile_read(sim.ctx, PIC_PROF_PUSH)
     field_ms, _ = pic_profile_read(sim.ctx, PIC_PROF_FIELD)
     sort_ms, sort_n = pic_profile_read(sim.ctx, PIC_PROF_SORT)
     lists_ms, _ = pic_profile_read(sim.ctx, PIC_PROF_LISTS)
     pic_profile_enable(sim.ctx, False)
-    n_start, n_end = sum(c0["n_alive"]), sum(c1["n_alive"])
+    md1, coll1 = _counter_sum(sim, "md_particles"), _counter_sum(sim, "n_collisions")
+    fall1 = sum(sim.counters(r)["tile_fallback"] for r in range(len(wls)))
+    # timed window 2: the same number of steps as a user runs them (the tuned
+    # settings, no kernel events: replays of the captured step graph unless
+    # the tuner found direct launches faster)
+    log(f"[bench] timing {steps} steps (tuned path)")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    n_end2 = _alive(sim)
+    tuned_ps = 0.5 * (n_end + n_end2) * steps
     particle_steps = 0.5 * (n_start + n_end) * steps
     wall = t1 - t0
-    nn = wl["nx"] * wl["ny"] * (wl["nz"] + 1)
-    prec = wl["precision"]
+    prec = wls[0]["precision"]
+    nn = sum(w["nx"] * w["ny"] * (w["nz"] + 1) for w in wls)
     alg_bytes = particle_steps * 2 * RECORD_BYTES[prec] + steps * nn * NODE_BYTES[prec]
     achieved = alg_bytes / (push_ms * 1e-3) / 1e9 if push_ms > 0 else 0.0
     res = dict(
-        value=particle_steps / wall,
-        ms_per_step=1e3 * wall / steps,
-        n_start=n_start, n_end=n_end,
+        value=tuned_ps / (t3 - t2),
+        ms_per_step=1e3 * (t3 - t2) / steps,
+        n_start=n_start, n_end=n_end2, replicas=len(wls),
+        particles_loaded=sum(2 * w["nx"] * w["ny"] * w["nz"] * w["ppc"] for w in wls),
+        settings=tuning,
+        autotune_trials=[dict(t, ms_per_step=round(ms, 4)) for t, ms in trials],
+        steps_before_timing=steps_before,
+        direct_with_kernel_events=dict(value=particle_steps / wall, ms_per_step=1e3 * wall / steps),
         push_ms_per_launch=push_ms / max(push_n, 1),
         push_launches=push_n,
         field_ms_per_step=field_ms / steps,
@@ -80,13 +119,15 @@ def run_form(wl, steps, warmup, sort_interval=16):
         sort_ms_total=sort_ms, sort_launches=sort_n,
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                      kernel="push_" + prec, bytes_per_launch=alg_bytes / max(push_n, 1)),
-        refine_residual=c1["refine_residual"] if prec == "fp32r" else None,
-        tile_fallback_blocks=c1["tile_fallback"] - c0["tile_fallback"],
-        md_particle_steps=sum(c1["md_particles"]) - sum(c0["md_particles"]),
-        collisions=sum(c1["n_collisions"]) - sum(c0["n_collisions"]),
+                      kernel=("push_batch_f32r" if tuning.get("batch_push") else "push_" + prec),
+                      bytes_per_launch=alg_bytes / max(push_n, 1)),
+        refine_residual=sim.counters(0)["refine_residual"] if prec == "fp32r" else None,
+        tile_fallback_blocks=fall1 - fall0,
+        md_particle_steps=md1 - md0,
+        collisions=coll1 - coll0,
     )
-    log(f"[bench] {prec}: {res['value']:.3e} particle-steps/s, {res['ms_per_step']:.3f} ms/step, "
+    log(f"[bench] {label}: {res['value']:.3e} particle-steps/s, {res['ms_per_step']:.3f} ms/step "
+        f"(direct with events {res['direct_with_kernel_events']['ms_per_step']:.3f} ms/step), "
         f"push {res['push_ms_per_launch']:.3f} ms/launch, {achieved:.0f} GB/s")
     sim.close()
     return res
@@ -134,14 +175,22 @@ def cpu_baseline(wl, steps=2):
                        f"from the oracle's own loading, {t1 - t0:.1f} s")
 
 
+def form_workloads(form, workload):
+    from paper_1801_00972_amd import workloads as W
+    if form == "batched":
+        return W.ensemble() if workload == "full" else W.small_ensemble()
+    return [W.full_fp64(form) if workload == "full" else dict(W.small_fp64(), precision=form)]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", choices=["full", "small"], default="full")
-    ap.add_argument("--forms", default="fp32r,fp64")
+    ap.add_argument("--forms", default="fp32r,fp64,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--sort-interval", type=int, default=16)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -159,10 +208,13 @@ def main():
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {}
     for form in forms:
-        wl = W.full_fp64(form) if args.workload == "full" else dict(W.small_fp64(), precision=form)
-        results[form] = run_form(wl, args.steps, args.warmup, args.sort_interval)
+        wls = form_workloads(form, args.workload)
+        results[form] = run_form(wls, args.steps, args.warmup, args.sort_interval,
+                                 autotune=not args.no_autotune,
+                                 label=f"{form} {wls[0]['name']}" if len(wls) == 1 else
+                                 f"batched ensemble of {len(wls)}")
     head = "fp32r" if "fp32r" in results else forms[0]
-    wl = W.full_fp64(head) if args.workload == "full" else dict(W.small_fp64(), precision=head)
+    wl = form_workloads(head, args.workload)[0]
     R = results[head]
     line = {
         "metric": METRIC,
@@ -175,10 +227,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if head == "fp32r" else "f64",
+        "dtype": "f32" if head in ("fp32r", "batched") else "f64",
         "data": "synthetic",
         "config": {
-            "workload": wl["name"],
+            "workload": wl["name"] if head != "batched" else "ensemble",
             "precision": head,
             "grid": [wl["nx"], wl["ny"], wl["nz"]],
             "ppc_per_species": wl["ppc"],
@@ -186,7 +238,7 @@ def main():
             "grains": int(len(wl["grain_pos"])),
             "pp_cutoff_cells": wl["cutoff"],
             "stated_err": {"fp32r": 1e-5, "fp64": 1e-12},
-            "sort_interval": args.sort_interval,
+            "settings": R["settings"],
         },
         "roofline": R["roofline"],
         "forms": {k: {kk: v for kk, v in r.items() if kk != "roofline"} | {"roofline": r["roofline"]}
@@ -194,6 +246,8 @@ def main():
     }
     if "fp64" in results and "fp32r" in results:
         line["speedup_fp32r_vs_fp64"] = results["fp32r"]["value"] / results["fp64"]["value"]
+    if "fp64" in results and "batched" in results:
+        line["speedup_batched_vs_fp64"] = results["batched"]["value"] / results["fp64"]["value"]
     cb = copy_bandwidth()
     line["copy_bandwidth"] = cb
     line["roofline"]["frac_of_measured_copy"] = round(R["roofline"]["achieved"] / cb["GBs"], 4)

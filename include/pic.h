@@ -191,6 +191,56 @@ int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out);
 int pic_derived(pic_ctx* ctx, int replica, double out[7]);
 
 /*
+ * Launch settings.  None of them changes what a step computes: in the FP32R
+ * form the particle state (as a set of records) and every count after n steps
+ * are bitwise the same under any settings, because each particle's update is
+ * a function of its own record and the field alone and the fixed-point
+ * deposit is order-free; in the FP64 form the deposit's rounding depends on
+ * the particle order.  The array order of the particles depends on them.
+ *   sort_interval  steps between cell sorts (0: never after loading);
+ *                  initially pic_config.sort_interval of replica 0
+ *   tile_margin    cells of drift around a chunk's box staged in LDS by the
+ *                  push (0..4; particles beyond it take the global-memory
+ *                  path); initially 2
+ *   batch_push     1: the pushes of every replica and species run as one
+ *                  persistent launch (all replicas FP32R only); initially 1
+ *                  for an FP32R ensemble, else 0
+ *   batch_blocks   the persistent grid, a multiple of 8 (the XCD count);
+ *                  initially 4 per compute unit
+ *   use_graphs     1: a step is the replay of a captured HIP graph; 0: direct
+ *                  launches; initially 1
+ */
+typedef struct pic_tuning {
+  int32_t sort_interval;
+  int32_t tile_margin;
+  int32_t batch_push;
+  int32_t batch_blocks;
+  int32_t use_graphs;
+} pic_tuning;
+
+/* pic_get_tuning / pic_set_tuning -- read or replace the settings
+ * (synchronises the stream; captured graphs are dropped).  PIC_EINVAL for a
+ * value out of range or batch_push on a context that cannot batch. */
+int pic_get_tuning(pic_ctx* ctx, pic_tuning* out);
+int pic_set_tuning(pic_ctx* ctx, const pic_tuning* t);
+
+/*
+ * pic_autotune -- choose the settings by measurement on live steps: starting
+ * from the current settings, a coordinate search over sort_interval in
+ * {4, 8, 16, 32}, then tile_margin in {1, 2, 3}, then (FP32R contexts)
+ * batch_push off or on with batch_blocks of 2, 3, 4 or 6 per compute unit,
+ * then use_graphs on or off; each trial captures its graphs, takes 2 untimed steps and times trial_steps
+ * steps with HIP events (a multiple of 32 gives every interval the same share
+ * of sorts).  The best settings are applied.  Every step taken is a real
+ * step of the simulation (see the invariance above).  If tried and
+ * ms_per_step are given, the first `capacity` trials are written there;
+ * *n_tried (nullable) receives the number of trials.
+ * Errors: PIC_EINVAL, PIC_ESTATE (kernel timing enabled), PIC_EDEVICE.
+ */
+int pic_autotune(pic_ctx* ctx, int trial_steps, pic_tuning* tried, double* ms_per_step,
+                 int capacity, int* n_tried);
+
+/*
  * Kernel timing.  pic_profile_enable(ctx, 1) clears the record and brackets
  * every following launch of the selected kernel class with HIP events on the
  * context's stream; pic_profile_read synchronises and returns the summed

@@ -45,6 +45,11 @@ __device__ __forceinline__ void normal_pair(uint32_t wa, uint32_t wb, double& n0
   n1 = r * s;
 }
 
+__device__ __forceinline__ double rf_voltage(const RfDrive& d) {
+  const double t = (double)(*d.step) * d.dt;
+  return d.V_dc + d.V_rf * sin(2.0 * kPi * d.f_rf * t);
+}
+
 // wrap an index that is at most one period outside [0, n)
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 

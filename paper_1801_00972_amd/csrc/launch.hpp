@@ -22,6 +22,10 @@ void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTab
                      const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st);
 void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
                       const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st);
+// the push of every (replica, species) of an FP32R ensemble in one persistent launch;
+// start[d] is the first work item (chunk) of descriptor d, start[ndesc] the total
+void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int ndesc, int grid,
+                            hipStream_t st);
 // the listed particles: sub-cycled MD motion (with its collision and deposit), then collisions
 void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
                       const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
@@ -44,14 +48,15 @@ void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L,
 void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const WorkLists& L, int* hist,
                       int* sums, int nx, int ny, int nz, long capacity, hipStream_t st);
 void launch_fill_int(int* a, long n, int v, hipStream_t st);
+void launch_advance_step(uint32_t* step, hipStream_t st);
 
 // mesh
 void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double* b, void* work,
-                      const void* tw_x, const void* tw_y, const void* inv, double* phi, double V,
+                      const void* tw_x, const void* tw_y, const void* inv, double* phi, RfDrive rf,
                       hipStream_t st);
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
-                          const void* tw_y32, const void* inv32, double* phi, double V,
+                          const void* tw_y32, const void* inv32, double* phi, RfDrive rf,
                           int sweeps, double* norms, hipStream_t st);
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
                     hipStream_t st);

@@ -79,9 +79,10 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(FftGeom g, const cplx<T>
                                                         int forward, cplx<T>* __restrict__ work,
                                                         const double* __restrict__ rin,
                                                         double in_scale, double* __restrict__ rout,
-                                                        double out_scale, double V, int nz) {
+                                                        double out_scale, RfDrive rf, int nz) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
+  const double V = OUT == OUT_REAL_LIFT ? rf_voltage(rf) : 0.0;
   C* buf0 = reinterpret_cast<C*>(smem_raw);
   C* buf1 = buf0 + g.L * g.N;
   const int N = g.N, L = g.L;
@@ -167,7 +168,8 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(FftGeom g, const cplx<T>
       work[off] = v;
     } else if (OUT == OUT_REAL_LIFT) {
       // interior plane k = plane + 1 of phi
-      rout[off + g.real_plane_offset] = (double)v.x * out_scale + V * (double)(plane + 1) / (double)nz;
+      rout[off + g.real_plane_offset] =
+          (double)v.x * out_scale + V * (double)(plane + 1) / (double)nz;
     } else {
       rout[off] += (double)v.x * out_scale;
     }
@@ -425,7 +427,8 @@ __global__ __launch_bounds__(1024) void norm_reduce_kernel(const double* __restr
 
 // phi = psi + V k / nz on the interior, 0 and V on the electrodes
 __global__ void lift_kernel(const double* __restrict__ psi, double* __restrict__ phi, int nx,
-                            int ny, int nz, double V) {
+                            int ny, int nz, RfDrive rf) {
+  const double V = rf_voltage(rf);
   const long plane = (long)nx * ny;
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= plane * (nz + 1)) return;
@@ -435,7 +438,8 @@ __global__ void lift_kernel(const double* __restrict__ psi, double* __restrict__
   else phi[n] = psi[n - plane] + V * (double)k / (double)nz;
 }
 
-__global__ void walls_kernel(double* __restrict__ phi, long plane, int nz, double V) {
+__global__ void walls_kernel(double* __restrict__ phi, long plane, int nz, RfDrive rf) {
+  const double V = rf_voltage(rf);
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= plane) return;
   phi[n] = 0.0;
@@ -565,7 +569,7 @@ static FftGeom make_geom(const FftPlanHost& P, bool along_x, int nx, int ny, lon
 template <typename T>
 static void fft_launch(const FftGeom& g, int planes, const void* tw, int forward, int in_mode,
                        int out_mode, void* work, const double* rin, double in_scale, double* rout,
-                       double out_scale, double V, int nz, hipStream_t st) {
+                       double out_scale, RfDrive rf, int nz, hipStream_t st) {
   using C = cplx<T>;
   const int blocks = planes * (g.lines_per_plane / g.L);
   const size_t lds = 2 * sizeof(C) * g.L * g.N;
@@ -573,16 +577,16 @@ static void fft_launch(const FftGeom& g, int planes, const void* tw, int forward
   C* w = (C*)work;
   if (in_mode == IN_REAL && out_mode == OUT_COMPLEX)
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_REAL, OUT_COMPLEX>), dim3(blocks), dim3(256), lds, st,
-                       g, t, forward, w, rin, in_scale, rout, out_scale, V, nz);
+                       g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
   else if (in_mode == IN_COMPLEX && out_mode == OUT_COMPLEX)
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_COMPLEX>), dim3(blocks), dim3(256), lds,
-                       st, g, t, forward, w, rin, in_scale, rout, out_scale, V, nz);
+                       st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
   else if (out_mode == OUT_REAL_LIFT)
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_LIFT>), dim3(blocks), dim3(256), lds,
-                       st, g, t, forward, w, rin, in_scale, rout, out_scale, V, nz);
+                       st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
   else
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_ACCUM>), dim3(blocks), dim3(256),
-                       lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, V, nz);
+                       lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
 }
 
 // one FFT + tridiagonal + inverse FFT solve of A psi = b (T = double or float);
@@ -590,28 +594,28 @@ static void fft_launch(const FftGeom& g, int planes, const void* tw, int forward
 template <typename T>
 static void solve_once(const FftPlanHost& P, int nx, int ny, int nz, const double* b, void* work,
                        const void* tw_x, const void* tw_y, const void* inv, int out_mode,
-                       double* out, double V, hipStream_t st) {
+                       double* out, RfDrive rf, hipStream_t st) {
   const long plane = (long)nx * ny;
   const int K = nz - 1;
   const FftGeom gx = make_geom(P, true, nx, ny, plane);
   const FftGeom gy = make_geom(P, false, nx, ny, plane);
-  fft_launch<T>(gx, K, tw_x, 1, IN_REAL, OUT_COMPLEX, work, b, 1.0, nullptr, 0.0, 0.0, nz, st);
-  fft_launch<T>(gy, K, tw_y, 1, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, 0.0, nz,
+  fft_launch<T>(gx, K, tw_x, 1, IN_REAL, OUT_COMPLEX, work, b, 1.0, nullptr, 0.0, rf, nz, st);
+  fft_launch<T>(gy, K, tw_y, 1, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, rf, nz,
                 st);
   hipLaunchKernelGGL(thomas_kernel<T>, dim3(nb256(plane)), dim3(256), 0, st, (cplx<T>*)work,
                      (const T*)inv, K, plane);
-  fft_launch<T>(gy, K, tw_y, 0, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, 0.0, nz,
+  fft_launch<T>(gy, K, tw_y, 0, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, rf, nz,
                 st);
   fft_launch<T>(gx, K, tw_x, 0, IN_COMPLEX, out_mode, work, nullptr, 0.0, out,
-                1.0 / (double)plane, V, nz, st);
+                1.0 / (double)plane, rf, nz, st);
 }
 
 void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double* b, void* work,
-                      const void* tw_x, const void* tw_y, const void* inv, double* phi, double V,
+                      const void* tw_x, const void* tw_y, const void* inv, double* phi, RfDrive rf,
                       hipStream_t st) {
-  solve_once<double>(P, nx, ny, nz, b, work, tw_x, tw_y, inv, OUT_REAL_LIFT, phi, V, st);
+  solve_once<double>(P, nx, ny, nz, b, work, tw_x, tw_y, inv, OUT_REAL_LIFT, phi, rf, st);
   hipLaunchKernelGGL(walls_kernel, dim3(nb256((long)nx * ny)), dim3(256), 0, st, phi,
-                     (long)nx * ny, nz, V);
+                     (long)nx * ny, nz, rf);
 }
 
 // FP32 solves refined in FP64: psi = 0, r = b; repeat sweeps times
@@ -620,14 +624,14 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
 // 256 interior nodes.
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
-                          const void* tw_y32, const void* inv32, double* phi, double V,
+                          const void* tw_y32, const void* inv32, double* phi, RfDrive rf,
                           int sweeps, double* norms, hipStream_t st) {
   const long plane = (long)nx * ny;
   const long n_int = plane * (nz - 1);
   hipLaunchKernelGGL(zero_f64_kernel, dim3(nb256(n_int)), dim3(256), 0, st, psi, n_int);
   const double* rhs = b;
   for (int it = 0; it < sweeps; ++it) {
-    solve_once<float>(P, nx, ny, nz, rhs, work32, tw_x32, tw_y32, inv32, OUT_REAL_ACCUM, psi, 0.0,
+    solve_once<float>(P, nx, ny, nz, rhs, work32, tw_x32, tw_y32, inv32, OUT_REAL_ACCUM, psi, rf,
                       st);
     hipLaunchKernelGGL(residual_kernel, dim3(nb256(n_int)), dim3(256), 0, st, psi, b, r, nx, ny,
                        nz - 1, norms + 2);
@@ -636,7 +640,7 @@ void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const do
     rhs = r;
   }
   hipLaunchKernelGGL(lift_kernel, dim3(nb256(plane * (nz + 1))), dim3(256), 0, st, psi, phi, nx, ny,
-                     nz, V);
+                     nz, rf);
 }
 
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,

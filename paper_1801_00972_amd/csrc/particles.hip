@@ -36,7 +36,6 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kPPT = 4;                   // consecutive particles per thread
 constexpr int kChunk = kBlock * kPPT;     // particles per block
 constexpr int kTileNodes = 1024;          // LDS field and deposit tile capacity (nodes)
-constexpr int kMargin = 2;                // cells of drift allowed around a chunk's box
 
 // int32 cell index of the FP32R form: i | j << 10 | k << 20 (nx, ny <= 1024, nz < 2048);
 // -1 marks an empty slot
@@ -270,11 +269,11 @@ __device__ int md_move(const ET* __restrict__ E, const MdTables& md, const Grain
 // the neutral drawn from the 300 K reservoir.
 __device__ __forceinline__ void collide(const SpeciesStep& S, uint32_t id, double v[3], bool& coll,
                                         bool& capv) {
-  const uint4 r = philox4x32_10(id, S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+  const uint4 r = philox4x32_10(id, *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
   if ((uint64_t)r.x >= S.T_null) return;
   double vn[3] = {0.0, 0.0, 0.0};
   if (S.sp == 1) {
-    const uint4 q = philox4x32_10(id, S.step, kNeutral, 1u, S.key0, S.key1);
+    const uint4 q = philox4x32_10(id, *S.step, kNeutral, 1u, S.key0, S.key1);
     double n0, n1, n2, n3;
     normal_pair(q.x, q.y, n0, n1);
     normal_pair(q.z, q.w, n2, n3);
@@ -433,7 +432,7 @@ __device__ __forceinline__ int push_one_f64(const SpeciesStep& S, const double E
 // The arrays are kept sorted by 4x4x4 cell tiles, so the 1024 particles of a
 // chunk (the slots one push block streams) sit in a small box of cells.  The
 // box is taken exactly right after each sort; the push block stages the field
-// on that box plus kMargin cells in LDS and accumulates its deposit there.
+// on that box plus a margin of cells in LDS and accumulates its deposit there.
 // Particles that have drifted outside it (fast electrons) gather and deposit
 // through global memory instead.  Along the periodic x,y the box is the raw
 // range of the index or the range shifted by n/2, whichever is shorter.
@@ -486,14 +485,15 @@ __device__ __forceinline__ void block_minmax(int v[10], int (*s_red)[10]) {
 }
 
 // the chunk box plus m cells, in nodes; shrinks the margin until it fits in LDS
-__device__ __forceinline__ Tile make_tile(const int32_t* __restrict__ box, int nx, int ny, int nz) {
+__device__ __forceinline__ Tile make_tile(const int32_t* __restrict__ box, int nx, int ny, int nz,
+                                          int margin) {
   Tile t;
   t.on = false;
   t.x0 = t.y0 = t.k0 = 0;
   t.tx = t.ty = t.tz = 0;
   const int i0 = box[0], ni = box[1], j0 = box[2], nj = box[3], k0 = box[4], nk = box[5];
   if (ni <= 0) return t;
-  for (int m = kMargin; m >= 0; --m) {
+  for (int m = margin; m >= 0; --m) {
     int x0 = i0 - m, tx = ni + 2 * m + 1;
     if (ni + 2 * m >= nx) {
       x0 = 0;
@@ -657,18 +657,29 @@ __device__ __forceinline__ void tally_store(const unsigned* s_t, unsigned long l
 // cell first), whose occupied nodes are then added to rho.  Particles starting
 // inside an MD cube are left untouched and listed for the sub-cycled kernel;
 // candidates are listed for the collision kernel.
+// LDS of one push block (FP32R)
+struct PushSmemF32 {
+  float4 E[kTileNodes];
+  long long rho[kTileNodes];
+  unsigned tally[TL_N];
+  int nmd, ncoll, nout, mdbase;
+  int32_t md[kChunk];
+};
+
 template <bool kMove>
-__global__ __launch_bounds__(kBlock) void push_f32r_kernel(PartF32R P,
-                                                           const float4* __restrict__ E,
-                                                           long long* __restrict__ rho, MdTables md,
-                                                           SpeciesStep S, WorkLists L) {
-  __shared__ float4 s_E[kTileNodes];
-  __shared__ long long s_rho[kTileNodes];
-  __shared__ unsigned s_tally[TL_N];
-  __shared__ int s_nmd, s_ncoll, s_nout, s_mdbase;
-  __shared__ int32_t s_md[kChunk];
+__device__ __forceinline__ void push_chunk_f32r(const PartF32R& P, const float4* __restrict__ E,
+                                                long long* __restrict__ rho, const MdTables& md,
+                                                const SpeciesStep& S, const WorkLists& L, long chunk,
+                                                PushSmemF32& sm) {
+  float4* s_E = sm.E;
+  long long* s_rho = sm.rho;
+  unsigned* s_tally = sm.tally;
+  int& s_nmd = sm.nmd;
+  int& s_ncoll = sm.ncoll;
+  int& s_nout = sm.nout;
+  int& s_mdbase = sm.mdbase;
+  int32_t* s_md = sm.md;
   const int n = L.cnt[0];
-  const long chunk = xcd_chunk(blockIdx.x, gridDim.x);
   const long chunk0 = chunk * kChunk;
   if (chunk0 >= n) {
     if (kMove && threadIdx.x == 0) {
@@ -677,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void push_f32r_kernel(PartF32R P,
     }
     return;
   }
-  const Tile tile = make_tile(L.box + 6 * chunk, S.nx, S.ny, S.nz);
+  const Tile tile = make_tile(L.box + 6 * chunk, S.nx, S.ny, S.nz, S.margin);
   const int vol = tile.on ? tile.tx * tile.ty * tile.tz : 0;
   const float rtx = 1.0f / (float)max(tile.tx, 1), rtxy = 1.0f / (float)max(tile.tx * tile.ty, 1);
   for (int t = threadIdx.x; t < vol; t += kBlock) {
@@ -743,7 +754,7 @@ __global__ __launch_bounds__(kBlock) void push_f32r_kernel(PartF32R P,
         st[q] = push_one_f32(S, ec, o[q], v[q], ci, cj, ck);
         if (st[q] == ST_ALIVE) {
           cell[q] = pack_cell(ci, cj, ck);
-          const uint4 r = philox4x32_10(id[q], S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+          const uint4 r = philox4x32_10(id[q], *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
           cand[q] = (uint64_t)r.x < S.T_null;
         } else {
           cell[q] = -1;
@@ -832,6 +843,40 @@ __global__ __launch_bounds__(kBlock) void push_f32r_kernel(PartF32R P,
   }
 }
 
+template <bool kMove>
+__global__ __launch_bounds__(kBlock) void push_f32r_kernel(PartF32R P,
+                                                           const float4* __restrict__ E,
+                                                           long long* __restrict__ rho, MdTables md,
+                                                           SpeciesStep S, WorkLists L) {
+  __shared__ PushSmemF32 sm;
+  push_chunk_f32r<kMove>(P, E, rho, md, S, L, xcd_chunk(blockIdx.x, gridDim.x), sm);
+}
+
+// ---------------------------------------------------------------- push, ensemble
+// One persistent launch over the chunks of every (replica, species) of an
+// ensemble: work item i belongs to descriptor d with start[d] <= i < start[d+1]
+// (starts are multiples of 8, so the XCD remapping stays a permutation per
+// descriptor); blocks stride over the items.
+__global__ __launch_bounds__(kBlock) void push_batch_f32r_kernel(const PushDescF32* __restrict__ descs,
+                                                                 const int32_t* __restrict__ start,
+                                                                 int ndesc) {
+  __shared__ PushSmemF32 sm;
+  const int total = start[ndesc];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int lo = 0, hi = ndesc;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (start[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    const int local = item - start[lo];
+    const PushDescF32& d = descs[lo];
+    push_chunk_f32r<true>(d.P, d.E, d.rho, d.md, d.S, d.L, xcd_chunk(local, start[lo + 1] - start[lo]),
+                          sm);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- push, FP64
 // The same kernel on FP64 records: positions in cell units, velocities in m/s;
 // an empty slot has z = -1.  The field tile holds (Ex,Ey),(Ez,0) pairs.
@@ -854,7 +899,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(PartF64 P, const doubl
     }
     return;
   }
-  const Tile tile = make_tile(L.box + 6 * chunk, S.nx, S.ny, S.nz);
+  const Tile tile = make_tile(L.box + 6 * chunk, S.nx, S.ny, S.nz, S.margin);
   const int vol = tile.on ? tile.tx * tile.ty * tile.tz : 0;
   const float rtx = 1.0f / (float)max(tile.tx, 1), rtxy = 1.0f / (float)max(tile.tx * tile.ty, 1);
   for (int t = threadIdx.x; t < vol; t += kBlock) {
@@ -936,7 +981,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(PartF64 P, const doubl
         st[q] = push_one_f64(S, Ep, x[q], v[q]);
         if (st[q] == ST_ALIVE) {
           cell[q] = pack_cell((int)floor(x[q][0]), (int)floor(x[q][1]), (int)floor(x[q][2]));
-          const uint4 r = philox4x32_10(id[q], S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+          const uint4 r = philox4x32_10(id[q], *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
           cand[q] = (uint64_t)r.x < S.T_null;
         } else {
           x[q][2] = -1.0;
@@ -1228,7 +1273,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(PartF32R P, const floa
       bool coll = false, capv = false;
       if (do_mcc) {
         const uint32_t id = P.id[p];
-        const uint4 r = philox4x32_10(id, S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+        const uint4 r = philox4x32_10(id, *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
         if ((uint64_t)r.x < S.T_null) {
           double vd[3] = {v[0], v[1], v[2]};
           collide(S, id, vd, coll, capv);
@@ -1290,7 +1335,7 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(PartF64 P, const double
       bool coll = false, capv = false;
       if (do_mcc) {
         const uint32_t id = P.id[p];
-        const uint4 r = philox4x32_10(id, S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+        const uint4 r = philox4x32_10(id, *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
         if ((uint64_t)r.x < S.T_null) collide(S, id, v, coll, capv);
       }
       t_coll += coll;
@@ -1556,10 +1601,19 @@ __global__ void fill_int_kernel(int* a, long n, int v) {
   if (i < n) a[i] = v;
 }
 
+// k -> k + 1 at the end of a step
+__global__ void advance_step_kernel(uint32_t* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1u;
+}
+
 // ---------------------------------------------------------------- launchers
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 int push_chunks(long capacity) { return (nblk(capacity, kChunk) + 7) / 8 * 8; }
+
+void launch_advance_step(uint32_t* step, hipStream_t st) {
+  hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, step);
+}
 
 void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
                      const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st) {
@@ -1573,6 +1627,12 @@ void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const M
   if (capacity <= 0) return;
   hipLaunchKernelGGL(push_f32r_kernel<true>, dim3(push_chunks(capacity)), dim3(kBlock), 0, st, P,
                      (const float4*)E, rho, md, S, L);
+}
+
+void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int ndesc, int grid,
+                            hipStream_t st) {
+  if (ndesc <= 0 || grid <= 0) return;
+  hipLaunchKernelGGL(push_batch_f32r_kernel, dim3(grid), dim3(kBlock), 0, st, descs, start, ndesc);
 }
 
 constexpr int kMdBlocks = 2048;

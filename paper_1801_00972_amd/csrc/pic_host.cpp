@@ -74,8 +74,9 @@ struct Replica {
   // sort
   int* d_hist = nullptr;
   int* d_sums = nullptr;
-  uint32_t step = 0;
-  int since_sort = 0;
+  uint32_t step = 0;       // host mirror of *d_step
+  uint32_t* d_step = nullptr;
+  int margin = 2;          // tile margin of the push (cells)
   DevMem mem;
 };
 
@@ -91,8 +92,32 @@ struct pic_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[4];
+  // launch settings (pic_set_tuning)
+  pic_tuning tune{};
+  int since_sort = 0;
+  // captured steps, by phase (see step_all)
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph[8] = {};
+  // batched push: descriptors of every (replica, species) for each (particle
+  // buffer, rho buffer) phase, and the first chunk of each descriptor
+  bool batchable = false;
+  int ndesc = 0;
+  PushDescF32* d_desc = nullptr;
+  int32_t* d_start = nullptr;
+  int n_cu = 256;
+  void drop_graphs() {
+    for (hipGraphExec_t& g : graph)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
   ~pic_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    drop_graphs();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    if (d_desc) (void)hipFree(d_desc);
+    if (d_start) (void)hipFree(d_start);
   }
 };
 
@@ -154,10 +179,6 @@ int lines_per_block(int N, int lines) {
   return L;
 }
 
-double rf_voltage(const pic_config& c, uint32_t k) {
-  const double t = (double)k * c.dt;
-  return c.V_dc + c.V_rf * std::sin(2.0 * kPi * c.f_rf * t);
-}
 
 int periodic_delta(int a, int b, int n) {
   int d = ((a - b) % n + n) % n;
@@ -333,6 +354,7 @@ SpeciesStep species_step(const Replica& R, int sp) {
   S.nxy = (int)R.nxy;
   S.sp = sp;
   S.md_sub = c.md_subcycles;
+  S.margin = R.margin;
   S.dx = c.dx;
   const double qm = R.q[sp] / R.m[sp];
   const double h = c.dt / (double)c.md_subcycles;
@@ -350,7 +372,7 @@ SpeciesStep species_step(const Replica& R, int sp) {
   S.mass_ratio_n = R.m[1] / (R.m[0] + R.m[1]);
   S.key0 = (uint32_t)(c.seed & 0xffffffffu);
   S.key1 = (uint32_t)(c.seed >> 32);
-  S.step = R.step;
+  S.step = R.d_step;
   S.Qp = R.Qp;
   S.sign = sp == 0 ? -1.0 : 1.0;
   S.isign = sp == 0 ? -1 : 1;
@@ -383,6 +405,8 @@ int alloc_particles(pic_ctx* ctx, Replica& R) {
       }
     }
   TRY(dalloc(ctx, R, &R.d_cnt, 16));
+  TRY(dalloc(ctx, R, &R.d_step, 1));
+  HIPCHK(ctx, hipMemsetAsync(R.d_step, 0, 4, ctx->stream));
   R.nchunks = push_chunks(R.cap[0]);
   for (int sp = 0; sp < 2; ++sp) {
     WorkLists& L = R.lists[sp];
@@ -439,14 +463,14 @@ int deposit_current(pic_ctx* ctx, Replica& R) {
 int solve_fields(pic_ctx* ctx, Replica& R) {
   hipStream_t st = ctx->stream;
   const pic_config& c = R.cfg;
-  const double V = rf_voltage(c, R.step);
+  const RfDrive rf{c.V_dc, c.V_rf, c.f_rf, c.dt, R.d_step};
   const double vol = c.dx * c.dx * c.dx;
   if (R.prec == PIC_FP64) {
     const double scale = -c.dx * c.dx / kEps0 * (R.we / vol);
     launch_rhs_f64((const double*)R.rho[R.rho_cur], scale, R.b, R.nx, R.ny, R.nz, st);
     launch_grain_rhs(R.d_gc, R.md.gpos, c.n_grains, R.nx, R.ny, R.nz, R.we, R.d_Q, R.b, scale, 0,
                      R.Qp, st);
-    launch_solve_f64(R.fft, R.nx, R.ny, R.nz, R.b, R.work, R.tw_x, R.tw_y, R.inv, R.phi, V, st);
+    launch_solve_f64(R.fft, R.nx, R.ny, R.nz, R.b, R.work, R.tw_x, R.tw_y, R.inv, R.phi, rf, st);
     launch_efield_f64(R.phi, (double*)R.E, R.nx, R.ny, R.nz, c.dx, st);
   } else {
     const double scale = -c.dx * c.dx / kEps0 * (kCharge / 4294967296.0 / vol);
@@ -454,7 +478,7 @@ int solve_fields(pic_ctx* ctx, Replica& R) {
     launch_grain_rhs(R.d_gc, R.md.gpos, c.n_grains, R.nx, R.ny, R.nz, R.we, R.d_Q, R.b, scale, 1,
                      R.Qp, st);
     launch_solve_refined(R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y, R.inv,
-                         R.phi, V, c.max_refine, R.norms, st);
+                         R.phi, rf, c.max_refine, R.norms, st);
     launch_efield_f32(R.phi, (float*)R.E, R.nx, R.ny, R.nz, c.dx, st);
   }
   CHECK_LAUNCH(ctx);
@@ -488,7 +512,24 @@ int read_tallies(pic_ctx* ctx, Replica& R, int sp, unsigned long long out[TL_N])
   return PIC_OK;
 }
 
-int step_replica(pic_ctx* ctx, Replica& R) {
+// the sort of both species into the other buffer, at the end of a step
+int enqueue_sort(pic_ctx* ctx, Replica& R) {
+  const int o = 1 - R.cur;
+  for (int sp = 0; sp < 2; ++sp) {
+    if (R.prec == PIC_FP64)
+      launch_sort_f64(R.p64[sp][R.cur], R.p64[sp][o], R.lists[sp], R.d_hist, R.d_sums, R.nx, R.ny,
+                      R.nz, R.cap[sp], ctx->stream);
+    else
+      launch_sort_f32r(R.p32[sp][R.cur], R.p32[sp][o], R.lists[sp], R.d_hist, R.d_sums, R.nx,
+                       R.ny, R.nz, R.cap[sp], ctx->stream);
+  }
+  CHECK_LAUNCH(ctx);
+  return PIC_OK;
+}
+
+// launches one step of a replica on ctx->stream from the host state at the
+// start of the step (buffer phases); advance_host then moves the host mirrors
+int enqueue_step(pic_ctx* ctx, Replica& R, bool sort_now) {
   hipStream_t st = ctx->stream;
   hipEvent_t f0 = prof_event(ctx);
   TRY(solve_fields(ctx, R));
@@ -522,15 +563,201 @@ int step_replica(pic_ctx* ctx, Replica& R) {
       prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
   }
+  launch_advance_step(R.d_step, st);
   CHECK_LAUNCH(ctx);
-  R.rho_cur = rnx;
-  R.step += 1;
-  if (R.cfg.sort_interval > 0 && ++R.since_sort >= R.cfg.sort_interval) {
-    R.since_sort = 0;
+  if (sort_now) {
     hipEvent_t s0 = prof_event(ctx);
-    TRY(resort(ctx, R));
+    TRY(enqueue_sort(ctx, R));
     prof_pair(ctx, PIC_PROF_SORT, s0, prof_event(ctx));
   }
+  return PIC_OK;
+}
+
+// one step of every replica of an FP32R context with the push of all
+// replicas and species in one persistent launch (replicas in the same phase)
+int enqueue_batch(pic_ctx* ctx, bool sort_now) {
+  hipStream_t st = ctx->stream;
+  const Replica& R0 = *ctx->reps[0];
+  hipEvent_t f0 = prof_event(ctx);
+  for (auto& R : ctx->reps) {
+    TRY(solve_fields(ctx, *R));
+    launch_zero_i64((long long*)R->rho[1 - R->rho_cur], R->nn, st);
+  }
+  CHECK_LAUNCH(ctx);
+  prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
+  const int phase = R0.cur | (R0.rho_cur << 1);
+  hipEvent_t a = prof_event(ctx);
+  launch_push_batch_f32r(ctx->d_desc + (size_t)phase * ctx->ndesc, ctx->d_start, ctx->ndesc,
+                         ctx->tune.batch_blocks, st);
+  CHECK_LAUNCH(ctx);
+  hipEvent_t b = prof_event(ctx);
+  for (auto& R : ctx->reps) {
+    const int rnx = 1 - R->rho_cur;
+    for (int sp = 0; sp < 2; ++sp)
+      launch_lists_f32r(R->p32[sp][R->cur], (const float*)R->E, (long long*)R->rho[rnx], R->md,
+                        species_step(*R, sp), R->d_gc, R->lists[sp], 1, R->cap[sp], st);
+    launch_advance_step(R->d_step, st);
+  }
+  CHECK_LAUNCH(ctx);
+  prof_pair(ctx, PIC_PROF_PUSH, a, b);
+  prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
+  if (sort_now) {
+    hipEvent_t s0 = prof_event(ctx);
+    for (auto& R : ctx->reps) TRY(enqueue_sort(ctx, *R));
+    prof_pair(ctx, PIC_PROF_SORT, s0, prof_event(ctx));
+  }
+  return PIC_OK;
+}
+
+bool replicas_aligned(const pic_ctx* ctx) {
+  const Replica& R0 = *ctx->reps[0];
+  for (auto& R : ctx->reps)
+    if (R->cur != R0.cur || R->rho_cur != R0.rho_cur) return false;
+  return true;
+}
+
+// one step of every replica, launched on ctx->stream
+int enqueue_all(pic_ctx* ctx, bool sort_now) {
+  if (ctx->batchable && ctx->tune.batch_push && replicas_aligned(ctx))
+    return enqueue_batch(ctx, sort_now);
+  for (auto& R : ctx->reps) TRY(enqueue_step(ctx, *R, sort_now));
+  return PIC_OK;
+}
+
+// (re)builds the descriptors of the batched push: for phase (cur, rho_cur),
+// descriptor 2 r + sp pushes species sp of replica r from buffer cur and
+// deposits into rho[1 - rho_cur]
+int build_batch(pic_ctx* ctx) {
+  ctx->batchable = false;
+  for (auto& R : ctx->reps)
+    if (R->prec != PIC_FP32R) return PIC_OK;
+  const int nd = 2 * (int)ctx->reps.size();
+  std::vector<PushDescF32> h((size_t)4 * nd);
+  std::vector<int32_t> start(nd + 1, 0);
+  for (int phase = 0; phase < 4; ++phase)
+    for (int r = 0; r < (int)ctx->reps.size(); ++r) {
+      const Replica& R = *ctx->reps[r];
+      for (int sp = 0; sp < 2; ++sp) {
+        PushDescF32& d = h[(size_t)phase * nd + 2 * r + sp];
+        d.P = R.p32[sp][phase & 1];
+        d.E = (const float4*)R.E;
+        d.rho = (long long*)R.rho[1 - (phase >> 1)];
+        d.md = R.md;
+        d.S = species_step(R, sp);
+        d.L = R.lists[sp];
+        if (phase == 0) {
+          const long total = (long)start[2 * r + sp] + push_chunks(R.cap[sp]);
+          if (total > 0x7fffffffL) return PIC_OK;  // beyond the int32 item index
+          start[2 * r + sp + 1] = (int32_t)total;
+        }
+      }
+    }
+  if (!ctx->d_desc) {
+    HIPCHK(ctx, hipMalloc(&ctx->d_desc, h.size() * sizeof(PushDescF32)));
+    HIPCHK(ctx, hipMalloc(&ctx->d_start, start.size() * sizeof(int32_t)));
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(ctx->d_desc, h.data(), h.size() * sizeof(PushDescF32),
+                        hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(ctx->d_start, start.data(), start.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice));
+  ctx->ndesc = nd;
+  ctx->batchable = true;
+  return PIC_OK;
+}
+
+void advance_host(Replica& R, bool sort_now) {
+  R.rho_cur = 1 - R.rho_cur;
+  R.step += 1;
+  if (sort_now) R.cur = 1 - R.cur;
+}
+
+// captures the step of phase `key` (particle buffer, rho buffer, sort) into
+// ctx->graph[key] without running it: the host phases of the replicas are set
+// to the key for the capture and restored after
+int capture_step(pic_ctx* ctx, int key) {
+  if (ctx->graph[key]) return PIC_OK;
+  if (!ctx->capture_stream)
+    HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+  std::vector<std::pair<int, int>> saved;
+  for (auto& R : ctx->reps) {
+    saved.push_back({R->cur, R->rho_cur});
+    R->cur = key & 1;
+    R->rho_cur = (key >> 1) & 1;
+  }
+  hipStream_t user = ctx->stream;
+  ctx->stream = ctx->capture_stream;
+  hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+  int rc = PIC_OK;
+  hipGraph_t g = nullptr;
+  if (e == hipSuccess) {
+    rc = enqueue_all(ctx, (key >> 2) & 1);
+    e = hipStreamEndCapture(ctx->stream, &g);
+  }
+  ctx->stream = user;
+  for (size_t r = 0; r < saved.size(); ++r) {
+    ctx->reps[r]->cur = saved[r].first;
+    ctx->reps[r]->rho_cur = saved[r].second;
+  }
+  if (rc != PIC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(ctx, PIC_EDEVICE, "graph capture failed");
+  const hipError_t ei = hipGraphInstantiate(&ctx->graph[key], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    ctx->graph[key] = nullptr;
+    return fail(ctx, PIC_EDEVICE, "graph instantiation failed");
+  }
+  return PIC_OK;
+}
+
+// one step of every replica: direct launches when profiling (the events must
+// bracket single kernels) or when the replicas are in different buffer
+// phases, otherwise the replay of the captured graph of the whole step for
+// the current (particle buffer, rho buffer, sort) phase on the caller's stream
+int step_all(pic_ctx* ctx) {
+  const int interval = ctx->tune.sort_interval;
+  const bool sort_now = interval > 0 && ctx->since_sort + 1 >= interval;
+  const Replica& R0 = *ctx->reps[0];
+  if (ctx->prof || !ctx->tune.use_graphs || !replicas_aligned(ctx)) {
+    TRY(enqueue_all(ctx, sort_now));
+  } else {
+    const int key = R0.cur | (R0.rho_cur << 1) | ((sort_now ? 1 : 0) << 2);
+    if (!ctx->graph[key]) {
+      // the capture stream is not ordered after the caller's stream: the
+      // graph's first launch must not overtake work queued there
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      TRY(capture_step(ctx, key));
+    }
+    HIPCHK(ctx, hipGraphLaunch(ctx->graph[key], ctx->stream));
+  }
+  for (auto& R : ctx->reps) advance_host(*R, sort_now);
+  ctx->since_sort = sort_now ? 0 : ctx->since_sort + 1;
+  return PIC_OK;
+}
+
+int check_tuning(const pic_ctx* ctx, const pic_tuning& t, std::string& why) {
+  if (t.sort_interval < 0 || t.sort_interval > 1000000) why = "sort_interval out of range";
+  else if (t.tile_margin < 0 || t.tile_margin > 4) why = "tile_margin must be in 0..4";
+  else if (t.batch_push != 0 && t.batch_push != 1) why = "batch_push must be 0 or 1";
+  else if (t.batch_push && !ctx->batchable) why = "batch_push needs an all-FP32R context";
+  else if (t.batch_blocks < 8 || t.batch_blocks % 8 || t.batch_blocks > 65536)
+    why = "batch_blocks must be a multiple of 8 in 8..65536";
+  else if (t.use_graphs != 0 && t.use_graphs != 1) why = "use_graphs must be 0 or 1";
+  return why.empty() ? PIC_OK : PIC_EINVAL;
+}
+
+int apply_tuning(pic_ctx* ctx, const pic_tuning& t) {
+  std::string why;
+  if (check_tuning(ctx, t, why) != PIC_OK) return fail(ctx, PIC_EINVAL, why);
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const bool margin_changed = t.tile_margin != ctx->tune.tile_margin;
+  ctx->tune = t;
+  for (auto& R : ctx->reps) R->margin = t.tile_margin;
+  if (margin_changed && ctx->batchable) TRY(build_batch(ctx));
+  ctx->drop_graphs();
   return PIC_OK;
 }
 
@@ -553,7 +780,8 @@ int unit_fields(pic_ctx* ctx, Replica& R) {
   for (int g = 0; g < ng; ++g) {
     launch_zero_f64(R.b, R.n_int, st);
     launch_unit_rhs(R.md.gpos, g, R.nx, R.ny, R.nz, scale, R.b, st);
-    launch_solve_f64(R.fft, R.nx, R.ny, R.nz, R.b, work, tw_x, tw_y, inv, R.phi, 0.0, st);
+    launch_solve_f64(R.fft, R.nx, R.ny, R.nz, R.b, work, tw_x, tw_y, inv, R.phi,
+                     RfDrive{0.0, 0.0, 0.0, 0.0, R.d_step}, st);
     launch_efield_f64(R.phi, E, R.nx, R.ny, R.nz, c.dx, st);
     launch_extract_cube(E, R.md.gcell, g, c.pp_cutoff_cells, R.nx, R.ny,
                         const_cast<double*>(R.md.U), st);
@@ -696,6 +924,21 @@ int pic_init(const pic_config* cfgs, int n_replicas, void* hip_stream, pic_ctx**
     }
     ctx->reps.push_back(std::move(R));
   }
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      ncu > 0)
+    ctx->n_cu = ncu;
+  if (build_batch(ctx.get()) != PIC_OK) {
+    g_init_error = ctx->err;
+    return PIC_EDEVICE;
+  }
+  pic_tuning& t = ctx->tune;
+  t.sort_interval = ctx->reps[0]->cfg.sort_interval;
+  t.tile_margin = 2;
+  t.batch_push = ctx->batchable && n_replicas > 1 ? 1 : 0;
+  t.batch_blocks = (4 * ctx->n_cu + 7) / 8 * 8;
+  t.use_graphs = 1;
   *out = ctx.release();
   return PIC_OK;
 }
@@ -704,8 +947,7 @@ int pic_step(pic_ctx* ctx, int n_steps) {
   if (!ctx) return PIC_EINVAL;
   if (ctx->sticky) return ctx->sticky;
   if (n_steps < 0) return fail(ctx, PIC_EINVAL, "n_steps < 0");
-  for (int s = 0; s < n_steps; ++s)
-    for (auto& R : ctx->reps) TRY(step_replica(ctx, *R));
+  for (int s = 0; s < n_steps; ++s) TRY(step_all(ctx));
   return PIC_OK;
 }
 
@@ -876,13 +1118,15 @@ int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
       if (!ok) return fail(ctx, PIC_ENUMERIC, "particle outside the box or not finite");
     }
   }
-  R->cur = 0;
-  R->rho_cur = 0;
+  // upload into the spare buffer; the sort below brings the particles back to
+  // the current one, so every replica keeps its buffer phase
+  const int up = 1 - R->cur;
+  R->cur = up;
   for (int sp = 0; sp < 2; ++sp) {
     const long cnt = v->n[sp];
     if (cnt == 0) continue;
     if (R->prec == PIC_FP64) {
-      const PartF64& P = R->p64[sp][0];
+      const PartF64& P = R->p64[sp][up];
       std::vector<double> a(cnt);
       double* dst[6] = {P.x, P.y, P.z, P.vx, P.vy, P.vz};
       for (int q = 0; q < 6; ++q) {
@@ -892,7 +1136,7 @@ int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
       }
       HIPCHK(ctx, hipMemcpy(P.id, v->id[sp], cnt * 4, hipMemcpyHostToDevice));
     } else {
-      const PartF32R& P = R->p32[sp][0];
+      const PartF32R& P = R->p32[sp][up];
       std::vector<int32_t> cell(cnt);
       std::vector<float> a(6 * cnt);
       for (long i = 0; i < cnt; ++i) {
@@ -936,7 +1180,7 @@ int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
     HIPCHK(ctx, hipMemcpy(R->d_gc, gc.data(), 16 * ng, hipMemcpyHostToDevice));
   }
   R->step = v->step;
-  R->since_sort = 0;
+  HIPCHK(ctx, hipMemcpy(R->d_step, &v->step, 4, hipMemcpyHostToDevice));
   TRY(resort(ctx, *R));
   TRY(deposit_current(ctx, *R));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -994,6 +1238,108 @@ int pic_profile_read(pic_ctx* ctx, int cls, double* total_ms, int64_t* launches)
   *total_ms = tot;
   *launches = (int64_t)ctx->ev_pairs[cls].size();
   return PIC_OK;
+}
+
+int pic_get_tuning(pic_ctx* ctx, pic_tuning* out) {
+  if (!ctx || !out) return PIC_EINVAL;
+  *out = ctx->tune;
+  return PIC_OK;
+}
+
+int pic_set_tuning(pic_ctx* ctx, const pic_tuning* t) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  if (!t) return fail(ctx, PIC_EINVAL, "tuning is NULL");
+  return apply_tuning(ctx, *t);
+}
+
+int pic_autotune(pic_ctx* ctx, int trial_steps, pic_tuning* tried, double* ms_per_step,
+                 int capacity, int* n_tried) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  if (trial_steps < 1) return fail(ctx, PIC_EINVAL, "trial_steps < 1");
+  if (capacity < 0 || (capacity > 0 && (!tried || !ms_per_step)))
+    return fail(ctx, PIC_EINVAL, "bad trial record buffers");
+  if (ctx->prof) return fail(ctx, PIC_ESTATE, "autotune while kernel timing is enabled");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ctx, PIC_EDEVICE, "hipEventCreate failed");
+  }
+  int count = 0;
+  // GPU time of trial_steps steps under t, after every graph of t is captured
+  // and two untimed steps
+  auto measure = [&](const pic_tuning& t, double* ms) -> int {
+    TRY(apply_tuning(ctx, t));
+    if (t.use_graphs && replicas_aligned(ctx))
+      for (int key = 0; key < 8; ++key)
+        if (t.sort_interval > 0 || !(key & 4)) TRY(capture_step(ctx, key));
+    for (int k = 0; k < 2; ++k) TRY(step_all(ctx));
+    HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+    for (int k = 0; k < trial_steps; ++k) TRY(step_all(ctx));
+    HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&f, e0, e1));
+    *ms = (double)f / trial_steps;
+    if (count < capacity) {
+      tried[count] = t;
+      ms_per_step[count] = *ms;
+    }
+    ++count;
+    return PIC_OK;
+  };
+  pic_tuning best = ctx->tune;
+  double best_ms = 0.0;
+  int rc = measure(best, &best_ms);
+  // coordinate search: sort interval, tile margin, the batched push, graphs
+  std::vector<pic_tuning> cands;
+  for (int axis = 0; axis < 4 && rc == PIC_OK; ++axis) {
+    cands.clear();
+    if (axis == 0) {
+      for (int si : {4, 8, 16, 32}) {
+        pic_tuning t = best;
+        t.sort_interval = si;
+        cands.push_back(t);
+      }
+    } else if (axis == 1) {
+      for (int m : {1, 2, 3}) {
+        pic_tuning t = best;
+        t.tile_margin = m;
+        cands.push_back(t);
+      }
+    } else if (axis == 2 && ctx->batchable) {
+      pic_tuning t = best;
+      t.batch_push = 0;
+      cands.push_back(t);
+      for (int k : {2, 3, 4, 6}) {
+        t = best;
+        t.batch_push = 1;
+        t.batch_blocks = (k * ctx->n_cu + 7) / 8 * 8;
+        cands.push_back(t);
+      }
+    } else if (axis == 3) {
+      pic_tuning t = best;
+      t.use_graphs = 1 - best.use_graphs;
+      cands.push_back(t);
+    }
+    for (const pic_tuning& t : cands) {
+      if (std::memcmp(&t, &best, sizeof(t)) == 0) continue;
+      double ms = 0.0;
+      rc = measure(t, &ms);
+      if (rc != PIC_OK) break;
+      if (ms < best_ms) {
+        best = t;
+        best_ms = ms;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (n_tried) *n_tried = count;
+  if (rc != PIC_OK) return rc;
+  return apply_tuning(ctx, best);
 }
 
 int pic_derived(pic_ctx* ctx, int replica, double out[7]) {

@@ -30,6 +30,13 @@ struct PartF32R {
   uint32_t* id;
 };
 
+// phi on the rf electrode at t_k = k dt: V_dc + V_rf sin(2 pi f_rf t_k), with k
+// read from device memory so a captured step needs no new arguments
+struct RfDrive {
+  double V_dc, V_rf, f_rf, dt;
+  const uint32_t* step;
+};
+
 // per-species work lists and counters of one step (device)
 // coll and out are segmented by chunk (the 1024 consecutive slots one push
 // block streams): chunk c owns entries [1024 c, 1024 c + count[c]).
@@ -69,6 +76,7 @@ struct SpeciesStep {
   int nx, ny, nz, nxy;
   int sp;                  // 0 electron, 1 ion
   int md_sub;
+  int margin;              // cells of drift allowed around a chunk's box (LDS tiles)
   double dx;
   double qm_dt, dt_dx;     // (q/m) dt, dt/dx
   double qm_h, h_dx;       // the same for the MD sub-step h = dt / md_sub
@@ -80,11 +88,22 @@ struct SpeciesStep {
   double vth_gas;
   double mass_ratio_e;     // m_e / (m_e + M)
   double mass_ratio_n;     // M / (m_e + M)
-  uint32_t key0, key1, step;
+  uint32_t key0, key1;
+  const uint32_t* step;    // device: the step index k of the replica
   // deposit
   int64_t Qp;              // macro charge, 2^-32 e
   double sign;             // -1 electrons, +1 ions
   long long isign;
+};
+
+// one (replica, species) of a batched push launch
+struct PushDescF32 {
+  PartF32R P;
+  const float4* E;
+  long long* rho;
+  MdTables md;
+  SpeciesStep S;
+  WorkLists L;
 };
 
 }  // namespace pic

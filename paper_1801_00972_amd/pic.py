@@ -8,6 +8,7 @@ PyTorch supplies the HIP stream and, optionally, device output tensors.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
@@ -21,7 +22,8 @@ PIC_PHI, PIC_E, PIC_RHO, PIC_RHO_FIXED = 1, 2, 4, 8
 
 SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destroy",
            "pic_last_error", "pic_get_state", "pic_set_state", "pic_get_counters", "pic_derived",
-           "pic_profile_enable", "pic_profile_read")
+           "pic_profile_enable", "pic_profile_read", "pic_get_tuning", "pic_set_tuning",
+           "pic_autotune")
 PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT, PIC_PROF_LISTS = 0, 1, 2, 3
 
 
@@ -69,6 +71,13 @@ class pic_counters(C.Structure):
     ]
 
 
+class pic_tuning(C.Structure):
+    _fields_ = [("sort_interval", C.c_int32), ("tile_margin", C.c_int32),
+                ("batch_push", C.c_int32), ("batch_blocks", C.c_int32), ("use_graphs", C.c_int32)]
+
+
+TUNING_KEYS = tuple(f[0] for f in pic_tuning._fields_)
+
 _lib = None
 
 
@@ -95,9 +104,13 @@ def lib():
         L.pic_derived.argtypes = [P, C.c_int, C.POINTER(C.c_double)]
         L.pic_profile_enable.argtypes = [P, C.c_int]
         L.pic_profile_read.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.pic_get_tuning.argtypes = [P, C.POINTER(pic_tuning)]
+        L.pic_set_tuning.argtypes = [P, C.POINTER(pic_tuning)]
+        L.pic_autotune.argtypes = [P, C.c_int, C.POINTER(pic_tuning), C.POINTER(C.c_double), C.c_int,
+                                   C.POINTER(C.c_int)]
         for name in ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_get_state",
                      "pic_set_state", "pic_get_counters", "pic_derived", "pic_profile_enable",
-                     "pic_profile_read"):
+                     "pic_profile_read", "pic_get_tuning", "pic_set_tuning", "pic_autotune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -257,6 +270,33 @@ def pic_profile_read(ctx, kernel_class):
     return ms.value, n.value
 
 
+def pic_get_tuning(ctx):
+    t = pic_tuning()
+    _check(lib().pic_get_tuning(ctx, C.byref(t)), ctx)
+    return {k: int(getattr(t, k)) for k in TUNING_KEYS}
+
+
+def pic_set_tuning(ctx, tuning: dict):
+    t = pic_tuning()
+    cur = pic_get_tuning(ctx)
+    unknown = set(tuning) - set(TUNING_KEYS)
+    if unknown:
+        raise ValueError(f"unknown tuning keys {sorted(unknown)}")
+    for k in TUNING_KEYS:
+        setattr(t, k, int(tuning.get(k, cur[k])))
+    _check(lib().pic_set_tuning(ctx, C.byref(t)), ctx)
+
+
+def pic_autotune(ctx, trial_steps=32, capacity=64):
+    """Runs the search; returns the list of (settings, ms per step) tried."""
+    tried = (pic_tuning * capacity)()
+    ms = (C.c_double * capacity)()
+    n = C.c_int()
+    _check(lib().pic_autotune(ctx, int(trial_steps), tried, ms, capacity, C.byref(n)), ctx)
+    return [({k: int(getattr(tried[i], k)) for k in TUNING_KEYS}, float(ms[i]))
+            for i in range(min(n.value, capacity))]
+
+
 # ---------------------------------------------------------------- convenience
 class Simulation:
     """One context over one or more replicas (workload dicts)."""
@@ -303,6 +343,44 @@ class Simulation:
 
     def derived(self, replica=0):
         return pic_derived(self.ctx, replica)
+
+    def tuning(self):
+        return pic_get_tuning(self.ctx)
+
+    def set_tuning(self, **kw):
+        pic_set_tuning(self.ctx, kw)
+
+    def tuning_key(self):
+        """What the best settings depend on: the shapes of the replicas, the
+        arithmetic form and the device."""
+        import torch
+        dev = torch.cuda.get_device_properties(0).gcnArchName if torch.cuda.is_available() else "none"
+        shapes = [(w["nx"], w["ny"], w["nz"], w["ppc"], len(w.get("grain_pos", [])), w.get("cutoff", 3),
+                   w.get("precision", "fp64")) for w in self.wls]
+        return json.dumps([dev, shapes])
+
+    def autotune(self, trial_steps=32, cache=None):
+        """Chooses the launch settings by timing live steps (pic_autotune) and
+        applies them.  With `cache` (a JSON file path) a previous result for
+        the same key is applied without searching, and a new one is stored.
+        Returns (settings, trials); trials is empty for a cache hit."""
+        key = self.tuning_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_tuning(**table[key])
+                return self.tuning(), []
+        trials = pic_autotune(self.ctx, trial_steps)
+        best = self.tuning()
+        if cache:
+            table[key] = best
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return best, trials
 
     def close(self):
         if self.ctx:

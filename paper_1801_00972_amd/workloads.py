@@ -126,6 +126,19 @@ def ensemble(n_replicas: int = 16, seed: int = 4) -> list:
     return out
 
 
+def small_ensemble() -> list:
+    """Three uneven small FP32-refined replicas (a quick form of the ensemble)."""
+    out = []
+    for r, (nx, ny, nz, ppc, g) in enumerate(((16, 16, 32, 8, [[8.0, 8.0, 16.0]]),
+                                              (24, 24, 48, 6, [[12.0, 12.0, 30.5], [6.2, 17.9, 28.0]]),
+                                              (32, 16, 40, 4, [[10.5, 8.5, 20.0]]))):
+        wl = dict(_BASE, nx=nx, ny=ny, nz=nz, ppc=ppc, steps=500, cutoff=2, seed=r,
+                  grain_pos=np.asarray(g, np.float64), precision="fp32r")
+        wl["name"] = f"replica{r}_{nx}x{ny}x{nz}_ppc{ppc}"
+        out.append(wl)
+    return out
+
+
 def tiny(nx=8, ny=8, nz=12, ppc=2, grains=None, **kw) -> dict:
     """Small boxes for parity cases that still span several tiles."""
     wl = dict(_BASE, nx=nx, ny=ny, nz=nz, ppc=ppc, steps=10,
