@@ -43,7 +43,7 @@ def _counter_sum(sim, key):
     return sum(sum(sim.counters(r)[key]) for r in range(len(sim.wls)))
 
 
-def run_form(wls, steps, warmup, sort_interval=16, autotune=True, label=None):
+def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
     """Times one arithmetic form on one context (a list of replica workloads:
     one for the single-run forms, several for the batched ensemble)."""
     import torch
@@ -61,7 +61,7 @@ def run_form(wls, steps, warmup, sort_interval=16, autotune=True, label=None):
     tuning, trials = sim.tuning(), []
     if autotune:
         log("[bench] autotune (live steps)")
-        tuning, trials = sim.autotune(trial_steps=32)
+        tuning, trials = sim.autotune(trial_steps=48)
         log(f"[bench] settings {tuning} after {len(trials)} trials")
     log(f"[bench] warmup {warmup} steps")
     sim.step(warmup)
@@ -191,7 +191,7 @@ def main():
     ap.add_argument("--forms", default="fp32r,fp64,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--sort-interval", type=int, default=16)
+    ap.add_argument("--sort-interval", type=int, default=8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

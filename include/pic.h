@@ -80,7 +80,7 @@ typedef struct pic_config {
   int32_t md_subcycles;
   int32_t precision;           /* PIC_FP64 or PIC_FP32R */
   int32_t max_refine;          /* FP32R: residual-refinement sweeps per solve (>= 1) */
-  int32_t sort_interval;       /* steps between full cell sorts of the particles (>= 1) */
+  int32_t sort_interval;       /* steps between re-binnings of the electrons (0: never; see pic_tuning) */
   double dx, dt;
   double n0;
   double Te_eV, Ti_eV;
@@ -119,7 +119,7 @@ typedef struct pic_counters {
   int32_t refine_sweeps;      /* FP32R: sweeps in the last solve */
   double refine_residual;     /* FP32R: ||b - A phi|| / ||b|| after the last solve */
   int64_t numeric_bad;        /* particles removed for a non-finite position (0 for valid input) */
-  int64_t tile_fallback;      /* push blocks whose deposit tile exceeded LDS (global atomics) */
+  int64_t tile_fallback;      /* particle-steps outside their tile's LDS window (global-memory path) */
 } pic_counters;
 
 /*
@@ -197,22 +197,28 @@ int pic_derived(pic_ctx* ctx, int replica, double out[7]);
  * a function of its own record and the field alone and the fixed-point
  * deposit is order-free; in the FP64 form the deposit's rounding depends on
  * the particle order.  The array order of the particles depends on them.
- *   sort_interval  steps between cell sorts (0: never after loading);
- *                  initially pic_config.sort_interval of replica 0
- *   tile_margin    cells of drift around a chunk's box staged in LDS by the
- *                  push (0..4; particles beyond it take the global-memory
- *                  path); initially 2
- *   batch_push     1: the pushes of every replica and species run as one
- *                  persistent launch (all replicas FP32R only); initially 1
- *                  for an FP32R ensemble, else 0
- *   batch_blocks   the persistent grid, a multiple of 8 (the XCD count);
- *                  initially 4 per compute unit
- *   use_graphs     1: a step is the replay of a captured HIP graph; 0: direct
- *                  launches; initially 1
+ * The particles are kept binned by tiles of 4x4x4 cells; the push stages the
+ * field of each tile plus a margin of cells (its window) in LDS.
+ *   sort_interval      steps between re-binnings of the electrons (0: never
+ *                      after loading); initially pic_config.sort_interval of
+ *                      replica 0
+ *   ion_sort_interval  the same for the ions; initially 64
+ *   tile_margin        the electrons' window margin in cells (0..3; particles
+ *                      beyond it take the global-memory path); initially 2
+ *   ion_tile_margin    the same for the ions; initially 1
+ *   batch_push         1: the pushes of every replica and species run as one
+ *                      persistent launch (all replicas FP32R only); initially
+ *                      1 for an FP32R ensemble, else 0
+ *   batch_blocks       the persistent grid, a multiple of 8 (the XCD count);
+ *                      initially 4 per compute unit
+ *   use_graphs         1: a step is the replay of a captured HIP graph; 0:
+ *                      direct launches; initially 1
  */
 typedef struct pic_tuning {
   int32_t sort_interval;
+  int32_t ion_sort_interval;
   int32_t tile_margin;
+  int32_t ion_tile_margin;
   int32_t batch_push;
   int32_t batch_blocks;
   int32_t use_graphs;
@@ -227,14 +233,17 @@ int pic_set_tuning(pic_ctx* ctx, const pic_tuning* t);
 /*
  * pic_autotune -- choose the settings by measurement on live steps: starting
  * from the current settings, a coordinate search over sort_interval in
- * {4, 8, 16, 32}, then tile_margin in {1, 2, 3}, then (FP32R contexts)
+ * {4, 6, 8, 12, 16}, then tile_margin in {1, 2, 3}, then (FP32R contexts)
  * batch_push off or on with batch_blocks of 2, 3, 4 or 6 per compute unit,
- * then use_graphs on or off; each trial captures its graphs, takes 2 untimed steps and times trial_steps
- * steps with HIP events (a multiple of 32 gives every interval the same share
- * of sorts).  The best settings are applied.  Every step taken is a real
- * step of the simulation (see the invariance above).  If tried and
- * ms_per_step are given, the first `capacity` trials are written there;
- * *n_tried (nullable) receives the number of trials.
+ * then use_graphs on or off (the ion settings are kept).  Each trial takes 2
+ * untimed steps, then trial_steps steps, each bracketed by HIP events after
+ * any graph capture (a multiple of 48 gives every interval the same share of
+ * re-binnings).  As the plasma evolves during the search, each candidate is
+ * timed between two timings of the incumbent and wins only against their
+ * mean.  The best settings are applied.  Every step taken is a real step of
+ * the simulation (see the invariance above).  If tried and ms_per_step are
+ * given, the first `capacity` trials are written there (incumbent re-timings
+ * included); *n_tried (nullable) receives the number of trials.
  * Errors: PIC_EINVAL, PIC_ESTATE (kernel timing enabled), PIC_EDEVICE.
  */
 int pic_autotune(pic_ctx* ctx, int trial_steps, pic_tuning* tried, double* ms_per_step,

@@ -13,40 +13,42 @@ struct FftPlanHost {
   int L_x, L_y;
 };
 
-// particles: arrays updated in place, WorkLists.cnt[0] slots in use, work
-// lists and tallies segmented by 1024-slot chunk
-int push_chunks(long capacity);             // chunks (push blocks) for a capacity
-long sort_keys(int nx, int ny, int nz);     // size of the sort histogram
+// particles: arrays binned by 4x4x4-cell tile and updated in place (see
+// WorkLists); one push block per tile, the grid padded to a multiple of 8
+int tile_grid(int nx, int ny, int nz);      // tiles rounded up to a multiple of 8
+long sort_keys(int nx, int ny, int nz);     // size of the sort histogram (cells in tile order)
 // the streaming kernel of one species (gather, push, walls, candidate test, deposit)
 void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
-                     const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st);
+                     const SpeciesStep& S, const WorkLists& L, hipStream_t st);
 void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
-                      const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st);
+                      const SpeciesStep& S, const WorkLists& L, hipStream_t st);
 // the push of every (replica, species) of an FP32R ensemble in one persistent launch;
-// start[d] is the first work item (chunk) of descriptor d, start[ndesc] the total
+// start[d] is the first work item (tile) of descriptor d, start[ndesc] the total
 void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int ndesc, int grid,
                             hipStream_t st);
-// the listed particles: sub-cycled MD motion (with its collision and deposit), then collisions
+// the listed particles: outliers, sub-cycled MD motion (with its collision and
+// deposit), then the collisions of the candidates
 void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
                       const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
-                      long capacity, hipStream_t st);
+                      hipStream_t st);
 void launch_lists_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
                        const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
-                       long capacity, hipStream_t st);
+                       hipStream_t st);
 void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
                      uint32_t k1, double vth, hipStream_t st);
 void launch_init_f32r(const PartF32R& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
                       uint32_t k1, double vth, hipStream_t st);
-// deposit of the current positions through the chunk tiles (arrays freshly sorted)
+// deposit of the current positions through the tile windows (arrays freshly sorted)
 void launch_deposit_f64(const PartF64& P, double* rho, const MdTables& md, const SpeciesStep& S,
-                        const WorkLists& L, long capacity, hipStream_t st);
+                        const WorkLists& L, hipStream_t st);
 void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
-                         const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st);
-// counting sort into dst (dropping empty slots), then the chunk boxes of dst
+                         const SpeciesStep& S, const WorkLists& L, hipStream_t st);
+// counting sort of the slots in use into dst (dropping empty slots, padding
+// every tile to a multiple of 4); capacity bounds the slots in use
 void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L, int* hist,
-                     int* sums, int nx, int ny, int nz, long capacity, hipStream_t st);
+                     int* sums, long capacity, hipStream_t st);
 void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const WorkLists& L, int* hist,
-                      int* sums, int nx, int ny, int nz, long capacity, hipStream_t st);
+                      int* sums, long capacity, hipStream_t st);
 void launch_fill_int(int* a, long n, int v, hipStream_t st);
 void launch_advance_step(uint32_t* step, hipStream_t st);
 

@@ -34,8 +34,7 @@ __device__ __forceinline__ int z_status(const double x[3], const SpeciesStep& S)
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kPPT = 4;                   // consecutive particles per thread
-constexpr int kChunk = kBlock * kPPT;     // particles per block
-constexpr int kTileNodes = 1024;          // LDS field and deposit tile capacity (nodes)
+constexpr int kChunk = kBlock * kPPT;     // slots one pass of a push block streams
 
 // int32 cell index of the FP32R form: i | j << 10 | k << 20 (nx, ny <= 1024, nz < 2048);
 // -1 marks an empty slot
@@ -45,8 +44,8 @@ __device__ __forceinline__ int cell_k(int c) { return c >> 20; }
 __device__ __forceinline__ int pack_cell(int i, int j, int k) { return i | (j << 10) | (k << 20); }
 
 // Blocks are dealt round-robin to the 8 XCDs; give each XCD one contiguous
-// run of chunks so neighbouring chunks share that XCD's L2.  nb is a multiple
-// of 8, so this is a permutation of [0, nb).
+// run of tiles (a slab in z) so neighbouring tiles share that XCD's L2.  nb is
+// a multiple of 8, so this is a permutation of [0, nb).
 __device__ __forceinline__ long xcd_chunk(long b, long nb) { return (b % 8) * (nb / 8) + b / 8; }
 
 // ---------------------------------------------------------------- field loads
@@ -428,71 +427,29 @@ __device__ __forceinline__ int push_one_f64(const SpeciesStep& S, const double E
   return z_status(x, S);
 }
 
-// ---------------------------------------------------------------- chunk tiles
-// The arrays are kept sorted by 4x4x4 cell tiles, so the 1024 particles of a
-// chunk (the slots one push block streams) sit in a small box of cells.  The
-// box is taken exactly right after each sort; the push block stages the field
-// on that box plus a margin of cells in LDS and accumulates its deposit there.
-// Particles that have drifted outside it (fast electrons) gather and deposit
-// through global memory instead.  Along the periodic x,y the box is the raw
-// range of the index or the range shifted by n/2, whichever is shorter.
+// ---------------------------------------------------------------- tile windows
+// The arrays are binned by tiles of 4x4x4 cells.  One push block takes one
+// tile: it stages the field on the tile's cells plus a margin of cells (the
+// window) in LDS and accumulates its deposit there.  Particles that have
+// drifted beyond the window since the last sort (fast electrons) are left to
+// the outlier kernel, which gathers and deposits through global memory.
 struct Tile {
   int x0, y0, k0;  // first node (x0, y0 may be negative: periodic)
   int tx, ty, tz;  // nodes per edge
   bool on;
 };
 
-__device__ __forceinline__ void box_update(int v[10], int i, int j, int k, int nx, int ny) {
-  const int si = i + (nx >> 1) >= nx ? i + (nx >> 1) - nx : i + (nx >> 1);
-  const int sj = j + (ny >> 1) >= ny ? j + (ny >> 1) - ny : j + (ny >> 1);
-  v[0] = min(v[0], i);
-  v[1] = max(v[1], i);
-  v[2] = min(v[2], si);
-  v[3] = max(v[3], si);
-  v[4] = min(v[4], j);
-  v[5] = max(v[5], j);
-  v[6] = min(v[6], sj);
-  v[7] = max(v[7], sj);
-  v[8] = min(v[8], k);
-  v[9] = max(v[9], k);
-}
-
-// cells [c0, c0 + nc) along a periodic axis covering the raw or shifted range
-__device__ __forceinline__ void axis_cells(int lo, int hi, int slo, int shi, int n, int& c0,
-                                           int& nc) {
-  if (hi - lo <= shi - slo) {
-    c0 = lo;
-    nc = hi - lo + 1;
-  } else {
-    c0 = slo - (n >> 1);
-    nc = shi - slo + 1;
-  }
-}
-
-// block-wide min/max of the 10 box values (every thread gets the result)
-__device__ __forceinline__ void block_minmax(int v[10], int (*s_red)[10]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int t = 0; t < 10; ++t) v[t] = (t & 1) ? wave_max(v[t]) : wave_min(v[t]);
-  if (lane == 0)
-    for (int t = 0; t < 10; ++t) s_red[wave][t] = v[t];
-  __syncthreads();
-  for (int t = 0; t < 10; ++t) {
-    int r = s_red[0][t];
-    for (int w = 1; w < kWaves; ++w) r = (t & 1) ? max(r, s_red[w][t]) : min(r, s_red[w][t]);
-    v[t] = r;
-  }
-}
-
-// the chunk box plus m cells, in nodes; shrinks the margin until it fits in LDS
-__device__ __forceinline__ Tile make_tile(const int32_t* __restrict__ box, int nx, int ny, int nz,
-                                          int margin) {
-  Tile t;
-  t.on = false;
-  t.x0 = t.y0 = t.k0 = 0;
-  t.tx = t.ty = t.tz = 0;
-  const int i0 = box[0], ni = box[1], j0 = box[2], nj = box[3], k0 = box[4], nk = box[5];
-  if (ni <= 0) return t;
+// the window of tile t: its cells plus m cells on each side, in nodes; the
+// margin shrinks until the window fits `cap` nodes
+__device__ __forceinline__ Tile make_tile(int t, const WorkLists& L, int nx, int ny, int nz,
+                                          int margin, int cap) {
+  Tile w;
+  w.on = false;
+  w.x0 = w.y0 = w.k0 = 0;
+  w.tx = w.ty = w.tz = 0;
+  const int ti = t % L.ntx, tj = (t / L.ntx) % L.nty, tk = t / (L.ntx * L.nty);
+  const int i0 = 4 * ti, ni = min(4, nx - i0), j0 = 4 * tj, nj = min(4, ny - j0);
+  const int k0 = 4 * tk, nk = min(4, nz - k0);
   for (int m = margin; m >= 0; --m) {
     int x0 = i0 - m, tx = ni + 2 * m + 1;
     if (ni + 2 * m >= nx) {
@@ -506,18 +463,18 @@ __device__ __forceinline__ Tile make_tile(const int32_t* __restrict__ box, int n
     }
     const int klo = max(0, k0 - m), khi = min(nz - 1, k0 + nk - 1 + m);
     const int tz = khi - klo + 2;
-    if (tx * ty * tz <= kTileNodes) {
-      t.x0 = x0;
-      t.y0 = y0;
-      t.k0 = klo;
-      t.tx = tx;
-      t.ty = ty;
-      t.tz = tz;
-      t.on = true;
-      return t;
+    if (tx * ty * tz <= cap) {
+      w.x0 = x0;
+      w.y0 = y0;
+      w.k0 = klo;
+      w.tx = tx;
+      w.ty = ty;
+      w.tz = tz;
+      w.on = true;
+      return w;
     }
   }
-  return t;
+  return w;
 }
 
 // tile-local index of the cell's lower corner node, or -1 if the cell's 8
@@ -623,7 +580,7 @@ __device__ __forceinline__ void deposit_global_f64(double* __restrict__ rho, con
   corner_add<double>(none, -1, nullptr, rho, S, i, j, k, w);
 }
 
-// append to the chunk's list segment: one LDS atomic per wave
+// append to a list segment: one LDS atomic per wave
 __device__ __forceinline__ void chunk_append(bool flag, int32_t* seg, int* s_n, int value) {
   const unsigned long long m = __ballot(flag);
   if (!m) return;
@@ -636,7 +593,7 @@ __device__ __forceinline__ void chunk_append(bool flag, int32_t* seg, int* s_n, 
 }
 
 // block-level tallies: wave sums into LDS; thread 0 then adds them to the
-// chunk's own accumulators (each chunk has one writer per kernel: no atomics)
+// tile's own accumulators (each tile has one writer per kernel: no atomics)
 __device__ __forceinline__ void tally_add(unsigned* s_t, int which, int v) {
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(&s_t[which], (unsigned)v);
@@ -647,199 +604,220 @@ __device__ __forceinline__ void tally_store(const unsigned* s_t, unsigned long l
     if (s_t[w]) tally[w] += s_t[w];
 }
 
+// The MD particles of one pass of a push block are staged in LDS and appended
+// to the dense MD list with one reservation.  Every thread calls this after a
+// barrier that follows the pass's last append.
+constexpr int kMdStage = kBlock * kPPT;
+__device__ __forceinline__ void md_flush(int32_t* s_md, int* s_nmd, int* s_mdbase,
+                                         const WorkLists& L) {
+  const int nmd = *s_nmd;
+  __syncthreads();  // every thread has read the count before it changes
+  if (nmd == 0) return;
+  if (threadIdx.x == 0) {
+    *s_mdbase = atomicAdd(&L.cnt[2], nmd);
+    *s_nmd = 0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nmd; t += kBlock) L.md[*s_mdbase + t] = s_md[t];
+  __syncthreads();  // the stage is free again
+}
+
 // ---------------------------------------------------------------- push, FP32R
-// One block streams the kChunk consecutive slots of its chunk, four per thread
-// with 16-byte loads and stores, and updates them in place: gather from the
-// LDS field tile (the 8 node fields are reused while consecutive particles
-// share a cell), kick Eq. (2), drift Eq. (1) in cell + offset form, periodic
-// wrap, electrode absorption, collision candidate test; the new positions are
-// deposited into the LDS tile (per-thread sums over a run of particles in one
-// cell first), whose occupied nodes are then added to rho.  Particles starting
-// inside an MD cube are left untouched and listed for the sub-cycled kernel;
-// candidates are listed for the collision kernel.
+// One block streams the slots of its tile, 1024 per pass, four consecutive
+// slots per thread with 16-byte loads and stores, and updates them in place:
+// gather from the LDS field window (the 8 node fields are reused while
+// consecutive particles share a cell), kick Eq. (2), drift Eq. (1) in cell +
+// offset form, periodic wrap, electrode absorption, collision candidate test;
+// the new positions are deposited into the LDS window (per-thread sums over a
+// run of particles in one cell first), whose occupied nodes are then added to
+// rho.  Particles starting inside an MD cube are left untouched and listed for
+// the sub-cycled kernel; candidates are listed for the collision kernel.
+constexpr int kWinF32 = 1331;  // window capacity (nodes): a tile with a 3-cell margin
+
 // LDS of one push block (FP32R)
 struct PushSmemF32 {
-  float4 E[kTileNodes];
-  long long rho[kTileNodes];
+  float4 E[kWinF32];
+  long long rho[kWinF32];
   unsigned tally[TL_N];
   int nmd, ncoll, nout, mdbase;
-  int32_t md[kChunk];
+  int32_t md[kMdStage];
 };
 
 template <bool kMove>
-__device__ __forceinline__ void push_chunk_f32r(const PartF32R& P, const float4* __restrict__ E,
-                                                long long* __restrict__ rho, const MdTables& md,
-                                                const SpeciesStep& S, const WorkLists& L, long chunk,
-                                                PushSmemF32& sm) {
-  float4* s_E = sm.E;
-  long long* s_rho = sm.rho;
-  unsigned* s_tally = sm.tally;
-  int& s_nmd = sm.nmd;
-  int& s_ncoll = sm.ncoll;
-  int& s_nout = sm.nout;
-  int& s_mdbase = sm.mdbase;
-  int32_t* s_md = sm.md;
-  const int n = L.cnt[0];
-  const long chunk0 = chunk * kChunk;
-  if (chunk0 >= n) {
+__device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* __restrict__ E,
+                                               long long* __restrict__ rho, const MdTables& md,
+                                               const SpeciesStep& S, const WorkLists& L, int tidx,
+                                               PushSmemF32& sm) {
+  const int beg = L.tstart[tidx], end = L.tstart[tidx + 1];
+  if (beg >= end) {
     if (kMove && threadIdx.x == 0) {
-      L.coll_cnt[chunk] = 0;
-      L.out_cnt[chunk] = 0;
+      L.coll_cnt[tidx] = 0;
+      L.out_cnt[tidx] = 0;
     }
     return;
   }
-  const Tile tile = make_tile(L.box + 6 * chunk, S.nx, S.ny, S.nz, S.margin);
+  const Tile tile = make_tile(tidx, L, S.nx, S.ny, S.nz, S.margin, kWinF32);
   const int vol = tile.on ? tile.tx * tile.ty * tile.tz : 0;
   const float rtx = 1.0f / (float)max(tile.tx, 1), rtxy = 1.0f / (float)max(tile.tx * tile.ty, 1);
   for (int t = threadIdx.x; t < vol; t += kBlock) {
-    if (kMove) s_E[t] = E[tile_node(tile, t, rtx, rtxy, S.nx, S.ny, S.nxy)];
-    s_rho[t] = 0;
+    if (kMove) sm.E[t] = E[tile_node(tile, t, rtx, rtxy, S.nx, S.ny, S.nxy)];
+    sm.rho[t] = 0;
   }
-  if (threadIdx.x < TL_N) s_tally[threadIdx.x] = 0;
+  if (threadIdx.x < TL_N) sm.tally[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
-    s_nmd = 0;
-    s_ncoll = 0;
-    s_nout = 0;
+    sm.nmd = 0;
+    sm.ncoll = 0;
+    sm.nout = 0;
   }
-  const long g4 = chunk0 / kPPT + threadIdx.x;
-  const long p0 = g4 * kPPT;
-  const int4 c4 = reinterpret_cast<const int4*>(P.cell)[g4];
-  const float4 X4 = reinterpret_cast<const float4*>(P.ox)[g4];
-  const float4 Y4 = reinterpret_cast<const float4*>(P.oy)[g4];
-  const float4 Z4 = reinterpret_cast<const float4*>(P.oz)[g4];
-  const float4 U4 = reinterpret_cast<const float4*>(P.vx)[g4];
-  const float4 V4 = reinterpret_cast<const float4*>(P.vy)[g4];
-  const float4 W4 = reinterpret_cast<const float4*>(P.vz)[g4];
-  const uint4 I4 = reinterpret_cast<const uint4*>(P.id)[g4];
   __syncthreads();
-  int cell[kPPT] = {c4.x, c4.y, c4.z, c4.w};
-  float o[kPPT][3] = {{X4.x, Y4.x, Z4.x}, {X4.y, Y4.y, Z4.y}, {X4.z, Y4.z, Z4.z}, {X4.w, Y4.w, Z4.w}};
-  float v[kPPT][3] = {{U4.x, V4.x, W4.x}, {U4.y, V4.y, W4.y}, {U4.z, V4.z, W4.z}, {U4.w, V4.w, W4.w}};
-  const uint32_t id[kPPT] = {I4.x, I4.y, I4.z, I4.w};
-  int st[kPPT];
-  bool cand[kPPT];
-  int cached = -1;
-  float ec[8][3];
-  int n_out = 0;
-#pragma unroll
-  for (int q = 0; q < kPPT; ++q) {
-    st[q] = ST_NONE;
-    cand[q] = false;
-    if (!kMove) {
-      if (p0 + q < n && cell[q] >= 0) st[q] = ST_ALIVE;
-      continue;
+  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0, n_out = 0;
+  for (int base = beg; base < end; base += kChunk) {
+    // tile ranges are multiples of 4 slots: a thread's four slots are all in
+    // the tile or all beyond it
+    const int p0 = base + kPPT * (int)threadIdx.x;
+    const bool have = p0 < end;
+    const long g4 = p0 / kPPT;
+    int4 c4 = make_int4(-1, -1, -1, -1);
+    float4 X4{}, Y4{}, Z4{}, U4{}, V4{}, W4{};
+    uint4 I4{};
+    if (have) {
+      c4 = reinterpret_cast<const int4*>(P.cell)[g4];
+      X4 = reinterpret_cast<const float4*>(P.ox)[g4];
+      Y4 = reinterpret_cast<const float4*>(P.oy)[g4];
+      Z4 = reinterpret_cast<const float4*>(P.oz)[g4];
+      U4 = reinterpret_cast<const float4*>(P.vx)[g4];
+      V4 = reinterpret_cast<const float4*>(P.vy)[g4];
+      W4 = reinterpret_cast<const float4*>(P.vz)[g4];
+      I4 = reinterpret_cast<const uint4*>(P.id)[g4];
     }
-    if (p0 + q < n && cell[q] >= 0) {
+    int cell[kPPT] = {c4.x, c4.y, c4.z, c4.w};
+    float o[kPPT][3] = {{X4.x, Y4.x, Z4.x}, {X4.y, Y4.y, Z4.y}, {X4.z, Y4.z, Z4.z}, {X4.w, Y4.w, Z4.w}};
+    float v[kPPT][3] = {{U4.x, V4.x, W4.x}, {U4.y, V4.y, W4.y}, {U4.z, V4.z, W4.z}, {U4.w, V4.w, W4.w}};
+    const uint32_t id[kPPT] = {I4.x, I4.y, I4.z, I4.w};
+    int st[kPPT];
+    bool cand[kPPT];
+    int cached = -1;
+    float ec[8][3];
+#pragma unroll
+    for (int q = 0; q < kPPT; ++q) {
+      st[q] = ST_NONE;
+      cand[q] = false;
+      if (cell[q] < 0) continue;
+      if (!kMove) {
+        st[q] = ST_ALIVE;
+        continue;
+      }
       int ci = cell_i(cell[q]), cj = cell_j(cell[q]), ck = cell_k(cell[q]);
       if (md_lookup(md, S.nx, S.ny, ci, cj, ck) != 0u) {
         st[q] = ST_MD;
-      } else {
-        const int lb = cell[q] == cached ? 0 : tile_cell(tile, ci, cj, ck, S.nx, S.ny);
-        if (lb < 0) {
-          // outside the chunk's tile: left for the outlier kernel (no global
-          // gather here, so no wave waits on a dependent memory round trip)
-          st[q] = ST_OUT;
-          continue;
-        }
-        if (cell[q] != cached) {
-          cached = cell[q];
+        continue;
+      }
+      const int lb = cell[q] == cached ? 0 : tile_cell(tile, ci, cj, ck, S.nx, S.ny);
+      if (lb < 0) {
+        // outside the window: left for the outlier kernel (no global gather
+        // here, so no wave waits on a dependent memory round trip)
+        st[q] = ST_OUT;
+        continue;
+      }
+      if (cell[q] != cached) {
+        cached = cell[q];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const float4 e = s_E[lb + (t & 1) + tile.tx * (((t >> 1) & 1) + tile.ty * (t >> 2))];
-            ec[t][0] = e.x;
-            ec[t][1] = e.y;
-            ec[t][2] = e.z;
-          }
-        }
-        st[q] = push_one_f32(S, ec, o[q], v[q], ci, cj, ck);
-        if (st[q] == ST_ALIVE) {
-          cell[q] = pack_cell(ci, cj, ck);
-          const uint4 r = philox4x32_10(id[q], *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
-          cand[q] = (uint64_t)r.x < S.T_null;
-        } else {
-          cell[q] = -1;
+        for (int t = 0; t < 8; ++t) {
+          const float4 e = sm.E[lb + (t & 1) + tile.tx * (((t >> 1) & 1) + tile.ty * (t >> 2))];
+          ec[t][0] = e.x;
+          ec[t][1] = e.y;
+          ec[t][2] = e.z;
         }
       }
+      st[q] = push_one_f32(S, ec, o[q], v[q], ci, cj, ck);
+      if (st[q] == ST_ALIVE) {
+        cell[q] = pack_cell(ci, cj, ck);
+        const uint4 r = philox4x32_10(id[q], *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+        cand[q] = (uint64_t)r.x < S.T_null;
+      } else {
+        cell[q] = -1;
+      }
     }
-  }
-  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0;
-  if (kMove) {
+    if (kMove) {
+#pragma unroll
+      for (int q = 0; q < kPPT; ++q) {
+        chunk_append(st[q] == ST_MD, sm.md, &sm.nmd, p0 + q);
+        chunk_append(cand[q], L.coll + beg, &sm.ncoll, p0 + q);
+        chunk_append(st[q] == ST_OUT, L.out + beg, &sm.nout, p0 + q);
+        n_out += st[q] == ST_OUT;
+        n_w0 += st[q] == ST_WALL0;
+        n_w1 += st[q] == ST_WALL1;
+        n_bad += st[q] == ST_BAD;
+        n_md += st[q] == ST_MD;
+      }
+      if (have) {
+        reinterpret_cast<int4*>(P.cell)[g4] = make_int4(cell[0], cell[1], cell[2], cell[3]);
+        reinterpret_cast<float4*>(P.ox)[g4] = make_float4(o[0][0], o[1][0], o[2][0], o[3][0]);
+        reinterpret_cast<float4*>(P.oy)[g4] = make_float4(o[0][1], o[1][1], o[2][1], o[3][1]);
+        reinterpret_cast<float4*>(P.oz)[g4] = make_float4(o[0][2], o[1][2], o[2][2], o[3][2]);
+        reinterpret_cast<float4*>(P.vx)[g4] = make_float4(v[0][0], v[1][0], v[2][0], v[3][0]);
+        reinterpret_cast<float4*>(P.vy)[g4] = make_float4(v[0][1], v[1][1], v[2][1], v[3][1]);
+        reinterpret_cast<float4*>(P.vz)[g4] = make_float4(v[0][2], v[1][2], v[2][2], v[3][2]);
+      }
+    }
+
+    // deposit of rho_{k+1}
+    long long acc[8];
+    int acc_cell = -1;
 #pragma unroll
     for (int q = 0; q < kPPT; ++q) {
-      chunk_append(st[q] == ST_MD, s_md, &s_nmd, (int)(p0 + q));
-      chunk_append(cand[q], L.coll + chunk0, &s_ncoll, (int)(p0 + q));
-      chunk_append(st[q] == ST_OUT, L.out + chunk0, &s_nout, (int)(p0 + q));
-      n_out += st[q] == ST_OUT;
-      n_w0 += st[q] == ST_WALL0;
-      n_w1 += st[q] == ST_WALL1;
-      n_bad += st[q] == ST_BAD;
-      n_md += st[q] == ST_MD;
+      if (st[q] != ST_ALIVE) continue;
+      long long part[8];
+      split8(S.Qp, o[q][0], o[q][1], o[q][2], part);
+      if (cell[q] == acc_cell) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] += part[t];
+      } else {
+        if (acc_cell >= 0) {
+          const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
+#pragma unroll
+          for (int t = 0; t < 8; ++t) acc[t] *= S.isign;
+          corner_add<long long>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), sm.rho, rho, S, ai,
+                                aj, ak, acc);
+        }
+        acc_cell = cell[q];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] = part[t];
+      }
+    }
+    if (acc_cell >= 0) {
+      const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t] *= S.isign;
+      corner_add<long long>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), sm.rho, rho, S, ai, aj,
+                            ak, acc);
+    }
+    if (kMove) {
+      __syncthreads();
+      md_flush(sm.md, &sm.nmd, &sm.mdbase, L);
     }
   }
   if (kMove) {
-  reinterpret_cast<int4*>(P.cell)[g4] = make_int4(cell[0], cell[1], cell[2], cell[3]);
-  reinterpret_cast<float4*>(P.ox)[g4] = make_float4(o[0][0], o[1][0], o[2][0], o[3][0]);
-  reinterpret_cast<float4*>(P.oy)[g4] = make_float4(o[0][1], o[1][1], o[2][1], o[3][1]);
-  reinterpret_cast<float4*>(P.oz)[g4] = make_float4(o[0][2], o[1][2], o[2][2], o[3][2]);
-  reinterpret_cast<float4*>(P.vx)[g4] = make_float4(v[0][0], v[1][0], v[2][0], v[3][0]);
-  reinterpret_cast<float4*>(P.vy)[g4] = make_float4(v[0][1], v[1][1], v[2][1], v[3][1]);
-  reinterpret_cast<float4*>(P.vz)[g4] = make_float4(v[0][2], v[1][2], v[2][2], v[3][2]);
+    tally_add(sm.tally, TL_W0, n_w0);
+    tally_add(sm.tally, TL_W1, n_w1);
+    tally_add(sm.tally, TL_BAD, n_bad);
+    tally_add(sm.tally, TL_MD, n_md);
+    tally_add(sm.tally, TL_DEAD, n_w0 + n_w1 + n_bad);
+    tally_add(sm.tally, TL_FALL, n_out);
   }
-
-  // deposit of rho_{k+1}
-  long long acc[8];
-  int acc_cell = -1;
-#pragma unroll
-  for (int q = 0; q < kPPT; ++q) {
-    if (st[q] != ST_ALIVE) continue;
-    long long part[8];
-    split8(S.Qp, o[q][0], o[q][1], o[q][2], part);
-    if (cell[q] == acc_cell) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) acc[t] += part[t];
-    } else {
-      if (acc_cell >= 0) {
-        const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) acc[t] *= S.isign;
-        corner_add<long long>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj,
-                              ak, acc);
-      }
-      acc_cell = cell[q];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) acc[t] = part[t];
-    }
-  }
-  if (acc_cell >= 0) {
-    const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] *= S.isign;
-    corner_add<long long>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj, ak,
-                          acc);
-  }
-  tally_add(s_tally, TL_W0, n_w0);
-  tally_add(s_tally, TL_W1, n_w1);
-  tally_add(s_tally, TL_BAD, n_bad);
-  tally_add(s_tally, TL_MD, n_md);
-  tally_add(s_tally, TL_DEAD, n_w0 + n_w1 + n_bad);
-  tally_add(s_tally, TL_FALL, n_out);
   __syncthreads();
   for (int t = threadIdx.x; t < vol; t += kBlock) {
-    const long long val = s_rho[t];
+    const long long val = sm.rho[t];
     if (val != 0)
       atomicAdd((unsigned long long*)&rho[tile_node(tile, t, rtx, rtxy, S.nx, S.ny, S.nxy)],
                 (unsigned long long)val);
   }
   if (kMove) {
-    // the MD particles join one dense list: one reservation per block that has any
     if (threadIdx.x == 0) {
-      L.coll_cnt[chunk] = s_ncoll;
-      L.out_cnt[chunk] = s_nout;
-      if (s_nmd) s_mdbase = atomicAdd(&L.cnt[2], s_nmd);
+      L.coll_cnt[tidx] = sm.ncoll;
+      L.out_cnt[tidx] = sm.nout;
     }
-    tally_store(s_tally, L.tally + TL_N * chunk);
-    __syncthreads();
-    for (int t = threadIdx.x; t < s_nmd; t += kBlock) L.md[s_mdbase + t] = s_md[t];
+    tally_store(sm.tally, L.tally + (long)TL_N * tidx);
   }
 }
 
@@ -849,14 +827,14 @@ __global__ __launch_bounds__(kBlock) void push_f32r_kernel(PartF32R P,
                                                            long long* __restrict__ rho, MdTables md,
                                                            SpeciesStep S, WorkLists L) {
   __shared__ PushSmemF32 sm;
-  push_chunk_f32r<kMove>(P, E, rho, md, S, L, xcd_chunk(blockIdx.x, gridDim.x), sm);
+  push_tile_f32r<kMove>(P, E, rho, md, S, L, (int)xcd_chunk(blockIdx.x, gridDim.x), sm);
 }
 
 // ---------------------------------------------------------------- push, ensemble
-// One persistent launch over the chunks of every (replica, species) of an
+// One persistent launch over the tiles of every (replica, species) of an
 // ensemble: work item i belongs to descriptor d with start[d] <= i < start[d+1]
-// (starts are multiples of 8, so the XCD remapping stays a permutation per
-// descriptor); blocks stride over the items.
+// (each descriptor has a multiple of 8 tiles, so the XCD remapping stays a
+// permutation per descriptor); blocks stride over the items.
 __global__ __launch_bounds__(kBlock) void push_batch_f32r_kernel(const PushDescF32* __restrict__ descs,
                                                                  const int32_t* __restrict__ start,
                                                                  int ndesc) {
@@ -871,35 +849,36 @@ __global__ __launch_bounds__(kBlock) void push_batch_f32r_kernel(const PushDescF
     }
     const int local = item - start[lo];
     const PushDescF32& d = descs[lo];
-    push_chunk_f32r<true>(d.P, d.E, d.rho, d.md, d.S, d.L, xcd_chunk(local, start[lo + 1] - start[lo]),
-                          sm);
+    push_tile_f32r<true>(d.P, d.E, d.rho, d.md, d.S, d.L,
+                         (int)xcd_chunk(local, start[lo + 1] - start[lo]), sm);
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- push, FP64
 // The same kernel on FP64 records: positions in cell units, velocities in m/s;
-// an empty slot has z = -1.  The field tile holds (Ex,Ey),(Ez,0) pairs.
+// an empty slot has z = -1.  The field window holds (Ex,Ey),(Ez,0) pairs.
+constexpr int kWinF64 = 729;  // window capacity (nodes): a tile with a 2-cell margin
+
 template <bool kMove>
 __global__ __launch_bounds__(kBlock) void push_f64_kernel(PartF64 P, const double2* __restrict__ E,
                                                           double* __restrict__ rho, MdTables md,
                                                           SpeciesStep S, WorkLists L) {
-  __shared__ double2 s_E[2 * kTileNodes];
-  __shared__ double s_rho[kTileNodes];
+  __shared__ double2 s_E[2 * kWinF64];
+  __shared__ double s_rho[kWinF64];
   __shared__ unsigned s_tally[TL_N];
   __shared__ int s_nmd, s_ncoll, s_nout, s_mdbase;
-  __shared__ int32_t s_md[kChunk];
-  const int n = L.cnt[0];
-  const long chunk = xcd_chunk(blockIdx.x, gridDim.x);
-  const long chunk0 = chunk * kChunk;
-  if (chunk0 >= n) {
+  __shared__ int32_t s_md[kMdStage];
+  const int tidx = (int)xcd_chunk(blockIdx.x, gridDim.x);
+  const int beg = L.tstart[tidx], end = L.tstart[tidx + 1];
+  if (beg >= end) {
     if (kMove && threadIdx.x == 0) {
-      L.coll_cnt[chunk] = 0;
-      L.out_cnt[chunk] = 0;
+      L.coll_cnt[tidx] = 0;
+      L.out_cnt[tidx] = 0;
     }
     return;
   }
-  const Tile tile = make_tile(L.box + 6 * chunk, S.nx, S.ny, S.nz, S.margin);
+  const Tile tile = make_tile(tidx, L, S.nx, S.ny, S.nz, S.margin, kWinF64);
   const int vol = tile.on ? tile.tx * tile.ty * tile.tz : 0;
   const float rtx = 1.0f / (float)max(tile.tx, 1), rtxy = 1.0f / (float)max(tile.tx * tile.ty, 1);
   for (int t = threadIdx.x; t < vol; t += kBlock) {
@@ -916,9 +895,20 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(PartF64 P, const doubl
     s_ncoll = 0;
     s_nout = 0;
   }
-  const long g4 = chunk0 / kPPT + threadIdx.x;
-  const long p0 = g4 * kPPT;
-  double x[kPPT][3], v[kPPT][3];
+  __syncthreads();
+  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0, n_out = 0;
+  for (int base = beg; base < end; base += kChunk) {
+    const int p0 = base + kPPT * (int)threadIdx.x;
+    const bool have = p0 < end;  // four slots in the tile, or none
+    const long g4 = p0 / kPPT;
+    double x[kPPT][3], v[kPPT][3];
+    uint32_t id[kPPT] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < kPPT; ++q) {
+      x[q][0] = x[q][1] = v[q][0] = v[q][1] = v[q][2] = 0.0;
+      x[q][2] = -1.0;
+    }
+    if (have) {
 #define PIC_LOAD4(arr, dst, a)                                            \
   {                                                                       \
     const double2 lo = reinterpret_cast<const double2*>(arr)[2 * g4];     \
@@ -928,198 +918,152 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(PartF64 P, const doubl
     dst[2][a] = hi.x;                                                     \
     dst[3][a] = hi.y;                                                     \
   }
-  PIC_LOAD4(P.x, x, 0)
-  PIC_LOAD4(P.y, x, 1)
-  PIC_LOAD4(P.z, x, 2)
-  PIC_LOAD4(P.vx, v, 0)
-  PIC_LOAD4(P.vy, v, 1)
-  PIC_LOAD4(P.vz, v, 2)
+      PIC_LOAD4(P.x, x, 0)
+      PIC_LOAD4(P.y, x, 1)
+      PIC_LOAD4(P.z, x, 2)
+      PIC_LOAD4(P.vx, v, 0)
+      PIC_LOAD4(P.vy, v, 1)
+      PIC_LOAD4(P.vz, v, 2)
 #undef PIC_LOAD4
-  const uint4 I4 = reinterpret_cast<const uint4*>(P.id)[g4];
-  const uint32_t id[kPPT] = {I4.x, I4.y, I4.z, I4.w};
-  __syncthreads();
-  int st[kPPT], cell[kPPT];
-  bool cand[kPPT];
-  int n_out = 0;
-#pragma unroll
-  for (int q = 0; q < kPPT; ++q) {
-    st[q] = ST_NONE;
-    cand[q] = false;
-    cell[q] = -1;
-    if (!kMove) {
-      if (p0 + q < n && x[q][2] >= 0.0) {
-        st[q] = ST_ALIVE;
-        cell[q] = pack_cell((int)floor(x[q][0]), (int)floor(x[q][1]), (int)floor(x[q][2]));
-      }
-      continue;
+      const uint4 I4 = reinterpret_cast<const uint4*>(P.id)[g4];
+      id[0] = I4.x;
+      id[1] = I4.y;
+      id[2] = I4.z;
+      id[3] = I4.w;
     }
-    if (p0 + q < n && x[q][2] >= 0.0) {
-      const int i0 = (int)floor(x[q][0]), j0 = (int)floor(x[q][1]), k0 = (int)floor(x[q][2]);
-      if (md_lookup(md, S.nx, S.ny, i0, j0, k0) != 0u) {
-        st[q] = ST_MD;
-      } else {
-        double Ep[3];
-        const double fx = x[q][0] - i0, fy = x[q][1] - j0, fz = x[q][2] - k0;
-        const int lb = tile_cell(tile, i0, j0, k0, S.nx, S.ny);
-        if (lb < 0) {
-          st[q] = ST_OUT;  // left for the outlier kernel
-          continue;
-        }
-        {
-          const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
-          Ep[0] = Ep[1] = Ep[2] = 0.0;
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int l = lb + (t & 1) + tile.tx * (((t >> 1) & 1) + tile.ty * (t >> 2));
-            const double w = wx[t & 1] * wy[(t >> 1) & 1] * wz[t >> 2];
-            const double2 a = s_E[2 * l], b2 = s_E[2 * l + 1];
-            Ep[0] += w * a.x;
-            Ep[1] += w * a.y;
-            Ep[2] += w * b2.x;
-          }
-        }
-        st[q] = push_one_f64(S, Ep, x[q], v[q]);
-        if (st[q] == ST_ALIVE) {
-          cell[q] = pack_cell((int)floor(x[q][0]), (int)floor(x[q][1]), (int)floor(x[q][2]));
-          const uint4 r = philox4x32_10(id[q], *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
-          cand[q] = (uint64_t)r.x < S.T_null;
-        } else {
-          x[q][2] = -1.0;
-        }
-      }
-    }
-  }
-  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0;
-  if (kMove) {
+    int st[kPPT], cell[kPPT];
+    bool cand[kPPT];
 #pragma unroll
     for (int q = 0; q < kPPT; ++q) {
-      chunk_append(st[q] == ST_MD, s_md, &s_nmd, (int)(p0 + q));
-      chunk_append(cand[q], L.coll + chunk0, &s_ncoll, (int)(p0 + q));
-      chunk_append(st[q] == ST_OUT, L.out + chunk0, &s_nout, (int)(p0 + q));
-      n_out += st[q] == ST_OUT;
-      n_w0 += st[q] == ST_WALL0;
-      n_w1 += st[q] == ST_WALL1;
-      n_bad += st[q] == ST_BAD;
-      n_md += st[q] == ST_MD;
+      st[q] = ST_NONE;
+      cand[q] = false;
+      cell[q] = -1;
+      if (!(x[q][2] >= 0.0)) continue;
+      const int i0 = (int)floor(x[q][0]), j0 = (int)floor(x[q][1]), k0 = (int)floor(x[q][2]);
+      if (!kMove) {
+        st[q] = ST_ALIVE;
+        cell[q] = pack_cell(i0, j0, k0);
+        continue;
+      }
+      if (md_lookup(md, S.nx, S.ny, i0, j0, k0) != 0u) {
+        st[q] = ST_MD;
+        continue;
+      }
+      const int lb = tile_cell(tile, i0, j0, k0, S.nx, S.ny);
+      if (lb < 0) {
+        st[q] = ST_OUT;  // left for the outlier kernel
+        continue;
+      }
+      double Ep[3];
+      {
+        const double fx = x[q][0] - i0, fy = x[q][1] - j0, fz = x[q][2] - k0;
+        const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+        Ep[0] = Ep[1] = Ep[2] = 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int l = lb + (t & 1) + tile.tx * (((t >> 1) & 1) + tile.ty * (t >> 2));
+          const double w = wx[t & 1] * wy[(t >> 1) & 1] * wz[t >> 2];
+          const double2 a = s_E[2 * l], b2 = s_E[2 * l + 1];
+          Ep[0] += w * a.x;
+          Ep[1] += w * a.y;
+          Ep[2] += w * b2.x;
+        }
+      }
+      st[q] = push_one_f64(S, Ep, x[q], v[q]);
+      if (st[q] == ST_ALIVE) {
+        cell[q] = pack_cell((int)floor(x[q][0]), (int)floor(x[q][1]), (int)floor(x[q][2]));
+        const uint4 r = philox4x32_10(id[q], *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
+        cand[q] = (uint64_t)r.x < S.T_null;
+      } else {
+        x[q][2] = -1.0;
+      }
     }
-  }
-  if (kMove) {
+    if (kMove) {
+#pragma unroll
+      for (int q = 0; q < kPPT; ++q) {
+        chunk_append(st[q] == ST_MD, s_md, &s_nmd, p0 + q);
+        chunk_append(cand[q], L.coll + beg, &s_ncoll, p0 + q);
+        chunk_append(st[q] == ST_OUT, L.out + beg, &s_nout, p0 + q);
+        n_out += st[q] == ST_OUT;
+        n_w0 += st[q] == ST_WALL0;
+        n_w1 += st[q] == ST_WALL1;
+        n_bad += st[q] == ST_BAD;
+        n_md += st[q] == ST_MD;
+      }
+      if (have) {
 #define PIC_STORE4(arr, srcv, a)                                                          \
   {                                                                                       \
     reinterpret_cast<double2*>(arr)[2 * g4] = make_double2(srcv[0][a], srcv[1][a]);     \
     reinterpret_cast<double2*>(arr)[2 * g4 + 1] = make_double2(srcv[2][a], srcv[3][a]); \
   }
-  PIC_STORE4(P.x, x, 0)
-  PIC_STORE4(P.y, x, 1)
-  PIC_STORE4(P.z, x, 2)
-  PIC_STORE4(P.vx, v, 0)
-  PIC_STORE4(P.vy, v, 1)
-  PIC_STORE4(P.vz, v, 2)
+        PIC_STORE4(P.x, x, 0)
+        PIC_STORE4(P.y, x, 1)
+        PIC_STORE4(P.z, x, 2)
+        PIC_STORE4(P.vx, v, 0)
+        PIC_STORE4(P.vy, v, 1)
+        PIC_STORE4(P.vz, v, 2)
 #undef PIC_STORE4
-  }
-
-  double acc[8];
-  int acc_cell = -1;
-#pragma unroll
-  for (int q = 0; q < kPPT; ++q) {
-    if (st[q] != ST_ALIVE) continue;
-    double w[8];
-    const int i = cell_i(cell[q]), j = cell_j(cell[q]), k = cell_k(cell[q]);
-    cic_weights_d(x[q][0] - i, x[q][1] - j, x[q][2] - k, S.sign, w);
-    if (cell[q] == acc_cell) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) acc[t] += w[t];
-    } else {
-      if (acc_cell >= 0) {
-        const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
-        corner_add<double>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj, ak,
-                           acc);
       }
-      acc_cell = cell[q];
+    }
+
+    double acc[8];
+    int acc_cell = -1;
 #pragma unroll
-      for (int t = 0; t < 8; ++t) acc[t] = w[t];
+    for (int q = 0; q < kPPT; ++q) {
+      if (st[q] != ST_ALIVE) continue;
+      double w[8];
+      const int i = cell_i(cell[q]), j = cell_j(cell[q]), k = cell_k(cell[q]);
+      cic_weights_d(x[q][0] - i, x[q][1] - j, x[q][2] - k, S.sign, w);
+      if (cell[q] == acc_cell) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] += w[t];
+      } else {
+        if (acc_cell >= 0) {
+          const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
+          corner_add<double>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj,
+                             ak, acc);
+        }
+        acc_cell = cell[q];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] = w[t];
+      }
+    }
+    if (acc_cell >= 0) {
+      const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
+      corner_add<double>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj, ak,
+                         acc);
+    }
+    if (kMove) {
+      __syncthreads();
+      md_flush(s_md, &s_nmd, &s_mdbase, L);
     }
   }
-  if (acc_cell >= 0) {
-    const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
-    corner_add<double>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), s_rho, rho, S, ai, aj, ak, acc);
+  if (kMove) {
+    tally_add(s_tally, TL_W0, n_w0);
+    tally_add(s_tally, TL_W1, n_w1);
+    tally_add(s_tally, TL_BAD, n_bad);
+    tally_add(s_tally, TL_MD, n_md);
+    tally_add(s_tally, TL_DEAD, n_w0 + n_w1 + n_bad);
+    tally_add(s_tally, TL_FALL, n_out);
   }
-  tally_add(s_tally, TL_W0, n_w0);
-  tally_add(s_tally, TL_W1, n_w1);
-  tally_add(s_tally, TL_BAD, n_bad);
-  tally_add(s_tally, TL_MD, n_md);
-  tally_add(s_tally, TL_DEAD, n_w0 + n_w1 + n_bad);
-  tally_add(s_tally, TL_FALL, n_out);
   __syncthreads();
   for (int t = threadIdx.x; t < vol; t += kBlock) {
     const double val = s_rho[t];
     if (val != 0.0) unsafeAtomicAdd(&rho[tile_node(tile, t, rtx, rtxy, S.nx, S.ny, S.nxy)], val);
   }
   if (kMove) {
-    // the MD particles join one dense list: one reservation per block that has any
     if (threadIdx.x == 0) {
-      L.coll_cnt[chunk] = s_ncoll;
-      L.out_cnt[chunk] = s_nout;
-      if (s_nmd) s_mdbase = atomicAdd(&L.cnt[2], s_nmd);
+      L.coll_cnt[tidx] = s_ncoll;
+      L.out_cnt[tidx] = s_nout;
     }
-    tally_store(s_tally, L.tally + TL_N * chunk);
-    __syncthreads();
-    for (int t = threadIdx.x; t < s_nmd; t += kBlock) L.md[s_mdbase + t] = s_md[t];
+    tally_store(s_tally, L.tally + (long)TL_N * tidx);
   }
-}
-
-// ---------------------------------------------------------------- chunk boxes
-// After a sort: the exact cell box of each chunk's particles.
-__device__ __forceinline__ bool slot_cell(const PartF64& P, long p, int& i, int& j, int& k) {
-  if (!(P.z[p] >= 0.0)) return false;
-  i = (int)floor(P.x[p]);
-  j = (int)floor(P.y[p]);
-  k = (int)floor(P.z[p]);
-  return true;
-}
-__device__ __forceinline__ bool slot_cell(const PartF32R& P, long p, int& i, int& j, int& k) {
-  const int c = P.cell[p];
-  if (c < 0) return false;
-  i = cell_i(c);
-  j = cell_j(c);
-  k = cell_k(c);
-  return true;
-}
-
-template <typename PT>
-__global__ __launch_bounds__(kBlock) void chunk_box_kernel(PT P, WorkLists L, int nx, int ny) {
-  __shared__ int s_red[kWaves][10];
-  const int n = L.cnt[0];
-  const long chunk = blockIdx.x;
-  const long chunk0 = chunk * kChunk;
-  int v[10] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
-  for (int q = 0; q < kPPT; ++q) {
-    const long p = chunk0 + q * kBlock + threadIdx.x;
-    int i, j, k;
-    if (p < n && slot_cell(P, p, i, j, k)) box_update(v, i, j, k, nx, ny);
-  }
-  block_minmax(v, s_red);
-  if (threadIdx.x != 0) return;
-  int32_t* b = L.box + 6 * chunk;
-  if (v[0] > v[1]) {
-    for (int t = 0; t < 6; ++t) b[t] = 0;
-    return;
-  }
-  int c0, nc;
-  axis_cells(v[0], v[1], v[2], v[3], nx, c0, nc);
-  b[0] = c0;
-  b[1] = nc;
-  axis_cells(v[4], v[5], v[6], v[7], ny, c0, nc);
-  b[2] = c0;
-  b[3] = nc;
-  b[4] = v[8];
-  b[5] = v[9] - v[8] + 1;
 }
 
 // ---------------------------------------------------------------- MD particles
 // The particles that started the step inside an MD cube: the sub-cycled PPPM
 // motion in FP64, grain and electrode absorption, the collision, the deposit.
-// One block per chunk list segment.
+// One thread per entry of the dense list.
 __device__ __forceinline__ void load_d(const PartF64& P, long p, double x[3], double v[3]) {
   x[0] = P.x[p];
   x[1] = P.y[p];
@@ -1187,7 +1131,7 @@ template <typename PT, typename ET, typename RT>
 __global__ __launch_bounds__(64) void md_kernel(PT P, const ET* __restrict__ E, RT* __restrict__ rho,
                                                 MdTables md, SpeciesStep S,
                                                 unsigned long long* __restrict__ grain_count,
-                                                WorkLists L, int nchunks, int do_mcc) {
+                                                WorkLists L, int do_mcc) {
   const int total = L.cnt[2];
   if ((long)blockIdx.x * 64 >= total) return;
   constexpr int kStage = 256;
@@ -1205,7 +1149,7 @@ __global__ __launch_bounds__(64) void md_kernel(PT P, const ET* __restrict__ E, 
     __syncthreads();
     G = GrainView{s_gpos, s_gcell, s_Q};
   }
-  unsigned long long* tally = L.tally + (long)TL_N * nchunks;  // the MD row
+  unsigned long long* tally = L.tally + (long)TL_N * L.ngrid;  // the MD row
   for (long base = (long)blockIdx.x * 64; base < total; base += (long)gridDim.x * 64) {
     const int idx = (int)base + threadIdx.x;
     int st = ST_NONE;
@@ -1239,17 +1183,17 @@ __global__ void md_reset_kernel(int32_t* cnt) {
 }
 
 // ---------------------------------------------------------------- outliers
-// Particles that started outside their chunk's tile (they drifted since the
+// Particles that started outside their tile's window (they drifted since the
 // last sort): the same push with the field gathered from global memory and the
 // charge deposited with global atomics, the collision done in place.  One wave
-// per chunk segment.
+// per tile segment.
 __global__ __launch_bounds__(64) void outlier_f32r_kernel(PartF32R P, const float4* __restrict__ E,
                                                           long long* __restrict__ rho,
                                                           SpeciesStep S, WorkLists L, int do_mcc) {
-  const long chunk = blockIdx.x;
-  const int count = L.out_cnt[chunk];
+  const int tidx = blockIdx.x;
+  const int count = L.out_cnt[tidx];
   if (count == 0) return;
-  const int32_t* seg = L.out + chunk * kChunk;
+  const int32_t* seg = L.out + L.tstart[tidx];
   int t_w0 = 0, t_w1 = 0, t_bad = 0, t_coll = 0, t_cap = 0;
   for (int idx = threadIdx.x; idx < count; idx += 64) {
     const long p = seg[idx];
@@ -1305,7 +1249,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(PartF32R P, const floa
   t_coll = wave_sum(t_coll);
   t_cap = wave_sum(t_cap);
   if (threadIdx.x == 0) {
-    unsigned long long* tl = L.tally + TL_N * chunk;
+    unsigned long long* tl = L.tally + (long)TL_N * tidx;
     tl[TL_W0] += t_w0;
     tl[TL_W1] += t_w1;
     tl[TL_BAD] += t_bad;
@@ -1318,10 +1262,10 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(PartF32R P, const floa
 __global__ __launch_bounds__(64) void outlier_f64_kernel(PartF64 P, const double2* __restrict__ E,
                                                          double* __restrict__ rho, SpeciesStep S,
                                                          WorkLists L, int do_mcc) {
-  const long chunk = blockIdx.x;
-  const int count = L.out_cnt[chunk];
+  const int tidx = blockIdx.x;
+  const int count = L.out_cnt[tidx];
   if (count == 0) return;
-  const int32_t* seg = L.out + chunk * kChunk;
+  const int32_t* seg = L.out + L.tstart[tidx];
   int t_w0 = 0, t_w1 = 0, t_bad = 0, t_coll = 0, t_cap = 0;
   for (int idx = threadIdx.x; idx < count; idx += 64) {
     const long p = seg[idx];
@@ -1357,7 +1301,7 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(PartF64 P, const double
   t_coll = wave_sum(t_coll);
   t_cap = wave_sum(t_cap);
   if (threadIdx.x == 0) {
-    unsigned long long* tl = L.tally + TL_N * chunk;
+    unsigned long long* tl = L.tally + (long)TL_N * tidx;
     tl[TL_W0] += t_w0;
     tl[TL_W1] += t_w1;
     tl[TL_BAD] += t_bad;
@@ -1368,13 +1312,13 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(PartF64 P, const double
 }
 
 // ---------------------------------------------------------------- collisions
-// One wave per chunk list segment of collision candidates.
+// One wave per tile segment of collision candidates.
 template <typename PT>
 __global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLists L) {
-  const long chunk = blockIdx.x;
-  const int count = L.coll_cnt[chunk];
+  const int tidx = blockIdx.x;
+  const int count = L.coll_cnt[tidx];
   if (count == 0) return;
-  const int32_t* seg = L.coll + chunk * kChunk;
+  const int32_t* seg = L.coll + L.tstart[tidx];
   int n_coll = 0, n_cap = 0;
   for (int idx = threadIdx.x; idx < count; idx += 64) {
     const long p = seg[idx];
@@ -1392,8 +1336,8 @@ __global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLi
   n_coll = wave_sum(n_coll);
   n_cap = wave_sum(n_cap);
   if (threadIdx.x == 0) {
-    L.tally[TL_N * chunk + TL_COLL] += (unsigned long long)n_coll;
-    L.tally[TL_N * chunk + TL_CAP] += (unsigned long long)n_cap;
+    L.tally[(long)TL_N * tidx + TL_COLL] += (unsigned long long)n_coll;
+    L.tally[(long)TL_N * tidx + TL_CAP] += (unsigned long long)n_cap;
   }
 }
 
@@ -1451,8 +1395,11 @@ __global__ void init_f32r_kernel(PartF32R P, int n, int ppc, int nx, int ny, int
 }
 
 // ---------------------------------------------------------------- cell sort
-// Counting sort of one species by linear cell index (x fastest), dropping the
-// empty slots: histogram, exclusive scan, scatter into the other buffer.
+// Counting sort of one species into the other buffer by cell in tile order,
+// dropping the empty slots: a histogram over the cells, the size of every
+// tile rounded up to a multiple of 4 slots and the exclusive scan of the
+// sizes (the tile starts), the cursor of every cell (its tile's start plus the
+// cells before it in the tile), the padding slots marked empty, the scatter.
 // key of a cell in 4x4x4-tile order (tiles x fastest, cells x fastest inside a tile)
 struct TileOrder {
   int ntx, nty;  // tiles along x, y
@@ -1531,15 +1478,41 @@ __global__ void sort_scatter_kernel(PT src, PT dst, const int* __restrict__ cnt,
   if (key >= 0) copy_particle(src, p, dst, base + r.rank);
 }
 
-// after the scatter the survivors fill [0, cnt[4]) of the other buffer; the
-// empty-slot counts start again from zero
-__global__ void sort_finish_kernel(int* cnt, unsigned long long* tally, int nchunks) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c <= nchunks) tally[TL_N * c + TL_DEAD] = 0;  // row nchunks: the MD kernel
-  if (c == 0) {
-    cnt[0] = cnt[4];
-    cnt[4] = 0;
+// one wave per tile t <= ngrid: the tile's size rounded up to a multiple of 4
+// (0 for the padding tiles of the grid and for the end entry t = ngrid)
+__global__ void tile_size_kernel(const int* __restrict__ hist, int* __restrict__ tsize, int ntiles,
+                                 int ngrid) {
+  const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t > ngrid) return;
+  const int sum = wave_sum(t < ntiles ? hist[64 * t + lane] : 0);
+  if (lane == 0) tsize[t] = (sum + 3) & ~3;
+}
+
+// one wave per tile: hist becomes the first slot of each cell; the padding
+// slots at the end of the tile are marked empty
+template <typename PT>
+__global__ void tile_cursor_kernel(int* __restrict__ hist, const int* __restrict__ tstart, PT dst,
+                                   int ntiles) {
+  const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= ntiles) return;
+  const int c = hist[64 * t + lane];
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += u;
   }
+  const int first = tstart[t];
+  hist[64 * t + lane] = first + incl - c;
+  const int pad = first + __shfl(incl, 63, 64) + lane;
+  if (pad < tstart[t + 1]) kill(dst, pad);
+}
+
+// after the scatter the tiles fill [0, tstart[ngrid]) of the other buffer
+__global__ void sort_finish_kernel(int* cnt, const int* tstart, int ngrid) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) cnt[0] = tstart[ngrid];
 }
 
 // exclusive scan of an int array: per-block sums, scan of the sums, per-block scan
@@ -1609,23 +1582,25 @@ __global__ void advance_step_kernel(uint32_t* step) {
 // ---------------------------------------------------------------- launchers
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
-int push_chunks(long capacity) { return (nblk(capacity, kChunk) + 7) / 8 * 8; }
+int tile_grid(int nx, int ny, int nz) {
+  return (((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) + 7) / 8 * 8;
+}
 
 void launch_advance_step(uint32_t* step, hipStream_t st) {
   hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, step);
 }
 
 void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
-                     const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st) {
-  if (capacity <= 0) return;
-  hipLaunchKernelGGL(push_f64_kernel<true>, dim3(push_chunks(capacity)), dim3(kBlock), 0, st, P,
+                     const SpeciesStep& S, const WorkLists& L, hipStream_t st) {
+  if (L.ngrid <= 0) return;
+  hipLaunchKernelGGL(push_f64_kernel<true>, dim3(L.ngrid), dim3(kBlock), 0, st, P,
                      (const double2*)E, rho, md, S, L);
 }
 
 void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
-                      const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st) {
-  if (capacity <= 0) return;
-  hipLaunchKernelGGL(push_f32r_kernel<true>, dim3(push_chunks(capacity)), dim3(kBlock), 0, st, P,
+                      const SpeciesStep& S, const WorkLists& L, hipStream_t st) {
+  if (L.ngrid <= 0) return;
+  hipLaunchKernelGGL(push_f32r_kernel<true>, dim3(L.ngrid), dim3(kBlock), 0, st, P,
                      (const float4*)E, rho, md, S, L);
 }
 
@@ -1639,28 +1614,28 @@ constexpr int kMdBlocks = 2048;
 
 void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
                       const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
-                      long capacity, hipStream_t st) {
-  if (capacity <= 0) return;
-  const int nc = push_chunks(capacity);
+                      hipStream_t st) {
+  if (L.ngrid <= 0) return;
+  const int nc = L.ngrid;
   hipLaunchKernelGGL(outlier_f64_kernel, dim3(nc), dim3(64), 0, st, P, (const double2*)E, rho, S, L,
                      do_mcc);
   if (md.n_grains > 0)
     hipLaunchKernelGGL((md_kernel<PartF64, double2, double>), dim3(kMdBlocks), dim3(64), 0, st, P,
-                       (const double2*)E, rho, md, S, gc, L, nc, do_mcc);
+                       (const double2*)E, rho, md, S, gc, L, do_mcc);
   hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L.cnt);
   if (do_mcc) hipLaunchKernelGGL(collide_kernel<PartF64>, dim3(nc), dim3(64), 0, st, P, S, L);
 }
 
 void launch_lists_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
                        const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
-                       long capacity, hipStream_t st) {
-  if (capacity <= 0) return;
-  const int nc = push_chunks(capacity);
+                       hipStream_t st) {
+  if (L.ngrid <= 0) return;
+  const int nc = L.ngrid;
   hipLaunchKernelGGL(outlier_f32r_kernel, dim3(nc), dim3(64), 0, st, P, (const float4*)E, rho, S,
                      L, do_mcc);
   if (md.n_grains > 0)
     hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(kMdBlocks), dim3(64), 0, st,
-                       P, (const float4*)E, rho, md, S, gc, L, nc, do_mcc);
+                       P, (const float4*)E, rho, md, S, gc, L, do_mcc);
   hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L.cnt);
   if (do_mcc) hipLaunchKernelGGL(collide_kernel<PartF32R>, dim3(nc), dim3(64), 0, st, P, S, L);
 }
@@ -1680,17 +1655,17 @@ void launch_init_f32r(const PartF32R& P, int n, int ppc, int nx, int ny, int sp,
 }
 
 void launch_deposit_f64(const PartF64& P, double* rho, const MdTables& md, const SpeciesStep& S,
-                        const WorkLists& L, long capacity, hipStream_t st) {
-  if (capacity <= 0) return;
-  hipLaunchKernelGGL(push_f64_kernel<false>, dim3(push_chunks(capacity)), dim3(kBlock), 0, st, P,
-                     nullptr, rho, md, S, L);
+                        const WorkLists& L, hipStream_t st) {
+  if (L.ngrid <= 0) return;
+  hipLaunchKernelGGL(push_f64_kernel<false>, dim3(L.ngrid), dim3(kBlock), 0, st, P, nullptr, rho,
+                     md, S, L);
 }
 
 void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
-                         const SpeciesStep& S, const WorkLists& L, long capacity, hipStream_t st) {
-  if (capacity <= 0) return;
-  hipLaunchKernelGGL(push_f32r_kernel<false>, dim3(push_chunks(capacity)), dim3(kBlock), 0, st, P,
-                     nullptr, rho, md, S, L);
+                         const SpeciesStep& S, const WorkLists& L, hipStream_t st) {
+  if (L.ngrid <= 0) return;
+  hipLaunchKernelGGL(push_f32r_kernel<false>, dim3(L.ngrid), dim3(kBlock), 0, st, P, nullptr, rho,
+                     md, S, L);
 }
 
 void launch_fill_int(int* a, long n, int v, hipStream_t st) {
@@ -1703,35 +1678,37 @@ long sort_keys(int nx, int ny, int nz) {
 }
 
 template <typename PT>
-static void sort_impl(const PT& src, const PT& dst, const WorkLists& L, int* hist, int* sums, int nx,
-                      int ny, int nz, long capacity, hipStream_t st) {
-  const TileOrder o{(nx + 3) / 4, (ny + 3) / 4};
-  const long nkey = sort_keys(nx, ny, nz);
-  launch_fill_int(hist, nkey, 0, st);
+static void sort_impl(const PT& src, const PT& dst, const WorkLists& L, int* hist, int* sums,
+                      long capacity, hipStream_t st) {
+  const TileOrder o{L.ntx, L.nty};
+  const int ntiles = L.ntx * L.nty * L.ntz;
+  launch_fill_int(hist, 64L * ntiles, 0, st);
   hipLaunchKernelGGL(sort_hist_kernel<PT>, dim3(nblk(capacity, 256)), dim3(256), 0, st, src, L.cnt,
                      hist, o);
-  const int nb = nblk(nkey, kScanBlock);
-  hipLaunchKernelGGL(scan_block_sums, dim3(nb), dim3(kScanBlock), 0, st, hist, (int)nkey, sums);
+  const int n = L.ngrid + 1;
+  hipLaunchKernelGGL(tile_size_kernel, dim3(nblk(64L * n, 256)), dim3(256), 0, st, hist, L.tstart,
+                     ntiles, L.ngrid);
+  const int nb = nblk(n, kScanBlock);
+  hipLaunchKernelGGL(scan_block_sums, dim3(nb), dim3(kScanBlock), 0, st, L.tstart, n, sums);
   hipLaunchKernelGGL(scan_sums_serial, dim3(1), dim3(kScanBlock), 0, st, sums, nb, L.cnt + 4);
-  hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kScanBlock), 0, st, hist, (int)nkey, sums, hist);
+  hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kScanBlock), 0, st, L.tstart, n, sums, L.tstart);
+  hipLaunchKernelGGL(tile_cursor_kernel<PT>, dim3(nblk(64L * ntiles, 256)), dim3(256), 0, st, hist,
+                     L.tstart, dst, ntiles);
   hipLaunchKernelGGL(sort_scatter_kernel<PT>, dim3(nblk(capacity, 256)), dim3(256), 0, st, src,
                      dst, L.cnt, hist, o);
-  const int nc = push_chunks(capacity);
-  hipLaunchKernelGGL(sort_finish_kernel, dim3(nblk(nc + 1, 256)), dim3(256), 0, st, L.cnt, L.tally,
-                     nc);
-  hipLaunchKernelGGL(chunk_box_kernel<PT>, dim3(nc), dim3(kBlock), 0, st, dst, L, nx, ny);
+  hipLaunchKernelGGL(sort_finish_kernel, dim3(1), dim3(64), 0, st, L.cnt, L.tstart, L.ngrid);
 }
 
 void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L, int* hist,
-                     int* sums, int nx, int ny, int nz, long capacity, hipStream_t st) {
+                     int* sums, long capacity, hipStream_t st) {
   if (capacity <= 0) return;
-  sort_impl(src, dst, L, hist, sums, nx, ny, nz, capacity, st);
+  sort_impl(src, dst, L, hist, sums, capacity, st);
 }
 
 void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const WorkLists& L, int* hist,
-                      int* sums, int nx, int ny, int nz, long capacity, hipStream_t st) {
+                      int* sums, long capacity, hipStream_t st) {
   if (capacity <= 0) return;
-  sort_impl(src, dst, L, hist, sums, nx, ny, nz, capacity, st);
+  sort_impl(src, dst, L, hist, sums, capacity, st);
 }
 
 }  // namespace pic

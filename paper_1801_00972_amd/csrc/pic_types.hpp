@@ -38,21 +38,26 @@ struct RfDrive {
 };
 
 // per-species work lists and counters of one step (device)
-// coll and out are segmented by chunk (the 1024 consecutive slots one push
-// block streams): chunk c owns entries [1024 c, 1024 c + count[c]).
+// The particle arrays are binned by tiles of 4x4x4 cells (tiles x fastest,
+// then y, then z): tile t owns slots [tstart[t], tstart[t+1]), a multiple of 4
+// long, ordered by cell inside the tile and padded with empty slots.  The
+// grid of tiles is padded to a multiple of 8 (the XCD count) with empty tiles.
+// coll and out are segmented the same way: tile t's entries start at tstart[t].
 struct WorkLists {
   int32_t* md;        // dense list: slots of particles that start the step in an MD cube
-  int32_t* coll;      // slots of collision candidates (chunk segments)
-  int32_t* out;       // slots of particles outside their chunk's tile (chunk segments)
-  int32_t* coll_cnt;  // [chunk] entries in coll
-  int32_t* out_cnt;   // [chunk] entries in out
-  int32_t* box;       // [chunk][6] cell box of the chunk at the last sort: i0, ni, j0, nj, k0, nk
-  unsigned long long* tally;  // [chunk + 1][TL_N] accumulated event counts (see TallyKind);
+  int32_t* coll;      // slots of collision candidates (tile segments)
+  int32_t* out;       // slots of particles outside their tile's LDS window (tile segments)
+  int32_t* coll_cnt;  // [ngrid] entries in coll
+  int32_t* out_cnt;   // [ngrid] entries in out
+  int32_t* tstart;    // [ngrid + 1] first slot of each tile (set by the sort)
+  unsigned long long* tally;  // [ngrid + 1][TL_N] accumulated event counts (see TallyKind);
                               // the last row collects the MD kernel's events
-  int32_t* cnt;       // [0] slots in use, [2] entries in md, [4] survivors of the sort
+  int32_t* cnt;       // [0] slots in use, [2] entries in md, [4] scan total of the sort
+  int ntx, nty, ntz;  // tiles along x, y, z
+  int ngrid;          // tiles rounded up to a multiple of 8
 };
 
-// per-chunk event counts; TL_DEAD counts empty slots since the last sort
+// per-tile event counts, accumulated since loading; TL_DEAD counts removed particles
 enum TallyKind { TL_W0 = 0, TL_W1, TL_BAD, TL_MD, TL_FALL, TL_COLL, TL_CAP, TL_DEAD, TL_N };
 
 // near-grain (MD) tables of one replica
@@ -76,7 +81,7 @@ struct SpeciesStep {
   int nx, ny, nz, nxy;
   int sp;                  // 0 electron, 1 ion
   int md_sub;
-  int margin;              // cells of drift allowed around a chunk's box (LDS tiles)
+  int margin;              // cells of drift around a tile staged in the LDS window
   double dx;
   double qm_dt, dt_dx;     // (q/m) dt, dt/dx
   double qm_h, h_dx;       // the same for the MD sub-step h = dt / md_sub

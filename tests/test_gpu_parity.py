@@ -230,6 +230,8 @@ def test_graph_replay_matches_direct_launches(prec):
     from paper_1801_00972_amd.pic import PIC_PHI, pic_profile_enable
     wl = dict(W.small_fp64(), precision=prec)
     a, b = _sim(wl, sort_interval=4), _sim(wl, sort_interval=4)
+    for sim in (a, b):  # the ions are re-binned on their own interval
+        sim.set_tuning(ion_sort_interval=5)
     pic_profile_enable(b.ctx, True)
     for rep in range(6):  # crosses two sorts and both buffer phases
         a.step(3)
