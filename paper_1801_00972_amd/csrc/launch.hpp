@@ -16,7 +16,7 @@ struct FftPlanHost {
 // particles: arrays binned by 4x4x4-cell tile and updated in place (see
 // WorkLists); one push block per tile, the grid padded to a multiple of 8
 int tile_grid(int nx, int ny, int nz);      // tiles rounded up to a multiple of 8
-long sort_keys(int nx, int ny, int nz);     // size of the sort histogram (cells in tile order)
+long sort_keys(int nx, int ny, int nz);     // ints of sort workspace (tile counts and cursors)
 // the streaming kernel of one species (gather, push, walls, candidate test, deposit)
 void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
                      const SpeciesStep& S, const WorkLists& L, hipStream_t st);

@@ -860,8 +860,9 @@ __global__ __launch_bounds__(kBlock) void push_batch_f32r_kernel(const PushDescF
 // an empty slot has z = -1.  The field window holds (Ex,Ey),(Ez,0) pairs.
 constexpr int kWinF64 = 729;  // window capacity (nodes): a tile with a 2-cell margin
 
+// (at most 168 VGPRs: three waves per SIMD)
 template <bool kMove>
-__global__ __launch_bounds__(kBlock) void push_f64_kernel(PartF64 P, const double2* __restrict__ E,
+__global__ __launch_bounds__(kBlock, 3) void push_f64_kernel(PartF64 P, const double2* __restrict__ E,
                                                           double* __restrict__ rho, MdTables md,
                                                           SpeciesStep S, WorkLists L) {
   __shared__ double2 s_E[2 * kWinF64];
@@ -1394,16 +1395,27 @@ __global__ void init_f32r_kernel(PartF32R P, int n, int ppc, int nx, int ny, int
   P.id[p] = (uint32_t)p;
 }
 
-// ---------------------------------------------------------------- cell sort
-// Counting sort of one species into the other buffer by cell in tile order,
-// dropping the empty slots: a histogram over the cells, the size of every
-// tile rounded up to a multiple of 4 slots and the exclusive scan of the
-// sizes (the tile starts), the cursor of every cell (its tile's start plus the
-// cells before it in the tile), the padding slots marked empty, the scatter.
-// key of a cell in 4x4x4-tile order (tiles x fastest, cells x fastest inside a tile)
+// ---------------------------------------------------------------- re-binning
+// Counting sort of one species into the other buffer by tile, and by cell
+// inside each tile, dropping the empty slots.  Each block takes kSortSlots
+// consecutive slots of the (nearly binned) source:
+//  1. count: the block's particles per destination tile, aggregated in an LDS
+//     table, then one global atomic per (block, tile);
+//  2. the tile sizes rounded up to a multiple of 4 and their exclusive scan
+//     (the tile starts); each tile's cursor starts at its start; the padding
+//     slots are marked empty;
+//  3. scatter: per block again, one returning atomic per (block, tile)
+//     reserves a contiguous run of the tile, and an LDS counting sort of the
+//     block's particles by (tile, cell) places them in their runs in cell
+//     order.
+// A destination tile is thus a concatenation of cell-sorted runs, one per
+// source block that sends particles into it (mostly one or two).  No atomic
+// is taken per cell, so the cost does not grow with how far the particles
+// have drifted since the last sort.
 struct TileOrder {
   int ntx, nty;  // tiles along x, y
 };
+// key of a cell: tile index (tiles x fastest) * 64 + cell inside the tile (x fastest)
 __device__ __forceinline__ int tiled_key(int i, int j, int k, TileOrder o) {
   return (((k >> 2) * o.nty + (j >> 2)) * o.ntx + (i >> 2)) * 64 + ((k & 3) * 4 + (j & 3)) * 4 +
          (i & 3);
@@ -1420,7 +1432,7 @@ __device__ __forceinline__ int sort_key(const PartF32R& P, int p, TileOrder o) {
 
 // Runs of equal keys in neighbouring lanes (the input is nearly sorted): each
 // lane learns the lane that heads its run, its rank in the run and, for the
-// head, the run length, so one atomic serves the whole run.
+// head, the run length, so one operation serves the whole run.
 struct Run {
   int head, rank, len;
 };
@@ -1438,76 +1450,224 @@ __device__ __forceinline__ Run lane_run(int key) {
   return r;
 }
 
-template <typename PT>
-__global__ void sort_hist_kernel(PT P, int* __restrict__ cnt, int* __restrict__ hist, TileOrder o) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int key = p < cnt[0] ? sort_key(P, p, o) : -1;
-  const Run r = lane_run(key);
-  if (key >= 0 && r.rank == 0) atomicAdd(&hist[key], r.len);
+// Each wave takes kSortRounds rounds of 64 consecutive slots (a block covers
+// kSortSlots slots); every load of a thread is issued before its first atomic.
+constexpr int kSortRounds = 4;
+constexpr int kSortSlots = 4 * 64 * kSortRounds;
+constexpr int kTable = 64;  // destination tiles per block held in LDS (open addressing)
+
+__device__ __forceinline__ int sort_first_slot() {
+  return blockIdx.x * kSortSlots + (threadIdx.x >> 6) * 64 * kSortRounds + (threadIdx.x & 63);
 }
 
-__device__ __forceinline__ void copy_particle(const PartF64& a, int i, const PartF64& b, int j) {
-  b.x[j] = a.x[i];
-  b.y[j] = a.y[i];
-  b.z[j] = a.z[i];
-  b.vx[j] = a.vx[i];
-  b.vy[j] = a.vy[i];
-  b.vz[j] = a.vz[i];
-  b.id[j] = a.id[i];
-}
-__device__ __forceinline__ void copy_particle(const PartF32R& a, int i, const PartF32R& b, int j) {
-  b.cell[j] = a.cell[i];
-  b.ox[j] = a.ox[i];
-  b.oy[j] = a.oy[i];
-  b.oz[j] = a.oz[i];
-  b.vx[j] = a.vx[i];
-  b.vy[j] = a.vy[i];
-  b.vz[j] = a.vz[i];
-  b.id[j] = a.id[i];
+// the LDS table slot of tile t, inserted if new; -1 when the table is full
+__device__ __forceinline__ int table_slot(int* s_tile, int t) {
+  const unsigned h = ((unsigned)t * 2654435761u) >> 26;
+  for (int probe = 0; probe < kTable; ++probe) {
+    const int i = (int)((h + probe) & (kTable - 1));
+    const int old = atomicCAS(&s_tile[i], -1, t);
+    if (old == -1 || old == t) return i;
+  }
+  return -1;
 }
 
 template <typename PT>
-__global__ void sort_scatter_kernel(PT src, PT dst, const int* __restrict__ cnt,
-                                    int* __restrict__ cursor, TileOrder o) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int key = p < cnt[0] ? sort_key(src, p, o) : -1;
-  const Run r = lane_run(key);
-  int base = 0;
-  if (key >= 0 && r.rank == 0) base = atomicAdd(&cursor[key], r.len);
-  base = __shfl(base, r.head, 64);
-  if (key >= 0) copy_particle(src, p, dst, base + r.rank);
+__global__ __launch_bounds__(256) void bin_count_kernel(PT P, const int* __restrict__ cnt,
+                                                        int* __restrict__ tcount, TileOrder o) {
+  __shared__ int s_tile[kTable], s_n[kTable];
+  if (threadIdx.x < kTable) {
+    s_tile[threadIdx.x] = -1;
+    s_n[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  const int n = cnt[0];
+  const int first = sort_first_slot();
+  int key[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int p = first + 64 * r;
+    key[r] = p < n ? sort_key(P, p, o) : -1;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int t = key[r] >= 0 ? key[r] >> 6 : -1;
+    const Run run = lane_run(t);
+    if (t >= 0 && run.rank == 0) {
+      const int sl = table_slot(s_tile, t);
+      if (sl >= 0) atomicAdd(&s_n[sl], run.len);
+      else atomicAdd(&tcount[t], run.len);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kTable && s_tile[threadIdx.x] >= 0)
+    atomicAdd(&tcount[s_tile[threadIdx.x]], s_n[threadIdx.x]);
 }
 
-// one wave per tile t <= ngrid: the tile's size rounded up to a multiple of 4
-// (0 for the padding tiles of the grid and for the end entry t = ngrid)
-__global__ void tile_size_kernel(const int* __restrict__ hist, int* __restrict__ tsize, int ntiles,
-                                 int ngrid) {
-  const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t > ngrid) return;
-  const int sum = wave_sum(t < ntiles ? hist[64 * t + lane] : 0);
-  if (lane == 0) tsize[t] = (sum + 3) & ~3;
+// one particle record in registers
+struct RecF64 {
+  double x, y, z, vx, vy, vz;
+  uint32_t id;
+};
+struct RecF32R {
+  int cell;
+  float ox, oy, oz, vx, vy, vz;
+  uint32_t id;
+};
+__device__ __forceinline__ void load_rec(const PartF64& a, int i, RecF64& r) {
+  r.x = a.x[i];
+  r.y = a.y[i];
+  r.z = a.z[i];
+  r.vx = a.vx[i];
+  r.vy = a.vy[i];
+  r.vz = a.vz[i];
+  r.id = a.id[i];
 }
-
-// one wave per tile: hist becomes the first slot of each cell; the padding
-// slots at the end of the tile are marked empty
+__device__ __forceinline__ void store_rec(const PartF64& b, int j, const RecF64& r) {
+  b.x[j] = r.x;
+  b.y[j] = r.y;
+  b.z[j] = r.z;
+  b.vx[j] = r.vx;
+  b.vy[j] = r.vy;
+  b.vz[j] = r.vz;
+  b.id[j] = r.id;
+}
+__device__ __forceinline__ int rec_key(const RecF64& r, TileOrder o) {
+  if (!(r.z >= 0.0)) return -1;
+  return tiled_key((int)floor(r.x), (int)floor(r.y), (int)floor(r.z), o);
+}
+__device__ __forceinline__ void load_rec(const PartF32R& a, int i, RecF32R& r) {
+  r.cell = a.cell[i];
+  r.ox = a.ox[i];
+  r.oy = a.oy[i];
+  r.oz = a.oz[i];
+  r.vx = a.vx[i];
+  r.vy = a.vy[i];
+  r.vz = a.vz[i];
+  r.id = a.id[i];
+}
+__device__ __forceinline__ void store_rec(const PartF32R& b, int j, const RecF32R& r) {
+  b.cell[j] = r.cell;
+  b.ox[j] = r.ox;
+  b.oy[j] = r.oy;
+  b.oz[j] = r.oz;
+  b.vx[j] = r.vx;
+  b.vy[j] = r.vy;
+  b.vz[j] = r.vz;
+  b.id[j] = r.id;
+}
+__device__ __forceinline__ int rec_key(const RecF32R& r, TileOrder o) {
+  if (r.cell < 0) return -1;
+  return tiled_key(cell_i(r.cell), cell_j(r.cell), cell_k(r.cell), o);
+}
 template <typename PT>
-__global__ void tile_cursor_kernel(int* __restrict__ hist, const int* __restrict__ tstart, PT dst,
-                                   int ntiles) {
-  const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t >= ntiles) return;
-  const int c = hist[64 * t + lane];
-  int incl = c;
+struct RecOf;
+template <>
+struct RecOf<PartF64> {
+  using type = RecF64;
+};
+template <>
+struct RecOf<PartF32R> {
+  using type = RecF32R;
+};
+
+template <typename PT>
+__global__ __launch_bounds__(256) void bin_scatter_kernel(PT src, PT dst, const int* __restrict__ cnt,
+                                                          int* __restrict__ cursor, TileOrder o) {
+  using Rec = typename RecOf<PT>::type;
+  constexpr int kBins = kTable * 64;         // (table slot, cell in tile)
+  constexpr int kPerThread = kBins / 256;    // bins scanned per thread
+  __shared__ int s_tile[kTable], s_base[kTable];
+  __shared__ int s_bin[kBins];
+  __shared__ int s_wsum[4];
+  for (int i = threadIdx.x; i < kBins; i += 256) s_bin[i] = 0;
+  if (threadIdx.x < kTable) s_tile[threadIdx.x] = -1;
+  const int n = cnt[0];
+  const int first = sort_first_slot();
+  Rec rec[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int p = first + 64 * r;
+    if (p < n) load_rec(src, p, rec[r]);
+  }
+  __syncthreads();
+  int key[kSortRounds], slot[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    key[r] = first + 64 * r < n ? rec_key(rec[r], o) : -1;
+    const int t = key[r] >= 0 ? key[r] >> 6 : -1;
+    const Run run = lane_run(t);
+    int sl = -1;
+    if (t >= 0 && run.rank == 0) sl = table_slot(s_tile, t);
+    sl = __shfl(sl, run.head, 64);
+    slot[r] = t >= 0 ? sl : -1;
+    if (slot[r] >= 0) atomicAdd(&s_bin[slot[r] * 64 + (key[r] & 63)], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the bins in (slot, cell) order: block-local positions
+  int local[kPerThread], sum = 0;
+#pragma unroll
+  for (int b = 0; b < kPerThread; ++b) {
+    local[b] = s_bin[kPerThread * threadIdx.x + b];
+    sum += local[b];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = sum;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const int u = __shfl_up(incl, off, 64);
     if (lane >= off) incl += u;
   }
-  const int first = tstart[t];
-  hist[64 * t + lane] = first + incl - c;
-  const int pad = first + __shfl(incl, 63, 64) + lane;
-  if (pad < tstart[t + 1]) kill(dst, pad);
+  if (lane == 63) s_wsum[w] = incl;
+  __syncthreads();
+  int run = incl - sum, total = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < w) run += s_wsum[k];
+    total += s_wsum[k];
+  }
+#pragma unroll
+  for (int b = 0; b < kPerThread; ++b) {
+    s_bin[kPerThread * threadIdx.x + b] = run;
+    run += local[b];
+  }
+  __syncthreads();
+  // one reservation per (block, tile): the run of the tile this block fills
+  if (threadIdx.x < kTable && s_tile[threadIdx.x] >= 0) {
+    const int g0 = s_bin[64 * threadIdx.x];
+    const int g1 = threadIdx.x + 1 < kTable ? s_bin[64 * (threadIdx.x + 1)] : total;
+    s_base[threadIdx.x] = atomicAdd(&cursor[s_tile[threadIdx.x]], g1 - g0) - g0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    if (key[r] < 0) continue;
+    int dest;
+    if (slot[r] >= 0)
+      dest = s_base[slot[r]] + atomicAdd(&s_bin[slot[r] * 64 + (key[r] & 63)], 1);
+    else
+      dest = atomicAdd(&cursor[key[r] >> 6], 1);  // the table was full: any place in the tile
+    store_rec(dst, dest, rec[r]);
+  }
+}
+
+// t <= ngrid: the tile's size rounded up to a multiple of 4 (0 for the grid's
+// padding tiles and the end entry), scanned afterwards into the tile starts
+__global__ void tile_size_kernel(const int* __restrict__ tcount, int* __restrict__ tsize,
+                                 int ngrid) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > ngrid) return;
+  tsize[t] = t < ngrid ? (tcount[t] + 3) & ~3 : 0;
+}
+
+// every tile's cursor at its start; its padding slots marked empty
+template <typename PT>
+__global__ void tile_pad_kernel(const int* __restrict__ tcount, const int* __restrict__ tstart,
+                                int* __restrict__ cursor, PT dst, int ngrid) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ngrid) return;
+  const int s = tstart[t];
+  cursor[t] = s;
+  for (int p = s + tcount[t]; p < tstart[t + 1]; ++p) kill(dst, p);
 }
 
 // after the scatter the tiles fill [0, tstart[ngrid]) of the other buffer
@@ -1673,30 +1833,29 @@ void launch_fill_int(int* a, long n, int v, hipStream_t st) {
   hipLaunchKernelGGL(fill_int_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a, n, v);
 }
 
-long sort_keys(int nx, int ny, int nz) {
-  return (long)((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) * 64;
-}
+long sort_keys(int nx, int ny, int nz) { return 2L * tile_grid(nx, ny, nz) + 1; }
 
 template <typename PT>
 static void sort_impl(const PT& src, const PT& dst, const WorkLists& L, int* hist, int* sums,
                       long capacity, hipStream_t st) {
   const TileOrder o{L.ntx, L.nty};
-  const int ntiles = L.ntx * L.nty * L.ntz;
-  launch_fill_int(hist, 64L * ntiles, 0, st);
-  hipLaunchKernelGGL(sort_hist_kernel<PT>, dim3(nblk(capacity, 256)), dim3(256), 0, st, src, L.cnt,
-                     hist, o);
-  const int n = L.ngrid + 1;
-  hipLaunchKernelGGL(tile_size_kernel, dim3(nblk(64L * n, 256)), dim3(256), 0, st, hist, L.tstart,
-                     ntiles, L.ngrid);
+  const int ng = L.ngrid;
+  int* tcount = hist;            // [ngrid + 1]
+  int* cursor = hist + ng + 1;   // [ngrid]
+  launch_fill_int(hist, 2L * ng + 1, 0, st);
+  hipLaunchKernelGGL(bin_count_kernel<PT>, dim3(nblk(capacity, kSortSlots)), dim3(256), 0, st, src,
+                     L.cnt, tcount, o);
+  const int n = ng + 1;
+  hipLaunchKernelGGL(tile_size_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, tcount, L.tstart, ng);
   const int nb = nblk(n, kScanBlock);
   hipLaunchKernelGGL(scan_block_sums, dim3(nb), dim3(kScanBlock), 0, st, L.tstart, n, sums);
   hipLaunchKernelGGL(scan_sums_serial, dim3(1), dim3(kScanBlock), 0, st, sums, nb, L.cnt + 4);
   hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kScanBlock), 0, st, L.tstart, n, sums, L.tstart);
-  hipLaunchKernelGGL(tile_cursor_kernel<PT>, dim3(nblk(64L * ntiles, 256)), dim3(256), 0, st, hist,
-                     L.tstart, dst, ntiles);
-  hipLaunchKernelGGL(sort_scatter_kernel<PT>, dim3(nblk(capacity, 256)), dim3(256), 0, st, src,
-                     dst, L.cnt, hist, o);
-  hipLaunchKernelGGL(sort_finish_kernel, dim3(1), dim3(64), 0, st, L.cnt, L.tstart, L.ngrid);
+  hipLaunchKernelGGL(tile_pad_kernel<PT>, dim3(nblk(ng, 256)), dim3(256), 0, st, tcount, L.tstart,
+                     cursor, dst, ng);
+  hipLaunchKernelGGL(bin_scatter_kernel<PT>, dim3(nblk(capacity, kSortSlots)), dim3(256), 0, st,
+                     src, dst, L.cnt, cursor, o);
+  hipLaunchKernelGGL(sort_finish_kernel, dim3(1), dim3(64), 0, st, L.cnt, L.tstart, ng);
 }
 
 void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L, int* hist,
