@@ -17,10 +17,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
                                                uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    // each 32x32 -> 64-bit product is one multiply-add instruction
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     c0 = hi1 ^ c1 ^ k0;
     c1 = lo1;
     c2 = hi0 ^ c3 ^ k1;
@@ -29,6 +30,41 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     k1 += 0xBB67AE85u;
   }
   return make_uint4(c0, c1, c2, c3);
+}
+
+// word 0 of Philox4x32-10 for N counters (c0[q], c1, c2, c3) with one key:
+// the rounds above, interleaved over the counters so each round key is
+// formed once
+template <int N>
+__device__ __forceinline__ void philox_word0(const uint32_t* c0in, uint32_t c1, uint32_t c2,
+                                             uint32_t c3, uint32_t k0, uint32_t k1,
+                                             uint32_t* out) {
+  uint32_t a[N], b[N], c[N], d[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    a[q] = c0in[q];
+    b[q] = c1;
+    c[q] = c2;
+    d[q] = c3;
+  }
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const uint64_t p0 = (uint64_t)0xD2511F53u * a[q];
+      const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[q];
+      const uint32_t na = (uint32_t)(p1 >> 32) ^ b[q] ^ k0;
+      const uint32_t nc = (uint32_t)(p0 >> 32) ^ d[q] ^ k1;
+      b[q] = (uint32_t)p1;
+      d[q] = (uint32_t)p0;
+      a[q] = na;
+      c[q] = nc;
+    }
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = a[q];
 }
 
 // (w + 1/2) 2^-32: uniform on the open interval (0, 1)

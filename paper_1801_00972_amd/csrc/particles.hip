@@ -329,21 +329,31 @@ __device__ __forceinline__ void deposit_f64(double* __restrict__ rho, const Spec
 // parts, along x by q1 = (Q f24) >> 24 with f24 = floor(offset 2^24), then each
 // half along y, each quarter along z; integer atomics, so the sum is exact and
 // independent of order.
+// a * b for 0 <= a < 2^63, 0 <= b < 2^32 with a * b < 2^63: two 32x32 -> 64-bit
+// multiply-adds instead of a general 64-bit product
+__device__ __forceinline__ long long mul_q(long long a, uint32_t b) {
+  const unsigned long long ua = (unsigned long long)a;
+  const unsigned long long lo = (unsigned long long)(uint32_t)ua * b;
+  const unsigned long long hi = (unsigned long long)(uint32_t)(ua >> 32) * b;
+  return (long long)(lo + (hi << 32));
+}
+
 __device__ __forceinline__ void split8(long long Q, float ox, float oy, float oz,
                                        long long part[8]) {
-  const long long qx = (long long)(ox * 16777216.0f);
-  const long long qy = (long long)(oy * 16777216.0f);
-  const long long qz = (long long)(oz * 16777216.0f);
+  // offsets in [0, 1): f24 in [0, 2^24), the parts stay in [0, Q]
+  const uint32_t qx = (uint32_t)(ox * 16777216.0f);
+  const uint32_t qy = (uint32_t)(oy * 16777216.0f);
+  const uint32_t qz = (uint32_t)(oz * 16777216.0f);
   long long ax[2];
-  ax[1] = (Q * qx) >> 24;
+  ax[1] = mul_q(Q, qx) >> 24;
   ax[0] = Q - ax[1];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
-    const long long y1 = (ax[a] * qy) >> 24;
+    const long long y1 = mul_q(ax[a], qy) >> 24;
     const long long yy[2] = {ax[a] - y1, y1};
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const long long z1 = (yy[b] * qz) >> 24;
+      const long long z1 = mul_q(yy[b], qz) >> 24;
       part[a + 2 * b] = yy[b] - z1;
       part[a + 2 * b + 4] = z1;
     }
@@ -622,6 +632,36 @@ __device__ __forceinline__ void md_flush(int32_t* s_md, int* s_nmd, int* s_mdbas
   __syncthreads();  // the stage is free again
 }
 
+// one run of same-cell charge parts (magnitudes) into the window, or, outside
+// it, with the species' sign straight to the global mesh
+__device__ __forceinline__ void deposit_run(const Tile& tile, long long* s_rho,
+                                            long long* __restrict__ rho, const SpeciesStep& S,
+                                            int c, long long acc[8]) {
+  const int ai = cell_i(c), aj = cell_j(c), ak = cell_k(c);
+  const int lb = tile_cell(tile, ai, aj, ak, S.nx, S.ny);
+  if (lb < 0 && S.isign < 0) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = -acc[t];
+  }
+  corner_add<long long>(tile, lb, s_rho, rho, S, ai, aj, ak, acc);
+}
+
+// whether any cell of the window lies in the bounding box of the MD cubes
+// (periodic in x, y)
+__device__ __forceinline__ bool window_meets_md(const Tile& w, const MdTables& md, int nx, int ny) {
+  if (md.n_grains == 0) return false;
+  if (!w.on) return true;
+  const int wx = w.tx - 1, wy = w.ty - 1;  // cells of the window per axis
+  int dx = (w.x0 - md.bx0) % nx;
+  if (dx < 0) dx += nx;
+  int dy = (w.y0 - md.by0) % ny;
+  if (dy < 0) dy += ny;
+  const bool mx = wx >= nx || dx < md.bsx || dx + wx > nx;
+  const bool my = wy >= ny || dy < md.bsy || dy + wy > ny;
+  const bool mz = w.k0 < md.bz0 + md.bsz && md.bz0 < w.k0 + w.tz - 1;
+  return mx && my && mz;
+}
+
 // ---------------------------------------------------------------- push, FP32R
 // One block streams the slots of its tile, 1024 per pass, four consecutive
 // slots per thread with 16-byte loads and stores, and updates them in place:
@@ -640,7 +680,7 @@ struct PushSmemF32 {
   long long rho[kWinF32];
   unsigned tally[TL_N];
   int nmd, ncoll, nout, mdbase;
-  int32_t md[kMdStage];
+  int32_t md[2 * kChunk];  // MD slots of up to two passes
 };
 
 template <bool kMove>
@@ -669,9 +709,13 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
     sm.ncoll = 0;
     sm.nout = 0;
   }
+  // MD cubes near the window: only then does every particle need the lookup
+  const bool md_near = window_meets_md(tile, md, S.nx, S.ny);
   __syncthreads();
+  // event counts per thread, one byte per status, added up every 32 passes
+  unsigned long long packed = 0ull;
   int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0, n_out = 0;
-  for (int base = beg; base < end; base += kChunk) {
+  for (int base = beg, pass = 0; base < end; base += kChunk, ++pass) {
     // tile ranges are multiples of 4 slots: a thread's four slots are all in
     // the tile or all beyond it
     const int p0 = base + kPPT * (int)threadIdx.x;
@@ -708,11 +752,14 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
         continue;
       }
       int ci = cell_i(cell[q]), cj = cell_j(cell[q]), ck = cell_k(cell[q]);
-      if (md_lookup(md, S.nx, S.ny, ci, cj, ck) != 0u) {
-        st[q] = ST_MD;
-        continue;
-      }
+      // (a cached cell has passed both tests already)
       const int lb = cell[q] == cached ? 0 : tile_cell(tile, ci, cj, ck, S.nx, S.ny);
+      if ((md_near && cell[q] != cached) || lb < 0) {
+        if (md_lookup(md, S.nx, S.ny, ci, cj, ck) != 0u) {
+          st[q] = ST_MD;
+          continue;
+        }
+      }
       if (lb < 0) {
         // outside the window: left for the outlier kernel (no global gather
         // here, so no wave waits on a dependent memory round trip)
@@ -730,25 +777,27 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
         }
       }
       st[q] = push_one_f32(S, ec, o[q], v[q], ci, cj, ck);
-      if (st[q] == ST_ALIVE) {
-        cell[q] = pack_cell(ci, cj, ck);
-        const uint4 r = philox4x32_10(id[q], *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
-        cand[q] = (uint64_t)r.x < S.T_null;
-      } else {
-        cell[q] = -1;
-      }
+      cell[q] = st[q] == ST_ALIVE ? pack_cell(ci, cj, ck) : -1;
     }
     if (kMove) {
+      // collision candidates of the survivors: word 0 of Philox(id, k, COLL, s)
+      uint32_t w0[kPPT];
+      philox_word0<kPPT>(id, *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1, w0);
 #pragma unroll
       for (int q = 0; q < kPPT; ++q) {
+        cand[q] = st[q] == ST_ALIVE && (uint64_t)w0[q] < S.T_null;
         chunk_append(st[q] == ST_MD, sm.md, &sm.nmd, p0 + q);
         chunk_append(cand[q], L.coll + beg, &sm.ncoll, p0 + q);
         chunk_append(st[q] == ST_OUT, L.out + beg, &sm.nout, p0 + q);
-        n_out += st[q] == ST_OUT;
-        n_w0 += st[q] == ST_WALL0;
-        n_w1 += st[q] == ST_WALL1;
-        n_bad += st[q] == ST_BAD;
-        n_md += st[q] == ST_MD;
+        packed += 1ull << (8 * st[q]);
+      }
+      if ((pass & 31) == 31) {
+        n_w0 += (int)((packed >> (8 * ST_WALL0)) & 255u);
+        n_w1 += (int)((packed >> (8 * ST_WALL1)) & 255u);
+        n_bad += (int)((packed >> (8 * ST_BAD)) & 255u);
+        n_md += (int)((packed >> (8 * ST_MD)) & 255u);
+        n_out += (int)((packed >> (8 * ST_OUT)) & 255u);
+        packed = 0ull;
       }
       if (have) {
         reinterpret_cast<int4*>(P.cell)[g4] = make_int4(cell[0], cell[1], cell[2], cell[3]);
@@ -773,31 +822,26 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
 #pragma unroll
         for (int t = 0; t < 8; ++t) acc[t] += part[t];
       } else {
-        if (acc_cell >= 0) {
-          const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
-#pragma unroll
-          for (int t = 0; t < 8; ++t) acc[t] *= S.isign;
-          corner_add<long long>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), sm.rho, rho, S, ai,
-                                aj, ak, acc);
-        }
+        if (acc_cell >= 0) deposit_run(tile, sm.rho, rho, S, acc_cell, acc);
         acc_cell = cell[q];
 #pragma unroll
         for (int t = 0; t < 8; ++t) acc[t] = part[t];
       }
     }
-    if (acc_cell >= 0) {
-      const int ai = cell_i(acc_cell), aj = cell_j(acc_cell), ak = cell_k(acc_cell);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) acc[t] *= S.isign;
-      corner_add<long long>(tile, tile_cell(tile, ai, aj, ak, S.nx, S.ny), sm.rho, rho, S, ai, aj,
-                            ak, acc);
-    }
-    if (kMove) {
+    if (acc_cell >= 0) deposit_run(tile, sm.rho, rho, S, acc_cell, acc);
+    // the MD stage holds two passes: flush after every second pass (a
+    // block-uniform decision) and after the last
+    if (kMove && (pass & 1) && base + kChunk < end) {
       __syncthreads();
       md_flush(sm.md, &sm.nmd, &sm.mdbase, L);
     }
   }
   if (kMove) {
+    n_w0 += (int)((packed >> (8 * ST_WALL0)) & 255u);
+    n_w1 += (int)((packed >> (8 * ST_WALL1)) & 255u);
+    n_bad += (int)((packed >> (8 * ST_BAD)) & 255u);
+    n_md += (int)((packed >> (8 * ST_MD)) & 255u);
+    n_out += (int)((packed >> (8 * ST_OUT)) & 255u);
     tally_add(sm.tally, TL_W0, n_w0);
     tally_add(sm.tally, TL_W1, n_w1);
     tally_add(sm.tally, TL_BAD, n_bad);
@@ -806,11 +850,12 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
     tally_add(sm.tally, TL_FALL, n_out);
   }
   __syncthreads();
+  // the window holds the magnitudes; the species' sign is applied here
   for (int t = threadIdx.x; t < vol; t += kBlock) {
     const long long val = sm.rho[t];
     if (val != 0)
       atomicAdd((unsigned long long*)&rho[tile_node(tile, t, rtx, rtxy, S.nx, S.ny, S.nxy)],
-                (unsigned long long)val);
+                (unsigned long long)(S.isign < 0 ? -val : val));
   }
   if (kMove) {
     if (threadIdx.x == 0) {
@@ -818,11 +863,13 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
       L.out_cnt[tidx] = sm.nout;
     }
     tally_store(sm.tally, L.tally + (long)TL_N * tidx);
+    md_flush(sm.md, &sm.nmd, &sm.mdbase, L);
   }
 }
 
+// (at most 128 VGPRs: four waves per SIMD, which the streaming needs)
 template <bool kMove>
-__global__ __launch_bounds__(kBlock) void push_f32r_kernel(PartF32R P,
+__global__ __launch_bounds__(kBlock, 4) void push_f32r_kernel(PartF32R P,
                                                            const float4* __restrict__ E,
                                                            long long* __restrict__ rho, MdTables md,
                                                            SpeciesStep S, WorkLists L) {
@@ -835,7 +882,7 @@ __global__ __launch_bounds__(kBlock) void push_f32r_kernel(PartF32R P,
 // ensemble: work item i belongs to descriptor d with start[d] <= i < start[d+1]
 // (each descriptor has a multiple of 8 tiles, so the XCD remapping stays a
 // permutation per descriptor); blocks stride over the items.
-__global__ __launch_bounds__(kBlock) void push_batch_f32r_kernel(const PushDescF32* __restrict__ descs,
+__global__ __launch_bounds__(kBlock, 4) void push_batch_f32r_kernel(const PushDescF32* __restrict__ descs,
                                                                  const int32_t* __restrict__ start,
                                                                  int ndesc) {
   __shared__ PushSmemF32 sm;
