@@ -31,6 +31,33 @@ RECORD_BYTES = {"fp32r": 32, "fp64": 52}      # per particle: read once, written
 NODE_BYTES = {"fp32r": 16 + 8, "fp64": 32 + 8}  # per node and step: E read, rho written
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_push_f32r_full_64x64x256_ppc32.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_00972_amd", "csrc", f)
+                  for f in ("particles.hip", "device_common.hpp", "pic_types.hpp")]
+
+
+def traffic_per_particle_step(kernel):
+    """HBM bytes per particle-step of the push kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE record, if it was taken on the current
+    kernel sources (else None)."""
+    import hashlib
+    if kernel != "push_fp32r" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    rec = None
+    for line in open(TRAFFIC_PROFILE):
+        if line.startswith("traffic-record:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["fetch_bytes_per_particle_step"] + rec["write_bytes_per_particle_step"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -103,6 +130,9 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
     nn = sum(w["nx"] * w["ny"] * (w["nz"] + 1) for w in wls)
     alg_bytes = particle_steps * 2 * RECORD_BYTES[prec] + steps * nn * NODE_BYTES[prec]
     achieved = alg_bytes / (push_ms * 1e-3) / 1e9 if push_ms > 0 else 0.0
+    kernel = "push_batch_f32r" if tuning.get("batch_push") else "push_" + prec
+    tpps = traffic_per_particle_step(kernel)
+    traffic = tpps * particle_steps / max(push_n, 1) if tpps else None
     res = dict(
         value=tuned_ps / (t3 - t2),
         ms_per_step=1e3 * (t3 - t2) / steps,
@@ -118,9 +148,10 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
         lists_ms_per_step=lists_ms / steps,
         sort_ms_total=sort_ms, sort_launches=sort_n,
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                      kernel=("push_batch_f32r" if tuning.get("batch_push") else "push_" + prec),
-                      bytes_per_launch=alg_bytes / max(push_n, 1)),
+                      frac=round(achieved / HBM_PEAK_GBS, 4),
+                      traffic=round(traffic) if traffic else None,
+                      traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, calibrated)",
+                      kernel=kernel, bytes_per_launch=alg_bytes / max(push_n, 1)),
         refine_residual=sim.counters(0)["refine_residual"] if prec == "fp32r" else None,
         tile_fallback_blocks=fall1 - fall0,
         md_particle_steps=md1 - md0,
