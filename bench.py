@@ -185,7 +185,7 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
     return dict(bytes_per_copy=2 * nbytes, ms=ms, GBs=2 * nbytes / (ms * 1e-3) / 1e9)
 
 
-def cpu_baseline(wl, steps=2):
+def cpu_baseline(wl, steps=6):
     """The oracle, as it stands, on the same workload: loading untimed, then a
     bounded number of full steps timed on the host cores."""
     import oracle
