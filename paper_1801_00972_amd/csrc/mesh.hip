@@ -55,6 +55,84 @@ __device__ __forceinline__ C cmi(C a, bool fwd) {
   return r;
 }
 
+// one radix-R butterfly of a Stockham stage: legs x[k xs] in, y[j ys] out,
+// twiddled by w_N^{j p s}; R is a compile-time constant so the legs stay in
+// registers
+template <int R, typename C>
+__device__ __forceinline__ void butterfly(const C* x, C* y, int xs, int ys, int N, int p, int s,
+                                          const C* __restrict__ tw, bool forward) {
+  C a[R], out[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) a[k] = x[k * xs];
+  if constexpr (R == 2) {
+    out[0] = cadd(a[0], a[1]);
+    out[1] = csub(a[0], a[1]);
+  } else if constexpr (R == 4) {
+    const C t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    const C t2 = cadd(a[1], a[3]), t3 = cmi(csub(a[1], a[3]), forward);
+    out[0] = cadd(t0, t2);
+    out[1] = cadd(t1, t3);
+    out[2] = csub(t0, t2);
+    out[3] = csub(t1, t3);
+  } else {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      C acc = a[0];
+#pragma unroll
+      for (int k = 1; k < R; ++k) {
+        C w = tw[((j * k) % R) * (N / R)];
+        if (forward) w.y = -w.y;
+        acc = cadd(acc, cmul(a[k], w));
+      }
+      out[j] = acc;
+    }
+  }
+  y[0] = out[0];
+#pragma unroll
+  for (int j = 1; j < R; ++j) {
+    C w = tw[(long)j * p * s % N];
+    if (forward) w.y = -w.y;
+    y[j * ys] = cmul(out[j], w);
+  }
+}
+
+// the stages of one transform of L lines of length N held in LDS; element e
+// of line l at buf[l * ls + e * es]; returns the buffer that holds the result
+template <typename C>
+__device__ C* fft_stages(C* src, C* dst, int N, int L, int ls, int es, const int* fac, int nfac,
+                         const C* __restrict__ tw, bool forward) {
+  // neighbouring threads take neighbouring elements of a line when elements
+  // are contiguous, else neighbouring lines (no LDS bank conflicts either way)
+  const bool lfast = es != 1;
+  int n = N, s = 1;
+  for (int f = 0; f < nfac; ++f) {
+    const int r = fac[f];
+    const int m = n / r;
+    const int per_line = N / r;
+    for (int b = threadIdx.x; b < L * per_line; b += blockDim.x) {
+      const int l = lfast ? b % L : b / per_line;
+      const int t = lfast ? b / L : b - l * per_line;
+      const int p = t / s, q = t - p * s;
+      const C* x = src + l * ls + (q + s * p) * es;
+      C* y = dst + l * ls + (q + s * r * p) * es;
+      const int xs = s * m * es, ys = s * es;
+      switch (r) {
+        case 2: butterfly<2>(x, y, xs, ys, N, p, s, tw, forward); break;
+        case 3: butterfly<3>(x, y, xs, ys, N, p, s, tw, forward); break;
+        case 4: butterfly<4>(x, y, xs, ys, N, p, s, tw, forward); break;
+        default: butterfly<5>(x, y, xs, ys, N, p, s, tw, forward); break;
+      }
+    }
+    __syncthreads();
+    C* tmp = src;
+    src = dst;
+    dst = tmp;
+    n = m;
+    s *= r;
+  }
+  return src;
+}
+
 // ---------------------------------------------------------------- FFT lines
 // One block transforms L lines of length N held in LDS, ping-ponging between
 // two buffers through the Stockham stages (decimation in frequency):
@@ -107,57 +185,7 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(FftGeom g, const cplx<T>
   }
   __syncthreads();
 
-  C* src = buf0;
-  C* dst = buf1;
-  int n = N, s = 1;
-  for (int f = 0; f < g.nfac; ++f) {
-    const int r = g.fac[f];
-    const int m = n / r;
-    const int per_line = N / r;  // = m * s butterflies per line
-    for (int b = threadIdx.x; b < L * per_line; b += blockDim.x) {
-      const int l = b / per_line;
-      const int t = b - l * per_line;
-      const int p = t / s, q = t - p * s;
-      const C* x = src + l * N + q + s * p;
-      C* y = dst + l * N + q + s * r * p;
-      C a[5];
-      for (int k = 0; k < r; ++k) a[k] = x[s * k * m];
-      C out[5];
-      if (r == 2) {
-        out[0] = cadd(a[0], a[1]);
-        out[1] = csub(a[0], a[1]);
-      } else if (r == 4) {
-        const C t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
-        const C t2 = cadd(a[1], a[3]), t3 = cmi(csub(a[1], a[3]), forward != 0);
-        out[0] = cadd(t0, t2);
-        out[1] = cadd(t1, t3);
-        out[2] = csub(t0, t2);
-        out[3] = csub(t1, t3);
-      } else {
-        for (int j = 0; j < r; ++j) {
-          C acc = a[0];
-          for (int k = 1; k < r; ++k) {
-            C w = tw[((j * k) % r) * (N / r)];
-            if (forward) w.y = -w.y;
-            acc = cadd(acc, cmul(a[k], w));
-          }
-          out[j] = acc;
-        }
-      }
-      y[0] = out[0];
-      for (int j = 1; j < r; ++j) {
-        C w = tw[(long)j * p * s % N];
-        if (forward) w.y = -w.y;
-        y[s * j] = cmul(out[j], w);
-      }
-    }
-    __syncthreads();
-    C* tmp = src;
-    src = dst;
-    dst = tmp;
-    n = m;
-    s *= r;
-  }
+  C* src = fft_stages(buf0, buf1, N, L, N, 1, g.fac, g.nfac, tw, forward != 0);
 
   for (int idx = threadIdx.x; idx < L * N; idx += blockDim.x) {
     const int l = e_fast ? idx / N : idx % L;
@@ -172,6 +200,165 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(FftGeom g, const cplx<T>
           (double)v.x * out_scale + V * (double)(plane + 1) / (double)nz;
     } else {
       rout[off] += (double)v.x * out_scale;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- FFT planes
+// One block transforms one whole plane (nx * ny points) in LDS: the x lines,
+// then the y lines, with the same Stockham stages as above on strided lines,
+// so a 2-D transform costs one read and one write of the plane.  Used when
+// two plane buffers fit in LDS.
+struct Fft2Geom {
+  int nx, ny;
+  int nfx, fx[12];
+  int nfy, fy[12];
+};
+
+constexpr int kPlaneThreads = 1024;
+
+template <typename T, int IN, int OUT>
+__global__ __launch_bounds__(kPlaneThreads) void fft_plane_kernel(Fft2Geom g, const cplx<T>* __restrict__ tw_x,
+                                                        const cplx<T>* __restrict__ tw_y,
+                                                        int forward, cplx<T>* __restrict__ work,
+                                                        const double* __restrict__ rin,
+                                                        double in_scale, double* __restrict__ rout,
+                                                        double out_scale, RfDrive rf, int nz) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  const int nx = g.nx, ny = g.ny, np = nx * ny;
+  C* b0 = reinterpret_cast<C*>(smem_raw);
+  C* b1 = b0 + np;
+  const int plane = blockIdx.x;
+  const long pbase = (long)plane * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    C v;
+    if (IN == IN_REAL) {
+      v.x = (T)(rin[pbase + i] * in_scale);
+      v.y = (T)0;
+    } else {
+      v = work[pbase + i];
+    }
+    b0[i] = v;
+  }
+  __syncthreads();
+  C* res;
+  if (forward) {  // x lines (rows, contiguous), then y lines (columns)
+    res = fft_stages(b0, b1, nx, ny, nx, 1, g.fx, g.nfx, tw_x, true);
+    C* other = res == b0 ? b1 : b0;
+    res = fft_stages(res, other, ny, nx, 1, nx, g.fy, g.nfy, tw_y, true);
+  } else {  // y lines, then x lines
+    res = fft_stages(b0, b1, ny, nx, 1, nx, g.fy, g.nfy, tw_y, false);
+    C* other = res == b0 ? b1 : b0;
+    res = fft_stages(res, other, nx, ny, nx, 1, g.fx, g.nfx, tw_x, false);
+  }
+  const double V = OUT == OUT_REAL_LIFT ? rf_voltage(rf) : 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const C v = res[i];
+    if (OUT == OUT_COMPLEX) {
+      work[pbase + i] = v;
+    } else if (OUT == OUT_REAL_LIFT) {
+      // interior plane k = plane + 1 of phi
+      rout[pbase + np + i] = (double)v.x * out_scale + V * (double)(plane + 1) / (double)nz;
+    } else {
+      rout[pbase + i] += (double)v.x * out_scale;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- tridiagonal, chunked
+// The two sweeps of the tridiagonal solve as first-order affine recurrences,
+// each split into kTriChunks chunks along z per mode:
+//   forward  y_k = f_k (d_k - y_{k-1})   = a_k y_{k-1} + f_k d_k,  a_k = -f_k,
+//   backward x_k = y_k - f_k x_{k+1}     = a_k x_{k+1} + y_k.
+// Each thread composes the affine map of its chunk, the maps of the earlier
+// chunks give its incoming value (LDS), and the chunk is re-run from it.  The
+// recursion depth drops from K to K / kTriChunks + kTriChunks.
+constexpr int kTriChunks = 16;
+constexpr int kTriModes = 16;  // modes per block (16 x 16 = 256 threads)
+
+template <typename T, int kTriMaxLen>  // rows per chunk held in registers
+__global__ __launch_bounds__(256) void thomas_chunked_kernel(cplx<T>* __restrict__ d,
+                                                             const T* __restrict__ inv, int K,
+                                                             long modes) {
+  using C = cplx<T>;
+  __shared__ T s_A[kTriChunks][kTriModes];
+  __shared__ C s_B[kTriChunks][kTriModes];
+  const int lm = threadIdx.x % kTriModes, c = threadIdx.x / kTriModes;
+  const long mn = (long)blockIdx.x * kTriModes + lm;
+  const bool on = mn < modes;
+  const int len = (K + kTriChunks - 1) / kTriChunks;
+  const int k0 = c * len;
+  const int k1 = min(K, k0 + len);
+  C v[kTriMaxLen];
+  T f[kTriMaxLen];
+#pragma unroll
+  for (int i = 0; i < kTriMaxLen; ++i) {
+    if (on && i < k1 - k0) {
+      v[i] = d[(long)(k0 + i) * modes + mn];
+      f[i] = inv[(long)(k0 + i) * modes + mn];
+    }
+  }
+  // forward sweep: the chunk's map y_out = A y_in + B
+  T A = (T)1;
+  C B;
+  B.x = B.y = (T)0;
+#pragma unroll
+  for (int i = 0; i < kTriMaxLen; ++i) {
+    if (i < k1 - k0) {
+      A = -f[i] * A;
+      B.x = f[i] * (v[i].x - B.x);
+      B.y = f[i] * (v[i].y - B.y);
+    }
+  }
+  s_A[c][lm] = A;
+  s_B[c][lm] = B;
+  __syncthreads();
+  C y;
+  y.x = y.y = (T)0;
+  for (int cc = 0; cc < c; ++cc) {
+    const T a = s_A[cc][lm];
+    const C b = s_B[cc][lm];
+    y.x = a * y.x + b.x;
+    y.y = a * y.y + b.y;
+  }
+#pragma unroll
+  for (int i = 0; i < kTriMaxLen; ++i) {
+    if (i < k1 - k0) {
+      y.x = f[i] * (v[i].x - y.x);
+      y.y = f[i] * (v[i].y - y.y);
+      v[i] = y;
+    }
+  }
+  __syncthreads();
+  // backward sweep from the chunk's end: x_start = A x_next + B
+  A = (T)1;
+  B.x = B.y = (T)0;
+#pragma unroll
+  for (int i = kTriMaxLen - 1; i >= 0; --i) {
+    if (i < k1 - k0) {
+      A = -f[i] * A;
+      B.x = v[i].x - f[i] * B.x;
+      B.y = v[i].y - f[i] * B.y;
+    }
+  }
+  s_A[c][lm] = A;
+  s_B[c][lm] = B;
+  __syncthreads();
+  C x;
+  x.x = x.y = (T)0;
+  for (int cc = kTriChunks - 1; cc > c; --cc) {
+    const T a = s_A[cc][lm];
+    const C b = s_B[cc][lm];
+    x.x = a * x.x + b.x;
+    x.y = a * x.y + b.y;
+  }
+#pragma unroll
+  for (int i = kTriMaxLen - 1; i >= 0; --i) {
+    if (i < k1 - k0) {
+      x.x = v[i].x - f[i] * x.x;
+      x.y = v[i].y - f[i] * x.y;
+      if (on) d[(long)(k0 + i) * modes + mn] = x;
     }
   }
 }
@@ -317,6 +504,52 @@ __global__ void grain_rhs_kernel(const unsigned long long* __restrict__ counts, 
       const double add = mode == 1 ? scale * (double)(net * part[t]) : scale * (double)net * w[t];
       b[n[t] - plane] += add;
     }
+  }
+}
+
+// The same in parallel for up to kGrainPairs / 8 grains: thread p takes
+// corner t = p % 8 of grain g = p / 8; the first (grain, corner) pair of each
+// node adds, in (grain, corner) order, every contribution to that node, so the
+// sums are those of the serial loop above, bit for bit.
+constexpr int kGrainPairs = 2048;
+__global__ __launch_bounds__(256) void grain_rhs_par_kernel(
+    const unsigned long long* __restrict__ counts, const double* gpos, int ng, int nx, int ny,
+    int nz, double we, double* __restrict__ Q, double* __restrict__ b, double scale, int mode,
+    long long Qp) {
+  __shared__ long s_node[kGrainPairs];
+  __shared__ double s_add[kGrainPairs];
+  const long plane = (long)nx * ny;
+  const int npair = 8 * ng;
+  for (int p = threadIdx.x; p < npair; p += blockDim.x) {
+    const int g = p >> 3, t = p & 7;
+    const long long net = (long long)counts[2 * g + 1] - (long long)counts[2 * g + 0];
+    if (t == 0) Q[g] = (double)net * we;
+    long n[8];
+    double w[8];
+    float off[3];
+    int cell[3];
+    grain_nodes(gpos, g, nx, ny, n, w, off, cell);
+    long long part[8];
+    if (mode == 1) {
+      const double X = gpos[3 * g], Y = gpos[3 * g + 1], Z = gpos[3 * g + 2];
+      grain_split(Qp, X - floor(X), Y - floor(Y), Z - floor(Z), part);
+    }
+    const long k = n[t] / plane;
+    const bool in = b && net != 0 && k >= 1 && k <= nz - 1;
+    s_node[p] = in ? n[t] : -1;
+    s_add[p] = mode == 1 ? scale * (double)(net * part[t]) : scale * (double)net * w[t];
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < npair; p += blockDim.x) {
+    const long node = s_node[p];
+    if (node < 0) continue;
+    bool first = true;
+    for (int q = 0; q < p && first; ++q) first = s_node[q] != node;
+    if (!first) continue;
+    double v = b[node - plane];
+    for (int q = p; q < npair; ++q)
+      if (s_node[q] == node) v += s_add[q];
+    b[node - plane] = v;
   }
 }
 
@@ -589,6 +822,55 @@ static void fft_launch(const FftGeom& g, int planes, const void* tw, int forward
                        lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
 }
 
+// 2-D plane transforms when two plane buffers fit in 64 KB of LDS
+constexpr size_t kPlaneLds = 65536;
+
+template <typename T>
+static void fft_plane_launch(const FftPlanHost& P, int nx, int ny, int planes, const void* tw_x,
+                             const void* tw_y, int forward, int in_mode, int out_mode, void* work,
+                             const double* rin, double* rout, double out_scale, RfDrive rf, int nz,
+                             hipStream_t st) {
+  using C = cplx<T>;
+  Fft2Geom g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nfx = P.nfac_x;
+  g.nfy = P.nfac_y;
+  for (int i = 0; i < 12; ++i) {
+    g.fx[i] = P.fac_x[i];
+    g.fy[i] = P.fac_y[i];
+  }
+  const size_t lds = 2 * sizeof(C) * (size_t)nx * ny;
+  const C* tx = (const C*)tw_x;
+  const C* ty = (const C*)tw_y;
+  C* w = (C*)work;
+  if (in_mode == IN_REAL)
+    hipLaunchKernelGGL((fft_plane_kernel<T, IN_REAL, OUT_COMPLEX>), dim3(planes), dim3(kPlaneThreads), lds, st,
+                       g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
+  else if (out_mode == OUT_REAL_LIFT)
+    hipLaunchKernelGGL((fft_plane_kernel<T, IN_COMPLEX, OUT_REAL_LIFT>), dim3(planes),
+                       dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
+  else
+    hipLaunchKernelGGL((fft_plane_kernel<T, IN_COMPLEX, OUT_REAL_ACCUM>), dim3(planes),
+                       dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
+}
+
+template <typename T>
+static void tridiag_launch(void* work, const void* inv, int K, long modes, hipStream_t st) {
+  using C = cplx<T>;
+  const int len = (K + kTriChunks - 1) / kTriChunks;
+  const int blocks = (int)((modes + kTriModes - 1) / kTriModes);
+  if (len <= 16)
+    hipLaunchKernelGGL((thomas_chunked_kernel<T, 16>), dim3(blocks), dim3(256), 0, st, (C*)work,
+                       (const T*)inv, K, modes);
+  else if (len <= 32)
+    hipLaunchKernelGGL((thomas_chunked_kernel<T, 32>), dim3(blocks), dim3(256), 0, st, (C*)work,
+                       (const T*)inv, K, modes);
+  else
+    hipLaunchKernelGGL(thomas_kernel<T>, dim3(nb256(modes)), dim3(256), 0, st, (C*)work,
+                       (const T*)inv, K, modes);
+}
+
 // one FFT + tridiagonal + inverse FFT solve of A psi = b (T = double or float);
 // out_mode OUT_REAL_LIFT writes phi (with the lift), OUT_REAL_ACCUM adds to psi
 template <typename T>
@@ -597,13 +879,20 @@ static void solve_once(const FftPlanHost& P, int nx, int ny, int nz, const doubl
                        double* out, RfDrive rf, hipStream_t st) {
   const long plane = (long)nx * ny;
   const int K = nz - 1;
+  if (2 * sizeof(cplx<T>) * (size_t)plane <= kPlaneLds) {
+    fft_plane_launch<T>(P, nx, ny, K, tw_x, tw_y, 1, IN_REAL, OUT_COMPLEX, work, b, nullptr, 0.0,
+                        rf, nz, st);
+    tridiag_launch<T>(work, inv, K, plane, st);
+    fft_plane_launch<T>(P, nx, ny, K, tw_x, tw_y, 0, IN_COMPLEX, out_mode, work, nullptr, out,
+                        1.0 / (double)plane, rf, nz, st);
+    return;
+  }
   const FftGeom gx = make_geom(P, true, nx, ny, plane);
   const FftGeom gy = make_geom(P, false, nx, ny, plane);
   fft_launch<T>(gx, K, tw_x, 1, IN_REAL, OUT_COMPLEX, work, b, 1.0, nullptr, 0.0, rf, nz, st);
   fft_launch<T>(gy, K, tw_y, 1, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, rf, nz,
                 st);
-  hipLaunchKernelGGL(thomas_kernel<T>, dim3(nb256(plane)), dim3(256), 0, st, (cplx<T>*)work,
-                     (const T*)inv, K, plane);
+  tridiag_launch<T>(work, inv, K, plane, st);
   fft_launch<T>(gy, K, tw_y, 0, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, rf, nz,
                 st);
   fft_launch<T>(gx, K, tw_x, 0, IN_COMPLEX, out_mode, work, nullptr, 0.0, out,
@@ -660,8 +949,12 @@ void launch_grain_rhs(const unsigned long long* counts, const double* gpos, int 
                       int nz, double we, double* Q, double* b, double scale, int mode,
                       long long Qp, hipStream_t st) {
   if (ng <= 0) return;
-  hipLaunchKernelGGL(grain_rhs_kernel, dim3(1), dim3(64), 0, st, counts, gpos, ng, nx, ny, nz, we,
-                     Q, b, scale, mode, Qp);
+  if (8 * ng <= kGrainPairs)
+    hipLaunchKernelGGL(grain_rhs_par_kernel, dim3(1), dim3(256), 0, st, counts, gpos, ng, nx, ny,
+                       nz, we, Q, b, scale, mode, Qp);
+  else
+    hipLaunchKernelGGL(grain_rhs_kernel, dim3(1), dim3(64), 0, st, counts, gpos, ng, nx, ny, nz,
+                       we, Q, b, scale, mode, Qp);
 }
 
 void launch_unit_rhs(const double* gpos, int g, int nx, int ny, int nz, double scale, double* b,
