@@ -16,6 +16,8 @@ struct FftPlanHost {
 // particles: arrays binned by 4x4x4-cell tile and updated in place (see
 // WorkLists); one push block per tile, the grid padded to a multiple of 8
 int tile_grid(int nx, int ny, int nz);      // tiles rounded up to a multiple of 8
+// blocks of the MD kernel; each owns a tally row after the ngrid tile rows
+constexpr int kMdTallyRows = 4096;
 long sort_keys(int nx, int ny, int nz);     // ints of sort workspace (tile counts and cursors)
 // the streaming kernel of one species (gather, push, walls, candidate test, deposit)
 void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
@@ -34,6 +36,8 @@ void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTa
 void launch_lists_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
                        const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
                        hipStream_t st);
+// the corrected node fields of the MD cells (after E_k and the grain charges)
+void launch_md_field(const void* E, int e_f64, const MdTables& md, int nx, int ny, hipStream_t st);
 void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
                      uint32_t k1, double vth, hipStream_t st);
 void launch_init_f32r(const PartF32R& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,

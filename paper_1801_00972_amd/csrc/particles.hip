@@ -93,27 +93,44 @@ __device__ __forceinline__ void gather_d(const ET* __restrict__ E, const Species
 }
 
 // ---------------------------------------------------------------- MD region
-__device__ __forceinline__ uint32_t md_lookup(const MdTables& md, int nx, int ny, int i, int j,
-                                              int k) {
-  if (md.n_grains == 0) return 0u;
+// index of cell (i, j, k) in the bounding box of the MD cubes, or -1
+__device__ __forceinline__ long md_box_index(const MdTables& md, int nx, int ny, int i, int j,
+                                             int k) {
+  if (md.n_grains == 0) return -1;
   int a = i - md.bx0;
   if (a < 0) a += nx;
-  if (a >= md.bsx) return 0u;
+  if (a >= md.bsx) return -1;
   int b = j - md.by0;
   if (b < 0) b += ny;
-  if (b >= md.bsy) return 0u;
+  if (b >= md.bsy) return -1;
   const int c = k - md.bz0;
-  if (c < 0 || c >= md.bsz) return 0u;
-  const uint32_t cl = md.cell_list[((long)c * md.bsy + b) * md.bsx + a];
+  if (c < 0 || c >= md.bsz) return -1;
+  return ((long)c * md.bsy + b) * md.bsx + a;
+}
+
+__device__ __forceinline__ uint32_t md_lookup(const MdTables& md, int nx, int ny, int i, int j,
+                                              int k) {
+  const long bi = md_box_index(md, nx, ny, i, j, k);
+  if (bi < 0) return 0u;
+  const uint32_t cl = md.cell_list[bi];
   return (cl & 255u) ? cl : 0u;  // a cell of the box outside every cube has no grains
 }
 
-// per-grain data the sub-stepping reads every sub-step (staged in LDS when few)
+// per-grain data the sub-stepping reads every sub-step (staged in LDS)
 struct GrainView {
   const double* gpos;   // [g][3] cell units
-  const int32_t* gcell; // [g][3]
-  const double* Q;      // [g] coulomb, frozen for the step
+  const double* Q;      // [g] grain charge frozen for the step, times qscale:
+  double qscale;        // Q qscale = Q / (4 pi eps0 dx^2)
 };
+
+// 1 / sqrt(a), a > 0: the hardware estimate refined by two Newton steps
+// y <- y (3 - a y^2) / 2 (each squares the relative error)
+__device__ __forceinline__ double rsqrt_refined(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  y = y * (1.5 - 0.5 * a * y * y);
+  y = y * (1.5 - 0.5 * a * y * y);
+  return y;
+}
 
 // separation x - x_g (cell units), minimum image across the periodic x,y
 __device__ __forceinline__ void grain_sep(const GrainView& G, const SpeciesStep& S, int g,
@@ -125,30 +142,6 @@ __device__ __forceinline__ void grain_sep(const GrainView& G, const SpeciesStep&
   else if (r[0] < -0.5 * S.nx) r[0] += S.nx;
   if (r[1] > 0.5 * S.ny) r[1] -= S.ny;
   else if (r[1] < -0.5 * S.ny) r[1] += S.ny;
-}
-
-// CIC gather of grain g's unit-charge field from its cube of nodes
-__device__ __forceinline__ void gather_unit(const MdTables& md, const GrainView& G,
-                                            const SpeciesStep& S, int g, int i0, int j0, int k0,
-                                            double fx, double fy, double fz, double out[3]) {
-  const int c = md.cutoff, side = md.side;
-  const long cube = (long)side * side * side;
-  int lx = i0 - (G.gcell[3 * g + 0] - c);
-  lx = ((lx % S.nx) + S.nx) % S.nx;
-  int ly = j0 - (G.gcell[3 * g + 1] - c);
-  ly = ((ly % S.ny) + S.ny) % S.ny;
-  const int lz = k0 - (G.gcell[3 * g + 2] - c);
-  const double* U = md.U + (long)g * 3 * cube;
-  out[0] = out[1] = out[2] = 0.0;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int a = t & 1, b = (t >> 1) & 1, cc = t >> 2;
-    const double w = (a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy) * (cc ? fz : 1.0 - fz);
-    const long l = ((long)(lz + cc) * side + (ly + b)) * side + (lx + a);
-    out[0] += w * U[l];
-    out[1] += w * U[cube + l];
-    out[2] += w * U[2 * cube + l];
-  }
 }
 
 __device__ __forceinline__ double wrap_coord(double X, int n) {
@@ -163,23 +156,45 @@ constexpr int kMdCache = 8;  // grains of the current cell kept in registers
 
 // Sub-cycled PPPM motion near grains, Eq. (5)-(6): md_sub sub-steps of
 // h = dt/md_sub with E = E_mesh - sum_g Q_g U_g + sum_g Q_g r / (4 pi eps0 r^3)
-// over the grains whose cube holds the current cell; hit when |r| <= a.
-// A particle crosses a cell boundary in only a few of its sub-steps, so the
-// cell's 8 node fields and grain list are kept until the cell changes.
+// over the grains whose cube holds the current cell; hit when |r| <= a (the
+// lowest grain index of the cell's list wins).  The first two terms are
+// gathered from the cell's corrected node fields (built once per step by
+// md_field_kernel).  A particle crosses a cell boundary in only a few of its
+// sub-steps, so the cell's node fields and grain list are kept until the cell
+// changes.
 template <typename ET>
 __device__ int md_move(const ET* __restrict__ E, const MdTables& md, const GrainView& G,
                        const SpeciesStep& S, double x[3], double v[3], int& hit) {
-  int e_cell = -1, l_cell = -1;
+  int e_cell = -1;
   double ec[8][3];
   uint32_t cl = 0u;
+  int cnt = 0;
   int gl[kMdCache];
-  auto load_list = [&](int cell, int i0, int j0, int k0) {
-    if (cell == l_cell) return;
-    l_cell = cell;
-    cl = md_lookup(md, S.nx, S.ny, i0, j0, k0);
+  auto load_cell = [&](int cell, int i0, int j0, int k0) {
+    if (cell == e_cell) return;
+    e_cell = cell;
+    const long bi = md_box_index(md, S.nx, S.ny, i0, j0, k0);
+    cl = bi >= 0 ? md.cell_list[bi] : 0u;
+    cnt = (int)(cl & 255u);
+    if (cnt > 0) {
+      const double* src = md.ecorr + bi * 24;
 #pragma unroll
-    for (int t = 0; t < kMdCache; ++t)
-      gl[t] = t < (int)(cl & 255u) ? md.grain_idx[(cl >> 8) + t] : 0;
+      for (int c = 0; c < 8; ++c) {
+        ec[c][0] = src[3 * c];
+        ec[c][1] = src[3 * c + 1];
+        ec[c][2] = src[3 * c + 2];
+      }
+    } else {
+      const int i1 = i0 + 1 == S.nx ? 0 : i0 + 1;
+      const int j1 = j0 + 1 == S.ny ? 0 : j0 + 1;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        load_node(E, ((c & 1) ? i1 : i0) + (long)S.nx * (((c >> 1) & 1) ? j1 : j0) +
+                         (long)S.nxy * (k0 + (c >> 2)),
+                  ec[c][0], ec[c][1], ec[c][2]);
+    }
+#pragma unroll
+    for (int u = 0; u < kMdCache; ++u) gl[u] = u < cnt ? md.grain_idx[(cl >> 8) + u] : 0;
   };
   auto grain_at = [&](int t) -> int {
     int g = 0;
@@ -192,44 +207,32 @@ __device__ int md_move(const ET* __restrict__ E, const MdTables& md, const Grain
     int i0 = (int)floor(x[0]), j0 = (int)floor(x[1]), k0 = (int)floor(x[2]);
     const double fx = x[0] - i0, fy = x[1] - j0, fz = x[2] - k0;
     int cell = pack_cell(i0, j0, k0);
-    if (cell != e_cell) {
-      e_cell = cell;
-      const int i1 = i0 + 1 == S.nx ? 0 : i0 + 1;
-      const int j1 = j0 + 1 == S.ny ? 0 : j0 + 1;
-#pragma unroll
-      for (int t = 0; t < 8; ++t)
-        load_node(E, ((t & 1) ? i1 : i0) + (long)S.nx * (((t >> 1) & 1) ? j1 : j0) +
-                         (long)S.nxy * (k0 + (t >> 2)),
-                  ec[t][0], ec[t][1], ec[t][2]);
-    }
-    load_list(cell, i0, j0, k0);
+    load_cell(cell, i0, j0, k0);
     double Ep[3] = {0.0, 0.0, 0.0};
     {
       const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const double w = wx[t & 1] * wy[(t >> 1) & 1] * wz[t >> 2];
-        Ep[0] += w * ec[t][0];
-        Ep[1] += w * ec[t][1];
-        Ep[2] += w * ec[t][2];
+      for (int c = 0; c < 8; ++c) {
+        const double wt = wx[c & 1] * wy[(c >> 1) & 1] * wz[c >> 2];
+        Ep[0] += wt * ec[c][0];
+        Ep[1] += wt * ec[c][1];
+        Ep[2] += wt * ec[c][2];
       }
     }
-    for (int t = 0; t < (int)(cl & 255u); ++t) {
+    // the grains' Coulomb fields (their mesh parts are in the corrected
+    // nodes): Q r / (4 pi eps0 |r|^3) with r in cells and Q qscale = Q / (4 pi eps0 dx^2)
+    for (int t = 0; t < cnt; ++t) {
       const int g = grain_at(t);
-      const double Q = G.Q[g];
-      if (Q == 0.0) continue;
+      const double Qc = G.Q[g] * G.qscale;
+      if (Qc == 0.0) continue;
       double r[3];
       grain_sep(G, S, g, x, r);
-      r[0] *= S.dx;
-      r[1] *= S.dx;
-      r[2] *= S.dx;
       const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-      const double inv = 1.0 / (4.0 * kPi * kEps0 * r2 * sqrt(r2));
-      double Um[3];
-      gather_unit(md, G, S, g, i0, j0, k0, fx, fy, fz, Um);
-      Ep[0] += Q * (r[0] * inv - Um[0]);
-      Ep[1] += Q * (r[1] * inv - Um[1]);
-      Ep[2] += Q * (r[2] * inv - Um[2]);
+      const double rs = rsqrt_refined(r2);
+      const double inv = Qc * rs * rs * rs;
+      Ep[0] += r[0] * inv;
+      Ep[1] += r[1] * inv;
+      Ep[2] += r[2] * inv;
     }
     v[0] += S.qm_h * Ep[0];
     v[1] += S.qm_h * Ep[1];
@@ -243,8 +246,8 @@ __device__ int md_move(const ET* __restrict__ E, const MdTables& md, const Grain
     j0 = (int)floor(x[1]);
     k0 = (int)floor(x[2]);
     cell = pack_cell(i0, j0, k0);
-    load_list(cell, i0, j0, k0);
-    for (int t = 0; t < (int)(cl & 255u); ++t) {
+    load_cell(cell, i0, j0, k0);
+    for (int t = 0; t < cnt; ++t) {
       const int g = grain_at(t);
       double r[3];
       grain_sep(G, S, g, x, r);
@@ -258,6 +261,50 @@ __device__ int md_move(const ET* __restrict__ E, const MdTables& md, const Grain
     }
   }
   return ST_ALIVE;
+}
+
+// The corrected node fields of Eq. (5) for every cell of the MD box that lies
+// in a cube, once per step after E_k and the grain charges: for corner t of
+// the cell, E_k(node) - sum_g Q_g U_g(node) over the cell's grains, in list
+// order.  One thread per (cell, corner).
+template <typename ET>
+__global__ void md_field_kernel(const ET* __restrict__ E, MdTables md, int nx, int ny, int nxy) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nbox = (long)md.bsx * md.bsy * md.bsz;
+  if (gid >= 8 * nbox) return;
+  const long bi = gid >> 3;
+  const int t = (int)(gid & 7);
+  const uint32_t cl = md.cell_list[bi];
+  const int cnt = (int)(cl & 255u);
+  if (cnt == 0) return;
+  const int a = (int)(bi % md.bsx), b = (int)((bi / md.bsx) % md.bsy);
+  const int c = (int)(bi / ((long)md.bsx * md.bsy));
+  const int i0 = (md.bx0 + a) % nx, j0 = (md.by0 + b) % ny, k0 = md.bz0 + c;
+  const int ta = t & 1, tb = (t >> 1) & 1, tc = t >> 2;
+  const int in = i0 + ta == nx ? 0 : i0 + ta, jn = j0 + tb == ny ? 0 : j0 + tb;
+  double ex, ey, ez;
+  load_node(E, in + (long)nx * jn + (long)nxy * (k0 + tc), ex, ey, ez);
+  const int side = md.side;
+  const long cube = (long)side * side * side;
+  for (int u = 0; u < cnt; ++u) {
+    const int g = md.grain_idx[(cl >> 8) + u];
+    const double Q = md.Q[g];
+    if (Q == 0.0) continue;
+    int lx = i0 - (md.gcell[3 * g + 0] - md.cutoff);
+    lx = ((lx % nx) + nx) % nx;
+    int ly = j0 - (md.gcell[3 * g + 1] - md.cutoff);
+    ly = ((ly % ny) + ny) % ny;
+    const int lz = k0 - (md.gcell[3 * g + 2] - md.cutoff);
+    const long l = ((long)(lz + tc) * side + (ly + tb)) * side + (lx + ta);
+    const double* U = md.U + (long)g * 3 * cube;
+    ex -= Q * U[l];
+    ey -= Q * U[cube + l];
+    ez -= Q * U[2 * cube + l];
+  }
+  double* dst = md.ecorr + bi * 24 + 3 * t;
+  dst[0] = ex;
+  dst[1] = ey;
+  dst[2] = ez;
 }
 
 // ---------------------------------------------------------------- collisions
@@ -361,11 +408,6 @@ __device__ __forceinline__ void split8(long long Q, float ox, float oy, float oz
 }
 
 // ---------------------------------------------------------------- wave helpers
-__device__ __forceinline__ void wave_count(bool flag, unsigned long long* dst) {
-  const unsigned long long m = __ballot(flag);
-  if ((threadIdx.x & 63) == 0 && m) atomicAdd(dst, (unsigned long long)__popcll(m));
-}
-
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -562,7 +604,7 @@ __device__ __forceinline__ void corner_add(const Tile& T, int lbase, A* s_rho, A
   }
 }
 
-// one particle's CIC charge straight to the global mesh (loading, MD particles)
+// one particle's CIC charge straight to the global mesh (particles outside their tile's window)
 __device__ __forceinline__ void deposit_global_fixed(long long* __restrict__ rho,
                                                      const SpeciesStep& S, int i, int j, int k,
                                                      float ox, float oy, float oz) {
@@ -579,15 +621,6 @@ __device__ __forceinline__ void cic_weights_d(double fx, double fy, double fz, d
   const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
 #pragma unroll
   for (int t = 0; t < 8; ++t) w[t] = s * wx[t & 1] * wy[(t >> 1) & 1] * wz[t >> 2];
-}
-
-__device__ __forceinline__ void deposit_global_f64(double* __restrict__ rho, const SpeciesStep& S,
-                                                   double X, double Y, double Z) {
-  const int i = (int)floor(X), j = (int)floor(Y), k = (int)floor(Z);
-  double w[8];
-  cic_weights_d(X - i, Y - j, Z - k, S.sign, w);
-  Tile none{};
-  corner_add<double>(none, -1, nullptr, rho, S, i, j, k, w);
 }
 
 // append to a list segment: one LDS atomic per wave
@@ -1130,20 +1163,23 @@ __device__ __forceinline__ void load_d(const PartF32R& P, long p, double x[3], d
   v[2] = P.vz[p];
 }
 
-// store the survivor (returns false if rounding put it on the rf electrode)
-__device__ __forceinline__ bool store_d(const PartF64& P, long p, const double x[3],
-                                        const double v[3], double* rho, const SpeciesStep& S) {
+// store the survivor; returns its cell (-1 if rounding put it on the rf
+// electrode) and the eight corner shares of its charge
+__device__ __forceinline__ int store_d(const PartF64& P, long p, const double x[3],
+                                       const double v[3], const SpeciesStep& S, double part[8]) {
   P.x[p] = x[0];
   P.y[p] = x[1];
   P.z[p] = x[2];
   P.vx[p] = v[0];
   P.vy[p] = v[1];
   P.vz[p] = v[2];
-  deposit_global_f64(rho, S, x[0], x[1], x[2]);
-  return true;
+  const int i = (int)floor(x[0]), j = (int)floor(x[1]), k = (int)floor(x[2]);
+  cic_weights_d(x[0] - i, x[1] - j, x[2] - k, S.sign, part);
+  return pack_cell(i, j, k);
 }
-__device__ __forceinline__ bool store_d(const PartF32R& P, long p, const double x[3],
-                                        const double v[3], long long* rho, const SpeciesStep& S) {
+__device__ __forceinline__ int store_d(const PartF32R& P, long p, const double x[3],
+                                       const double v[3], const SpeciesStep& S,
+                                       long long part[8]) {
   int c[3];
   float f[3];
   const int n3[3] = {S.nx, S.ny, S.nz};
@@ -1162,67 +1198,124 @@ __device__ __forceinline__ bool store_d(const PartF32R& P, long p, const double 
   P.vz[p] = (float)v[2];
   if (c[2] >= S.nz) {
     P.cell[p] = -1;
-    return false;
+    return -1;
   }
   P.cell[p] = pack_cell(c[0], c[1], c[2]);
   P.ox[p] = f[0];
   P.oy[p] = f[1];
   P.oz[p] = f[2];
-  deposit_global_fixed(rho, S, c[0], c[1], c[2], f[0], f[1], f[2]);
-  return true;
+  split8(S.Qp, f[0], f[1], f[2], part);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) part[t] *= S.isign;
+  return P.cell[p];
 }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum_t(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// The charges of a wave's MD particles to the global mesh.  The particles of
+// a cell of the dense list tend to sit in neighbouring lanes and hit the same
+// eight nodes, which all MD blocks share, so per distinct cell the wave first
+// sums the corner shares and one lane adds them (for the fixed-point charge
+// the sums are exact and the mesh does not depend on the grouping).  After
+// kDepGroups distinct cells the remaining lanes add their own shares.
+constexpr int kDepGroups = 16;
+template <typename A>
+__device__ __forceinline__ void deposit_wave(A* __restrict__ rho, const SpeciesStep& S, int cell,
+                                             const A part[8]) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(cell >= 0);
+  Tile none{};
+  for (int it = 0; it < kDepGroups && pending; ++it) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int key = __shfl(cell, leader, 64);
+    const bool mine = cell == key;
+    const unsigned long long m = __ballot(mine);
+    pending &= ~m;
+    A sum[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) sum[t] = wave_sum_t<A>(mine ? part[t] : (A)0);
+    if (lane == leader)
+      corner_add<A>(none, -1, nullptr, rho, S, cell_i(key), cell_j(key), cell_k(key), sum);
+  }
+  if ((pending >> lane) & 1ull)
+    corner_add<A>(none, -1, nullptr, rho, S, cell_i(cell), cell_j(cell), cell_k(cell), part);
+}
+
 __device__ __forceinline__ void kill(const PartF64& P, long p) { P.z[p] = -1.0; }
 __device__ __forceinline__ void kill(const PartF32R& P, long p) { P.cell[p] = -1; }
 
-// one MD particle per thread over the dense list of this step
+// one thread per MD particle of the dense list of this step; events go to the
+// block's own tally row, grain hits to LDS counters first
+constexpr int kMdThreads = 64;
 template <typename PT, typename ET, typename RT>
-__global__ __launch_bounds__(64) void md_kernel(PT P, const ET* __restrict__ E, RT* __restrict__ rho,
-                                                MdTables md, SpeciesStep S,
-                                                unsigned long long* __restrict__ grain_count,
-                                                WorkLists L, int do_mcc) {
+__global__ __launch_bounds__(kMdThreads) void md_kernel(PT P, const ET* __restrict__ E,
+                                                        RT* __restrict__ rho, MdTables md,
+                                                        SpeciesStep S,
+                                                        unsigned long long* __restrict__ grain_count,
+                                                        WorkLists L, int do_mcc) {
   const int total = L.cnt[2];
-  if ((long)blockIdx.x * 64 >= total) return;
+  if ((long)blockIdx.x * kMdThreads >= total) return;
   constexpr int kStage = 256;
-  __shared__ double s_gpos[3 * kStage], s_Q[kStage];
-  __shared__ int32_t s_gcell[3 * kStage];
-  GrainView G{md.gpos, md.gcell, md.Q};
-  if (md.n_grains <= kStage) {
-    for (int t = threadIdx.x; t < md.n_grains; t += blockDim.x) {
-      s_Q[t] = md.Q[t];
-      for (int a = 0; a < 3; ++a) {
-        s_gpos[3 * t + a] = md.gpos[3 * t + a];
-        s_gcell[3 * t + a] = md.gcell[3 * t + a];
-      }
-    }
-    __syncthreads();
-    G = GrainView{s_gpos, s_gcell, s_Q};
+  __shared__ double s_gpos[3 * kStage], s_Qc[kStage];
+  __shared__ unsigned s_hits[kStage];
+  for (int t = threadIdx.x; t < min(md.n_grains, kStage); t += blockDim.x) {
+    s_Qc[t] = md.Q[t] * S.coul_c;
+    s_hits[t] = 0u;
+    for (int a = 0; a < 3; ++a) s_gpos[3 * t + a] = md.gpos[3 * t + a];
   }
-  unsigned long long* tally = L.tally + (long)TL_N * L.ngrid;  // the MD row
-  for (long base = (long)blockIdx.x * 64; base < total; base += (long)gridDim.x * 64) {
-    const int idx = (int)base + threadIdx.x;
-    int st = ST_NONE;
+  __syncthreads();
+  const GrainView G = md.n_grains <= kStage ? GrainView{s_gpos, s_Qc, 1.0}
+                                            : GrainView{md.gpos, md.Q, S.coul_c};
+  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_coll = 0, n_cap = 0, n_dead = 0;
+  for (long base = (long)blockIdx.x * kMdThreads; base < total;
+       base += (long)gridDim.x * kMdThreads) {
+    const long idx = base + threadIdx.x;
+    int st = ST_NONE, cell = -1;
     bool coll = false, capv = false;
+    RT part[8];
     if (idx < total) {
       const long p = L.md[idx];
       double x[3], v[3];
       load_d(P, p, x, v);
       int hit = -1;
       st = md_move(E, md, G, S, x, v, hit);
-      if (st == ST_GRAIN) atomicAdd(&grain_count[2 * hit + S.sp], 1ull);
+      if (st == ST_GRAIN) {
+        if (hit < kStage) atomicAdd(&s_hits[hit], 1u);
+        else atomicAdd(&grain_count[2 * hit + S.sp], 1ull);
+      }
       if (st == ST_ALIVE && do_mcc) collide(S, P.id[p], v, coll, capv);
       if (st == ST_ALIVE) {
-        if (!store_d(P, p, x, v, rho, S)) st = ST_WALL1;
+        cell = store_d(P, p, x, v, S, part);
+        if (cell < 0) st = ST_WALL1;
       } else {
         kill(P, p);
       }
     }
-    wave_count(st == ST_WALL0, &tally[TL_W0]);
-    wave_count(st == ST_WALL1, &tally[TL_W1]);
-    wave_count(st == ST_BAD, &tally[TL_BAD]);
-    wave_count(coll, &tally[TL_COLL]);
-    wave_count(capv, &tally[TL_CAP]);
-    wave_count(st == ST_WALL0 || st == ST_WALL1 || st == ST_BAD || st == ST_GRAIN, &tally[TL_DEAD]);
+    deposit_wave<RT>(rho, S, cell, part);
+    n_w0 += st == ST_WALL0;
+    n_w1 += st == ST_WALL1;
+    n_bad += st == ST_BAD;
+    n_coll += coll;
+    n_cap += capv;
+    n_dead += st == ST_WALL0 || st == ST_WALL1 || st == ST_BAD || st == ST_GRAIN;
   }
+  int c6[6] = {n_w0, n_w1, n_bad, n_coll, n_cap, n_dead};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) c6[k] = wave_sum(c6[k]);
+  if (threadIdx.x == 0) {  // this block's own tally row (no atomics)
+    unsigned long long* tally = L.tally + (long)TL_N * (L.ngrid + blockIdx.x);
+    const int kinds[6] = {TL_W0, TL_W1, TL_BAD, TL_COLL, TL_CAP, TL_DEAD};
+    for (int k = 0; k < 6; ++k)
+      if (c6[k]) tally[kinds[k]] += (unsigned long long)c6[k];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < min(md.n_grains, kStage); t += blockDim.x)
+    if (s_hits[t]) atomicAdd(&grain_count[2 * t + S.sp], (unsigned long long)s_hits[t]);
 }
 
 // the dense MD list starts empty for the next step
@@ -1332,7 +1425,10 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(PartF64 P, const double
       }
       t_coll += coll;
       t_cap += capv;
-      store_d(P, p, x, v, rho, S);
+      double part[8];
+      const int c = store_d(P, p, x, v, S, part);
+      Tile none{};
+      corner_add<double>(none, -1, nullptr, rho, S, cell_i(c), cell_j(c), cell_k(c), part);
     } else {
       kill(P, p);
       P.vx[p] = v[0];
@@ -1817,7 +1913,19 @@ void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int 
   hipLaunchKernelGGL(push_batch_f32r_kernel, dim3(grid), dim3(kBlock), 0, st, descs, start, ndesc);
 }
 
-constexpr int kMdBlocks = 2048;
+constexpr int kMdBlocks = kMdTallyRows;
+
+void launch_md_field(const void* E, int e_f64, const MdTables& md, int nx, int ny,
+                     hipStream_t st) {
+  if (md.n_grains == 0) return;
+  const long n = 8L * md.bsx * md.bsy * md.bsz;
+  if (e_f64)
+    hipLaunchKernelGGL(md_field_kernel<double2>, dim3(nblk(n, 256)), dim3(256), 0, st,
+                       (const double2*)E, md, nx, ny, nx * ny);
+  else
+    hipLaunchKernelGGL(md_field_kernel<float4>, dim3(nblk(n, 256)), dim3(256), 0, st,
+                       (const float4*)E, md, nx, ny, nx * ny);
+}
 
 void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
                       const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
@@ -1827,7 +1935,7 @@ void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTa
   hipLaunchKernelGGL(outlier_f64_kernel, dim3(nc), dim3(64), 0, st, P, (const double2*)E, rho, S, L,
                      do_mcc);
   if (md.n_grains > 0)
-    hipLaunchKernelGGL((md_kernel<PartF64, double2, double>), dim3(kMdBlocks), dim3(64), 0, st, P,
+    hipLaunchKernelGGL((md_kernel<PartF64, double2, double>), dim3(kMdBlocks), dim3(kMdThreads), 0, st, P,
                        (const double2*)E, rho, md, S, gc, L, do_mcc);
   hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L.cnt);
   if (do_mcc) hipLaunchKernelGGL(collide_kernel<PartF64>, dim3(nc), dim3(64), 0, st, P, S, L);
@@ -1841,7 +1949,7 @@ void launch_lists_f32r(const PartF32R& P, const float* E, long long* rho, const 
   hipLaunchKernelGGL(outlier_f32r_kernel, dim3(nc), dim3(64), 0, st, P, (const float4*)E, rho, S,
                      L, do_mcc);
   if (md.n_grains > 0)
-    hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(kMdBlocks), dim3(64), 0, st,
+    hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(kMdBlocks), dim3(kMdThreads), 0, st,
                        P, (const float4*)E, rho, md, S, gc, L, do_mcc);
   hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L.cnt);
   if (do_mcc) hipLaunchKernelGGL(collide_kernel<PartF32R>, dim3(nc), dim3(64), 0, st, P, S, L);

@@ -299,6 +299,7 @@ int setup_md(pic_ctx* ctx, Replica& R) {
   TRY(dalloc(ctx, R, &d_gpos, 3 * ng));
   TRY(dalloc(ctx, R, &d_gcell, 3 * ng));
   TRY(dalloc(ctx, R, &d_U, (size_t)ng * 3 * cube));
+  TRY(dalloc(ctx, R, &md.ecorr, cell_list.size() * 24));
   HIPCHK(ctx, hipMemcpy(d_cl, cell_list.data(), cell_list.size() * 4, hipMemcpyHostToDevice));
   if (!idx.empty())
     HIPCHK(ctx, hipMemcpy(d_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice));
@@ -361,6 +362,7 @@ SpeciesStep species_step(const Replica& R, int sp) {
   S.md_sub = c.md_subcycles;
   S.margin = R.margin[sp];
   S.dx = c.dx;
+  S.coul_c = 1.0 / (4.0 * kPi * kEps0 * c.dx * c.dx);
   const double qm = R.q[sp] / R.m[sp];
   const double h = c.dt / (double)c.md_subcycles;
   S.qm = qm;
@@ -424,9 +426,9 @@ int alloc_particles(pic_ctx* ctx, Replica& R) {
     TRY(dalloc(ctx, R, &L.coll_cnt, R.ngrid));
     TRY(dalloc(ctx, R, &L.out_cnt, R.ngrid));
     TRY(dalloc(ctx, R, &L.tstart, R.ngrid + 1));
-    TRY(dalloc(ctx, R, &L.tally, TL_N * (R.ngrid + 1)));
+    TRY(dalloc(ctx, R, &L.tally, TL_N * (R.ngrid + kMdTallyRows)));
     L.cnt = R.d_cnt + 8 * sp;
-    HIPCHK(ctx, hipMemsetAsync(L.tally, 0, 8 * TL_N * (R.ngrid + 1), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(L.tally, 0, 8 * TL_N * (R.ngrid + kMdTallyRows), ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(L.tstart, 0, 4 * (R.ngrid + 1), ctx->stream));
   }
   return PIC_OK;
@@ -480,6 +482,7 @@ int solve_fields(pic_ctx* ctx, Replica& R) {
                      R.Qp, st);
     launch_solve_f64(R.fft, R.nx, R.ny, R.nz, R.b, R.work, R.tw_x, R.tw_y, R.inv, R.phi, rf, st);
     launch_efield_f64(R.phi, (double*)R.E, R.nx, R.ny, R.nz, c.dx, st);
+    launch_md_field(R.E, 1, R.md, R.nx, R.ny, st);
   } else {
     const double scale = -c.dx * c.dx / kEps0 * (kCharge / 4294967296.0 / vol);
     launch_rhs_fixed((const long long*)R.rho[R.rho_cur], scale, R.b, R.nx, R.ny, R.nz, st);
@@ -488,6 +491,7 @@ int solve_fields(pic_ctx* ctx, Replica& R) {
     launch_solve_refined(R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y, R.inv,
                          R.phi, rf, c.max_refine, R.norms, st);
     launch_efield_f32(R.phi, (float*)R.E, R.nx, R.ny, R.nz, c.dx, st);
+    launch_md_field(R.E, 0, R.md, R.nx, R.ny, st);
   }
   CHECK_LAUNCH(ctx);
   return PIC_OK;
@@ -518,10 +522,10 @@ int resort(pic_ctx* ctx, Replica& R) {
 
 // event tallies of one species summed over the tiles
 int read_tallies(pic_ctx* ctx, Replica& R, int sp, unsigned long long out[TL_N]) {
-  std::vector<unsigned long long> h((size_t)TL_N * (R.ngrid + 1));
+  std::vector<unsigned long long> h((size_t)TL_N * (R.ngrid + kMdTallyRows));
   HIPCHK(ctx, hipMemcpy(h.data(), R.lists[sp].tally, h.size() * 8, hipMemcpyDeviceToHost));
   for (int w = 0; w < TL_N; ++w) out[w] = 0;
-  for (long c = 0; c <= R.ngrid; ++c)
+  for (long c = 0; c < R.ngrid + kMdTallyRows; ++c)
     for (int w = 0; w < TL_N; ++w) out[w] += h[(size_t)TL_N * c + w];
   return PIC_OK;
 }
@@ -1214,7 +1218,7 @@ int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) R->wall_base[a][b] = v->wall_count[a][b];
   for (int sp = 0; sp < 2; ++sp)
-    HIPCHK(ctx, hipMemset(R->lists[sp].tally, 0, 8 * TL_N * (R->ngrid + 1)));
+    HIPCHK(ctx, hipMemset(R->lists[sp].tally, 0, 8 * TL_N * (R->ngrid + kMdTallyRows)));
   const int ng = R->cfg.n_grains;
   if (ng > 0) {
     std::vector<int64_t> gc(2 * ng, 0);

@@ -50,8 +50,8 @@ struct WorkLists {
   int32_t* coll_cnt;  // [ngrid] entries in coll
   int32_t* out_cnt;   // [ngrid] entries in out
   int32_t* tstart;    // [ngrid + 1] first slot of each tile (set by the sort)
-  unsigned long long* tally;  // [ngrid + 1][TL_N] accumulated event counts (see TallyKind);
-                              // the last row collects the MD kernel's events
+  unsigned long long* tally;  // [ngrid + MD blocks][TL_N] accumulated event counts (see
+                              // TallyKind); one row per tile, then one per MD block
   int32_t* cnt;       // [0] slots in use, [2] entries in md, [4] scan total of the sort
   int ntx, nty, ntz;  // tiles along x, y, z
   int ngrid;          // tiles rounded up to a multiple of 8
@@ -73,6 +73,9 @@ struct MdTables {
   const int32_t* gcell;       // [g][3] floor of gpos
   const double* Q;            // [g] grain charge (C) frozen at the start of the step
   const double* U;            // [g][3][side^3] unit-charge mesh field on the cube
+  double* ecorr;              // [bsz][bsy][bsx][8][3] per box cell, rebuilt every step:
+                              // E_k - sum_g Q_g U_g on the cell's 8 nodes (V/m), the sum
+                              // over the grains whose cube holds the cell
   double a2;                  // grain radius^2 (m^2)
 };
 
@@ -83,6 +86,7 @@ struct SpeciesStep {
   int md_sub;
   int margin;              // cells of drift around a tile staged in the LDS window
   double dx;
+  double coul_c;           // 1 / (4 pi eps0 dx^2): Coulomb field per charge at one cell
   double qm_dt, dt_dx;     // (q/m) dt, dt/dx
   double qm_h, h_dx;       // the same for the MD sub-step h = dt / md_sub
   double qm;               // q/m
