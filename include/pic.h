@@ -59,6 +59,8 @@ extern "C" {
 #define PIC_E         2u  /* double [3][nodes]                  V/m      */
 #define PIC_RHO       4u  /* double [nodes]  plasma + grains    C/m^3    */
 #define PIC_RHO_FIXED 8u  /* int64  [nodes]  PIC_FP32R only     2^-32 e  */
+#define PIC_N        16u  /* double [2][nodes] e, Ar+           m^-3     */
+#define PIC_FLUX     32u  /* double [2][3][nodes] e, Ar+; x,y,z m^-2 s^-1 */
 
 /*
  * One replica.  Read-only; copied by pic_init.
@@ -156,10 +158,19 @@ int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C);
 /*
  * pic_fields -- the mesh quantities at the current step k for the current
  * particle state (solving if needed): out[b] receives the quantity of the
- * b-th set bit of `what`, in the order PHI, E, RHO, RHO_FIXED.  Buffers are
- * host pointers (out_on_device = 0, the call synchronises) or device
- * pointers on the context's device (out_on_device = 1, stream-ordered).
- * Errors: PIC_EINVAL (bad replica, NULL buffer, RHO_FIXED without FP32R).
+ * b-th set bit of `what`, in the order PHI, E, RHO, RHO_FIXED, N, FLUX.
+ * Buffers are host pointers (out_on_device = 0, the call synchronises) or
+ * device pointers on the context's device (out_on_device = 1,
+ * stream-ordered).  Every array is x-fastest over the nx ny (nz+1) nodes.
+ * N and FLUX are the particle densities and fluxes of the paper's results
+ * (Sec. IV, densities and ion and electron fluxes): per species s and node,
+ * n_s = (w / dx^3) sum_p W_p and flux_s = (w / dx^3) sum_p v_p W_p, with W_p
+ * the particle's cloud-in-cell weight for the node (the charge assignment of
+ * Sec. III) at x_k, and v_p the stored half-step velocity v_{k-1/2}.  They
+ * are computed on request (summed in FP64 with atomics, so the last bits
+ * depend on the order of additions) and are not part of pic_step.
+ * Errors: PIC_EINVAL (bad replica, NULL buffer, RHO_FIXED without FP32R,
+ * unknown bits).
  */
 int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int out_on_device);
 

@@ -98,6 +98,7 @@ def lib():
         L.orc_deposit.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp]
         L.orc_deposit_fixed.argtypes = [C.POINTER(_Config), C.POINTER(_State),
                                         C.POINTER(C.c_int64)]
+        L.orc_moments.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp, dp]
         L.orc_poisson.argtypes = [C.POINTER(_Config), dp, C.c_double, dp]
         L.orc_efield.argtypes = [C.POINTER(_Config), dp, dp]
         L.orc_fields.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp,
@@ -253,6 +254,17 @@ class Oracle:
         if rc:
             raise RuntimeError(f"orc_deposit_fixed failed ({rc})")
         return rho
+
+    def moments(self):
+        """Densities n [2][nodes] (m^-3) and fluxes [2][3][nodes] (m^-2 s^-1)
+        of electrons and ions at the current state."""
+        n = np.zeros(2 * self.n_nodes)
+        flux = np.zeros(6 * self.n_nodes)
+        rc = lib().orc_moments(C.byref(self.cfg), C.byref(self.st), _ptr(n, C.c_double),
+                               _ptr(flux, C.c_double))
+        if rc:
+            raise RuntimeError(f"orc_moments failed ({rc})")
+        return n.reshape(2, self.n_nodes), flux.reshape(2, 3, self.n_nodes)
 
     def poisson(self, rho, V: float) -> np.ndarray:
         rho = np.ascontiguousarray(rho, np.float64)

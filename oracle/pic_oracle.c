@@ -216,6 +216,37 @@ int orc_deposit(const orc_config* c, const orc_state* s, double* rho)
   return 0;
 }
 
+/* Particle moments on the nodes, the densities and fluxes of the results    */
+/* section (Sec. IV): n_s = w/dx^3 sum_p W and flux_s = w/dx^3 sum_p v W, with */
+/* the same cloud-in-cell weights W as the charge; v is the stored v_{k-1/2}. */
+/* n is [2][nodes], flux is [2][3][nodes].                                    */
+int orc_moments(const orc_config* c, const orc_state* s, double* n, double* flux)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return -1;
+  int64_t nn = orc_n_nodes(c);
+  memset(n, 0, sizeof(double) * 2 * nn);
+  memset(flux, 0, sizeof(double) * 6 * nn);
+  double scale = d.w / (c->dx * c->dx * c->dx);
+  for (int sp = 0; sp < 2; ++sp) {
+    double* ns = n + sp * nn;
+    double* fs = flux + 3 * sp * nn;
+    for (int64_t p = 0; p < s->n[sp]; ++p) {
+      if (!s->alive[sp][p]) continue;
+      const double* x = &s->pos[sp][3 * p];
+      const double* v = &s->vel[sp][3 * p];
+      cic8 W = cic_weights(c, x[0], x[1], x[2]);
+      for (int t = 0; t < 8; ++t) {
+        ns[W.node[t]] += W.w[t];
+        for (int a = 0; a < 3; ++a) fs[a * nn + W.node[t]] += v[a] * W.w[t];
+      }
+    }
+  }
+  for (int64_t m = 0; m < 2 * nn; ++m) n[m] *= scale;
+  for (int64_t m = 0; m < 6 * nn; ++m) flux[m] *= scale;
+  return 0;
+}
+
 /* Fixed-point CIC: the macro charge Qp (2^-32 e) is split along x, then each */
 /* half along y, then each quarter along z, by q1 = (Q * f24) >> 24 and        */
 /* q0 = Q - q1, where f24 = floor(offset * 2^24).  The 8 parts sum to Qp.      */

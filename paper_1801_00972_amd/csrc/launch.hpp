@@ -47,6 +47,10 @@ void launch_deposit_f64(const PartF64& P, double* rho, const MdTables& md, const
                         const WorkLists& L, hipStream_t st);
 void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
                          const SpeciesStep& S, const WorkLists& L, hipStream_t st);
+// density and flux moments of one species: mom [4][nn] gets W, v W summed per
+// node (added to what it holds); exactly one of P64, P32 is non-null
+void launch_moments(const PartF64* P64, const PartF32R* P32, const SpeciesStep& S,
+                    const WorkLists& L, double* mom, long nn, hipStream_t st);
 // counting sort of the slots in use into dst (dropping empty slots, padding
 // every tile to a multiple of 4); capacity bounds the slots in use
 void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L, int* hist,

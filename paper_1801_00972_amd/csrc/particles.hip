@@ -32,7 +32,6 @@ __device__ __forceinline__ int z_status(const double x[3], const SpeciesStep& S)
 }
 
 constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
 constexpr int kPPT = 4;                   // consecutive particles per thread
 constexpr int kChunk = kBlock * kPPT;     // slots one pass of a push block streams
 
@@ -1323,6 +1322,56 @@ __global__ void md_reset_kernel(int32_t* cnt) {
   if (threadIdx.x == 0 && blockIdx.x == 0) cnt[2] = 0;
 }
 
+// ---------------------------------------------------------------- moments
+// Density and flux moments of one species on the mesh nodes (the densities
+// and fluxes of Sec. IV): per node the sums over the particles of W and of
+// v W, where W is the particle's CIC weight for the node, the same
+// assignment as the charge deposit of Sec. III.  The host scales them by
+// w / dx^3.  v is the stored half-step velocity v_{k-1/2}.  One block per
+// tile: the tile's (4+1)^3 nodes accumulate in LDS and are then added to the
+// mesh; particles that left the tile since the last re-binning add to the
+// mesh directly.  mom is [4][nn]: W, v_x W, v_y W, v_z W.
+constexpr int kMomWin = 125;
+__device__ __forceinline__ bool slot_alive(const PartF64& P, long p) { return P.z[p] >= 0.0; }
+__device__ __forceinline__ bool slot_alive(const PartF32R& P, long p) { return P.cell[p] >= 0; }
+
+template <typename PT>
+__global__ __launch_bounds__(256) void moments_kernel(PT P, SpeciesStep S, WorkLists L,
+                                                      double* __restrict__ mom, long nn) {
+  const int t = blockIdx.x;
+  const long a = L.tstart[t], b = L.tstart[t + 1];
+  if (a == b) return;
+  __shared__ double s_m[4][kMomWin];
+  const Tile T = make_tile(t, L, S.nx, S.ny, S.nz, 0, kMomWin);
+  for (int u = threadIdx.x; u < 4 * kMomWin; u += blockDim.x) s_m[u / kMomWin][u % kMomWin] = 0.0;
+  __syncthreads();
+  for (long p = a + threadIdx.x; p < b; p += blockDim.x) {
+    if (!slot_alive(P, p)) continue;
+    double x[3], v[3], w[8], val[8];
+    load_d(P, p, x, v);
+    const int i = (int)floor(x[0]), j = (int)floor(x[1]), k = (int)floor(x[2]);
+    cic_weights_d(x[0] - i, x[1] - j, x[2] - k, 1.0, w);
+    const int lb = tile_cell(T, i, j, k, S.nx, S.ny);
+    corner_add<double>(T, lb, s_m[0], mom, S, i, j, k, w);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) val[c] = v[q] * w[c];
+      corner_add<double>(T, lb, s_m[q + 1], mom + (q + 1) * nn, S, i, j, k, val);
+    }
+  }
+  __syncthreads();
+  if (!T.on) return;
+  const int nt = T.tx * T.ty * T.tz;
+  const float rtx = 1.0f / (float)T.tx, rtxy = 1.0f / (float)(T.tx * T.ty);
+  for (int u = threadIdx.x; u < nt; u += blockDim.x) {
+    const long node = tile_node(T, u, rtx, rtxy, S.nx, S.ny, S.nxy);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (s_m[q][u] != 0.0) unsafeAtomicAdd(&mom[q * nn + node], s_m[q][u]);
+  }
+}
+
 // ---------------------------------------------------------------- outliers
 // Particles that started outside their tile's window (they drifted since the
 // last sort): the same push with the field gathered from global memory and the
@@ -1981,6 +2030,17 @@ void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
   if (L.ngrid <= 0) return;
   hipLaunchKernelGGL(push_f32r_kernel<false>, dim3(L.ngrid), dim3(kBlock), 0, st, P, nullptr, rho,
                      md, S, L);
+}
+
+void launch_moments(const PartF64* P64, const PartF32R* P32, const SpeciesStep& S,
+                    const WorkLists& L, double* mom, long nn, hipStream_t st) {
+  if (L.ngrid <= 0) return;
+  if (P64)
+    hipLaunchKernelGGL(moments_kernel<PartF64>, dim3(L.ngrid), dim3(256), 0, st, *P64, S, L, mom,
+                       nn);
+  else
+    hipLaunchKernelGGL(moments_kernel<PartF32R>, dim3(L.ngrid), dim3(256), 0, st, *P32, S, L, mom,
+                       nn);
 }
 
 void launch_fill_int(int* a, long n, int v, hipStream_t st) {

@@ -67,6 +67,7 @@ struct Replica {
   double* tot64 = nullptr;
   long long* totfx = nullptr;
   double* eout = nullptr;
+  double* mom = nullptr;  // [species][4][nn] moments for pic_fields
   // near-grain tables
   MdTables md{};
   double* d_Q = nullptr;
@@ -1015,7 +1016,7 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
   if (ctx->sticky) return ctx->sticky;
   Replica* R = get_rep(ctx, replica);
   if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
-  if (!out || (what & ~15u)) return fail(ctx, PIC_EINVAL, "bad selection or out");
+  if (!out || (what & ~63u)) return fail(ctx, PIC_EINVAL, "bad selection or out");
   if ((what & PIC_RHO_FIXED) && R->prec != PIC_FP32R)
     return fail(ctx, PIC_EINVAL, "PIC_RHO_FIXED needs the FP32R form");
   hipStream_t st = ctx->stream;
@@ -1027,12 +1028,33 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
   const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   int slot = 0;
   const double vol = R->cfg.dx * R->cfg.dx * R->cfg.dx;
-  for (unsigned bit = 1; bit <= PIC_RHO_FIXED; bit <<= 1) {
+  if (what & (PIC_N | PIC_FLUX)) {
+    if (!R->mom) TRY(dalloc(ctx, *R, &R->mom, 8 * nn));
+    launch_zero_f64(R->mom, 8 * nn, st);
+    for (int sp = 0; sp < 2; ++sp) {
+      const SpeciesStep S = species_step(*R, sp);
+      double* m = R->mom + 4 * nn * sp;
+      if (R->prec == PIC_FP64)
+        launch_moments(&R->p64[sp][R->cur[sp]], nullptr, S, R->lists[sp], m, nn, st);
+      else
+        launch_moments(nullptr, &R->p32[sp][R->cur[sp]], S, R->lists[sp], m, nn, st);
+    }
+    launch_scale(R->mom, nullptr, R->w / vol, R->mom, 8 * nn, st);
+    CHECK_LAUNCH(ctx);
+  }
+  for (unsigned bit = 1; bit <= PIC_FLUX; bit <<= 1) {
     if (!(what & bit)) continue;
     void* dst = out[slot++];
     if (!dst) return fail(ctx, PIC_EINVAL, "NULL output buffer");
     if (bit == PIC_PHI) {
       HIPCHK(ctx, hipMemcpyAsync(dst, R->phi, nn * 8, kind, st));
+    } else if (bit == PIC_N) {
+      for (int sp = 0; sp < 2; ++sp)
+        HIPCHK(ctx, hipMemcpyAsync((char*)dst + sp * nn * 8, R->mom + 4 * nn * sp, nn * 8, kind, st));
+    } else if (bit == PIC_FLUX) {
+      for (int sp = 0; sp < 2; ++sp)
+        HIPCHK(ctx, hipMemcpyAsync((char*)dst + 3 * sp * nn * 8, R->mom + (4 * sp + 1) * nn,
+                                   3 * nn * 8, kind, st));
     } else if (bit == PIC_E) {
       launch_e_out(R->prec == PIC_FP64 ? (const double*)R->E : nullptr,
                    R->prec == PIC_FP64 ? nullptr : (const float*)R->E, R->eout, nn, st);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ECONFIG, PIC_ENOMEM, PIC_EDEVICE, PIC_ENUMERIC, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PIC_FP64, PIC_FP32R = 0, 1
-PIC_PHI, PIC_E, PIC_RHO, PIC_RHO_FIXED = 1, 2, 4, 8
+PIC_PHI, PIC_E, PIC_RHO, PIC_RHO_FIXED, PIC_N, PIC_FLUX = 1, 2, 4, 8, 16, 32
 
 SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destroy",
            "pic_last_error", "pic_get_state", "pic_set_state", "pic_get_counters", "pic_derived",
@@ -322,7 +322,9 @@ class Simulation:
         outs, names = [], []
         for bit, name, shape, dt in ((PIC_PHI, "phi", (nn,), np.float64), (PIC_E, "E", (3, nn), np.float64),
                                      (PIC_RHO, "rho", (nn,), np.float64),
-                                     (PIC_RHO_FIXED, "rho_fixed", (nn,), np.int64)):
+                                     (PIC_RHO_FIXED, "rho_fixed", (nn,), np.int64),
+                                     (PIC_N, "n", (2, nn), np.float64),
+                                     (PIC_FLUX, "flux", (2, 3, nn), np.float64)):
             if what & bit:
                 outs.append(np.zeros(shape, dt))
                 names.append(name)

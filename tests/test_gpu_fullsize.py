@@ -2,7 +2,8 @@
 launch configuration bench.py times), on outputs the oracle can compute one by
 one: all mesh quantities of a state the GPU produced after a few steps, and one
 step of a sample of particles (uniform, near grains, near the electrodes)
-moved by the oracle in its own field.  Plus exact particle conservation."""
+moved by the oracle in its own field; the densities and fluxes of that
+state.  Plus exact particle conservation."""
 import numpy as np
 import pytest
 
@@ -61,6 +62,14 @@ def test_fullsize_fields_and_sampled_step(prec):
     e_E = rel_inf(g["E"], o["E"])
     print(f"  fields: phi {e_phi:.2e} E {e_E:.2e}", flush=True)
     assert e_phi <= TOL[prec] and e_E <= TOL[prec]
+    # densities and fluxes of the same state
+    from paper_1801_00972_amd.pic import PIC_FLUX, PIC_N
+    gm = sim.fields(0, PIC_N | PIC_FLUX)
+    n_o, flux_o = orc.moments()
+    e_n, e_f = rel_inf(gm["n"], n_o), rel_inf(gm["flux"], flux_o)
+    print(f"  moments: n {e_n:.2e} flux {e_f:.2e}", flush=True)
+    assert e_n <= 1e-12 and e_f <= 1e-12
+    del gm, n_o, flux_o
     # one step of a sample, moved by the oracle in its own field
     rng = np.random.default_rng(11)
     small = oracle.Oracle(wl)

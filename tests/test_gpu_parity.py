@@ -169,6 +169,31 @@ def test_ten_steps_from_loading(prec):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32r"])
+@pytest.mark.parametrize("rebin", [0, 3])
+def test_density_and_flux_moments(prec, rebin):
+    """n and flux of both species on the nodes (pic_fields PIC_N | PIC_FLUX)
+    against the oracle's moments of the same state, with particles drifting
+    out of their tiles (no re-binning) or re-binned every 3 steps."""
+    from paper_1801_00972_amd.pic import PIC_FLUX, PIC_N
+    wl = dict(W.small_fp64(), precision=prec)
+    sim = _sim(wl)
+    sim.set_tuning(sort_interval=rebin, ion_sort_interval=rebin)
+    for seg in range(3):
+        sim.step(4)
+        st = sim.get_state()
+        n, flux = oracle_from_state(wl, st).moments()
+        g = sim.fields(0, PIC_N | PIC_FLUX)
+        e_n, e_f = rel_inf(g["n"], n), rel_inf(g["flux"], flux)
+        print(f"  step {st['step']}: n {e_n:.2e} flux {e_f:.2e}", flush=True)
+        assert e_n <= 1e-13 and e_f <= 1e-12
+        # number of particles: sum of n dx^3 / w
+        w, vol = sim.derived()["w"], wl["dx"] ** 3
+        for s in range(2):
+            assert g["n"][s].sum() * vol / w == pytest.approx(len(st[s]["id"]), rel=1e-12)
+    sim.close()
+
+
 def test_fixed_point_total_charge_is_exact():
     wl = W.small_fp32r()
     sim = _sim(wl)
