@@ -174,6 +174,35 @@ int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C);
  */
 int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int out_on_device);
 
+/*
+ * Time- and rf-phase-averaged diagnostics (the averaged densities, fluxes and
+ * potential of the paper's results, Sec. IV: ion fluxes averaged over rf
+ * periods, electron fluxes resolved in rf phase).
+ *
+ * pic_average -- interval > 0 clears the averages of every replica and
+ * starts sampling: at the start of the next step k and then of every
+ * interval-th step, phi_k and the moments of PIC_N and PIC_FLUX (at x_k with
+ * v_{k-1/2}, as pic_fields gives them) are added to the sums of rf-phase bin
+ * b = floor(phase_bins frac(f_rf k dt)), and the bin's sample count is
+ * incremented.  interval = 0 stops sampling and keeps the sums.  Samples
+ * run inside pic_step (captured with the step when graphs are on).  Device
+ * memory: 9 nodes doubles per bin and replica.
+ * Errors: PIC_EINVAL (interval < 0, phase_bins outside 1..PIC_MAX_PHASE_BINS),
+ * PIC_ENOMEM.
+ *
+ * pic_average_read -- the averages of bin `bin` (or over all bins for
+ * bin = -1): out[b] receives the quantity of the b-th set bit of `what` (a
+ * subset of PIC_PHI | PIC_N | PIC_FLUX, layouts as in pic_fields), each the
+ * sum over samples divided by their number (zeros with no sample).
+ * samples (nullable host pointer) receives that number.  Buffers as in
+ * pic_fields.  Errors: PIC_EINVAL (bad replica, bin, bits or buffer),
+ * PIC_ESTATE (pic_average never started).
+ */
+#define PIC_MAX_PHASE_BINS 64
+int pic_average(pic_ctx* ctx, int interval, int phase_bins);
+int pic_average_read(pic_ctx* ctx, int replica, int bin, unsigned what, void* const* out,
+                     int out_on_device, int64_t* samples);
+
 /* pic_destroy -- free the context and all its device memory (NULL is a no-op). */
 void pic_destroy(pic_ctx* ctx);
 

@@ -86,6 +86,14 @@ __device__ __forceinline__ double rf_voltage(const RfDrive& d) {
   return d.V_dc + d.V_rf * sin(2.0 * kPi * d.f_rf * t);
 }
 
+// rf-phase bin of step k for time averages: the phase f_rf k dt modulo one
+// period, in nbins equal bins
+__device__ __forceinline__ int phase_bin(uint32_t k, double f_rf, double dt, int nbins) {
+  const double x = f_rf * ((double)k * dt);
+  const int b = (int)((x - floor(x)) * (double)nbins);
+  return b < 0 ? 0 : (b >= nbins ? nbins - 1 : b);
+}
+
 // wrap an index that is at most one period outside [0, n)
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 

@@ -48,9 +48,19 @@ void launch_deposit_f64(const PartF64& P, double* rho, const MdTables& md, const
 void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
                          const SpeciesStep& S, const WorkLists& L, hipStream_t st);
 // density and flux moments of one species: mom [4][nn] gets W, v W summed per
-// node (added to what it holds); exactly one of P64, P32 is non-null
+// node (added to what it holds, in the rf-phase bin of the step if avg.step
+// is set); exactly one of P64, P32 is non-null
 void launch_moments(const PartF64* P64, const PartF32R* P32, const SpeciesStep& S,
-                    const WorkLists& L, double* mom, long nn, hipStream_t st);
+                    const WorkLists& L, double* mom, long nn, const AvgBins& avg,
+                    hipStream_t st);
+// time averages: phi added to its rf-phase bin (avg.stride apart), and one
+// sample counted in cnt[bin]
+void launch_avg_phi(const double* phi, double* acc, long nn, const AvgBins& avg,
+                    unsigned long long* cnt, hipStream_t st);
+// out[u] = (sum over bins b0..b1-1 of acc[b stride + u]) / (samples in those
+// bins), times wv for u >= nn (the moments), for u < 9 nn
+void launch_avg_out(const double* acc, int b0, int b1, long stride, long nn,
+                    const unsigned long long* cnt, double wv, double* out, hipStream_t st);
 // counting sort of the slots in use into dst (dropping empty slots, padding
 // every tile to a multiple of 4); capacity bounds the slots in use
 void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L, int* hist,

@@ -768,6 +768,30 @@ __global__ void scale_kernel(const double* __restrict__ in, const long long* __r
   out[n] = conv * (in ? in[n] : (double)infx[n]);
 }
 
+// time averages: phi_k into the rf-phase bin of step k, one sample counted
+__global__ void avg_phi_kernel(const double* __restrict__ phi, double* __restrict__ acc, long nn,
+                               AvgBins avg, unsigned long long* __restrict__ cnt) {
+  const int b = phase_bin(*avg.step, avg.f_rf, avg.dt, avg.nbins);
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n == 0) cnt[b] += 1ull;
+  if (n < nn) acc[avg.stride * b + n] += phi[n];
+}
+
+// the averages over bins b0..b1-1: phi (u < nn) and the moments (times wv)
+__global__ void avg_out_kernel(const double* __restrict__ acc, int b0, int b1, long stride, long nn,
+                               const unsigned long long* __restrict__ cnt, double wv,
+                               double* __restrict__ out) {
+  const long u = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= 9 * nn) return;
+  double s = 0.0;
+  unsigned long long c = 0;
+  for (int b = b0; b < b1; ++b) {
+    s += acc[stride * b + u];
+    c += cnt[b];
+  }
+  out[u] = c ? s / (double)c * (u < nn ? 1.0 : wv) : 0.0;
+}
+
 __global__ void zero_f64_kernel(double* a, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = 0.0;
@@ -1000,6 +1024,17 @@ void launch_rho_total(const double* acc64, const long long* accfx, double* tot64
 void launch_scale(const double* in, const long long* infx, double conv, double* out, long nn,
                   hipStream_t st) {
   hipLaunchKernelGGL(scale_kernel, dim3(nb256(nn)), dim3(256), 0, st, in, infx, conv, out, nn);
+}
+
+void launch_avg_phi(const double* phi, double* acc, long nn, const AvgBins& avg,
+                    unsigned long long* cnt, hipStream_t st) {
+  hipLaunchKernelGGL(avg_phi_kernel, dim3(nb256(nn)), dim3(256), 0, st, phi, acc, nn, avg, cnt);
+}
+
+void launch_avg_out(const double* acc, int b0, int b1, long stride, long nn,
+                    const unsigned long long* cnt, double wv, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(avg_out_kernel, dim3(nb256(9 * nn)), dim3(256), 0, st, acc, b0, b1, stride, nn,
+                     cnt, wv, out);
 }
 
 void launch_zero_f64(double* a, long n, hipStream_t st) {

@@ -1330,15 +1330,19 @@ __global__ void md_reset_kernel(int32_t* cnt) {
 // w / dx^3.  v is the stored half-step velocity v_{k-1/2}.  One block per
 // tile: the tile's (4+1)^3 nodes accumulate in LDS and are then added to the
 // mesh; particles that left the tile since the last re-binning add to the
-// mesh directly.  mom is [4][nn]: W, v_x W, v_y W, v_z W.
+// mesh directly.  mom is [4][nn]: W, v_x W, v_y W, v_z W.  For the time
+// averages (avg.step non-null) the sums go to the rf-phase bin of the
+// current step, avg.stride doubles further per bin.
 constexpr int kMomWin = 125;
 __device__ __forceinline__ bool slot_alive(const PartF64& P, long p) { return P.z[p] >= 0.0; }
 __device__ __forceinline__ bool slot_alive(const PartF32R& P, long p) { return P.cell[p] >= 0; }
 
 template <typename PT>
 __global__ __launch_bounds__(256) void moments_kernel(PT P, SpeciesStep S, WorkLists L,
-                                                      double* __restrict__ mom, long nn) {
+                                                      double* __restrict__ mom, long nn,
+                                                      AvgBins avg) {
   const int t = blockIdx.x;
+  if (avg.step) mom += avg.stride * phase_bin(*avg.step, avg.f_rf, avg.dt, avg.nbins);
   const long a = L.tstart[t], b = L.tstart[t + 1];
   if (a == b) return;
   __shared__ double s_m[4][kMomWin];
@@ -2033,14 +2037,15 @@ void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
 }
 
 void launch_moments(const PartF64* P64, const PartF32R* P32, const SpeciesStep& S,
-                    const WorkLists& L, double* mom, long nn, hipStream_t st) {
+                    const WorkLists& L, double* mom, long nn, const AvgBins& avg,
+                    hipStream_t st) {
   if (L.ngrid <= 0) return;
   if (P64)
     hipLaunchKernelGGL(moments_kernel<PartF64>, dim3(L.ngrid), dim3(256), 0, st, *P64, S, L, mom,
-                       nn);
+                       nn, avg);
   else
     hipLaunchKernelGGL(moments_kernel<PartF32R>, dim3(L.ngrid), dim3(256), 0, st, *P32, S, L, mom,
-                       nn);
+                       nn, avg);
 }
 
 void launch_fill_int(int* a, long n, int v, hipStream_t st) {

@@ -68,6 +68,12 @@ struct Replica {
   long long* totfx = nullptr;
   double* eout = nullptr;
   double* mom = nullptr;  // [species][4][nn] moments for pic_fields
+  // time averages (pic_average): per rf-phase bin [9][nn] sums of phi, then
+  // W, v W of electrons and of ions; samples per bin; the read-out buffer
+  double* avg = nullptr;
+  unsigned long long* d_avg_cnt = nullptr;
+  int avg_cap = 0;  // bins allocated
+  double* avg_out = nullptr;
   // near-grain tables
   MdTables md{};
   double* d_Q = nullptr;
@@ -100,7 +106,10 @@ struct pic_ctx {
   int since_sort[2]{};
   // captured steps, by phase (see step_all)
   hipStream_t capture_stream = nullptr;
-  hipGraphExec_t graph[32] = {};
+  hipGraphExec_t graph[64] = {};
+  // time averages: a sample every avg_interval steps (0: off) into avg_bins
+  // rf-phase bins; since_avg counts the steps since the last sample
+  int avg_interval = 0, avg_bins = 0, since_avg = 0;
   // batched push: descriptors of every (replica, species) for each phase of
   // the buffers (electron, ion, rho), and the first tile of each descriptor
   bool batchable = false;
@@ -536,12 +545,35 @@ int read_tallies(pic_ctx* ctx, Replica& R, int sp, unsigned long long out[TL_N])
 // the species sorted at its end (bit sp of `sorts`).
 int phase_of(const Replica& R) { return R.cur[0] | (R.cur[1] << 1) | (R.rho_cur << 2); }
 
+AvgBins avg_bins_of(const pic_ctx* ctx, const Replica& R) {
+  return AvgBins{R.d_step, R.cfg.f_rf, R.cfg.dt, ctx->avg_bins, 9 * R.nn};
+}
+
+// one sample of the time averages at the start of a step: phi_k and the
+// moments of x_k, v_{k-1/2}, into the rf-phase bin of step k
+int enqueue_sample(pic_ctx* ctx, Replica& R) {
+  hipStream_t st = ctx->stream;
+  const AvgBins ab = avg_bins_of(ctx, R);
+  launch_avg_phi(R.phi, R.avg, R.nn, ab, R.d_avg_cnt, st);
+  for (int sp = 0; sp < 2; ++sp) {
+    const SpeciesStep S = species_step(R, sp);
+    double* m = R.avg + (1 + 4 * sp) * R.nn;
+    if (R.prec == PIC_FP64)
+      launch_moments(&R.p64[sp][R.cur[sp]], nullptr, S, R.lists[sp], m, R.nn, ab, st);
+    else
+      launch_moments(nullptr, &R.p32[sp][R.cur[sp]], S, R.lists[sp], m, R.nn, ab, st);
+  }
+  CHECK_LAUNCH(ctx);
+  return PIC_OK;
+}
+
 // launches one step of a replica on ctx->stream from the host state at the
 // start of the step (buffer phases); advance_host then moves the host mirrors
-int enqueue_step(pic_ctx* ctx, Replica& R, int sorts) {
+int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   hipStream_t st = ctx->stream;
   hipEvent_t f0 = prof_event(ctx);
   TRY(solve_fields(ctx, R));
+  if (sample) TRY(enqueue_sample(ctx, R));
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
   const int rnx = 1 - R.rho_cur;
   const int do_mcc = 1;
@@ -585,12 +617,13 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts) {
 
 // one step of every replica of an FP32R context with the push of all
 // replicas and species in one persistent launch (replicas in the same phase)
-int enqueue_batch(pic_ctx* ctx, int sorts) {
+int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   hipStream_t st = ctx->stream;
   const Replica& R0 = *ctx->reps[0];
   hipEvent_t f0 = prof_event(ctx);
   for (auto& R : ctx->reps) {
     TRY(solve_fields(ctx, *R));
+    if (sample) TRY(enqueue_sample(ctx, *R));
     launch_zero_i64((long long*)R->rho[1 - R->rho_cur], R->nn, st);
   }
   CHECK_LAUNCH(ctx);
@@ -628,10 +661,10 @@ bool replicas_aligned(const pic_ctx* ctx) {
 }
 
 // one step of every replica, launched on ctx->stream
-int enqueue_all(pic_ctx* ctx, int sorts) {
+int enqueue_all(pic_ctx* ctx, int sorts, int sample) {
   if (ctx->batchable && ctx->tune.batch_push && replicas_aligned(ctx))
-    return enqueue_batch(ctx, sorts);
-  for (auto& R : ctx->reps) TRY(enqueue_step(ctx, *R, sorts));
+    return enqueue_batch(ctx, sorts, sample);
+  for (auto& R : ctx->reps) TRY(enqueue_step(ctx, *R, sorts, sample));
   return PIC_OK;
 }
 
@@ -684,7 +717,7 @@ void advance_host(Replica& R, int sorts) {
     if (sorts & (1 << sp)) R.cur[sp] = 1 - R.cur[sp];
 }
 
-// captures the step of `key` = buffer phase | sorts << 3 into ctx->graph[key]
+// captures the step of `key` = buffer phase | sorts << 3 | sample << 5 into ctx->graph[key]
 // without running it: the host phases of the replicas are set to the key for
 // the capture and restored after
 int capture_step(pic_ctx* ctx, int key) {
@@ -704,7 +737,7 @@ int capture_step(pic_ctx* ctx, int key) {
   int rc = PIC_OK;
   hipGraph_t g = nullptr;
   if (e == hipSuccess) {
-    rc = enqueue_all(ctx, key >> 3);
+    rc = enqueue_all(ctx, (key >> 3) & 3, key >> 5);
     e = hipStreamEndCapture(ctx->stream, &g);
   }
   ctx->stream = user;
@@ -742,15 +775,16 @@ int due_sorts(const pic_ctx* ctx) {
 // the current phase and sorts, on the caller's stream
 int step_all(pic_ctx* ctx) {
   const int sorts = due_sorts(ctx);
+  const int sample = ctx->avg_interval > 0 && ctx->since_avg == 0;
   // with step timing on, an event pair brackets the step's launches (after
   // any capture, so host-side capture time is not counted)
   std::vector<hipEvent_t>* ev = ctx->step_ev;
   const bool timed = ev && ctx->step_ev_used + 2 <= ev->size();
   if (ctx->prof || !ctx->tune.use_graphs || !replicas_aligned(ctx)) {
     if (timed) HIPCHK(ctx, hipEventRecord((*ev)[ctx->step_ev_used], ctx->stream));
-    TRY(enqueue_all(ctx, sorts));
+    TRY(enqueue_all(ctx, sorts, sample));
   } else {
-    const int key = phase_of(*ctx->reps[0]) | (sorts << 3);
+    const int key = phase_of(*ctx->reps[0]) | (sorts << 3) | (sample << 5);
     if (!ctx->graph[key]) {
       // the capture stream is not ordered after the caller's stream: the
       // graph's first launch must not overtake work queued there
@@ -767,6 +801,7 @@ int step_all(pic_ctx* ctx) {
   for (auto& R : ctx->reps) advance_host(*R, sorts);
   for (int sp = 0; sp < 2; ++sp)
     ctx->since_sort[sp] = (sorts & (1 << sp)) ? 0 : ctx->since_sort[sp] + 1;
+  if (ctx->avg_interval > 0) ctx->since_avg = (ctx->since_avg + 1) % ctx->avg_interval;
   return PIC_OK;
 }
 
@@ -1035,9 +1070,9 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
       const SpeciesStep S = species_step(*R, sp);
       double* m = R->mom + 4 * nn * sp;
       if (R->prec == PIC_FP64)
-        launch_moments(&R->p64[sp][R->cur[sp]], nullptr, S, R->lists[sp], m, nn, st);
+        launch_moments(&R->p64[sp][R->cur[sp]], nullptr, S, R->lists[sp], m, nn, AvgBins{}, st);
       else
-        launch_moments(nullptr, &R->p32[sp][R->cur[sp]], S, R->lists[sp], m, nn, st);
+        launch_moments(nullptr, &R->p32[sp][R->cur[sp]], S, R->lists[sp], m, nn, AvgBins{}, st);
     }
     launch_scale(R->mom, nullptr, R->w / vol, R->mom, 8 * nn, st);
     CHECK_LAUNCH(ctx);
@@ -1075,6 +1110,76 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
         HIPCHK(ctx, hipMemcpyAsync(dst, R->totfx, nn * 8, kind, st));
     }
     CHECK_LAUNCH(ctx);
+  }
+  if (!out_on_device) HIPCHK(ctx, hipStreamSynchronize(st));
+  return PIC_OK;
+}
+
+int pic_average(pic_ctx* ctx, int interval, int phase_bins) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  if (interval < 0) return fail(ctx, PIC_EINVAL, "interval must be >= 0");
+  if (interval == 0) {
+    ctx->avg_interval = 0;
+    return PIC_OK;
+  }
+  if (phase_bins < 1 || phase_bins > PIC_MAX_PHASE_BINS)
+    return fail(ctx, PIC_EINVAL, "phase_bins out of range");
+  hipStream_t st = ctx->stream;
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  for (auto& R : ctx->reps) {
+    if (R->avg_cap < phase_bins) {
+      TRY(dalloc(ctx, *R, &R->avg, (size_t)9 * R->nn * phase_bins));
+      TRY(dalloc(ctx, *R, &R->d_avg_cnt, (size_t)phase_bins));
+      R->avg_cap = phase_bins;
+    }
+    launch_zero_f64(R->avg, 9 * R->nn * phase_bins, st);
+    launch_zero_i64((long long*)R->d_avg_cnt, phase_bins, st);
+  }
+  CHECK_LAUNCH(ctx);
+  ctx->avg_interval = interval;
+  ctx->avg_bins = phase_bins;
+  ctx->since_avg = 0;
+  ctx->drop_graphs();  // the captured samples hold the bin count and buffers
+  return PIC_OK;
+}
+
+int pic_average_read(pic_ctx* ctx, int replica, int bin, unsigned what, void* const* out,
+                     int out_on_device, int64_t* samples) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
+  if (!R->avg || ctx->avg_bins == 0) return fail(ctx, PIC_ESTATE, "no averages: call pic_average");
+  if ((what & ~(PIC_PHI | PIC_N | PIC_FLUX)) || (what && !out))
+    return fail(ctx, PIC_EINVAL, "bad selection or out");
+  if (bin < -1 || bin >= ctx->avg_bins) return fail(ctx, PIC_EINVAL, "bad bin");
+  hipStream_t st = ctx->stream;
+  const long nn = R->nn;
+  const int b0 = bin < 0 ? 0 : bin, b1 = bin < 0 ? ctx->avg_bins : bin + 1;
+  if (!R->avg_out) TRY(dalloc(ctx, *R, &R->avg_out, 9 * nn));
+  const double vol = R->cfg.dx * R->cfg.dx * R->cfg.dx;
+  launch_avg_out(R->avg, b0, b1, 9 * nn, nn, R->d_avg_cnt, R->w / vol, R->avg_out, st);
+  CHECK_LAUNCH(ctx);
+  const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  int slot = 0;
+  for (unsigned bit : {PIC_PHI, PIC_N, PIC_FLUX}) {
+    if (!(what & bit)) continue;
+    char* dst = (char*)out[slot++];
+    if (!dst) return fail(ctx, PIC_EINVAL, "NULL output buffer");
+    for (int sp = 0; sp < (bit == PIC_PHI ? 1 : 2); ++sp) {
+      const double* src = bit == PIC_PHI ? R->avg_out
+                          : R->avg_out + (1 + 4 * sp + (bit == PIC_FLUX ? 1 : 0)) * nn;
+      const long len = bit == PIC_FLUX ? 3 * nn : nn;
+      HIPCHK(ctx, hipMemcpyAsync(dst + sp * len * 8, src, len * 8, kind, st));
+    }
+  }
+  if (samples) {
+    std::vector<unsigned long long> c(ctx->avg_bins);
+    HIPCHK(ctx, hipMemcpyAsync(c.data(), R->d_avg_cnt, c.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    *samples = 0;
+    for (int b = b0; b < b1; ++b) *samples += (int64_t)c[b];
   }
   if (!out_on_device) HIPCHK(ctx, hipStreamSynchronize(st));
   return PIC_OK;

@@ -106,6 +106,15 @@ struct SpeciesStep {
 };
 
 // one (replica, species) of a batched push launch
+// rf-phase binning of the time averages: sums of step k go to bin
+// phase_bin(k), `stride` doubles apart; step == nullptr means no binning
+struct AvgBins {
+  const uint32_t* step;
+  double f_rf, dt;
+  int nbins;
+  long stride;
+};
+
 struct PushDescF32 {
   PartF32R P;
   const float4* E;

@@ -23,7 +23,8 @@ PIC_PHI, PIC_E, PIC_RHO, PIC_RHO_FIXED, PIC_N, PIC_FLUX = 1, 2, 4, 8, 16, 32
 SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destroy",
            "pic_last_error", "pic_get_state", "pic_set_state", "pic_get_counters", "pic_derived",
            "pic_profile_enable", "pic_profile_read", "pic_get_tuning", "pic_set_tuning",
-           "pic_autotune")
+           "pic_autotune", "pic_average", "pic_average_read")
+PIC_MAX_PHASE_BINS = 64
 PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT, PIC_PROF_LISTS = 0, 1, 2, 3
 
 
@@ -109,9 +110,13 @@ def lib():
         L.pic_set_tuning.argtypes = [P, C.POINTER(pic_tuning)]
         L.pic_autotune.argtypes = [P, C.c_int, C.POINTER(pic_tuning), C.POINTER(C.c_double), C.c_int,
                                    C.POINTER(C.c_int)]
+        L.pic_average.argtypes = [P, C.c_int, C.c_int]
+        L.pic_average_read.argtypes = [P, C.c_int, C.c_int, C.c_uint, C.POINTER(P), C.c_int,
+                                       C.POINTER(C.c_int64)]
         for name in ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_get_state",
                      "pic_set_state", "pic_get_counters", "pic_derived", "pic_profile_enable",
-                     "pic_profile_read", "pic_get_tuning", "pic_set_tuning", "pic_autotune"):
+                     "pic_profile_read", "pic_get_tuning", "pic_set_tuning", "pic_autotune",
+                     "pic_average", "pic_average_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -184,6 +189,21 @@ def pic_fields(ctx, replica, what, outs, out_on_device=False):
     for i, o in enumerate(outs):
         ptrs[i] = o.data_ptr() if hasattr(o, "data_ptr") else o.ctypes.data
     _check(lib().pic_fields(ctx, replica, what, ptrs, 1 if out_on_device else 0), ctx)
+
+
+def pic_average(ctx, interval, phase_bins=1):
+    _check(lib().pic_average(ctx, int(interval), int(phase_bins)), ctx)
+
+
+def pic_average_read(ctx, replica, bin, what, outs, out_on_device=False):
+    """outs: buffers in PHI, N, FLUX order; returns the number of samples."""
+    ptrs = (C.c_void_p * max(len(outs), 1))()
+    for i, o in enumerate(outs):
+        ptrs[i] = o.data_ptr() if hasattr(o, "data_ptr") else o.ctypes.data
+    n = C.c_int64(0)
+    _check(lib().pic_average_read(ctx, replica, bin, what, ptrs, 1 if out_on_device else 0,
+                                  C.byref(n)), ctx)
+    return int(n.value)
 
 
 def pic_destroy(ctx):
@@ -330,6 +350,23 @@ class Simulation:
                 names.append(name)
         pic_fields(self.ctx, replica, what, outs, False)
         return dict(zip(names, outs))
+
+    def average(self, interval, phase_bins=1):
+        """Start (interval > 0) or stop (0) sampling the time averages."""
+        pic_average(self.ctx, interval, phase_bins)
+
+    def averages(self, replica=0, bin=-1, what=PIC_PHI | PIC_N | PIC_FLUX):
+        nn = self.n_nodes[replica]
+        outs, names = [], []
+        for bit, name, shape in ((PIC_PHI, "phi", (nn,)), (PIC_N, "n", (2, nn)),
+                                 (PIC_FLUX, "flux", (2, 3, nn))):
+            if what & bit:
+                outs.append(np.zeros(shape))
+                names.append(name)
+        n = pic_average_read(self.ctx, replica, bin, what, outs, False)
+        out = dict(zip(names, outs))
+        out["samples"] = n
+        return out
 
     def get_state(self, replica=0):
         cap = [self.capacity[replica]] * 2
