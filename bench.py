@@ -36,10 +36,10 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_00972_amd", "csrc", f)
                   for f in ("particles.hip", "device_common.hpp", "pic_types.hpp")]
 
 
-def traffic_per_particle_step(kernel):
+def traffic_per_particle_step(kernel, workload):
     """HBM bytes per particle-step of the push kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE record, if it was taken on the current
-    kernel sources (else None)."""
+    kernel sources and this workload (else None)."""
     import hashlib
     if kernel != "push_fp32r" or not os.path.exists(TRAFFIC_PROFILE):
         return None
@@ -47,7 +47,7 @@ def traffic_per_particle_step(kernel):
     for line in open(TRAFFIC_PROFILE):
         if line.startswith("traffic-record:"):
             rec = json.loads(line.split(":", 1)[1])
-    if rec is None:
+    if rec is None or rec.get("workload") != workload:
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -131,7 +131,7 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
     alg_bytes = particle_steps * 2 * RECORD_BYTES[prec] + steps * nn * NODE_BYTES[prec]
     achieved = alg_bytes / (push_ms * 1e-3) / 1e9 if push_ms > 0 else 0.0
     kernel = "push_batch_f32r" if tuning.get("batch_push") else "push_" + prec
-    tpps = traffic_per_particle_step(kernel)
+    tpps = traffic_per_particle_step(kernel, wls[0]["name"] if len(wls) == 1 else "ensemble")
     traffic = tpps * particle_steps / max(push_n, 1) if tpps else None
     res = dict(
         value=tuned_ps / (t3 - t2),
@@ -208,6 +208,10 @@ def cpu_baseline(wl, steps=6):
 
 def form_workloads(form, workload):
     from paper_1801_00972_amd import workloads as W
+    if workload == "large":
+        if form != "fp32r":
+            raise SystemExit("the large workload (128x128x512, 16 ppc, 64 grains) is FP32R only")
+        return [W.large_fp32r()]
     if form == "batched":
         return W.ensemble() if workload == "full" else W.small_ensemble()
     return [W.full_fp64(form) if workload == "full" else dict(W.small_fp64(), precision=form)]
@@ -218,7 +222,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["full", "small"], default="full")
+    ap.add_argument("--workload", choices=["full", "small", "large"], default="full")
     ap.add_argument("--forms", default="fp32r,fp64,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -237,6 +241,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    if args.workload == "large":
+        forms = ["fp32r"]
     results = {}
     for form in forms:
         wls = form_workloads(form, args.workload)
@@ -282,7 +288,10 @@ def main():
     cb = copy_bandwidth()
     line["copy_bandwidth"] = cb
     line["roofline"]["frac_of_measured_copy"] = round(R["roofline"]["achieved"] / cb["GBs"], 4)
-    if not args.no_cpu_baseline:
+    if args.workload == "large":
+        # 2.7e8 FP64 oracle particles take ~15 GB and minutes per step: not a bounded sample
+        line["cpu_baseline"] = None
+    elif not args.no_cpu_baseline:
         cb = cpu_baseline(W.full_fp64("fp64") if args.workload == "full" else W.small_fp64())
         line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)

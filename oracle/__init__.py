@@ -297,13 +297,25 @@ class Oracle:
             out["rho_fixed"] = rf
         return out
 
-    def unit_fields(self) -> np.ndarray:
+    def unit_fields(self, progress=None) -> np.ndarray:
+        """The grains' unit-charge fields on their cubes.  With a progress
+        callback they are computed one grain at a time (each grain's field
+        depends on its own position only) and progress(g) is called after
+        grain g."""
         side = 2 * self.cfg.cutoff + 2
         U = np.zeros((self.n_grains, 3, side, side, side))
-        if self.n_grains:
+        if self.n_grains and progress is None:
             rc = lib().orc_unit_fields(C.byref(self.cfg), _ptr(U, C.c_double))
             if rc:
                 raise RuntimeError(f"orc_unit_fields failed ({rc})")
+        for g in range(self.n_grains if progress is not None else 0):
+            one = Oracle(dict(self.wl, grain_pos=self.grain_pos[g:g + 1]), flags=self.flags)
+            Ug = np.zeros((1, 3, side, side, side))
+            rc = lib().orc_unit_fields(C.byref(one.cfg), _ptr(Ug, C.c_double))
+            if rc:
+                raise RuntimeError(f"orc_unit_fields failed ({rc})")
+            U[g] = Ug[0]
+            progress(g)
         return U
 
     def md_grains(self, i: int, j: int, k: int):
@@ -311,11 +323,11 @@ class Oracle:
         n = lib().orc_md_grains(C.byref(self.cfg), i, j, k, out, 64)
         return [out[t] for t in range(min(n, 64))]
 
-    def _units(self):
+    def _units(self, progress=None):
         if self.n_grains == 0 or (self.flags & NO_MESH):
             return None
         if self._U is None:
-            self._U = np.ascontiguousarray(self.unit_fields())
+            self._U = np.ascontiguousarray(self.unit_fields(progress))
         return self._U
 
     def step(self, n: int = 1):

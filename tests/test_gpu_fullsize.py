@@ -19,11 +19,13 @@ TOL = {"fp64": 1e-12, "fp32r": 1e-5}
 def _select(pos, grains, nz, rng, n_uniform=2000, n_grain=1500, n_wall=500):
     n = len(pos)
     pick = [rng.choice(n, size=min(n_uniform, n), replace=False)]
-    d2 = np.full(n, np.inf)
+    grains = np.asarray(grains)
+    box = np.flatnonzero(np.all((pos >= grains.min(0) - 3.5) & (pos <= grains.max(0) + 3.5), axis=1))
+    d2 = np.full(len(box), np.inf)
     for g in grains:
-        d = pos - g
+        d = pos[box] - g
         d2 = np.minimum(d2, np.sum(d * d, axis=1))
-    near = np.flatnonzero(d2 < 3.5 ** 2)
+    near = box[d2 < 3.5 ** 2]
     if len(near):
         pick.append(rng.choice(near, size=min(n_grain, len(near)), replace=False))
     wall = np.flatnonzero((pos[:, 2] < 0.3) | (pos[:, 2] > nz - 0.3))
