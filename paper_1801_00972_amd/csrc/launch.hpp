@@ -28,14 +28,20 @@ void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const M
 // start[d] is the first work item (tile) of descriptor d, start[ndesc] the total
 void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int ndesc, int grid,
                             hipStream_t st);
-// the listed particles: outliers, sub-cycled MD motion (with its collision and
-// deposit), then the collisions of the candidates
-void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
-                      const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
-                      hipStream_t st);
-void launch_lists_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
-                       const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
-                       hipStream_t st);
+// the collisions of one species' push candidates (right after its push)
+void launch_collide_f64(const PartF64& P, const SpeciesStep& S, const WorkLists& L,
+                        hipStream_t st);
+void launch_collide_f32r(const PartF32R& P, const SpeciesStep& S, const WorkLists& L,
+                         hipStream_t st);
+// the listed particles of both species of a replica, after both pushes:
+// outliers and sub-cycled MD motion (each with its collision and deposit);
+// each kernel covers both species in one launch
+void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const MdTables& md,
+                      const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
+                      int do_mcc, hipStream_t st);
+void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, const MdTables& md,
+                       const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
+                       int do_mcc, hipStream_t st);
 // the corrected node fields of the MD cells (after E_k and the grain charges)
 void launch_md_field(const void* E, int e_f64, const MdTables& md, int nx, int ny, hipStream_t st);
 void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,

@@ -703,7 +703,8 @@ __device__ __forceinline__ bool window_meets_md(const Tile& w, const MdTables& m
 // the new positions are deposited into the LDS window (per-thread sums over a
 // run of particles in one cell first), whose occupied nodes are then added to
 // rho.  Particles starting inside an MD cube are left untouched and listed for
-// the sub-cycled kernel; candidates are listed for the collision kernel.
+// the sub-cycled kernel; candidates are listed for the collision kernel, which
+// runs right after the push while the records it wrote are still in cache.
 constexpr int kWinF32 = 1331;  // window capacity (nodes): a tile with a 3-cell margin
 
 // LDS of one push block (FP32R)
@@ -1248,17 +1249,22 @@ __device__ __forceinline__ void deposit_wave(A* __restrict__ rho, const SpeciesS
 __device__ __forceinline__ void kill(const PartF64& P, long p) { P.z[p] = -1.0; }
 __device__ __forceinline__ void kill(const PartF32R& P, long p) { P.cell[p] = -1; }
 
-// one thread per MD particle of the dense list of this step; events go to the
+// one thread per MD particle of the dense list of this step, both species in
+// one launch (blocks [0, nb) electrons, [nb, 2 nb) ions); events go to the
 // block's own tally row, grain hits to LDS counters first
 constexpr int kMdThreads = 64;
 template <typename PT, typename ET, typename RT>
-__global__ __launch_bounds__(kMdThreads) void md_kernel(PT P, const ET* __restrict__ E,
+__global__ __launch_bounds__(kMdThreads) void md_kernel(SpeciesPair<PT> pr, const ET* __restrict__ E,
                                                         RT* __restrict__ rho, MdTables md,
-                                                        SpeciesStep S,
                                                         unsigned long long* __restrict__ grain_count,
-                                                        WorkLists L, int do_mcc) {
+                                                        int do_mcc) {
+  const int sp = (int)blockIdx.x >= pr.nb;
+  const PT P = pr.P[sp];
+  const SpeciesStep S = pr.S[sp];
+  const WorkLists L = pr.L[sp];
+  const int bid = (int)blockIdx.x - sp * pr.nb;
   const int total = L.cnt[2];
-  if ((long)blockIdx.x * kMdThreads >= total) return;
+  if ((long)bid * kMdThreads >= total) return;
   constexpr int kStage = 256;
   __shared__ double s_gpos[3 * kStage], s_Qc[kStage];
   __shared__ unsigned s_hits[kStage];
@@ -1271,8 +1277,7 @@ __global__ __launch_bounds__(kMdThreads) void md_kernel(PT P, const ET* __restri
   const GrainView G = md.n_grains <= kStage ? GrainView{s_gpos, s_Qc, 1.0}
                                             : GrainView{md.gpos, md.Q, S.coul_c};
   int n_w0 = 0, n_w1 = 0, n_bad = 0, n_coll = 0, n_cap = 0, n_dead = 0;
-  for (long base = (long)blockIdx.x * kMdThreads; base < total;
-       base += (long)gridDim.x * kMdThreads) {
+  for (long base = (long)bid * kMdThreads; base < total; base += (long)pr.nb * kMdThreads) {
     const long idx = base + threadIdx.x;
     int st = ST_NONE, cell = -1;
     bool coll = false, capv = false;
@@ -1307,7 +1312,7 @@ __global__ __launch_bounds__(kMdThreads) void md_kernel(PT P, const ET* __restri
 #pragma unroll
   for (int k = 0; k < 6; ++k) c6[k] = wave_sum(c6[k]);
   if (threadIdx.x == 0) {  // this block's own tally row (no atomics)
-    unsigned long long* tally = L.tally + (long)TL_N * (L.ngrid + blockIdx.x);
+    unsigned long long* tally = L.tally + (long)TL_N * (L.ngrid + bid);
     const int kinds[6] = {TL_W0, TL_W1, TL_BAD, TL_COLL, TL_CAP, TL_DEAD};
     for (int k = 0; k < 6; ++k)
       if (c6[k]) tally[kinds[k]] += (unsigned long long)c6[k];
@@ -1318,8 +1323,11 @@ __global__ __launch_bounds__(kMdThreads) void md_kernel(PT P, const ET* __restri
 }
 
 // the dense MD list starts empty for the next step
-__global__ void md_reset_kernel(int32_t* cnt) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) cnt[2] = 0;
+__global__ void md_reset_kernel(int32_t* cnt0, int32_t* cnt1) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    cnt0[2] = 0;
+    cnt1[2] = 0;
+  }
 }
 
 // ---------------------------------------------------------------- moments
@@ -1381,10 +1389,14 @@ __global__ __launch_bounds__(256) void moments_kernel(PT P, SpeciesStep S, WorkL
 // last sort): the same push with the field gathered from global memory and the
 // charge deposited with global atomics, the collision done in place.  One wave
 // per tile segment.
-__global__ __launch_bounds__(64) void outlier_f32r_kernel(PartF32R P, const float4* __restrict__ E,
-                                                          long long* __restrict__ rho,
-                                                          SpeciesStep S, WorkLists L, int do_mcc) {
-  const int tidx = blockIdx.x;
+__global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> pr,
+                                                          const float4* __restrict__ E,
+                                                          long long* __restrict__ rho, int do_mcc) {
+  const int sp = (int)blockIdx.x >= pr.nb;
+  const PartF32R P = pr.P[sp];
+  const SpeciesStep S = pr.S[sp];
+  const WorkLists L = pr.L[sp];
+  const int tidx = (int)blockIdx.x - sp * pr.nb;
   const int count = L.out_cnt[tidx];
   if (count == 0) return;
   const int32_t* seg = L.out + L.tstart[tidx];
@@ -1453,10 +1465,14 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(PartF32R P, const floa
   }
 }
 
-__global__ __launch_bounds__(64) void outlier_f64_kernel(PartF64 P, const double2* __restrict__ E,
-                                                         double* __restrict__ rho, SpeciesStep S,
-                                                         WorkLists L, int do_mcc) {
-  const int tidx = blockIdx.x;
+__global__ __launch_bounds__(64) void outlier_f64_kernel(SpeciesPair<PartF64> pr,
+                                                         const double2* __restrict__ E,
+                                                         double* __restrict__ rho, int do_mcc) {
+  const int sp = (int)blockIdx.x >= pr.nb;
+  const PartF64 P = pr.P[sp];
+  const SpeciesStep S = pr.S[sp];
+  const WorkLists L = pr.L[sp];
+  const int tidx = (int)blockIdx.x - sp * pr.nb;
   const int count = L.out_cnt[tidx];
   if (count == 0) return;
   const int32_t* seg = L.out + L.tstart[tidx];
@@ -1980,32 +1996,46 @@ void launch_md_field(const void* E, int e_f64, const MdTables& md, int nx, int n
                        (const float4*)E, md, nx, ny, nx * ny);
 }
 
-void launch_lists_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
-                      const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
-                      hipStream_t st) {
-  if (L.ngrid <= 0) return;
-  const int nc = L.ngrid;
-  hipLaunchKernelGGL(outlier_f64_kernel, dim3(nc), dim3(64), 0, st, P, (const double2*)E, rho, S, L,
-                     do_mcc);
-  if (md.n_grains > 0)
-    hipLaunchKernelGGL((md_kernel<PartF64, double2, double>), dim3(kMdBlocks), dim3(kMdThreads), 0, st, P,
-                       (const double2*)E, rho, md, S, gc, L, do_mcc);
-  hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L.cnt);
-  if (do_mcc) hipLaunchKernelGGL(collide_kernel<PartF64>, dim3(nc), dim3(64), 0, st, P, S, L);
+void launch_collide_f64(const PartF64& P, const SpeciesStep& S, const WorkLists& L,
+                        hipStream_t st) {
+  if (L.ngrid > 0)
+    hipLaunchKernelGGL(collide_kernel<PartF64>, dim3(L.ngrid), dim3(64), 0, st, P, S, L);
 }
 
-void launch_lists_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
-                       const SpeciesStep& S, unsigned long long* gc, const WorkLists& L, int do_mcc,
-                       hipStream_t st) {
-  if (L.ngrid <= 0) return;
-  const int nc = L.ngrid;
-  hipLaunchKernelGGL(outlier_f32r_kernel, dim3(nc), dim3(64), 0, st, P, (const float4*)E, rho, S,
-                     L, do_mcc);
-  if (md.n_grains > 0)
-    hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(kMdBlocks), dim3(kMdThreads), 0, st,
-                       P, (const float4*)E, rho, md, S, gc, L, do_mcc);
-  hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L.cnt);
-  if (do_mcc) hipLaunchKernelGGL(collide_kernel<PartF32R>, dim3(nc), dim3(64), 0, st, P, S, L);
+void launch_collide_f32r(const PartF32R& P, const SpeciesStep& S, const WorkLists& L,
+                         hipStream_t st) {
+  if (L.ngrid > 0)
+    hipLaunchKernelGGL(collide_kernel<PartF32R>, dim3(L.ngrid), dim3(64), 0, st, P, S, L);
+}
+
+void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const MdTables& md,
+                      const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
+                      int do_mcc, hipStream_t st) {
+  if (L[0].ngrid <= 0) return;
+  SpeciesPair<PartF64> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, L[0].ngrid};
+  hipLaunchKernelGGL(outlier_f64_kernel, dim3(2 * pr.nb), dim3(64), 0, st, pr, (const double2*)E,
+                     rho, do_mcc);
+  if (md.n_grains > 0) {
+    pr.nb = kMdBlocks;
+    hipLaunchKernelGGL((md_kernel<PartF64, double2, double>), dim3(2 * kMdBlocks), dim3(kMdThreads),
+                       0, st, pr, (const double2*)E, rho, md, gc, do_mcc);
+  }
+  hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L[0].cnt, L[1].cnt);
+}
+
+void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, const MdTables& md,
+                       const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
+                       int do_mcc, hipStream_t st) {
+  if (L[0].ngrid <= 0) return;
+  SpeciesPair<PartF32R> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, L[0].ngrid};
+  hipLaunchKernelGGL(outlier_f32r_kernel, dim3(2 * pr.nb), dim3(64), 0, st, pr, (const float4*)E,
+                     rho, do_mcc);
+  if (md.n_grains > 0) {
+    pr.nb = kMdBlocks;
+    hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(2 * kMdBlocks),
+                       dim3(kMdThreads), 0, st, pr, (const float4*)E, rho, md, gc, do_mcc);
+  }
+  hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L[0].cnt, L[1].cnt);
 }
 
 void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,

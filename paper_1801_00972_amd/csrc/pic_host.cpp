@@ -577,32 +577,38 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
   const int rnx = 1 - R.rho_cur;
   const int do_mcc = 1;
+  const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
   if (R.prec == PIC_FP64) {
     launch_zero_f64((double*)R.rho[rnx], R.nn, st);
+    const PartF64 P[2] = {R.p64[0][R.cur[0]], R.p64[1][R.cur[1]]};
     for (int sp = 0; sp < 2; ++sp) {
-      const SpeciesStep S = species_step(R, sp);
-      const PartF64& P = R.p64[sp][R.cur[sp]];
       hipEvent_t a = prof_event(ctx);
-      launch_push_f64(P, (const double*)R.E, (double*)R.rho[rnx], R.md, S, R.lists[sp], st);
+      launch_push_f64(P[sp], (const double*)R.E, (double*)R.rho[rnx], R.md, S[sp], R.lists[sp], st);
       hipEvent_t b = prof_event(ctx);
-      launch_lists_f64(P, (const double*)R.E, (double*)R.rho[rnx], R.md, S, R.d_gc, R.lists[sp],
-                       do_mcc, st);
+      launch_collide_f64(P[sp], S[sp], R.lists[sp], st);
       prof_pair(ctx, PIC_PROF_PUSH, a, b);
       prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
+    hipEvent_t b = prof_event(ctx);
+    launch_lists_f64(P, (const double*)R.E, (double*)R.rho[rnx], R.md, S, R.d_gc, R.lists, do_mcc,
+                     st);
+    prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
   } else {
     launch_zero_i64((long long*)R.rho[rnx], R.nn, st);
+    const PartF32R P[2] = {R.p32[0][R.cur[0]], R.p32[1][R.cur[1]]};
     for (int sp = 0; sp < 2; ++sp) {
-      const SpeciesStep S = species_step(R, sp);
-      const PartF32R& P = R.p32[sp][R.cur[sp]];
       hipEvent_t a = prof_event(ctx);
-      launch_push_f32r(P, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.lists[sp], st);
+      launch_push_f32r(P[sp], (const float*)R.E, (long long*)R.rho[rnx], R.md, S[sp], R.lists[sp],
+                       st);
       hipEvent_t b = prof_event(ctx);
-      launch_lists_f32r(P, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc, R.lists[sp],
-                        do_mcc, st);
+      launch_collide_f32r(P[sp], S[sp], R.lists[sp], st);
       prof_pair(ctx, PIC_PROF_PUSH, a, b);
       prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
+    hipEvent_t b = prof_event(ctx);
+    launch_lists_f32r(P, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc, R.lists,
+                      do_mcc, st);
+    prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
   }
   launch_advance_step(R.d_step, st);
   CHECK_LAUNCH(ctx);
@@ -635,9 +641,11 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   hipEvent_t b = prof_event(ctx);
   for (auto& R : ctx->reps) {
     const int rnx = 1 - R->rho_cur;
-    for (int sp = 0; sp < 2; ++sp)
-      launch_lists_f32r(R->p32[sp][R->cur[sp]], (const float*)R->E, (long long*)R->rho[rnx], R->md,
-                        species_step(*R, sp), R->d_gc, R->lists[sp], 1, st);
+    const PartF32R P[2] = {R->p32[0][R->cur[0]], R->p32[1][R->cur[1]]};
+    const SpeciesStep S[2] = {species_step(*R, 0), species_step(*R, 1)};
+    for (int sp = 0; sp < 2; ++sp) launch_collide_f32r(P[sp], S[sp], R->lists[sp], st);
+    launch_lists_f32r(P, (const float*)R->E, (long long*)R->rho[rnx], R->md, S, R->d_gc, R->lists, 1,
+                      st);
     launch_advance_step(R->d_step, st);
   }
   CHECK_LAUNCH(ctx);

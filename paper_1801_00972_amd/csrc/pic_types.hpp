@@ -106,6 +106,16 @@ struct SpeciesStep {
 };
 
 // one (replica, species) of a batched push launch
+// both species of one replica for the kernels that follow the push: blocks
+// [0, nb) of a launch work on species 0, [nb, 2 nb) on species 1
+template <typename PT>
+struct SpeciesPair {
+  PT P[2];
+  SpeciesStep S[2];
+  WorkLists L[2];
+  int nb;
+};
+
 // rf-phase binning of the time averages: sums of step k go to bin
 // phase_bin(k), `stride` doubles apart; step == nullptr means no binning
 struct AvgBins {
