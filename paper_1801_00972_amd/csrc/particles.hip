@@ -1251,13 +1251,14 @@ __device__ __forceinline__ void kill(const PartF32R& P, long p) { P.cell[p] = -1
 
 // one thread per MD particle of the dense list of this step, both species in
 // one launch (blocks [0, nb) electrons, [nb, 2 nb) ions); events go to the
-// block's own tally row, grain hits to LDS counters first
+// block's own tally row, grain hits to LDS counters first.  The survivors'
+// collisions follow in md_collide_kernel (kept out of this kernel so that its
+// registers allow three waves per SIMD).
 constexpr int kMdThreads = 64;
 template <typename PT, typename ET, typename RT>
 __global__ __launch_bounds__(kMdThreads) void md_kernel(SpeciesPair<PT> pr, const ET* __restrict__ E,
                                                         RT* __restrict__ rho, MdTables md,
-                                                        unsigned long long* __restrict__ grain_count,
-                                                        int do_mcc) {
+                                                        unsigned long long* __restrict__ grain_count) {
   const int sp = (int)blockIdx.x >= pr.nb;
   const PT P = pr.P[sp];
   const SpeciesStep S = pr.S[sp];
@@ -1276,11 +1277,10 @@ __global__ __launch_bounds__(kMdThreads) void md_kernel(SpeciesPair<PT> pr, cons
   __syncthreads();
   const GrainView G = md.n_grains <= kStage ? GrainView{s_gpos, s_Qc, 1.0}
                                             : GrainView{md.gpos, md.Q, S.coul_c};
-  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_coll = 0, n_cap = 0, n_dead = 0;
+  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_dead = 0;
   for (long base = (long)bid * kMdThreads; base < total; base += (long)pr.nb * kMdThreads) {
     const long idx = base + threadIdx.x;
     int st = ST_NONE, cell = -1;
-    bool coll = false, capv = false;
     RT part[8];
     if (idx < total) {
       const long p = L.md[idx];
@@ -1292,7 +1292,6 @@ __global__ __launch_bounds__(kMdThreads) void md_kernel(SpeciesPair<PT> pr, cons
         if (hit < kStage) atomicAdd(&s_hits[hit], 1u);
         else atomicAdd(&grain_count[2 * hit + S.sp], 1ull);
       }
-      if (st == ST_ALIVE && do_mcc) collide(S, P.id[p], v, coll, capv);
       if (st == ST_ALIVE) {
         cell = store_d(P, p, x, v, S, part);
         if (cell < 0) st = ST_WALL1;
@@ -1304,18 +1303,17 @@ __global__ __launch_bounds__(kMdThreads) void md_kernel(SpeciesPair<PT> pr, cons
     n_w0 += st == ST_WALL0;
     n_w1 += st == ST_WALL1;
     n_bad += st == ST_BAD;
-    n_coll += coll;
-    n_cap += capv;
     n_dead += st == ST_WALL0 || st == ST_WALL1 || st == ST_BAD || st == ST_GRAIN;
   }
-  int c6[6] = {n_w0, n_w1, n_bad, n_coll, n_cap, n_dead};
+  int c4[4] = {n_w0, n_w1, n_bad, n_dead};
 #pragma unroll
-  for (int k = 0; k < 6; ++k) c6[k] = wave_sum(c6[k]);
+  for (int k = 0; k < 4; ++k) c4[k] = wave_sum(c4[k]);
   if (threadIdx.x == 0) {  // this block's own tally row (no atomics)
     unsigned long long* tally = L.tally + (long)TL_N * (L.ngrid + bid);
-    const int kinds[6] = {TL_W0, TL_W1, TL_BAD, TL_COLL, TL_CAP, TL_DEAD};
-    for (int k = 0; k < 6; ++k)
-      if (c6[k]) tally[kinds[k]] += (unsigned long long)c6[k];
+    const int kinds[4] = {TL_W0, TL_W1, TL_BAD, TL_DEAD};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (c4[k]) tally[kinds[k]] += (unsigned long long)c4[k];
   }
   __syncthreads();
   for (int t = threadIdx.x; t < min(md.n_grains, kStage); t += blockDim.x)
@@ -1381,6 +1379,42 @@ __global__ __launch_bounds__(256) void moments_kernel(PT P, SpeciesStep S, WorkL
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (s_m[q][u] != 0.0) unsafeAtomicAdd(&mom[q * nn + node], s_m[q][u]);
+  }
+}
+
+// The collisions of the MD particles that survived their sub-cycled motion,
+// from their stored velocities (same list, blocks and tally rows as md_kernel).
+template <typename PT>
+__global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> pr) {
+  const int sp = (int)blockIdx.x >= pr.nb;
+  const PT P = pr.P[sp];
+  const SpeciesStep S = pr.S[sp];
+  const WorkLists L = pr.L[sp];
+  const int bid = (int)blockIdx.x - sp * pr.nb;
+  const int total = L.cnt[2];
+  if ((long)bid * kMdThreads >= total) return;
+  int n_coll = 0, n_cap = 0;
+  for (long idx = (long)bid * kMdThreads + threadIdx.x; idx < total;
+       idx += (long)pr.nb * kMdThreads) {
+    const long p = L.md[idx];
+    if (!slot_alive(P, p)) continue;
+    bool coll = false, capv = false;
+    double v[3] = {(double)P.vx[p], (double)P.vy[p], (double)P.vz[p]};
+    collide(S, P.id[p], v, coll, capv);
+    if (coll) {
+      P.vx[p] = v[0];
+      P.vy[p] = v[1];
+      P.vz[p] = v[2];
+    }
+    n_coll += coll;
+    n_cap += capv;
+  }
+  n_coll = wave_sum(n_coll);
+  n_cap = wave_sum(n_cap);
+  if (threadIdx.x == 0) {
+    unsigned long long* tally = L.tally + (long)TL_N * (L.ngrid + bid);
+    if (n_coll) tally[TL_COLL] += (unsigned long long)n_coll;
+    if (n_cap) tally[TL_CAP] += (unsigned long long)n_cap;
   }
 }
 
@@ -2018,7 +2052,10 @@ void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const Md
   if (md.n_grains > 0) {
     pr.nb = kMdBlocks;
     hipLaunchKernelGGL((md_kernel<PartF64, double2, double>), dim3(2 * kMdBlocks), dim3(kMdThreads),
-                       0, st, pr, (const double2*)E, rho, md, gc, do_mcc);
+                       0, st, pr, (const double2*)E, rho, md, gc);
+    if (do_mcc)
+      hipLaunchKernelGGL(md_collide_kernel<PartF64>, dim3(2 * kMdBlocks), dim3(kMdThreads), 0, st,
+                         pr);
   }
   hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L[0].cnt, L[1].cnt);
 }
@@ -2033,7 +2070,10 @@ void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, cons
   if (md.n_grains > 0) {
     pr.nb = kMdBlocks;
     hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(2 * kMdBlocks),
-                       dim3(kMdThreads), 0, st, pr, (const float4*)E, rho, md, gc, do_mcc);
+                       dim3(kMdThreads), 0, st, pr, (const float4*)E, rho, md, gc);
+    if (do_mcc)
+      hipLaunchKernelGGL(md_collide_kernel<PartF32R>, dim3(2 * kMdBlocks), dim3(kMdThreads), 0, st,
+                         pr);
   }
   hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L[0].cnt, L[1].cnt);
 }
