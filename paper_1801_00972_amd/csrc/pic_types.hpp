@@ -105,7 +105,6 @@ struct SpeciesStep {
   long long isign;
 };
 
-// one (replica, species) of a batched push launch
 // both species of one replica for the kernels that follow the push: blocks
 // [0, nb) of a launch work on species 0, [nb, 2 nb) on species 1
 template <typename PT>
@@ -125,6 +124,7 @@ struct AvgBins {
   long stride;
 };
 
+// one (replica, species) of a batched push launch
 struct PushDescF32 {
   PartF32R P;
   const float4* E;
