@@ -634,6 +634,32 @@ __device__ __forceinline__ void chunk_append(bool flag, int32_t* seg, int* s_n, 
   if (flag) seg[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
 }
 
+// the same for the slots p0 .. p0 + kPPT - 1 of every lane at once: one LDS
+// reservation for the whole wave (entries lane-ordered per q); every lane of
+// the wave must take part.  (Used by the FP64 push; in the FP32R push the
+// flags' registers cost more than the atomics saved.)
+__device__ __forceinline__ void chunk_append4(const bool (&flag)[kPPT], int32_t* seg, int* s_n,
+                                              int p0) {
+  unsigned long long m[kPPT];
+  int total = 0;
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    m[q] = __ballot(flag[q]);
+    total += __popcll(m[q]);
+  }
+  if (!total) return;
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(s_n, total);
+  base = __shfl(base, 0, 64);
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    if (flag[q]) seg[base + __popcll(m[q] & below)] = p0 + q;
+    base += __popcll(m[q]);
+  }
+}
+
 // block-level tallies: wave sums into LDS; thread 0 then adds them to the
 // tile's own accumulators (each tile has one writer per kernel: no atomics)
 __device__ __forceinline__ void tally_add(unsigned* s_t, int which, int v) {
@@ -1060,11 +1086,17 @@ __global__ __launch_bounds__(kBlock, 3) void push_f64_kernel(PartF64 P, const do
       }
     }
     if (kMove) {
+      bool is_md[kPPT], is_out[kPPT];
 #pragma unroll
       for (int q = 0; q < kPPT; ++q) {
-        chunk_append(st[q] == ST_MD, s_md, &s_nmd, p0 + q);
-        chunk_append(cand[q], L.coll + beg, &s_ncoll, p0 + q);
-        chunk_append(st[q] == ST_OUT, L.out + beg, &s_nout, p0 + q);
+        is_md[q] = st[q] == ST_MD;
+        is_out[q] = st[q] == ST_OUT;
+      }
+      chunk_append4(is_md, s_md, &s_nmd, p0);
+      chunk_append4(cand, L.coll + beg, &s_ncoll, p0);
+      chunk_append4(is_out, L.out + beg, &s_nout, p0);
+#pragma unroll
+      for (int q = 0; q < kPPT; ++q) {
         n_out += st[q] == ST_OUT;
         n_w0 += st[q] == ST_WALL0;
         n_w1 += st[q] == ST_WALL1;
