@@ -14,8 +14,9 @@ struct FftPlanHost {
 };
 
 // particles: arrays binned by 4x4x4-cell tile and updated in place (see
-// WorkLists); one push block per tile, the grid padded to a multiple of 8
-int tile_grid(int nx, int ny, int nz);      // tiles rounded up to a multiple of 8
+// WorkLists); one push block per tile or pair of tiles, the grid padded to a
+// multiple of 16
+int tile_grid(int nx, int ny, int nz);      // tiles rounded up to a multiple of 16
 // blocks of the MD kernel; each owns a tally row after the ngrid tile rows
 constexpr int kMdTallyRows = 4096;
 long sort_keys(int nx, int ny, int nz);     // ints of sort workspace (tile counts and cursors)

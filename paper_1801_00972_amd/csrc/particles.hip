@@ -490,16 +490,17 @@ struct Tile {
   bool on;
 };
 
-// the window of tile t: its cells plus m cells on each side, in nodes; the
-// margin shrinks until the window fits `cap` nodes
+// the window of tiles t .. t + span - 1 (consecutive along x): their cells
+// plus m cells on each side, in nodes; the margin shrinks until the window
+// fits `cap` nodes
 __device__ __forceinline__ Tile make_tile(int t, const WorkLists& L, int nx, int ny, int nz,
-                                          int margin, int cap) {
+                                          int margin, int cap, int span = 1) {
   Tile w;
   w.on = false;
   w.x0 = w.y0 = w.k0 = 0;
   w.tx = w.ty = w.tz = 0;
   const int ti = t % L.ntx, tj = (t / L.ntx) % L.nty, tk = t / (L.ntx * L.nty);
-  const int i0 = 4 * ti, ni = min(4, nx - i0), j0 = 4 * tj, nj = min(4, ny - j0);
+  const int i0 = 4 * ti, ni = min(4 * span, nx - i0), j0 = 4 * tj, nj = min(4, ny - j0);
   const int k0 = 4 * tk, nk = min(4, nz - k0);
   for (int m = margin; m >= 0; --m) {
     int x0 = i0 - m, tx = ni + 2 * m + 1;
@@ -742,20 +743,21 @@ struct PushSmemF32 {
   int32_t md[2 * kChunk];  // MD slots of up to two passes
 };
 
+// A block takes `span` tiles that are consecutive along x (1 or 2): their
+// slots are one contiguous range and they share one window; the lists of the
+// span go to the first tile's segments, the others' counts are zero.
 template <bool kMove>
 __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* __restrict__ E,
                                                long long* __restrict__ rho, const MdTables& md,
                                                const SpeciesStep& S, const WorkLists& L, int tidx,
-                                               PushSmemF32& sm) {
-  const int beg = L.tstart[tidx], end = L.tstart[tidx + 1];
-  if (beg >= end) {
-    if (kMove && threadIdx.x == 0) {
-      L.coll_cnt[tidx] = 0;
-      L.out_cnt[tidx] = 0;
-    }
-    return;
+                                               int span, PushSmemF32& sm) {
+  const int beg = L.tstart[tidx], end = L.tstart[tidx + span];
+  if (kMove && threadIdx.x < span) {
+    L.coll_cnt[tidx + threadIdx.x] = 0;
+    L.out_cnt[tidx + threadIdx.x] = 0;
   }
-  const Tile tile = make_tile(tidx, L, S.nx, S.ny, S.nz, S.margin, kWinF32);
+  if (beg >= end) return;
+  const Tile tile = make_tile(tidx, L, S.nx, S.ny, S.nz, S.margin, kWinF32, span);
   const int vol = tile.on ? tile.tx * tile.ty * tile.tz : 0;
   const float rtx = 1.0f / (float)max(tile.tx, 1), rtxy = 1.0f / (float)max(tile.tx * tile.ty, 1);
   for (int t = threadIdx.x; t < vol; t += kBlock) {
@@ -931,9 +933,10 @@ template <bool kMove>
 __global__ __launch_bounds__(kBlock, 4) void push_f32r_kernel(PartF32R P,
                                                            const float4* __restrict__ E,
                                                            long long* __restrict__ rho, MdTables md,
-                                                           SpeciesStep S, WorkLists L) {
+                                                           SpeciesStep S, WorkLists L, int span) {
   __shared__ PushSmemF32 sm;
-  push_tile_f32r<kMove>(P, E, rho, md, S, L, (int)xcd_chunk(blockIdx.x, gridDim.x), sm);
+  push_tile_f32r<kMove>(P, E, rho, md, S, L, span * (int)xcd_chunk(blockIdx.x, gridDim.x), span,
+                        sm);
 }
 
 // ---------------------------------------------------------------- push, ensemble
@@ -956,7 +959,7 @@ __global__ __launch_bounds__(kBlock, 4) void push_batch_f32r_kernel(const PushDe
     const int local = item - start[lo];
     const PushDescF32& d = descs[lo];
     push_tile_f32r<true>(d.P, d.E, d.rho, d.md, d.S, d.L,
-                         (int)xcd_chunk(local, start[lo + 1] - start[lo]), sm);
+                         (int)xcd_chunk(local, start[lo + 1] - start[lo]), 1, sm);
     __syncthreads();
   }
 }
@@ -2021,8 +2024,12 @@ __global__ void advance_step_kernel(uint32_t* step) {
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 int tile_grid(int nx, int ny, int nz) {
-  return (((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) + 7) / 8 * 8;
+  return (((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) + 15) / 16 * 16;
 }
+
+// tiles per FP32R push block: pairs along x where the rows of tiles split into
+// pairs (the grid, a multiple of 16, then still gives a multiple of 8 blocks)
+static inline int push_span(const WorkLists& L) { return L.ntx % 2 == 0 ? 2 : 1; }
 
 void launch_advance_step(uint32_t* step, hipStream_t st) {
   hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, step);
@@ -2038,8 +2045,9 @@ void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTab
 void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
                       const SpeciesStep& S, const WorkLists& L, hipStream_t st) {
   if (L.ngrid <= 0) return;
-  hipLaunchKernelGGL(push_f32r_kernel<true>, dim3(L.ngrid), dim3(kBlock), 0, st, P,
-                     (const float4*)E, rho, md, S, L);
+  const int span = push_span(L);
+  hipLaunchKernelGGL(push_f32r_kernel<true>, dim3(L.ngrid / span), dim3(kBlock), 0, st, P,
+                     (const float4*)E, rho, md, S, L, span);
 }
 
 void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int ndesc, int grid,
@@ -2134,8 +2142,9 @@ void launch_deposit_f64(const PartF64& P, double* rho, const MdTables& md, const
 void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
                          const SpeciesStep& S, const WorkLists& L, hipStream_t st) {
   if (L.ngrid <= 0) return;
-  hipLaunchKernelGGL(push_f32r_kernel<false>, dim3(L.ngrid), dim3(kBlock), 0, st, P, nullptr, rho,
-                     md, S, L);
+  const int span = push_span(L);
+  hipLaunchKernelGGL(push_f32r_kernel<false>, dim3(L.ngrid / span), dim3(kBlock), 0, st, P,
+                     nullptr, rho, md, S, L, span);
 }
 
 void launch_moments(const PartF64* P64, const PartF32R* P32, const SpeciesStep& S,

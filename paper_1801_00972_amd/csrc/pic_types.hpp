@@ -41,7 +41,7 @@ struct RfDrive {
 // The particle arrays are binned by tiles of 4x4x4 cells (tiles x fastest,
 // then y, then z): tile t owns slots [tstart[t], tstart[t+1]), a multiple of 4
 // long, ordered by cell inside the tile and padded with empty slots.  The
-// grid of tiles is padded to a multiple of 8 (the XCD count) with empty tiles.
+// grid of tiles is padded to a multiple of 16 (twice the XCD count) with empty tiles.
 // coll and out are segmented the same way: tile t's entries start at tstart[t].
 struct WorkLists {
   int32_t* md;        // dense list: slots of particles that start the step in an MD cube
