@@ -311,40 +311,74 @@ __global__ void md_field_kernel(const ET* __restrict__ E, MdTables md, int nx, i
 // is below the integer threshold of P' = 1 - exp(-n_g sigma g_cap dt); accept
 // with probability g / g_cap.  e-Ar: elastic, isotropic in the CM frame with
 // the neutral at rest.  Ar+-Ar: charge exchange, the ion takes the velocity of
-// the neutral drawn from the 300 K reservoir.
-__device__ __forceinline__ void collide(const SpeciesStep& S, uint32_t id, double v[3], bool& coll,
+// the neutral drawn from the 300 K reservoir.  T is the arithmetic of the
+// form: double for FP64; float for FP32R, whose velocities are FP32 (its
+// uniforms are the top 24 bits of the word plus one half, times 2^-24).
+template <typename PT>
+struct VelOf {
+  using type = double;
+};
+template <>
+struct VelOf<PartF32R> {
+  using type = float;
+};
+
+template <typename T>
+__device__ __forceinline__ T u01(uint32_t w) {
+  if constexpr (sizeof(T) == 8) return u01_open(w);
+  else return ((float)(w >> 8) + 0.5f) * 5.9604644775390625e-08f;
+}
+
+template <typename T>
+__device__ __forceinline__ void normal_pair_t(uint32_t wa, uint32_t wb, T& n0, T& n1) {
+  if constexpr (sizeof(T) == 8) {
+    normal_pair(wa, wb, n0, n1);
+  } else {
+    const float r = sqrtf(-2.0f * logf(u01<float>(wa)));
+    float sn, cs;
+    sincosf(2.0f * (float)kPi * u01<float>(wb), &sn, &cs);
+    n0 = r * cs;
+    n1 = r * sn;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void collide(const SpeciesStep& S, uint32_t id, T v[3], bool& coll,
                                         bool& capv) {
   const uint4 r = philox4x32_10(id, *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
   if ((uint64_t)r.x >= S.T_null) return;
-  double vn[3] = {0.0, 0.0, 0.0};
+  T vn[3] = {(T)0, (T)0, (T)0};
   if (S.sp == 1) {
     const uint4 q = philox4x32_10(id, *S.step, kNeutral, 1u, S.key0, S.key1);
-    double n0, n1, n2, n3;
-    normal_pair(q.x, q.y, n0, n1);
-    normal_pair(q.z, q.w, n2, n3);
-    vn[0] = S.vth_gas * n0;
-    vn[1] = S.vth_gas * n1;
-    vn[2] = S.vth_gas * n2;
+    T n0, n1, n2, n3;
+    normal_pair_t<T>(q.x, q.y, n0, n1);
+    normal_pair_t<T>(q.z, q.w, n2, n3);
+    const T vg = (T)S.vth_gas;
+    vn[0] = vg * n0;
+    vn[1] = vg * n1;
+    vn[2] = vg * n2;
   }
-  const double gx = v[0] - vn[0], gy = v[1] - vn[1], gz = v[2] - vn[2];
-  const double g = sqrt(gx * gx + gy * gy + gz * gz);
-  const double ratio = g / S.g_cap;
+  const T gx = v[0] - vn[0], gy = v[1] - vn[1], gz = v[2] - vn[2];
+  const T g = sqrt(gx * gx + gy * gy + gz * gz);
+  const T ratio = g / (T)S.g_cap;
   bool accept;
-  if (ratio > 1.0) {
+  if (ratio > (T)1) {
     capv = true;
     accept = true;
   } else {
-    accept = u01_open(r.y) < ratio;
+    accept = u01<T>(r.y) < ratio;
   }
   if (!accept) return;
   coll = true;
   if (S.sp == 0) {
-    const double cost = 1.0 - 2.0 * u01_open(r.z);
-    const double sint = sqrt(fmax(0.0, 1.0 - cost * cost));
-    double sp, cp;
-    sincos(2.0 * kPi * u01_open(r.w), &sp, &cp);
-    const double nh[3] = {sint * cp, sint * sp, cost};
-    for (int a = 0; a < 3; ++a) v[a] = S.mass_ratio_e * v[a] + S.mass_ratio_n * g * nh[a];
+    const T cost = (T)1 - (T)2 * u01<T>(r.z);
+    const T sint = sqrt(fmax((T)0, (T)1 - cost * cost));
+    T sp, cp;
+    if constexpr (sizeof(T) == 8) sincos(2.0 * kPi * u01<T>(r.w), &sp, &cp);
+    else sincosf(2.0f * (float)kPi * u01<T>(r.w), &sp, &cp);
+    const T nh[3] = {sint * cp, sint * sp, cost};
+    const T ae = (T)S.mass_ratio_e, an = (T)S.mass_ratio_n;
+    for (int a = 0; a < 3; ++a) v[a] = ae * v[a] + an * g * nh[a];
   } else {
     v[0] = vn[0];
     v[1] = vn[1];
@@ -940,9 +974,9 @@ __global__ __launch_bounds__(kBlock, 4) void push_f32r_kernel(PartF32R P,
 }
 
 // ---------------------------------------------------------------- push, ensemble
-// One persistent launch over the tiles of every (replica, species) of an
+// One persistent launch over the tile spans of every (replica, species) of an
 // ensemble: work item i belongs to descriptor d with start[d] <= i < start[d+1]
-// (each descriptor has a multiple of 8 tiles, so the XCD remapping stays a
+// (each descriptor has a multiple of 8 items, so the XCD remapping stays a
 // permutation per descriptor); blocks stride over the items.
 __global__ __launch_bounds__(kBlock, 4) void push_batch_f32r_kernel(const PushDescF32* __restrict__ descs,
                                                                  const int32_t* __restrict__ start,
@@ -959,7 +993,7 @@ __global__ __launch_bounds__(kBlock, 4) void push_batch_f32r_kernel(const PushDe
     const int local = item - start[lo];
     const PushDescF32& d = descs[lo];
     push_tile_f32r<true>(d.P, d.E, d.rho, d.md, d.S, d.L,
-                         (int)xcd_chunk(local, start[lo + 1] - start[lo]), 1, sm);
+                         d.span * (int)xcd_chunk(local, start[lo + 1] - start[lo]), d.span, sm);
     __syncthreads();
   }
 }
@@ -1434,7 +1468,7 @@ __global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> 
     const long p = L.md[idx];
     if (!slot_alive(P, p)) continue;
     bool coll = false, capv = false;
-    double v[3] = {(double)P.vx[p], (double)P.vy[p], (double)P.vz[p]};
+    typename VelOf<PT>::type v[3] = {P.vx[p], P.vy[p], P.vz[p]};
     collide(S, P.id[p], v, coll, capv);
     if (coll) {
       P.vx[p] = v[0];
@@ -1465,7 +1499,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> 
   const PartF32R P = pr.P[sp];
   const SpeciesStep S = pr.S[sp];
   const WorkLists L = pr.L[sp];
-  const int tidx = (int)blockIdx.x - sp * pr.nb;
+  const int tidx = ((int)blockIdx.x - sp * pr.nb) * pr.span;
   const int count = L.out_cnt[tidx];
   if (count == 0) return;
   const int32_t* seg = L.out + L.tstart[tidx];
@@ -1493,13 +1527,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> 
       if (do_mcc) {
         const uint32_t id = P.id[p];
         const uint4 r = philox4x32_10(id, *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
-        if ((uint64_t)r.x < S.T_null) {
-          double vd[3] = {v[0], v[1], v[2]};
-          collide(S, id, vd, coll, capv);
-          v[0] = (float)vd[0];
-          v[1] = (float)vd[1];
-          v[2] = (float)vd[2];
-        }
+        if ((uint64_t)r.x < S.T_null) collide(S, id, v, coll, capv);
       }
       t_coll += coll;
       t_cap += capv;
@@ -1594,10 +1622,11 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(SpeciesPair<PartF64> pr
 }
 
 // ---------------------------------------------------------------- collisions
-// One wave per tile segment of collision candidates.
+// One wave per push block's segment of collision candidates (the push block
+// of `span` tiles lists them at its first tile).
 template <typename PT>
-__global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLists L) {
-  const int tidx = blockIdx.x;
+__global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLists L, int span) {
+  const int tidx = (int)blockIdx.x * span;
   const int count = L.coll_cnt[tidx];
   if (count == 0) return;
   const int32_t* seg = L.coll + L.tstart[tidx];
@@ -1605,7 +1634,7 @@ __global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLi
   for (int idx = threadIdx.x; idx < count; idx += 64) {
     const long p = seg[idx];
     bool coll = false, capv = false;
-    double v[3] = {(double)P.vx[p], (double)P.vy[p], (double)P.vz[p]};
+    typename VelOf<PT>::type v[3] = {P.vx[p], P.vy[p], P.vz[p]};
     collide(S, P.id[p], v, coll, capv);
     if (coll) {
       P.vx[p] = v[0];
@@ -2027,9 +2056,6 @@ int tile_grid(int nx, int ny, int nz) {
   return (((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) + 15) / 16 * 16;
 }
 
-// tiles per FP32R push block: pairs along x where the rows of tiles split into
-// pairs (the grid, a multiple of 16, then still gives a multiple of 8 blocks)
-static inline int push_span(const WorkLists& L) { return L.ntx % 2 == 0 ? 2 : 1; }
 
 void launch_advance_step(uint32_t* step, hipStream_t st) {
   hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, step);
@@ -2073,20 +2099,21 @@ void launch_md_field(const void* E, int e_f64, const MdTables& md, int nx, int n
 void launch_collide_f64(const PartF64& P, const SpeciesStep& S, const WorkLists& L,
                         hipStream_t st) {
   if (L.ngrid > 0)
-    hipLaunchKernelGGL(collide_kernel<PartF64>, dim3(L.ngrid), dim3(64), 0, st, P, S, L);
+    hipLaunchKernelGGL(collide_kernel<PartF64>, dim3(L.ngrid), dim3(64), 0, st, P, S, L, 1);
 }
 
 void launch_collide_f32r(const PartF32R& P, const SpeciesStep& S, const WorkLists& L,
                          hipStream_t st) {
   if (L.ngrid > 0)
-    hipLaunchKernelGGL(collide_kernel<PartF32R>, dim3(L.ngrid), dim3(64), 0, st, P, S, L);
+    hipLaunchKernelGGL(collide_kernel<PartF32R>, dim3(L.ngrid / push_span(L)), dim3(64), 0, st, P,
+                       S, L, push_span(L));
 }
 
 void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const MdTables& md,
                       const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
                       int do_mcc, hipStream_t st) {
   if (L[0].ngrid <= 0) return;
-  SpeciesPair<PartF64> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, L[0].ngrid};
+  SpeciesPair<PartF64> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, L[0].ngrid, 1};
   hipLaunchKernelGGL(outlier_f64_kernel, dim3(2 * pr.nb), dim3(64), 0, st, pr, (const double2*)E,
                      rho, do_mcc);
   if (md.n_grains > 0) {
@@ -2104,7 +2131,8 @@ void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, cons
                        const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
                        int do_mcc, hipStream_t st) {
   if (L[0].ngrid <= 0) return;
-  SpeciesPair<PartF32R> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, L[0].ngrid};
+  const int span = push_span(L[0]);
+  SpeciesPair<PartF32R> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, L[0].ngrid / span, span};
   hipLaunchKernelGGL(outlier_f32r_kernel, dim3(2 * pr.nb), dim3(64), 0, st, pr, (const float4*)E,
                      rho, do_mcc);
   if (md.n_grains > 0) {

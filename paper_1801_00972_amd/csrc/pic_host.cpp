@@ -697,8 +697,9 @@ int build_batch(pic_ctx* ctx) {
         d.md = R.md;
         d.S = species_step(R, sp);
         d.L = R.lists[sp];
+        d.span = push_span(R.lists[sp]);
         if (ph == 0) {
-          const long total = (long)start[2 * r + sp] + R.ngrid;
+          const long total = (long)start[2 * r + sp] + R.ngrid / d.span;
           if (total > 0x7fffffffL) return PIC_OK;  // beyond the int32 item index
           start[2 * r + sp + 1] = (int32_t)total;
         }

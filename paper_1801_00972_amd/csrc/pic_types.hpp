@@ -106,13 +106,15 @@ struct SpeciesStep {
 };
 
 // both species of one replica for the kernels that follow the push: blocks
-// [0, nb) of a launch work on species 0, [nb, 2 nb) on species 1
+// [0, nb) of a launch work on species 0, [nb, 2 nb) on species 1; a tile
+// kernel's block b takes the lists of tile b * span (the push blocks' spans)
 template <typename PT>
 struct SpeciesPair {
   PT P[2];
   SpeciesStep S[2];
   WorkLists L[2];
   int nb;
+  int span;
 };
 
 // rf-phase binning of the time averages: sums of step k go to bin
@@ -132,6 +134,12 @@ struct PushDescF32 {
   MdTables md;
   SpeciesStep S;
   WorkLists L;
+  int span;  // tiles per push block (push_span)
 };
+
+// tiles per FP32R push block: pairs along x where the rows of tiles split into
+// pairs (the tile grid, a multiple of 16, then still gives a multiple of 8
+// blocks); the kernels that read the push's lists use the same span
+__host__ __device__ inline int push_span(const WorkLists& L) { return L.ntx % 2 == 0 ? 2 : 1; }
 
 }  // namespace pic
