@@ -695,6 +695,33 @@ __device__ __forceinline__ void chunk_append4(const bool (&flag)[kPPT], int32_t*
   }
 }
 
+// the slots p0 + q of every lane whose status st[q] is `want`, appended in
+// slot order (lane by lane, q ascending within a lane) with one reservation
+// for the wave: the dense MD list then runs through the cells in order, so the
+// MD kernel's waves meet few distinct cells when they deposit; every lane of
+// the wave must take part
+__device__ __forceinline__ void append_slot_order(const int (&st)[kPPT], int want, int32_t* seg,
+                                                  int* s_n, int p0) {
+  unsigned long long m[kPPT];
+  int total = 0;
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    m[q] = __ballot(st[q] == want);
+    total += __popcll(m[q]);
+  }
+  if (!total) return;
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(s_n, total);
+  base = __shfl(base, 0, 64);
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) base += __popcll(m[q] & below);
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q)
+    if (st[q] == want) seg[base++] = p0 + q;
+}
+
 // block-level tallies: wave sums into LDS; thread 0 then adds them to the
 // tile's own accumulators (each tile has one writer per kernel: no atomics)
 __device__ __forceinline__ void tally_add(unsigned* s_t, int which, int v) {
@@ -881,11 +908,11 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
 #pragma unroll
       for (int q = 0; q < kPPT; ++q) {
         cand[q] = st[q] == ST_ALIVE && (uint64_t)w0[q] < S.T_null;
-        chunk_append(st[q] == ST_MD, sm.md, &sm.nmd, p0 + q);
         chunk_append(cand[q], L.coll + beg, &sm.ncoll, p0 + q);
         chunk_append(st[q] == ST_OUT, L.out + beg, &sm.nout, p0 + q);
         packed += 1ull << (8 * st[q]);
       }
+      append_slot_order(st, ST_MD, sm.md, &sm.nmd, p0);
       if ((pass & 31) == 31) {
         n_w0 += (int)((packed >> (8 * ST_WALL0)) & 255u);
         n_w1 += (int)((packed >> (8 * ST_WALL1)) & 255u);
@@ -1123,13 +1150,10 @@ __global__ __launch_bounds__(kBlock, 3) void push_f64_kernel(PartF64 P, const do
       }
     }
     if (kMove) {
-      bool is_md[kPPT], is_out[kPPT];
+      bool is_out[kPPT];
 #pragma unroll
-      for (int q = 0; q < kPPT; ++q) {
-        is_md[q] = st[q] == ST_MD;
-        is_out[q] = st[q] == ST_OUT;
-      }
-      chunk_append4(is_md, s_md, &s_nmd, p0);
+      for (int q = 0; q < kPPT; ++q) is_out[q] = st[q] == ST_OUT;
+      append_slot_order(st, ST_MD, s_md, &s_nmd, p0);
       chunk_append4(cand, L.coll + beg, &s_ncoll, p0);
       chunk_append4(is_out, L.out + beg, &s_nout, p0);
 #pragma unroll
