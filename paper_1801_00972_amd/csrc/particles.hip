@@ -1904,6 +1904,30 @@ struct RecOf<PartF32R> {
   using type = RecF32R;
 };
 
+// LDS staging of a block's FP32R records (one array per field) and their
+// destinations
+template <int N>
+struct SortStage {
+  int cell[N];
+  float ox[N], oy[N], oz[N], vx[N], vy[N], vz[N];
+  uint32_t id[N];
+  int dest[N];
+  __device__ void put(int u, const RecF32R& r) {
+    cell[u] = r.cell;
+    ox[u] = r.ox;
+    oy[u] = r.oy;
+    oz[u] = r.oz;
+    vx[u] = r.vx;
+    vy[u] = r.vy;
+    vz[u] = r.vz;
+    id[u] = r.id;
+  }
+  __device__ RecF32R get(int u) const {
+    return RecF32R{cell[u], ox[u], oy[u], oz[u], vx[u], vy[u], vz[u], id[u]};
+  }
+  __device__ void put(int, const RecF64&) {}
+};
+
 template <typename PT>
 __global__ __launch_bounds__(256) void bin_scatter_kernel(PT src, PT dst, const int* __restrict__ cnt,
                                                           int* __restrict__ cursor, TileOrder o) {
@@ -1934,7 +1958,10 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(PT src, PT dst, const 
     if (t >= 0 && run.rank == 0) sl = table_slot(s_tile, t);
     sl = __shfl(sl, run.head, 64);
     slot[r] = t >= 0 ? sl : -1;
-    if (slot[r] >= 0) atomicAdd(&s_bin[slot[r] * 64 + (key[r] & 63)], 1);
+    // one LDS atomic per run of equal bins (the input is nearly sorted)
+    const int bk = slot[r] >= 0 ? slot[r] * 64 + (key[r] & 63) : -1;
+    const Run brun = lane_run(bk);
+    if (bk >= 0 && brun.rank == 0) atomicAdd(&s_bin[bk], brun.len);
   }
   __syncthreads();
   // exclusive scan of the bins in (slot, cell) order: block-local positions
@@ -1972,15 +1999,34 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(PT src, PT dst, const 
     s_base[threadIdx.x] = atomicAdd(&cursor[s_tile[threadIdx.x]], g1 - g0) - g0;
   }
   __syncthreads();
+  // FP32R records are staged in LDS at their block-local places and then
+  // written out in destination order (whole lines); FP64 records go directly
+  constexpr bool kStaged = std::is_same<PT, PartF32R>::value;
+  __shared__ SortStage<kStaged ? kSortSlots : 1> s_stage;
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
+    // places in the bin: one LDS atomic per run, lanes of a run in lane order
+    const int bk = slot[r] >= 0 ? slot[r] * 64 + (key[r] & 63) : -1;
+    const Run brun = lane_run(bk);
+    int d0 = 0;
+    if (bk >= 0 && brun.rank == 0) d0 = atomicAdd(&s_bin[bk], brun.len);
+    d0 = __shfl(d0, brun.head, 64);
     if (key[r] < 0) continue;
-    int dest;
-    if (slot[r] >= 0)
-      dest = s_base[slot[r]] + atomicAdd(&s_bin[slot[r] * 64 + (key[r] & 63)], 1);
-    else
-      dest = atomicAdd(&cursor[key[r] >> 6], 1);  // the table was full: any place in the tile
-    store_rec(dst, dest, rec[r]);
+    if (slot[r] >= 0) {
+      const int u = d0 + brun.rank;
+      if constexpr (kStaged) {
+        s_stage.put(u, rec[r]);
+        s_stage.dest[u] = s_base[slot[r]] + u;
+      } else {
+        store_rec(dst, s_base[slot[r]] + u, rec[r]);
+      }
+    } else {
+      store_rec(dst, atomicAdd(&cursor[key[r] >> 6], 1), rec[r]);  // the table was full
+    }
+  }
+  if constexpr (kStaged) {
+    __syncthreads();
+    for (int u = threadIdx.x; u < total; u += 256) store_rec(dst, s_stage.dest[u], s_stage.get(u));
   }
 }
 
