@@ -1790,8 +1790,15 @@ constexpr int kSortRounds = 4;
 constexpr int kSortSlots = 4 * 64 * kSortRounds;
 constexpr int kTable = 64;  // destination tiles per block held in LDS (open addressing)
 
+template <int Rounds = kSortRounds>
 __device__ __forceinline__ int sort_first_slot() {
-  return blockIdx.x * kSortSlots + (threadIdx.x >> 6) * 64 * kSortRounds + (threadIdx.x & 63);
+  return blockIdx.x * (256 * Rounds) + (threadIdx.x >> 6) * 64 * Rounds + (threadIdx.x & 63);
+}
+// rounds per wave of the scatter: half for FP64 records, so that a block's
+// staged records fit in LDS
+template <typename PT>
+constexpr int scatter_rounds() {
+  return std::is_same<PT, PartF64>::value ? kSortRounds / 2 : kSortRounds;
 }
 
 // the LDS table slot of tile t, inserted if new; -1 when the table is full
@@ -1904,10 +1911,12 @@ struct RecOf<PartF32R> {
   using type = RecF32R;
 };
 
-// LDS staging of a block's FP32R records (one array per field) and their
-// destinations
+// LDS staging of a block's records (one array per field, so neighbouring
+// lanes touch neighbouring words) and their destinations
+template <typename Rec, int N>
+struct SortStage;
 template <int N>
-struct SortStage {
+struct SortStage<RecF32R, N> {
   int cell[N];
   float ox[N], oy[N], oz[N], vx[N], vy[N], vz[N];
   uint32_t id[N];
@@ -1925,7 +1934,24 @@ struct SortStage {
   __device__ RecF32R get(int u) const {
     return RecF32R{cell[u], ox[u], oy[u], oz[u], vx[u], vy[u], vz[u], id[u]};
   }
-  __device__ void put(int, const RecF64&) {}
+};
+template <int N>
+struct SortStage<RecF64, N> {
+  double x[N], y[N], z[N], vx[N], vy[N], vz[N];
+  uint32_t id[N];
+  int dest[N];
+  __device__ void put(int u, const RecF64& r) {
+    x[u] = r.x;
+    y[u] = r.y;
+    z[u] = r.z;
+    vx[u] = r.vx;
+    vy[u] = r.vy;
+    vz[u] = r.vz;
+    id[u] = r.id;
+  }
+  __device__ RecF64 get(int u) const {
+    return RecF64{x[u], y[u], z[u], vx[u], vy[u], vz[u], id[u]};
+  }
 };
 
 template <typename PT>
@@ -1940,17 +1966,18 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(PT src, PT dst, const 
   for (int i = threadIdx.x; i < kBins; i += 256) s_bin[i] = 0;
   if (threadIdx.x < kTable) s_tile[threadIdx.x] = -1;
   const int n = cnt[0];
-  const int first = sort_first_slot();
-  Rec rec[kSortRounds];
+  constexpr int R = scatter_rounds<PT>();
+  const int first = sort_first_slot<R>();
+  Rec rec[R];
 #pragma unroll
-  for (int r = 0; r < kSortRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int p = first + 64 * r;
     if (p < n) load_rec(src, p, rec[r]);
   }
   __syncthreads();
-  int key[kSortRounds], slot[kSortRounds];
+  int key[R], slot[R];
 #pragma unroll
-  for (int r = 0; r < kSortRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     key[r] = first + 64 * r < n ? rec_key(rec[r], o) : -1;
     const int t = key[r] >= 0 ? key[r] >> 6 : -1;
     const Run run = lane_run(t);
@@ -1999,12 +2026,11 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(PT src, PT dst, const 
     s_base[threadIdx.x] = atomicAdd(&cursor[s_tile[threadIdx.x]], g1 - g0) - g0;
   }
   __syncthreads();
-  // FP32R records are staged in LDS at their block-local places and then
-  // written out in destination order (whole lines); FP64 records go directly
-  constexpr bool kStaged = std::is_same<PT, PartF32R>::value;
-  __shared__ SortStage<kStaged ? kSortSlots : 1> s_stage;
+  // the records are staged in LDS at their block-local places and then
+  // written out in destination order (whole lines)
+  __shared__ SortStage<Rec, 256 * R> s_stage;
 #pragma unroll
-  for (int r = 0; r < kSortRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     // places in the bin: one LDS atomic per run, lanes of a run in lane order
     const int bk = slot[r] >= 0 ? slot[r] * 64 + (key[r] & 63) : -1;
     const Run brun = lane_run(bk);
@@ -2014,20 +2040,14 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(PT src, PT dst, const 
     if (key[r] < 0) continue;
     if (slot[r] >= 0) {
       const int u = d0 + brun.rank;
-      if constexpr (kStaged) {
-        s_stage.put(u, rec[r]);
-        s_stage.dest[u] = s_base[slot[r]] + u;
-      } else {
-        store_rec(dst, s_base[slot[r]] + u, rec[r]);
-      }
+      s_stage.put(u, rec[r]);
+      s_stage.dest[u] = s_base[slot[r]] + u;
     } else {
       store_rec(dst, atomicAdd(&cursor[key[r] >> 6], 1), rec[r]);  // the table was full
     }
   }
-  if constexpr (kStaged) {
-    __syncthreads();
-    for (int u = threadIdx.x; u < total; u += 256) store_rec(dst, s_stage.dest[u], s_stage.get(u));
-  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < total; u += 256) store_rec(dst, s_stage.dest[u], s_stage.get(u));
 }
 
 // t <= ngrid: the tile's size rounded up to a multiple of 4 (0 for the grid's
@@ -2282,7 +2302,8 @@ static void sort_impl(const PT& src, const PT& dst, const WorkLists& L, int* his
   hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kScanBlock), 0, st, L.tstart, n, sums, L.tstart);
   hipLaunchKernelGGL(tile_pad_kernel<PT>, dim3(nblk(ng, 256)), dim3(256), 0, st, tcount, L.tstart,
                      cursor, dst, ng);
-  hipLaunchKernelGGL(bin_scatter_kernel<PT>, dim3(nblk(capacity, kSortSlots)), dim3(256), 0, st,
+  hipLaunchKernelGGL(bin_scatter_kernel<PT>, dim3(nblk(capacity, 256 * scatter_rounds<PT>())),
+                     dim3(256), 0, st,
                      src, dst, L.cnt, cursor, o);
   hipLaunchKernelGGL(sort_finish_kernel, dim3(1), dim3(64), 0, st, L.cnt, L.tstart, ng);
 }
