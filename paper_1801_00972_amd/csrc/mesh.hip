@@ -88,9 +88,10 @@ __device__ __forceinline__ void butterfly(const C* x, C* y, int xs, int ys, int 
     }
   }
   y[0] = out[0];
+  // j p s < N: the stages keep n s = N and p < n / R
 #pragma unroll
   for (int j = 1; j < R; ++j) {
-    C w = tw[(long)j * p * s % N];
+    C w = tw[j * p * s];
     if (forward) w.y = -w.y;
     y[j * ys] = cmul(out[j], w);
   }
