@@ -599,10 +599,12 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
                                                        int K, double* __restrict__ partials) {
   __shared__ double s_r[256], s_b[256];
   const long plane = (long)nx * ny;
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  // grid: x over the plane's nodes, y over the planes
+  const int pn = (int)(blockIdx.x * blockDim.x + threadIdx.x), k = (int)blockIdx.y;
+  const long i = (long)k * plane + pn;
   double rr = 0.0, bb = 0.0;
-  if (i < plane * K) {
-    const int x = (int)(i % nx), y = (int)((i / nx) % ny), k = (int)(i / plane);
+  if (pn < plane && k < K) {
+    const int y = pn / nx, x = pn - y * nx;
     const long row = i - x, pl = i - (long)y * nx - x;
     const double c = psi[i];
     const double xp = psi[row + (x + 1 == nx ? 0 : x + 1)];
@@ -629,8 +631,9 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = s_r[0];
-    partials[2 * blockIdx.x + 1] = s_b[0];
+    const long blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
+    partials[2 * blk] = s_r[0];
+    partials[2 * blk + 1] = s_b[0];
   }
 }
 
@@ -664,9 +667,9 @@ __global__ void lift_kernel(const double* __restrict__ psi, double* __restrict__
                             int ny, int nz, RfDrive rf) {
   const double V = rf_voltage(rf);
   const long plane = (long)nx * ny;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= plane * (nz + 1)) return;
-  const int k = (int)(n / plane);
+  const int pn = (int)(blockIdx.x * blockDim.x + threadIdx.x), k = (int)blockIdx.y;
+  if (pn >= plane) return;
+  const long n = (long)k * plane + pn;
   if (k == 0) phi[n] = 0.0;
   else if (k == nz) phi[n] = V;
   else phi[n] = psi[n - plane] + V * (double)k / (double)nz;
@@ -688,9 +691,11 @@ template <typename OutT>
 __global__ void efield_kernel(const double* __restrict__ phi, OutT* __restrict__ E, int nx, int ny,
                               int nz, double dx) {
   const long plane = (long)nx * ny;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= plane * (nz + 1)) return;
-  const int x = (int)(n % nx), y = (int)((n / nx) % ny), k = (int)(n / plane);
+  // grid: x over the plane's nodes, y over the planes
+  const int pn = (int)(blockIdx.x * blockDim.x + threadIdx.x), k = (int)blockIdx.y;
+  if (pn >= plane) return;
+  const long n = (long)k * plane + pn;
+  const int y = pn / nx, x = pn - y * nx;
   const long row = n - x, pl = n - (long)y * nx - x;
   const double ex = -(phi[row + (x + 1 == nx ? 0 : x + 1)] - phi[row + (x == 0 ? nx - 1 : x - 1)]) /
                     (2.0 * dx);
@@ -934,8 +939,8 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
 
 // FP32 solves refined in FP64: psi = 0, r = b; repeat sweeps times
 // { psi += solve32(r); r = b - A psi }; phi = psi + lift.  norms[0..1] receive
-// ||r||^2, ||b||^2 of the last sweep; norms[2..] hold 2 per-block partials per
-// 256 interior nodes.
+// ||r||^2, ||b||^2 of the last sweep; norms[2..] hold 2 partials per residual
+// block: ceil(nx ny / 256) blocks per interior plane.
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
                           const void* tw_y32, const void* inv32, double* phi, RfDrive rf,
@@ -947,14 +952,14 @@ void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const do
   for (int it = 0; it < sweeps; ++it) {
     solve_once<float>(P, nx, ny, nz, rhs, work32, tw_x32, tw_y32, inv32, OUT_REAL_ACCUM, psi, rf,
                       st);
-    hipLaunchKernelGGL(residual_kernel, dim3(nb256(n_int)), dim3(256), 0, st, psi, b, r, nx, ny,
-                       nz - 1, norms + 2);
-    hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb256(n_int),
-                       norms);
+    hipLaunchKernelGGL(residual_kernel, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi, b, r,
+                       nx, ny, nz - 1, norms + 2);
+    hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2,
+                       nb256(plane) * (nz - 1), norms);
     rhs = r;
   }
-  hipLaunchKernelGGL(lift_kernel, dim3(nb256(plane * (nz + 1))), dim3(256), 0, st, psi, phi, nx, ny,
-                     nz, rf);
+  hipLaunchKernelGGL(lift_kernel, dim3(nb256(plane), nz + 1), dim3(256), 0, st, psi, phi, nx, ny, nz,
+                     rf);
 }
 
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
@@ -996,15 +1001,13 @@ void launch_extract_cube(const double* E, const int* gcell, int g, int c, int nx
 
 void launch_efield_f64(const double* phi, double* E, int nx, int ny, int nz, double dx,
                        hipStream_t st) {
-  const long nn = (long)nx * ny * (nz + 1);
-  hipLaunchKernelGGL(efield_kernel<double2>, dim3(nb256(nn)), dim3(256), 0, st, phi, (double2*)E,
-                     nx, ny, nz, dx);
+  hipLaunchKernelGGL(efield_kernel<double2>, dim3(nb256((long)nx * ny), nz + 1), dim3(256), 0, st,
+                     phi, (double2*)E, nx, ny, nz, dx);
 }
 void launch_efield_f32(const double* phi, float* E, int nx, int ny, int nz, double dx,
                        hipStream_t st) {
-  const long nn = (long)nx * ny * (nz + 1);
-  hipLaunchKernelGGL(efield_kernel<float4>, dim3(nb256(nn)), dim3(256), 0, st, phi, (float4*)E, nx,
-                     ny, nz, dx);
+  hipLaunchKernelGGL(efield_kernel<float4>, dim3(nb256((long)nx * ny), nz + 1), dim3(256), 0, st,
+                     phi, (float4*)E, nx, ny, nz, dx);
 }
 
 void launch_e_out(const double* E64, const float* E32, double* out, long nn, hipStream_t st) {

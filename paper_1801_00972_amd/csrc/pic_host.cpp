@@ -951,7 +951,8 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   }
   TRY(dalloc(ctx, R, &R.b, R.n_int));
   TRY(dalloc(ctx, R, &R.phi, R.nn));
-  TRY(dalloc(ctx, R, &R.norms, 2 + 2 * ((R.n_int + 255) / 256)));
+  // two sums and a partial pair per residual block (blocks of 256 nodes per plane)
+  TRY(dalloc(ctx, R, &R.norms, 2 + 2 * ((R.nxy + 255) / 256) * (R.nz - 1)));
   TRY(dalloc(ctx, R, &R.d_gc, 2 * std::max(c.n_grains, 1)));
   const long nkey = sort_keys(R.nx, R.ny, R.nz);
   TRY(dalloc(ctx, R, &R.d_hist, nkey));
