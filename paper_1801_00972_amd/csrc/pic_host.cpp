@@ -106,6 +106,11 @@ struct pic_ctx {
   int since_sort[2]{};
   // captured steps, by phase (see step_all)
   hipStream_t capture_stream = nullptr;
+  // replicas stepped one by one are spread over worker streams (default
+  // priority), forked from and joined back into the caller's stream
+  std::vector<hipStream_t> workers;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
   hipGraphExec_t graph[64] = {};
   // time averages: a sample every avg_interval steps (0: off) into avg_bins
   // rf-phase bins; since_avg counts the steps since the last sample
@@ -131,6 +136,9 @@ struct pic_ctx {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     drop_graphs();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    for (hipStream_t w : workers) (void)hipStreamDestroy(w);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
     if (d_desc) (void)hipFree(d_desc);
     if (d_start) (void)hipFree(d_start);
   }
@@ -669,11 +677,48 @@ bool replicas_aligned(const pic_ctx* ctx) {
 }
 
 // one step of every replica, launched on ctx->stream
+constexpr int kWorkers = 4;  // worker streams for the replicas of an ensemble
+
+// Several replicas stepped one by one: replica r goes to worker stream
+// r % kWorkers, after an event on the caller's stream, which then waits for
+// every worker (a fork and join that graph capture records as dependencies).
+// The replicas share no memory, so their kernels may overlap.  With kernel
+// timing on, everything stays on the caller's stream.
+int enqueue_replicas(pic_ctx* ctx, int sorts, int sample) {
+  const int nw = std::min<int>(kWorkers, (int)ctx->reps.size());
+  if (nw <= 1 || ctx->prof) {
+    for (auto& R : ctx->reps) TRY(enqueue_step(ctx, *R, sorts, sample));
+    return PIC_OK;
+  }
+  if (ctx->workers.empty()) {
+    ctx->workers.assign(nw, nullptr);
+    ctx->join_ev.assign(nw, nullptr);
+    for (int w = 0; w < nw; ++w) {
+      HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->workers[w], hipStreamNonBlocking));
+      HIPCHK(ctx, hipEventCreateWithFlags(&ctx->join_ev[w], hipEventDisableTiming));
+    }
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+  }
+  hipStream_t caller = ctx->stream;
+  HIPCHK(ctx, hipEventRecord(ctx->fork_ev, caller));
+  for (int w = 0; w < nw; ++w) HIPCHK(ctx, hipStreamWaitEvent(ctx->workers[w], ctx->fork_ev, 0));
+  int rc = PIC_OK;
+  for (size_t r = 0; r < ctx->reps.size() && rc == PIC_OK; ++r) {
+    ctx->stream = ctx->workers[r % nw];
+    rc = enqueue_step(ctx, *ctx->reps[r], sorts, sample);
+  }
+  ctx->stream = caller;
+  for (int w = 0; w < nw; ++w) {
+    HIPCHK(ctx, hipEventRecord(ctx->join_ev[w], ctx->workers[w]));
+    HIPCHK(ctx, hipStreamWaitEvent(caller, ctx->join_ev[w], 0));
+  }
+  return rc;
+}
+
 int enqueue_all(pic_ctx* ctx, int sorts, int sample) {
   if (ctx->batchable && ctx->tune.batch_push && replicas_aligned(ctx))
     return enqueue_batch(ctx, sorts, sample);
-  for (auto& R : ctx->reps) TRY(enqueue_step(ctx, *R, sorts, sample));
-  return PIC_OK;
+  return enqueue_replicas(ctx, sorts, sample);
 }
 
 // (re)builds the descriptors of the batched push: for buffer phase ph,
