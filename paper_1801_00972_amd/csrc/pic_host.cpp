@@ -629,65 +629,18 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   return PIC_OK;
 }
 
-// one step of every replica of an FP32R context with the push of all
-// replicas and species in one persistent launch (replicas in the same phase)
-int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
-  hipStream_t st = ctx->stream;
-  const Replica& R0 = *ctx->reps[0];
-  hipEvent_t f0 = prof_event(ctx);
-  for (auto& R : ctx->reps) {
-    TRY(solve_fields(ctx, *R));
-    if (sample) TRY(enqueue_sample(ctx, *R));
-    launch_zero_i64((long long*)R->rho[1 - R->rho_cur], R->nn, st);
-  }
-  CHECK_LAUNCH(ctx);
-  prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
-  hipEvent_t a = prof_event(ctx);
-  launch_push_batch_f32r(ctx->d_desc + (size_t)phase_of(R0) * ctx->ndesc, ctx->d_start, ctx->ndesc,
-                         ctx->tune.batch_blocks, st);
-  CHECK_LAUNCH(ctx);
-  hipEvent_t b = prof_event(ctx);
-  for (auto& R : ctx->reps) {
-    const int rnx = 1 - R->rho_cur;
-    const PartF32R P[2] = {R->p32[0][R->cur[0]], R->p32[1][R->cur[1]]};
-    const SpeciesStep S[2] = {species_step(*R, 0), species_step(*R, 1)};
-    for (int sp = 0; sp < 2; ++sp) launch_collide_f32r(P[sp], S[sp], R->lists[sp], st);
-    launch_lists_f32r(P, (const float*)R->E, (long long*)R->rho[rnx], R->md, S, R->d_gc, R->lists, 1,
-                      st);
-    launch_advance_step(R->d_step, st);
-  }
-  CHECK_LAUNCH(ctx);
-  prof_pair(ctx, PIC_PROF_PUSH, a, b);
-  prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
-  if (sorts) {
-    hipEvent_t s0 = prof_event(ctx);
-    for (auto& R : ctx->reps)
-      for (int sp = 0; sp < 2; ++sp)
-        if (sorts & (1 << sp)) TRY(enqueue_sort(ctx, *R, sp));
-    prof_pair(ctx, PIC_PROF_SORT, s0, prof_event(ctx));
-  }
-  return PIC_OK;
-}
-
-bool replicas_aligned(const pic_ctx* ctx) {
-  const int p0 = phase_of(*ctx->reps[0]);
-  for (auto& R : ctx->reps)
-    if (phase_of(*R) != p0) return false;
-  return true;
-}
-
-// one step of every replica, launched on ctx->stream
 constexpr int kWorkers = 4;  // worker streams for the replicas of an ensemble
 
-// Several replicas stepped one by one: replica r goes to worker stream
-// r % kWorkers, after an event on the caller's stream, which then waits for
-// every worker (a fork and join that graph capture records as dependencies).
-// The replicas share no memory, so their kernels may overlap.  With kernel
-// timing on, everything stays on the caller's stream.
-int enqueue_replicas(pic_ctx* ctx, int sorts, int sample) {
+// Runs fn(R) for every replica: replica r on worker stream r % kWorkers, after
+// an event on the caller's stream, which then waits for every worker (a fork
+// and join that graph capture records as dependencies).  The replicas share
+// no memory, so their kernels may overlap.  With kernel timing on, or one
+// replica, everything stays on the caller's stream.
+template <typename Fn>
+int for_replicas(pic_ctx* ctx, Fn fn) {
   const int nw = std::min<int>(kWorkers, (int)ctx->reps.size());
   if (nw <= 1 || ctx->prof) {
-    for (auto& R : ctx->reps) TRY(enqueue_step(ctx, *R, sorts, sample));
+    for (auto& R : ctx->reps) TRY(fn(*R));
     return PIC_OK;
   }
   if (ctx->workers.empty()) {
@@ -705,7 +658,7 @@ int enqueue_replicas(pic_ctx* ctx, int sorts, int sample) {
   int rc = PIC_OK;
   for (size_t r = 0; r < ctx->reps.size() && rc == PIC_OK; ++r) {
     ctx->stream = ctx->workers[r % nw];
-    rc = enqueue_step(ctx, *ctx->reps[r], sorts, sample);
+    rc = fn(*ctx->reps[r]);
   }
   ctx->stream = caller;
   for (int w = 0; w < nw; ++w) {
@@ -715,10 +668,63 @@ int enqueue_replicas(pic_ctx* ctx, int sorts, int sample) {
   return rc;
 }
 
+// one step of every replica of an FP32R context with the push of all
+// replicas and species in one persistent launch (replicas in the same phase)
+int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
+  hipStream_t st = ctx->stream;
+  const Replica& R0 = *ctx->reps[0];
+  hipEvent_t f0 = prof_event(ctx);
+  TRY(for_replicas(ctx, [&](Replica& R) -> int {
+    TRY(solve_fields(ctx, R));
+    if (sample) TRY(enqueue_sample(ctx, R));
+    launch_zero_i64((long long*)R.rho[1 - R.rho_cur], R.nn, ctx->stream);
+    return PIC_OK;
+  }));
+  CHECK_LAUNCH(ctx);
+  prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
+  hipEvent_t a = prof_event(ctx);
+  launch_push_batch_f32r(ctx->d_desc + (size_t)phase_of(R0) * ctx->ndesc, ctx->d_start, ctx->ndesc,
+                         ctx->tune.batch_blocks, st);
+  CHECK_LAUNCH(ctx);
+  hipEvent_t b = prof_event(ctx);
+  TRY(for_replicas(ctx, [&](Replica& R) -> int {
+    hipStream_t ws = ctx->stream;
+    const int rnx = 1 - R.rho_cur;
+    const PartF32R P[2] = {R.p32[0][R.cur[0]], R.p32[1][R.cur[1]]};
+    const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
+    for (int sp = 0; sp < 2; ++sp) launch_collide_f32r(P[sp], S[sp], R.lists[sp], ws);
+    launch_lists_f32r(P, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc, R.lists, 1,
+                      ws);
+    launch_advance_step(R.d_step, ws);
+    return PIC_OK;
+  }));
+  CHECK_LAUNCH(ctx);
+  prof_pair(ctx, PIC_PROF_PUSH, a, b);
+  prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
+  if (sorts) {
+    hipEvent_t s0 = prof_event(ctx);
+    TRY(for_replicas(ctx, [&](Replica& R) -> int {
+      for (int sp = 0; sp < 2; ++sp)
+        if (sorts & (1 << sp)) TRY(enqueue_sort(ctx, R, sp));
+      return PIC_OK;
+    }));
+    prof_pair(ctx, PIC_PROF_SORT, s0, prof_event(ctx));
+  }
+  return PIC_OK;
+}
+
+bool replicas_aligned(const pic_ctx* ctx) {
+  const int p0 = phase_of(*ctx->reps[0]);
+  for (auto& R : ctx->reps)
+    if (phase_of(*R) != p0) return false;
+  return true;
+}
+
+// one step of every replica, launched on ctx->stream
 int enqueue_all(pic_ctx* ctx, int sorts, int sample) {
   if (ctx->batchable && ctx->tune.batch_push && replicas_aligned(ctx))
     return enqueue_batch(ctx, sorts, sample);
-  return enqueue_replicas(ctx, sorts, sample);
+  return for_replicas(ctx, [&](Replica& R) { return enqueue_step(ctx, R, sorts, sample); });
 }
 
 // (re)builds the descriptors of the batched push: for buffer phase ph,
