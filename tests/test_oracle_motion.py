@@ -245,3 +245,44 @@ def test_oracle_is_deterministic():
     b.step(5)
     for s in range(2):
         assert np.array_equal(a.pos[s], b.pos[s]) and np.array_equal(a.vel[s], b.vel[s])
+
+
+def test_collisionless_push_conserves_leapfrog_energy():
+    # Energy conservation of a collisionless push: a potential well
+    # phi = c (z dx - z0)^2 on the nodes, differenced by the oracle's own E
+    # stencil (exact on quadratics) and gathered by CIC (exact on linear
+    # fields), gives each particle a linear restoring force k = 2 q c.  The
+    # leapfrog of Eq. (1)-(2) then keeps 1/2 m v_{n-1/2}.v_{n+1/2} + q phi(x_n)
+    # constant to rounding (the difference of consecutive values cancels
+    # term by term), for electrons (c < 0) and, in the mirrored well, ions.
+    wl = W.tiny(nx=6, ny=5, nz=40)
+    dt, dx, nz = wl["dt"], wl["dx"], wl["nz"]
+    z0 = 0.5 * nz * dx
+    rng = np.random.default_rng(7)
+    for s, q, m, w in ((0, -E_CH, ME, 2.0e9), (1, E_CH, M_AR, 4.0e7)):
+        c = m * w * w / (2.0 * q)  # V/m^2, well for the species' charge sign
+        o = oracle.Oracle(wl, flags=oracle.NO_MCC)
+        k = np.repeat(np.arange(nz + 1), wl["nx"] * wl["ny"])
+        phi = c * (k * dx - z0) ** 2
+        E = o.efield(phi)
+        n = 64
+        pos = np.column_stack([rng.uniform(0, 6, n), rng.uniform(0, 5, n),
+                               rng.uniform(0.35 * nz, 0.65 * nz, n)])
+        vth = np.sqrt(E_CH * (3.0 if s == 0 else 0.03) / m)
+        vel = rng.normal(size=(n, 3)) * vth * 0.3
+        o.set_particles(s, pos, vel, np.arange(n))
+        o.set_particles(1 - s, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0))
+        v_prev = o.vel[s].copy()
+        x_prev = o.pos[s].copy()
+        inv = None
+        for step in range(400):
+            o.step_in_field(E, 1)
+            assert o.n_alive(s) == n  # the well keeps every particle off the electrodes
+            v_next = o.vel[s]
+            energy = 0.5 * m * np.sum(v_prev * v_next, axis=1) + q * c * (x_prev[:, 2] * dx - z0) ** 2
+            if inv is None:
+                inv = energy
+                scale = np.abs(0.5 * m * np.sum(vel * vel, axis=1)) + np.abs(q * c) * (0.15 * nz * dx) ** 2
+            assert np.all(np.abs(energy - inv) <= 1e-10 * scale), (s, step)
+            v_prev = v_next.copy()
+            x_prev = o.pos[s].copy()
