@@ -47,6 +47,17 @@ __device__ __forceinline__ int pack_cell(int i, int j, int k) { return i | (j <<
 // a multiple of 8, so this is a permutation of [0, nb).
 __device__ __forceinline__ long xcd_chunk(long b, long nb) { return (b % 8) * (nb / 8) + b / 8; }
 
+// The same dealing with the XCDs' runs cut into chunks of `chunk` items and
+// interleaved (XCD x takes chunks x, x + 8, ...): with a chunk of one z-layer
+// of tiles every XCD works on layers spread over the whole height, so the
+// particle density's variation along z (the sheaths) does not load some XCDs
+// more than others, while neighbouring tiles of a layer still share an L2.
+// nb / 8 must be a multiple of chunk (then it is a permutation of [0, nb)).
+__device__ __forceinline__ long xcd_interleave(long b, long chunk) {
+  const long x = b % 8, i = b / 8;
+  return ((i / chunk) * 8 + x) * chunk + i % chunk;
+}
+
 // ---------------------------------------------------------------- field loads
 __device__ __forceinline__ void load_node(const double2* __restrict__ E, long n, double& ex,
                                           double& ey, double& ez) {
@@ -1018,9 +1029,10 @@ template <bool kMove>
 __global__ __launch_bounds__(kBlock, 4) void push_f32r_kernel(PartF32R P,
                                                            const float4* __restrict__ E,
                                                            long long* __restrict__ rho, MdTables md,
-                                                           SpeciesStep S, WorkLists L, int span) {
+                                                           SpeciesStep S, WorkLists L, int span,
+                                                           int chunk) {
   __shared__ PushSmemF32 sm;
-  push_tile_f32r<kMove>(P, E, rho, md, S, L, span * (int)xcd_chunk(blockIdx.x, gridDim.x), span,
+  push_tile_f32r<kMove>(P, E, rho, md, S, L, span * (int)xcd_interleave(blockIdx.x, chunk), span,
                         sm);
 }
 
@@ -1058,13 +1070,13 @@ constexpr int kWinF64 = 729;  // window capacity (nodes): a tile with a 2-cell m
 template <bool kMove>
 __global__ __launch_bounds__(kBlock, 3) void push_f64_kernel(PartF64 P, const double2* __restrict__ E,
                                                           double* __restrict__ rho, MdTables md,
-                                                          SpeciesStep S, WorkLists L) {
+                                                          SpeciesStep S, WorkLists L, int chunk) {
   __shared__ double2 s_E[2 * kWinF64];
   __shared__ double s_rho[kWinF64];
   __shared__ unsigned s_tally[TL_N];
   __shared__ int s_nmd, s_ncoll, s_nout, s_mdbase;
   __shared__ int32_t s_md[kMdStage];
-  const int tidx = (int)xcd_chunk(blockIdx.x, gridDim.x);
+  const int tidx = (int)xcd_interleave(blockIdx.x, chunk);
   const int beg = L.tstart[tidx], end = L.tstart[tidx + 1];
   if (beg >= end) {
     if (kMove && threadIdx.x == 0) {
@@ -2170,6 +2182,15 @@ int tile_grid(int nx, int ny, int nz) {
   return (((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) + 15) / 16 * 16;
 }
 
+// the chunk of xcd_interleave for a push grid of nb blocks of `span` tiles: one
+// z-layer of tiles, cut down to a divisor of the blocks per XCD
+static int push_chunk(const WorkLists& L, int span) {
+  const int per_xcd = L.ngrid / span / 8;
+  int c = std::max(1, std::min(per_xcd, L.ntx * L.nty / span));
+  while (c > 1 && per_xcd % c) --c;
+  return c;
+}
+
 
 void launch_advance_step(uint32_t* step, hipStream_t st) {
   hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, step);
@@ -2179,7 +2200,7 @@ void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTab
                      const SpeciesStep& S, const WorkLists& L, hipStream_t st) {
   if (L.ngrid <= 0) return;
   hipLaunchKernelGGL(push_f64_kernel<true>, dim3(L.ngrid), dim3(kBlock), 0, st, P,
-                     (const double2*)E, rho, md, S, L);
+                     (const double2*)E, rho, md, S, L, push_chunk(L, 1));
 }
 
 void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
@@ -2187,7 +2208,7 @@ void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const M
   if (L.ngrid <= 0) return;
   const int span = push_span(L);
   hipLaunchKernelGGL(push_f32r_kernel<true>, dim3(L.ngrid / span), dim3(kBlock), 0, st, P,
-                     (const float4*)E, rho, md, S, L, span);
+                     (const float4*)E, rho, md, S, L, span, push_chunk(L, span));
 }
 
 void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int ndesc, int grid,
@@ -2278,7 +2299,7 @@ void launch_deposit_f64(const PartF64& P, double* rho, const MdTables& md, const
                         const WorkLists& L, hipStream_t st) {
   if (L.ngrid <= 0) return;
   hipLaunchKernelGGL(push_f64_kernel<false>, dim3(L.ngrid), dim3(kBlock), 0, st, P, nullptr, rho,
-                     md, S, L);
+                     md, S, L, push_chunk(L, 1));
 }
 
 void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
@@ -2286,7 +2307,7 @@ void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
   if (L.ngrid <= 0) return;
   const int span = push_span(L);
   hipLaunchKernelGGL(push_f32r_kernel<false>, dim3(L.ngrid / span), dim3(kBlock), 0, st, P,
-                     nullptr, rho, md, S, L, span);
+                     nullptr, rho, md, S, L, span, push_chunk(L, span));
 }
 
 void launch_moments(const PartF64* P64, const PartF32R* P32, const SpeciesStep& S,
