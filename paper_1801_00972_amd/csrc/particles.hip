@@ -1040,7 +1040,8 @@ __global__ __launch_bounds__(kBlock, 4) void push_f32r_kernel(PartF32R P,
 // One persistent launch over the tile spans of every (replica, species) of an
 // ensemble: work item i belongs to descriptor d with start[d] <= i < start[d+1]
 // (each descriptor has a multiple of 8 items, so the XCD remapping stays a
-// permutation per descriptor); blocks stride over the items.
+// permutation per descriptor); blocks stride over the items (a grid that is
+// a multiple of 8 keeps item i on XCD i % 8).
 __global__ __launch_bounds__(kBlock, 4) void push_batch_f32r_kernel(const PushDescF32* __restrict__ descs,
                                                                  const int32_t* __restrict__ start,
                                                                  int ndesc) {
@@ -1056,7 +1057,7 @@ __global__ __launch_bounds__(kBlock, 4) void push_batch_f32r_kernel(const PushDe
     const int local = item - start[lo];
     const PushDescF32& d = descs[lo];
     push_tile_f32r<true>(d.P, d.E, d.rho, d.md, d.S, d.L,
-                         d.span * (int)xcd_chunk(local, start[lo + 1] - start[lo]), d.span, sm);
+                         d.span * (int)xcd_interleave(local, d.chunk), d.span, sm);
     __syncthreads();
   }
 }
@@ -2180,15 +2181,6 @@ static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 int tile_grid(int nx, int ny, int nz) {
   return (((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) + 15) / 16 * 16;
-}
-
-// the chunk of xcd_interleave for a push grid of nb blocks of `span` tiles: one
-// z-layer of tiles, cut down to a divisor of the blocks per XCD
-static int push_chunk(const WorkLists& L, int span) {
-  const int per_xcd = L.ngrid / span / 8;
-  int c = std::max(1, std::min(per_xcd, L.ntx * L.nty / span));
-  while (c > 1 && per_xcd % c) --c;
-  return c;
 }
 
 

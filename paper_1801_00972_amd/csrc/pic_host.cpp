@@ -749,6 +749,7 @@ int build_batch(pic_ctx* ctx) {
         d.S = species_step(R, sp);
         d.L = R.lists[sp];
         d.span = push_span(R.lists[sp]);
+        d.chunk = push_chunk(R.lists[sp], d.span);
         if (ph == 0) {
           const long total = (long)start[2 * r + sp] + R.ngrid / d.span;
           if (total > 0x7fffffffL) return PIC_OK;  // beyond the int32 item index

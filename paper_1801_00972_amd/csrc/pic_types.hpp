@@ -134,12 +134,25 @@ struct PushDescF32 {
   MdTables md;
   SpeciesStep S;
   WorkLists L;
-  int span;  // tiles per push block (push_span)
+  int span;   // tiles per push block (push_span)
+  int chunk;  // z-layer chunk of the XCD interleaving (push_chunk)
 };
 
 // tiles per FP32R push block: pairs along x where the rows of tiles split into
 // pairs (the tile grid, a multiple of 16, then still gives a multiple of 8
 // blocks); the kernels that read the push's lists use the same span
 __host__ __device__ inline int push_span(const WorkLists& L) { return L.ntx % 2 == 0 ? 2 : 1; }
+
+// the chunk of the push blocks' XCD interleaving for a grid of ngrid / span
+// blocks: one z-layer of tile spans, cut down to a divisor of the blocks per
+// XCD
+inline int push_chunk(const WorkLists& L, int span) {
+  const int per_xcd = L.ngrid / span / 8;
+  int c = L.ntx * L.nty / span;
+  c = c < per_xcd ? c : per_xcd;
+  if (c < 1) c = 1;
+  while (c > 1 && per_xcd % c) --c;
+  return c;
+}
 
 }  // namespace pic
