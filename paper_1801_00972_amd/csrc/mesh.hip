@@ -151,7 +151,7 @@ struct FftGeom {
 };
 
 enum { IN_COMPLEX = 0, IN_REAL = 1 };
-enum { OUT_COMPLEX = 0, OUT_REAL_LIFT = 1, OUT_REAL_ACCUM = 2 };
+enum { OUT_COMPLEX = 0, OUT_REAL_LIFT = 1, OUT_REAL_ACCUM = 2, OUT_REAL_STORE = 3 };
 
 template <typename T, int IN, int OUT>
 __global__ __launch_bounds__(256) void fft_lines_kernel(FftGeom g, const cplx<T>* __restrict__ tw,
@@ -199,6 +199,8 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(FftGeom g, const cplx<T>
       // interior plane k = plane + 1 of phi
       rout[off + g.real_plane_offset] =
           (double)v.x * out_scale + V * (double)(plane + 1) / (double)nz;
+    } else if (OUT == OUT_REAL_STORE) {
+      rout[off] = (double)v.x * out_scale;
     } else {
       rout[off] += (double)v.x * out_scale;
     }
@@ -261,6 +263,8 @@ __global__ __launch_bounds__(kPlaneThreads) void fft_plane_kernel(Fft2Geom g, co
     } else if (OUT == OUT_REAL_LIFT) {
       // interior plane k = plane + 1 of phi
       rout[pbase + np + i] = (double)v.x * out_scale + V * (double)(plane + 1) / (double)nz;
+    } else if (OUT == OUT_REAL_STORE) {
+      rout[pbase + i] = (double)v.x * out_scale;
     } else {
       rout[pbase + i] += (double)v.x * out_scale;
     }
@@ -592,7 +596,8 @@ __global__ void extract_cube_kernel(const double2* __restrict__ E, const int* gc
 
 // ---------------------------------------------------------------- refinement
 // r = b - A psi on the interior nodes (psi = 0 on the electrodes), FP64;
-// accumulates ||r||^2 and ||b||^2
+// with NORMS, also the per-block partial sums of ||r||^2 and ||b||^2
+template <bool NORMS>
 __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict__ psi,
                                                        const double* __restrict__ b,
                                                        double* __restrict__ r, int nx, int ny,
@@ -620,6 +625,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
     rr = ri * ri;
     bb = bi * bi;
   }
+  if (!NORMS) return;
   s_r[threadIdx.x] = rr;
   s_b[threadIdx.x] = bb;
   __syncthreads();
@@ -847,6 +853,9 @@ static void fft_launch(const FftGeom& g, int planes, const void* tw, int forward
   else if (out_mode == OUT_REAL_LIFT)
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_LIFT>), dim3(blocks), dim3(256), lds,
                        st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
+  else if (out_mode == OUT_REAL_STORE)
+    hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_STORE>), dim3(blocks), dim3(256),
+                       lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
   else
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_ACCUM>), dim3(blocks), dim3(256),
                        lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
@@ -879,6 +888,9 @@ static void fft_plane_launch(const FftPlanHost& P, int nx, int ny, int planes, c
                        g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
   else if (out_mode == OUT_REAL_LIFT)
     hipLaunchKernelGGL((fft_plane_kernel<T, IN_COMPLEX, OUT_REAL_LIFT>), dim3(planes),
+                       dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
+  else if (out_mode == OUT_REAL_STORE)
+    hipLaunchKernelGGL((fft_plane_kernel<T, IN_COMPLEX, OUT_REAL_STORE>), dim3(planes),
                        dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
   else
     hipLaunchKernelGGL((fft_plane_kernel<T, IN_COMPLEX, OUT_REAL_ACCUM>), dim3(planes),
@@ -937,25 +949,28 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
                      (long)nx * ny, nz, rf);
 }
 
-// FP32 solves refined in FP64: psi = 0, r = b; repeat sweeps times
-// { psi += solve32(r); r = b - A psi }; phi = psi + lift.  norms[0..1] receive
-// ||r||^2, ||b||^2 of the last sweep; norms[2..] hold 2 partials per residual
-// block: ceil(nx ny / 256) blocks per interior plane.
+// FP32 solves refined in FP64: psi = solve32(b); r = b - A psi; then sweeps - 1
+// times { psi += solve32(r); r = b - A psi }; phi = psi + lift (sweeps >= 1).
+// norms[0..1] receive ||r||^2, ||b||^2 of the last sweep; norms[2..] hold 2
+// partials per residual block: ceil(nx ny / 256) blocks per interior plane.
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
                           const void* tw_y32, const void* inv32, double* phi, RfDrive rf,
                           int sweeps, double* norms, hipStream_t st) {
   const long plane = (long)nx * ny;
-  const long n_int = plane * (nz - 1);
-  hipLaunchKernelGGL(zero_f64_kernel, dim3(nb256(n_int)), dim3(256), 0, st, psi, n_int);
   const double* rhs = b;
   for (int it = 0; it < sweeps; ++it) {
-    solve_once<float>(P, nx, ny, nz, rhs, work32, tw_x32, tw_y32, inv32, OUT_REAL_ACCUM, psi, rf,
-                      st);
-    hipLaunchKernelGGL(residual_kernel, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi, b, r,
-                       nx, ny, nz - 1, norms + 2);
-    hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2,
-                       nb256(plane) * (nz - 1), norms);
+    solve_once<float>(P, nx, ny, nz, rhs, work32, tw_x32, tw_y32, inv32,
+                      it == 0 ? OUT_REAL_STORE : OUT_REAL_ACCUM, psi, rf, st);
+    if (it + 1 < sweeps) {
+      hipLaunchKernelGGL(residual_kernel<false>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi,
+                         b, r, nx, ny, nz - 1, norms + 2);
+    } else {
+      hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi,
+                         b, r, nx, ny, nz - 1, norms + 2);
+      hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2,
+                         nb256(plane) * (nz - 1), norms);
+    }
     rhs = r;
   }
   hipLaunchKernelGGL(lift_kernel, dim3(nb256(plane), nz + 1), dim3(256), 0, st, psi, phi, nx, ny, nz,
