@@ -99,6 +99,8 @@ def lib():
         L.orc_deposit_fixed.argtypes = [C.POINTER(_Config), C.POINTER(_State),
                                         C.POINTER(C.c_int64)]
         L.orc_moments.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp, dp]
+        L.orc_fine_moments.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp, C.c_double,
+                                       C.POINTER(C.c_int32), dp, dp]
         L.orc_poisson.argtypes = [C.POINTER(_Config), dp, C.c_double, dp]
         L.orc_efield.argtypes = [C.POINTER(_Config), dp, dp]
         L.orc_fields.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp,
@@ -265,6 +267,23 @@ class Oracle:
         if rc:
             raise RuntimeError(f"orc_moments failed ({rc})")
         return n.reshape(2, self.n_nodes), flux.reshape(2, 3, self.n_nodes)
+
+    def fine_moments(self, origin, h: float, cells):
+        """Densities [2][fine nodes] and fluxes [2][3][fine nodes] on the fine
+        grid of a sub-box (Sec. IV, the grid over the grains' region): lower
+        corner `origin` (grid units), cell edge `h` (grid units), `cells`
+        cells per axis, (cells + 1) nodes per axis, x fastest."""
+        o = np.ascontiguousarray(origin, np.float64)
+        m = np.ascontiguousarray(cells, np.int32)
+        fn = int(np.prod(m.astype(np.int64) + 1))
+        n = np.zeros(2 * fn)
+        flux = np.zeros(6 * fn)
+        rc = lib().orc_fine_moments(C.byref(self.cfg), C.byref(self.st), _ptr(o, C.c_double),
+                                    float(h), _ptr(m, C.c_int32), _ptr(n, C.c_double),
+                                    _ptr(flux, C.c_double))
+        if rc:
+            raise RuntimeError(f"orc_fine_moments failed ({rc})")
+        return n.reshape(2, fn), flux.reshape(2, 3, fn)
 
     def poisson(self, rho, V: float) -> np.ndarray:
         rho = np.ascontiguousarray(rho, np.float64)

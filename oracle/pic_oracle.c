@@ -247,6 +247,56 @@ int orc_moments(const orc_config* c, const orc_state* s, double* n, double* flux
   return 0;
 }
 
+/* Densities and fluxes on a fine cubical grid over a sub-box: the grid of   */
+/* 0.08 dx cells over the region of the grains (Sec. IV).  The box's lower    */
+/* corner is origin (grid units); its cells have edge h (grid units), m[a]    */
+/* cells and m[a] + 1 nodes per axis, x fastest.  A particle whose            */
+/* u = (x - origin) / h lies in [0, m) on every axis is assigned to the 8     */
+/* nodes of its fine cell with the cloud-in-cell weights; a particle outside  */
+/* the box adds nothing.  n = w sum W / (h dx)^3, flux = w sum v W / (h dx)^3. */
+int orc_fine_moments(const orc_config* c, const orc_state* s, const double origin[3], double h,
+                     const int32_t m[3], double* n, double* flux)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return -1;
+  if (!(h > 0.0) || m[0] < 1 || m[1] < 1 || m[2] < 1) return -2;
+  const int64_t mx = m[0] + 1, my = m[1] + 1, mz = m[2] + 1;
+  const int64_t fn = mx * my * mz;
+  memset(n, 0, sizeof(double) * 2 * fn);
+  memset(flux, 0, sizeof(double) * 6 * fn);
+  const double hdx = h * c->dx;
+  const double scale = d.w / (hdx * hdx * hdx);
+  for (int sp = 0; sp < 2; ++sp) {
+    double* ns = n + sp * fn;
+    double* fs = flux + 3 * sp * fn;
+    for (int64_t p = 0; p < s->n[sp]; ++p) {
+      if (!s->alive[sp][p]) continue;
+      const double* x = &s->pos[sp][3 * p];
+      const double* v = &s->vel[sp][3 * p];
+      double u[3];
+      int inside = 1;
+      for (int a = 0; a < 3; ++a) {
+        u[a] = (x[a] - origin[a]) / h;
+        if (!(u[a] >= 0.0 && u[a] < (double)m[a])) inside = 0;
+      }
+      if (!inside) continue;
+      const int64_t i0 = (int64_t)floor(u[0]), j0 = (int64_t)floor(u[1]), k0 = (int64_t)floor(u[2]);
+      const double fx = u[0] - (double)i0, fy = u[1] - (double)j0, fz = u[2] - (double)k0;
+      for (int cc = 0; cc < 2; ++cc)
+        for (int b = 0; b < 2; ++b)
+          for (int a = 0; a < 2; ++a) {
+            const double wt = (a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy) * (cc ? fz : 1.0 - fz);
+            const int64_t node = ((k0 + cc) * my + (j0 + b)) * mx + (i0 + a);
+            ns[node] += wt;
+            for (int q = 0; q < 3; ++q) fs[q * fn + node] += v[q] * wt;
+          }
+    }
+  }
+  for (int64_t q = 0; q < 2 * fn; ++q) n[q] *= scale;
+  for (int64_t q = 0; q < 6 * fn; ++q) flux[q] *= scale;
+  return 0;
+}
+
 /* Fixed-point CIC: the macro charge Qp (2^-32 e) is split along x, then each */
 /* half along y, then each quarter along z, by q1 = (Q * f24) >> 24 and        */
 /* q0 = Q - q1, where f24 = floor(offset * 2^24).  The 8 parts sum to Qp.      */

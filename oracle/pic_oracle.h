@@ -102,6 +102,8 @@ int orc_deposit(const orc_config* c, const orc_state* s, double* rho);
 int orc_deposit_fixed(const orc_config* c, const orc_state* s, int64_t* rho_fixed);
 /* densities n [2][nodes] (m^-3) and fluxes [2][3][nodes] (m^-2 s^-1) */
 int orc_moments(const orc_config* c, const orc_state* s, double* n, double* flux);
+int orc_fine_moments(const orc_config* c, const orc_state* s, const double origin[3], double h,
+                     const int32_t m[3], double* n, double* flux);
 
 /* Poisson: phi on all nodes, Dirichlet phi(k=0)=0, phi(k=nz)=V */
 int orc_poisson(const orc_config* c, const double* rho, double V, double* phi);

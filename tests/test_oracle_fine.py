@@ -1,0 +1,121 @@
+"""Pins of the oracle's fine-grid moments: the densities and fluxes on the
+fine cubical grid over the grains' region (Sec. IV, cells of 0.08 dx), with
+the cloud-in-cell weights of Sec. III on the fine nodes.
+
+Pins: with unit fine cells on an integer origin the fine grid is a block of
+the PIC mesh, so the fine moments equal the PIC moments (pinned on their own)
+on those nodes; number conservation and linear reproduction with a
+non-integer origin and h (which fix the scale, each axis and the node
+positions o + h i); flux = n v for a common velocity; a particle on a fine
+node puts all its weight there; particles outside the box add nothing.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_00972_amd import workloads as W
+
+
+def _oracle(wl, pos_e, vel_e, pos_i=None, vel_i=None):
+    o = oracle.Oracle(wl)
+    pos_i = np.zeros((0, 3)) if pos_i is None else pos_i
+    vel_i = np.zeros((0, 3)) if vel_i is None else vel_i
+    o.set_particles(0, pos_e, vel_e, np.arange(len(pos_e)))
+    o.set_particles(1, pos_i, vel_i, np.arange(len(pos_i)))
+    return o
+
+
+def _nodes(origin, h, cells):
+    """Positions (grid units) of the fine nodes, x fastest: [3][fine nodes]."""
+    ax = [origin[a] + h * np.arange(cells[a] + 1) for a in range(3)]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()])
+
+
+def test_unit_cells_on_integer_origin_match_the_pic_moments():
+    wl = W.tiny(nx=8, ny=7, nz=9)
+    rng = np.random.default_rng(11)
+    lo, hi = np.array([1.0, 1.0, 1.0]), np.array([7.0, 6.0, 8.0])
+    pos = rng.uniform(lo, hi, size=(500, 3))
+    vel = rng.normal(size=(500, 3)) * [1e5, 2e5, 3e5]
+    pos_i = rng.uniform(lo, hi, size=(300, 3))
+    vel_i = rng.normal(size=(300, 3)) * 300.0
+    o = _oracle(wl, pos, vel, pos_i, vel_i)
+    cells = [6, 5, 7]
+    fn, ff = o.fine_moments(lo, 1.0, cells)
+    n, flux = o.moments()
+    nx, ny, nz = wl["nx"], wl["ny"], wl["nz"]
+    for s in range(2):
+        block = n[s].reshape(nz + 1, ny, nx)[1:9, 1:7, 1:8]
+        np.testing.assert_allclose(fn[s].reshape(8, 6, 7), block, rtol=1e-14, atol=0)
+        for a in range(3):
+            block = flux[s, a].reshape(nz + 1, ny, nx)[1:9, 1:7, 1:8]
+            np.testing.assert_allclose(ff[s, a].reshape(8, 6, 7), block, rtol=1e-13,
+                                       atol=1e-14 * np.abs(flux).max())
+
+
+def test_number_and_first_moments_are_conserved():
+    wl = W.tiny(nx=8, ny=7, nz=9)
+    rng = np.random.default_rng(12)
+    origin, h, cells = np.array([2.3, 1.7, 3.1]), 0.08, [30, 40, 25]
+    top = origin + h * np.array(cells)
+    # half inside the box, half anywhere in the domain
+    pos = np.concatenate([rng.uniform(origin, top, size=(400, 3)),
+                          rng.uniform([0, 0, 0], [8, 7, 9], size=(400, 3))])
+    vel = rng.normal(size=(800, 3)) * [1e5, 2e5, 3e5]
+    o = _oracle(wl, pos, vel)
+    fn, ff = o.fine_moments(origin, h, cells)
+    inside = np.all((pos >= origin) & (pos < top), axis=1)
+    w = o.derived()["w"]
+    vol = (h * wl["dx"]) ** 3
+    assert fn[0].sum() * vol == pytest.approx(w * inside.sum(), rel=1e-12)
+    node = _nodes(origin, h, cells)
+    for a in range(3):
+        assert (fn[0] * node[a]).sum() * vol == pytest.approx(w * pos[inside, a].sum(), rel=1e-12)
+        assert ff[0, a].sum() * vol == pytest.approx(w * vel[inside, a].sum(), rel=1e-11)
+    assert not np.any(fn[1]) and not np.any(ff[1])
+
+
+def test_common_velocity_gives_flux_n_v():
+    wl = W.tiny(nx=6, ny=5, nz=7)
+    rng = np.random.default_rng(13)
+    origin, h, cells = np.array([1.5, 1.25, 2.0]), 0.25, [12, 10, 14]
+    pos = rng.uniform([0, 0, 0], [6, 5, 7], size=(600, 3))
+    v0 = np.array([-3.0e5, 1.0e5, 2.0e5])
+    o = _oracle(wl, np.zeros((0, 3)), np.zeros((0, 3)), pos, np.tile(v0, (600, 1)))
+    fn, ff = o.fine_moments(origin, h, cells)
+    assert fn[1].sum() > 0
+    for a in range(3):
+        np.testing.assert_allclose(ff[1, a], fn[1] * v0[a], rtol=1e-13, atol=0)
+
+
+def test_particle_on_a_fine_node_weighs_only_that_node():
+    wl = W.tiny(nx=6, ny=5, nz=7)
+    origin, h, cells = np.array([0.5, 0.75, 1.0]), 0.25, [8, 8, 8]
+    idx = (3, 5, 2)
+    pos = np.array([[origin[a] + h * idx[a] for a in range(3)]])
+    o = _oracle(wl, pos, np.array([[1.0, 2.0, 3.0]]))
+    fn, ff = o.fine_moments(origin, h, cells)
+    expect = o.derived()["w"] / (h * wl["dx"]) ** 3
+    node = (idx[2] * 9 + idx[1]) * 9 + idx[0]
+    assert fn[0, node] == pytest.approx(expect, rel=1e-15)
+    assert np.count_nonzero(fn[0]) == 1
+    assert ff[0, 2, node] == pytest.approx(3.0 * expect, rel=1e-15)
+
+
+def test_particles_outside_the_box_add_nothing():
+    wl = W.tiny(nx=6, ny=5, nz=7)
+    rng = np.random.default_rng(14)
+    origin, h, cells = np.array([2.0, 1.0, 3.0]), 0.1, [10, 20, 15]
+    top = origin + h * np.array(cells)
+    pos = rng.uniform(origin, top, size=(200, 3))
+    vel = rng.normal(size=(200, 3)) * 1e5
+    # outside: one axis pushed past each face, including the top face itself
+    out = rng.uniform(origin, top, size=(6, 3))
+    for f in range(6):
+        a = f % 3
+        out[f, a] = origin[a] - 0.01 if f < 3 else top[a]
+    base = _oracle(wl, pos, vel).fine_moments(origin, h, cells)
+    more = _oracle(wl, np.concatenate([pos, out]),
+                   np.concatenate([vel, rng.normal(size=(6, 3)) * 1e5])).fine_moments(origin, h, cells)
+    assert np.array_equal(base[0], more[0]) and np.array_equal(base[1], more[1])
