@@ -61,6 +61,8 @@ extern "C" {
 #define PIC_RHO_FIXED 8u  /* int64  [nodes]  PIC_FP32R only     2^-32 e  */
 #define PIC_N        16u  /* double [2][nodes] e, Ar+           m^-3     */
 #define PIC_FLUX     32u  /* double [2][3][nodes] e, Ar+; x,y,z m^-2 s^-1 */
+#define PIC_FINE_N   64u  /* double [2][fine nodes]               m^-3     */
+#define PIC_FINE_FLUX 128u /* double [2][3][fine nodes]           m^-2 s^-1 */
 
 /*
  * One replica.  Read-only; copied by pic_init.
@@ -158,7 +160,8 @@ int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C);
 /*
  * pic_fields -- the mesh quantities at the current step k for the current
  * particle state (solving if needed): out[b] receives the quantity of the
- * b-th set bit of `what`, in the order PHI, E, RHO, RHO_FIXED, N, FLUX.
+ * b-th set bit of `what`, in the order PHI, E, RHO, RHO_FIXED, N, FLUX,
+ * FINE_N, FINE_FLUX (the last two on the fine grid of pic_set_fine_grid).
  * Buffers are host pointers (out_on_device = 0, the call synchronises) or
  * device pointers on the context's device (out_on_device = 1,
  * stream-ordered).  Every array is x-fastest over the nx ny (nz+1) nodes.
@@ -170,7 +173,7 @@ int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C);
  * are computed on request (summed in FP64 with atomics, so the last bits
  * depend on the order of additions) and are not part of pic_step.
  * Errors: PIC_EINVAL (bad replica, NULL buffer, RHO_FIXED without FP32R,
- * unknown bits).
+ * unknown bits), PIC_ESTATE (FINE bits without a fine grid).
  */
 int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int out_on_device);
 
@@ -192,16 +195,51 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
  *
  * pic_average_read -- the averages of bin `bin` (or over all bins for
  * bin = -1): out[b] receives the quantity of the b-th set bit of `what` (a
- * subset of PIC_PHI | PIC_N | PIC_FLUX, layouts as in pic_fields), each the
+ * subset of PIC_PHI | PIC_N | PIC_FLUX, with PIC_FINE_N | PIC_FINE_FLUX
+ * when the fine grid was sampled, layouts as in pic_fields), each the
  * sum over samples divided by their number (zeros with no sample).
  * samples (nullable host pointer) receives that number.  Buffers as in
  * pic_fields.  Errors: PIC_EINVAL (bad replica, bin, bits or buffer),
- * PIC_ESTATE (pic_average never started).
+ * PIC_ESTATE (pic_average never started, or FINE bits without fine sums).
  */
 #define PIC_MAX_PHASE_BINS 64
 int pic_average(pic_ctx* ctx, int interval, int phase_bins);
 int pic_average_read(pic_ctx* ctx, int replica, int bin, unsigned what, void* const* out,
                      int out_on_device, int64_t* samples);
+
+/*
+ * Fine diagnostic grid (the paper's results, Sec. IV: densities and fluxes
+ * over the region of the grains on a cubical grid of 0.08 dx cells, much
+ * finer than the PIC cells).
+ *
+ * pic_set_fine_grid -- sets (g != NULL) or removes (NULL) the fine grid of
+ * a replica.  g->origin is the box's lower corner in grid units (cells of
+ * dx), g->h the fine cell edge in grid units (> 0), g->cells[a] >= 1 the
+ * cells per axis; the fine nodes are origin + h (i, j, k), cells[a] + 1 per
+ * axis, x fastest, at most PIC_MAX_FINE_NODES.  The box lies inside the
+ * domain: 0 <= origin[a] and origin[a] + cells[a] h <= nx, ny, nz (no
+ * periodic wrap).  A particle at x (grid units) whose u = (x - origin) / h
+ * lies in [0, cells[a]) on every axis adds its cloud-in-cell weights W for
+ * the 8 nodes of its fine cell; other particles add nothing.  Per species:
+ * n = (w / (h dx)^3) sum W and flux = (w / (h dx)^3) sum v W, with x_k and
+ * v_{k-1/2} as for PIC_N and PIC_FLUX (FP64 sums with atomics).
+ * With a fine grid set, pic_fields accepts PIC_FINE_N and PIC_FINE_FLUX, and
+ * a later pic_average also samples the fine grid, after which
+ * pic_average_read accepts the same bits (their output buffers follow the
+ * PIC quantities' in out[]).  Setting or removing the grid drops the fine
+ * sums of earlier averaging.  Device memory: 8 doubles per fine node for
+ * pic_fields, and 8 per fine node and phase bin while averaging.
+ * Errors: PIC_EINVAL (bad replica, h, cells, or a box outside the domain),
+ * PIC_ESTATE (averaging is running: stop it with interval 0 first).
+ */
+typedef struct pic_fine_grid {
+  double origin[3];  /* lower corner, grid units */
+  double h;          /* fine cell edge, grid units */
+  int32_t cells[3];  /* fine cells per axis */
+  int32_t reserved;  /* 0 */
+} pic_fine_grid;
+#define PIC_MAX_FINE_NODES (1L << 26)
+int pic_set_fine_grid(pic_ctx* ctx, int replica, const pic_fine_grid* g);
 
 /* pic_destroy -- free the context and all its device memory (NULL is a no-op). */
 void pic_destroy(pic_ctx* ctx);

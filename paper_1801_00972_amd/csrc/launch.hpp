@@ -60,13 +60,19 @@ void launch_deposit_f32r(const PartF32R& P, long long* rho, const MdTables& md,
 void launch_moments(const PartF64* P64, const PartF32R* P32, const SpeciesStep& S,
                     const WorkLists& L, double* mom, long nn, const AvgBins& avg,
                     hipStream_t st);
+// fine-grid moments of one species: mom [4][fb.fn] gets W, v W of the
+// particles inside the box summed per fine node (added as in launch_moments);
+// capacity bounds the slots in use
+void launch_fine_moments(const PartF64* P64, const PartF32R* P32, const WorkLists& L,
+                         const FineBox& fb, double* mom, const AvgBins& avg, long capacity,
+                         hipStream_t st);
 // time averages: phi added to its rf-phase bin (avg.stride apart), and one
 // sample counted in cnt[bin]
 void launch_avg_phi(const double* phi, double* acc, long nn, const AvgBins& avg,
                     unsigned long long* cnt, hipStream_t st);
 // out[u] = (sum over bins b0..b1-1 of acc[b stride + u]) / (samples in those
-// bins), times wv for u >= nn (the moments), for u < 9 nn
-void launch_avg_out(const double* acc, int b0, int b1, long stride, long nn,
+// bins), times wv for u >= n_plain (the moments), for u < total
+void launch_avg_out(const double* acc, int b0, int b1, long stride, long total, long n_plain,
                     const unsigned long long* cnt, double wv, double* out, hipStream_t st);
 // counting sort of the slots in use into dst (dropping empty slots, padding
 // every tile to a multiple of 4); capacity bounds the slots in use

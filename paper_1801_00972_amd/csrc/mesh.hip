@@ -789,19 +789,19 @@ __global__ void avg_phi_kernel(const double* __restrict__ phi, double* __restric
   if (n < nn) acc[avg.stride * b + n] += phi[n];
 }
 
-// the averages over bins b0..b1-1: phi (u < nn) and the moments (times wv)
-__global__ void avg_out_kernel(const double* __restrict__ acc, int b0, int b1, long stride, long nn,
-                               const unsigned long long* __restrict__ cnt, double wv,
-                               double* __restrict__ out) {
+// the averages over bins b0..b1-1: phi (u < n_plain) and the moments (times wv)
+__global__ void avg_out_kernel(const double* __restrict__ acc, int b0, int b1, long stride,
+                               long total, long n_plain, const unsigned long long* __restrict__ cnt,
+                               double wv, double* __restrict__ out) {
   const long u = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= 9 * nn) return;
+  if (u >= total) return;
   double s = 0.0;
   unsigned long long c = 0;
   for (int b = b0; b < b1; ++b) {
     s += acc[stride * b + u];
     c += cnt[b];
   }
-  out[u] = c ? s / (double)c * (u < nn ? 1.0 : wv) : 0.0;
+  out[u] = c ? s / (double)c * (u < n_plain ? 1.0 : wv) : 0.0;
 }
 
 __global__ void zero_f64_kernel(double* a, long n) {
@@ -1050,10 +1050,11 @@ void launch_avg_phi(const double* phi, double* acc, long nn, const AvgBins& avg,
   hipLaunchKernelGGL(avg_phi_kernel, dim3(nb256(nn)), dim3(256), 0, st, phi, acc, nn, avg, cnt);
 }
 
-void launch_avg_out(const double* acc, int b0, int b1, long stride, long nn,
+void launch_avg_out(const double* acc, int b0, int b1, long stride, long total, long n_plain,
                     const unsigned long long* cnt, double wv, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(avg_out_kernel, dim3(nb256(9 * nn)), dim3(256), 0, st, acc, b0, b1, stride, nn,
-                     cnt, wv, out);
+  if (total <= 0) return;
+  hipLaunchKernelGGL(avg_out_kernel, dim3(nb256(total)), dim3(256), 0, st, acc, b0, b1, stride,
+                     total, n_plain, cnt, wv, out);
 }
 
 void launch_zero_f64(double* a, long n, hipStream_t st) {

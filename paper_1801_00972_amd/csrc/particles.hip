@@ -1512,6 +1512,62 @@ __global__ __launch_bounds__(256) void moments_kernel(PT P, SpeciesStep S, WorkL
   }
 }
 
+// Fine diagnostic grid (the grid finer than the PIC cells over the grains'
+// region, Sec. IV): a particle whose u = (x - o) / h lies in [0, m) on every
+// axis adds its cloud-in-cell weights W and v W to the 8 nodes of its fine
+// cell.  Grid-stride over the slots in use; the PIC cell is tested first, so
+// the records of particles far from the box are not read whole.  Global FP64
+// atomics: the box holds few particles per fine cell.
+__device__ __forceinline__ bool fine_cell_near(const FineBox& fb, int i, int j, int k) {
+  return i >= fb.lo[0] && i < fb.hi[0] && j >= fb.lo[1] && j < fb.hi[1] && k >= fb.lo[2] &&
+         k < fb.hi[2];
+}
+__device__ __forceinline__ bool fine_near(const PartF64& P, long p, const FineBox& fb) {
+  const double z = P.z[p];
+  if (!(z >= 0.0)) return false;
+  return fine_cell_near(fb, (int)floor(P.x[p]), (int)floor(P.y[p]), (int)floor(z));
+}
+__device__ __forceinline__ bool fine_near(const PartF32R& P, long p, const FineBox& fb) {
+  const int c = P.cell[p];
+  return c >= 0 && fine_cell_near(fb, cell_i(c), cell_j(c), cell_k(c));
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void fine_moments_kernel(PT P, WorkLists L, FineBox fb,
+                                                           double* __restrict__ mom,
+                                                           AvgBins avg) {
+  if (avg.step) mom += avg.stride * phase_bin(*avg.step, avg.f_rf, avg.dt, avg.nbins);
+  const long total = L.tstart[L.ngrid];
+  for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+       p += (long)gridDim.x * blockDim.x) {
+    if (!fine_near(P, p, fb)) continue;
+    double x[3], v[3], u[3];
+    load_d(P, p, x, v);
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      u[a] = (x[a] - fb.o[a]) / fb.h;
+      in = in && u[a] >= 0.0 && u[a] < (double)fb.m[a];
+    }
+    if (!in) continue;
+    const long i = (long)floor(u[0]), j = (long)floor(u[1]), k = (long)floor(u[2]);
+    const double fx = u[0] - (double)i, fy = u[1] - (double)j, fz = u[2] - (double)k;
+    const long base = (k * fb.my + j) * fb.mx + i;
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const double wt = (a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy) * (cc ? fz : 1.0 - fz);
+          const long node = base + ((long)cc * fb.my + b) * fb.mx + a;
+          unsafeAtomicAdd(&mom[node], wt);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) unsafeAtomicAdd(&mom[(q + 1) * fb.fn + node], v[q] * wt);
+        }
+  }
+}
+
 // The collisions of the MD particles that survived their sub-cycled motion,
 // from their stored velocities (same list, blocks and tally rows as md_kernel).
 template <typename PT>
@@ -2312,6 +2368,19 @@ void launch_moments(const PartF64* P64, const PartF32R* P32, const SpeciesStep& 
   else
     hipLaunchKernelGGL(moments_kernel<PartF32R>, dim3(L.ngrid), dim3(256), 0, st, *P32, S, L, mom,
                        nn, avg);
+}
+
+void launch_fine_moments(const PartF64* P64, const PartF32R* P32, const WorkLists& L,
+                         const FineBox& fb, double* mom, const AvgBins& avg, long capacity,
+                         hipStream_t st) {
+  const int blocks = (int)std::min<long>(nblk(capacity, 256), 4096);
+  if (blocks <= 0) return;
+  if (P64)
+    hipLaunchKernelGGL(fine_moments_kernel<PartF64>, dim3(blocks), dim3(256), 0, st, *P64, L, fb,
+                       mom, avg);
+  else
+    hipLaunchKernelGGL(fine_moments_kernel<PartF32R>, dim3(blocks), dim3(256), 0, st, *P32, L, fb,
+                       mom, avg);
 }
 
 void launch_fill_int(int* a, long n, int v, hipStream_t st) {

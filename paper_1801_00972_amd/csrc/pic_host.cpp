@@ -74,6 +74,15 @@ struct Replica {
   unsigned long long* d_avg_cnt = nullptr;
   int avg_cap = 0;  // bins allocated
   double* avg_out = nullptr;
+  // fine diagnostic grid (pic_set_fine_grid): moments for pic_fields [2][4][fn],
+  // per-bin sums while averaging [bins][2][4][fn] (fine_avg_on: the sums
+  // belong to the current box), the read-out buffer
+  bool fine_on = false, fine_avg_on = false;
+  FineBox fine{};
+  double* fine_mom = nullptr;
+  double* fine_avg = nullptr;
+  int fine_cap = 0;
+  double* fine_out = nullptr;
   // near-grain tables
   MdTables md{};
   double* d_Q = nullptr;
@@ -178,6 +187,19 @@ int dalloc(pic_ctx* ctx, Replica& R, T** p, size_t count) {
   R.mem.blocks.push_back(q);
   *p = static_cast<T*>(q);
   return PIC_OK;
+}
+
+template <typename T>
+void dfree(Replica& R, T*& p) {
+  if (!p) return;
+  auto& v = R.mem.blocks;
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i] == (void*)p) {
+      (void)hipFree(v[i]);
+      v.erase(v.begin() + (long)i);
+      break;
+    }
+  p = nullptr;
 }
 
 #define TRY(x)               \
@@ -557,6 +579,22 @@ AvgBins avg_bins_of(const pic_ctx* ctx, const Replica& R) {
   return AvgBins{R.d_step, R.cfg.f_rf, R.cfg.dt, ctx->avg_bins, 9 * R.nn};
 }
 
+// fine-grid moments of both species added to mom [2][4][fn] (in the
+// rf-phase bin of the step when avg.step is set)
+int enqueue_fine(pic_ctx* ctx, Replica& R, double* mom, const AvgBins& avg) {
+  for (int sp = 0; sp < 2; ++sp) {
+    double* m = mom + 4 * R.fine.fn * sp;
+    if (R.prec == PIC_FP64)
+      launch_fine_moments(&R.p64[sp][R.cur[sp]], nullptr, R.lists[sp], R.fine, m, avg, R.cap[sp],
+                          ctx->stream);
+    else
+      launch_fine_moments(nullptr, &R.p32[sp][R.cur[sp]], R.lists[sp], R.fine, m, avg, R.cap[sp],
+                          ctx->stream);
+  }
+  CHECK_LAUNCH(ctx);
+  return PIC_OK;
+}
+
 // one sample of the time averages at the start of a step: phi_k and the
 // moments of x_k, v_{k-1/2}, into the rf-phase bin of step k
 int enqueue_sample(pic_ctx* ctx, Replica& R) {
@@ -570,6 +608,10 @@ int enqueue_sample(pic_ctx* ctx, Replica& R) {
       launch_moments(&R.p64[sp][R.cur[sp]], nullptr, S, R.lists[sp], m, R.nn, ab, st);
     else
       launch_moments(nullptr, &R.p32[sp][R.cur[sp]], S, R.lists[sp], m, R.nn, ab, st);
+  }
+  if (R.fine_avg_on) {
+    const AvgBins fb{R.d_step, R.cfg.f_rf, R.cfg.dt, ctx->avg_bins, 8 * R.fine.fn};
+    TRY(enqueue_fine(ctx, R, R.fine_avg, fb));
   }
   CHECK_LAUNCH(ctx);
   return PIC_OK;
@@ -1113,9 +1155,11 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
   if (ctx->sticky) return ctx->sticky;
   Replica* R = get_rep(ctx, replica);
   if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
-  if (!out || (what & ~63u)) return fail(ctx, PIC_EINVAL, "bad selection or out");
+  if (!out || (what & ~255u)) return fail(ctx, PIC_EINVAL, "bad selection or out");
   if ((what & PIC_RHO_FIXED) && R->prec != PIC_FP32R)
     return fail(ctx, PIC_EINVAL, "PIC_RHO_FIXED needs the FP32R form");
+  if ((what & (PIC_FINE_N | PIC_FINE_FLUX)) && !R->fine_on)
+    return fail(ctx, PIC_ESTATE, "no fine grid: call pic_set_fine_grid");
   hipStream_t st = ctx->stream;
   TRY(solve_fields(ctx, *R));
   const long nn = R->nn;
@@ -1139,11 +1183,26 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
     launch_scale(R->mom, nullptr, R->w / vol, R->mom, 8 * nn, st);
     CHECK_LAUNCH(ctx);
   }
-  for (unsigned bit = 1; bit <= PIC_FLUX; bit <<= 1) {
+  const long fn = R->fine.fn;
+  if (what & (PIC_FINE_N | PIC_FINE_FLUX)) {
+    if (!R->fine_mom) TRY(dalloc(ctx, *R, &R->fine_mom, 8 * fn));
+    launch_zero_f64(R->fine_mom, 8 * fn, st);
+    TRY(enqueue_fine(ctx, *R, R->fine_mom, AvgBins{}));
+    const double hdx = R->fine.h * R->cfg.dx;
+    launch_scale(R->fine_mom, nullptr, R->w / (hdx * hdx * hdx), R->fine_mom, 8 * fn, st);
+    CHECK_LAUNCH(ctx);
+  }
+  for (unsigned bit = 1; bit <= PIC_FINE_FLUX; bit <<= 1) {
     if (!(what & bit)) continue;
     void* dst = out[slot++];
     if (!dst) return fail(ctx, PIC_EINVAL, "NULL output buffer");
-    if (bit == PIC_PHI) {
+    if (bit == PIC_FINE_N || bit == PIC_FINE_FLUX) {
+      const long len = bit == PIC_FINE_FLUX ? 3 * fn : fn;
+      for (int sp = 0; sp < 2; ++sp)
+        HIPCHK(ctx, hipMemcpyAsync((char*)dst + sp * len * 8,
+                                   R->fine_mom + (4 * sp + (bit == PIC_FINE_FLUX ? 1 : 0)) * fn,
+                                   len * 8, kind, st));
+    } else if (bit == PIC_PHI) {
       HIPCHK(ctx, hipMemcpyAsync(dst, R->phi, nn * 8, kind, st));
     } else if (bit == PIC_N) {
       for (int sp = 0; sp < 2; ++sp)
@@ -1197,6 +1256,17 @@ int pic_average(pic_ctx* ctx, int interval, int phase_bins) {
     }
     launch_zero_f64(R->avg, 9 * R->nn * phase_bins, st);
     launch_zero_i64((long long*)R->d_avg_cnt, phase_bins, st);
+    R->fine_avg_on = R->fine_on;
+    if (R->fine_on) {
+      const long fn = R->fine.fn;
+      if (R->fine_cap < phase_bins) {
+        dfree(*R, R->fine_avg);
+        R->fine_cap = 0;
+        TRY(dalloc(ctx, *R, &R->fine_avg, (size_t)8 * fn * phase_bins));
+        R->fine_cap = phase_bins;
+      }
+      launch_zero_f64(R->fine_avg, 8 * fn * phase_bins, st);
+    }
   }
   CHECK_LAUNCH(ctx);
   ctx->avg_interval = interval;
@@ -1213,22 +1283,39 @@ int pic_average_read(pic_ctx* ctx, int replica, int bin, unsigned what, void* co
   Replica* R = get_rep(ctx, replica);
   if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
   if (!R->avg || ctx->avg_bins == 0) return fail(ctx, PIC_ESTATE, "no averages: call pic_average");
-  if ((what & ~(PIC_PHI | PIC_N | PIC_FLUX)) || (what && !out))
+  if ((what & ~(PIC_PHI | PIC_N | PIC_FLUX | PIC_FINE_N | PIC_FINE_FLUX)) || (what && !out))
     return fail(ctx, PIC_EINVAL, "bad selection or out");
+  if ((what & (PIC_FINE_N | PIC_FINE_FLUX)) && !R->fine_avg_on)
+    return fail(ctx, PIC_ESTATE, "no fine-grid averages: set the fine grid before pic_average");
   if (bin < -1 || bin >= ctx->avg_bins) return fail(ctx, PIC_EINVAL, "bad bin");
   hipStream_t st = ctx->stream;
   const long nn = R->nn;
   const int b0 = bin < 0 ? 0 : bin, b1 = bin < 0 ? ctx->avg_bins : bin + 1;
   if (!R->avg_out) TRY(dalloc(ctx, *R, &R->avg_out, 9 * nn));
   const double vol = R->cfg.dx * R->cfg.dx * R->cfg.dx;
-  launch_avg_out(R->avg, b0, b1, 9 * nn, nn, R->d_avg_cnt, R->w / vol, R->avg_out, st);
+  launch_avg_out(R->avg, b0, b1, 9 * nn, 9 * nn, nn, R->d_avg_cnt, R->w / vol, R->avg_out, st);
+  const long fn = R->fine.fn;
+  if (what & (PIC_FINE_N | PIC_FINE_FLUX)) {
+    if (!R->fine_out) TRY(dalloc(ctx, *R, &R->fine_out, 8 * fn));
+    const double hdx = R->fine.h * R->cfg.dx;
+    launch_avg_out(R->fine_avg, b0, b1, 8 * fn, 8 * fn, 0, R->d_avg_cnt, R->w / (hdx * hdx * hdx),
+                   R->fine_out, st);
+  }
   CHECK_LAUNCH(ctx);
   const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   int slot = 0;
-  for (unsigned bit : {PIC_PHI, PIC_N, PIC_FLUX}) {
+  for (unsigned bit : {PIC_PHI, PIC_N, PIC_FLUX, PIC_FINE_N, PIC_FINE_FLUX}) {
     if (!(what & bit)) continue;
     char* dst = (char*)out[slot++];
     if (!dst) return fail(ctx, PIC_EINVAL, "NULL output buffer");
+    if (bit == PIC_FINE_N || bit == PIC_FINE_FLUX) {
+      const long len = bit == PIC_FINE_FLUX ? 3 * fn : fn;
+      for (int sp = 0; sp < 2; ++sp)
+        HIPCHK(ctx, hipMemcpyAsync(dst + sp * len * 8,
+                                   R->fine_out + (4 * sp + (bit == PIC_FINE_FLUX ? 1 : 0)) * fn,
+                                   len * 8, kind, st));
+      continue;
+    }
     for (int sp = 0; sp < (bit == PIC_PHI ? 1 : 2); ++sp) {
       const double* src = bit == PIC_PHI ? R->avg_out
                           : R->avg_out + (1 + 4 * sp + (bit == PIC_FLUX ? 1 : 0)) * nn;
@@ -1244,6 +1331,49 @@ int pic_average_read(pic_ctx* ctx, int replica, int bin, unsigned what, void* co
     for (int b = b0; b < b1; ++b) *samples += (int64_t)c[b];
   }
   if (!out_on_device) HIPCHK(ctx, hipStreamSynchronize(st));
+  return PIC_OK;
+}
+
+int pic_set_fine_grid(pic_ctx* ctx, int replica, const pic_fine_grid* g) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
+  if (ctx->avg_interval > 0)
+    return fail(ctx, PIC_ESTATE, "averaging is running: stop it before changing the fine grid");
+  FineBox fb{};
+  if (g) {
+    const int n[3] = {R->nx, R->ny, R->nz};
+    if (!(std::isfinite(g->h) && g->h > 0.0)) return fail(ctx, PIC_EINVAL, "fine grid: h must be > 0");
+    long nodes = 1;
+    for (int a = 0; a < 3; ++a) {
+      if (g->cells[a] < 1) return fail(ctx, PIC_EINVAL, "fine grid: cells must be >= 1");
+      const double top = g->origin[a] + g->h * (double)g->cells[a];
+      if (!(std::isfinite(g->origin[a]) && g->origin[a] >= 0.0 && top <= (double)n[a]))
+        return fail(ctx, PIC_EINVAL, "fine grid: the box must lie inside the domain");
+      nodes *= (long)g->cells[a] + 1;
+      if (nodes > PIC_MAX_FINE_NODES)
+        return fail(ctx, PIC_EINVAL, "fine grid: more than PIC_MAX_FINE_NODES nodes");
+      fb.o[a] = g->origin[a];
+      fb.m[a] = g->cells[a];
+      // PIC cells that can hold a particle of the box, one cell of slack for rounding
+      fb.lo[a] = (int)std::floor(g->origin[a]) - 1;
+      fb.hi[a] = (int)std::ceil(top) + 1;
+    }
+    fb.h = g->h;
+    fb.mx = (long)fb.m[0] + 1;
+    fb.my = (long)fb.m[1] + 1;
+    fb.fn = nodes;
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  dfree(*R, R->fine_mom);
+  dfree(*R, R->fine_avg);
+  dfree(*R, R->fine_out);
+  R->fine_cap = 0;
+  R->fine_avg_on = false;
+  R->fine_on = g != nullptr;
+  R->fine = fb;
+  ctx->drop_graphs();  // captured samples hold the fine buffers
   return PIC_OK;
 }
 

@@ -126,6 +126,17 @@ struct AvgBins {
   long stride;
 };
 
+// fine diagnostic grid over a sub-box: lower corner o and cell edge h in
+// grid units, m cells per axis; PIC cells lo <= cell < hi can hold a particle
+// inside; mx, my nodes along x, y and fn nodes in all (x fastest)
+struct FineBox {
+  double o[3];
+  double h;
+  int m[3];
+  int lo[3], hi[3];
+  long mx, my, fn;
+};
+
 // one (replica, species) of a batched push launch
 struct PushDescF32 {
   PartF32R P;

@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 PIC_OK, PIC_EINVAL, PIC_ECONFIG, PIC_ENOMEM, PIC_EDEVICE, PIC_ENUMERIC, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PIC_FP64, PIC_FP32R = 0, 1
 PIC_PHI, PIC_E, PIC_RHO, PIC_RHO_FIXED, PIC_N, PIC_FLUX = 1, 2, 4, 8, 16, 32
+PIC_FINE_N, PIC_FINE_FLUX = 64, 128
+PIC_MAX_FINE_NODES = 1 << 26
 
 SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destroy",
            "pic_last_error", "pic_get_state", "pic_set_state", "pic_get_counters", "pic_derived",
            "pic_profile_enable", "pic_profile_read", "pic_get_tuning", "pic_set_tuning",
-           "pic_autotune", "pic_average", "pic_average_read")
+           "pic_autotune", "pic_average", "pic_average_read", "pic_set_fine_grid")
 PIC_MAX_PHASE_BINS = 64
 PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT, PIC_PROF_LISTS = 0, 1, 2, 3
 
@@ -72,6 +74,11 @@ class pic_counters(C.Structure):
     ]
 
 
+class pic_fine_grid(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("h", C.c_double), ("cells", C.c_int32 * 3),
+                ("reserved", C.c_int32)]
+
+
 class pic_tuning(C.Structure):
     _fields_ = [("sort_interval", C.c_int32), ("ion_sort_interval", C.c_int32),
                 ("tile_margin", C.c_int32), ("ion_tile_margin", C.c_int32),
@@ -113,10 +120,11 @@ def lib():
         L.pic_average.argtypes = [P, C.c_int, C.c_int]
         L.pic_average_read.argtypes = [P, C.c_int, C.c_int, C.c_uint, C.POINTER(P), C.c_int,
                                        C.POINTER(C.c_int64)]
+        L.pic_set_fine_grid.argtypes = [P, C.c_int, C.POINTER(pic_fine_grid)]
         for name in ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_get_state",
                      "pic_set_state", "pic_get_counters", "pic_derived", "pic_profile_enable",
                      "pic_profile_read", "pic_get_tuning", "pic_set_tuning", "pic_autotune",
-                     "pic_average", "pic_average_read"):
+                     "pic_average", "pic_average_read", "pic_set_fine_grid"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -204,6 +212,19 @@ def pic_average_read(ctx, replica, bin, what, outs, out_on_device=False):
     _check(lib().pic_average_read(ctx, replica, bin, what, ptrs, 1 if out_on_device else 0,
                                   C.byref(n)), ctx)
     return int(n.value)
+
+
+def pic_set_fine_grid(ctx, replica, origin=None, h=None, cells=None):
+    """Sets the fine diagnostic grid of a replica (origin None removes it)."""
+    if origin is None:
+        _check(lib().pic_set_fine_grid(ctx, replica, None), ctx)
+        return
+    g = pic_fine_grid()
+    for a in range(3):
+        g.origin[a] = float(origin[a])
+        g.cells[a] = int(cells[a])
+    g.h = float(h)
+    _check(lib().pic_set_fine_grid(ctx, replica, C.byref(g)), ctx)
 
 
 def pic_destroy(ctx):
@@ -333,18 +354,22 @@ class Simulation:
         self.n_nodes = [w["nx"] * w["ny"] * (w["nz"] + 1) for w in self.wls]
         self.n_grains = [m[1].shape[0] for m in made]
         self.capacity = [w["nx"] * w["ny"] * w["nz"] * w["ppc"] for w in self.wls]
+        self.fine_nodes = [0] * len(self.wls)
 
     def step(self, n=1):
         pic_step(self.ctx, n)
 
     def fields(self, replica=0, what=PIC_PHI | PIC_E | PIC_RHO):
         nn = self.n_nodes[replica]
+        fn = self.fine_nodes[replica]
         outs, names = [], []
         for bit, name, shape, dt in ((PIC_PHI, "phi", (nn,), np.float64), (PIC_E, "E", (3, nn), np.float64),
                                      (PIC_RHO, "rho", (nn,), np.float64),
                                      (PIC_RHO_FIXED, "rho_fixed", (nn,), np.int64),
                                      (PIC_N, "n", (2, nn), np.float64),
-                                     (PIC_FLUX, "flux", (2, 3, nn), np.float64)):
+                                     (PIC_FLUX, "flux", (2, 3, nn), np.float64),
+                                     (PIC_FINE_N, "fine_n", (2, fn), np.float64),
+                                     (PIC_FINE_FLUX, "fine_flux", (2, 3, fn), np.float64)):
             if what & bit:
                 outs.append(np.zeros(shape, dt))
                 names.append(name)
@@ -355,11 +380,19 @@ class Simulation:
         """Start (interval > 0) or stop (0) sampling the time averages."""
         pic_average(self.ctx, interval, phase_bins)
 
+    def set_fine_grid(self, origin=None, h=None, cells=None, replica=0):
+        """Sets (or, with origin None, removes) the replica's fine diagnostic
+        grid: lower corner and cell edge in grid units, cells per axis."""
+        pic_set_fine_grid(self.ctx, replica, origin, h, cells)
+        self.fine_nodes[replica] = 0 if origin is None else int(np.prod([int(c) + 1 for c in cells]))
+
     def averages(self, replica=0, bin=-1, what=PIC_PHI | PIC_N | PIC_FLUX):
         nn = self.n_nodes[replica]
+        fn = self.fine_nodes[replica]
         outs, names = [], []
         for bit, name, shape in ((PIC_PHI, "phi", (nn,)), (PIC_N, "n", (2, nn)),
-                                 (PIC_FLUX, "flux", (2, 3, nn))):
+                                 (PIC_FLUX, "flux", (2, 3, nn)), (PIC_FINE_N, "fine_n", (2, fn)),
+                                 (PIC_FINE_FLUX, "fine_flux", (2, 3, fn))):
             if what & bit:
                 outs.append(np.zeros(shape))
                 names.append(name)

@@ -40,7 +40,8 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_1801_00972_amd import pic
     src = tmp_path / "layout.c"
     structs = {"pic_config": pic.pic_config, "pic_state_view": pic.pic_state_view,
-               "pic_counters": pic.pic_counters, "pic_tuning": pic.pic_tuning}
+               "pic_counters": pic.pic_counters, "pic_tuning": pic.pic_tuning,
+               "pic_fine_grid": pic.pic_fine_grid}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic.h"', "int main(void){"]
     for sname, cls in structs.items():
         lines.append(f'printf("{sname} size %zu\\n", sizeof({sname}));')

@@ -1,5 +1,5 @@
 """Time- and rf-phase-averaged diagnostics (pic_average, pic_average_read)
-through the C ABI, against the oracle.
+through the C ABI, against the oracle, with and without the fine grid.
 
 The GPU samples phi_k and the particle moments inside pic_step (in the
 captured step graph, in direct launches, and in the batched step of an
@@ -36,21 +36,32 @@ def _wls(form):
     return [base, other]
 
 
-@pytest.mark.parametrize("form,graphs,interval,bins", [
-    ("fp64", 1, 2, 3), ("fp32r", 1, 3, 4), ("fp32r", 0, 1, 2), ("batched", 1, 2, 3)])
-def test_averages_match_oracle(form, graphs, interval, bins):
-    from paper_1801_00972_amd.pic import Simulation
+# fine grids of the replicas (origin, h, cells): 0.08-cell cells around the
+# small box's grain, and half cells over the second replica's grain
+FINE = [((7.0, 7.0, 15.0), 0.08, (25, 25, 25)), ((0.0, 8.0, 7.0), 0.5, (8, 4, 5))]
+
+
+@pytest.mark.parametrize("form,graphs,interval,bins,fine", [
+    ("fp64", 1, 2, 3, 0), ("fp32r", 1, 3, 4, 1), ("fp32r", 0, 1, 2, 0), ("fp64", 0, 1, 2, 1),
+    ("batched", 1, 2, 3, 1)])
+def test_averages_match_oracle(form, graphs, interval, bins, fine):
+    from paper_1801_00972_amd.pic import PIC_FINE_FLUX, PIC_FINE_N, PIC_FLUX, PIC_N, PIC_PHI, Simulation
     wls = _wls(form)
     prec = wls[0]["precision"]
-    print(f"[case] {form} graphs={graphs} interval={interval} bins={bins}", flush=True)
+    print(f"[case] {form} graphs={graphs} interval={interval} bins={bins} fine={fine}", flush=True)
     sim = Simulation(wls if form == "batched" else wls[0])
     sim.set_tuning(use_graphs=graphs)
     if form == "batched":
         assert sim.tuning()["batch_push"] == 1
+    R = len(wls)
+    if fine:
+        for r in range(R):
+            sim.set_fine_grid(*FINE[r], replica=r)
+    what = PIC_PHI | PIC_N | PIC_FLUX | ((PIC_FINE_N | PIC_FINE_FLUX) if fine else 0)
     sim.step(2)
     sim.average(interval, bins)
-    R = len(wls)
-    acc = [[dict(phi=0.0, n=0.0, flux=0.0, count=0, V=0.0) for _ in range(bins)] for _ in range(R)]
+    acc = [[dict(phi=0.0, n=0.0, flux=0.0, fine_n=0.0, fine_flux=0.0, count=0, V=0.0)
+            for _ in range(bins)] for _ in range(R)]
     for s in range(13):
         if s % interval == 0:
             for r in range(R):
@@ -62,16 +73,20 @@ def test_averages_match_oracle(form, graphs, interval, bins):
                 a["phi"] = a["phi"] + f["phi"]
                 a["n"] = a["n"] + n
                 a["flux"] = a["flux"] + flux
+                if fine:
+                    fn_, ff_ = orc.fine_moments(*FINE[r])
+                    a["fine_n"] = a["fine_n"] + fn_
+                    a["fine_flux"] = a["fine_flux"] + ff_
                 a["count"] += 1
                 a["V"] = max(a["V"], abs(orc.rf_voltage(st["step"])))
         sim.step(1)
     for r in range(R):
-        total = dict(phi=0.0, n=0.0, flux=0.0, count=0, V=0.0)
+        total = dict(phi=0.0, n=0.0, flux=0.0, fine_n=0.0, fine_flux=0.0, count=0, V=0.0)
         for b in range(bins):
             a = acc[r][b]
-            g = sim.averages(r, b)
+            g = sim.averages(r, b, what=what)
             assert g["samples"] == a["count"]
-            for k in ("phi", "n", "flux"):
+            for k in ("phi", "n", "flux", "fine_n", "fine_flux"):
                 total[k] = total[k] + a[k]
             total["count"] += a["count"]
             total["V"] = max(total["V"], a["V"])
@@ -84,10 +99,18 @@ def test_averages_match_oracle(form, graphs, interval, bins):
             print(f"  replica {r} bin {b}: {a['count']} samples, phi {e_phi:.2e} n {e_n:.2e} "
                   f"flux {e_f:.2e}", flush=True)
             assert e_phi <= FIELD_TOL[prec] and e_n <= 1e-12 and e_f <= 1e-12
-        g = sim.averages(r, -1)
+            if fine:
+                e_fn = rel_inf(g["fine_n"], a["fine_n"] / a["count"])
+                e_ff = rel_inf(g["fine_flux"], a["fine_flux"] / a["count"])
+                print(f"    fine grid: n {e_fn:.2e} flux {e_ff:.2e}", flush=True)
+                assert np.any(a["fine_n"]) and e_fn <= 1e-12 and e_ff <= 1e-12
+        g = sim.averages(r, -1, what=what)
         assert g["samples"] == total["count"] == len(range(0, 13, interval))
         assert rel_inf(g["n"], total["n"] / total["count"]) <= 1e-12
         assert rel_inf(g["phi"], total["phi"] / total["count"], floor=total["V"]) <= FIELD_TOL[prec]
+        if fine:
+            assert rel_inf(g["fine_n"], total["fine_n"] / total["count"]) <= 1e-12
+            assert rel_inf(g["fine_flux"], total["fine_flux"] / total["count"]) <= 1e-12
     # stopped: the sums stay as they are
     sim.average(0)
     sim.step(3)

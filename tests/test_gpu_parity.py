@@ -194,6 +194,75 @@ def test_density_and_flux_moments(prec, rebin):
     sim.close()
 
 
+def _inside(pos, origin, h, cells):
+    u = (pos - np.asarray(origin)) / h
+    return np.all((u >= 0.0) & (u < np.asarray(cells, np.float64)), axis=1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32r"])
+@pytest.mark.parametrize("box", ["grain", "ragged", "unit"])
+def test_fine_grid_moments(prec, box):
+    """Densities and fluxes on the fine diagnostic grid (pic_fields
+    PIC_FINE_N | PIC_FINE_FLUX) against the oracle's fine moments of the same
+    state: 0.08-cell cells around the grain, a ragged box of half cells that
+    spans x and touches both electrodes, and unit cells off the PIC nodes;
+    particles drift out of their tiles (no re-binning).  The number of
+    particles inside the box is exact."""
+    from paper_1801_00972_amd.pic import PIC_FINE_FLUX, PIC_FINE_N
+    origin, h, cells = {"grain": ((7.0, 7.0, 15.0), 0.08, (25, 25, 25)),
+                        "ragged": ((0.0, 3.25, 0.0), 0.5, (32, 17, 64)),
+                        "unit": ((2.5, 3.25, 4.75), 1.0, (10, 9, 20))}[box]
+    print(f"[case] {prec} fine grid {box}: origin {origin} h {h} cells {cells}", flush=True)
+    wl = dict(W.small_fp64(), precision=prec)
+    sim = _sim(wl)
+    sim.set_tuning(sort_interval=0, ion_sort_interval=0)
+    sim.set_fine_grid(origin, h, cells)
+    w, vol = sim.derived()["w"], (h * wl["dx"]) ** 3
+    for seg in range(2):
+        sim.step(3)
+        st = sim.get_state()
+        n, flux = oracle_from_state(wl, st).fine_moments(origin, h, cells)
+        g = sim.fields(0, PIC_FINE_N | PIC_FINE_FLUX)
+        e_n, e_f = rel_inf(g["fine_n"], n), rel_inf(g["fine_flux"], flux)
+        inside = [int(_inside(st[s]["pos"], origin, h, cells).sum()) for s in range(2)]
+        print(f"  step {st['step']}: {inside} particles inside, n {e_n:.2e} flux {e_f:.2e}", flush=True)
+        assert min(inside) > 0
+        assert e_n <= 1e-12 and e_f <= 1e-12
+        for s in range(2):
+            assert g["fine_n"][s].sum() * vol / w == pytest.approx(inside[s], rel=1e-12)
+    sim.close()
+
+
+def test_fine_grid_arguments_are_checked():
+    from paper_1801_00972_amd.pic import PIC_FINE_N, PIC_N, PicError
+    wl = W.small_fp32r()
+    sim = _sim(wl)
+    with pytest.raises(PicError):
+        sim.fields(0, PIC_FINE_N)  # no fine grid
+    for origin, h, cells in (((0, 0, 0), 0.0, (4, 4, 4)), ((0, 0, 0), -1.0, (4, 4, 4)),
+                             ((0, 0, 0), 0.5, (0, 4, 4)), ((-0.1, 0, 0), 0.5, (4, 4, 4)),
+                             ((12.0, 0, 0), 0.5, (9, 4, 4)), ((0, 0, 30.0), 1.0, (1, 1, 3)),
+                             ((0, 0, 0), float("nan"), (4, 4, 4)),
+                             ((0, 0, 0), 1e-3, (1000, 1000, 1000))):
+        with pytest.raises(PicError):
+            sim.set_fine_grid(origin, h, cells)
+    sim.set_fine_grid((0, 0, 0), 0.5, (32, 32, 64))  # the whole domain
+    sim.average(1, 2)
+    with pytest.raises(PicError):
+        sim.set_fine_grid((1, 1, 1), 0.5, (4, 4, 4))  # averaging is running
+    sim.step(2)
+    assert sim.averages(0, -1, what=PIC_FINE_N)["samples"] == 2
+    sim.average(0)
+    sim.set_fine_grid((1, 1, 1), 0.5, (4, 4, 4))
+    with pytest.raises(PicError):
+        sim.averages(0, -1, what=PIC_FINE_N)  # the sums were of the old box
+    assert sim.averages(0, -1, what=PIC_N)["samples"] == 2
+    sim.set_fine_grid(None)
+    with pytest.raises(PicError):
+        sim.fields(0, PIC_FINE_N)
+    sim.close()
+
+
 def test_fixed_point_total_charge_is_exact():
     wl = W.small_fp32r()
     sim = _sim(wl)
