@@ -40,14 +40,14 @@ class _Config(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("ppc_e", C.c_int32), ("ppc_i", C.c_int32), ("n_grains", C.c_int32),
         ("cutoff", C.c_int32), ("md_sub", C.c_int32), ("flags", C.c_int32),
-        ("pad0", C.c_int32),
+        ("coulomb_interval", C.c_int32),
         ("dx", C.c_double), ("dt", C.c_double), ("n0", C.c_double),
         ("Te_eV", C.c_double), ("Ti_eV", C.c_double),
         ("p_gas", C.c_double), ("T_gas", C.c_double),
         ("sigma_e", C.c_double), ("sigma_i", C.c_double),
         ("V_dc", C.c_double), ("V_rf", C.c_double), ("f_rf", C.c_double),
         ("grain_radius", C.c_double), ("E_cap_eV", C.c_double),
-        ("Q_frozen_e", C.c_double),
+        ("Q_frozen_e", C.c_double), ("coulomb_lnL", C.c_double),
         ("seed", C.c_uint64),
         ("grain_pos", C.POINTER(C.c_double)),
     ]
@@ -99,6 +99,14 @@ def lib():
         L.orc_deposit_fixed.argtypes = [C.POINTER(_Config), C.POINTER(_State),
                                         C.POINTER(C.c_int64)]
         L.orc_moments.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp, dp]
+        L.orc_coulomb.argtypes = [C.POINTER(_Config), C.POINTER(_State)]
+        L.orc_coulomb.restype = C.c_int64
+        L.orc_coulomb_pair.argtypes = [C.POINTER(_Config), C.c_int, C.c_int, dp, dp, C.c_double,
+                                       C.c_double]
+        L.orc_coulomb_pair.restype = None
+        L.orc_coulomb_var.argtypes = [C.POINTER(_Config), C.c_int, C.c_int, C.c_double, C.c_double,
+                                      C.c_double]
+        L.orc_coulomb_var.restype = C.c_double
         L.orc_fine_moments.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp, C.c_double,
                                        C.POINTER(C.c_int32), dp, dp]
         L.orc_poisson.argtypes = [C.POINTER(_Config), dp, C.c_double, dp]
@@ -139,6 +147,8 @@ class Oracle:
                   "sigma_i", "V_dc", "V_rf", "f_rf", "grain_radius", "E_cap_eV"):
             setattr(cfg, k, float(wl[k]))
         cfg.Q_frozen_e = float(Q_frozen_e)
+        cfg.coulomb_interval = int(wl.get("coulomb_interval", 0))
+        cfg.coulomb_lnL = float(wl.get("coulomb_lnL", 10.0))
         cfg.seed = int(wl.get("seed", 0))
         cfg.grain_pos = _ptr(self.grain_pos, C.c_double)
         self.cfg = cfg
@@ -348,6 +358,26 @@ class Oracle:
         if self._U is None:
             self._U = np.ascontiguousarray(self.unit_fields(progress))
         return self._U
+
+    def coulomb(self) -> int:
+        """One pass of the Coulomb collisions (Table I, binary model of
+        Takizuka and Abe) at the current step; returns the collision count."""
+        rc = lib().orc_coulomb(C.byref(self.cfg), C.byref(self.st))
+        if rc < 0:
+            raise RuntimeError(f"orc_coulomb failed ({rc})")
+        return int(rc)
+
+    def coulomb_pair(self, sa: int, sb: int, va, vb, delta: float, phi: float):
+        """One binary collision with given delta = tan(theta/2) and azimuth."""
+        a = np.array(va, np.float64)
+        b = np.array(vb, np.float64)
+        lib().orc_coulomb_pair(C.byref(self.cfg), sa, sb, _ptr(a, C.c_double), _ptr(b, C.c_double),
+                               float(delta), float(phi))
+        return a, b
+
+    def coulomb_var(self, sa: int, sb: int, u: float, nL: float, dtc: float) -> float:
+        return float(lib().orc_coulomb_var(C.byref(self.cfg), sa, sb, float(u), float(nL),
+                                           float(dtc)))
 
     def step(self, n: int = 1):
         U = self._units()

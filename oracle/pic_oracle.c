@@ -24,7 +24,8 @@
 #define O_PI      3.14159265358979323846
 
 /* Philox counter word 2: what a draw is for */
-enum { PUR_INIT_POS = 1, PUR_INIT_VEL = 2, PUR_COLL = 3, PUR_NEUTRAL = 4 };
+enum { PUR_INIT_POS = 1, PUR_INIT_VEL = 2, PUR_COLL = 3, PUR_NEUTRAL = 4, PUR_CORDER = 5,
+       PUR_CPAIR = 6 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32  */
@@ -737,6 +738,172 @@ static void collide(const orc_config* c, const orc_derived* d, int sp, uint32_t 
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Coulomb collisions (Table I: e-e, e-Ar+, Ar+-Ar+), the binary model of      */
+/* Takizuka and Abe cited with the collision set: the particles of a cell are  */
+/* paired at random; each pair's relative velocity u turns by an angle theta   */
+/* with delta = tan(theta/2) normal of variance                                */
+/*   q_a^2 q_b^2 n_L lnL dtc / (8 pi eps0^2 mu^2 |u|^3)                        */
+/* (mu the reduced mass, n_L the density of the less numerous species of the   */
+/* pair, the species' own density for like particles) and a uniform azimuth   */
+/* phi about u; both velocities change so that momentum and energy are kept.  */
+/* ------------------------------------------------------------------------ */
+double orc_coulomb_var(const orc_config* c, int sa, int sb, double u, double nL, double dtc)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return NAN;
+  double mu = d.m[sa] * d.m[sb] / (d.m[sa] + d.m[sb]);
+  double qq = d.q[sa] * d.q[sb];
+  return qq * qq * nL * c->coulomb_lnL * dtc / (8.0 * O_PI * O_EPS0 * O_EPS0 * mu * mu * u * u * u);
+}
+
+void orc_coulomb_pair(const orc_config* c, int sa, int sb, double* va, double* vb, double delta,
+                      double phi)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return;
+  double u[3] = {va[0] - vb[0], va[1] - vb[1], va[2] - vb[2]};
+  double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  double up = sqrt(u[0] * u[0] + u[1] * u[1]);
+  double sn = 2.0 * delta / (1.0 + delta * delta);        /* sin theta */
+  double omc = 2.0 * delta * delta / (1.0 + delta * delta); /* 1 - cos theta */
+  double cp = cos(phi), sp = sin(phi);
+  double du[3];
+  if (up > 0.0) {
+    du[0] = (u[0] / up) * u[2] * sn * cp - (u[1] / up) * um * sn * sp - u[0] * omc;
+    du[1] = (u[1] / up) * u[2] * sn * cp + (u[0] / up) * um * sn * sp - u[1] * omc;
+    du[2] = -up * sn * cp - u[2] * omc;
+  } else {
+    /* u along z: the same rotation with the azimuth measured from x */
+    du[0] = um * sn * cp;
+    du[1] = um * sn * sp;
+    du[2] = -u[2] * omc;
+  }
+  double mu = d.m[sa] * d.m[sb] / (d.m[sa] + d.m[sb]);
+  for (int a = 0; a < 3; ++a) {
+    va[a] += (mu / d.m[sa]) * du[a];
+    vb[a] -= (mu / d.m[sb]) * du[a];
+  }
+}
+
+/* one collision of the pass: draws from Philox(id of the pair's first      */
+/* particle, k, PUR_CPAIR, kind), kind 0 e-e, 1 Ar+-Ar+, 2 + a for unlike    */
+/* pairs whose more numerous species is a; delta from the Box-Muller cosine */
+/* branch of words 0 and 1, phi = 2 pi u(word 2)                            */
+static void coulomb_one(const orc_config* c, int sa, int sb, double* va, double* vb, double nL,
+                        double dtc, uint32_t id, uint32_t k, uint32_t kind)
+{
+  double u[3] = {va[0] - vb[0], va[1] - vb[1], va[2] - vb[2]};
+  double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  if (!(um > 0.0)) return;
+  uint32_t r[4];
+  draw(c, id, k, PUR_CPAIR, kind, r);
+  double n0, n1;
+  box_muller(r[0], r[1], &n0, &n1);
+  double delta = sqrt(orc_coulomb_var(c, sa, sb, um, nL, dtc)) * n0;
+  orc_coulomb_pair(c, sa, sb, va, vb, delta, 2.0 * O_PI * unif_open(r[2]));
+}
+
+typedef struct {
+  int64_t cell;
+  uint64_t key; /* Philox(id, k, PUR_CORDER, species) word 0, then id */
+  int64_t p;
+} ckey;
+
+static int cmp_ckey(const void* a, const void* b)
+{
+  const ckey* x = (const ckey*)a;
+  const ckey* y = (const ckey*)b;
+  if (x->cell != y->cell) return x->cell < y->cell ? -1 : 1;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return 0;
+}
+
+/* Pairing in a cell.  Each species' particles are put in the order of their */
+/* keys.  Like particles: consecutive pairs (p0,p1), (p2,p3), ...; an odd     */
+/* count of three or more starts with the triplet (p0,p1), (p1,p2), (p2,p0),  */
+/* each at half the time step.  Unlike particles: with N_a >= N_b (electrons  */
+/* on a tie) particle j of a collides with particle j mod N_b of b, in order  */
+/* of j, at density n_L = N_b w / dx^3.  Order: e-e, Ar+-Ar+, then e-Ar+.    */
+int64_t orc_coulomb(const orc_config* c, orc_state* s)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return -1;
+  if (c->coulomb_interval <= 0) return 0;
+  const uint32_t k = s->step;
+  const double dtc = c->coulomb_interval * c->dt;
+  const double vol = c->dx * c->dx * c->dx;
+  ckey* L[2] = {NULL, NULL};
+  int64_t n[2] = {0, 0};
+  for (int sp = 0; sp < 2; ++sp) {
+    L[sp] = (ckey*)malloc(sizeof(ckey) * (size_t)(s->n[sp] > 0 ? s->n[sp] : 1));
+    if (!L[sp]) {
+      free(L[0]);
+      return -2;
+    }
+    for (int64_t p = 0; p < s->n[sp]; ++p) {
+      if (!s->alive[sp][p]) continue;
+      const double* x = &s->pos[sp][3 * p];
+      int64_t i = (int64_t)floor(x[0]), j = (int64_t)floor(x[1]), kk = (int64_t)floor(x[2]);
+      uint32_t r[4];
+      draw(c, s->id[sp][p], k, PUR_CORDER, (uint32_t)sp, r);
+      ckey e = {(kk * c->ny + j) * c->nx + i, ((uint64_t)r[0] << 32) | s->id[sp][p], p};
+      L[sp][n[sp]++] = e;
+    }
+    qsort(L[sp], (size_t)n[sp], sizeof(ckey), cmp_ckey);
+  }
+  int64_t ncoll = 0;
+  int64_t a0[2] = {0, 0};
+  while (a0[0] < n[0] || a0[1] < n[1]) {
+    /* the next cell holding a particle of either species */
+    int64_t cell = INT64_MAX;
+    for (int sp = 0; sp < 2; ++sp)
+      if (a0[sp] < n[sp] && L[sp][a0[sp]].cell < cell) cell = L[sp][a0[sp]].cell;
+    int64_t a1[2];
+    for (int sp = 0; sp < 2; ++sp) {
+      a1[sp] = a0[sp];
+      while (a1[sp] < n[sp] && L[sp][a1[sp]].cell == cell) ++a1[sp];
+    }
+#define VEL(sp, q) (&s->vel[sp][3 * L[sp][q].p])
+#define PID(sp, q) (s->id[sp][L[sp][q].p])
+    for (int sp = 0; sp < 2; ++sp) {
+      int64_t N = a1[sp] - a0[sp], b = a0[sp];
+      if (N < 2) continue;
+      double ns = (double)N * d.w / vol;
+      int64_t q = b;
+      if (N % 2 == 1) {
+        coulomb_one(c, sp, sp, VEL(sp, b), VEL(sp, b + 1), ns, 0.5 * dtc, PID(sp, b), k, sp);
+        coulomb_one(c, sp, sp, VEL(sp, b + 1), VEL(sp, b + 2), ns, 0.5 * dtc, PID(sp, b + 1), k, sp);
+        coulomb_one(c, sp, sp, VEL(sp, b + 2), VEL(sp, b), ns, 0.5 * dtc, PID(sp, b + 2), k, sp);
+        ncoll += 3;
+        q = b + 3;
+      }
+      for (; q + 1 < a1[sp]; q += 2) {
+        coulomb_one(c, sp, sp, VEL(sp, q), VEL(sp, q + 1), ns, dtc, PID(sp, q), k, sp);
+        ncoll += 1;
+      }
+    }
+    int64_t Ne = a1[0] - a0[0], Ni = a1[1] - a0[1];
+    if (Ne > 0 && Ni > 0) {
+      int sa = Ne >= Ni ? 0 : 1, sb = 1 - sa;
+      int64_t Na = sa == 0 ? Ne : Ni, Nb = sa == 0 ? Ni : Ne;
+      double nL = (double)Nb * d.w / vol;
+      for (int64_t j = 0; j < Na; ++j) {
+        coulomb_one(c, sa, sb, VEL(sa, a0[sa] + j), VEL(sb, a0[sb] + j % Nb), nL, dtc,
+                    PID(sa, a0[sa] + j), k, 2 + (uint32_t)sa);
+        ncoll += 1;
+      }
+    }
+#undef VEL
+#undef PID
+    a0[0] = a1[0];
+    a0[1] = a1[1];
+  }
+  free(L[0]);
+  free(L[1]);
+  return ncoll;
+}
+
 static int move_all(const orc_config* c, orc_state* s, const double* E, const double* U)
 {
   orc_derived d;
@@ -747,6 +914,9 @@ static int move_all(const orc_config* c, orc_state* s, const double* E, const do
   const double* Uuse = (c->flags & ORC_NO_MESH) ? NULL : U;
   const double* Euse = (c->flags & ORC_NO_MESH) ? NULL : E;
   uint32_t k = s->step;
+  /* Coulomb collisions on (x_k, v_{k-1/2}) at the start of every interval-th step */
+  if (c->coulomb_interval > 0 && k % (uint32_t)c->coulomb_interval == 0 && orc_coulomb(c, s) < 0)
+    return -6;
   for (int sp = 0; sp < 2; ++sp) {
     double qm = d.q[sp] / d.m[sp];
     int64_t wall[2] = {0, 0};

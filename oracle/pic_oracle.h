@@ -46,7 +46,7 @@ typedef struct orc_config {
   int32_t cutoff;            /* MD cube half-width c, in cells */
   int32_t md_sub;            /* sub-steps per step in the MD region (40) */
   int32_t flags;             /* ORC_* test modes */
-  int32_t pad0;
+  int32_t coulomb_interval;  /* Coulomb collisions every this many steps (0: none) */
   double dx, dt;             /* m, s */
   double n0;                 /* plasma density setting the macro-particle weight */
   double Te_eV, Ti_eV;       /* load temperatures, kT in eV */
@@ -56,6 +56,7 @@ typedef struct orc_config {
   double grain_radius;       /* m */
   double E_cap_eV;           /* null-collision cap on the relative kinetic energy */
   double Q_frozen_e;         /* grain charge in e when ORC_FROZEN_Q is set */
+  double coulomb_lnL;        /* Coulomb logarithm of the charged-particle collisions */
   uint64_t seed;             /* Philox key */
   const double* grain_pos;   /* [n_grains][3], cell units */
 } orc_config;
@@ -104,6 +105,20 @@ int orc_deposit_fixed(const orc_config* c, const orc_state* s, int64_t* rho_fixe
 int orc_moments(const orc_config* c, const orc_state* s, double* n, double* flux);
 int orc_fine_moments(const orc_config* c, const orc_state* s, const double origin[3], double h,
                      const int32_t m[3], double* n, double* flux);
+
+/* Coulomb collisions of the charged particles (Table I; binary model of
+ * Takizuka and Abe): one pass over all cells at the state's step k, with
+ * time step coulomb_interval * dt.  orc_step applies it at the start of
+ * every step k with k % coulomb_interval == 0.  Returns the number of
+ * binary collisions performed (>= 0) or a negative error. */
+int64_t orc_coulomb(const orc_config* c, orc_state* s);
+/* one binary collision of the model on the velocities va (species sa) and vb
+ * (species sb) with the given rotation draws: delta = tan(theta/2), phi */
+void orc_coulomb_pair(const orc_config* c, int sa, int sb, double* va, double* vb, double delta,
+                      double phi);
+/* the variance of delta = tan(theta/2) for relative speed u, density nL of
+ * the partner species and time step dtc */
+double orc_coulomb_var(const orc_config* c, int sa, int sb, double u, double nL, double dtc);
 
 /* Poisson: phi on all nodes, Dirichlet phi(k=0)=0, phi(k=nz)=V */
 int orc_poisson(const orc_config* c, const double* rho, double V, double* phi);
