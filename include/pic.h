@@ -74,7 +74,23 @@ extern "C" {
  *   neighbours, Sec. III);  md_subcycles sub-steps of dt / md_subcycles are taken
  *   inside it (40 in the paper);
  *   E_cap_eV caps the relative kinetic energy used by the null-collision
- *   method (a particle above the cap collides and is counted).
+ *   method (a particle above the cap collides and is counted);
+ *   coulomb_interval > 0 switches on the Coulomb collisions between the
+ *   charged particles (Table I: e-e, e-Ar+, Ar+-Ar+; the binary model of
+ *   Takizuka and Abe cited there): at the start of every step k with
+ *   k % coulomb_interval == 0 the particles of each cell are paired at random
+ *   and each pair's relative velocity turns by a random angle theta about
+ *   itself, delta = tan(theta/2) normal with variance
+ *   q_a^2 q_b^2 n_L coulomb_lnL dt_c / (8 pi eps0^2 mu^2 |u|^3), dt_c =
+ *   coulomb_interval dt, n_L the density of the less numerous species of
+ *   the pair (the species' own for like particles), mu the reduced mass;
+ *   momentum and energy are kept.  The pairing: each species' particles in
+ *   the order of their Philox keys; like particles in consecutive pairs, an
+ *   odd count of three or more starting with a triplet (three collisions at
+ *   dt_c / 2); unlike particles j of the more numerous species (electrons on
+ *   a tie) with particle j mod N_b of the other, in order of j; e-e, then
+ *   Ar+-Ar+, then e-Ar+.  With Coulomb collisions on, steps are launched
+ *   directly (no graph replay).
  */
 typedef struct pic_config {
   int32_t nx, ny, nz;
@@ -96,6 +112,9 @@ typedef struct pic_config {
   double refine_tol;           /* FP32R: target ||b - A phi|| / ||b|| (diagnostic) */
   uint64_t seed;               /* Philox key of the replica */
   const double* grain_pos;     /* host pointer, [n_grains][3], cell units */
+  int32_t coulomb_interval;    /* steps between Coulomb-collision passes (0: none) */
+  int32_t reserved0;           /* 0 */
+  double coulomb_lnL;          /* Coulomb logarithm (> 0 when coulomb_interval > 0) */
 } pic_config;
 
 typedef struct pic_ctx pic_ctx;
@@ -124,6 +143,7 @@ typedef struct pic_counters {
   double refine_residual;     /* FP32R: ||b - A phi|| / ||b|| after the last solve */
   int64_t numeric_bad;        /* particles removed for a non-finite position (0 for valid input) */
   int64_t tile_fallback;      /* particle-steps outside their tile's LDS window (global-memory path) */
+  int64_t n_coulomb;          /* binary Coulomb collisions (pairings) performed */
 } pic_counters;
 
 /*

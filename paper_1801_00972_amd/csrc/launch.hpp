@@ -66,6 +66,37 @@ void launch_moments(const PartF64* P64, const PartF32R* P32, const SpeciesStep& 
 void launch_fine_moments(const PartF64* P64, const PartF32R* P32, const WorkLists& L,
                          const FineBox& fb, double* mom, const AvgBins& avg, long capacity,
                          hipStream_t st);
+// Coulomb collisions (coulomb.hip).  Work buffers of a replica: per species
+// the per-cell counts turned into range starts [ncell + 1], fill cursors
+// [ncell], the (order key, slot) entries [cap] and the slots in key order
+// [cap]; the scan's block sums [coulomb_scan_sums(ncell)]; the pairings
+// performed (accumulated).
+struct CoulombBufs {
+  int* start[2];
+  int* fill[2];
+  unsigned long long* key[2];
+  int* slot[2];
+  int* ord[2];
+  int* sums;
+  unsigned long long* count;
+};
+// constants of a pass: pair kinds 0 e-e, 1 Ar+-Ar+, 2 e-Ar+; the variance of
+// delta is c_var[kind] n_L / |u|^3 with n_L = (particles) w_vol; species s of
+// a pair changes by +- frac[kind][s] du
+struct CoulombConst {
+  int nx, ny, ncell;
+  uint32_t key0, key1;
+  const uint32_t* step;
+  double w_vol;
+  double c_var[3];
+  double frac[3][2];
+};
+long coulomb_scan_sums(long ncell);
+// one pass over both species of a replica; exactly one of P64, P32 is non-null
+// (each then points to the two species' arrays); cap bounds the slots in use
+void launch_coulomb(const PartF64* P64, const PartF32R* P32, const WorkLists L[2],
+                    const CoulombBufs& B, const CoulombConst& C, const long cap[2],
+                    hipStream_t st);
 // time averages: phi added to its rf-phase bin (avg.stride apart), and one
 // sample counted in cnt[bin]
 void launch_avg_phi(const double* phi, double* acc, long nn, const AvgBins& avg,

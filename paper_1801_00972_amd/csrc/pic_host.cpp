@@ -83,6 +83,8 @@ struct Replica {
   double* fine_avg = nullptr;
   int fine_cap = 0;
   double* fine_out = nullptr;
+  // Coulomb collisions (cfg.coulomb_interval > 0): work buffers of a pass
+  CoulombBufs coul{};
   // near-grain tables
   MdTables md{};
   double* d_Q = nullptr;
@@ -124,6 +126,8 @@ struct pic_ctx {
   // time averages: a sample every avg_interval steps (0: off) into avg_bins
   // rf-phase bins; since_avg counts the steps since the last sample
   int avg_interval = 0, avg_bins = 0, since_avg = 0;
+  // some replica has Coulomb collisions on
+  bool coulomb = false;
   // batched push: descriptors of every (replica, species) for each phase of
   // the buffers (electron, ion, rho), and the first tile of each descriptor
   bool batchable = false;
@@ -273,6 +277,9 @@ int validate(const pic_config& c, std::string& why) {
   if (c.n_grains > 0 && !c.grain_pos) return bad("grain_pos is NULL");
   if (c.n_grains > 0 && !(c.grain_radius > 0)) return bad("grain_radius must be > 0");
   if (c.sort_interval < 0) return bad("sort_interval must be >= 0");
+  if (c.coulomb_interval < 0) return bad("coulomb_interval must be >= 0");
+  if (c.coulomb_interval > 0 && !(std::isfinite(c.coulomb_lnL) && c.coulomb_lnL > 0))
+    return bad("coulomb_lnL must be > 0");
   return PIC_OK;
 }
 
@@ -595,6 +602,44 @@ int enqueue_fine(pic_ctx* ctx, Replica& R, double* mom, const AvgBins& avg) {
   return PIC_OK;
 }
 
+// Coulomb collisions at the start of step k when k % coulomb_interval == 0
+bool coulomb_due(const Replica& R) {
+  return R.cfg.coulomb_interval > 0 && R.step % (uint32_t)R.cfg.coulomb_interval == 0;
+}
+
+int enqueue_coulomb(pic_ctx* ctx, Replica& R) {
+  const pic_config& c = R.cfg;
+  CoulombConst C{};
+  C.nx = R.nx;
+  C.ny = R.ny;
+  C.ncell = (int)R.ncell;
+  C.key0 = (uint32_t)(c.seed & 0xffffffffu);
+  C.key1 = (uint32_t)(c.seed >> 32);
+  C.step = R.d_step;
+  C.w_vol = R.w / (c.dx * c.dx * c.dx);
+  const double m[2] = {kMassE, kMassAr}, q[2] = {-kCharge, kCharge};
+  const double dtc = (double)c.coulomb_interval * c.dt;
+  const int kinds[3][2] = {{0, 0}, {1, 1}, {0, 1}};
+  for (int t = 0; t < 3; ++t) {
+    const int a = kinds[t][0], b = kinds[t][1];
+    const double mu = m[a] * m[b] / (m[a] + m[b]);
+    const double qq = q[a] * q[b];
+    C.c_var[t] = qq * qq * c.coulomb_lnL * dtc / (8.0 * kPi * kEps0 * kEps0 * mu * mu);
+    C.frac[t][a] = mu / m[a];
+    C.frac[t][b] = mu / m[b];
+  }
+  const WorkLists L[2] = {R.lists[0], R.lists[1]};
+  if (R.prec == PIC_FP64) {
+    const PartF64 P[2] = {R.p64[0][R.cur[0]], R.p64[1][R.cur[1]]};
+    launch_coulomb(P, nullptr, L, R.coul, C, R.cap, ctx->stream);
+  } else {
+    const PartF32R P[2] = {R.p32[0][R.cur[0]], R.p32[1][R.cur[1]]};
+    launch_coulomb(nullptr, P, L, R.coul, C, R.cap, ctx->stream);
+  }
+  CHECK_LAUNCH(ctx);
+  return PIC_OK;
+}
+
 // one sample of the time averages at the start of a step: phi_k and the
 // moments of x_k, v_{k-1/2}, into the rf-phase bin of step k
 int enqueue_sample(pic_ctx* ctx, Replica& R) {
@@ -624,6 +669,7 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   hipEvent_t f0 = prof_event(ctx);
   TRY(solve_fields(ctx, R));
   if (sample) TRY(enqueue_sample(ctx, R));
+  if (coulomb_due(R)) TRY(enqueue_coulomb(ctx, R));
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
   const int rnx = 1 - R.rho_cur;
   const int do_mcc = 1;
@@ -719,6 +765,7 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   TRY(for_replicas(ctx, [&](Replica& R) -> int {
     TRY(solve_fields(ctx, R));
     if (sample) TRY(enqueue_sample(ctx, R));
+    if (coulomb_due(R)) TRY(enqueue_coulomb(ctx, R));
     launch_zero_i64((long long*)R.rho[1 - R.rho_cur], R.nn, ctx->stream);
     return PIC_OK;
   }));
@@ -883,7 +930,8 @@ int step_all(pic_ctx* ctx) {
   // any capture, so host-side capture time is not counted)
   std::vector<hipEvent_t>* ev = ctx->step_ev;
   const bool timed = ev && ctx->step_ev_used + 2 <= ev->size();
-  if (ctx->prof || !ctx->tune.use_graphs || !replicas_aligned(ctx)) {
+  // Coulomb passes fall on some steps only: those contexts launch directly
+  if (ctx->prof || !ctx->tune.use_graphs || ctx->coulomb || !replicas_aligned(ctx)) {
     if (timed) HIPCHK(ctx, hipEventRecord((*ev)[ctx->step_ev_used], ctx->stream));
     TRY(enqueue_all(ctx, sorts, sample));
   } else {
@@ -1053,6 +1101,19 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   TRY(dalloc(ctx, R, &R.d_sums, (nkey + 1023) / 1024 + 1));
   HIPCHK(ctx, hipMemsetAsync(R.d_gc, 0, 16 * std::max(c.n_grains, 1), st));
   HIPCHK(ctx, hipMemsetAsync(R.norms, 0, 16, st));
+  if (c.coulomb_interval > 0) {
+    for (int sp = 0; sp < 2; ++sp) {
+      TRY(dalloc(ctx, R, &R.coul.start[sp], R.ncell + 1));
+      TRY(dalloc(ctx, R, &R.coul.fill[sp], R.ncell));
+      TRY(dalloc(ctx, R, &R.coul.key[sp], R.cap[sp]));
+      TRY(dalloc(ctx, R, &R.coul.slot[sp], R.cap[sp]));
+      TRY(dalloc(ctx, R, &R.coul.ord[sp], R.cap[sp]));
+    }
+    TRY(dalloc(ctx, R, &R.coul.sums, coulomb_scan_sums(R.ncell)));
+    TRY(dalloc(ctx, R, &R.coul.count, 1));
+    launch_zero_i64((long long*)R.coul.count, 1, st);
+    ctx->coulomb = true;
+  }
   TRY(setup_md(ctx, R));
   TRY(unit_fields(ctx, R));
 
@@ -1578,6 +1639,11 @@ int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out) {
   out->step = R->step;
   out->refine_sweeps = R->prec == PIC_FP32R ? R->cfg.max_refine : 0;
   out->refine_residual = norms[1] > 0 ? std::sqrt(norms[0] / norms[1]) : std::sqrt(norms[0]);
+  if (R->coul.count) {
+    unsigned long long nc = 0;
+    HIPCHK(ctx, hipMemcpy(&nc, R->coul.count, sizeof(nc), hipMemcpyDeviceToHost));
+    out->n_coulomb = (int64_t)nc;
+  }
   return PIC_OK;
 }
 

@@ -50,6 +50,7 @@ class pic_config(C.Structure):
         ("grain_radius", C.c_double), ("E_cap_eV", C.c_double), ("refine_tol", C.c_double),
         ("seed", C.c_uint64),
         ("grain_pos", C.POINTER(C.c_double)),
+        ("coulomb_interval", C.c_int32), ("reserved0", C.c_int32), ("coulomb_lnL", C.c_double),
     ]
 
 
@@ -70,7 +71,7 @@ class pic_counters(C.Structure):
         ("cap_violation", C.c_int64 * 2), ("n_collisions", C.c_int64 * 2),
         ("md_particles", C.c_int64 * 2),
         ("step", C.c_uint32), ("refine_sweeps", C.c_int32), ("refine_residual", C.c_double),
-        ("numeric_bad", C.c_int64), ("tile_fallback", C.c_int64),
+        ("numeric_bad", C.c_int64), ("tile_fallback", C.c_int64), ("n_coulomb", C.c_int64),
     ]
 
 
@@ -159,6 +160,8 @@ def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 2):
     c.refine_tol = float(wl.get("refine_tol", 1e-10))
     c.seed = int(wl.get("seed", 0))
     c.grain_pos = g.ctypes.data_as(C.POINTER(C.c_double))
+    c.coulomb_interval = int(wl.get("coulomb_interval", 0))
+    c.coulomb_lnL = float(wl.get("coulomb_lnL", 10.0))
     return c, g
 
 
@@ -291,7 +294,8 @@ def pic_get_counters(ctx, replica):
                 cap_violation=list(c.cap_violation), n_collisions=list(c.n_collisions),
                 md_particles=list(c.md_particles), step=int(c.step),
                 refine_sweeps=int(c.refine_sweeps), refine_residual=float(c.refine_residual),
-                numeric_bad=int(c.numeric_bad), tile_fallback=int(c.tile_fallback))
+                numeric_bad=int(c.numeric_bad), tile_fallback=int(c.tile_fallback),
+                n_coulomb=int(c.n_coulomb))
 
 
 def pic_derived(ctx, replica):
