@@ -29,6 +29,13 @@ METRIC = "particle-steps/s + % HBM roofline, FP32-refined/batched vs FP64 at sta
 HBM_PEAK_GBS = 8000.0
 RECORD_BYTES = {"fp32r": 32, "fp64": 52}      # per particle: read once, written once
 NODE_BYTES = {"fp32r": 16 + 8, "fp64": 32 + 8}  # per node and step: E read, rho written
+# one Coulomb-collision pass, per alive particle: cell read to count and to
+# scatter, id read, order key and slot written, then read, the slots in key
+# order written and read, id read, velocity read and written (FP64: three
+# position doubles instead of the packed cell, double velocities); per cell
+# and species: the count cleared, scanned, its cursor cleared, its range read
+COULOMB_BYTES = {"fp32r": 72, "fp64": 136}
+COULOMB_CELL_BYTES = 48
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_push_f32r_full_64x64x256_ppc32.md")
@@ -66,6 +73,10 @@ def _alive(sim):
     return sum(sum(sim.counters(r)["n_alive"]) for r in range(len(sim.wls)))
 
 
+def _counter_sum_scalar(sim, key):
+    return sum(sim.counters(r)[key] for r in range(len(sim.wls)))
+
+
 def _counter_sum(sim, key):
     return sum(sum(sim.counters(r)[key]) for r in range(len(sim.wls)))
 
@@ -75,9 +86,9 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
     one for the single-run forms, several for the batched ensemble)."""
     import torch
 
-    from paper_1801_00972_amd.pic import (PIC_PROF_FIELD, PIC_PROF_LISTS, PIC_PROF_PUSH,
-                                          PIC_PROF_SORT, Simulation, pic_profile_enable,
-                                          pic_profile_read)
+    from paper_1801_00972_amd.pic import (PIC_PROF_COULOMB, PIC_PROF_FIELD, PIC_PROF_LISTS,
+                                          PIC_PROF_PUSH, PIC_PROF_SORT, Simulation,
+                                          pic_profile_enable, pic_profile_read)
 
     label = label or wls[0]["name"]
     log(f"[bench] init {label} ({len(wls)} replica(s))")
@@ -98,6 +109,7 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
     n_start = _alive(sim)
     md0, coll0 = _counter_sum(sim, "md_particles"), _counter_sum(sim, "n_collisions")
     fall0 = sum(sim.counters(r)["tile_fallback"] for r in range(len(wls)))
+    coul0 = _counter_sum_scalar(sim, "n_coulomb")
     pic_profile_enable(sim.ctx, True)
     torch.cuda.synchronize()
     log(f"[bench] timing {steps} steps (direct launches, kernel events)")
@@ -110,6 +122,8 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
     field_ms, _ = pic_profile_read(sim.ctx, PIC_PROF_FIELD)
     sort_ms, sort_n = pic_profile_read(sim.ctx, PIC_PROF_SORT)
     lists_ms, _ = pic_profile_read(sim.ctx, PIC_PROF_LISTS)
+    coul_ms, coul_n = pic_profile_read(sim.ctx, PIC_PROF_COULOMB)
+    coul_pairs = _counter_sum_scalar(sim, "n_coulomb") - coul0
     pic_profile_enable(sim.ctx, False)
     md1, coll1 = _counter_sum(sim, "md_particles"), _counter_sum(sim, "n_collisions")
     fall1 = sum(sim.counters(r)["tile_fallback"] for r in range(len(wls)))
@@ -157,6 +171,18 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
         md_particle_steps=md1 - md0,
         collisions=coll1 - coll0,
     )
+    if coul_n:
+        # the pass runs at the start of a step on the particles alive then
+        ncell = sum(w["nx"] * w["ny"] * w["nz"] for w in wls)
+        per_pass = 0.5 * (n_start + n_end) * COULOMB_BYTES[prec] + ncell * COULOMB_CELL_BYTES
+        gbs = per_pass * coul_n / (coul_ms * 1e-3) / 1e9
+        res["coulomb"] = dict(interval=wls[0].get("coulomb_interval", 0), passes=coul_n,
+                              ms_per_pass=coul_ms / coul_n, pairings=coul_pairs,
+                              roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
+                                            unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                                            bytes_per_pass=per_pass))
+        log(f"[bench] {label}: Coulomb pass {res['coulomb']['ms_per_pass']:.3f} ms "
+            f"({coul_n} passes), {gbs:.0f} GB/s algorithmic")
     log(f"[bench] {label}: {res['value']:.3e} particle-steps/s, {res['ms_per_step']:.3f} ms/step "
         f"(direct with events {res['direct_with_kernel_events']['ms_per_step']:.3f} ms/step), "
         f"push {res['push_ms_per_launch']:.3f} ms/launch, {achieved:.0f} GB/s")
@@ -206,7 +232,15 @@ def cpu_baseline(wl, steps=6):
                        f"from the oracle's own loading, {t1 - t0:.1f} s")
 
 
-def form_workloads(form, workload):
+def form_workloads(form, workload, coulomb=0):
+    wls = _form_workloads(form, workload)
+    if coulomb:
+        # Coulomb collisions every `coulomb` steps, Coulomb logarithm 10
+        wls = [dict(w, coulomb_interval=coulomb, coulomb_lnL=10.0) for w in wls]
+    return wls
+
+
+def _form_workloads(form, workload):
     from paper_1801_00972_amd import workloads as W
     if workload == "large":
         if form != "fp32r":
@@ -227,6 +261,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--sort-interval", type=int, default=8)
+    ap.add_argument("--coulomb", type=int, default=0,
+                    help="Coulomb collisions every N steps (0: off, the default workloads)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -245,7 +281,7 @@ def main():
         forms = ["fp32r"]
     results = {}
     for form in forms:
-        wls = form_workloads(form, args.workload)
+        wls = form_workloads(form, args.workload, args.coulomb)
         results[form] = run_form(wls, args.steps, args.warmup, args.sort_interval,
                                  autotune=not args.no_autotune,
                                  label=f"{form} {wls[0]['name']}" if len(wls) == 1 else
@@ -275,6 +311,7 @@ def main():
             "grains": int(len(wl["grain_pos"])),
             "pp_cutoff_cells": wl["cutoff"],
             "stated_err": {"fp32r": 1e-5, "fp64": 1e-12},
+            "coulomb_interval": args.coulomb,
             "settings": R["settings"],
         },
         "roofline": R["roofline"],

@@ -358,11 +358,15 @@ int pic_autotune(pic_ctx* ctx, int trial_steps, pic_tuning* tried, double* ms_pe
  *   PIC_PROF_SORT   the periodic cell sort of both species
  *   PIC_PROF_LISTS  the listed particles of one species: sub-cycled near-grain
  *                   motion and the collisions of the candidates
+ *   PIC_PROF_COULOMB  one Coulomb-collision pass of a replica (steps launched
+ *                   one replica at a time; in the batched step it is part of
+ *                   PIC_PROF_FIELD)
  */
 #define PIC_PROF_PUSH  0
 #define PIC_PROF_FIELD 1
 #define PIC_PROF_SORT  2
 #define PIC_PROF_LISTS 3
+#define PIC_PROF_COULOMB 4
 int pic_profile_enable(pic_ctx* ctx, int on);
 int pic_profile_read(pic_ctx* ctx, int kernel_class, double* total_ms, int64_t* launches);
 

@@ -9,10 +9,14 @@
 //     key is the particle's Philox word (id, k, order purpose, species) above
 //     its id, so the order inside a cell does not depend on the scatter's
 //     atomics;
-//  3. one 64-lane block per cell ranks each species' range by key, then runs
+//  3. one wave per block strides over the cells: it stages a cell's keys,
+//     slots, ids and velocities in LDS, ranks each species by key, then runs
 //     the like pairs (e-e and Ar+-Ar+, pairs in parallel, an odd count's
 //     triplet on lane 0), a barrier, and the unlike pairs (one lane per
-//     particle of the less numerous species, its partners in order).
+//     particle of the less numerous species, its partners in order), all in
+//     FP64, and writes the velocities back once; cells with more particles
+//     than the stage holds run the same rule through global memory.
+// Counting and scattering take one atomic per run of equal cells in a wave.
 // The collisions of one pass touch disjoint particles except where the
 // pairing rule orders them, so this is the sequential pass of the rule.
 #include <hip/hip_runtime.h>
@@ -66,13 +70,38 @@ __device__ __forceinline__ void store_v(const PartF32R& P, long p, const double 
   P.vz[p] = (float)v[2];
 }
 
+// Runs of equal cells in consecutive lanes of a wave (the slots are grouped
+// by tile and by cell after a re-binning): each lane learns its run's first
+// lane; the first lane also the run's length.  All 64 lanes must call it.
+__device__ __forceinline__ void wave_run(int cell, int& head, int& len) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int prev = __shfl_up(cell, 1);
+  const bool first = lane == 0 || prev != cell;
+  const unsigned long long heads = __ballot(first);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+  head = 63 - __clzll(heads & upto);
+  const unsigned long long after = heads & ~upto;
+  len = (after ? __ffsll((long long)after) - 1 : 64) - lane;
+}
+
+// the cell of slot p, or -1 for an empty slot or one past the end
+template <typename PT>
+__device__ __forceinline__ int slot_cell(const PT& P, long p, long total, int nx, int ny) {
+  return (p < total && alive(P, p)) ? cell_of(P, p, nx, ny) : -1;
+}
+
 template <typename PT>
 __global__ __launch_bounds__(256) void coul_count_kernel(PT P, WorkLists L, int nx, int ny,
                                                          int* __restrict__ cnt) {
   const long total = L.tstart[L.ngrid];
-  for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < total;
-       p += (long)gridDim.x * blockDim.x)
-    if (alive(P, p)) atomicAdd(&cnt[cell_of(P, p, nx, ny)], 1);
+  const long wave0 = ((long)blockIdx.x * blockDim.x + threadIdx.x) & ~63L;
+  const int lane = (int)(threadIdx.x & 63);
+  for (long base = wave0; base < total; base += (long)gridDim.x * blockDim.x) {
+    const int c = slot_cell(P, base + lane, total, nx, ny);
+    int head, len;
+    wave_run(c, head, len);
+    if (head == lane && c >= 0) atomicAdd(&cnt[c], len);
+  }
 }
 
 // exclusive scan of a[0..n) in place: blocks of kScanChunk, their totals in sums
@@ -144,11 +173,18 @@ __global__ __launch_bounds__(256) void coul_scatter_kernel(PT P, WorkLists L, Co
                                                            int* __restrict__ slot) {
   const long total = L.tstart[L.ngrid];
   const uint32_t k = *C.step;
-  for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < total;
-       p += (long)gridDim.x * blockDim.x) {
-    if (!alive(P, p)) continue;
-    const int c = cell_of(P, p, C.nx, C.ny);
-    const int at = start[c] + atomicAdd(&fill[c], 1);
+  const long wave0 = ((long)blockIdx.x * blockDim.x + threadIdx.x) & ~63L;
+  const int lane = (int)(threadIdx.x & 63);
+  for (long base = wave0; base < total; base += (long)gridDim.x * blockDim.x) {
+    const long p = base + lane;
+    const int c = slot_cell(P, p, total, C.nx, C.ny);
+    int head, len;
+    wave_run(c, head, len);
+    int off = 0;
+    if (head == lane && c >= 0) off = atomicAdd(&fill[c], len);
+    off = __shfl(off, head) + (lane - head);
+    if (c < 0) continue;
+    const int at = start[c] + off;
     const uint32_t id = P.id[p];
     const uint4 r = philox4x32_10(id, k, kCOrder, (uint32_t)sp, C.key0, C.key1);
     key[at] = ((unsigned long long)r.x << 32) | id;
@@ -166,18 +202,21 @@ __device__ void coul_collide(const CoulombConst& C, uint32_t k, uint32_t word, d
   const double um = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
   if (!(um > 0.0)) return;
   const uint4 r = philox4x32_10(id, k, kCPair, word, C.key0, C.key1);
-  double n0, n1;
-  normal_pair(r.x, r.y, n0, n1);
+  // Box-Muller, cosine branch: sqrt(-2 ln u1) cos(2 pi u2); cospi / sincospi
+  // take the angle in half turns, which needs no range reduction by pi
+  const double n0 = sqrt(-2.0 * log(u01_open(r.x))) * cospi(2.0 * u01_open(r.y));
   const double delta = sqrt(cv / (um * um * um)) * n0;
-  const double phi = 2.0 * kPi * u01_open(r.z);
-  const double sn = 2.0 * delta / (1.0 + delta * delta);
-  const double omc = 2.0 * delta * delta / (1.0 + delta * delta);
-  const double cp = cos(phi), sp = sin(phi);
+  double sp, cp;
+  sincospi(2.0 * u01_open(r.z), &sp, &cp);
+  const double inv = 1.0 / (1.0 + delta * delta);
+  const double sn = 2.0 * delta * inv;
+  const double omc = 2.0 * delta * delta * inv;
   const double up = sqrt(u0 * u0 + u1 * u1);
   double du[3];
   if (up > 0.0) {
-    du[0] = (u0 / up) * u2 * sn * cp - (u1 / up) * um * sn * sp - u0 * omc;
-    du[1] = (u1 / up) * u2 * sn * cp + (u0 / up) * um * sn * sp - u1 * omc;
+    const double iu = 1.0 / up;
+    du[0] = (u0 * iu) * u2 * sn * cp - (u1 * iu) * um * sn * sp - u0 * omc;
+    du[1] = (u1 * iu) * u2 * sn * cp + (u0 * iu) * um * sn * sp - u1 * omc;
     du[2] = -up * sn * cp - u2 * omc;
   } else {
     du[0] = um * sn * cp;
@@ -191,98 +230,179 @@ __device__ void coul_collide(const CoulombConst& C, uint32_t k, uint32_t word, d
   }
 }
 
+// The pairing rule on velocities held in a cell's arrays (LDS or registers),
+// in key order: like pairs of both species (lanes over pairs, an odd count's
+// triplet on lane 0), a barrier, then the unlike pairs (lane r takes particle
+// r of the less numerous species b and its partners j = r, r + N_b, ... of a).
+// V(s, q) is the velocity of the q-th particle of species s in key order,
+// ID(s, q) its id.
+#define COUL_PAIRS(V, ID)                                                                     \
+  {                                                                                         \
+    /* like items of both species in one list: species 0's, then 1's; an */                \
+    /* odd count's triplet is its species' first item */                                   \
+    int items[2];                                                                           \
+    _Pragma("unroll") for (int s = 0; s < 2; ++s)                                            \
+      items[s] = n[s] < 2 ? 0 : ((n[s] & 1) ? 1 + (n[s] - 3) / 2 : n[s] / 2);                 \
+    for (int it = lane; it < items[0] + items[1]; it += 64) {                               \
+      const int s = it < items[0] ? 0 : 1;                                                  \
+      const int i = it - (s ? items[0] : 0);                                                \
+      const int N = n[s];                                                                   \
+      const double cv = C.c_var[s] * (double)N * C.w_vol;                                   \
+      const double f = C.frac[s][s];                                                        \
+      if ((N & 1) && i == 0) {                                                              \
+        coul_collide(C, k, (uint32_t)s, 0.5 * cv, f, f, V(s, 0), V(s, 1), ID(s, 0));        \
+        coul_collide(C, k, (uint32_t)s, 0.5 * cv, f, f, V(s, 1), V(s, 2), ID(s, 1));        \
+        coul_collide(C, k, (uint32_t)s, 0.5 * cv, f, f, V(s, 2), V(s, 0), ID(s, 2));        \
+      } else {                                                                              \
+        const int q = (N & 1) ? 3 + 2 * (i - 1) : 2 * i;                                     \
+        coul_collide(C, k, (uint32_t)s, cv, f, f, V(s, q), V(s, q + 1), ID(s, q));          \
+      }                                                                                     \
+    }                                                                                       \
+    __syncthreads();                                                                        \
+    if (n[0] > 0 && n[1] > 0) {                                                             \
+      const int sa = n[0] >= n[1] ? 0 : 1, sb = 1 - sa;                                     \
+      const int Na = n[sa], Nb = n[sb];                                                     \
+      const double cv = C.c_var[2] * (double)Nb * C.w_vol;                                  \
+      for (int r = lane; r < Nb; r += 64)                                                   \
+        for (int j = r; j < Na; j += Nb)                                                    \
+          coul_collide(C, k, 2u + (uint32_t)sa, cv, C.frac[2][sa], C.frac[2][sb], V(sa, j), \
+                       V(sb, r), ID(sa, j));                                                \
+    }                                                                                       \
+    __syncthreads();                                                                        \
+  }
+
+// cells whose species each hold at most kCellCap particles go through LDS
+constexpr int kCellCap = 128;
+struct CellStage {
+  unsigned long long key[2][kCellCap];
+  int slot_in[2][kCellCap];
+  int slot[2][kCellCap];  // in key order
+  uint32_t id[2][kCellCap];
+  double v[2][kCellCap][3];
+};
+
+// cells above the LDS capacity: velocities in global memory through the
+// slots in key order
 template <typename PT>
-__device__ __forceinline__ void like_pair(const PT& P, const CoulombConst& C, uint32_t k, int sp,
-                                          const int* ord, int qa, int qb, double cv) {
-  const long pa = ord[qa], pb = ord[qb];
+__device__ void global_collide(const PT P[2], const int* const ord[2], const CoulombConst& C,
+                               uint32_t k, uint32_t word, double cv, double fa, double fb, int sa,
+                               int qa, int sb, int qb, uint32_t id) {
+  const long pa = ord[sa][qa], pb = ord[sb][qb];
   double va[3], vb[3];
-  load_v(P, pa, va);
-  load_v(P, pb, vb);
-  coul_collide(C, k, (uint32_t)sp, cv, C.frac[sp][sp], C.frac[sp][sp], va, vb, P.id[pa]);
-  store_v(P, pa, va);
-  store_v(P, pb, vb);
+  load_v(P[sa], pa, va);
+  load_v(P[sb], pb, vb);
+  coul_collide(C, k, word, cv, fa, fb, va, vb, id);
+  store_v(P[sa], pa, va);
+  store_v(P[sb], pb, vb);
 }
 
+// One wave per block strides over the cells.
 template <typename PT>
 __global__ __launch_bounds__(64) void coul_pair_kernel(PT Pe, PT Pi, CoulombBufs B,
                                                        CoulombConst C) {
-  const int c = blockIdx.x;
+  __shared__ CellStage sm;
   const int lane = threadIdx.x;
   const PT P[2] = {Pe, Pi};
-  int r0[2], n[2];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    r0[s] = B.start[s][c];
-    n[s] = B.start[s][c + 1] - r0[s];
-  }
-  if (n[0] + n[1] < 2) return;
   const uint32_t k = *C.step;
-  // rank by key (unique: the id is in the low word)
+  unsigned long long pairings = 0;  // this wave's cells, added to the counter once
+  for (int c = blockIdx.x; c < C.ncell; c += gridDim.x) {
+    int r0[2], n[2];
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const unsigned long long* key = B.key[s] + r0[s];
-    for (int q = lane; q < n[s]; q += 64) {
-      const unsigned long long kq = key[q];
-      int rank = 0;
-      for (int t = 0; t < n[s]; ++t) rank += key[t] < kq;
-      B.ord[s][r0[s] + rank] = B.slot[s][r0[s] + q];
+    for (int s = 0; s < 2; ++s) {
+      r0[s] = B.start[s][c];
+      n[s] = B.start[s][c + 1] - r0[s];
     }
-  }
-  __syncthreads();
-  // like pairs, both species
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const int N = n[s];
-    if (N < 2) continue;
-    const int* ord = B.ord[s] + r0[s];
-    const double cv = C.c_var[s] * (double)N * C.w_vol;
-    int first = 0;
-    if (N & 1) {
-      if (lane == 0) {
-        like_pair(P[s], C, k, s, ord, 0, 1, 0.5 * cv);
-        like_pair(P[s], C, k, s, ord, 1, 2, 0.5 * cv);
-        like_pair(P[s], C, k, s, ord, 2, 0, 0.5 * cv);
-      }
-      first = 3;
-    }
-    for (int q = first + 2 * lane; q + 1 < N; q += 128) like_pair(P[s], C, k, s, ord, q, q + 1, cv);
-  }
-  __syncthreads();
-  // unlike pairs: lane r takes particle r of the less numerous species b and
-  // its partners j = r, r + N_b, ... of species a, in order
-  if (n[0] > 0 && n[1] > 0) {
-    const int sa = n[0] >= n[1] ? 0 : 1, sb = 1 - sa;
-    const int Na = n[sa], Nb = n[sb];
-    const int* oa = B.ord[sa] + r0[sa];
-    const int* ob = B.ord[sb] + r0[sb];
-    const double cv = C.c_var[2] * (double)Nb * C.w_vol;
-    for (int r = lane; r < Nb; r += 64) {
-      const long pb = ob[r];
-      double vb[3];
-      load_v(P[sb], pb, vb);
-      for (int j = r; j < Na; j += Nb) {
-        const long pa = oa[j];
-        double va[3];
-        load_v(P[sa], pa, va);
-        coul_collide(C, k, 2u + (uint32_t)sa, cv, C.frac[2][sa], C.frac[2][sb], va, vb,
-                     P[sa].id[pa]);
-        store_v(P[sa], pa, va);
-        // the b particle's velocity is kept in registers between its
-        // collisions but rounded to the record's precision after each, as the
-        // records hold it
-        store_v(P[sb], pb, vb);
-        load_v(P[sb], pb, vb);
-      }
-    }
-  }
-  if (lane == 0) {
-    unsigned long long m = 0;
+    if (n[0] + n[1] < 2) continue;
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      if (n[s] >= 2) m += (n[s] & 1) ? 3 + (n[s] - 3) / 2 : n[s] / 2;
-    if (n[0] > 0 && n[1] > 0) m += n[0] > n[1] ? n[0] : n[1];
-    if (m) atomicAdd(B.count, m);
+      if (n[s] >= 2) pairings += (n[s] & 1) ? 3 + (n[s] - 3) / 2 : n[s] / 2;
+    if (n[0] > 0 && n[1] > 0) pairings += n[0] > n[1] ? n[0] : n[1];
+    if (n[0] <= kCellCap && n[1] <= kCellCap) {
+      // stage: keys and slots, then rank, gathering ids and velocities in key order
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        for (int q = lane; q < n[s]; q += 64) {
+          sm.key[s][q] = B.key[s][r0[s] + q];
+          sm.slot_in[s][q] = B.slot[s][r0[s] + q];
+        }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        for (int q = lane; q < n[s]; q += 64) {
+          const unsigned long long kq = sm.key[s][q];
+          int rank = 0;
+          for (int t = 0; t < n[s]; ++t) rank += sm.key[s][t] < kq;
+          const int p = sm.slot_in[s][q];
+          sm.slot[s][rank] = p;
+          sm.id[s][rank] = P[s].id[p];
+          load_v(P[s], p, sm.v[s][rank]);
+        }
+      __syncthreads();
+#define LDS_V(s, q) (sm.v[s][q])
+#define LDS_ID(s, q) (sm.id[s][q])
+      COUL_PAIRS(LDS_V, LDS_ID)
+#undef LDS_V
+#undef LDS_ID
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        for (int q = lane; q < n[s]; q += 64) store_v(P[s], sm.slot[s][q], sm.v[s][q]);
+      __syncthreads();
+    } else {
+      // rank into the global order array, collide through it
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const unsigned long long* key = B.key[s] + r0[s];
+        for (int q = lane; q < n[s]; q += 64) {
+          const unsigned long long kq = key[q];
+          int rank = 0;
+          for (int t = 0; t < n[s]; ++t) rank += key[t] < kq;
+          B.ord[s][r0[s] + rank] = B.slot[s][r0[s] + q];
+        }
+      }
+      __syncthreads();
+      const int* const ord[2] = {B.ord[0] + r0[0], B.ord[1] + r0[1]};
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int N = n[s];
+        if (N < 2) continue;
+        const double cv = C.c_var[s] * (double)N * C.w_vol;
+        const double f = C.frac[s][s];
+        int first = 0;
+        if (N & 1) {
+          if (lane == 0) {
+            global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 0, s, 1, P[s].id[ord[s][0]]);
+            global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 1, s, 2, P[s].id[ord[s][1]]);
+            global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 2, s, 0, P[s].id[ord[s][2]]);
+          }
+          first = 3;
+        }
+        for (int q = first + 2 * lane; q + 1 < N; q += 128)
+          global_collide(P, ord, C, k, (uint32_t)s, cv, f, f, s, q, s, q + 1, P[s].id[ord[s][q]]);
+      }
+      __syncthreads();
+      if (n[0] > 0 && n[1] > 0) {
+        const int sa = n[0] >= n[1] ? 0 : 1, sb = 1 - sa;
+        const int Na = n[sa], Nb = n[sb];
+        const double cv = C.c_var[2] * (double)Nb * C.w_vol;
+        for (int r = lane; r < Nb; r += 64) {
+          const long pb = ord[sb][r];
+          double vb[3];
+          load_v(P[sb], pb, vb);
+          for (int j = r; j < Na; j += Nb) {
+            const long pa = ord[sa][j];
+            double va[3];
+            load_v(P[sa], pa, va);
+            coul_collide(C, k, 2u + (uint32_t)sa, cv, C.frac[2][sa], C.frac[2][sb], va, vb,
+                         P[sa].id[pa]);
+            store_v(P[sa], pa, va);
+          }
+          store_v(P[sb], pb, vb);
+        }
+      }
+      __syncthreads();
+    }
   }
+  if (lane == 0 && pairings) atomicAdd(B.count, pairings);
 }
 
 template <typename PT>
@@ -305,7 +425,8 @@ void coulomb_impl(const PT P[2], const WorkLists L[2], const CoulombBufs& B, con
       hipLaunchKernelGGL(coul_scatter_kernel<PT>, dim3(g), dim3(256), 0, st, P[s], L[s], C, s,
                          B.start[s], B.fill[s], B.key[s], B.slot[s]);
   }
-  hipLaunchKernelGGL(coul_pair_kernel<PT>, dim3((unsigned)ncell), dim3(64), 0, st, P[0], P[1], B, C);
+  const int grid = (int)std::min<long>(ncell, 32768);
+  hipLaunchKernelGGL(coul_pair_kernel<PT>, dim3(grid), dim3(64), 0, st, P[0], P[1], B, C);
 }
 
 }  // namespace

@@ -111,7 +111,7 @@ struct pic_ctx {
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[4];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[5];
   // launch settings (pic_set_tuning)
   pic_tuning tune{};
   int since_sort[2]{};
@@ -669,8 +669,12 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   hipEvent_t f0 = prof_event(ctx);
   TRY(solve_fields(ctx, R));
   if (sample) TRY(enqueue_sample(ctx, R));
-  if (coulomb_due(R)) TRY(enqueue_coulomb(ctx, R));
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
+  if (coulomb_due(R)) {
+    hipEvent_t c0 = prof_event(ctx);
+    TRY(enqueue_coulomb(ctx, R));
+    prof_pair(ctx, PIC_PROF_COULOMB, c0, prof_event(ctx));
+  }
   const int rnx = 1 - R.rho_cur;
   const int do_mcc = 1;
   const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
@@ -1658,7 +1662,7 @@ int pic_profile_enable(pic_ctx* ctx, int on) {
 
 int pic_profile_read(pic_ctx* ctx, int cls, double* total_ms, int64_t* launches) {
   if (!ctx) return PIC_EINVAL;
-  if (cls < 0 || cls > 3 || !total_ms || !launches) return fail(ctx, PIC_EINVAL, "bad arguments");
+  if (cls < 0 || cls > PIC_PROF_COULOMB || !total_ms || !launches) return fail(ctx, PIC_EINVAL, "bad arguments");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   double tot = 0.0;
   for (auto& p : ctx->ev_pairs[cls]) {

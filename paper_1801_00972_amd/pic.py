@@ -27,7 +27,7 @@ SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destr
            "pic_profile_enable", "pic_profile_read", "pic_get_tuning", "pic_set_tuning",
            "pic_autotune", "pic_average", "pic_average_read", "pic_set_fine_grid")
 PIC_MAX_PHASE_BINS = 64
-PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT, PIC_PROF_LISTS = 0, 1, 2, 3
+PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT, PIC_PROF_LISTS, PIC_PROF_COULOMB = 0, 1, 2, 3, 4
 
 
 class PicError(RuntimeError):
