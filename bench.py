@@ -81,7 +81,20 @@ def _counter_sum(sim, key):
     return sum(sum(sim.counters(r)[key]) for r in range(len(sim.wls)))
 
 
-def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
+def fine_box(wl, h=0.08, cells=200):
+    """The paper's diagnostic grid: cells^3 cells of h dx (200 of 0.08 dx cover
+    16 PIC cells) around the centre of the grain cluster, inside the domain."""
+    import numpy as np
+    span = h * cells
+    centre = np.asarray(wl["grain_pos"]).mean(axis=0) if len(wl["grain_pos"]) else \
+        np.array([wl["nx"], wl["ny"], wl["nz"]]) / 2.0
+    lim = np.array([wl["nx"], wl["ny"], wl["nz"]]) - span
+    origin = np.clip(np.floor(centre - span / 2), 0, lim)
+    return origin, h, (cells, cells, cells)
+
+
+def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None, average=0,
+             fine=False):
     """Times one arithmetic form on one context (a list of replica workloads:
     one for the single-run forms, several for the batched ensemble)."""
     import torch
@@ -101,6 +114,12 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
         log("[bench] autotune (live steps)")
         tuning, trials = sim.autotune(trial_steps=48)
         log(f"[bench] settings {tuning} after {len(trials)} trials")
+    if fine:
+        for r, w in enumerate(wls):
+            sim.set_fine_grid(*fine_box(w), replica=r)
+    if average:
+        # rf-phase-resolved averages (4 bins) sampled every `average` steps
+        sim.average(average, 4)
     log(f"[bench] warmup {warmup} steps")
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -171,6 +190,10 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None):
         md_particle_steps=md1 - md0,
         collisions=coll1 - coll0,
     )
+    if average:
+        res["averages"] = dict(interval=average, phase_bins=4,
+                               fine_nodes=sim.fine_nodes if fine else None,
+                               samples=sim.averages(0, -1, what=0)["samples"])
     if coul_n:
         # the pass runs at the start of a step on the particles alive then
         ncell = sum(w["nx"] * w["ny"] * w["nz"] for w in wls)
@@ -261,6 +284,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--sort-interval", type=int, default=8)
+    ap.add_argument("--average", type=int, default=0,
+                    help="sample the time averages every N steps (0: off)")
+    ap.add_argument("--fine", action="store_true",
+                    help="with --average: also the 200^3 grid of 0.08 dx over the grain cluster")
     ap.add_argument("--coulomb", type=int, default=0,
                     help="Coulomb collisions every N steps (0: off, the default workloads)")
     args = ap.parse_args()
@@ -283,7 +310,8 @@ def main():
     for form in forms:
         wls = form_workloads(form, args.workload, args.coulomb)
         results[form] = run_form(wls, args.steps, args.warmup, args.sort_interval,
-                                 autotune=not args.no_autotune,
+                                 autotune=not args.no_autotune, average=args.average,
+                                 fine=args.fine and args.average > 0,
                                  label=f"{form} {wls[0]['name']}" if len(wls) == 1 else
                                  f"batched ensemble of {len(wls)}")
     head = "fp32r" if "fp32r" in results else forms[0]
@@ -312,6 +340,8 @@ def main():
             "pp_cutoff_cells": wl["cutoff"],
             "stated_err": {"fp32r": 1e-5, "fp64": 1e-12},
             "coulomb_interval": args.coulomb,
+            "average_interval": args.average,
+            "fine_grid": bool(args.fine and args.average),
             "settings": R["settings"],
         },
         "roofline": R["roofline"],

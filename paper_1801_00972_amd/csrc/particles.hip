@@ -1469,7 +1469,12 @@ __global__ void md_reset_kernel(int32_t* cnt0, int32_t* cnt1) {
 // mesh directly.  mom is [4][nn]: W, v_x W, v_y W, v_z W.  For the time
 // averages (avg.step non-null) the sums go to the rf-phase bin of the
 // current step, avg.stride doubles further per bin.
-constexpr int kMomWin = 125;
+// the moment window: the tile's nodes plus the species' drift margin (as the
+// push stages them; at most 2 cells here), so particles that drifted out of
+// their tile since the last re-binning still add in LDS
+constexpr int kMomWin = 729;
+// copies of the window: thread t adds into copy t % kMomCopies (summed at the flush)
+constexpr int kMomCopies = 1;
 __device__ __forceinline__ bool slot_alive(const PartF64& P, long p) { return P.z[p] >= 0.0; }
 __device__ __forceinline__ bool slot_alive(const PartF32R& P, long p) { return P.cell[p] >= 0; }
 
@@ -1481,24 +1486,63 @@ __global__ __launch_bounds__(256) void moments_kernel(PT P, SpeciesStep S, WorkL
   if (avg.step) mom += avg.stride * phase_bin(*avg.step, avg.f_rf, avg.dt, avg.nbins);
   const long a = L.tstart[t], b = L.tstart[t + 1];
   if (a == b) return;
-  __shared__ double s_m[4][kMomWin];
-  const Tile T = make_tile(t, L, S.nx, S.ny, S.nz, 0, kMomWin);
-  for (int u = threadIdx.x; u < 4 * kMomWin; u += blockDim.x) s_m[u / kMomWin][u % kMomWin] = 0.0;
+  __shared__ double s_m[kMomCopies][4][kMomWin];
+  const Tile T = make_tile(t, L, S.nx, S.ny, S.nz, S.margin, kMomWin);
+  for (int u = threadIdx.x; u < kMomCopies * 4 * kMomWin; u += blockDim.x) (&s_m[0][0][0])[u] = 0.0;
   __syncthreads();
-  for (long p = a + threadIdx.x; p < b; p += blockDim.x) {
+  const int cp = (int)threadIdx.x % kMomCopies;
+  // each thread walks a contiguous run of slots: the slots of a tile are grouped
+  // by cell, so consecutive particles of one cell are summed in registers and
+  // reach the LDS window once per run
+  const long per = (b - a + blockDim.x - 1) / blockDim.x;
+  const long p0 = a + (long)threadIdx.x * per, p1 = p0 + per < b ? p0 + per : b;
+  int run_lb = -1;
+  double acc[4][8];
+  for (long p = p0; p < p1; ++p) {
     if (!slot_alive(P, p)) continue;
-    double x[3], v[3], w[8], val[8];
+    double x[3], v[3], w[8];
     load_d(P, p, x, v);
     const int i = (int)floor(x[0]), j = (int)floor(x[1]), k = (int)floor(x[2]);
     cic_weights_d(x[0] - i, x[1] - j, x[2] - k, 1.0, w);
     const int lb = tile_cell(T, i, j, k, S.nx, S.ny);
-    corner_add<double>(T, lb, s_m[0], mom, S, i, j, k, w);
+    if (lb < 0) {
+      // outside the window: straight to the mesh
+      double val[8];
+      corner_add<double>(T, -1, s_m[cp][0], mom, S, i, j, k, w);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+      for (int q = 0; q < 3; ++q) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) val[c] = v[q] * w[c];
-      corner_add<double>(T, lb, s_m[q + 1], mom + (q + 1) * nn, S, i, j, k, val);
+        for (int c = 0; c < 8; ++c) val[c] = v[q] * w[c];
+        corner_add<double>(T, -1, s_m[cp][q + 1], mom + (q + 1) * nn, S, i, j, k, val);
+      }
+      continue;
     }
+    if (lb != run_lb) {
+      if (run_lb >= 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) corner_add<double>(T, run_lb, s_m[cp][q], mom, S, 0, 0, 0, acc[q]);
+      }
+      run_lb = lb;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        acc[0][c] = w[c];
+        acc[1][c] = v[0] * w[c];
+        acc[2][c] = v[1] * w[c];
+        acc[3][c] = v[2] * w[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        acc[0][c] += w[c];
+        acc[1][c] += v[0] * w[c];
+        acc[2][c] += v[1] * w[c];
+        acc[3][c] += v[2] * w[c];
+      }
+    }
+  }
+  if (run_lb >= 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) corner_add<double>(T, run_lb, s_m[cp][q], mom, S, 0, 0, 0, acc[q]);
   }
   __syncthreads();
   if (!T.on) return;
@@ -1507,8 +1551,12 @@ __global__ __launch_bounds__(256) void moments_kernel(PT P, SpeciesStep S, WorkL
   for (int u = threadIdx.x; u < nt; u += blockDim.x) {
     const long node = tile_node(T, u, rtx, rtxy, S.nx, S.ny, S.nxy);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (s_m[q][u] != 0.0) unsafeAtomicAdd(&mom[q * nn + node], s_m[q][u]);
+    for (int q = 0; q < 4; ++q) {
+      double sum = 0.0;
+#pragma unroll
+      for (int c = 0; c < kMomCopies; ++c) sum += s_m[c][q][u];
+      if (sum != 0.0) unsafeAtomicAdd(&mom[q * nn + node], sum);
+    }
   }
 }
 
