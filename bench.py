@@ -250,9 +250,36 @@ def cpu_baseline(wl, steps=6):
     t1 = time.perf_counter()
     n1 = o.n_alive(0) + o.n_alive(1)
     ps = 0.5 * (n0 + n1) * steps
-    return dict(value=ps / (t1 - t0), unit="particle-steps/s", cores=threads, kind="oracle",
-                sample=f"{steps} full FP64 oracle steps of {wl['name']} ({n0} particles) "
-                       f"from the oracle's own loading, {t1 - t0:.1f} s")
+    res = dict(value=ps / (t1 - t0), unit="particle-steps/s", cores=threads, kind="oracle",
+               sample=f"{steps} full FP64 oracle steps of {wl['name']} ({n0} particles) "
+                      f"from the oracle's own loading, {t1 - t0:.1f} s",
+               cpu_model=_cpu_model())
+    # the same oracle on one thread, one more step of the same run
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        n2 = o.n_alive(0) + o.n_alive(1)
+        t2 = time.perf_counter()
+        o.step(1)
+        t3 = time.perf_counter()
+        n3 = o.n_alive(0) + o.n_alive(1)
+        gomp.omp_set_num_threads(threads)
+        res["single_thread"] = dict(value=0.5 * (n2 + n3) / (t3 - t2), unit="particle-steps/s",
+                                    sample=f"step {steps + 1} of the same run, {t3 - t2:.1f} s")
+    except OSError:
+        res["single_thread"] = None
+    return res
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def form_workloads(form, workload, coulomb=0):
