@@ -48,6 +48,10 @@ class _Config(C.Structure):
         ("V_dc", C.c_double), ("V_rf", C.c_double), ("f_rf", C.c_double),
         ("grain_radius", C.c_double), ("E_cap_eV", C.c_double),
         ("Q_frozen_e", C.c_double), ("coulomb_lnL", C.c_double),
+        ("xs_n", C.c_int32), ("pad1", C.c_int32),
+        ("xs_E", C.POINTER(C.c_double)), ("xs_e_el", C.POINTER(C.c_double)),
+        ("xs_e_ex", C.POINTER(C.c_double)), ("xs_i_cx", C.POINTER(C.c_double)),
+        ("xs_i_el", C.POINTER(C.c_double)), ("E_ex_eV", C.c_double),
         ("seed", C.c_uint64),
         ("grain_pos", C.POINTER(C.c_double)),
     ]
@@ -58,7 +62,7 @@ class _Derived(C.Structure):
         ("w", C.c_double), ("Qp", C.c_int64), ("n_gas", C.c_double),
         ("q", C.c_double * 2), ("m", C.c_double * 2), ("vth", C.c_double * 2),
         ("g_cap", C.c_double * 2), ("P_null", C.c_double * 2),
-        ("T_null", C.c_uint64 * 2), ("vth_gas", C.c_double),
+        ("T_null", C.c_uint64 * 2), ("vth_gas", C.c_double), ("sg_max", C.c_double * 2),
     ]
 
 
@@ -99,6 +103,10 @@ def lib():
         L.orc_deposit_fixed.argtypes = [C.POINTER(_Config), C.POINTER(_State),
                                         C.POINTER(C.c_int64)]
         L.orc_moments.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp, dp]
+        L.orc_xs_sgmax.argtypes = [C.POINTER(_Config), C.c_int]
+        L.orc_xs_sgmax.restype = C.c_double
+        L.orc_xs_at.argtypes = [C.POINTER(_Config), dp, C.c_double]
+        L.orc_xs_at.restype = C.c_double
         L.orc_coulomb.argtypes = [C.POINTER(_Config), C.POINTER(_State)]
         L.orc_coulomb.restype = C.c_int64
         L.orc_coulomb_pair.argtypes = [C.POINTER(_Config), C.c_int, C.c_int, dp, dp, C.c_double,
@@ -149,6 +157,19 @@ class Oracle:
         cfg.Q_frozen_e = float(Q_frozen_e)
         cfg.coulomb_interval = int(wl.get("coulomb_interval", 0))
         cfg.coulomb_lnL = float(wl.get("coulomb_lnL", 10.0))
+        xs = wl.get("xs")
+        self._xs = {}
+        if xs:
+            for k in ("E", "e_el", "e_ex", "i_cx", "i_el"):
+                if xs.get(k) is not None:
+                    self._xs[k] = np.ascontiguousarray(xs[k], np.float64)
+            cfg.xs_n = len(self._xs["E"])
+            cfg.xs_E = _ptr(self._xs["E"], C.c_double)
+            cfg.xs_e_el = _ptr(self._xs["e_el"], C.c_double)
+            cfg.xs_e_ex = _ptr(self._xs.get("e_ex"), C.c_double)
+            cfg.xs_i_cx = _ptr(self._xs["i_cx"], C.c_double)
+            cfg.xs_i_el = _ptr(self._xs.get("i_el"), C.c_double)
+            cfg.E_ex_eV = float(xs.get("E_ex", 0.0))
         cfg.seed = int(wl.get("seed", 0))
         cfg.grain_pos = _ptr(self.grain_pos, C.c_double)
         self.cfg = cfg
@@ -234,7 +255,7 @@ class Oracle:
             raise ValueError(f"orc_derive failed ({rc})")
         return {"w": d.w, "Qp": d.Qp, "n_gas": d.n_gas, "q": list(d.q), "m": list(d.m),
                 "vth": list(d.vth), "g_cap": list(d.g_cap), "P_null": list(d.P_null),
-                "T_null": list(d.T_null), "vth_gas": d.vth_gas}
+                "T_null": list(d.T_null), "vth_gas": d.vth_gas, "sg_max": list(d.sg_max)}
 
     def rf_voltage(self, k: int) -> float:
         return lib().orc_rf_voltage(C.byref(self.cfg), k)
@@ -358,6 +379,13 @@ class Oracle:
         if self._U is None:
             self._U = np.ascontiguousarray(self.unit_fields(progress))
         return self._U
+
+    def xs_sgmax(self, sp: int) -> float:
+        """max over g <= g_cap of g sigma_total(E(g)) of the tables."""
+        return float(lib().orc_xs_sgmax(C.byref(self.cfg), sp))
+
+    def xs_at(self, table: str, E_eV: float) -> float:
+        return float(lib().orc_xs_at(C.byref(self.cfg), _ptr(self._xs[table], C.c_double), E_eV))
 
     def coulomb(self) -> int:
         """One pass of the Coulomb collisions (Table I, binary model of

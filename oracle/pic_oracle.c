@@ -93,12 +93,74 @@ int orc_derive(const orc_config* c, orc_derived* d)
   double sigma[2] = {c->sigma_e, c->sigma_i};
   for (int s = 0; s < 2; ++s) {
     d->g_cap[s] = sqrt(2.0 * c->E_cap_eV * O_ECHARGE / d->m[s]);
-    double nu_max = d->n_gas * sigma[s] * d->g_cap[s];
+    d->sg_max[s] = c->xs_n > 0 ? orc_xs_sgmax(c, s) : sigma[s] * d->g_cap[s];
+    double nu_max = d->n_gas * d->sg_max[s];
     d->P_null[s] = -expm1(-nu_max * c->dt);
     d->T_null[s] = (uint64_t)floor(d->P_null[s] * 4294967296.0);
   }
   d->vth_gas = sqrt(O_KB * c->T_gas / O_MAR);
   return 0;
+}
+
+/* sigma(E) of a table: linear between the grid points, the end values past them */
+double orc_xs_at(const orc_config* c, const double* table, double E)
+{
+  if (!table) return 0.0;
+  const double* x = c->xs_E;
+  int n = c->xs_n;
+  if (E <= x[0]) return table[0];
+  if (E >= x[n - 1]) return table[n - 1];
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (x[mid] <= E) lo = mid;
+    else hi = mid;
+  }
+  double t = (E - x[lo]) / (x[hi] - x[lo]);
+  return table[lo] + t * (table[hi] - table[lo]);
+}
+
+/* total cross section of a species at E */
+static double xs_total(const orc_config* c, int sp, double E)
+{
+  if (sp == 0) return orc_xs_at(c, c->xs_e_el, E) + orc_xs_at(c, c->xs_e_ex, E);
+  return orc_xs_at(c, c->xs_i_cx, E) + orc_xs_at(c, c->xs_i_el, E);
+}
+
+/* max over 0 <= E <= E_cap of g(E) sigma_total(E), g = sqrt(2 E e / m):    */
+/* on a piece where sigma = a + b E the function a sqrt(E) + b E^(3/2) has    */
+/* its only stationary point at E = -a / (3 b); the maximum is there or at   */
+/* a piece's end (past the grid sigma is constant and sqrt(E) increases).   */
+double orc_xs_sgmax(const orc_config* c, int sp)
+{
+  double m = sp == 0 ? O_ME : O_MAR;
+  double Ecap = c->E_cap_eV;
+  double best = 0.0;
+  double cand[3];
+  for (int i = -1; i < c->xs_n; ++i) {
+    double lo = i < 0 ? 0.0 : c->xs_E[i];
+    double hi = i + 1 < c->xs_n ? c->xs_E[i + 1] : Ecap;
+    if (lo > Ecap) break;
+    if (hi > Ecap) hi = Ecap;
+    if (hi < lo) continue;
+    int nc = 0;
+    cand[nc++] = lo;
+    cand[nc++] = hi;
+    if (i >= 0 && i + 1 < c->xs_n) {
+      double s0 = xs_total(c, sp, lo), s1 = xs_total(c, sp, c->xs_E[i + 1]);
+      double b = (s1 - s0) / (c->xs_E[i + 1] - lo);
+      double a = s0 - b * lo;
+      if (b < 0.0) {
+        double Es = -a / (3.0 * b);
+        if (Es > lo && Es < hi) cand[nc++] = Es;
+      }
+    }
+    for (int q = 0; q < nc; ++q) {
+      double f = xs_total(c, sp, cand[q]) * sqrt(2.0 * cand[q] * O_ECHARGE / m);
+      if (f > best) best = f;
+    }
+  }
+  return best;
 }
 
 double orc_rf_voltage(const orc_config* c, uint32_t k)
@@ -692,6 +754,66 @@ static int move_md(const orc_config* c, const double* E, const double* U, const 
   return MV_ALIVE;
 }
 
+/* the same with energy-dependent cross sections: the process is picked by  */
+/* u1 against the cumulative g sigma_k(E) / (g sigma)_max.  Electrons:      */
+/* elastic, then excitation (only with the CM energy above E_ex: the CM     */
+/* energy drops by E_ex, isotropic scattering); ions: charge exchange, then */
+/* isotropic elastic scattering in the CM frame of ion and neutral.  Above  */
+/* the bound (a cap violation) the collision happens and u1 splits sigma.   */
+static void collide_xs(const orc_config* c, const orc_derived* d, int sp, const uint32_t r[4],
+                       const double* vn, double* v, double* margin, int64_t* cap_viol,
+                       int64_t* ncoll)
+{
+  double gv[3] = {v[0] - vn[0], v[1] - vn[1], v[2] - vn[2]};
+  double g2 = gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2];
+  double g = sqrt(g2);
+  double E = 0.5 * d->m[sp] * g2 / O_ECHARGE;
+  double s1, s2;
+  if (sp == 0) {
+    double mu = d->m[0] * d->m[1] / (d->m[0] + d->m[1]);
+    s1 = orc_xs_at(c, c->xs_e_el, E);
+    s2 = 0.5 * mu * g2 > c->E_ex_eV * O_ECHARGE ? orc_xs_at(c, c->xs_e_ex, E) : 0.0;
+  } else {
+    s1 = orc_xs_at(c, c->xs_i_cx, E);
+    s2 = orc_xs_at(c, c->xs_i_el, E);
+  }
+  double a1 = g * s1 / d->sg_max[sp], a2 = g * (s1 + s2) / d->sg_max[sp];
+  double u1 = unif_open(r[1]);
+  int proc; /* 0 none, 1 first process, 2 second */
+  if (a2 > 1.0) {
+#pragma omp atomic
+    cap_viol[sp] += 1;
+    proc = u1 * (s1 + s2) < s1 ? 1 : 2;
+  } else {
+    *margin = dmin(*margin, dmin(fabs(u1 - a1), fabs(u1 - a2)));
+    proc = u1 < a1 ? 1 : (u1 < a2 ? 2 : 0);
+  }
+  if (proc == 0) return;
+#pragma omp atomic
+  ncoll[sp] += 1;
+  if (sp == 1 && proc == 1) {
+    for (int a = 0; a < 3; ++a) v[a] = vn[a]; /* charge exchange */
+    return;
+  }
+  double cost = 1.0 - 2.0 * unif_open(r[2]);
+  double sint = sqrt(fmax(0.0, 1.0 - cost * cost));
+  double ph = 2.0 * O_PI * unif_open(r[3]);
+  double nh[3] = {sint * cos(ph), sint * sin(ph), cost};
+  double mt = d->m[0] + d->m[1];
+  if (sp == 0) {
+    /* neutral at rest: v' = (m v + M 0) / (m + M) + M / (m + M) g' n */
+    double gp = g;
+    if (proc == 2) {
+      double mu = d->m[0] * d->m[1] / mt;
+      gp = sqrt(g2 - 2.0 * c->E_ex_eV * O_ECHARGE / mu);
+    }
+    for (int a = 0; a < 3; ++a) v[a] = (d->m[0] / mt) * v[a] + (d->m[1] / mt) * gp * nh[a];
+  } else {
+    /* ion and neutral of equal mass: v' = (v + v_n) / 2 + (g / 2) n */
+    for (int a = 0; a < 3; ++a) v[a] = 0.5 * (v[a] + vn[a]) + 0.5 * g * nh[a];
+  }
+}
+
 /* binary collision with a neutral drawn from the reservoir, null-collision form */
 static void collide(const orc_config* c, const orc_derived* d, int sp, uint32_t id, uint32_t k,
                     double* v, double* margin, int64_t* cap_viol, int64_t* ncoll)
@@ -707,6 +829,10 @@ static void collide(const orc_config* c, const orc_derived* d, int sp, uint32_t 
     box_muller(rn[0], rn[1], &vn[0], &vn[1]);
     box_muller(rn[2], rn[3], &vn[2], &unused);
     for (int a = 0; a < 3; ++a) vn[a] *= d->vth_gas;
+  }
+  if (c->xs_n > 0) {
+    collide_xs(c, d, sp, r, vn, v, margin, cap_viol, ncoll);
+    return;
   }
   double gv[3] = {v[0] - vn[0], v[1] - vn[1], v[2] - vn[2]};
   double g = sqrt(gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2]);

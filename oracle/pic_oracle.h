@@ -57,6 +57,18 @@ typedef struct orc_config {
   double E_cap_eV;           /* null-collision cap on the relative kinetic energy */
   double Q_frozen_e;         /* grain charge in e when ORC_FROZEN_Q is set */
   double coulomb_lnL;        /* Coulomb logarithm of the charged-particle collisions */
+  /* energy-dependent cross sections (xs_n = 0: the constant sigma_e, sigma_i
+     above, e-Ar elastic and Ar+-Ar charge exchange only).  One energy grid,
+     the projectile's energy with the target at rest (eV), increasing;
+     sigma(E) linear between the points and constant past the ends. */
+  int32_t xs_n;
+  int32_t pad1;
+  const double* xs_E;        /* [xs_n] eV */
+  const double* xs_e_el;     /* [xs_n] e-Ar elastic, m^2 */
+  const double* xs_e_ex;     /* [xs_n] e-Ar excitation, m^2, nullable */
+  const double* xs_i_cx;     /* [xs_n] Ar+-Ar charge exchange, m^2 */
+  const double* xs_i_el;     /* [xs_n] Ar+-Ar elastic (isotropic), m^2, nullable */
+  double E_ex_eV;            /* excitation energy */
   uint64_t seed;             /* Philox key */
   const double* grain_pos;   /* [n_grains][3], cell units */
 } orc_config;
@@ -71,6 +83,7 @@ typedef struct orc_derived {
   double P_null[2];          /* candidate probability per step */
   uint64_t T_null[2];        /* integer candidate threshold floor(P * 2^32) */
   double vth_gas;            /* sqrt(kB T_gas / M_Ar) */
+  double sg_max[2];          /* tables: max over g <= g_cap of g sigma_total */
 } orc_derived;
 
 typedef struct orc_state {
@@ -105,6 +118,11 @@ int orc_deposit_fixed(const orc_config* c, const orc_state* s, int64_t* rho_fixe
 int orc_moments(const orc_config* c, const orc_state* s, double* n, double* flux);
 int orc_fine_moments(const orc_config* c, const orc_state* s, const double origin[3], double h,
                      const int32_t m[3], double* n, double* flux);
+
+/* cross-section tables: sigma of one table at energy E (eV), and the bound
+ * max over g <= g_cap of g sigma_total(E(g)) of a species */
+double orc_xs_at(const orc_config* c, const double* table, double E_eV);
+double orc_xs_sgmax(const orc_config* c, int sp);
 
 /* Coulomb collisions of the charged particles (Table I; binary model of
  * Takizuka and Abe): one pass over all cells at the state's step k, with
