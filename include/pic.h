@@ -115,7 +115,29 @@ typedef struct pic_config {
   int32_t coulomb_interval;    /* steps between Coulomb-collision passes (0: none) */
   int32_t reserved0;           /* 0 */
   double coulomb_lnL;          /* Coulomb logarithm (> 0 when coulomb_interval > 0) */
+  /* energy-dependent cross sections (xs_n = 0: the constant sigma_e_el and
+   * sigma_i_cx above).  Host arrays of xs_n points, copied by pic_init: one
+   * energy grid, the projectile's kinetic energy with the target at rest
+   * (eV, increasing, >= 0); sigma(E) is linear between the points and
+   * constant past the ends.  The null-collision rate bound is the maximum of
+   * g sigma_total(E(g)) for relative speeds up to the E_cap_eV speed; the
+   * process of a candidate is picked by a uniform draw against the
+   * cumulative g sigma_k / bound: electrons elastic, then excitation (only
+   * with a centre-of-mass energy above E_ex_eV, which it removes; isotropic
+   * scattering in the centre-of-mass frame, neutral at rest); ions charge
+   * exchange, then isotropic elastic scattering in the centre-of-mass frame
+   * of ion and drawn neutral (Table I's e + Ar elastic, excitation,
+   * Ar+ + Ar charge exchange and elastic; ionisation is not provided). */
+  int32_t xs_n;                /* 0, or 2 .. PIC_MAX_XS points */
+  int32_t reserved1;           /* 0 */
+  const double* xs_E;          /* [xs_n] eV */
+  const double* xs_e_el;       /* [xs_n] e-Ar elastic, m^2 */
+  const double* xs_e_ex;       /* [xs_n] e-Ar excitation, m^2, nullable (none) */
+  const double* xs_i_cx;       /* [xs_n] Ar+-Ar charge exchange, m^2 */
+  const double* xs_i_el;       /* [xs_n] Ar+-Ar elastic, m^2, nullable (none) */
+  double E_ex_eV;              /* excitation energy (>= 0) */
 } pic_config;
+#define PIC_MAX_XS 4096
 
 typedef struct pic_ctx pic_ctx;
 

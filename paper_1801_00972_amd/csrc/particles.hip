@@ -353,9 +353,94 @@ __device__ __forceinline__ void normal_pair_t(uint32_t wa, uint32_t wb, T& n0, T
   }
 }
 
+// sigma of table column `col` at energy E (eV): linear between the grid
+// points, the end values past them
+__device__ inline double xs_at(const SpeciesStep& S, int col, double E) {
+  const double* x = S.xs;
+  const double* t = S.xs + (long)col * S.xs_n;
+  const int n = S.xs_n;
+  if (E <= x[0]) return t[0];
+  if (E >= x[n - 1]) return t[n - 1];
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (x[mid] <= E) lo = mid;
+    else hi = mid;
+  }
+  const double f = (E - x[lo]) / (x[hi] - x[lo]);
+  return t[lo] + f * (t[hi] - t[lo]);
+}
+
+// A candidate's collision with energy-dependent cross sections (FP64 in
+// both forms): the process is picked by u1 against the cumulative
+// g sigma_k(E) / (g sigma)_max, E the projectile's energy with the target at
+// rest.  Electrons: elastic, then excitation (CM energy above E_ex; the CM
+// energy drops by E_ex, isotropic scattering); ions: charge exchange, then
+// isotropic elastic scattering in the CM frame of ion and neutral (equal
+// masses).  Above the bound the collision happens (counted) and u1 splits
+// the cross section.
+template <typename T>
+__device__ void collide_xs(const SpeciesStep& S, const uint4& r, const T vn[3], T v[3], bool& coll,
+                           bool& capv) {
+  const double gx = (double)v[0] - (double)vn[0], gy = (double)v[1] - (double)vn[1],
+               gz = (double)v[2] - (double)vn[2];
+  const double g2 = gx * gx + gy * gy + gz * gz;
+  const double g = sqrt(g2);
+  const double E = 0.5 * g2 / fabs(S.qm);  // m g^2 / 2 in eV (|q| = e)
+  double s1, s2;
+  if (S.sp == 0) {
+    s1 = xs_at(S, 1, E);
+    s2 = g2 > S.ex_g2 ? xs_at(S, 2, E) : 0.0;
+  } else {
+    s1 = xs_at(S, 3, E);
+    s2 = xs_at(S, 4, E);
+  }
+  const double a1 = g * s1 / S.sg_max, a2 = g * (s1 + s2) / S.sg_max;
+  const double u1 = u01_open(r.y);
+  int proc;
+  if (a2 > 1.0) {
+    capv = true;
+    proc = u1 * (s1 + s2) < s1 ? 1 : 2;
+  } else {
+    proc = u1 < a1 ? 1 : (u1 < a2 ? 2 : 0);
+  }
+  if (proc == 0) return;
+  coll = true;
+  if (S.sp == 1 && proc == 1) {
+    v[0] = vn[0];
+    v[1] = vn[1];
+    v[2] = vn[2];
+    return;
+  }
+  const double cost = 1.0 - 2.0 * u01_open(r.z);
+  const double sint = sqrt(fmax(0.0, 1.0 - cost * cost));
+  double sp, cp;
+  sincos(2.0 * kPi * u01_open(r.w), &sp, &cp);
+  const double nh[3] = {sint * cp, sint * sp, cost};
+  if (S.sp == 0) {
+    const double gp = proc == 2 ? sqrt(g2 - S.ex_g2) : g;
+    for (int a = 0; a < 3; ++a) v[a] = (T)(S.mass_ratio_e * (double)v[a] + S.mass_ratio_n * gp * nh[a]);
+  } else {
+    for (int a = 0; a < 3; ++a) v[a] = (T)(0.5 * ((double)v[a] + (double)vn[a]) + 0.5 * g * nh[a]);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void collide(const SpeciesStep& S, uint32_t id, T v[3], bool& coll,
                                         bool& capv) {
+  if constexpr (sizeof(T) == 4) {
+    // FP32R records: the collision in FP64 (2 % of the particles per step),
+    // rounded once; a 24-bit uniform in the Box-Muller radius or the
+    // scattering angle could put a tail draw 1e-4 off
+    double vd[3] = {v[0], v[1], v[2]};
+    collide<double>(S, id, vd, coll, capv);
+    if (coll) {
+      v[0] = (T)vd[0];
+      v[1] = (T)vd[1];
+      v[2] = (T)vd[2];
+    }
+    return;
+  }
   const uint4 r = philox4x32_10(id, *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
   if ((uint64_t)r.x >= S.T_null) return;
   T vn[3] = {(T)0, (T)0, (T)0};
@@ -368,6 +453,10 @@ __device__ __forceinline__ void collide(const SpeciesStep& S, uint32_t id, T v[3
     vn[0] = vg * n0;
     vn[1] = vg * n1;
     vn[2] = vg * n2;
+  }
+  if (S.xs_n > 0) {
+    collide_xs<T>(S, r, vn, v, coll, capv);
+    return;
   }
   const T gx = v[0] - vn[0], gy = v[1] - vn[1], gz = v[2] - vn[2];
   const T g = sqrt(gx * gx + gy * gy + gz * gz);

@@ -39,6 +39,11 @@ struct Replica {
   long long Qp = 0;
   double q[2]{}, m[2]{}, vth[2]{}, g_cap[2]{}, P_null[2]{};
   uint64_t T_null[2]{};
+  // energy-dependent cross sections: host copy [5][n] (grid, e elastic,
+  // e excitation, ion charge exchange, ion elastic), device copy, the bounds
+  std::vector<double> xs;
+  double* d_xs = nullptr;
+  double sg_max[2]{};
   double vth_gas = 0;
   long n_load = 0;     // particles per species at load
   long cap[2]{};       // slots per species buffer (a multiple of 1024)
@@ -277,6 +282,17 @@ int validate(const pic_config& c, std::string& why) {
   if (c.n_grains > 0 && !c.grain_pos) return bad("grain_pos is NULL");
   if (c.n_grains > 0 && !(c.grain_radius > 0)) return bad("grain_radius must be > 0");
   if (c.sort_interval < 0) return bad("sort_interval must be >= 0");
+  if (c.xs_n != 0) {
+    if (c.xs_n < 2 || c.xs_n > PIC_MAX_XS) return bad("xs_n must be 0 or 2..PIC_MAX_XS");
+    if (!c.xs_E || !c.xs_e_el || !c.xs_i_cx) return bad("cross-section tables missing");
+    if (!(std::isfinite(c.E_ex_eV) && c.E_ex_eV >= 0)) return bad("E_ex_eV must be >= 0");
+    for (int i = 0; i < c.xs_n; ++i) {
+      if (!(std::isfinite(c.xs_E[i]) && c.xs_E[i] >= 0) || (i > 0 && !(c.xs_E[i] > c.xs_E[i - 1])))
+        return bad("xs_E must be finite, >= 0 and increasing");
+      for (const double* t : {c.xs_e_el, c.xs_e_ex, c.xs_i_cx, c.xs_i_el})
+        if (t && !(std::isfinite(t[i]) && t[i] >= 0)) return bad("cross sections must be >= 0");
+    }
+  }
   if (c.coulomb_interval < 0) return bad("coulomb_interval must be >= 0");
   if (c.coulomb_interval > 0 && !(std::isfinite(c.coulomb_lnL) && c.coulomb_lnL > 0))
     return bad("coulomb_lnL must be > 0");
@@ -424,6 +440,10 @@ SpeciesStep species_step(const Replica& R, int sp) {
   S.vth_gas = R.vth_gas;
   S.mass_ratio_e = R.m[0] / (R.m[0] + R.m[1]);
   S.mass_ratio_n = R.m[1] / (R.m[0] + R.m[1]);
+  S.xs = R.d_xs;
+  S.xs_n = c.xs_n;
+  S.sg_max = R.sg_max[sp];
+  S.ex_g2 = 2.0 * c.E_ex_eV * kCharge / (R.m[0] * R.m[1] / (R.m[0] + R.m[1]));
   S.key0 = (uint32_t)(c.seed & 0xffffffffu);
   S.key1 = (uint32_t)(c.seed >> 32);
   S.step = R.d_step;
@@ -1020,6 +1040,43 @@ int unit_fields(pic_ctx* ctx, Replica& R) {
   return PIC_OK;
 }
 
+// sigma of column k of the [5][n] table at E (eV): linear inside the grid,
+// the end values outside
+double xs_value(const std::vector<double>& xs, int n, int k, double E) {
+  const double* x = xs.data();
+  const double* t = xs.data() + (long)k * n;
+  if (E <= x[0]) return t[0];
+  if (E >= x[n - 1]) return t[n - 1];
+  const long hi = std::upper_bound(x, x + n, E) - x;  // x[hi - 1] <= E < x[hi]
+  const double f = (E - x[hi - 1]) / (x[hi] - x[hi - 1]);
+  return t[hi - 1] + f * (t[hi] - t[hi - 1]);
+}
+
+// bound of the null-collision method: the maximum over 0 <= E <= E_cap of
+// g(E) sigma_total(E), g = sqrt(2 E e / m).  Between grid points sigma_total
+// is a + b E, and a sqrt(E) + b E^1.5 is stationary only at E = -a / (3 b);
+// past the grid sigma is constant and g increases, so the candidates are the
+// grid points, E_cap and those stationary points.
+double xs_bound(const std::vector<double>& xs, int n, int sp, double E_cap, double m) {
+  const int c0 = sp == 0 ? 1 : 3;
+  auto total = [&](double E) { return xs_value(xs, n, c0, E) + xs_value(xs, n, c0 + 1, E); };
+  auto f = [&](double E) { return total(E) * std::sqrt(2.0 * E * kCharge / m); };
+  std::vector<double> cand{0.0, E_cap};
+  for (int i = 0; i < n; ++i)
+    if (xs[i] <= E_cap) cand.push_back(xs[i]);
+  for (int i = 0; i + 1 < n; ++i) {
+    const double e0 = xs[i], e1 = xs[i + 1];
+    const double b = (total(e1) - total(e0)) / (e1 - e0), a = total(e0) - b * e0;
+    if (b < 0) {
+      const double Es = -a / (3.0 * b);
+      if (Es > e0 && Es < e1 && Es <= E_cap) cand.push_back(Es);
+    }
+  }
+  double best = 0.0;
+  for (double E : cand) best = std::max(best, f(E));
+  return best;
+}
+
 int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   std::string why;
   if (validate(cin, why) != PIC_OK) return fail(ctx, PIC_EINVAL, why);
@@ -1047,13 +1104,29 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   R.vth[0] = std::sqrt(c.Te_eV * kCharge / kMassE);
   R.vth[1] = std::sqrt(c.Ti_eV * kCharge / kMassAr);
   const double sigma[2] = {c.sigma_e_el, c.sigma_i_cx};
+  if (c.xs_n > 0) {
+    const int n = c.xs_n;
+    R.xs.assign(5L * n, 0.0);
+    const double* cols[5] = {c.xs_E, c.xs_e_el, c.xs_e_ex, c.xs_i_cx, c.xs_i_el};
+    for (int k = 0; k < 5; ++k)
+      if (cols[k]) std::copy(cols[k], cols[k] + n, R.xs.begin() + (long)k * n);
+    // the caller's arrays are not kept
+    c.xs_E = c.xs_e_el = c.xs_e_ex = c.xs_i_cx = c.xs_i_el = nullptr;
+  }
   for (int s = 0; s < 2; ++s) {
     R.g_cap[s] = std::sqrt(2.0 * c.E_cap_eV * kCharge / R.m[s]);
-    const double nu_max = R.n_gas * sigma[s] * R.g_cap[s];
+    R.sg_max[s] = c.xs_n > 0 ? xs_bound(R.xs, c.xs_n, s, c.E_cap_eV, R.m[s])
+                             : sigma[s] * R.g_cap[s];
+    const double nu_max = R.n_gas * R.sg_max[s];
     R.P_null[s] = -std::expm1(-nu_max * c.dt);
     R.T_null[s] = (uint64_t)std::floor(R.P_null[s] * 4294967296.0);
   }
   R.vth_gas = std::sqrt(kBoltz * c.T_gas_K / kMassAr);
+  if (c.xs_n > 0) {
+    TRY(dalloc(ctx, R, &R.d_xs, R.xs.size()));
+    HIPCHK(ctx, hipMemcpyAsync(R.d_xs, R.xs.data(), R.xs.size() * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+  }
   R.n_load = R.ncell * c.ppc;
   // tiles of 4x4x4 cells; each tile's slot range is padded to a multiple of 4
   R.ntiles = ((R.nx + 3) / 4) * ((R.ny + 3) / 4) * ((R.nz + 3) / 4);

@@ -97,6 +97,14 @@ struct SpeciesStep {
   double vth_gas;
   double mass_ratio_e;     // m_e / (m_e + M)
   double mass_ratio_n;     // M / (m_e + M)
+  // energy-dependent cross sections (xs_n > 0): [5][xs_n] doubles: energy
+  // grid (eV), e-Ar elastic, e-Ar excitation, Ar+-Ar charge exchange, Ar+-Ar
+  // elastic (m^2); sg_max bounds g sigma_total; an excitation needs
+  // g^2 > ex_g2 = 2 E_ex / mu and leaves g'^2 = g^2 - ex_g2
+  const double* xs;
+  int xs_n;
+  double sg_max;
+  double ex_g2;
   uint32_t key0, key1;
   const uint32_t* step;    // device: the step index k of the replica
   // deposit

@@ -51,6 +51,10 @@ class pic_config(C.Structure):
         ("seed", C.c_uint64),
         ("grain_pos", C.POINTER(C.c_double)),
         ("coulomb_interval", C.c_int32), ("reserved0", C.c_int32), ("coulomb_lnL", C.c_double),
+        ("xs_n", C.c_int32), ("reserved1", C.c_int32),
+        ("xs_E", C.POINTER(C.c_double)), ("xs_e_el", C.POINTER(C.c_double)),
+        ("xs_e_ex", C.POINTER(C.c_double)), ("xs_i_cx", C.POINTER(C.c_double)),
+        ("xs_i_el", C.POINTER(C.c_double)), ("E_ex_eV", C.c_double),
     ]
 
 
@@ -162,7 +166,20 @@ def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 2):
     c.grain_pos = g.ctypes.data_as(C.POINTER(C.c_double))
     c.coulomb_interval = int(wl.get("coulomb_interval", 0))
     c.coulomb_lnL = float(wl.get("coulomb_lnL", 10.0))
-    return c, g
+    keep = [g]
+    xs = wl.get("xs")
+    if xs:
+        # cross-section tables: a dict of E (eV) and e_el, e_ex, i_cx, i_el (m^2), E_ex (eV)
+        arrays = {k: np.ascontiguousarray(xs[k], np.float64) for k in ("E", "e_el", "e_ex", "i_cx", "i_el")
+                  if xs.get(k) is not None}
+        keep.append(arrays)
+        c.xs_n = len(arrays["E"])
+        for k, field in (("E", "xs_E"), ("e_el", "xs_e_el"), ("e_ex", "xs_e_ex"), ("i_cx", "xs_i_cx"),
+                         ("i_el", "xs_i_el")):
+            if k in arrays:
+                setattr(c, field, arrays[k].ctypes.data_as(C.POINTER(C.c_double)))
+        c.E_ex_eV = float(xs.get("E_ex", 0.0))
+    return c, keep
 
 
 def current_stream():
@@ -356,7 +373,7 @@ class Simulation:
         self.ctx = pic_init([m[0] for m in made], len(made),
                             stream if stream is not None else current_stream())
         self.n_nodes = [w["nx"] * w["ny"] * (w["nz"] + 1) for w in self.wls]
-        self.n_grains = [m[1].shape[0] for m in made]
+        self.n_grains = [m[1][0].shape[0] for m in made]
         self.capacity = [w["nx"] * w["ny"] * w["nz"] * w["ppc"] for w in self.wls]
         self.fine_nodes = [0] * len(self.wls)
 

@@ -75,7 +75,8 @@ def test_workload_configs_are_consistent():
     from paper_1801_00972_amd import workloads as W
     from paper_1801_00972_amd.pic import make_config
     for wl in (W.small_fp64(), W.small_fp32r(), W.full_fp64(), W.full_fp64("fp32r")):
-        c, g = make_config(wl)
+        c, keep = make_config(wl)
+        g = keep[0]
         assert c.n_grains == len(g)
         c3 = int(wl["cutoff"])
         for p in g:
