@@ -282,8 +282,12 @@ def _cpu_model():
     return None
 
 
-def form_workloads(form, workload, coulomb=0):
+def form_workloads(form, workload, coulomb=0, xs=False):
     wls = _form_workloads(form, workload)
+    if xs:
+        from paper_1801_00972_amd import workloads as W
+        # energy-dependent cross sections from synthetic stand-in tables
+        wls = [dict(w, xs=W.stand_in_xs()) for w in wls]
     if coulomb:
         # Coulomb collisions every `coulomb` steps, Coulomb logarithm 10
         wls = [dict(w, coulomb_interval=coulomb, coulomb_lnL=10.0) for w in wls]
@@ -315,6 +319,8 @@ def main():
                     help="sample the time averages every N steps (0: off)")
     ap.add_argument("--fine", action="store_true",
                     help="with --average: also the 200^3 grid of 0.08 dx over the grain cluster")
+    ap.add_argument("--xs", action="store_true",
+                    help="energy-dependent cross sections (synthetic stand-in tables)")
     ap.add_argument("--coulomb", type=int, default=0,
                     help="Coulomb collisions every N steps (0: off, the default workloads)")
     args = ap.parse_args()
@@ -335,7 +341,7 @@ def main():
         forms = ["fp32r"]
     results = {}
     for form in forms:
-        wls = form_workloads(form, args.workload, args.coulomb)
+        wls = form_workloads(form, args.workload, args.coulomb, args.xs)
         results[form] = run_form(wls, args.steps, args.warmup, args.sort_interval,
                                  autotune=not args.no_autotune, average=args.average,
                                  fine=args.fine and args.average > 0,
@@ -367,6 +373,7 @@ def main():
             "pp_cutoff_cells": wl["cutoff"],
             "stated_err": {"fp32r": 1e-5, "fp64": 1e-12},
             "coulomb_interval": args.coulomb,
+            "cross_section_tables": bool(args.xs),
             "average_interval": args.average,
             "fine_grid": bool(args.fine and args.average),
             "settings": R["settings"],
