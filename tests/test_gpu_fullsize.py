@@ -105,3 +105,30 @@ def test_fullsize_fields_and_sampled_step(prec):
           f"dvel={rep['max_dvel']:.2e}", flush=True)
     assert rep["n"] > 4000 and rep["flips"] <= 3
     sim.close()
+
+
+def test_fullsize_fields_after_sheath_formation():
+    """The FP32R fields on a developed state (1,300 steps: sheaths formed, grains
+    charged, the refinement residual near 2e-10 after its two sweeps) against the
+    oracle's fields of that state."""
+    from paper_1801_00972_amd.pic import PIC_E, PIC_PHI, PIC_RHO_FIXED, Simulation
+    wl = W.full_fp64("fp32r")
+    print(f"[case] {wl['name']} after 1300 steps", flush=True)
+    sim = Simulation(wl)
+    for k in range(13):
+        sim.step(100)
+        print(f"  step {(k + 1) * 100}", flush=True)
+    st = sim.get_state()
+    g = sim.fields(0, PIC_PHI | PIC_E | PIC_RHO_FIXED)
+    res = sim.counters()["refine_residual"]
+    orc = oracle.Oracle(wl)
+    for s in range(2):
+        orc.set_particles(s, st[s]["pos"], st[s]["vel"], st[s]["id"])
+    orc.set_counts(grain_count=st["grain_count"], wall_count=st["wall_count"], step=st["step"])
+    o = orc.fields(fixed_point=True)
+    assert np.array_equal(g["rho_fixed"], o["rho_fixed"])
+    e_phi = rel_inf(g["phi"], o["phi"], floor=abs(orc.rf_voltage(st["step"])))
+    e_E = rel_inf(g["E"], o["E"])
+    print(f"  residual {res:.2e}: phi {e_phi:.2e} E {e_E:.2e}", flush=True)
+    assert e_phi <= TOL["fp32r"] and e_E <= TOL["fp32r"]
+    sim.close()
