@@ -107,6 +107,9 @@ def lib():
         L.orc_xs_sgmax.restype = C.c_double
         L.orc_xs_at.argtypes = [C.POINTER(_Config), dp, C.c_double]
         L.orc_xs_at.restype = C.c_double
+        L.orc_unit_potentials.argtypes = [C.POINTER(_Config), dp]
+        L.orc_fine_phi.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp, dp, dp, C.c_double,
+                                   C.POINTER(C.c_int32), dp]
         L.orc_coulomb.argtypes = [C.POINTER(_Config), C.POINTER(_State)]
         L.orc_coulomb.restype = C.c_int64
         L.orc_coulomb_pair.argtypes = [C.POINTER(_Config), C.c_int, C.c_int, dp, dp, C.c_double,
@@ -379,6 +382,31 @@ class Oracle:
         if self._U is None:
             self._U = np.ascontiguousarray(self.unit_fields(progress))
         return self._U
+
+    def unit_potentials(self):
+        """phi of a unit (1 C) charge of each grain on its MD cube's nodes."""
+        side = 2 * int(self.cfg.cutoff) + 2
+        U = np.zeros(max(self.n_grains, 1) * side ** 3)
+        rc = lib().orc_unit_potentials(C.byref(self.cfg), _ptr(U, C.c_double))
+        if rc:
+            raise RuntimeError(f"orc_unit_potentials failed ({rc})")
+        return U
+
+    def fine_phi(self, phi, origin, h: float, cells, Uphi=None):
+        """The potential on the fine grid (see fine_moments) from the mesh
+        potential phi: interpolated, with the grains' Coulomb potential in
+        place of their unit mesh potential inside their MD cubes."""
+        phi = np.ascontiguousarray(phi, np.float64).reshape(-1)
+        U = self.unit_potentials() if Uphi is None else np.ascontiguousarray(Uphi, np.float64)
+        o = np.ascontiguousarray(origin, np.float64)
+        m = np.ascontiguousarray(cells, np.int32)
+        out = np.zeros(int(np.prod(m.astype(np.int64) + 1)))
+        rc = lib().orc_fine_phi(C.byref(self.cfg), C.byref(self.st), _ptr(phi, C.c_double),
+                                _ptr(U, C.c_double), _ptr(o, C.c_double), float(h),
+                                _ptr(m, C.c_int32), _ptr(out, C.c_double))
+        if rc:
+            raise RuntimeError(f"orc_fine_phi failed ({rc})")
+        return out
 
     def xs_sgmax(self, sp: int) -> float:
         """max over g <= g_cap of g sigma_total(E(g)) of the tables."""

@@ -630,6 +630,117 @@ int orc_unit_fields(const orc_config* c, double* U)
   return rc;
 }
 
+/* phi of a unit (1 C) grain charge on the nodes of its MD cube: [g][side^3] */
+int orc_unit_potentials(const orc_config* c, double* Uphi)
+{
+  int64_t nn = orc_n_nodes(c);
+  int side = cube_side(c);
+  int64_t cube = (int64_t)side * side * side;
+  double* rho = (double*)malloc(sizeof(double) * nn);
+  double* phi = (double*)malloc(sizeof(double) * nn);
+  if (!rho || !phi) return -2;
+  double vol = c->dx * c->dx * c->dx;
+  int rc = 0;
+  for (int g = 0; g < c->n_grains && !rc; ++g) {
+    const double* xg = &c->grain_pos[3 * g];
+    int gi = (int)floor(xg[0]), gj = (int)floor(xg[1]), gk = (int)floor(xg[2]);
+    if (gk - c->cutoff < 0 || gk + c->cutoff + 1 > c->nz) { rc = -4; break; }
+    memset(rho, 0, sizeof(double) * nn);
+    cic8 W = cic_weights(c, xg[0], xg[1], xg[2]);
+    for (int t = 0; t < 8; ++t) rho[W.node[t]] += W.w[t] / vol;
+    if ((rc = orc_poisson(c, rho, 0.0, phi))) break;
+    for (int cz = 0; cz < side; ++cz)
+      for (int cy = 0; cy < side; ++cy)
+        for (int cx = 0; cx < side; ++cx)
+          Uphi[(int64_t)g * cube + ((int64_t)cz * side + cy) * side + cx] =
+              phi[node_index(c, wrap_index(gi - c->cutoff + cx, c->nx),
+                             wrap_index(gj - c->cutoff + cy, c->ny), gk - c->cutoff + cz)];
+  }
+  free(rho);
+  free(phi);
+  return rc;
+}
+
+/* The potential on the nodes of the fine grid (the paper's MD-region grid,   */
+/* Sec. IV), in the PPPM split of Eq. (5)-(6) applied to the potential: the   */
+/* mesh potential interpolated with the cloud-in-cell weights at the node,    */
+/* plus, for every grain whose MD cube holds the node's PIC cell, Q_g times   */
+/* the bare Coulomb potential 1/(4 pi eps0 r) (r at least the grain radius:   */
+/* the conducting grain's own potential inside it) minus the grain's          */
+/* unit-charge mesh potential interpolated the same way.  A node on the upper */
+/* face of the domain belongs to the last cell.                               */
+int orc_fine_phi(const orc_config* c, const orc_state* s, const double* phi,
+                 const double* Uphi, const double origin[3], double h, const int32_t m[3],
+                 double* out)
+{
+  orc_derived d;
+  if (orc_derive(c, &d)) return -1;
+  if (!(h > 0.0) || m[0] < 1 || m[1] < 1 || m[2] < 1) return -2;
+  const int side = cube_side(c);
+  const int64_t cube = (int64_t)side * side * side;
+  const int64_t mx = m[0] + 1, my = m[1] + 1, mz = m[2] + 1;
+  int* G = (int*)malloc(sizeof(int) * (c->n_grains > 0 ? c->n_grains : 1));
+  if (!G) return -3;
+  for (int64_t kk = 0; kk < mz; ++kk)
+    for (int64_t jj = 0; jj < my; ++jj)
+      for (int64_t ii = 0; ii < mx; ++ii) {
+        const double X[3] = {origin[0] + h * (double)ii, origin[1] + h * (double)jj,
+                             origin[2] + h * (double)kk};
+        const int n3[3] = {c->nx, c->ny, c->nz};
+        int cl[3];
+        double f[3];
+        for (int a = 0; a < 3; ++a) {
+          cl[a] = (int)floor(X[a]);
+          if (cl[a] > n3[a] - 1) cl[a] = n3[a] - 1;
+          f[a] = X[a] - (double)cl[a];
+        }
+        double w[8];
+        int64_t node[8];
+        int t = 0;
+        for (int cc = 0; cc < 2; ++cc)
+          for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+              w[t] = (a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1]) * (cc ? f[2] : 1.0 - f[2]);
+              node[t] = node_index(c, wrap_index(cl[0] + a, c->nx), wrap_index(cl[1] + b, c->ny),
+                                   cl[2] + cc);
+              ++t;
+            }
+        double v = 0.0;
+        for (t = 0; t < 8; ++t) v += w[t] * phi[node[t]];
+        int nG = orc_md_grains(c, cl[0], cl[1], cl[2], G, c->n_grains);
+        for (int q = 0; q < nG; ++q) {
+          const int g = G[q];
+          const double* xg = &c->grain_pos[3 * g];
+          const int gi = (int)floor(xg[0]), gj = (int)floor(xg[1]), gk = (int)floor(xg[2]);
+          double r2 = 0.0;
+          for (int a = 0; a < 3; ++a) {
+            double dd = X[a] - xg[a];
+            if (a < 2) dd -= n3[a] * floor(dd / n3[a] + 0.5);
+            r2 += dd * dd;
+          }
+          double r = sqrt(r2) * c->dx;
+          if (r < c->grain_radius) r = c->grain_radius;
+          /* the node's CIC corners in the cube's node frame */
+          const int ox = periodic_delta(cl[0], gi, c->nx) + c->cutoff;
+          const int oy = periodic_delta(cl[1], gj, c->ny) + c->cutoff;
+          const int oz = cl[2] - gk + c->cutoff;
+          double unit = 0.0;
+          t = 0;
+          for (int cc = 0; cc < 2; ++cc)
+            for (int b = 0; b < 2; ++b)
+              for (int a = 0; a < 2; ++a) {
+                unit += w[t] * Uphi[(int64_t)g * cube + ((int64_t)(oz + cc) * side + (oy + b)) * side +
+                                    (ox + a)];
+                ++t;
+              }
+          v += grain_charge(c, &d, s, g) * (1.0 / (4.0 * O_PI * O_EPS0 * r) - unit);
+        }
+        out[(kk * my + jj) * mx + ii] = v;
+      }
+  free(G);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* particle motion                                                            */
 /* ------------------------------------------------------------------------ */

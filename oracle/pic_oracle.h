@@ -147,6 +147,14 @@ int orc_fields(const orc_config* c, const orc_state* s, double* rho, int64_t* rh
                double* phi, double* E);
 /* unit-charge mesh field of each grain on its (2c+2)^3 node cube: [g][3][(2c+2)^3] */
 int orc_unit_fields(const orc_config* c, double* U);
+/* phi of a unit (1 C) grain charge on its MD cube's nodes: [g][(2c+2)^3] */
+int orc_unit_potentials(const orc_config* c, double* Uphi);
+/* the potential on the fine grid of orc_fine_moments (the mesh potential phi
+ * interpolated, plus the grains' Coulomb potential minus their unit mesh
+ * potential, as in the PPPM field) */
+int orc_fine_phi(const orc_config* c, const orc_state* s, const double* phi,
+                 const double* Uphi, const double origin[3], double h, const int32_t m[3],
+                 double* out);
 /* grains whose MD cube contains cell (i,j,k): writes indices, returns the count */
 int orc_md_grains(const orc_config* c, int i, int j, int k, int* out, int cap);
 

@@ -119,3 +119,50 @@ def test_particles_outside_the_box_add_nothing():
     more = _oracle(wl, np.concatenate([pos, out]),
                    np.concatenate([vel, rng.normal(size=(6, 3)) * 1e5])).fine_moments(origin, h, cells)
     assert np.array_equal(base[0], more[0]) and np.array_equal(base[1], more[1])
+
+
+def test_fine_phi_without_grains_interpolates_the_mesh_potential():
+    wl = W.tiny(nx=6, ny=5, nz=7)
+    o = _oracle(wl, np.zeros((0, 3)), np.zeros((0, 3)))
+    rng = np.random.default_rng(15)
+    nn = 6 * 5 * 8
+    phi = rng.normal(size=nn)
+    grid = phi.reshape(8, 5, 6)
+    # unit cells on an integer origin: the mesh values themselves
+    f = o.fine_phi(phi, [1.0, 0.0, 2.0], 1.0, [4, 4, 5]).reshape(6, 5, 5)
+    assert np.array_equal(f, grid[2:8, 0:5, 1:6])
+    # half cells: the midpoint of an x edge is the mean of its two ends; a box up
+    # to the upper z face and across the periodic x seam
+    f = o.fine_phi(phi, [5.0, 1.0, 5.0], 0.5, [2, 2, 4]).reshape(5, 3, 3)
+    assert f[0, 0, 1] == pytest.approx(0.5 * (grid[5, 1, 5] + grid[5, 1, 0]), rel=1e-14)
+    assert f[4, 2, 2] == pytest.approx(grid[7, 2, 0], rel=1e-14)
+    assert f[2, 1, 1] == pytest.approx(np.mean([grid[6, j, i] for j in (1, 2) for i in (5, 0)]),
+                                       rel=1e-13)
+
+
+def test_fine_phi_of_a_lone_grain_is_its_coulomb_potential():
+    # one grain of frozen charge in vacuum (no plasma, both electrodes at 0 V):
+    # the mesh potential is Q times the unit potential, so inside the MD cube the
+    # fine potential is the bare Coulomb potential (outside r >= a)
+    wl = W.tiny(nx=16, ny=16, nz=20, grains=[[8.3, 7.6, 10.45]], cutoff=2, V_dc=0.0, V_rf=0.0)
+    q_e = -2.0e4
+    o = oracle.Oracle(wl, flags=oracle.FROZEN_Q, Q_frozen_e=q_e)
+    o.set_particles(0, np.zeros((0, 3)), np.zeros((0, 3)), [])
+    o.set_particles(1, np.zeros((0, 3)), np.zeros((0, 3)), [])
+    phi = o.fields()["phi"]
+    origin, h, cells = np.array([6.0, 5.2, 8.1]), 0.1, [50, 49, 48]
+    f = o.fine_phi(phi, origin, h, cells)
+    ax = [origin[a] + h * np.arange(cells[a] + 1) for a in range(3)]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    g = np.array(wl["grain_pos"][0])
+    r = np.sqrt((x - g[0]) ** 2 + (y - g[1]) ** 2 + (z - g[2]) ** 2).ravel() * wl["dx"]
+    Q = q_e * 1.602176634e-19
+    coul = Q / (4 * np.pi * 8.8541878128e-12 * np.maximum(r, wl["grain_radius"]))
+    # nodes whose cell lies in the cube (cells 6..10, 5..9, 8..12 around the grain's cell)
+    cell = [np.minimum(np.floor(v), n - 1).ravel() for v, n in ((x, 16), (y, 16), (z, 20))]
+    inside = (np.abs(cell[0] - 8) <= 2) & (np.abs(cell[1] - 7) <= 2) & (np.abs(cell[2] - 10) <= 2)
+    assert inside.sum() > 10000 and (~inside).sum() > 1000
+    scale = abs(Q) / (4 * np.pi * 8.8541878128e-12 * wl["grain_radius"])
+    assert np.max(np.abs(f[inside] - coul[inside])) <= 1e-11 * scale
+    # outside the cube: the interpolated mesh potential, which differs from bare Coulomb
+    assert np.max(np.abs(f[~inside] - coul[~inside])) > 1e-6 * scale
