@@ -63,6 +63,7 @@ extern "C" {
 #define PIC_FLUX     32u  /* double [2][3][nodes] e, Ar+; x,y,z m^-2 s^-1 */
 #define PIC_FINE_N   64u  /* double [2][fine nodes]               m^-3     */
 #define PIC_FINE_FLUX 128u /* double [2][3][fine nodes]           m^-2 s^-1 */
+#define PIC_FINE_PHI 256u /* double [fine nodes]                   V        */
 
 /*
  * One replica.  Read-only; copied by pic_init.
@@ -203,7 +204,7 @@ int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C);
  * pic_fields -- the mesh quantities at the current step k for the current
  * particle state (solving if needed): out[b] receives the quantity of the
  * b-th set bit of `what`, in the order PHI, E, RHO, RHO_FIXED, N, FLUX,
- * FINE_N, FINE_FLUX (the last two on the fine grid of pic_set_fine_grid).
+ * FINE_N, FINE_FLUX, FINE_PHI (the last three on the fine grid of pic_set_fine_grid).
  * Buffers are host pointers (out_on_device = 0, the call synchronises) or
  * device pointers on the context's device (out_on_device = 1,
  * stream-ordered).  Every array is x-fastest over the nx ny (nz+1) nodes.
@@ -237,8 +238,8 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
  *
  * pic_average_read -- the averages of bin `bin` (or over all bins for
  * bin = -1): out[b] receives the quantity of the b-th set bit of `what` (a
- * subset of PIC_PHI | PIC_N | PIC_FLUX, with PIC_FINE_N | PIC_FINE_FLUX
- * when the fine grid was sampled, layouts as in pic_fields), each the
+ * subset of PIC_PHI | PIC_N | PIC_FLUX, with PIC_FINE_N | PIC_FINE_FLUX |
+ * PIC_FINE_PHI when the fine grid was sampled, layouts as in pic_fields), each the
  * sum over samples divided by their number (zeros with no sample).
  * samples (nullable host pointer) receives that number.  Buffers as in
  * pic_fields.  Errors: PIC_EINVAL (bad replica, bin, bits or buffer),
@@ -264,13 +265,19 @@ int pic_average_read(pic_ctx* ctx, int replica, int bin, unsigned what, void* co
  * lies in [0, cells[a]) on every axis adds its cloud-in-cell weights W for
  * the 8 nodes of its fine cell; other particles add nothing.  Per species:
  * n = (w / (h dx)^3) sum W and flux = (w / (h dx)^3) sum v W, with x_k and
- * v_{k-1/2} as for PIC_N and PIC_FLUX (FP64 sums with atomics).
- * With a fine grid set, pic_fields accepts PIC_FINE_N and PIC_FINE_FLUX, and
+ * v_{k-1/2} as for PIC_N and PIC_FLUX (FP64 sums with atomics).  PIC_FINE_PHI
+ * is the potential phi_k at the fine nodes in the split of Eq. (5)-(6): the
+ * mesh potential with the node's cloud-in-cell weights (a node on the
+ * domain's upper face in the last cell), plus for every grain whose MD cube
+ * holds the node's cell Q_g (1 / (4 pi eps0 max(r, a)) - the grain's
+ * unit-charge mesh potential at the node).
+ * With a fine grid set, pic_fields accepts PIC_FINE_N, PIC_FINE_FLUX and
+ * PIC_FINE_PHI (in that order after the PIC quantities), and
  * a later pic_average also samples the fine grid, after which
  * pic_average_read accepts the same bits (their output buffers follow the
  * PIC quantities' in out[]).  Setting or removing the grid drops the fine
- * sums of earlier averaging.  Device memory: 8 doubles per fine node for
- * pic_fields, and 8 per fine node and phase bin while averaging.
+ * sums of earlier averaging.  Device memory: 9 doubles per fine node for
+ * pic_fields, and 9 per fine node and phase bin while averaging.
  * Errors: PIC_EINVAL (bad replica, h, cells, or a box outside the domain),
  * PIC_ESTATE (averaging is running: stop it with interval 0 first).
  */

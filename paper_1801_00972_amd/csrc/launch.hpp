@@ -133,6 +133,14 @@ void launch_unit_rhs(const double* gpos, int g, int nx, int ny, int nz, double s
                      hipStream_t st);
 void launch_extract_cube(const double* E, const int* gcell, int g, int c, int nx, int ny, double* U,
                          hipStream_t st);
+// phi of the unit-charge solve on grain g's MD cube into Uphi[g][(2c+2)^3]
+void launch_extract_cube_phi(const double* phi, const int* gcell, int g, int c, int nx, int ny,
+                             double* Uphi, hipStream_t st);
+// the potential on the fine grid's nodes (stored, or added to the rf-phase
+// bin of the step when avg.step is set); Uphi may be null without grains
+void launch_fine_phi(const double* phi, const MdTables& md, const double* Uphi, const FineBox& fb,
+                     int nx, int ny, int nz, double dx, double radius, double* out,
+                     const AvgBins& avg, hipStream_t st);
 void launch_efield_f64(const double* phi, double* E, int nx, int ny, int nz, double dx,
                        hipStream_t st);
 void launch_efield_f32(const double* phi, float* E, int nx, int ny, int nz, double dx,

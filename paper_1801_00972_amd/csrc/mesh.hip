@@ -804,6 +804,100 @@ __global__ void avg_out_kernel(const double* __restrict__ acc, int b0, int b1, l
   out[u] = c ? s / (double)c * (u < n_plain ? 1.0 : wv) : 0.0;
 }
 
+// phi of the unit-charge solve on grain g's MD cube: Uphi[g][side^3]
+__global__ void extract_cube_phi_kernel(const double* __restrict__ phi, const int* gcell, int g,
+                                        int c, int nx, int ny, double* __restrict__ Uphi) {
+  const int side = 2 * c + 2;
+  const long cube = (long)side * side * side;
+  const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= cube) return;
+  const int cx = (int)(l % side), cy = (int)((l / side) % side), cz = (int)(l / (side * side));
+  int i = gcell[3 * g] - c + cx, j = gcell[3 * g + 1] - c + cy;
+  const int k = gcell[3 * g + 2] - c + cz;
+  i = ((i % nx) + nx) % nx;
+  j = ((j % ny) + ny) % ny;
+  Uphi[(long)g * cube + l] = phi[i + (long)nx * (j + (long)ny * k)];
+}
+
+// The potential on the nodes of the fine grid: the mesh potential with the
+// cloud-in-cell weights of the node (a node on the domain's upper face in the
+// last cell), plus for each grain whose MD cube holds the node's cell
+// Q_g (1 / (4 pi eps0 max(r, a)) - its unit mesh potential at the node), the
+// PPPM split of the field applied to the potential.  With avg.step set the
+// value is added to the rf-phase bin's sums.
+__global__ __launch_bounds__(256) void fine_phi_kernel(const double* __restrict__ phi,
+                                                       MdTables md,
+                                                       const double* __restrict__ Uphi,
+                                                       FineBox fb, int nx, int ny, int nz,
+                                                       double dx, double radius,
+                                                       double* __restrict__ out, AvgBins avg) {
+  if (avg.step) out += avg.stride * phase_bin(*avg.step, avg.f_rf, avg.dt, avg.nbins);
+  const long u = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= fb.fn) return;
+  const long ii = u % fb.mx, jj = (u / fb.mx) % fb.my, kk = u / (fb.mx * fb.my);
+  const double X[3] = {fb.o[0] + fb.h * (double)ii, fb.o[1] + fb.h * (double)jj,
+                       fb.o[2] + fb.h * (double)kk};
+  const int n3[3] = {nx, ny, nz};
+  int cl[3];
+  double f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cl[a] = (int)floor(X[a]);
+    if (cl[a] > n3[a] - 1) cl[a] = n3[a] - 1;
+    f[a] = X[a] - (double)cl[a];
+  }
+  const int i1 = cl[0] + 1 == nx ? 0 : cl[0] + 1, j1 = cl[1] + 1 == ny ? 0 : cl[1] + 1;
+  double w[8];
+  double v = 0.0;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int a = t & 1, b = (t >> 1) & 1, cc = t >> 2;
+    w[t] = (a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1]) * (cc ? f[2] : 1.0 - f[2]);
+    v += w[t] * phi[(a ? i1 : cl[0]) + (long)nx * ((b ? j1 : cl[1]) + (long)ny * (cl[2] + cc))];
+  }
+  if (md.n_grains > 0) {
+    // the periodic bounding box of the cubes: which grains' cubes hold this cell
+    int bx = cl[0] - md.bx0, by = cl[1] - md.by0;
+    const int bz = cl[2] - md.bz0;
+    if (bx < 0) bx += nx;
+    if (by < 0) by += ny;
+    if (bx < md.bsx && by < md.bsy && bz >= 0 && bz < md.bsz) {
+      const uint32_t e = md.cell_list[((long)bz * md.bsy + by) * md.bsx + bx];
+      const int first = (int)(e >> 8), cnt = (int)(e & 255u);
+      const int c = md.cutoff, side = md.side;
+      const long cube = (long)side * side * side;
+      for (int q = 0; q < cnt; ++q) {
+        const int g = md.grain_idx[first + q];
+        double r2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          double dd = X[a] - md.gpos[3 * g + a];
+          if (a < 2) dd -= (double)n3[a] * floor(dd / (double)n3[a] + 0.5);
+          r2 += dd * dd;
+        }
+        double r = sqrt(r2) * dx;
+        if (r < radius) r = radius;
+        // the node's corners in the cube's node frame
+        int ox = cl[0] - md.gcell[3 * g], oy = cl[1] - md.gcell[3 * g + 1];
+        ox -= nx * (int)floor((double)ox / nx + 0.5);
+        oy -= ny * (int)floor((double)oy / ny + 0.5);
+        ox += c;
+        oy += c;
+        const int oz = cl[2] - md.gcell[3 * g + 2] + c;
+        double unit = 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int a = t & 1, b = (t >> 1) & 1, cc = t >> 2;
+          unit += w[t] * Uphi[(long)g * cube + ((long)(oz + cc) * side + (oy + b)) * side + (ox + a)];
+        }
+        v += md.Q[g] * (1.0 / (4.0 * kPi * kEps0 * r) - unit);
+      }
+    }
+  }
+  if (avg.step) out[u] += v;
+  else out[u] = v;
+}
+
 __global__ void zero_f64_kernel(double* a, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = 0.0;
@@ -1055,6 +1149,21 @@ void launch_avg_out(const double* acc, int b0, int b1, long stride, long total, 
   if (total <= 0) return;
   hipLaunchKernelGGL(avg_out_kernel, dim3(nb256(total)), dim3(256), 0, st, acc, b0, b1, stride,
                      total, n_plain, cnt, wv, out);
+}
+
+void launch_extract_cube_phi(const double* phi, const int* gcell, int g, int c, int nx, int ny,
+                             double* Uphi, hipStream_t st) {
+  const long side = 2 * c + 2, cube = side * side * side;
+  hipLaunchKernelGGL(extract_cube_phi_kernel, dim3(nb256(cube)), dim3(256), 0, st, phi, gcell, g, c,
+                     nx, ny, Uphi);
+}
+
+void launch_fine_phi(const double* phi, const MdTables& md, const double* Uphi, const FineBox& fb,
+                     int nx, int ny, int nz, double dx, double radius, double* out,
+                     const AvgBins& avg, hipStream_t st) {
+  if (fb.fn <= 0) return;
+  hipLaunchKernelGGL(fine_phi_kernel, dim3(nb256(fb.fn)), dim3(256), 0, st, phi, md, Uphi, fb, nx, ny,
+                     nz, dx, radius, out, avg);
 }
 
 void launch_zero_f64(double* a, long n, hipStream_t st) {

@@ -85,6 +85,8 @@ struct Replica {
   bool fine_on = false, fine_avg_on = false;
   FineBox fine{};
   double* fine_mom = nullptr;
+  double* fine_phi = nullptr;  // [fn] the potential for pic_fields
+  double* Uphi = nullptr;      // [g][side^3] unit-charge potentials on the MD cubes
   double* fine_avg = nullptr;
   int fine_cap = 0;
   double* fine_out = nullptr;
@@ -675,8 +677,11 @@ int enqueue_sample(pic_ctx* ctx, Replica& R) {
       launch_moments(nullptr, &R.p32[sp][R.cur[sp]], S, R.lists[sp], m, R.nn, ab, st);
   }
   if (R.fine_avg_on) {
-    const AvgBins fb{R.d_step, R.cfg.f_rf, R.cfg.dt, ctx->avg_bins, 8 * R.fine.fn};
-    TRY(enqueue_fine(ctx, R, R.fine_avg, fb));
+    // per bin: the potential, then W and v W per species (9 fine-node arrays)
+    const AvgBins fb{R.d_step, R.cfg.f_rf, R.cfg.dt, ctx->avg_bins, 9 * R.fine.fn};
+    launch_fine_phi(R.phi, R.md, R.Uphi, R.fine, R.nx, R.ny, R.nz, R.cfg.dx, R.cfg.grain_radius,
+                    R.fine_avg, fb, ctx->stream);
+    TRY(enqueue_fine(ctx, R, R.fine_avg + R.fine.fn, fb));
   }
   CHECK_LAUNCH(ctx);
   return PIC_OK;
@@ -1026,11 +1031,14 @@ int unit_fields(pic_ctx* ctx, Replica& R) {
     TRY(dalloc(ctx, R, &E, 2 * 2 * R.nn));
   }
   const double scale = -c.dx * c.dx / kEps0 / (c.dx * c.dx * c.dx);
+  const long side = 2L * c.pp_cutoff_cells + 2;
+  TRY(dalloc(ctx, R, &R.Uphi, (size_t)ng * side * side * side));
   for (int g = 0; g < ng; ++g) {
     launch_zero_f64(R.b, R.n_int, st);
     launch_unit_rhs(R.md.gpos, g, R.nx, R.ny, R.nz, scale, R.b, st);
     launch_solve_f64(R.fft, R.nx, R.ny, R.nz, R.b, work, tw_x, tw_y, inv, R.phi,
                      RfDrive{0.0, 0.0, 0.0, 0.0, R.d_step}, st);
+    launch_extract_cube_phi(R.phi, R.md.gcell, g, c.pp_cutoff_cells, R.nx, R.ny, R.Uphi, st);
     launch_efield_f64(R.phi, E, R.nx, R.ny, R.nz, c.dx, st);
     launch_extract_cube(E, R.md.gcell, g, c.pp_cutoff_cells, R.nx, R.ny,
                         const_cast<double*>(R.md.U), st);
@@ -1293,10 +1301,10 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
   if (ctx->sticky) return ctx->sticky;
   Replica* R = get_rep(ctx, replica);
   if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
-  if (!out || (what & ~255u)) return fail(ctx, PIC_EINVAL, "bad selection or out");
+  if (!out || (what & ~511u)) return fail(ctx, PIC_EINVAL, "bad selection or out");
   if ((what & PIC_RHO_FIXED) && R->prec != PIC_FP32R)
     return fail(ctx, PIC_EINVAL, "PIC_RHO_FIXED needs the FP32R form");
-  if ((what & (PIC_FINE_N | PIC_FINE_FLUX)) && !R->fine_on)
+  if ((what & (PIC_FINE_N | PIC_FINE_FLUX | PIC_FINE_PHI)) && !R->fine_on)
     return fail(ctx, PIC_ESTATE, "no fine grid: call pic_set_fine_grid");
   hipStream_t st = ctx->stream;
   TRY(solve_fields(ctx, *R));
@@ -1330,11 +1338,19 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
     launch_scale(R->fine_mom, nullptr, R->w / (hdx * hdx * hdx), R->fine_mom, 8 * fn, st);
     CHECK_LAUNCH(ctx);
   }
-  for (unsigned bit = 1; bit <= PIC_FINE_FLUX; bit <<= 1) {
+  if (what & PIC_FINE_PHI) {
+    if (!R->fine_phi) TRY(dalloc(ctx, *R, &R->fine_phi, fn));
+    launch_fine_phi(R->phi, R->md, R->Uphi, R->fine, R->nx, R->ny, R->nz, R->cfg.dx,
+                    R->cfg.grain_radius, R->fine_phi, AvgBins{}, st);
+    CHECK_LAUNCH(ctx);
+  }
+  for (unsigned bit = 1; bit <= PIC_FINE_PHI; bit <<= 1) {
     if (!(what & bit)) continue;
     void* dst = out[slot++];
     if (!dst) return fail(ctx, PIC_EINVAL, "NULL output buffer");
-    if (bit == PIC_FINE_N || bit == PIC_FINE_FLUX) {
+    if (bit == PIC_FINE_PHI) {
+      HIPCHK(ctx, hipMemcpyAsync(dst, R->fine_phi, fn * 8, kind, st));
+    } else if (bit == PIC_FINE_N || bit == PIC_FINE_FLUX) {
       const long len = bit == PIC_FINE_FLUX ? 3 * fn : fn;
       for (int sp = 0; sp < 2; ++sp)
         HIPCHK(ctx, hipMemcpyAsync((char*)dst + sp * len * 8,
@@ -1400,10 +1416,10 @@ int pic_average(pic_ctx* ctx, int interval, int phase_bins) {
       if (R->fine_cap < phase_bins) {
         dfree(*R, R->fine_avg);
         R->fine_cap = 0;
-        TRY(dalloc(ctx, *R, &R->fine_avg, (size_t)8 * fn * phase_bins));
+        TRY(dalloc(ctx, *R, &R->fine_avg, (size_t)9 * fn * phase_bins));
         R->fine_cap = phase_bins;
       }
-      launch_zero_f64(R->fine_avg, 8 * fn * phase_bins, st);
+      launch_zero_f64(R->fine_avg, 9 * fn * phase_bins, st);
     }
   }
   CHECK_LAUNCH(ctx);
@@ -1421,9 +1437,10 @@ int pic_average_read(pic_ctx* ctx, int replica, int bin, unsigned what, void* co
   Replica* R = get_rep(ctx, replica);
   if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
   if (!R->avg || ctx->avg_bins == 0) return fail(ctx, PIC_ESTATE, "no averages: call pic_average");
-  if ((what & ~(PIC_PHI | PIC_N | PIC_FLUX | PIC_FINE_N | PIC_FINE_FLUX)) || (what && !out))
+  const unsigned fine_bits = PIC_FINE_N | PIC_FINE_FLUX | PIC_FINE_PHI;
+  if ((what & ~(PIC_PHI | PIC_N | PIC_FLUX | fine_bits)) || (what && !out))
     return fail(ctx, PIC_EINVAL, "bad selection or out");
-  if ((what & (PIC_FINE_N | PIC_FINE_FLUX)) && !R->fine_avg_on)
+  if ((what & fine_bits) && !R->fine_avg_on)
     return fail(ctx, PIC_ESTATE, "no fine-grid averages: set the fine grid before pic_average");
   if (bin < -1 || bin >= ctx->avg_bins) return fail(ctx, PIC_EINVAL, "bad bin");
   hipStream_t st = ctx->stream;
@@ -1433,24 +1450,28 @@ int pic_average_read(pic_ctx* ctx, int replica, int bin, unsigned what, void* co
   const double vol = R->cfg.dx * R->cfg.dx * R->cfg.dx;
   launch_avg_out(R->avg, b0, b1, 9 * nn, 9 * nn, nn, R->d_avg_cnt, R->w / vol, R->avg_out, st);
   const long fn = R->fine.fn;
-  if (what & (PIC_FINE_N | PIC_FINE_FLUX)) {
-    if (!R->fine_out) TRY(dalloc(ctx, *R, &R->fine_out, 8 * fn));
+  if (what & fine_bits) {
+    if (!R->fine_out) TRY(dalloc(ctx, *R, &R->fine_out, 9 * fn));
     const double hdx = R->fine.h * R->cfg.dx;
-    launch_avg_out(R->fine_avg, b0, b1, 8 * fn, 8 * fn, 0, R->d_avg_cnt, R->w / (hdx * hdx * hdx),
+    launch_avg_out(R->fine_avg, b0, b1, 9 * fn, 9 * fn, fn, R->d_avg_cnt, R->w / (hdx * hdx * hdx),
                    R->fine_out, st);
   }
   CHECK_LAUNCH(ctx);
   const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   int slot = 0;
-  for (unsigned bit : {PIC_PHI, PIC_N, PIC_FLUX, PIC_FINE_N, PIC_FINE_FLUX}) {
+  for (unsigned bit : {PIC_PHI, PIC_N, PIC_FLUX, PIC_FINE_N, PIC_FINE_FLUX, PIC_FINE_PHI}) {
     if (!(what & bit)) continue;
     char* dst = (char*)out[slot++];
     if (!dst) return fail(ctx, PIC_EINVAL, "NULL output buffer");
+    if (bit == PIC_FINE_PHI) {
+      HIPCHK(ctx, hipMemcpyAsync(dst, R->fine_out, fn * 8, kind, st));
+      continue;
+    }
     if (bit == PIC_FINE_N || bit == PIC_FINE_FLUX) {
       const long len = bit == PIC_FINE_FLUX ? 3 * fn : fn;
       for (int sp = 0; sp < 2; ++sp)
         HIPCHK(ctx, hipMemcpyAsync(dst + sp * len * 8,
-                                   R->fine_out + (4 * sp + (bit == PIC_FINE_FLUX ? 1 : 0)) * fn,
+                                   R->fine_out + fn + (4 * sp + (bit == PIC_FINE_FLUX ? 1 : 0)) * fn,
                                    len * 8, kind, st));
       continue;
     }
@@ -1505,6 +1526,7 @@ int pic_set_fine_grid(pic_ctx* ctx, int replica, const pic_fine_grid* g) {
   }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   dfree(*R, R->fine_mom);
+  dfree(*R, R->fine_phi);
   dfree(*R, R->fine_avg);
   dfree(*R, R->fine_out);
   R->fine_cap = 0;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 PIC_OK, PIC_EINVAL, PIC_ECONFIG, PIC_ENOMEM, PIC_EDEVICE, PIC_ENUMERIC, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PIC_FP64, PIC_FP32R = 0, 1
 PIC_PHI, PIC_E, PIC_RHO, PIC_RHO_FIXED, PIC_N, PIC_FLUX = 1, 2, 4, 8, 16, 32
-PIC_FINE_N, PIC_FINE_FLUX = 64, 128
+PIC_FINE_N, PIC_FINE_FLUX, PIC_FINE_PHI = 64, 128, 256
 PIC_MAX_FINE_NODES = 1 << 26
 
 SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destroy",
@@ -390,7 +390,8 @@ class Simulation:
                                      (PIC_N, "n", (2, nn), np.float64),
                                      (PIC_FLUX, "flux", (2, 3, nn), np.float64),
                                      (PIC_FINE_N, "fine_n", (2, fn), np.float64),
-                                     (PIC_FINE_FLUX, "fine_flux", (2, 3, fn), np.float64)):
+                                     (PIC_FINE_FLUX, "fine_flux", (2, 3, fn), np.float64),
+                                     (PIC_FINE_PHI, "fine_phi", (fn,), np.float64)):
             if what & bit:
                 outs.append(np.zeros(shape, dt))
                 names.append(name)
@@ -413,7 +414,8 @@ class Simulation:
         outs, names = [], []
         for bit, name, shape in ((PIC_PHI, "phi", (nn,)), (PIC_N, "n", (2, nn)),
                                  (PIC_FLUX, "flux", (2, 3, nn)), (PIC_FINE_N, "fine_n", (2, fn)),
-                                 (PIC_FINE_FLUX, "fine_flux", (2, 3, fn))):
+                                 (PIC_FINE_FLUX, "fine_flux", (2, 3, fn)),
+                                 (PIC_FINE_PHI, "fine_phi", (fn,))):
             if what & bit:
                 outs.append(np.zeros(shape))
                 names.append(name)

@@ -45,7 +45,8 @@ FINE = [((7.0, 7.0, 15.0), 0.08, (25, 25, 25)), ((0.0, 8.0, 7.0), 0.5, (8, 4, 5)
     ("fp64", 1, 2, 3, 0), ("fp32r", 1, 3, 4, 1), ("fp32r", 0, 1, 2, 0), ("fp64", 0, 1, 2, 1),
     ("batched", 1, 2, 3, 1)])
 def test_averages_match_oracle(form, graphs, interval, bins, fine):
-    from paper_1801_00972_amd.pic import PIC_FINE_FLUX, PIC_FINE_N, PIC_FLUX, PIC_N, PIC_PHI, Simulation
+    from paper_1801_00972_amd.pic import (PIC_FINE_FLUX, PIC_FINE_N, PIC_FINE_PHI, PIC_FLUX, PIC_N,
+                                          PIC_PHI, Simulation)
     wls = _wls(form)
     prec = wls[0]["precision"]
     print(f"[case] {form} graphs={graphs} interval={interval} bins={bins} fine={fine}", flush=True)
@@ -57,10 +58,10 @@ def test_averages_match_oracle(form, graphs, interval, bins, fine):
     if fine:
         for r in range(R):
             sim.set_fine_grid(*FINE[r], replica=r)
-    what = PIC_PHI | PIC_N | PIC_FLUX | ((PIC_FINE_N | PIC_FINE_FLUX) if fine else 0)
+    what = PIC_PHI | PIC_N | PIC_FLUX | ((PIC_FINE_N | PIC_FINE_FLUX | PIC_FINE_PHI) if fine else 0)
     sim.step(2)
     sim.average(interval, bins)
-    acc = [[dict(phi=0.0, n=0.0, flux=0.0, fine_n=0.0, fine_flux=0.0, count=0, V=0.0)
+    acc = [[dict(phi=0.0, n=0.0, flux=0.0, fine_n=0.0, fine_flux=0.0, fine_phi=0.0, count=0, V=0.0)
             for _ in range(bins)] for _ in range(R)]
     for s in range(13):
         if s % interval == 0:
@@ -77,16 +78,17 @@ def test_averages_match_oracle(form, graphs, interval, bins, fine):
                     fn_, ff_ = orc.fine_moments(*FINE[r])
                     a["fine_n"] = a["fine_n"] + fn_
                     a["fine_flux"] = a["fine_flux"] + ff_
+                    a["fine_phi"] = a["fine_phi"] + orc.fine_phi(f["phi"], *FINE[r])
                 a["count"] += 1
                 a["V"] = max(a["V"], abs(orc.rf_voltage(st["step"])))
         sim.step(1)
     for r in range(R):
-        total = dict(phi=0.0, n=0.0, flux=0.0, fine_n=0.0, fine_flux=0.0, count=0, V=0.0)
+        total = dict(phi=0.0, n=0.0, flux=0.0, fine_n=0.0, fine_flux=0.0, fine_phi=0.0, count=0, V=0.0)
         for b in range(bins):
             a = acc[r][b]
             g = sim.averages(r, b, what=what)
             assert g["samples"] == a["count"]
-            for k in ("phi", "n", "flux", "fine_n", "fine_flux"):
+            for k in ("phi", "n", "flux", "fine_n", "fine_flux", "fine_phi"):
                 total[k] = total[k] + a[k]
             total["count"] += a["count"]
             total["V"] = max(total["V"], a["V"])
@@ -102,8 +104,10 @@ def test_averages_match_oracle(form, graphs, interval, bins, fine):
             if fine:
                 e_fn = rel_inf(g["fine_n"], a["fine_n"] / a["count"])
                 e_ff = rel_inf(g["fine_flux"], a["fine_flux"] / a["count"])
-                print(f"    fine grid: n {e_fn:.2e} flux {e_ff:.2e}", flush=True)
+                e_fp = rel_inf(g["fine_phi"], a["fine_phi"] / a["count"], floor=a["V"])
+                print(f"    fine grid: n {e_fn:.2e} flux {e_ff:.2e} phi {e_fp:.2e}", flush=True)
                 assert np.any(a["fine_n"]) and e_fn <= 1e-12 and e_ff <= 1e-12
+                assert e_fp <= FIELD_TOL[prec]
         g = sim.averages(r, -1, what=what)
         assert g["samples"] == total["count"] == len(range(0, 13, interval))
         assert rel_inf(g["n"], total["n"] / total["count"]) <= 1e-12
@@ -111,6 +115,8 @@ def test_averages_match_oracle(form, graphs, interval, bins, fine):
         if fine:
             assert rel_inf(g["fine_n"], total["fine_n"] / total["count"]) <= 1e-12
             assert rel_inf(g["fine_flux"], total["fine_flux"] / total["count"]) <= 1e-12
+            assert rel_inf(g["fine_phi"], total["fine_phi"] / total["count"],
+                           floor=total["V"]) <= FIELD_TOL[prec]
     # stopped: the sums stay as they are
     sim.average(0)
     sim.step(3)

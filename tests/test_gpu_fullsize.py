@@ -73,18 +73,20 @@ def test_fullsize_fields_and_sampled_step(prec):
     assert e_n <= 1e-12 and e_f <= 1e-12
     del gm, n_o, flux_o
     # the fine grid of 200^3 cells of 0.08 dx over the grain cluster
-    from paper_1801_00972_amd.pic import PIC_FINE_FLUX, PIC_FINE_N
+    from paper_1801_00972_amd.pic import PIC_FINE_FLUX, PIC_FINE_N, PIC_FINE_PHI
     h, cells = 0.08, (200, 200, 200)
     centre = np.asarray(wl["grain_pos"]).mean(axis=0)
     origin = np.clip(np.floor(centre - 8.0), 0, [wl["nx"] - 16, wl["ny"] - 16, wl["nz"] - 16])
     sim.set_fine_grid(origin, h, cells)
-    gf = sim.fields(0, PIC_FINE_N | PIC_FINE_FLUX)
+    gf = sim.fields(0, PIC_FINE_N | PIC_FINE_FLUX | PIC_FINE_PHI)
     fn_o, ff_o = orc.fine_moments(origin, h, cells)
     e_n, e_f = rel_inf(gf["fine_n"], fn_o), rel_inf(gf["fine_flux"], ff_o)
-    print(f"  fine grid at {origin}: n {e_n:.2e} flux {e_f:.2e}", flush=True)
-    assert np.any(fn_o) and e_n <= 1e-12 and e_f <= 1e-12
+    fp_o = orc.fine_phi(o["phi"], origin, h, cells)
+    e_p = rel_inf(gf["fine_phi"], fp_o, floor=abs(orc.rf_voltage(st["step"])))
+    print(f"  fine grid at {origin}: n {e_n:.2e} flux {e_f:.2e} phi {e_p:.2e}", flush=True)
+    assert np.any(fn_o) and e_n <= 1e-12 and e_f <= 1e-12 and e_p <= TOL[prec]
     sim.set_fine_grid(None)
-    del gf, fn_o, ff_o
+    del gf, fn_o, ff_o, fp_o
     # one step of a sample, moved by the oracle in its own field
     rng = np.random.default_rng(11)
     small = oracle.Oracle(wl)

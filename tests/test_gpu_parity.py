@@ -208,7 +208,7 @@ def test_fine_grid_moments(prec, box):
     spans x and touches both electrodes, and unit cells off the PIC nodes;
     particles drift out of their tiles (no re-binning).  The number of
     particles inside the box is exact."""
-    from paper_1801_00972_amd.pic import PIC_FINE_FLUX, PIC_FINE_N
+    from paper_1801_00972_amd.pic import PIC_FINE_FLUX, PIC_FINE_N, PIC_FINE_PHI
     origin, h, cells = {"grain": ((7.0, 7.0, 15.0), 0.08, (25, 25, 25)),
                         "ragged": ((0.0, 3.25, 0.0), 0.5, (32, 17, 64)),
                         "unit": ((2.5, 3.25, 4.75), 1.0, (10, 9, 20))}[box]
@@ -221,9 +221,14 @@ def test_fine_grid_moments(prec, box):
     for seg in range(2):
         sim.step(3)
         st = sim.get_state()
-        n, flux = oracle_from_state(wl, st).fine_moments(origin, h, cells)
-        g = sim.fields(0, PIC_FINE_N | PIC_FINE_FLUX)
+        orc = oracle_from_state(wl, st)
+        n, flux = orc.fine_moments(origin, h, cells)
+        phi_o = orc.fine_phi(orc.fields(fixed_point=prec == "fp32r")["phi"], origin, h, cells)
+        g = sim.fields(0, PIC_FINE_N | PIC_FINE_FLUX | PIC_FINE_PHI)
         e_n, e_f = rel_inf(g["fine_n"], n), rel_inf(g["fine_flux"], flux)
+        e_p = rel_inf(g["fine_phi"], phi_o, floor=abs(orc.rf_voltage(st["step"])))
+        print(f"  fine phi {e_p:.2e}", flush=True)
+        assert e_p <= (1e-12 if prec == "fp64" else 1e-5)
         inside = [int(_inside(st[s]["pos"], origin, h, cells).sum()) for s in range(2)]
         print(f"  step {st['step']}: {inside} particles inside, n {e_n:.2e} flux {e_f:.2e}", flush=True)
         assert min(inside) > 0
