@@ -134,3 +134,76 @@ def test_fullsize_fields_after_sheath_formation():
     print(f"  residual {res:.2e}: phi {e_phi:.2e} E {e_E:.2e}", flush=True)
     assert e_phi <= TOL["fp32r"] and e_E <= TOL["fp32r"]
     sim.close()
+
+
+def _pairings(cells_e, cells_i, ncell):
+    """Binary collisions of one Coulomb pass by the pairing rule, from the cells."""
+    ne, ni = np.bincount(cells_e, minlength=ncell), np.bincount(cells_i, minlength=ncell)
+    total = 0
+    for n in (ne, ni):
+        odd = (n >= 3) & (n % 2 == 1)
+        total += int(np.sum(np.where(odd, 3 + (n - 3) // 2, np.where(n >= 2, n // 2, 0))))
+    return total + int(np.sum(np.where((ne > 0) & (ni > 0), np.maximum(ne, ni), 0)))
+
+
+def test_fullsize_coulomb_and_cross_section_tables():
+    """A step at the benchmark's full size with Coulomb collisions and the
+    synthetic cross-section tables.  A pass pairs the particles of each cell
+    only, so the oracle runs it on 16 whole z-planes around the grains; a
+    sample of those particles, with their post-pass velocities, is then moved
+    by the oracle in the full state's field and compared with the GPU step.
+    The GPU's pairing count over the whole box equals the pairing rule's
+    count from the cells.  A large Coulomb logarithm makes the pass turn
+    velocities visibly at the FP32R tolerance."""
+    from paper_1801_00972_amd.pic import Simulation
+    wl = dict(W.full_fp64("fp32r"), coulomb_interval=1, coulomb_lnL=1.0e6, xs=W.stand_in_xs())
+    print(f"[case] {wl['name']} with Coulomb collisions and cross-section tables", flush=True)
+    sim = Simulation(wl)
+    sim.step(3)
+    st = sim.get_state()
+    c0 = sim.counters()["n_coulomb"]
+    nx, ny, nz = wl["nx"], wl["ny"], wl["nz"]
+    cells = [(np.floor(st[s]["pos"]).astype(np.int64) * [1, nx, nx * ny]).sum(axis=1) for s in range(2)]
+    full = oracle.Oracle(wl)
+    for s in range(2):
+        full.set_particles(s, st[s]["pos"], st[s]["vel"], st[s]["id"])
+    full.set_counts(grain_count=st["grain_count"], wall_count=st["wall_count"], step=st["step"])
+    E = full.fields(fixed_point=True)["E"]
+    del full
+    print("  oracle fields done", flush=True)
+    # 16 whole z-planes around the grains
+    z0 = int(np.floor(np.asarray(wl["grain_pos"])[:, 2].mean())) - 8
+    sub = oracle.Oracle(wl)
+    rows = []
+    for s in range(2):
+        r = np.flatnonzero((st[s]["pos"][:, 2] >= z0) & (st[s]["pos"][:, 2] < z0 + 16))
+        rows.append(r)
+        sub.set_particles(s, st[s]["pos"][r].copy(), st[s]["vel"][r].copy(), st[s]["id"][r])
+    sub.set_counts(grain_count=st["grain_count"], step=st["step"])
+    pairs_sub = sub.coulomb()
+    sub_cells = [cells[s][rows[s]] for s in range(2)]
+    assert pairs_sub == _pairings(sub_cells[0], sub_cells[1], nx * ny * nz)
+    print(f"  oracle Coulomb pass on planes {z0}..{z0 + 15}: {pairs_sub} pairings", flush=True)
+    changed = sum(int(np.count_nonzero(np.any(sub.vel[s] != st[s]["vel"][rows[s]], axis=1)))
+                  for s in range(2))
+    rng = np.random.default_rng(12)
+    small = oracle.Oracle(dict(wl, coulomb_interval=0))
+    for s in range(2):
+        idx = _select(sub.pos[s], wl["grain_pos"], nz, rng)
+        small.set_particles(s, sub.pos[s][idx], sub.vel[s][idx], sub.id[s][idx])
+    small.set_counts(grain_count=st["grain_count"], step=st["step"])
+    small.step_in_field(E)
+    sim.step(1)
+    after = sim.get_state()
+    assert sim.counters()["n_coulomb"] - c0 == _pairings(cells[0], cells[1], nx * ny * nz)
+    gsub = {}
+    for s in range(2):
+        keep = np.isin(after[s]["id"], small.id[s])
+        gsub[s] = {k: after[s][k][keep] for k in ("pos", "vel", "id")}
+    rep = compare_step(wl, gsub, small, TOL["fp32r"], TOL["fp32r"], TOL["fp32r"])
+    print(f"  sampled step: n={rep['n']} flips={rep['flips']} dpos={rep['max_dpos']:.2e} "
+          f"dvel={rep['max_dvel']:.2e}; the pass changed {changed} of "
+          f"{len(rows[0]) + len(rows[1])} velocities", flush=True)
+    assert changed > 0.5 * (len(rows[0]) + len(rows[1]))
+    assert rep["n"] > 3000 and rep["flips"] <= 3
+    sim.close()
