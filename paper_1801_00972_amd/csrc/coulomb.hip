@@ -3,20 +3,24 @@
 // the paper cites with its collision set.
 //
 // One pass, at the start of every interval-th step on (x_k, v_{k-1/2}):
-//  1. count the alive particles of each species per cell and scan the counts
-//     into per-cell ranges;
+//  1. count the alive particles of each species per cell (cells numbered in
+//     the tile order of the particle bins) and scan the counts into per-cell
+//     ranges;
 //  2. scatter (order key, slot) of every particle into its cell's range; the
 //     key is the particle's Philox word (id, k, order purpose, species) above
 //     its id, so the order inside a cell does not depend on the scatter's
 //     atomics;
-//  3. one wave per block strides over the cells: it stages a cell's keys,
-//     slots, ids and velocities in LDS, ranks each species by key, then runs
-//     the like pairs (e-e and Ar+-Ar+, pairs in parallel, an odd count's
-//     triplet on lane 0), a barrier, and the unlike pairs (one lane per
-//     particle of the less numerous species, its partners in order), all in
-//     FP64, and writes the velocities back once; cells with more particles
-//     than the stage holds run the same rule through global memory.
-// Counting and scattering take one atomic per run of equal cells in a wave.
+//  3. one wave per block strides over pairs of cells, a half-wave per cell:
+//     each half stages its cell's keys, slots, ids and velocities in LDS,
+//     ranks each species by key, then runs the like items (e-e and Ar+-Ar+
+//     pairs, an odd count's triplet as one item) over its 32 lanes, a
+//     barrier, and the unlike pairs (one lane per particle of the less
+//     numerous species, its partners in order), all in FP64, and writes the
+//     velocities back once; a pair of cells with a species above the stage's
+//     64 runs both cells in turn through global memory with the whole wave.
+// Counting and scattering go a block per tile of the particle bins: an LDS
+// histogram and one global atomic per cell, one more per particle that has
+// left its tile since the last binning.
 // The collisions of one pass touch disjoint particles except where the
 // pairing rule orders them, so this is the sequential pass of the rule.
 #include <hip/hip_runtime.h>
@@ -39,14 +43,20 @@ inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 __device__ __forceinline__ bool alive(const PartF64& P, long p) { return P.z[p] >= 0.0; }
 __device__ __forceinline__ bool alive(const PartF32R& P, long p) { return P.cell[p] >= 0; }
 
-// linear cell index (i + nx (j + ny k)) of an alive particle
-__device__ __forceinline__ int cell_of(const PartF64& P, long p, int nx, int ny) {
-  const int i = (int)floor(P.x[p]), j = (int)floor(P.y[p]), k = (int)floor(P.z[p]);
-  return i + nx * (j + ny * k);
+// Cells are numbered in tile order: tile (i/4 + ntx (j/4 + nty k/4)), the
+// tile order of the particle bins, times 64 plus the cell inside its tile
+// (x fastest); cells of a tile past the box edge stay empty.  -1: not alive.
+__device__ __forceinline__ int tiled_cell(int i, int j, int k, int ntx, int nty) {
+  return (((k >> 2) * nty + (j >> 2)) * ntx + (i >> 2)) * 64 + ((k & 3) * 4 + (j & 3)) * 4 + (i & 3);
 }
-__device__ __forceinline__ int cell_of(const PartF32R& P, long p, int nx, int ny) {
+__device__ __forceinline__ int coul_cell(const PartF64& P, long p, int ntx, int nty) {
+  if (!(P.z[p] >= 0.0)) return -1;
+  return tiled_cell((int)floor(P.x[p]), (int)floor(P.y[p]), (int)floor(P.z[p]), ntx, nty);
+}
+__device__ __forceinline__ int coul_cell(const PartF32R& P, long p, int ntx, int nty) {
   const int c = P.cell[p];
-  return (c & 1023) + nx * (((c >> 10) & 1023) + ny * (c >> 20));
+  if (c < 0) return -1;
+  return tiled_cell(c & 1023, (c >> 10) & 1023, c >> 20, ntx, nty);
 }
 
 __device__ __forceinline__ void load_v(const PartF64& P, long p, double v[3]) {
@@ -70,37 +80,28 @@ __device__ __forceinline__ void store_v(const PartF32R& P, long p, const double 
   P.vz[p] = (float)v[2];
 }
 
-// Runs of equal cells in consecutive lanes of a wave (the slots are grouped
-// by tile and by cell after a re-binning): each lane learns its run's first
-// lane; the first lane also the run's length.  All 64 lanes must call it.
-__device__ __forceinline__ void wave_run(int cell, int& head, int& len) {
-  const int lane = (int)(threadIdx.x & 63);
-  const int prev = __shfl_up(cell, 1);
-  const bool first = lane == 0 || prev != cell;
-  const unsigned long long heads = __ballot(first);
-  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-  head = 63 - __clzll(heads & upto);
-  const unsigned long long after = heads & ~upto;
-  len = (after ? __ffsll((long long)after) - 1 : 64) - lane;
-}
-
-// the cell of slot p, or -1 for an empty slot or one past the end
+// A block per tile of the particle bins: an LDS histogram of the tile's cells,
+// then one global atomic per cell; a particle that has left its tile since
+// the last binning adds itself.
 template <typename PT>
-__device__ __forceinline__ int slot_cell(const PT& P, long p, long total, int nx, int ny) {
-  return (p < total && alive(P, p)) ? cell_of(P, p, nx, ny) : -1;
-}
-
-template <typename PT>
-__global__ __launch_bounds__(256) void coul_count_kernel(PT P, WorkLists L, int nx, int ny,
+__global__ __launch_bounds__(256) void coul_count_kernel(PT P, WorkLists L,
                                                          int* __restrict__ cnt) {
-  const long total = L.tstart[L.ngrid];
-  const long wave0 = ((long)blockIdx.x * blockDim.x + threadIdx.x) & ~63L;
-  const int lane = (int)(threadIdx.x & 63);
-  for (long base = wave0; base < total; base += (long)gridDim.x * blockDim.x) {
-    const int c = slot_cell(P, base + lane, total, nx, ny);
-    int head, len;
-    wave_run(c, head, len);
-    if (head == lane && c >= 0) atomicAdd(&cnt[c], len);
+  __shared__ int h[64];
+  for (int t = blockIdx.x; t < L.ngrid; t += gridDim.x) {
+    if (threadIdx.x < 64) h[threadIdx.x] = 0;
+    __syncthreads();
+    const long p1 = L.tstart[t + 1];
+    for (long p = L.tstart[t] + threadIdx.x; p < p1; p += 256) {
+      const int c = coul_cell(P, p, L.ntx, L.nty);
+      if (c < 0) continue;
+      if ((c >> 6) == t)
+        atomicAdd(&h[c & 63], 1);
+      else
+        atomicAdd(&cnt[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64 && h[threadIdx.x] > 0) atomicAdd(&cnt[64 * t + threadIdx.x], h[threadIdx.x]);
+    __syncthreads();
   }
 }
 
@@ -165,30 +166,44 @@ __global__ __launch_bounds__(256) void coul_scan_add(int* __restrict__ a, long n
   }
 }
 
+// (order key, slot) of every particle into its cell's range, a block per
+// tile: the tile's histogram again, one atomic per cell reserves the tile's
+// run of each cell, LDS atomics place the particles in it; a particle that
+// has left its tile reserves its own place.
 template <typename PT>
 __global__ __launch_bounds__(256) void coul_scatter_kernel(PT P, WorkLists L, CoulombConst C,
                                                            int sp, const int* __restrict__ start,
                                                            int* __restrict__ fill,
                                                            unsigned long long* __restrict__ key,
                                                            int* __restrict__ slot) {
-  const long total = L.tstart[L.ngrid];
+  __shared__ int h[64], at[64];
   const uint32_t k = *C.step;
-  const long wave0 = ((long)blockIdx.x * blockDim.x + threadIdx.x) & ~63L;
-  const int lane = (int)(threadIdx.x & 63);
-  for (long base = wave0; base < total; base += (long)gridDim.x * blockDim.x) {
-    const long p = base + lane;
-    const int c = slot_cell(P, p, total, C.nx, C.ny);
-    int head, len;
-    wave_run(c, head, len);
-    int off = 0;
-    if (head == lane && c >= 0) off = atomicAdd(&fill[c], len);
-    off = __shfl(off, head) + (lane - head);
-    if (c < 0) continue;
-    const int at = start[c] + off;
-    const uint32_t id = P.id[p];
-    const uint4 r = philox4x32_10(id, k, kCOrder, (uint32_t)sp, C.key0, C.key1);
-    key[at] = ((unsigned long long)r.x << 32) | id;
-    slot[at] = (int)p;
+  for (int t = blockIdx.x; t < L.ngrid; t += gridDim.x) {
+    if (threadIdx.x < 64) h[threadIdx.x] = 0;
+    __syncthreads();
+    const long p0 = L.tstart[t], p1 = L.tstart[t + 1];
+    for (long p = p0 + threadIdx.x; p < p1; p += 256) {
+      const int c = coul_cell(P, p, L.ntx, L.nty);
+      if (c >= 0 && (c >> 6) == t) atomicAdd(&h[c & 63], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int c = 64 * t + threadIdx.x, n = h[threadIdx.x];
+      at[threadIdx.x] = n > 0 ? start[c] + atomicAdd(&fill[c], n) : 0;
+      h[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (long p = p0 + threadIdx.x; p < p1; p += 256) {
+      const int c = coul_cell(P, p, L.ntx, L.nty);
+      if (c < 0) continue;
+      const int pos = (c >> 6) == t ? at[c & 63] + atomicAdd(&h[c & 63], 1)
+                                    : start[c] + atomicAdd(&fill[c], 1);
+      const uint32_t id = P.id[p];
+      const uint4 r = philox4x32_10(id, k, kCOrder, (uint32_t)sp, C.key0, C.key1);
+      key[pos] = ((unsigned long long)r.x << 32) | id;
+      slot[pos] = (int)p;
+    }
+    __syncthreads();
   }
 }
 
@@ -230,20 +245,20 @@ __device__ void coul_collide(const CoulombConst& C, uint32_t k, uint32_t word, d
   }
 }
 
-// The pairing rule on velocities held in a cell's arrays (LDS or registers),
-// in key order: like pairs of both species (lanes over pairs, an odd count's
-// triplet on lane 0), a barrier, then the unlike pairs (lane r takes particle
-// r of the less numerous species b and its partners j = r, r + N_b, ... of a).
+// The pairing rule on velocities held in a cell's arrays (LDS), in key order:
+// like items of both species (pairs, an odd count's triplet as one item) over
+// the cell's W lanes, a barrier, then the unlike pairs (lane r takes particle r
+// of the less numerous species b and its partners j = r, r + N_b, ... of a).
 // V(s, q) is the velocity of the q-th particle of species s in key order,
-// ID(s, q) its id.
-#define COUL_PAIRS(V, ID)                                                                     \
+// ID(s, q) its id; LANE is the lane's index among the cell's W lanes.
+#define COUL_PAIRS(V, ID, LANE, W)                                                            \
   {                                                                                         \
     /* like items of both species in one list: species 0's, then 1's; an */                \
     /* odd count's triplet is its species' first item */                                   \
     int items[2];                                                                           \
     _Pragma("unroll") for (int s = 0; s < 2; ++s)                                            \
       items[s] = n[s] < 2 ? 0 : ((n[s] & 1) ? 1 + (n[s] - 3) / 2 : n[s] / 2);                 \
-    for (int it = lane; it < items[0] + items[1]; it += 64) {                               \
+    for (int it = (LANE); it < items[0] + items[1]; it += (W)) {                            \
       const int s = it < items[0] ? 0 : 1;                                                  \
       const int i = it - (s ? items[0] : 0);                                                \
       const int N = n[s];                                                                   \
@@ -263,7 +278,7 @@ __device__ void coul_collide(const CoulombConst& C, uint32_t k, uint32_t word, d
       const int sa = n[0] >= n[1] ? 0 : 1, sb = 1 - sa;                                     \
       const int Na = n[sa], Nb = n[sb];                                                     \
       const double cv = C.c_var[2] * (double)Nb * C.w_vol;                                  \
-      for (int r = lane; r < Nb; r += 64)                                                   \
+      for (int r = (LANE); r < Nb; r += (W))                                                \
         for (int j = r; j < Na; j += Nb)                                                    \
           coul_collide(C, k, 2u + (uint32_t)sa, cv, C.frac[2][sa], C.frac[2][sb], V(sa, j), \
                        V(sb, r), ID(sa, j));                                                \
@@ -272,7 +287,7 @@ __device__ void coul_collide(const CoulombConst& C, uint32_t k, uint32_t word, d
   }
 
 // cells whose species each hold at most kCellCap particles go through LDS
-constexpr int kCellCap = 128;
+constexpr int kCellCap = 64;
 struct CellStage {
   unsigned long long key[2][kCellCap];
   int slot_in[2][kCellCap];
@@ -281,8 +296,8 @@ struct CellStage {
   double v[2][kCellCap][3];
 };
 
-// cells above the LDS capacity: velocities in global memory through the
-// slots in key order
+// cells above the LDS capacity: the rule through global memory, the slots
+// ranked into the order array, one cell at a time with the whole wave
 template <typename PT>
 __device__ void global_collide(const PT P[2], const int* const ord[2], const CoulombConst& C,
                                uint32_t k, uint32_t word, double cv, double fa, double fb, int sa,
@@ -296,113 +311,134 @@ __device__ void global_collide(const PT P[2], const int* const ord[2], const Cou
   store_v(P[sb], pb, vb);
 }
 
-// One wave per block strides over the cells.
+template <typename PT>
+__device__ void cell_global(const PT P[2], const CoulombBufs& B, const CoulombConst& C, uint32_t k,
+                            int c, int lane) {
+  int r0[2], n[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    r0[s] = B.start[s][c];
+    n[s] = B.start[s][c + 1] - r0[s];
+  }
+  if (n[0] + n[1] < 2) return;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const unsigned long long* key = B.key[s] + r0[s];
+    for (int q = lane; q < n[s]; q += 64) {
+      const unsigned long long kq = key[q];
+      int rank = 0;
+      for (int t = 0; t < n[s]; ++t) rank += key[t] < kq;
+      B.ord[s][r0[s] + rank] = B.slot[s][r0[s] + q];
+    }
+  }
+  __syncthreads();
+  const int* const ord[2] = {B.ord[0] + r0[0], B.ord[1] + r0[1]};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int N = n[s];
+    if (N < 2) continue;
+    const double cv = C.c_var[s] * (double)N * C.w_vol;
+    const double f = C.frac[s][s];
+    int first = 0;
+    if (N & 1) {
+      if (lane == 0) {
+        global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 0, s, 1, P[s].id[ord[s][0]]);
+        global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 1, s, 2, P[s].id[ord[s][1]]);
+        global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 2, s, 0, P[s].id[ord[s][2]]);
+      }
+      first = 3;
+    }
+    for (int q = first + 2 * lane; q + 1 < N; q += 128)
+      global_collide(P, ord, C, k, (uint32_t)s, cv, f, f, s, q, s, q + 1, P[s].id[ord[s][q]]);
+  }
+  __syncthreads();
+  if (n[0] > 0 && n[1] > 0) {
+    const int sa = n[0] >= n[1] ? 0 : 1, sb = 1 - sa;
+    const int Na = n[sa], Nb = n[sb];
+    const double cv = C.c_var[2] * (double)Nb * C.w_vol;
+    for (int r = lane; r < Nb; r += 64) {
+      const long pb = ord[sb][r];
+      double vb[3];
+      load_v(P[sb], pb, vb);
+      for (int j = r; j < Na; j += Nb) {
+        const long pa = ord[sa][j];
+        double va[3];
+        load_v(P[sa], pa, va);
+        coul_collide(C, k, 2u + (uint32_t)sa, cv, C.frac[2][sa], C.frac[2][sb], va, vb,
+                     P[sa].id[pa]);
+        store_v(P[sa], pa, va);
+      }
+      store_v(P[sb], pb, vb);
+    }
+  }
+  __syncthreads();
+}
+
+// One wave per block strides over pairs of cells: each half-wave stages its
+// cell in LDS and runs the rule there (the two cells side by side, their
+// barriers shared); a pair with a cell above the stage's capacity runs both
+// cells in turn through global memory with the whole wave.
 template <typename PT>
 __global__ __launch_bounds__(64) void coul_pair_kernel(PT Pe, PT Pi, CoulombBufs B,
                                                        CoulombConst C) {
-  __shared__ CellStage sm;
-  const int lane = threadIdx.x;
+  __shared__ CellStage stage[2];
+  const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
   const PT P[2] = {Pe, Pi};
   const uint32_t k = *C.step;
-  unsigned long long pairings = 0;  // this wave's cells, added to the counter once
-  for (int c = blockIdx.x; c < C.ncell; c += gridDim.x) {
-    int r0[2], n[2];
+  CellStage& sm = stage[half];
+  unsigned long long pairings = 0;  // this half's cells, added to the counter once
+  for (int c0 = 2 * (int)blockIdx.x; c0 < C.ncell; c0 += 2 * (int)gridDim.x) {
+    const int c = c0 + half;
+    int r0[2] = {0, 0}, n[2] = {0, 0};
+    if (c < C.ncell) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      r0[s] = B.start[s][c];
-      n[s] = B.start[s][c + 1] - r0[s];
+      for (int s = 0; s < 2; ++s) {
+        r0[s] = B.start[s][c];
+        n[s] = B.start[s][c + 1] - r0[s];
+      }
     }
-    if (n[0] + n[1] < 2) continue;
 #pragma unroll
     for (int s = 0; s < 2; ++s)
       if (n[s] >= 2) pairings += (n[s] & 1) ? 3 + (n[s] - 3) / 2 : n[s] / 2;
     if (n[0] > 0 && n[1] > 0) pairings += n[0] > n[1] ? n[0] : n[1];
-    if (n[0] <= kCellCap && n[1] <= kCellCap) {
-      // stage: keys and slots, then rank, gathering ids and velocities in key order
+    const bool fits = n[0] <= kCellCap && n[1] <= kCellCap;
+    if (__ballot(!fits) != 0ull) {
+      cell_global(P, B, C, k, c0, lane);
+      if (c0 + 1 < C.ncell) cell_global(P, B, C, k, c0 + 1, lane);
+      continue;
+    }
+    if (__ballot(n[0] + n[1] >= 2) == 0ull) continue;
+    // stage: keys and slots, then rank, gathering ids and velocities in key order
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-        for (int q = lane; q < n[s]; q += 64) {
-          sm.key[s][q] = B.key[s][r0[s] + q];
-          sm.slot_in[s][q] = B.slot[s][r0[s] + q];
-        }
-      __syncthreads();
+    for (int s = 0; s < 2; ++s)
+      for (int q = hl; q < n[s]; q += 32) {
+        sm.key[s][q] = B.key[s][r0[s] + q];
+        sm.slot_in[s][q] = B.slot[s][r0[s] + q];
+      }
+    __syncthreads();
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-        for (int q = lane; q < n[s]; q += 64) {
-          const unsigned long long kq = sm.key[s][q];
-          int rank = 0;
-          for (int t = 0; t < n[s]; ++t) rank += sm.key[s][t] < kq;
-          const int p = sm.slot_in[s][q];
-          sm.slot[s][rank] = p;
-          sm.id[s][rank] = P[s].id[p];
-          load_v(P[s], p, sm.v[s][rank]);
-        }
-      __syncthreads();
+    for (int s = 0; s < 2; ++s)
+      for (int q = hl; q < n[s]; q += 32) {
+        const unsigned long long kq = sm.key[s][q];
+        int rank = 0;
+        for (int t = 0; t < n[s]; ++t) rank += sm.key[s][t] < kq;
+        const int p = sm.slot_in[s][q];
+        sm.slot[s][rank] = p;
+        sm.id[s][rank] = P[s].id[p];
+        load_v(P[s], p, sm.v[s][rank]);
+      }
+    __syncthreads();
 #define LDS_V(s, q) (sm.v[s][q])
 #define LDS_ID(s, q) (sm.id[s][q])
-      COUL_PAIRS(LDS_V, LDS_ID)
+    COUL_PAIRS(LDS_V, LDS_ID, hl, 32)
 #undef LDS_V
 #undef LDS_ID
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-        for (int q = lane; q < n[s]; q += 64) store_v(P[s], sm.slot[s][q], sm.v[s][q]);
-      __syncthreads();
-    } else {
-      // rank into the global order array, collide through it
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const unsigned long long* key = B.key[s] + r0[s];
-        for (int q = lane; q < n[s]; q += 64) {
-          const unsigned long long kq = key[q];
-          int rank = 0;
-          for (int t = 0; t < n[s]; ++t) rank += key[t] < kq;
-          B.ord[s][r0[s] + rank] = B.slot[s][r0[s] + q];
-        }
-      }
-      __syncthreads();
-      const int* const ord[2] = {B.ord[0] + r0[0], B.ord[1] + r0[1]};
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int N = n[s];
-        if (N < 2) continue;
-        const double cv = C.c_var[s] * (double)N * C.w_vol;
-        const double f = C.frac[s][s];
-        int first = 0;
-        if (N & 1) {
-          if (lane == 0) {
-            global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 0, s, 1, P[s].id[ord[s][0]]);
-            global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 1, s, 2, P[s].id[ord[s][1]]);
-            global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 2, s, 0, P[s].id[ord[s][2]]);
-          }
-          first = 3;
-        }
-        for (int q = first + 2 * lane; q + 1 < N; q += 128)
-          global_collide(P, ord, C, k, (uint32_t)s, cv, f, f, s, q, s, q + 1, P[s].id[ord[s][q]]);
-      }
-      __syncthreads();
-      if (n[0] > 0 && n[1] > 0) {
-        const int sa = n[0] >= n[1] ? 0 : 1, sb = 1 - sa;
-        const int Na = n[sa], Nb = n[sb];
-        const double cv = C.c_var[2] * (double)Nb * C.w_vol;
-        for (int r = lane; r < Nb; r += 64) {
-          const long pb = ord[sb][r];
-          double vb[3];
-          load_v(P[sb], pb, vb);
-          for (int j = r; j < Na; j += Nb) {
-            const long pa = ord[sa][j];
-            double va[3];
-            load_v(P[sa], pa, va);
-            coul_collide(C, k, 2u + (uint32_t)sa, cv, C.frac[2][sa], C.frac[2][sb], va, vb,
-                         P[sa].id[pa]);
-            store_v(P[sa], pa, va);
-          }
-          store_v(P[sb], pb, vb);
-        }
-      }
-      __syncthreads();
-    }
+    for (int s = 0; s < 2; ++s)
+      for (int q = hl; q < n[s]; q += 32) store_v(P[s], sm.slot[s][q], sm.v[s][q]);
+    __syncthreads();
   }
-  if (lane == 0 && pairings) atomicAdd(B.count, pairings);
+  if (hl == 0 && pairings) atomicAdd(B.count, pairings);
 }
 
 template <typename PT>
@@ -412,20 +448,19 @@ void coulomb_impl(const PT P[2], const WorkLists L[2], const CoulombBufs& B, con
   for (int s = 0; s < 2; ++s) {
     launch_zero_i32(B.start[s], ncell + 1, st);
     launch_zero_i32(B.fill[s], ncell, st);
-    const int g = std::min(nblk(cap[s], 256), 65536);
-    if (g > 0)
-      hipLaunchKernelGGL(coul_count_kernel<PT>, dim3(g), dim3(256), 0, st, P[s], L[s], C.nx, C.ny,
-                         B.start[s]);
+    const int g = std::min(L[s].ngrid, 65536);
+    if (cap[s] > 0 && g > 0)
+      hipLaunchKernelGGL(coul_count_kernel<PT>, dim3(g), dim3(256), 0, st, P[s], L[s], B.start[s]);
     const long n = ncell + 1;
     const int nb = nblk(n, kScanChunk);
     hipLaunchKernelGGL(coul_scan_local, dim3(nb), dim3(256), 0, st, B.start[s], n, B.sums);
     hipLaunchKernelGGL(coul_scan_sums, dim3(1), dim3(256), 0, st, B.sums, nb);
     hipLaunchKernelGGL(coul_scan_add, dim3(nb), dim3(256), 0, st, B.start[s], n, B.sums);
-    if (g > 0)
+    if (cap[s] > 0 && g > 0)
       hipLaunchKernelGGL(coul_scatter_kernel<PT>, dim3(g), dim3(256), 0, st, P[s], L[s], C, s,
                          B.start[s], B.fill[s], B.key[s], B.slot[s]);
   }
-  const int grid = (int)std::min<long>(ncell, 32768);
+  const int grid = (int)std::min<long>((ncell + 1) / 2, 32768);
   hipLaunchKernelGGL(coul_pair_kernel<PT>, dim3(grid), dim3(64), 0, st, P[0], P[1], B, C);
 }
 

@@ -82,9 +82,10 @@ struct CoulombBufs {
 };
 // constants of a pass: pair kinds 0 e-e, 1 Ar+-Ar+, 2 e-Ar+; the variance of
 // delta is c_var[kind] n_L / |u|^3 with n_L = (particles) w_vol; species s of
-// a pair changes by +- frac[kind][s] du
+// a pair changes by +- frac[kind][s] du; ncell counts the cells in the tile
+// order of the particle bins (64 a tile, the start arrays hold ncell + 1)
 struct CoulombConst {
-  int nx, ny, ncell;
+  int ncell;
   uint32_t key0, key1;
   const uint32_t* step;
   double w_vol;

@@ -632,9 +632,7 @@ bool coulomb_due(const Replica& R) {
 int enqueue_coulomb(pic_ctx* ctx, Replica& R) {
   const pic_config& c = R.cfg;
   CoulombConst C{};
-  C.nx = R.nx;
-  C.ny = R.ny;
-  C.ncell = (int)R.ncell;
+  C.ncell = 64 * R.ngrid;
   C.key0 = (uint32_t)(c.seed & 0xffffffffu);
   C.key1 = (uint32_t)(c.seed >> 32);
   C.step = R.d_step;
@@ -1188,13 +1186,14 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   HIPCHK(ctx, hipMemsetAsync(R.norms, 0, 16, st));
   if (c.coulomb_interval > 0) {
     for (int sp = 0; sp < 2; ++sp) {
-      TRY(dalloc(ctx, R, &R.coul.start[sp], R.ncell + 1));
-      TRY(dalloc(ctx, R, &R.coul.fill[sp], R.ncell));
+      // cells in the tile order of the particle bins, 64 a tile
+      TRY(dalloc(ctx, R, &R.coul.start[sp], 64L * R.ngrid + 1));
+      TRY(dalloc(ctx, R, &R.coul.fill[sp], 64L * R.ngrid));
       TRY(dalloc(ctx, R, &R.coul.key[sp], R.cap[sp]));
       TRY(dalloc(ctx, R, &R.coul.slot[sp], R.cap[sp]));
       TRY(dalloc(ctx, R, &R.coul.ord[sp], R.cap[sp]));
     }
-    TRY(dalloc(ctx, R, &R.coul.sums, coulomb_scan_sums(R.ncell)));
+    TRY(dalloc(ctx, R, &R.coul.sums, coulomb_scan_sums(64L * R.ngrid)));
     TRY(dalloc(ctx, R, &R.coul.count, 1));
     launch_zero_i64((long long*)R.coul.count, 1, st);
     ctx->coulomb = true;

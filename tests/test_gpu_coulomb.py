@@ -4,7 +4,8 @@ through the C ABI against the oracle.
 The pass runs at the start of a step on the state both sides share, so the
 cells, pairing order and draws are the same; one step of the GPU is compared
 with one oracle step, particle by particle (FP64 1e-12, FP32R 1e-5), and the
-number of pairings is exact.  A large Coulomb logarithm makes the collisions
+number of pairings is exact.  The dense box puts more particles in many
+cells than a cell's shared-memory stage holds, so cells of both kinds run.  A large Coulomb logarithm makes the collisions
 turn velocities by O(1) angles so that a missing or misplaced pass cannot
 hide inside the FP32R tolerance.
 """
@@ -22,9 +23,11 @@ TOL = {"fp64": 1e-12, "fp32r": 1e-5}
 def _wl(box, prec, interval=1, lnL=2.0e5):
     if box == "small":
         wl = dict(W.small_fp64(), precision=prec)
-    else:  # ragged box, 3 particles per cell: many cells with 0, 1, odd counts
+    elif box == "ragged":  # 3 particles per cell: many cells with 0, 1, odd counts
         wl = W.tiny(nx=12, ny=10, nz=17, ppc=3, grains=[[0.3, 9.6, 8.5]], cutoff=2, precision=prec,
                     seed=5)
+    else:  # dense: a quarter of the cells hold over 128 electrons; an odd cell count
+        wl = W.tiny(nx=5, ny=3, nz=9, ppc=124, precision=prec, seed=9)
     wl["coulomb_interval"] = interval
     wl["coulomb_lnL"] = lnL
     return wl
@@ -55,7 +58,7 @@ def _step_vs_oracle(sim, wl, prec, check_count=True):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32r"])
-@pytest.mark.parametrize("box", ["small", "ragged"])
+@pytest.mark.parametrize("box", ["small", "ragged", "dense"])
 def test_coulomb_step_matches_oracle(prec, box):
     from paper_1801_00972_amd.pic import Simulation
     wl = _wl(box, prec)
