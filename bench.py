@@ -30,11 +30,11 @@ HBM_PEAK_GBS = 8000.0
 RECORD_BYTES = {"fp32r": 32, "fp64": 52}      # per particle: read once, written once
 NODE_BYTES = {"fp32r": 16 + 8, "fp64": 32 + 8}  # per node and step: E read, rho written
 # one Coulomb-collision pass, per alive particle: cell read to count and to
-# scatter, id read, order key and slot written, then read, the slots in key
-# order written and read, id read, velocity read and written (FP64: three
-# position doubles instead of the packed cell, double velocities); per cell
-# and species: the count cleared, scanned, its cursor cleared, its range read
-COULOMB_BYTES = {"fp32r": 72, "fp64": 136}
+# scatter, id read, order key and slot written, then read, id read, velocity
+# read and written (FP64: three position doubles instead of the packed cell,
+# double velocities); per cell and species: the count cleared, scanned, its
+# cursor cleared, its range read
+COULOMB_BYTES = {"fp32r": 64, "fp64": 128}
 COULOMB_CELL_BYTES = 48
 
 
