@@ -38,7 +38,10 @@ COULOMB_BYTES = {"fp32r": 64, "fp64": 128}
 COULOMB_CELL_BYTES = 48
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_push_f32r_full_64x64x256_ppc32.md")
+TRAFFIC_PROFILES = {
+    "push_fp32r": os.path.join(ROOT, "profiles", "hbm_traffic_push_f32r_full_64x64x256_ppc32.md"),
+    "push_fp64": os.path.join(ROOT, "profiles", "hbm_traffic_push_f64_full_64x64x256_ppc32.md"),
+}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_00972_amd", "csrc", f)
                   for f in ("particles.hip", "device_common.hpp", "pic_types.hpp")]
 
@@ -48,10 +51,11 @@ def traffic_per_particle_step(kernel, workload):
     rocprofv3 FETCH_SIZE/WRITE_SIZE record, if it was taken on the current
     kernel sources and this workload (else None)."""
     import hashlib
-    if kernel != "push_fp32r" or not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILES.get(kernel)
+    if path is None or not os.path.exists(path):
         return None
     rec = None
-    for line in open(TRAFFIC_PROFILE):
+    for line in open(path):
         if line.startswith("traffic-record:"):
             rec = json.loads(line.split(":", 1)[1])
     if rec is None or rec.get("workload") != workload:
