@@ -80,9 +80,24 @@ __device__ __forceinline__ void store_v(const PartF32R& P, long p, const double 
   P.vz[p] = (float)v[2];
 }
 
-// A block per tile of the particle bins: an LDS histogram of the tile's cells,
-// then one global atomic per cell; a particle that has left its tile since
-// the last binning adds itself.
+// Runs of equal cells in consecutive lanes of a wave (the slots of a tile are
+// grouped by cell after a re-binning): each lane learns its run's first lane,
+// the first lane also the run's length.  All 64 lanes must call it.
+__device__ __forceinline__ void wave_run(int cell, int& head, int& len) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int prev = __shfl_up(cell, 1);
+  const bool first = lane == 0 || prev != cell;
+  const unsigned long long heads = __ballot(first);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+  head = 63 - __clzll(heads & upto);
+  const unsigned long long after = heads & ~upto;
+  len = (after ? __ffsll((long long)after) - 1 : 64) - lane;
+}
+
+// A block per tile of the particle bins: an LDS histogram of the tile's cells
+// (one atomic per run of equal cells in a wave), then one global atomic per
+// cell; a run of particles that have left the tile since the last binning
+// adds itself.
 template <typename PT>
 __global__ __launch_bounds__(256) void coul_count_kernel(PT P, WorkLists L,
                                                          int* __restrict__ cnt) {
@@ -90,14 +105,18 @@ __global__ __launch_bounds__(256) void coul_count_kernel(PT P, WorkLists L,
   for (int t = blockIdx.x; t < L.ngrid; t += gridDim.x) {
     if (threadIdx.x < 64) h[threadIdx.x] = 0;
     __syncthreads();
-    const long p1 = L.tstart[t + 1];
-    for (long p = L.tstart[t] + threadIdx.x; p < p1; p += 256) {
-      const int c = coul_cell(P, p, L.ntx, L.nty);
-      if (c < 0) continue;
+    const long p0 = L.tstart[t], p1 = L.tstart[t + 1];
+    const int lane = (int)(threadIdx.x & 63);
+    for (long base = p0 + (threadIdx.x & ~63); base < p1; base += 256) {
+      const long p = base + lane;
+      const int c = p < p1 ? coul_cell(P, p, L.ntx, L.nty) : -1;
+      int head, len;
+      wave_run(c, head, len);
+      if (head != lane || c < 0) continue;
       if ((c >> 6) == t)
-        atomicAdd(&h[c & 63], 1);
+        atomicAdd(&h[c & 63], len);
       else
-        atomicAdd(&cnt[c], 1);
+        atomicAdd(&cnt[c], len);
     }
     __syncthreads();
     if (threadIdx.x < 64 && h[threadIdx.x] > 0) atomicAdd(&cnt[64 * t + threadIdx.x], h[threadIdx.x]);
@@ -168,8 +187,9 @@ __global__ __launch_bounds__(256) void coul_scan_add(int* __restrict__ a, long n
 
 // (order key, slot) of every particle into its cell's range, a block per
 // tile: the tile's histogram again, one atomic per cell reserves the tile's
-// run of each cell, LDS atomics place the particles in it; a particle that
-// has left its tile reserves its own place.
+// run of each cell, LDS atomics (one per run of equal cells in a wave) place
+// the particles in it; particles that have left the tile reserve their own
+// places.
 template <typename PT>
 __global__ __launch_bounds__(256) void coul_scatter_kernel(PT P, WorkLists L, CoulombConst C,
                                                            int sp, const int* __restrict__ start,
@@ -182,9 +202,13 @@ __global__ __launch_bounds__(256) void coul_scatter_kernel(PT P, WorkLists L, Co
     if (threadIdx.x < 64) h[threadIdx.x] = 0;
     __syncthreads();
     const long p0 = L.tstart[t], p1 = L.tstart[t + 1];
-    for (long p = p0 + threadIdx.x; p < p1; p += 256) {
-      const int c = coul_cell(P, p, L.ntx, L.nty);
-      if (c >= 0 && (c >> 6) == t) atomicAdd(&h[c & 63], 1);
+    const int lane = (int)(threadIdx.x & 63);
+    for (long base = p0 + (threadIdx.x & ~63); base < p1; base += 256) {
+      const long p = base + lane;
+      const int c = p < p1 ? coul_cell(P, p, L.ntx, L.nty) : -1;
+      int head, len;
+      wave_run(c, head, len);
+      if (head == lane && c >= 0 && (c >> 6) == t) atomicAdd(&h[c & 63], len);
     }
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -193,11 +217,17 @@ __global__ __launch_bounds__(256) void coul_scatter_kernel(PT P, WorkLists L, Co
       h[threadIdx.x] = 0;
     }
     __syncthreads();
-    for (long p = p0 + threadIdx.x; p < p1; p += 256) {
-      const int c = coul_cell(P, p, L.ntx, L.nty);
+    for (long base = p0 + (threadIdx.x & ~63); base < p1; base += 256) {
+      const long p = base + lane;
+      const int c = p < p1 ? coul_cell(P, p, L.ntx, L.nty) : -1;
+      int head, len;
+      wave_run(c, head, len);
+      int off = 0;
+      if (head == lane && c >= 0)
+        off = (c >> 6) == t ? at[c & 63] + atomicAdd(&h[c & 63], len)
+                            : start[c] + atomicAdd(&fill[c], len);
+      const int pos = __shfl(off, head) + (lane - head);
       if (c < 0) continue;
-      const int pos = (c >> 6) == t ? at[c & 63] + atomicAdd(&h[c & 63], 1)
-                                    : start[c] + atomicAdd(&fill[c], 1);
       const uint32_t id = P.id[p];
       const uint4 r = philox4x32_10(id, k, kCOrder, (uint32_t)sp, C.key0, C.key1);
       key[pos] = ((unsigned long long)r.x << 32) | id;
