@@ -40,8 +40,6 @@ constexpr int kScanChunk = 2048; // elements per block of the scan (256 threads 
 
 inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
-__device__ __forceinline__ bool alive(const PartF64& P, long p) { return P.z[p] >= 0.0; }
-__device__ __forceinline__ bool alive(const PartF32R& P, long p) { return P.cell[p] >= 0; }
 
 // Cells are numbered in tile order: tile (i/4 + ntx (j/4 + nty k/4)), the
 // tile order of the particle bins, times 64 plus the cell inside its tile
