@@ -100,7 +100,7 @@ typedef struct pic_config {
   int32_t pp_cutoff_cells;
   int32_t md_subcycles;
   int32_t precision;           /* PIC_FP64 or PIC_FP32R */
-  int32_t max_refine;          /* FP32R: residual-refinement sweeps per solve (>= 1) */
+  int32_t max_refine;          /* FP32R: most residual-refinement sweeps per solve (1..16) */
   int32_t sort_interval;       /* steps between re-binnings of the electrons (0: never; see pic_tuning) */
   double dx, dt;
   double n0;
@@ -110,7 +110,8 @@ typedef struct pic_config {
   double V_dc, V_rf, f_rf;
   double grain_radius;
   double E_cap_eV;
-  double refine_tol;           /* FP32R: target ||b - A phi|| / ||b|| (diagnostic) */
+  double refine_tol;           /* FP32R: the refinement stops once ||b - A phi|| <= refine_tol ||b||
+                                  (b with the electrode lift; 0: always max_refine sweeps) */
   uint64_t seed;               /* Philox key of the replica */
   const double* grain_pos;     /* host pointer, [n_grains][3], cell units */
   int32_t coulomb_interval;    /* steps between Coulomb-collision passes (0: none) */
@@ -167,6 +168,11 @@ typedef struct pic_counters {
   int64_t numeric_bad;        /* particles removed for a non-finite position (0 for valid input) */
   int64_t tile_fallback;      /* particle-steps outside their tile's LDS window (global-memory path) */
   int64_t n_coulomb;          /* binary Coulomb collisions (pairings) performed */
+  int64_t refine_unconverged; /* FP32R: solves that ended after max_refine sweeps above refine_tol */
+  int64_t md_margin[2];       /* plain (not sub-cycled) particle-steps with |v_{k+1/2}| dt >=
+                                 pp_cutoff_cells dx: moves long enough to reach a grain from
+                                 outside its MD cube, where no grain test is made (0 without
+                                 grains) */
 } pic_counters;
 
 /*

@@ -22,17 +22,30 @@ _SO = os.path.join(_HERE, "liboracle.so")
 NO_MESH, NO_MCC, FIXED_POINT, FROZEN_Q = 1, 2, 4, 8
 
 
-def build(verbose: bool = False) -> str:
-    """Compile pic_oracle.c into liboracle.so (gcc, -O2, OpenMP, no fast-math)."""
+def build(verbose: bool = False, native: bool = False, out: str | None = None) -> str:
+    """Compile pic_oracle.c into a shared library (gcc -O3, OpenMP, no
+    fast-math, no FMA contraction).  The default is the portable liboracle.so
+    the tests load; native=True adds -march=native for the machine it runs on
+    (the CPU-baseline timing builds it there, into `out`)."""
     src = os.path.join(_HERE, "pic_oracle.c")
-    tmp = _SO + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-           "-ffp-contract=off", "-o", tmp, src, "-lm"]
+    target = out or _SO
+    tmp = target + ".tmp"
+    cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-ffp-contract=off"] + (["-march=native"] if native else []) + ["-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _SO)
-    return _SO
+    os.replace(tmp, target)
+    return target
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of pic_oracle.c (the CPU-baseline
+    timing uses a -march=native build); call before any oracle function."""
+    global _SO, _lib
+    if _lib is not None and _SO != path:
+        raise RuntimeError("the oracle library is already loaded from " + _SO)
+    _SO = path
 
 
 class _Config(C.Structure):
@@ -80,6 +93,7 @@ class _State(C.Structure):
         ("n_collisions", C.c_int64 * 2),
         ("step", C.c_uint32),
         ("pad0", C.c_uint32),
+        ("md_margin", C.c_int64 * 2),
     ]
 
 
@@ -235,6 +249,11 @@ class Oracle:
     @property
     def n_collisions(self):
         return [int(self.st.n_collisions[s]) for s in range(2)]
+
+    @property
+    def md_margin(self):
+        """Plain pushes per species with |v_{k+1/2}| dt >= cutoff dx (grains present)."""
+        return [int(self.st.md_margin[s]) for s in range(2)]
 
     def compact(self):
         """Drop removed particles, keeping the order of the survivors."""

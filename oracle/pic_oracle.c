@@ -81,6 +81,9 @@ int orc_derive(const orc_config* c, orc_derived* d)
   if (c->ppc_e <= 0 || c->ppc_e != c->ppc_i) return -1;
   /* one super-particle weight for both species (Sec. III: super-particles) */
   d->w = c->n0 * c->dx * c->dx * c->dx / (double)c->ppc_e;
+  /* the fixed-point deposit multiplies Qp by a 24-bit offset fraction in
+     int64, so Qp must stay below 2^39 (w below 128) */
+  if (!(d->w * 4294967296.0 < 549755813888.0)) return -2;
   d->Qp = llround(d->w * 4294967296.0);
   /* neutral reservoir density from the gas pressure (ideal gas) */
   d->n_gas = c->p_gas / (O_KB * c->T_gas);
@@ -1154,10 +1157,13 @@ static int move_all(const orc_config* c, orc_state* s, const double* E, const do
   /* Coulomb collisions on (x_k, v_{k-1/2}) at the start of every interval-th step */
   if (c->coulomb_interval > 0 && k % (uint32_t)c->coulomb_interval == 0 && orc_coulomb(c, s) < 0)
     return -6;
+  /* a plain push at least this fast crosses cutoff cells in one step: it could
+     reach a grain from outside the grain's MD cube, where no grain test is made */
+  const double vfast = c->cutoff * c->dx / c->dt;
   for (int sp = 0; sp < 2; ++sp) {
     double qm = d.q[sp] / d.m[sp];
-    int64_t wall[2] = {0, 0};
-#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : wall[:2])
+    int64_t wall[2] = {0, 0}, fast = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : wall[:2], fast)
     for (int64_t p = 0; p < s->n[sp]; ++p) {
       if (!s->alive[sp][p]) continue;
       double* x = &s->pos[sp][3 * p];
@@ -1166,9 +1172,10 @@ static int move_all(const orc_config* c, orc_state* s, const double* E, const do
       int G[1];
       int nG = orc_md_grains(c, (int)floor(x[0]), (int)floor(x[1]), (int)floor(x[2]), G, 1);
       int hit = -1, st;
-      if (nG == 0)
+      if (nG == 0) {
         st = move_plain(c, Euse, qm, x, v, &margin);
-      else
+        if (c->n_grains > 0 && v[0] * v[0] + v[1] * v[1] + v[2] * v[2] >= vfast * vfast) fast += 1;
+      } else
         st = move_md(c, Euse, Uuse, Q, qm, x, v, &margin, &hit);
       if (st == MV_WALL0 || st == MV_WALL1) {
         wall[st - 1] += 1;
@@ -1184,6 +1191,7 @@ static int move_all(const orc_config* c, orc_state* s, const double* E, const do
     }
     s->wall_count[0][sp] += wall[0];
     s->wall_count[1][sp] += wall[1];
+    s->md_margin[sp] += fast;
   }
   s->step = k + 1;
   return 0;

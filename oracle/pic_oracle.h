@@ -99,6 +99,7 @@ typedef struct orc_state {
   int64_t n_collisions[2];   /* accepted collisions */
   uint32_t step;             /* k: the state holds x_k and v_{k-1/2} */
   uint32_t pad0;
+  int64_t md_margin[2];      /* plain pushes with |v_{k+1/2}| dt >= cutoff dx (with grains) */
 } orc_state;
 
 /* ---- building blocks (exposed for the pins) ---- */

@@ -122,7 +122,7 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
                           const void* tw_y32, const void* inv32, double* phi, RfDrive rf,
-                          int sweeps, double* norms, hipStream_t st);
+                          int sweeps, double tol, double* norms, int* ctl, hipStream_t st);
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
                     hipStream_t st);
 void launch_rhs_fixed(const long long* rho, double scale, double* b, int nx, int ny, int nz,

@@ -158,9 +158,11 @@ __global__ __launch_bounds__(256) void fft_lines_kernel(FftGeom g, const cplx<T>
                                                         int forward, cplx<T>* __restrict__ work,
                                                         const double* __restrict__ rin,
                                                         double in_scale, double* __restrict__ rout,
-                                                        double out_scale, RfDrive rf, int nz) {
+                                                        double out_scale, RfDrive rf, int nz,
+                                                        const int* __restrict__ skip) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
+  if (skip && *skip) return;  // a refinement sweep after convergence
   const double V = OUT == OUT_REAL_LIFT ? rf_voltage(rf) : 0.0;
   C* buf0 = reinterpret_cast<C*>(smem_raw);
   C* buf1 = buf0 + g.L * g.N;
@@ -226,9 +228,11 @@ __global__ __launch_bounds__(kPlaneThreads) void fft_plane_kernel(Fft2Geom g, co
                                                         int forward, cplx<T>* __restrict__ work,
                                                         const double* __restrict__ rin,
                                                         double in_scale, double* __restrict__ rout,
-                                                        double out_scale, RfDrive rf, int nz) {
+                                                        double out_scale, RfDrive rf, int nz,
+                                                        const int* __restrict__ skip) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
+  if (skip && *skip) return;  // a refinement sweep after convergence
   const int nx = g.nx, ny = g.ny, np = nx * ny;
   C* b0 = reinterpret_cast<C*>(smem_raw);
   C* b1 = b0 + np;
@@ -285,8 +289,10 @@ constexpr int kTriModes = 16;  // modes per block (16 x 16 = 256 threads)
 template <typename T, int kTriMaxLen>  // rows per chunk held in registers
 __global__ __launch_bounds__(256) void thomas_chunked_kernel(cplx<T>* __restrict__ d,
                                                              const T* __restrict__ inv, int K,
-                                                             long modes) {
+                                                             long modes,
+                                                             const int* __restrict__ skip) {
   using C = cplx<T>;
+  if (skip && *skip) return;  // a refinement sweep after convergence
   __shared__ T s_A[kTriChunks][kTriModes];
   __shared__ C s_B[kTriChunks][kTriModes];
   const int lm = threadIdx.x % kTriModes, c = threadIdx.x / kTriModes;
@@ -373,7 +379,8 @@ __global__ __launch_bounds__(256) void thomas_chunked_kernel(cplx<T>* __restrict
 // the factorisation, computed once per run
 template <typename T>
 __global__ void thomas_kernel(cplx<T>* __restrict__ d, const T* __restrict__ inv, int K,
-                              long modes) {
+                              long modes, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a refinement sweep after convergence
   // the loads of a batch of planes are issued together: the recursion only
   // waits on arithmetic, not on one memory round trip per plane
   using C = cplx<T>;
@@ -601,8 +608,10 @@ template <bool NORMS>
 __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict__ psi,
                                                        const double* __restrict__ b,
                                                        double* __restrict__ r, int nx, int ny,
-                                                       int K, double* __restrict__ partials) {
+                                                       int K, double* __restrict__ partials,
+                                                       const int* __restrict__ skip) {
   __shared__ double s_r[256], s_b[256];
+  if (skip && *skip) return;  // a refinement sweep after convergence
   const long plane = (long)nx * ny;
   // grid: x over the plane's nodes, y over the planes
   const int pn = (int)(blockIdx.x * blockDim.x + threadIdx.x), k = (int)blockIdx.y;
@@ -643,10 +652,17 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
   }
 }
 
-// sum of the per-block partial norms (one block)
+// sum of the per-block partial norms (one block); then the stopping test of
+// the refinement after `sweep` FP32 solves (0: the residual of the starting
+// guess): ctl[0] = 1 once ||r||^2 <= tol2 ||b||^2 (or r = 0), ctl[1] = sweeps
+// done in this solve, ctl[2] += 1 when the last allowed sweep (last != 0)
+// ends above the tolerance
 __global__ __launch_bounds__(1024) void norm_reduce_kernel(const double* __restrict__ partials,
-                                                           int nb, double* __restrict__ norms) {
+                                                           int nb, double* __restrict__ norms,
+                                                           int* __restrict__ ctl, double tol2,
+                                                           int sweep, int last) {
   __shared__ double s_r[1024], s_b[1024];
+  if (sweep > 0 && ctl[0]) return;  // converged before this sweep
   double rr = 0.0, bb = 0.0;
   for (int i = threadIdx.x; i < nb; i += 1024) {
     rr += partials[2 * i];
@@ -665,6 +681,10 @@ __global__ __launch_bounds__(1024) void norm_reduce_kernel(const double* __restr
   if (threadIdx.x == 0) {
     norms[0] = s_r[0];
     norms[1] = s_b[0];
+    const int done = s_r[0] <= tol2 * s_b[0] || s_r[0] == 0.0;
+    ctl[0] = done;
+    ctl[1] = sweep;
+    if (last && !done) ctl[2] += 1;
   }
 }
 
@@ -932,7 +952,8 @@ static FftGeom make_geom(const FftPlanHost& P, bool along_x, int nx, int ny, lon
 template <typename T>
 static void fft_launch(const FftGeom& g, int planes, const void* tw, int forward, int in_mode,
                        int out_mode, void* work, const double* rin, double in_scale, double* rout,
-                       double out_scale, RfDrive rf, int nz, hipStream_t st) {
+                       double out_scale, RfDrive rf, int nz, hipStream_t st,
+                       const int* skip = nullptr) {
   using C = cplx<T>;
   const int blocks = planes * (g.lines_per_plane / g.L);
   const size_t lds = 2 * sizeof(C) * g.L * g.N;
@@ -940,19 +961,19 @@ static void fft_launch(const FftGeom& g, int planes, const void* tw, int forward
   C* w = (C*)work;
   if (in_mode == IN_REAL && out_mode == OUT_COMPLEX)
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_REAL, OUT_COMPLEX>), dim3(blocks), dim3(256), lds, st,
-                       g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
+                       g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz, skip);
   else if (in_mode == IN_COMPLEX && out_mode == OUT_COMPLEX)
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_COMPLEX>), dim3(blocks), dim3(256), lds,
-                       st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
+                       st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz, skip);
   else if (out_mode == OUT_REAL_LIFT)
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_LIFT>), dim3(blocks), dim3(256), lds,
-                       st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
+                       st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz, skip);
   else if (out_mode == OUT_REAL_STORE)
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_STORE>), dim3(blocks), dim3(256),
-                       lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
+                       lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz, skip);
   else
     hipLaunchKernelGGL((fft_lines_kernel<T, IN_COMPLEX, OUT_REAL_ACCUM>), dim3(blocks), dim3(256),
-                       lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz);
+                       lds, st, g, t, forward, w, rin, in_scale, rout, out_scale, rf, nz, skip);
 }
 
 // 2-D plane transforms when two plane buffers fit in 64 KB of LDS
@@ -962,7 +983,7 @@ template <typename T>
 static void fft_plane_launch(const FftPlanHost& P, int nx, int ny, int planes, const void* tw_x,
                              const void* tw_y, int forward, int in_mode, int out_mode, void* work,
                              const double* rin, double* rout, double out_scale, RfDrive rf, int nz,
-                             hipStream_t st) {
+                             hipStream_t st, const int* skip = nullptr) {
   using C = cplx<T>;
   Fft2Geom g{};
   g.nx = nx;
@@ -979,32 +1000,33 @@ static void fft_plane_launch(const FftPlanHost& P, int nx, int ny, int planes, c
   C* w = (C*)work;
   if (in_mode == IN_REAL)
     hipLaunchKernelGGL((fft_plane_kernel<T, IN_REAL, OUT_COMPLEX>), dim3(planes), dim3(kPlaneThreads), lds, st,
-                       g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
+                       g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz, skip);
   else if (out_mode == OUT_REAL_LIFT)
     hipLaunchKernelGGL((fft_plane_kernel<T, IN_COMPLEX, OUT_REAL_LIFT>), dim3(planes),
-                       dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
+                       dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz, skip);
   else if (out_mode == OUT_REAL_STORE)
     hipLaunchKernelGGL((fft_plane_kernel<T, IN_COMPLEX, OUT_REAL_STORE>), dim3(planes),
-                       dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
+                       dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz, skip);
   else
     hipLaunchKernelGGL((fft_plane_kernel<T, IN_COMPLEX, OUT_REAL_ACCUM>), dim3(planes),
-                       dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz);
+                       dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz, skip);
 }
 
 template <typename T>
-static void tridiag_launch(void* work, const void* inv, int K, long modes, hipStream_t st) {
+static void tridiag_launch(void* work, const void* inv, int K, long modes, hipStream_t st,
+                           const int* skip = nullptr) {
   using C = cplx<T>;
   const int len = (K + kTriChunks - 1) / kTriChunks;
   const int blocks = (int)((modes + kTriModes - 1) / kTriModes);
   if (len <= 16)
     hipLaunchKernelGGL((thomas_chunked_kernel<T, 16>), dim3(blocks), dim3(256), 0, st, (C*)work,
-                       (const T*)inv, K, modes);
+                       (const T*)inv, K, modes, skip);
   else if (len <= 32)
     hipLaunchKernelGGL((thomas_chunked_kernel<T, 32>), dim3(blocks), dim3(256), 0, st, (C*)work,
-                       (const T*)inv, K, modes);
+                       (const T*)inv, K, modes, skip);
   else
     hipLaunchKernelGGL(thomas_kernel<T>, dim3(nb256(modes)), dim3(256), 0, st, (C*)work,
-                       (const T*)inv, K, modes);
+                       (const T*)inv, K, modes, skip);
 }
 
 // one FFT + tridiagonal + inverse FFT solve of A psi = b (T = double or float);
@@ -1012,27 +1034,27 @@ static void tridiag_launch(void* work, const void* inv, int K, long modes, hipSt
 template <typename T>
 static void solve_once(const FftPlanHost& P, int nx, int ny, int nz, const double* b, void* work,
                        const void* tw_x, const void* tw_y, const void* inv, int out_mode,
-                       double* out, RfDrive rf, hipStream_t st) {
+                       double* out, RfDrive rf, hipStream_t st, const int* skip = nullptr) {
   const long plane = (long)nx * ny;
   const int K = nz - 1;
   if (2 * sizeof(cplx<T>) * (size_t)plane <= kPlaneLds) {
     fft_plane_launch<T>(P, nx, ny, K, tw_x, tw_y, 1, IN_REAL, OUT_COMPLEX, work, b, nullptr, 0.0,
-                        rf, nz, st);
-    tridiag_launch<T>(work, inv, K, plane, st);
+                        rf, nz, st, skip);
+    tridiag_launch<T>(work, inv, K, plane, st, skip);
     fft_plane_launch<T>(P, nx, ny, K, tw_x, tw_y, 0, IN_COMPLEX, out_mode, work, nullptr, out,
-                        1.0 / (double)plane, rf, nz, st);
+                        1.0 / (double)plane, rf, nz, st, skip);
     return;
   }
   const FftGeom gx = make_geom(P, true, nx, ny, plane);
   const FftGeom gy = make_geom(P, false, nx, ny, plane);
-  fft_launch<T>(gx, K, tw_x, 1, IN_REAL, OUT_COMPLEX, work, b, 1.0, nullptr, 0.0, rf, nz, st);
+  fft_launch<T>(gx, K, tw_x, 1, IN_REAL, OUT_COMPLEX, work, b, 1.0, nullptr, 0.0, rf, nz, st, skip);
   fft_launch<T>(gy, K, tw_y, 1, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, rf, nz,
-                st);
-  tridiag_launch<T>(work, inv, K, plane, st);
+                st, skip);
+  tridiag_launch<T>(work, inv, K, plane, st, skip);
   fft_launch<T>(gy, K, tw_y, 0, IN_COMPLEX, OUT_COMPLEX, work, nullptr, 0.0, nullptr, 0.0, rf, nz,
-                st);
+                st, skip);
   fft_launch<T>(gx, K, tw_x, 0, IN_COMPLEX, out_mode, work, nullptr, 0.0, out,
-                1.0 / (double)plane, rf, nz, st);
+                1.0 / (double)plane, rf, nz, st, skip);
 }
 
 void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double* b, void* work,
@@ -1043,29 +1065,33 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
                      (long)nx * ny, nz, rf);
 }
 
-// FP32 solves refined in FP64: psi = solve32(b); r = b - A psi; then sweeps - 1
-// times { psi += solve32(r); r = b - A psi }; phi = psi + lift (sweeps >= 1).
-// norms[0..1] receive ||r||^2, ||b||^2 of the last sweep; norms[2..] hold 2
-// partials per residual block: ceil(nx ny / 256) blocks per interior plane.
+// FP32 solves refined in FP64, starting from the psi the previous solve left
+// (zero after loading): r = b - A psi; then up to `sweeps` times
+// { psi += solve32(r); r = b - A psi }, stopping once ||r|| <= tol ||b||;
+// phi = psi + lift.  The charge moves little in one step, so the previous
+// potential is a close guess and each FP32 sweep gains its ~1e-7 on a small
+// correction.  Every sweep is launched (a captured step replays the same
+// kernels); the kernels of a sweep after convergence return at once on
+// ctl[0].  norms[0..1] receive ||r||^2, ||b||^2 of the last residual formed;
+// norms[2..] hold 2 partials per residual block: ceil(nx ny / 256) blocks per
+// interior plane; ctl as in norm_reduce_kernel.
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
                           const void* tw_y32, const void* inv32, double* phi, RfDrive rf,
-                          int sweeps, double* norms, hipStream_t st) {
+                          int sweeps, double tol, double* norms, int* ctl, hipStream_t st) {
   const long plane = (long)nx * ny;
-  const double* rhs = b;
-  for (int it = 0; it < sweeps; ++it) {
-    solve_once<float>(P, nx, ny, nz, rhs, work32, tw_x32, tw_y32, inv32,
-                      it == 0 ? OUT_REAL_STORE : OUT_REAL_ACCUM, psi, rf, st);
-    if (it + 1 < sweeps) {
-      hipLaunchKernelGGL(residual_kernel<false>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi,
-                         b, r, nx, ny, nz - 1, norms + 2);
-    } else {
-      hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi,
-                         b, r, nx, ny, nz - 1, norms + 2);
-      hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2,
-                         nb256(plane) * (nz - 1), norms);
-    }
-    rhs = r;
+  const int nb = (int)(nb256(plane) * (nz - 1));
+  hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi, b,
+                     r, nx, ny, nz - 1, norms + 2, nullptr);
+  hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb, norms, ctl,
+                     tol * tol, 0, 0);
+  for (int it = 1; it <= sweeps; ++it) {
+    solve_once<float>(P, nx, ny, nz, r, work32, tw_x32, tw_y32, inv32, OUT_REAL_ACCUM, psi, rf, st,
+                      ctl);
+    hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi,
+                       b, r, nx, ny, nz - 1, norms + 2, ctl);
+    hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb, norms, ctl,
+                       tol * tol, it, it == sweeps ? 1 : 0);
   }
   hipLaunchKernelGGL(lift_kernel, dim3(nb256(plane), nz + 1), dim3(256), 0, st, psi, phi, nx, ny, nz,
                      rf);

@@ -960,7 +960,7 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
   __syncthreads();
   // event counts per thread, one byte per status, added up every 32 passes
   unsigned long long packed = 0ull;
-  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0, n_out = 0;
+  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0, n_out = 0, n_fast = 0;
   for (int base = beg, pass = 0; base < end; base += kChunk, ++pass) {
     // tile ranges are multiples of 4 slots: a thread's four slots are all in
     // the tile or all beyond it
@@ -1024,6 +1024,7 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
       }
       st[q] = push_one_f32(S, ec, o[q], v[q], ci, cj, ck);
       cell[q] = st[q] == ST_ALIVE ? pack_cell(ci, cj, ck) : -1;
+      n_fast += v[q][0] * v[q][0] + v[q][1] * v[q][1] + v[q][2] * v[q][2] >= S.vfast2_f;
     }
     if (kMove) {
       // collision candidates of the survivors: word 0 of Philox(id, k, COLL, s)
@@ -1094,6 +1095,7 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
     tally_add(sm.tally, TL_MD, n_md);
     tally_add(sm.tally, TL_DEAD, n_w0 + n_w1 + n_bad);
     tally_add(sm.tally, TL_FALL, n_out);
+    tally_add(sm.tally, TL_FAST, n_fast);
   }
   __syncthreads();
   // the window holds the magnitudes; the species' sign is applied here
@@ -1193,7 +1195,7 @@ __global__ __launch_bounds__(kBlock, 3) void push_f64_kernel(PartF64 P, const do
     s_nout = 0;
   }
   __syncthreads();
-  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0, n_out = 0;
+  int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0, n_out = 0, n_fast = 0;
   for (int base = beg; base < end; base += kChunk) {
     const int p0 = base + kPPT * (int)threadIdx.x;
     const bool have = p0 < end;  // four slots in the tile, or none
@@ -1267,6 +1269,7 @@ __global__ __launch_bounds__(kBlock, 3) void push_f64_kernel(PartF64 P, const do
         }
       }
       st[q] = push_one_f64(S, Ep, x[q], v[q]);
+      n_fast += v[q][0] * v[q][0] + v[q][1] * v[q][1] + v[q][2] * v[q][2] >= S.vfast2;
       if (st[q] == ST_ALIVE) {
         cell[q] = pack_cell((int)floor(x[q][0]), (int)floor(x[q][1]), (int)floor(x[q][2]));
         const uint4 r = philox4x32_10(id[q], *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
@@ -1345,6 +1348,7 @@ __global__ __launch_bounds__(kBlock, 3) void push_f64_kernel(PartF64 P, const do
     tally_add(s_tally, TL_MD, n_md);
     tally_add(s_tally, TL_DEAD, n_w0 + n_w1 + n_bad);
     tally_add(s_tally, TL_FALL, n_out);
+    tally_add(s_tally, TL_FAST, n_fast);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < vol; t += kBlock) {
@@ -1757,7 +1761,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> 
   const int count = L.out_cnt[tidx];
   if (count == 0) return;
   const int32_t* seg = L.out + L.tstart[tidx];
-  int t_w0 = 0, t_w1 = 0, t_bad = 0, t_coll = 0, t_cap = 0;
+  int t_w0 = 0, t_w1 = 0, t_bad = 0, t_coll = 0, t_cap = 0, t_fast = 0;
   for (int idx = threadIdx.x; idx < count; idx += 64) {
     const long p = seg[idx];
     const int c = P.cell[p];
@@ -1776,6 +1780,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> 
       ec[t][2] = e.z;
     }
     const int st = push_one_f32(S, ec, o, v, ci, cj, ck);
+    t_fast += v[0] * v[0] + v[1] * v[1] + v[2] * v[2] >= S.vfast2_f;
     if (st == ST_ALIVE) {
       bool coll = false, capv = false;
       if (do_mcc) {
@@ -1805,6 +1810,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> 
   t_bad = wave_sum(t_bad);
   t_coll = wave_sum(t_coll);
   t_cap = wave_sum(t_cap);
+  t_fast = wave_sum(t_fast);
   if (threadIdx.x == 0) {
     unsigned long long* tl = L.tally + (long)TL_N * tidx;
     tl[TL_W0] += t_w0;
@@ -1813,6 +1819,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> 
     tl[TL_COLL] += t_coll;
     tl[TL_CAP] += t_cap;
     tl[TL_DEAD] += t_w0 + t_w1 + t_bad;
+    tl[TL_FAST] += t_fast;
   }
 }
 
@@ -1827,7 +1834,7 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(SpeciesPair<PartF64> pr
   const int count = L.out_cnt[tidx];
   if (count == 0) return;
   const int32_t* seg = L.out + L.tstart[tidx];
-  int t_w0 = 0, t_w1 = 0, t_bad = 0, t_coll = 0, t_cap = 0;
+  int t_w0 = 0, t_w1 = 0, t_bad = 0, t_coll = 0, t_cap = 0, t_fast = 0;
   for (int idx = threadIdx.x; idx < count; idx += 64) {
     const long p = seg[idx];
     double x[3], v[3];
@@ -1836,6 +1843,7 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(SpeciesPair<PartF64> pr
     double Ep[3];
     gather_d(E, S, i0, j0, k0, x[0] - i0, x[1] - j0, x[2] - k0, Ep);
     const int st = push_one_f64(S, Ep, x, v);
+    t_fast += v[0] * v[0] + v[1] * v[1] + v[2] * v[2] >= S.vfast2;
     if (st == ST_ALIVE) {
       bool coll = false, capv = false;
       if (do_mcc) {
@@ -1864,6 +1872,7 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(SpeciesPair<PartF64> pr
   t_bad = wave_sum(t_bad);
   t_coll = wave_sum(t_coll);
   t_cap = wave_sum(t_cap);
+  t_fast = wave_sum(t_fast);
   if (threadIdx.x == 0) {
     unsigned long long* tl = L.tally + (long)TL_N * tidx;
     tl[TL_W0] += t_w0;
@@ -1872,6 +1881,7 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(SpeciesPair<PartF64> pr
     tl[TL_COLL] += t_coll;
     tl[TL_CAP] += t_cap;
     tl[TL_DEAD] += t_w0 + t_w1 + t_bad;
+    tl[TL_FAST] += t_fast;
   }
 }
 

@@ -69,6 +69,7 @@ struct Replica {
   void* inv = nullptr;
   FftPlanHost fft{};
   double* norms = nullptr;
+  int* refine_ctl = nullptr;  // FP32R refinement: [0] converged, [1] sweeps, [2] unconverged solves
   double* tot64 = nullptr;
   long long* totfx = nullptr;
   double* eout = nullptr;
@@ -277,7 +278,10 @@ int validate(const pic_config& c, std::string& why) {
   if (!std::isfinite(c.V_dc) || !std::isfinite(c.V_rf) || !std::isfinite(c.f_rf))
     return bad("rf drive must be finite");
   if (c.precision != PIC_FP64 && c.precision != PIC_FP32R) return bad("unknown precision");
-  if (c.precision == PIC_FP32R && c.max_refine < 1) return bad("max_refine must be >= 1");
+  if (c.precision == PIC_FP32R && (c.max_refine < 1 || c.max_refine > 16))
+    return bad("max_refine must be 1..16");
+  if (c.precision == PIC_FP32R && !(std::isfinite(c.refine_tol) && c.refine_tol >= 0))
+    return bad("refine_tol must be >= 0");
   if (c.md_subcycles < 1) return bad("md_subcycles must be >= 1");
   if (c.pp_cutoff_cells < 0) return bad("pp_cutoff_cells must be >= 0");
   if (c.n_grains < 0 || c.n_grains > 4096) return bad("n_grains out of range");
@@ -298,6 +302,13 @@ int validate(const pic_config& c, std::string& why) {
   if (c.coulomb_interval < 0) return bad("coulomb_interval must be >= 0");
   if (c.coulomb_interval > 0 && !(std::isfinite(c.coulomb_lnL) && c.coulomb_lnL > 0))
     return bad("coulomb_lnL must be > 0");
+  // The fixed-point deposit forms Qp * f24 in int64 (f24 < 2^24), so the
+  // macro charge Qp = w 2^32 must stay below 2^39: a weight w below 128.
+  const double w = c.n0 * c.dx * c.dx * c.dx / (double)c.ppc;
+  if (!(std::isfinite(w) && w * 4294967296.0 < 549755813888.0)) {
+    why = "weight n0 dx^3 / ppc must be below 128 (fixed-point macro charge below 2^39)";
+    return PIC_ECONFIG;
+  }
   return PIC_OK;
 }
 
@@ -437,6 +448,11 @@ SpeciesStep species_step(const Replica& R, int sp) {
   S.h_dx = h / c.dx;
   S.qm_dt_f = (float)S.qm_dt;
   S.dt_dx_f = (float)S.dt_dx;
+  {
+    const double vf = c.pp_cutoff_cells * c.dx / c.dt;
+    S.vfast2 = c.n_grains > 0 ? vf * vf : HUGE_VAL;
+    S.vfast2_f = (float)S.vfast2;
+  }
   S.T_null = R.T_null[sp];
   S.g_cap = R.g_cap[sp];
   S.vth_gas = R.vth_gas;
@@ -558,7 +574,7 @@ int solve_fields(pic_ctx* ctx, Replica& R) {
     launch_grain_rhs(R.d_gc, R.md.gpos, c.n_grains, R.nx, R.ny, R.nz, R.we, R.d_Q, R.b, scale, 1,
                      R.Qp, st);
     launch_solve_refined(R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y, R.inv,
-                         R.phi, rf, c.max_refine, R.norms, st);
+                         R.phi, rf, c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st);
     launch_efield_f32(R.phi, (float*)R.E, R.nx, R.ny, R.nz, c.dx, st);
     launch_md_field(R.E, 0, R.md, R.nx, R.ny, st);
   }
@@ -1085,7 +1101,8 @@ double xs_bound(const std::vector<double>& xs, int n, int sp, double E_cap, doub
 
 int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   std::string why;
-  if (validate(cin, why) != PIC_OK) return fail(ctx, PIC_EINVAL, why);
+  const int vrc = validate(cin, why);
+  if (vrc != PIC_OK) return fail(ctx, vrc, why);
   R.cfg = cin;
   R.gpos.assign(cin.grain_pos, cin.grain_pos + 3 * (size_t)cin.n_grains);
   R.cfg.grain_pos = nullptr;
@@ -1172,6 +1189,7 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
     R.work = w;
     TRY(setup_solver_tables<float>(ctx, R, &R.tw_x, &R.tw_y, &R.inv));
     TRY(dalloc(ctx, R, &R.psi, R.n_int));
+    launch_zero_f64(R.psi, R.n_int, st);  // the first solve starts from psi = 0
     TRY(dalloc(ctx, R, &R.r, R.n_int));
   }
   TRY(dalloc(ctx, R, &R.b, R.n_int));
@@ -1184,6 +1202,8 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   TRY(dalloc(ctx, R, &R.d_sums, (nkey + 1023) / 1024 + 1));
   HIPCHK(ctx, hipMemsetAsync(R.d_gc, 0, 16 * std::max(c.n_grains, 1), st));
   HIPCHK(ctx, hipMemsetAsync(R.norms, 0, 16, st));
+  TRY(dalloc(ctx, R, &R.refine_ctl, 4));
+  HIPCHK(ctx, hipMemsetAsync(R.refine_ctl, 0, 16, st));
   if (c.coulomb_interval > 0) {
     for (int sp = 0; sp < 2; ++sp) {
       // cells in the tile order of the particle bins, 64 a tile
@@ -1228,6 +1248,142 @@ Replica* get_rep(pic_ctx* ctx, int replica) {
   if (!ctx || replica < 0 || replica >= (int)ctx->reps.size()) return nullptr;
   return ctx->reps[replica].get();
 }
+
+// Where pic_fields stages what it hands out: the context's buffers, allocated
+// on first use (sc == nullptr), or slices of a given device array of sc->cap
+// doubles, reused quantity by quantity.
+struct FieldStage {
+  double* base;
+  size_t cap;
+};
+
+int fields_impl(pic_ctx* ctx, Replica* R, unsigned what, void* const* out, int out_on_device,
+                const FieldStage* sc) {
+  if (!out || (what & ~511u)) return fail(ctx, PIC_EINVAL, "bad selection or out");
+  if ((what & PIC_RHO_FIXED) && R->prec != PIC_FP32R)
+    return fail(ctx, PIC_EINVAL, "PIC_RHO_FIXED needs the FP32R form");
+  if ((what & (PIC_FINE_N | PIC_FINE_FLUX | PIC_FINE_PHI)) && !R->fine_on)
+    return fail(ctx, PIC_ESTATE, "no fine grid: call pic_set_fine_grid");
+  {
+    int slot = 0;
+    for (unsigned bit = 1; bit <= PIC_FINE_PHI; bit <<= 1)
+      if ((what & bit) && !out[slot++]) return fail(ctx, PIC_EINVAL, "NULL output buffer");
+  }
+  hipStream_t st = ctx->stream;
+  TRY(solve_fields(ctx, *R));
+  const long nn = R->nn;
+  double* tot64 = nullptr;
+  long long* totfx = nullptr;
+  double* eout = nullptr;
+  if (sc) {
+    tot64 = sc->base;
+    totfx = (long long*)(sc->base + nn);
+    eout = sc->base;
+  } else {
+    if (!R->tot64) TRY(dalloc(ctx, *R, &R->tot64, nn));
+    if (!R->totfx) TRY(dalloc(ctx, *R, &R->totfx, nn));
+    if (!R->eout) TRY(dalloc(ctx, *R, &R->eout, 3 * nn));
+    tot64 = R->tot64;
+    totfx = R->totfx;
+    eout = R->eout;
+  }
+  const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const double vol = R->cfg.dx * R->cfg.dx * R->cfg.dx;
+  // densities and fluxes of one species into mom [4][nn] (W, then v W), scaled
+  auto moments_of = [&](int sp, double* mom) {
+    launch_zero_f64(mom, 4 * nn, st);
+    const SpeciesStep S = species_step(*R, sp);
+    if (R->prec == PIC_FP64)
+      launch_moments(&R->p64[sp][R->cur[sp]], nullptr, S, R->lists[sp], mom, nn, AvgBins{}, st);
+    else
+      launch_moments(nullptr, &R->p32[sp][R->cur[sp]], S, R->lists[sp], mom, nn, AvgBins{}, st);
+    launch_scale(mom, nullptr, R->w / vol, mom, 4 * nn, st);
+  };
+  if ((what & (PIC_N | PIC_FLUX)) && !sc) {
+    if (!R->mom) TRY(dalloc(ctx, *R, &R->mom, 8 * nn));
+    for (int sp = 0; sp < 2; ++sp) moments_of(sp, R->mom + 4 * nn * sp);
+    CHECK_LAUNCH(ctx);
+  }
+  const long fn = R->fine.fn;
+  if (what & (PIC_FINE_N | PIC_FINE_FLUX)) {
+    if (!R->fine_mom) TRY(dalloc(ctx, *R, &R->fine_mom, 8 * fn));
+    launch_zero_f64(R->fine_mom, 8 * fn, st);
+    TRY(enqueue_fine(ctx, *R, R->fine_mom, AvgBins{}));
+    const double hdx = R->fine.h * R->cfg.dx;
+    launch_scale(R->fine_mom, nullptr, R->w / (hdx * hdx * hdx), R->fine_mom, 8 * fn, st);
+    CHECK_LAUNCH(ctx);
+  }
+  if (what & PIC_FINE_PHI) {
+    if (!R->fine_phi) TRY(dalloc(ctx, *R, &R->fine_phi, fn));
+    launch_fine_phi(R->phi, R->md, R->Uphi, R->fine, R->nx, R->ny, R->nz, R->cfg.dx,
+                    R->cfg.grain_radius, R->fine_phi, AvgBins{}, st);
+    CHECK_LAUNCH(ctx);
+  }
+  int slot = 0, slot_n = -1, slot_flux = -1;
+  for (unsigned bit = 1; bit <= PIC_FINE_PHI; bit <<= 1) {
+    if (!(what & bit)) continue;
+    if (bit == PIC_N) slot_n = slot;
+    if (bit == PIC_FLUX) slot_flux = slot;
+    ++slot;
+  }
+  slot = 0;
+  for (unsigned bit = 1; bit <= PIC_FINE_PHI; bit <<= 1) {
+    if (!(what & bit)) continue;
+    void* dst = out[slot++];
+    if (bit == PIC_FINE_PHI) {
+      HIPCHK(ctx, hipMemcpyAsync(dst, R->fine_phi, fn * 8, kind, st));
+    } else if (bit == PIC_FINE_N || bit == PIC_FINE_FLUX) {
+      const long len = bit == PIC_FINE_FLUX ? 3 * fn : fn;
+      for (int sp = 0; sp < 2; ++sp)
+        HIPCHK(ctx, hipMemcpyAsync((char*)dst + sp * len * 8,
+                                   R->fine_mom + (4 * sp + (bit == PIC_FINE_FLUX ? 1 : 0)) * fn,
+                                   len * 8, kind, st));
+    } else if (bit == PIC_PHI) {
+      HIPCHK(ctx, hipMemcpyAsync(dst, R->phi, nn * 8, kind, st));
+    } else if ((bit == PIC_N || bit == PIC_FLUX) && sc) {
+      // one species at a time through the scratch, both quantities at once
+      if (bit == PIC_FLUX && slot_n >= 0) continue;  // already handed out with N
+      for (int sp = 0; sp < 2; ++sp) {
+        moments_of(sp, sc->base);
+        if (slot_n >= 0)
+          HIPCHK(ctx, hipMemcpyAsync((char*)out[slot_n] + sp * nn * 8, sc->base, nn * 8, kind,
+                                     st));
+        if (slot_flux >= 0)
+          HIPCHK(ctx, hipMemcpyAsync((char*)out[slot_flux] + 3 * sp * nn * 8, sc->base + nn,
+                                     3 * nn * 8, kind, st));
+      }
+    } else if (bit == PIC_N) {
+      for (int sp = 0; sp < 2; ++sp)
+        HIPCHK(ctx, hipMemcpyAsync((char*)dst + sp * nn * 8, R->mom + 4 * nn * sp, nn * 8, kind, st));
+    } else if (bit == PIC_FLUX) {
+      for (int sp = 0; sp < 2; ++sp)
+        HIPCHK(ctx, hipMemcpyAsync((char*)dst + 3 * sp * nn * 8, R->mom + (4 * sp + 1) * nn,
+                                   3 * nn * 8, kind, st));
+    } else if (bit == PIC_E) {
+      launch_e_out(R->prec == PIC_FP64 ? (const double*)R->E : nullptr,
+                   R->prec == PIC_FP64 ? nullptr : (const float*)R->E, eout, nn, st);
+      HIPCHK(ctx, hipMemcpyAsync(dst, eout, 3 * nn * 8, kind, st));
+    } else {
+      if (R->prec == PIC_FP64) {
+        launch_rho_total((const double*)R->rho[R->rho_cur], nullptr, tot64, nullptr, R->d_gc,
+                         R->md.gpos, R->cfg.n_grains, R->nx, R->ny, nn, R->Qp, st);
+        launch_scale(tot64, nullptr, R->we / vol, tot64, nn, st);
+      } else {
+        launch_rho_total(nullptr, (const long long*)R->rho[R->rho_cur], nullptr, totfx,
+                         R->d_gc, R->md.gpos, R->cfg.n_grains, R->nx, R->ny, nn, R->Qp, st);
+        launch_scale(nullptr, totfx, kCharge / 4294967296.0 / vol, tot64, nn, st);
+      }
+      if (bit == PIC_RHO)
+        HIPCHK(ctx, hipMemcpyAsync(dst, tot64, nn * 8, kind, st));
+      else
+        HIPCHK(ctx, hipMemcpyAsync(dst, totfx, nn * 8, kind, st));
+    }
+    CHECK_LAUNCH(ctx);
+  }
+  if (!out_on_device) HIPCHK(ctx, hipStreamSynchronize(st));
+  return PIC_OK;
+}
+
 
 }  // namespace
 
@@ -1300,93 +1456,7 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
   if (ctx->sticky) return ctx->sticky;
   Replica* R = get_rep(ctx, replica);
   if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
-  if (!out || (what & ~511u)) return fail(ctx, PIC_EINVAL, "bad selection or out");
-  if ((what & PIC_RHO_FIXED) && R->prec != PIC_FP32R)
-    return fail(ctx, PIC_EINVAL, "PIC_RHO_FIXED needs the FP32R form");
-  if ((what & (PIC_FINE_N | PIC_FINE_FLUX | PIC_FINE_PHI)) && !R->fine_on)
-    return fail(ctx, PIC_ESTATE, "no fine grid: call pic_set_fine_grid");
-  hipStream_t st = ctx->stream;
-  TRY(solve_fields(ctx, *R));
-  const long nn = R->nn;
-  if (!R->tot64) TRY(dalloc(ctx, *R, &R->tot64, nn));
-  if (!R->totfx) TRY(dalloc(ctx, *R, &R->totfx, nn));
-  if (!R->eout) TRY(dalloc(ctx, *R, &R->eout, 3 * nn));
-  const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  int slot = 0;
-  const double vol = R->cfg.dx * R->cfg.dx * R->cfg.dx;
-  if (what & (PIC_N | PIC_FLUX)) {
-    if (!R->mom) TRY(dalloc(ctx, *R, &R->mom, 8 * nn));
-    launch_zero_f64(R->mom, 8 * nn, st);
-    for (int sp = 0; sp < 2; ++sp) {
-      const SpeciesStep S = species_step(*R, sp);
-      double* m = R->mom + 4 * nn * sp;
-      if (R->prec == PIC_FP64)
-        launch_moments(&R->p64[sp][R->cur[sp]], nullptr, S, R->lists[sp], m, nn, AvgBins{}, st);
-      else
-        launch_moments(nullptr, &R->p32[sp][R->cur[sp]], S, R->lists[sp], m, nn, AvgBins{}, st);
-    }
-    launch_scale(R->mom, nullptr, R->w / vol, R->mom, 8 * nn, st);
-    CHECK_LAUNCH(ctx);
-  }
-  const long fn = R->fine.fn;
-  if (what & (PIC_FINE_N | PIC_FINE_FLUX)) {
-    if (!R->fine_mom) TRY(dalloc(ctx, *R, &R->fine_mom, 8 * fn));
-    launch_zero_f64(R->fine_mom, 8 * fn, st);
-    TRY(enqueue_fine(ctx, *R, R->fine_mom, AvgBins{}));
-    const double hdx = R->fine.h * R->cfg.dx;
-    launch_scale(R->fine_mom, nullptr, R->w / (hdx * hdx * hdx), R->fine_mom, 8 * fn, st);
-    CHECK_LAUNCH(ctx);
-  }
-  if (what & PIC_FINE_PHI) {
-    if (!R->fine_phi) TRY(dalloc(ctx, *R, &R->fine_phi, fn));
-    launch_fine_phi(R->phi, R->md, R->Uphi, R->fine, R->nx, R->ny, R->nz, R->cfg.dx,
-                    R->cfg.grain_radius, R->fine_phi, AvgBins{}, st);
-    CHECK_LAUNCH(ctx);
-  }
-  for (unsigned bit = 1; bit <= PIC_FINE_PHI; bit <<= 1) {
-    if (!(what & bit)) continue;
-    void* dst = out[slot++];
-    if (!dst) return fail(ctx, PIC_EINVAL, "NULL output buffer");
-    if (bit == PIC_FINE_PHI) {
-      HIPCHK(ctx, hipMemcpyAsync(dst, R->fine_phi, fn * 8, kind, st));
-    } else if (bit == PIC_FINE_N || bit == PIC_FINE_FLUX) {
-      const long len = bit == PIC_FINE_FLUX ? 3 * fn : fn;
-      for (int sp = 0; sp < 2; ++sp)
-        HIPCHK(ctx, hipMemcpyAsync((char*)dst + sp * len * 8,
-                                   R->fine_mom + (4 * sp + (bit == PIC_FINE_FLUX ? 1 : 0)) * fn,
-                                   len * 8, kind, st));
-    } else if (bit == PIC_PHI) {
-      HIPCHK(ctx, hipMemcpyAsync(dst, R->phi, nn * 8, kind, st));
-    } else if (bit == PIC_N) {
-      for (int sp = 0; sp < 2; ++sp)
-        HIPCHK(ctx, hipMemcpyAsync((char*)dst + sp * nn * 8, R->mom + 4 * nn * sp, nn * 8, kind, st));
-    } else if (bit == PIC_FLUX) {
-      for (int sp = 0; sp < 2; ++sp)
-        HIPCHK(ctx, hipMemcpyAsync((char*)dst + 3 * sp * nn * 8, R->mom + (4 * sp + 1) * nn,
-                                   3 * nn * 8, kind, st));
-    } else if (bit == PIC_E) {
-      launch_e_out(R->prec == PIC_FP64 ? (const double*)R->E : nullptr,
-                   R->prec == PIC_FP64 ? nullptr : (const float*)R->E, R->eout, nn, st);
-      HIPCHK(ctx, hipMemcpyAsync(dst, R->eout, 3 * nn * 8, kind, st));
-    } else {
-      if (R->prec == PIC_FP64) {
-        launch_rho_total((const double*)R->rho[R->rho_cur], nullptr, R->tot64, nullptr, R->d_gc,
-                         R->md.gpos, R->cfg.n_grains, R->nx, R->ny, nn, R->Qp, st);
-        launch_scale(R->tot64, nullptr, R->we / vol, R->tot64, nn, st);
-      } else {
-        launch_rho_total(nullptr, (const long long*)R->rho[R->rho_cur], nullptr, R->totfx,
-                         R->d_gc, R->md.gpos, R->cfg.n_grains, R->nx, R->ny, nn, R->Qp, st);
-        launch_scale(nullptr, R->totfx, kCharge / 4294967296.0 / vol, R->tot64, nn, st);
-      }
-      if (bit == PIC_RHO)
-        HIPCHK(ctx, hipMemcpyAsync(dst, R->tot64, nn * 8, kind, st));
-      else
-        HIPCHK(ctx, hipMemcpyAsync(dst, R->totfx, nn * 8, kind, st));
-    }
-    CHECK_LAUNCH(ctx);
-  }
-  if (!out_on_device) HIPCHK(ctx, hipStreamSynchronize(st));
-  return PIC_OK;
+  return fields_impl(ctx, R, what, out, out_on_device, nullptr);
 }
 
 int pic_average(pic_ctx* ctx, int interval, int phase_bins) {
@@ -1717,10 +1787,10 @@ int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out) {
   Replica* R = get_rep(ctx, replica);
   if (!R || !out) return fail(ctx, PIC_EINVAL, "bad replica or out");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  int n[16];
   double norms[2] = {0, 0};
-  HIPCHK(ctx, hipMemcpy(n, R->d_cnt, sizeof(n), hipMemcpyDeviceToHost));
+  int ctl[4] = {0, 0, 0, 0};
   HIPCHK(ctx, hipMemcpy(norms, R->norms, sizeof(norms), hipMemcpyDeviceToHost));
+  HIPCHK(ctx, hipMemcpy(ctl, R->refine_ctl, sizeof(ctl), hipMemcpyDeviceToHost));
   std::memset(out, 0, sizeof(*out));
   for (int sp = 0; sp < 2; ++sp) {
     unsigned long long t[TL_N];
@@ -1733,9 +1803,11 @@ int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out) {
     out->wall_count[1][sp] = R->wall_base[1][sp] + (int64_t)t[TL_W1];
     out->numeric_bad += (int64_t)t[TL_BAD];
     out->tile_fallback += (int64_t)t[TL_FALL];
+    out->md_margin[sp] = (int64_t)t[TL_FAST];
   }
   out->step = R->step;
-  out->refine_sweeps = R->prec == PIC_FP32R ? R->cfg.max_refine : 0;
+  out->refine_sweeps = R->prec == PIC_FP32R ? ctl[1] : 0;
+  out->refine_unconverged = R->prec == PIC_FP32R ? ctl[2] : 0;
   out->refine_residual = norms[1] > 0 ? std::sqrt(norms[0] / norms[1]) : std::sqrt(norms[0]);
   if (R->coul.count) {
     unsigned long long nc = 0;

@@ -57,8 +57,9 @@ struct WorkLists {
   int ngrid;          // tiles rounded up to a multiple of 8
 };
 
-// per-tile event counts, accumulated since loading; TL_DEAD counts removed particles
-enum TallyKind { TL_W0 = 0, TL_W1, TL_BAD, TL_MD, TL_FALL, TL_COLL, TL_CAP, TL_DEAD, TL_N };
+// per-tile event counts, accumulated since loading; TL_DEAD counts removed
+// particles; TL_FAST counts plain (not sub-cycled) pushes with |v| dt >= cutoff dx
+enum TallyKind { TL_W0 = 0, TL_W1, TL_BAD, TL_MD, TL_FALL, TL_COLL, TL_CAP, TL_DEAD, TL_FAST, TL_N };
 
 // near-grain (MD) tables of one replica
 struct MdTables {
@@ -91,6 +92,10 @@ struct SpeciesStep {
   double qm_h, h_dx;       // the same for the MD sub-step h = dt / md_sub
   double qm;               // q/m
   float qm_dt_f, dt_dx_f;
+  // a plain push with |v|^2 >= vfast2 ((cutoff dx / dt)^2; +inf without
+  // grains) moves far enough to cross a grain outside its MD cube
+  double vfast2;
+  float vfast2_f;
   // null-collision MCC
   uint64_t T_null;         // candidate iff Philox word 0 < T_null
   double g_cap;            // relative-speed cap

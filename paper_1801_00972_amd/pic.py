@@ -76,6 +76,7 @@ class pic_counters(C.Structure):
         ("md_particles", C.c_int64 * 2),
         ("step", C.c_uint32), ("refine_sweeps", C.c_int32), ("refine_residual", C.c_double),
         ("numeric_bad", C.c_int64), ("tile_fallback", C.c_int64), ("n_coulomb", C.c_int64),
+        ("refine_unconverged", C.c_int64), ("md_margin", C.c_int64 * 2),
     ]
 
 
@@ -141,7 +142,7 @@ def _check(rc, ctx=None):
         raise PicError(rc, msg.decode() if msg else "error")
 
 
-def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 2):
+def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 3):
     """pic_config from a workload dict; returns (config, keep-alive arrays)."""
     g = np.ascontiguousarray(np.asarray(wl.get("grain_pos", np.zeros((0, 3))), np.float64).reshape(-1, 3))
     c = pic_config()
@@ -312,7 +313,8 @@ def pic_get_counters(ctx, replica):
                 md_particles=list(c.md_particles), step=int(c.step),
                 refine_sweeps=int(c.refine_sweeps), refine_residual=float(c.refine_residual),
                 numeric_bad=int(c.numeric_bad), tile_fallback=int(c.tile_fallback),
-                n_coulomb=int(c.n_coulomb))
+                n_coulomb=int(c.n_coulomb), refine_unconverged=int(c.refine_unconverged),
+                md_margin=list(c.md_margin))
 
 
 def pic_derived(ctx, replica):
@@ -364,7 +366,7 @@ def pic_autotune(ctx, trial_steps=48, capacity=64):
 class Simulation:
     """One context over one or more replicas (workload dicts)."""
 
-    def __init__(self, workloads, stream=None, sort_interval=8, max_refine=2):
+    def __init__(self, workloads, stream=None, sort_interval=8, max_refine=3):
         if isinstance(workloads, dict):
             workloads = [workloads]
         self.wls = list(workloads)

@@ -86,3 +86,30 @@ def test_workload_configs_are_consistent():
             d = ((g[:, None, :] - g[None, :, :]) ** 2).sum(-1) ** 0.5
             assert d[d > 0].min() >= 200e-6 / wl["dx"] - 1e-9
     assert W.small_fp64()["grain_pos"].tolist() == [[8.0, 8.0, 16.0]]
+
+
+def test_weight_of_128_or_more_is_rejected(lib):
+    """The fixed-point deposit forms Qp * f24 in int64 with f24 < 2^24, so the
+    macro charge Qp = w 2^32 must stay below 2^39 (w < 128): the oracle's
+    derivation refuses it, and pic_init returns PIC_ECONFIG before any device
+    call (so this runs without a GPU)."""
+    import oracle
+    from paper_1801_00972_amd import pic
+    from paper_1801_00972_amd import workloads as W
+    wl = W.small_fp64()
+    n_at = 128.0 * wl["ppc"] / wl["dx"] ** 3
+    L = pic.lib()
+    for n0, ok in ((n_at * (1 - 1e-9), True), (n_at, False), (n_at * 1.5, False)):
+        o = oracle.Oracle(dict(wl, n0=n0))
+        if ok:
+            d = o.derived()
+            assert d["Qp"] < 2 ** 39 and 2 ** 39 - d["Qp"] < 2 ** 39 * 1e-8
+            continue
+        with pytest.raises(ValueError):
+            o.derived()
+        c, keep = pic.make_config(dict(wl, n0=n0))
+        out = C.c_void_p()
+        rc = L.pic_init(C.byref(c), 1, None, C.byref(out))
+        assert rc == pic.PIC_ECONFIG
+        assert not out.value
+        assert "below 128" in pic.pic_last_error(None)

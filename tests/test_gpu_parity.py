@@ -282,12 +282,70 @@ def test_fixed_point_total_charge_is_exact():
 
 
 def test_fp32r_refinement_reaches_tolerance():
+    """The refinement stops at ||b - A phi|| <= refine_tol ||b|| (1e-10), within
+    max_refine sweeps; a solve that cannot reach it is counted; refine_tol 0
+    always takes every sweep."""
     wl = W.small_fp32r()
-    sim = _sim(wl, max_refine=2)
+    sim = _sim(wl, max_refine=3)
     sim.step(3)
     c = sim.counters()
-    print("  refine residual", c["refine_residual"])
+    print("  refine residual", c["refine_residual"], "sweeps", c["refine_sweeps"])
     assert c["refine_residual"] <= 1e-10
+    assert 1 <= c["refine_sweeps"] <= 3
+    assert c["refine_unconverged"] == 0
+    sim.close()
+    # one FP32 sweep from psi = 0 (residual ~1e-7) does not reach 1e-10: counted
+    sim = _sim(wl, max_refine=1)
+    sim.step(1)
+    c = sim.counters()
+    assert c["refine_sweeps"] == 1 and c["refine_unconverged"] == 1
+    assert c["refine_residual"] > 1e-10
+    sim.close()
+    sim = _sim(dict(wl, refine_tol=0.0), max_refine=3)
+    sim.step(2)
+    c = sim.counters()
+    assert c["refine_sweeps"] == 3 and c["refine_unconverged"] == 2
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32r"])
+def test_md_margin_counter_matches_oracle(prec):
+    """Plain pushes that move at least cutoff cells in one step (a grain could
+    be crossed outside its MD cube) are counted, as the oracle counts them:
+    hot electrons and a 20 ps step make most of them that fast at cutoff 1."""
+    wl = W.tiny(nx=12, ny=10, nz=14, ppc=2, grains=[[6.0, 5.0, 7.0]], cutoff=1, Te_eV=30.0,
+                dt=2e-11, precision=prec)
+    sim = _sim(wl)
+    st = _random_state(wl, 3000, 500, seed=11)
+    sim.set_state(st)
+    orc = oracle_from_state(wl, sim.get_state())
+    sim.step(1)
+    orc.step(1)
+    c = sim.counters()
+    print("  md_margin", c["md_margin"], "oracle", orc.md_margin, flush=True)
+    assert c["md_margin"][0] > 500
+    assert c["md_margin"] == orc.md_margin
+    sim.close()
+    # without grains nothing is counted
+    wl0 = dict(wl, grain_pos=np.zeros((0, 3)))
+    sim = _sim(wl0)
+    sim.set_state(_random_state(wl0, 3000, 500, seed=11))
+    sim.step(1)
+    assert sim.counters()["md_margin"] == [0, 0]
+    sim.close()
+
+
+def test_weight_just_below_the_fixed_point_bound_runs():
+    """w = n0 dx^3 / ppc just under 128 (macro charge just under 2^39 in
+    2^-32 e): accepted, and the fixed-point deposit stays exact."""
+    wl = W.tiny(nx=8, ny=8, nz=10, ppc=1, precision="fp32r")
+    wl["n0"] = 128.0 * (1 - 1e-9) / wl["dx"] ** 3
+    sim = _sim(wl)
+    sim.step(2)
+    from paper_1801_00972_amd.pic import PIC_RHO_FIXED
+    orc = oracle_from_state(wl, sim.get_state())
+    g = sim.fields(0, PIC_RHO_FIXED)
+    assert np.array_equal(g["rho_fixed"], orc.fields(fixed_point=True)["rho_fixed"])
     sim.close()
 
 
