@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
-NO_MESH, NO_MCC, FIXED_POINT, FROZEN_Q = 1, 2, 4, 8
+NO_MESH, NO_MCC, FIXED_POINT, FROZEN_Q, IMMOBILE_IONS, NO_MD = 1, 2, 4, 8, 16, 32
 
 
 def build(verbose: bool = False, native: bool = False, out: str | None = None) -> str:
@@ -141,6 +141,9 @@ def lib():
         L.orc_unit_fields.argtypes = [C.POINTER(_Config), dp]
         L.orc_md_grains.argtypes = [C.POINTER(_Config), C.c_int, C.c_int, C.c_int,
                                     C.POINTER(C.c_int), C.c_int]
+        L.orc_oml_collect.argtypes = [C.POINTER(_Config), C.c_int, C.c_double, C.c_int64, dp, dp,
+                                      C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.orc_oml_collect.restype = C.c_int64
         L.orc_step.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp]
         L.orc_step_in_field.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp, dp]
         _lib = L
@@ -453,6 +456,21 @@ class Oracle:
     def coulomb_var(self, sa: int, sb: int, u: float, nL: float, dtc: float) -> float:
         return float(lib().orc_coulomb_var(C.byref(self.cfg), sa, sb, float(u), float(nL),
                                            float(dtc)))
+
+    def oml_collect(self, species: int, R_c: float, pos, vel, max_calls: int):
+        """OML test mode (grain charging, Sec. IV.B): test particles moved in
+        the field of grain 0 alone (charge Q_frozen_e e, no mesh, no
+        collisions) until the grain absorbs them or they leave the sphere of
+        R_c cells around it.  Returns (absorbed, left, still inside)."""
+        pos = np.ascontiguousarray(pos, np.float64).copy()
+        vel = np.ascontiguousarray(vel, np.float64).copy()
+        n_out, n_open = C.c_int64(0), C.c_int64(0)
+        hits = lib().orc_oml_collect(C.byref(self.cfg), int(species), float(R_c), len(pos),
+                                     _ptr(pos, C.c_double), _ptr(vel, C.c_double), int(max_calls),
+                                     C.byref(n_out), C.byref(n_open))
+        if hits < 0:
+            raise RuntimeError(f"orc_oml_collect failed ({hits})")
+        return int(hits), int(n_out.value), int(n_open.value)
 
     def step(self, n: int = 1):
         U = self._units()

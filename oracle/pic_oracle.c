@@ -1166,15 +1166,20 @@ static int move_all(const orc_config* c, orc_state* s, const double* E, const do
 #pragma omp parallel for schedule(dynamic, 4096) reduction(+ : wall[:2], fast)
     for (int64_t p = 0; p < s->n[sp]; ++p) {
       if (!s->alive[sp][p]) continue;
+      if (sp == 1 && (c->flags & ORC_IMMOBILE_IONS)) continue;
       double* x = &s->pos[sp][3 * p];
       double* v = &s->vel[sp][3 * p];
       double margin = INFINITY;
       int G[1];
-      int nG = orc_md_grains(c, (int)floor(x[0]), (int)floor(x[1]), (int)floor(x[2]), G, 1);
+      int nG = (c->flags & ORC_NO_MD) ? 0
+                                      : orc_md_grains(c, (int)floor(x[0]), (int)floor(x[1]),
+                                                      (int)floor(x[2]), G, 1);
       int hit = -1, st;
       if (nG == 0) {
         st = move_plain(c, Euse, qm, x, v, &margin);
-        if (c->n_grains > 0 && v[0] * v[0] + v[1] * v[1] + v[2] * v[2] >= vfast * vfast) fast += 1;
+        if (c->n_grains > 0 && !(c->flags & ORC_NO_MD) &&
+            v[0] * v[0] + v[1] * v[1] + v[2] * v[2] >= vfast * vfast)
+          fast += 1;
       } else
         st = move_md(c, Euse, Uuse, Q, qm, x, v, &margin, &hit);
       if (st == MV_WALL0 || st == MV_WALL1) {
@@ -1195,6 +1200,58 @@ static int move_all(const orc_config* c, orc_state* s, const double* E, const do
   }
   s->step = k + 1;
   return 0;
+}
+
+/* Test mode for the orbit-motion-limited (OML) pin of grain charging
+ * (Sec. IV.B): test particles of species sp start at pos/vel (cell units,
+ * m/s; n of them) and move in the field of grain 0 alone -- charge
+ * c->Q_frozen_e e, no mesh field, no collisions -- by the MD sub-step of
+ * Eq. (5)-(6) (move_md with the configuration's dt and md_sub), with its
+ * grain test, until the grain absorbs them or they are farther than R_c
+ * cells from it; outside that sphere the grain's field counts as zero, so a
+ * particle that leaves does not come back.  The caller takes md_sub = 1 so
+ * that the sphere is tested after every sub-step.  A particle still inside
+ * after max_calls calls of move_md counts in *n_open.  Returns the number
+ * absorbed, *n_out those that left, or a negative error.  pos/vel end with
+ * the final states. */
+int64_t orc_oml_collect(const orc_config* c, int sp, double R_c, int64_t n, double* pos,
+                        double* vel, int64_t max_calls, int64_t* n_out, int64_t* n_open)
+{
+  orc_derived d;
+  if (orc_derive(c, &d) || c->n_grains < 1 || sp < 0 || sp > 1) return -1;
+  double Q[64];
+  for (int g = 0; g < c->n_grains && g < 64; ++g) Q[g] = g == 0 ? c->Q_frozen_e * O_ECHARGE : 0.0;
+  const double qm = d.q[sp] / d.m[sp];
+  int64_t hits = 0, outs = 0, open = 0, bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : hits, outs, open, bad)
+  for (int64_t p = 0; p < n; ++p) {
+    double* x = &pos[3 * p];
+    double* v = &vel[3 * p];
+    int64_t call = 0;
+    int fate = 0; /* 0 inside, 1 absorbed, 2 left */
+    for (; call < max_calls && fate == 0; ++call) {
+      double margin = INFINITY;
+      int hit = -1;
+      int st = move_md(c, NULL, NULL, Q, qm, x, v, &margin, &hit);
+      if (st == MV_GRAIN) {
+        fate = hit == 0 ? 1 : 3;
+      } else if (st != MV_ALIVE) {
+        fate = 3;
+      } else {
+        double r[3];
+        separation(c, 0, x[0], x[1], x[2], r);
+        if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > R_c * R_c) fate = 2;
+      }
+    }
+    if (fate == 1) hits += 1;
+    else if (fate == 2) outs += 1;
+    else if (fate == 0) open += 1;
+    else bad += 1;
+  }
+  if (bad) return -2;
+  if (n_out) *n_out = outs;
+  if (n_open) *n_open = open;
+  return hits;
 }
 
 int orc_step_in_field(const orc_config* c, orc_state* s, const double* E, const double* U)

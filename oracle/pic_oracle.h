@@ -38,6 +38,9 @@ extern "C" {
 #define ORC_NO_MCC       2  /* no collisions */
 #define ORC_FIXED_POINT  4  /* CIC deposit in int64 fixed point (2^-32 e units) */
 #define ORC_FROZEN_Q     8  /* grain charges do not change when particles hit */
+#define ORC_IMMOBILE_IONS 16 /* ions are deposited but never moved or collided */
+#define ORC_NO_MD       32  /* grains act only as CIC charges on the mesh: no MD
+                               region, no sub-cycling, no absorption */
 
 typedef struct orc_config {
   int32_t nx, ny, nz;        /* cells; x,y periodic, z bounded by two electrodes */
@@ -158,6 +161,14 @@ int orc_fine_phi(const orc_config* c, const orc_state* s, const double* phi,
                  double* out);
 /* grains whose MD cube contains cell (i,j,k): writes indices, returns the count */
 int orc_md_grains(const orc_config* c, int i, int j, int k, int* out, int cap);
+
+/* OML test mode (grain charging, Sec. IV.B): test particles of species sp
+ * moved in the field of grain 0 alone (charge Q_frozen_e e, no mesh, no
+ * collisions) by the MD sub-step until absorbed or farther than R_c cells from
+ * the grain; returns the number absorbed, *n_out those that left, *n_open
+ * those still inside after max_calls sub-step calls (see pic_oracle.c) */
+int64_t orc_oml_collect(const orc_config* c, int sp, double R_c, int64_t n, double* pos,
+                        double* vel, int64_t max_calls, int64_t* n_out, int64_t* n_open);
 
 /* one full time step k -> k+1 (deposit, solve, field, move, absorb, collide);
  * U: the grains' unit fields from orc_unit_fields (nullable without grains) */
