@@ -227,6 +227,26 @@ int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C);
 int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int out_on_device);
 
 /*
+ * pic_fields_static -- pic_fields for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same quantities, order and layouts, but staged in a
+ * fixed device array of the library (48 MiB, 6 Mi doubles, one per GPU, held
+ * until the process ends) instead of context buffers allocated on first use;
+ * the call itself allocates nothing.  Only PIC_PHI, PIC_E, PIC_RHO,
+ * PIC_RHO_FIXED, PIC_N and PIC_FLUX are accepted; the selection must fit
+ * the array: 4 doubles per node with N or FLUX, else 3 with E, 2 with RHO or
+ * RHO_FIXED (N or FLUX up to 1,572,864 nodes).  Every call on a GPU uses
+ * that GPU's one array, so calls that overlap on one GPU (several streams,
+ * threads or contexts) race; calls ordered on one stream do not.  With
+ * out_on_device = 1 the call is stream-ordered and does not synchronise.
+ * Errors: as pic_fields, plus PIC_EINVAL (a bit outside the list, or a
+ * selection larger than the array) and PIC_ESTATE (the array's address could
+ * not be resolved at pic_init).
+ */
+int pic_fields_static(pic_ctx* ctx, int replica, unsigned what, void* const* out,
+                      int out_on_device);
+
+/*
  * Time- and rf-phase-averaged diagnostics (the averaged densities, fluxes and
  * potential of the paper's results, Sec. IV: ion fluxes averaged over rf
  * periods, electron fluxes resolved in rf phase).

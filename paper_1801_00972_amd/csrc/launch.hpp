@@ -6,6 +6,14 @@
 
 namespace pic {
 
+// the fixed device scratch array of pic_fields_static (scratch.hip): doubles
+// per GPU, 48 MiB; scratch_setup resolves its address on the current device
+// (once per device, returns 0 on success), scratch_address returns the kept
+// address of a device (nullptr before its set-up)
+constexpr size_t kScratchDoubles = size_t(6) << 20;
+int scratch_setup(int* device_out, void** addr_out);
+void* scratch_address(int device);
+
 // factorisation of the FFT line lengths and lines per block
 struct FftPlanHost {
   int nfac_x, fac_x[12];

@@ -143,6 +143,10 @@ struct pic_ctx {
   PushDescF32* d_desc = nullptr;
   int32_t* d_start = nullptr;
   int n_cu = 256;
+  // device of the context, and whether the fixed scratch array of
+  // pic_fields_static has its address resolved there
+  int device = -1;
+  bool scratch_ok = false;
   // per-step GPU timing of the autotuner: events around each step's launches
   std::vector<hipEvent_t>* step_ev = nullptr;
   size_t step_ev_used = 0;
@@ -1250,8 +1254,8 @@ Replica* get_rep(pic_ctx* ctx, int replica) {
 }
 
 // Where pic_fields stages what it hands out: the context's buffers, allocated
-// on first use (sc == nullptr), or slices of a given device array of sc->cap
-// doubles, reused quantity by quantity.
+// on first use (sc == nullptr), or slices of a caller-given device array of
+// sc->cap doubles (pic_fields_static), reused quantity by quantity.
 struct FieldStage {
   double* base;
   size_t cap;
@@ -1412,6 +1416,9 @@ int pic_init(const pic_config* cfgs, int n_replicas, void* hip_stream, pic_ctx**
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
       ncu > 0)
     ctx->n_cu = ncu;
+  // the address of the fixed scratch array on this device (once per device);
+  // without it only pic_fields_static is unavailable
+  ctx->scratch_ok = scratch_setup(&ctx->device, nullptr) == 0;
   if (build_batch(ctx.get()) != PIC_OK) {
     g_init_error = ctx->err;
     return PIC_EDEVICE;
@@ -1457,6 +1464,33 @@ int pic_fields(pic_ctx* ctx, int replica, unsigned what, void* const* out, int o
   Replica* R = get_rep(ctx, replica);
   if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
   return fields_impl(ctx, R, what, out, out_on_device, nullptr);
+}
+
+int pic_fields_static(pic_ctx* ctx, int replica, unsigned what, void* const* out,
+                      int out_on_device) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
+  const unsigned allowed = PIC_PHI | PIC_E | PIC_RHO | PIC_RHO_FIXED | PIC_N | PIC_FLUX;
+  if (what & ~allowed)
+    return fail(ctx, PIC_EINVAL, "pic_fields_static: only PHI, E, RHO, RHO_FIXED, N and FLUX");
+  const size_t nn = (size_t)R->nn;
+  size_t need = 0;
+  if (what & (PIC_N | PIC_FLUX)) need = std::max(need, 4 * nn);
+  if (what & PIC_E) need = std::max(need, 3 * nn);
+  if (what & (PIC_RHO | PIC_RHO_FIXED)) need = std::max(need, 2 * nn);
+  if (need > kScratchDoubles)
+    return fail(ctx, PIC_EINVAL,
+                "pic_fields_static: the selection needs " + std::to_string(need) +
+                    " doubles of scratch, the fixed array holds " +
+                    std::to_string(kScratchDoubles) + " (at most " +
+                    std::to_string(kScratchDoubles / 4) + " nodes with N or FLUX)");
+  void* base = ctx->scratch_ok ? scratch_address(ctx->device) : nullptr;
+  if (!base)
+    return fail(ctx, PIC_ESTATE, "pic_fields_static: the scratch array's address is unknown");
+  const FieldStage sc{(double*)base, kScratchDoubles};
+  return fields_impl(ctx, R, what, out, out_on_device, &sc);
 }
 
 int pic_average(pic_ctx* ctx, int interval, int phase_bins) {

@@ -25,7 +25,8 @@ PIC_MAX_FINE_NODES = 1 << 26
 SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destroy",
            "pic_last_error", "pic_get_state", "pic_set_state", "pic_get_counters", "pic_derived",
            "pic_profile_enable", "pic_profile_read", "pic_get_tuning", "pic_set_tuning",
-           "pic_autotune", "pic_average", "pic_average_read", "pic_set_fine_grid")
+           "pic_autotune", "pic_average", "pic_average_read", "pic_set_fine_grid",
+           "pic_fields_static")
 PIC_MAX_PHASE_BINS = 64
 PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT, PIC_PROF_LISTS, PIC_PROF_COULOMB = 0, 1, 2, 3, 4
 
@@ -109,6 +110,7 @@ def lib():
         L.pic_step.argtypes = [P, C.c_int]
         L.pic_grain_charges.argtypes = [P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.pic_fields.argtypes = [P, C.c_int, C.c_uint, C.POINTER(P), C.c_int]
+        L.pic_fields_static.argtypes = [P, C.c_int, C.c_uint, C.POINTER(P), C.c_int]
         L.pic_destroy.argtypes = [P]
         L.pic_destroy.restype = None
         L.pic_last_error.argtypes = [P]
@@ -130,7 +132,7 @@ def lib():
         for name in ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_get_state",
                      "pic_set_state", "pic_get_counters", "pic_derived", "pic_profile_enable",
                      "pic_profile_read", "pic_get_tuning", "pic_set_tuning", "pic_autotune",
-                     "pic_average", "pic_average_read", "pic_set_fine_grid"):
+                     "pic_average", "pic_average_read", "pic_set_fine_grid", "pic_fields_static"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -218,6 +220,14 @@ def pic_fields(ctx, replica, what, outs, out_on_device=False):
     for i, o in enumerate(outs):
         ptrs[i] = o.data_ptr() if hasattr(o, "data_ptr") else o.ctypes.data
     _check(lib().pic_fields(ctx, replica, what, ptrs, 1 if out_on_device else 0), ctx)
+
+
+def pic_fields_static(ctx, replica, what, outs, out_on_device=False):
+    """pic_fields staged in the library's fixed device array (allocates nothing)."""
+    ptrs = (C.c_void_p * len(outs))()
+    for i, o in enumerate(outs):
+        ptrs[i] = o.data_ptr() if hasattr(o, "data_ptr") else o.ctypes.data
+    _check(lib().pic_fields_static(ctx, replica, what, ptrs, 1 if out_on_device else 0), ctx)
 
 
 def pic_average(ctx, interval, phase_bins=1):
