@@ -113,7 +113,8 @@ typedef struct pic_config {
   double refine_tol;           /* FP32R: the refinement stops once ||b - A phi|| <= refine_tol ||b||
                                   (b with the electrode lift; 0: always max_refine sweeps) */
   uint64_t seed;               /* Philox key of the replica */
-  const double* grain_pos;     /* host pointer, [n_grains][3], cell units */
+  const double* grain_pos;     /* host pointer, [n_grains][3], cell units; NULL: seeded
+                                  placement (cluster_center, cluster_radius, grain_min_sep) */
   int32_t coulomb_interval;    /* steps between Coulomb-collision passes (0: none) */
   int32_t reserved0;           /* 0 */
   double coulomb_lnL;          /* Coulomb logarithm (> 0 when coulomb_interval > 0) */
@@ -138,6 +139,19 @@ typedef struct pic_config {
   const double* xs_i_cx;       /* [xs_n] Ar+-Ar charge exchange, m^2 */
   const double* xs_i_el;       /* [xs_n] Ar+-Ar elastic, m^2, nullable (none) */
   double E_ex_eV;              /* excitation energy (>= 0) */
+  /* seeded grain placement, used when grain_pos is NULL and n_grains > 0 (the
+   * paper's 44 measured positions exist only in a figure): the grains are
+   * uniform in the sphere of cluster_radius around cluster_center (cell
+   * units), drawn by rejection with every grain at least grain_min_sep (cell
+   * units) from the grains placed before it; candidate t of grain g takes
+   * the uniforms u_a = (w_a + 1/2) 2^-32 of Philox4x32-10 words 0..2 of the
+   * counter (g, t, 7, 0) under `seed` and proposes x_a = c_a + R (2 u_a - 1)
+   * (FP64, no fused multiply-adds).  pic_grain_positions returns them.
+   * PIC_ECONFIG if a grain finds no room in 2^20 candidates; the placed grains
+   * must satisfy the grain_pos rules above. */
+  double cluster_center[3];
+  double cluster_radius;
+  double grain_min_sep;
 } pic_config;
 #define PIC_MAX_XS 4096
 
@@ -205,6 +219,20 @@ int pic_step(pic_ctx* ctx, int n_steps);
  * coulomb (host buffer of n_grains doubles).  Synchronises the stream.
  */
 int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C);
+
+/*
+ * pic_energy -- FP64 energy diagnostic of a replica at the current step k
+ * (solving for E_k if needed): out[0], out[1] the kinetic energies
+ * sum_p (1/2) m_s w |v_p|^2 of the electrons and ions (J; v at k - 1/2, as
+ * stored), out[2] the field energy (eps0 / 2) sum_n |E_n|^2 V_n (J; E_k as
+ * stored, V_n = dx^3, half on the two electrode planes), out[3] their sum.
+ * Summed in FP64 in a fixed order (repeatable).  Synchronises the stream.
+ */
+int pic_energy(pic_ctx* ctx, int replica, double out[4]);
+
+/* pic_grain_positions -- the grains of a replica, [n_grains][3] in cell units
+ * (host buffer): grain_pos as given, or the seeded placement's result. */
+int pic_grain_positions(pic_ctx* ctx, int replica, double* pos);
 
 /*
  * pic_fields -- the mesh quantities at the current step k for the current
@@ -334,6 +362,31 @@ const char* pic_last_error(const pic_ctx* ctx);
  */
 int pic_get_state(pic_ctx* ctx, int replica, pic_state_view* view);
 int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* view);
+
+/*
+ * Checkpoints (exact resume of the long runs of hundreds of rf periods that
+ * the paper's results average over, Sec. IV.A).
+ * pic_save writes every replica's state to the file `path` (written to
+ * path.tmp, then renamed): the particles as pic_get_state gives them, the
+ * step k, grain and electrode counts, the event counters, and in the FP32R
+ * form the potential the next field solve starts from, together with each
+ * replica's configuration.  pic_load replaces every replica's state with a
+ * checkpoint's; the context must come from pic_init with the same
+ * configurations (same order).  Counters continue from the saved values.
+ * Philox draws depend on (seed, id, step) only, so a run of 2n steps and a
+ * run of n steps, saved, loaded into a new context and continued for n
+ * steps give the same particles: bit for bit in the FP32R form, to round-off
+ * in the FP64 form (its deposit adds in floating point in an order that
+ * depends on the particles' array order).  Launch settings, the time
+ * averages and the fine grid are not part of a checkpoint.
+ * pic_load reads and checks the whole file before it changes any replica.
+ * Errors: PIC_EINVAL (NULL path, unreadable or unwritable file, not a
+ * checkpoint, truncated), PIC_ECONFIG (another number of replicas or a
+ * configuration that differs), PIC_ESTATE (pic_load while averaging runs),
+ * PIC_EDEVICE.
+ */
+int pic_save(pic_ctx* ctx, const char* path);
+int pic_load(pic_ctx* ctx, const char* path);
 
 /* pic_get_counters -- per-replica diagnostics; synchronises the stream. */
 int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out);

@@ -144,6 +144,7 @@ def lib():
         L.orc_oml_collect.argtypes = [C.POINTER(_Config), C.c_int, C.c_double, C.c_int64, dp, dp,
                                       C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.orc_oml_collect.restype = C.c_int64
+        L.orc_place_grains.argtypes = [C.c_uint64, C.c_int, dp, C.c_double, C.c_double, dp]
         L.orc_step.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp]
         L.orc_step_in_field.argtypes = [C.POINTER(_Config), C.POINTER(_State), dp, dp]
         _lib = L
@@ -162,8 +163,14 @@ class Oracle:
     def __init__(self, wl: dict, flags: int = 0, Q_frozen_e: float = 0.0):
         self.wl = dict(wl)
         self.flags = flags
-        self.grain_pos = np.ascontiguousarray(
-            np.asarray(wl.get("grain_pos", np.zeros((0, 3))), dtype=np.float64).reshape(-1, 3))
+        if wl.get("grain_pos") is None and wl.get("cluster"):
+            cl = wl["cluster"]  # seeded placement (the oracle's own implementation)
+            self.grain_pos = place_grains(int(wl.get("seed", 0)), int(cl["n"]), cl["center"],
+                                          float(cl["radius"]), float(cl.get("min_sep", 0.0)))
+        else:
+            g = wl.get("grain_pos")
+            self.grain_pos = np.ascontiguousarray(
+                np.asarray(np.zeros((0, 3)) if g is None else g, dtype=np.float64).reshape(-1, 3))
         cfg = _Config()
         cfg.nx, cfg.ny, cfg.nz = int(wl["nx"]), int(wl["ny"]), int(wl["nz"])
         cfg.ppc_e = cfg.ppc_i = int(wl["ppc"])
@@ -487,6 +494,18 @@ class Oracle:
                                          _ptr(E, C.c_double), _ptr(U, C.c_double))
             if rc:
                 raise RuntimeError(f"orc_step_in_field failed ({rc})")
+
+
+def place_grains(seed: int, n: int, center, radius: float, min_sep: float) -> np.ndarray:
+    """Seeded grain placement: n grains uniform in a sphere (cell units) with
+    a minimum separation, by rejection on Philox draws (see pic_oracle.h)."""
+    c = np.ascontiguousarray(center, np.float64)
+    out = np.zeros((n, 3))
+    rc = lib().orc_place_grains(int(seed), int(n), _ptr(c, C.c_double), float(radius),
+                                float(min_sep), _ptr(out, C.c_double))
+    if rc:
+        raise ValueError("grain placement failed: no room at the minimum separation")
+    return out
 
 
 def philox4x32_10(ctr, key):

@@ -25,7 +25,7 @@
 
 /* Philox counter word 2: what a draw is for */
 enum { PUR_INIT_POS = 1, PUR_INIT_VEL = 2, PUR_COLL = 3, PUR_NEUTRAL = 4, PUR_CORDER = 5,
-       PUR_CPAIR = 6 };
+       PUR_CPAIR = 6, PUR_GRAIN = 7 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32  */
@@ -71,6 +71,41 @@ static void box_muller(uint32_t wa, uint32_t wb, double* n0, double* n1)
   double th = 2.0 * O_PI * ub;
   *n0 = r * cos(th);
   *n1 = r * sin(th);
+}
+
+/* ------------------------------------------------------------------------ */
+/* seeded grain placement (the paper's cluster of Sec. II is known only from  */
+/* a figure): uniform in a sphere by rejection, with a minimum separation     */
+/* from the grains placed before; candidate t of grain g proposes             */
+/* x_a = c_a + R (2 u_a - 1) from words 0..2 of Philox(g, t, GRAIN, 0).        */
+/* ------------------------------------------------------------------------ */
+int orc_place_grains(uint64_t seed, int n, const double center[3], double radius, double min_sep,
+                     double* out)
+{
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  for (int g = 0; g < n; ++g) {
+    int placed = 0;
+    for (uint32_t t = 0; t < (1u << 20) && !placed; ++t) {
+      uint32_t ctr[4] = {(uint32_t)g, t, PUR_GRAIN, 0u}, w[4];
+      orc_philox4x32_10(ctr, key, w);
+      double p[3];
+      for (int a = 0; a < 3; ++a) p[a] = center[a] + radius * (2.0 * unif_open(w[a]) - 1.0);
+      double r2 = 0.0;
+      for (int a = 0; a < 3; ++a) r2 += (p[a] - center[a]) * (p[a] - center[a]);
+      if (r2 > radius * radius) continue;
+      int far = 1;
+      for (int h = 0; h < g && far; ++h) {
+        double q2 = 0.0;
+        for (int a = 0; a < 3; ++a) q2 += (p[a] - out[3 * h + a]) * (p[a] - out[3 * h + a]);
+        far = q2 >= min_sep * min_sep;
+      }
+      if (!far) continue;
+      for (int a = 0; a < 3; ++a) out[3 * g + a] = p[a];
+      placed = 1;
+    }
+    if (!placed) return -1;
+  }
+  return 0;
 }
 
 /* ------------------------------------------------------------------------ */

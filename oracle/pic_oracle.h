@@ -111,6 +111,14 @@ int  orc_derive(const orc_config* c, orc_derived* d);
 double orc_rf_voltage(const orc_config* c, uint32_t k);
 int64_t orc_n_nodes(const orc_config* c);
 
+/* seeded grain placement: n grains uniform in the sphere of `radius` around
+ * `center` (cell units) by rejection, each at least min_sep from the grains
+ * placed before it; candidate t of grain g proposes c + R (2u - 1) from words
+ * 0..2 of Philox(g, t, 7, 0) under `seed`.  out: [n][3]; -1 if a grain finds
+ * no room in 2^20 candidates. */
+int orc_place_grains(uint64_t seed, int n, const double center[3], double radius, double min_sep,
+                     double* out);
+
 /* particle loading: fills pos/vel/id for n = nx*ny*nz*ppc particles per species */
 int orc_init_particles(const orc_config* c, orc_state* s);
 

@@ -13,8 +13,9 @@ namespace pic {
 // products of counter words 0 and 2 with the published multipliers, xor-mixed
 // with the other words and the round key; the key advances by the Weyl
 // constants after each round.
-__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1) {
+// (also used on the host, for the seeded grain placement)
+__host__ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                        uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     // each 32x32 -> 64-bit product is one multiply-add instruction

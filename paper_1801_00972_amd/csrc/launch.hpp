@@ -121,6 +121,13 @@ void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L,
 void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const WorkLists& L, int* hist,
                       int* sums, long capacity, hipStream_t st);
 void launch_fill_int(int* a, long n, int v, hipStream_t st);
+// FP64 energy diagnostic: per-block sums (energy_blocks() of them) of |v|^2
+// over a species' live particles, and of |E|^2 times each node's share of a
+// cell volume over the mesh (E as stored: double pairs if e_f64, else float4)
+int energy_blocks();
+void launch_energy(const PartF64* P64, const PartF32R* P32, const WorkLists& L, double* out,
+                   hipStream_t st);
+void launch_field_energy(const void* E, int e_f64, long nxy, int nz, double* out, hipStream_t st);
 void launch_advance_step(uint32_t* step, hipStream_t st);
 
 // mesh

@@ -2379,6 +2379,52 @@ __global__ void advance_step_kernel(uint32_t* step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1u;
 }
 
+// ---------------------------------------------------------------- energy
+// FP64 energy diagnostic.  Per block: the sum of |v|^2 over the live slots it
+// strides (kinetic), or of |E|^2 times the node's share of a cell volume (half
+// on the two electrode planes) over the nodes it strides (field); block b
+// writes out[b].  A fixed grid and order make the sums repeatable.
+constexpr int kEnergyBlocks = 1024;
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double s_w[kBlock / 64];
+  v = wave_sum_t<double>(v);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) t += s_w[w];
+  return t;
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void kinetic_kernel(PT P, const int32_t* __restrict__ cnt,
+                                                         double* __restrict__ out) {
+  const long slots = cnt[0];
+  double s = 0.0;
+  for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < slots; p += (long)gridDim.x * kBlock) {
+    if (!slot_alive(P, p)) continue;
+    const double vx = P.vx[p], vy = P.vy[p], vz = P.vz[p];
+    s += vx * vx + vy * vy + vz * vz;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+template <typename ET>
+__global__ __launch_bounds__(kBlock) void field_energy_kernel(const ET* __restrict__ E, long nxy,
+                                                              int nz, double* __restrict__ out) {
+  const long nn = nxy * (nz + 1);
+  double s = 0.0;
+  for (long n = (long)blockIdx.x * kBlock + threadIdx.x; n < nn; n += (long)gridDim.x * kBlock) {
+    double ex, ey, ez;
+    load_node(E, n, ex, ey, ez);
+    const long k = n / nxy;
+    s += (k == 0 || k == nz ? 0.5 : 1.0) * (ex * ex + ey * ey + ez * ez);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 // ---------------------------------------------------------------- launchers
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
@@ -2528,6 +2574,27 @@ void launch_fine_moments(const PartF64* P64, const PartF32R* P32, const WorkList
   else
     hipLaunchKernelGGL(fine_moments_kernel<PartF32R>, dim3(blocks), dim3(256), 0, st, *P32, L, fb,
                        mom, avg);
+}
+
+int energy_blocks() { return kEnergyBlocks; }
+
+void launch_energy(const PartF64* P64, const PartF32R* P32, const WorkLists& L, double* out,
+                   hipStream_t st) {
+  if (P64)
+    hipLaunchKernelGGL(kinetic_kernel<PartF64>, dim3(kEnergyBlocks), dim3(kBlock), 0, st, *P64,
+                       L.cnt, out);
+  else
+    hipLaunchKernelGGL(kinetic_kernel<PartF32R>, dim3(kEnergyBlocks), dim3(kBlock), 0, st, *P32,
+                       L.cnt, out);
+}
+
+void launch_field_energy(const void* E, int e_f64, long nxy, int nz, double* out, hipStream_t st) {
+  if (e_f64)
+    hipLaunchKernelGGL(field_energy_kernel<double2>, dim3(kEnergyBlocks), dim3(kBlock), 0, st,
+                       (const double2*)E, nxy, nz, out);
+  else
+    hipLaunchKernelGGL(field_energy_kernel<float4>, dim3(kEnergyBlocks), dim3(kBlock), 0, st,
+                       (const float4*)E, nxy, nz, out);
 }
 
 void launch_fill_int(int* a, long n, int v, hipStream_t st) {

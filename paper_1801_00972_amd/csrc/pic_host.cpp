@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "device_common.hpp"
 #include "launch.hpp"
 #include "pic.h"
 
@@ -74,6 +75,7 @@ struct Replica {
   long long* totfx = nullptr;
   double* eout = nullptr;
   double* mom = nullptr;  // [species][4][nn] moments for pic_fields
+  double* energy = nullptr;  // [3][energy_blocks()] partial sums of pic_energy
   // time averages (pic_average): per rf-phase bin [9][nn] sums of phi, then
   // W, v W of electrons and of ions; samples per bin; the read-out buffer
   double* avg = nullptr;
@@ -264,6 +266,60 @@ void periodic_bbox(const std::vector<char>& cov, int n, int* origin, int* size) 
   *size = n - best_len;
 }
 
+// Seeded grain placement (pic_config.grain_pos == NULL): uniform in the
+// sphere of cluster_radius around cluster_center (cell units) by rejection,
+// each candidate at least grain_min_sep from every grain placed before it.
+// Candidate t of grain g takes three uniforms u_a = (w_a + 1/2) 2^-32 from
+// Philox4x32-10 words 0..2 of the counter (g, t, purpose 7, 0) under the
+// replica's seed, and proposes x_a = c_a + R (2 u_a - 1).  The arithmetic is
+// kept free of fused multiply-adds so that any FP64 implementation of the
+// same steps gives the same bits.
+int place_grains(const pic_config& c, std::vector<double>& out, std::string& why) {
+#pragma clang fp contract(off)
+  const int ng = c.n_grains;
+  const double R = c.cluster_radius, R2 = R * R, d2 = c.grain_min_sep * c.grain_min_sep;
+  const uint32_t k0 = (uint32_t)(c.seed & 0xffffffffu), k1 = (uint32_t)(c.seed >> 32);
+  out.assign(3 * (size_t)ng, 0.0);
+  for (int g = 0; g < ng; ++g) {
+    bool placed = false;
+    for (uint32_t t = 0; t < (1u << 20) && !placed; ++t) {
+      const uint4 w = philox4x32_10((uint32_t)g, t, kGrain, 0u, k0, k1);
+      const uint32_t word[3] = {w.x, w.y, w.z};
+      double p[3];
+      for (int a = 0; a < 3; ++a) {
+        const double u = ((double)word[a] + 0.5) * 2.3283064365386962890625e-10;
+        const double s = 2.0 * u - 1.0;
+        const double off = R * s;
+        p[a] = c.cluster_center[a] + off;
+      }
+      double r2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        const double d = p[a] - c.cluster_center[a];
+        r2 += d * d;
+      }
+      if (r2 > R2) continue;
+      bool far = true;
+      for (int h = 0; h < g && far; ++h) {
+        double q2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          const double d = p[a] - out[3 * (size_t)h + a];
+          q2 += d * d;
+        }
+        far = q2 >= d2;
+      }
+      if (!far) continue;
+      for (int a = 0; a < 3; ++a) out[3 * (size_t)g + a] = p[a];
+      placed = true;
+    }
+    if (!placed) {
+      why = "grain placement failed: no room for grain " + std::to_string(g) +
+            " at the minimum separation";
+      return PIC_ECONFIG;
+    }
+  }
+  return PIC_OK;
+}
+
 int validate(const pic_config& c, std::string& why) {
   auto bad = [&](const std::string& s) { why = s; return PIC_EINVAL; };
   if (c.nx < 2 || c.ny < 2 || c.nz < 2) return bad("nx, ny, nz must be >= 2");
@@ -289,7 +345,15 @@ int validate(const pic_config& c, std::string& why) {
   if (c.md_subcycles < 1) return bad("md_subcycles must be >= 1");
   if (c.pp_cutoff_cells < 0) return bad("pp_cutoff_cells must be >= 0");
   if (c.n_grains < 0 || c.n_grains > 4096) return bad("n_grains out of range");
-  if (c.n_grains > 0 && !c.grain_pos) return bad("grain_pos is NULL");
+  if (c.n_grains > 0 && !c.grain_pos) {
+    // seeded placement: the cluster must be a sphere inside the box
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(c.cluster_center[a])) return bad("cluster_center must be finite");
+    if (!(std::isfinite(c.cluster_radius) && c.cluster_radius > 0))
+      return bad("cluster_radius must be > 0 (grain_pos is NULL)");
+    if (!(std::isfinite(c.grain_min_sep) && c.grain_min_sep >= 0))
+      return bad("grain_min_sep must be >= 0");
+  }
   if (c.n_grains > 0 && !(c.grain_radius > 0)) return bad("grain_radius must be > 0");
   if (c.sort_interval < 0) return bad("sort_interval must be >= 0");
   if (c.xs_n != 0) {
@@ -1108,7 +1172,12 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   const int vrc = validate(cin, why);
   if (vrc != PIC_OK) return fail(ctx, vrc, why);
   R.cfg = cin;
-  R.gpos.assign(cin.grain_pos, cin.grain_pos + 3 * (size_t)cin.n_grains);
+  if (cin.n_grains > 0 && !cin.grain_pos) {
+    const int prc = place_grains(cin, R.gpos, why);
+    if (prc != PIC_OK) return fail(ctx, prc, why);
+  } else {
+    R.gpos.assign(cin.grain_pos, cin.grain_pos + 3 * (size_t)cin.n_grains);
+  }
   R.cfg.grain_pos = nullptr;
   pic_config& c = R.cfg;
   R.nx = c.nx;
@@ -1389,6 +1458,76 @@ int fields_impl(pic_ctx* ctx, Replica* R, unsigned what, void* const* out, int o
 }
 
 
+// ---------------------------------------------------------------- checkpoints
+// Binary, native byte order: "PICCKPT1", n_replicas, then per replica its
+// configuration (the scalars below, the grain positions and the cross-section
+// tables, which a loading context must match), the step, grain and electrode
+// counts, the event-counter totals, and per species the particles as
+// pic_get_state gives them; FP32R adds the potential the next solve starts
+// from (psi), so a resumed run repeats the uninterrupted one bit for bit.
+struct CkptConfig {
+  int32_t nx, ny, nz, ppc, n_grains, cutoff, md_sub, precision, max_refine, coulomb_interval,
+      xs_n, pad;
+  double dx, dt, n0, Te, Ti, p_gas, T_gas, sig_e, sig_i, V_dc, V_rf, f_rf, radius, E_cap,
+      refine_tol, lnL, E_ex;
+  uint64_t seed;
+};
+
+CkptConfig ckpt_config(const Replica& R) {
+  const pic_config& c = R.cfg;
+  CkptConfig k;
+  std::memset(&k, 0, sizeof(k));
+  k.nx = c.nx;
+  k.ny = c.ny;
+  k.nz = c.nz;
+  k.ppc = c.ppc;
+  k.n_grains = c.n_grains;
+  k.cutoff = c.pp_cutoff_cells;
+  k.md_sub = c.md_subcycles;
+  k.precision = c.precision;
+  k.max_refine = c.max_refine;
+  k.coulomb_interval = c.coulomb_interval;
+  k.xs_n = c.xs_n;
+  k.dx = c.dx;
+  k.dt = c.dt;
+  k.n0 = c.n0;
+  k.Te = c.Te_eV;
+  k.Ti = c.Ti_eV;
+  k.p_gas = c.p_gas_Pa;
+  k.T_gas = c.T_gas_K;
+  k.sig_e = c.sigma_e_el;
+  k.sig_i = c.sigma_i_cx;
+  k.V_dc = c.V_dc;
+  k.V_rf = c.V_rf;
+  k.f_rf = c.f_rf;
+  k.radius = c.grain_radius;
+  k.E_cap = c.E_cap_eV;
+  k.refine_tol = c.refine_tol;
+  k.lnL = c.coulomb_lnL;
+  k.E_ex = c.E_ex_eV;
+  k.seed = c.seed;
+  return k;
+}
+
+constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '1'};
+constexpr int kCkptTallies[] = {TL_MD, TL_FALL, TL_COLL, TL_CAP, TL_BAD, TL_FAST};
+
+struct File {
+  FILE* f = nullptr;
+  ~File() {
+    if (f) std::fclose(f);
+  }
+};
+
+template <typename T>
+bool put(FILE* f, const T* p, size_t n) {
+  return n == 0 || std::fwrite(p, sizeof(T), n, f) == n;
+}
+template <typename T>
+bool get(FILE* f, T* p, size_t n) {
+  return n == 0 || std::fread(p, sizeof(T), n, f) == n;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -1455,6 +1594,49 @@ int pic_grain_charges(pic_ctx* ctx, int replica, int64_t* counts, double* Q_C) {
   HIPCHK(ctx, hipMemcpy(counts, R->d_gc, 16 * ng, hipMemcpyDeviceToHost));
   if (Q_C)
     for (int g = 0; g < ng; ++g) Q_C[g] = (double)(counts[2 * g + 1] - counts[2 * g]) * R->we;
+  return PIC_OK;
+}
+
+int pic_energy(pic_ctx* ctx, int replica, double out[4]) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R || !out) return fail(ctx, PIC_EINVAL, "bad replica or out");
+  const int nb = energy_blocks();
+  if (!R->energy) TRY(dalloc(ctx, *R, &R->energy, 3 * (size_t)nb));
+  TRY(solve_fields(ctx, *R));
+  for (int sp = 0; sp < 2; ++sp) {
+    if (R->prec == PIC_FP64)
+      launch_energy(&R->p64[sp][R->cur[sp]], nullptr, R->lists[sp], R->energy + sp * nb,
+                    ctx->stream);
+    else
+      launch_energy(nullptr, &R->p32[sp][R->cur[sp]], R->lists[sp], R->energy + sp * nb,
+                    ctx->stream);
+  }
+  launch_field_energy(R->E, R->prec == PIC_FP64, R->nxy, R->nz, R->energy + 2 * nb, ctx->stream);
+  CHECK_LAUNCH(ctx);
+  std::vector<double> h(3 * (size_t)nb);
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(h.data(), R->energy, h.size() * 8, hipMemcpyDeviceToHost));
+  double sum[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < 3; ++q)
+    for (int b = 0; b < nb; ++b) sum[q] += h[(size_t)q * nb + b];
+  const double vol = R->cfg.dx * R->cfg.dx * R->cfg.dx;
+  out[0] = 0.5 * R->m[0] * R->w * sum[0];
+  out[1] = 0.5 * R->m[1] * R->w * sum[1];
+  out[2] = 0.5 * kEps0 * vol * sum[2];
+  out[3] = out[0] + out[1] + out[2];
+  return PIC_OK;
+}
+
+int pic_grain_positions(pic_ctx* ctx, int replica, double* pos) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  Replica* R = get_rep(ctx, replica);
+  if (!R) return fail(ctx, PIC_EINVAL, "bad replica index");
+  if (R->cfg.n_grains == 0) return PIC_OK;
+  if (!pos) return fail(ctx, PIC_EINVAL, "pos is NULL");
+  std::copy(R->gpos.begin(), R->gpos.end(), pos);
   return PIC_OK;
 }
 
@@ -1812,6 +1994,170 @@ int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
   TRY(resort(ctx, *R));
   TRY(deposit_current(ctx, *R));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return PIC_OK;
+}
+
+int pic_save(pic_ctx* ctx, const char* path) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  if (!path) return fail(ctx, PIC_EINVAL, "path is NULL");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    File out;
+    out.f = std::fopen(tmp.c_str(), "wb");
+    if (!out.f) return fail(ctx, PIC_EINVAL, std::string("cannot write ") + tmp);
+    const uint32_t nrep = (uint32_t)ctx->reps.size();
+    bool ok = put(out.f, kCkptMagic, 8) && put(out.f, &nrep, 1);
+    for (uint32_t r = 0; ok && r < nrep; ++r) {
+      Replica& R = *ctx->reps[r];
+      const CkptConfig k = ckpt_config(R);
+      const int ng = R.cfg.n_grains;
+      ok = put(out.f, &k, 1) && put(out.f, R.gpos.data(), R.gpos.size()) &&
+           put(out.f, R.xs.data(), R.xs.size());
+      // particles and counts
+      pic_state_view v;
+      std::memset(&v, 0, sizeof(v));
+      std::vector<double> pos[2], vel[2];
+      std::vector<uint32_t> id[2];
+      for (int sp = 0; sp < 2; ++sp) {
+        v.capacity[sp] = R.cap[sp];
+        pos[sp].resize(3 * (size_t)R.cap[sp]);
+        vel[sp].resize(3 * (size_t)R.cap[sp]);
+        id[sp].resize((size_t)R.cap[sp]);
+        v.pos[sp] = pos[sp].data();
+        v.vel[sp] = vel[sp].data();
+        v.id[sp] = id[sp].data();
+      }
+      std::vector<int64_t> gc(2 * (size_t)std::max(ng, 1), 0);
+      v.grain_count = gc.data();
+      TRY(pic_get_state(ctx, (int)r, &v));
+      ok = ok && put(out.f, &v.step, 1) && put(out.f, gc.data(), 2 * (size_t)ng) &&
+           put(out.f, &v.wall_count[0][0], 4);
+      for (int sp = 0; ok && sp < 2; ++sp) {
+        unsigned long long t[TL_N];
+        TRY(read_tallies(ctx, R, sp, t));
+        for (int w : kCkptTallies) ok = ok && put(out.f, &t[w], 1);
+      }
+      unsigned long long n_coul = 0;
+      if (R.coul.count)
+        HIPCHK(ctx, hipMemcpy(&n_coul, R.coul.count, 8, hipMemcpyDeviceToHost));
+      int ctl[4] = {0, 0, 0, 0};
+      HIPCHK(ctx, hipMemcpy(ctl, R.refine_ctl, sizeof(ctl), hipMemcpyDeviceToHost));
+      ok = ok && put(out.f, &n_coul, 1) && put(out.f, &ctl[2], 1);
+      for (int sp = 0; ok && sp < 2; ++sp) {
+        const int64_t n = v.n[sp];
+        ok = put(out.f, &n, 1) && put(out.f, pos[sp].data(), 3 * (size_t)n) &&
+             put(out.f, vel[sp].data(), 3 * (size_t)n) && put(out.f, id[sp].data(), (size_t)n);
+      }
+      const int64_t npsi = R.prec == PIC_FP32R ? R.n_int : 0;
+      std::vector<double> psi((size_t)npsi);
+      if (npsi)
+        HIPCHK(ctx, hipMemcpy(psi.data(), R.psi, npsi * 8, hipMemcpyDeviceToHost));
+      ok = ok && put(out.f, &npsi, 1) && put(out.f, psi.data(), (size_t)npsi);
+    }
+    if (!ok || std::fflush(out.f) != 0) return fail(ctx, PIC_EINVAL, "writing " + tmp + " failed");
+  }
+  if (std::rename(tmp.c_str(), path) != 0)
+    return fail(ctx, PIC_EINVAL, std::string("cannot rename the checkpoint to ") + path);
+  return PIC_OK;
+}
+
+int pic_load(pic_ctx* ctx, const char* path) {
+  if (!ctx) return PIC_EINVAL;
+  if (ctx->sticky) return ctx->sticky;
+  if (!path) return fail(ctx, PIC_EINVAL, "path is NULL");
+  if (ctx->avg_interval > 0)
+    return fail(ctx, PIC_ESTATE, "averaging is running: stop it with pic_average(ctx, 0, 0)");
+  File in;
+  in.f = std::fopen(path, "rb");
+  if (!in.f) return fail(ctx, PIC_EINVAL, std::string("cannot read ") + path);
+  char magic[8];
+  uint32_t nrep = 0;
+  if (!get(in.f, magic, 8) || std::memcmp(magic, kCkptMagic, 8) != 0 || !get(in.f, &nrep, 1))
+    return fail(ctx, PIC_EINVAL, "not a checkpoint of this library");
+  if (nrep != ctx->reps.size())
+    return fail(ctx, PIC_ECONFIG, "the checkpoint holds another number of replicas");
+  // the whole file is read and checked before any replica changes
+  struct Saved {
+    pic_state_view v;
+    std::vector<int64_t> gc;
+    std::vector<double> pos[2], vel[2], psi;
+    std::vector<uint32_t> id[2];
+    unsigned long long t[2][6];
+    unsigned long long n_coul = 0;
+    int unconverged = 0;
+  };
+  std::vector<Saved> saved(nrep);
+  const std::string trunc = "checkpoint truncated";
+  for (uint32_t r = 0; r < nrep; ++r) {
+    Replica& R = *ctx->reps[r];
+    Saved& S = saved[r];
+    CkptConfig k;
+    if (!get(in.f, &k, 1)) return fail(ctx, PIC_EINVAL, trunc);
+    const CkptConfig mine = ckpt_config(R);
+    if (std::memcmp(&k, &mine, sizeof(k)) != 0)
+      return fail(ctx, PIC_ECONFIG, "replica " + std::to_string(r) +
+                                        ": the checkpoint's configuration differs");
+    std::vector<double> gpos(R.gpos.size()), xs(R.xs.size());
+    if (!get(in.f, gpos.data(), gpos.size()) || !get(in.f, xs.data(), xs.size()))
+      return fail(ctx, PIC_EINVAL, trunc);
+    if (gpos != R.gpos || xs != R.xs)
+      return fail(ctx, PIC_ECONFIG, "replica " + std::to_string(r) +
+                                        ": grain positions or cross sections differ");
+    const int ng = R.cfg.n_grains;
+    pic_state_view& v = S.v;
+    std::memset(&v, 0, sizeof(v));
+    S.gc.assign(2 * (size_t)std::max(ng, 1), 0);
+    if (!get(in.f, &v.step, 1) || !get(in.f, S.gc.data(), 2 * (size_t)ng) ||
+        !get(in.f, &v.wall_count[0][0], 4) || !get(in.f, &S.t[0][0], 12) ||
+        !get(in.f, &S.n_coul, 1) || !get(in.f, &S.unconverged, 1))
+      return fail(ctx, PIC_EINVAL, trunc);
+    for (int sp = 0; sp < 2; ++sp) {
+      int64_t n = 0;
+      if (!get(in.f, &n, 1)) return fail(ctx, PIC_EINVAL, trunc);
+      if (n < 0 || n > R.cap[sp] - 4L * R.ntiles)
+        return fail(ctx, PIC_EINVAL, "bad particle count in the checkpoint");
+      S.pos[sp].resize(3 * (size_t)n);
+      S.vel[sp].resize(3 * (size_t)n);
+      S.id[sp].resize((size_t)n);
+      if (!get(in.f, S.pos[sp].data(), 3 * (size_t)n) ||
+          !get(in.f, S.vel[sp].data(), 3 * (size_t)n) || !get(in.f, S.id[sp].data(), (size_t)n))
+        return fail(ctx, PIC_EINVAL, trunc);
+      v.n[sp] = v.capacity[sp] = n;
+    }
+    int64_t npsi = 0;
+    if (!get(in.f, &npsi, 1)) return fail(ctx, PIC_EINVAL, trunc);
+    if (npsi != (R.prec == PIC_FP32R ? R.n_int : 0))
+      return fail(ctx, PIC_EINVAL, "bad potential size in the checkpoint");
+    S.psi.resize((size_t)npsi);
+    if (!get(in.f, S.psi.data(), (size_t)npsi)) return fail(ctx, PIC_EINVAL, trunc);
+  }
+  char extra;
+  if (std::fread(&extra, 1, 1, in.f) != 0)
+    return fail(ctx, PIC_EINVAL, "trailing data in the checkpoint");
+  for (uint32_t r = 0; r < nrep; ++r) {
+    Replica& R = *ctx->reps[r];
+    Saved& S = saved[r];
+    for (int sp = 0; sp < 2; ++sp) {
+      S.v.pos[sp] = S.pos[sp].data();
+      S.v.vel[sp] = S.vel[sp].data();
+      S.v.id[sp] = S.id[sp].data();
+    }
+    S.v.grain_count = R.cfg.n_grains > 0 ? S.gc.data() : nullptr;
+    TRY(pic_set_state(ctx, (int)r, &S.v));
+    // the event totals continue: they go to the first tile's tally row
+    for (int sp = 0; sp < 2; ++sp) {
+      std::vector<unsigned long long> row(TL_N, 0ull);
+      for (int w = 0; w < 6; ++w) row[kCkptTallies[w]] = S.t[sp][w];
+      HIPCHK(ctx, hipMemcpy(R.lists[sp].tally, row.data(), 8 * TL_N, hipMemcpyHostToDevice));
+    }
+    if (R.coul.count) HIPCHK(ctx, hipMemcpy(R.coul.count, &S.n_coul, 8, hipMemcpyHostToDevice));
+    const int ctl[4] = {0, 0, S.unconverged, 0};
+    HIPCHK(ctx, hipMemcpy(R.refine_ctl, ctl, sizeof(ctl), hipMemcpyHostToDevice));
+    if (!S.psi.empty())
+      HIPCHK(ctx, hipMemcpy(R.psi, S.psi.data(), S.psi.size() * 8, hipMemcpyHostToDevice));
+  }
   return PIC_OK;
 }
 

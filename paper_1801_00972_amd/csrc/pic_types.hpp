@@ -15,7 +15,7 @@ constexpr double kMassAr = 39.948 * kAmu;
 constexpr double kPi = 3.14159265358979323846;
 
 // Philox counter word 2: what a draw is for
-enum Purpose : uint32_t { kInitPos = 1, kInitVel = 2, kColl = 3, kNeutral = 4 };
+enum Purpose : uint32_t { kInitPos = 1, kInitVel = 2, kColl = 3, kNeutral = 4, kGrain = 7 };
 
 // particle arrays of one species, structure of arrays
 struct PartF64 {

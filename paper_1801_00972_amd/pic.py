@@ -26,7 +26,8 @@ SYMBOLS = ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_destr
            "pic_last_error", "pic_get_state", "pic_set_state", "pic_get_counters", "pic_derived",
            "pic_profile_enable", "pic_profile_read", "pic_get_tuning", "pic_set_tuning",
            "pic_autotune", "pic_average", "pic_average_read", "pic_set_fine_grid",
-           "pic_fields_static")
+           "pic_fields_static", "pic_save", "pic_load", "pic_grain_positions",
+           "pic_energy")
 PIC_MAX_PHASE_BINS = 64
 PIC_PROF_PUSH, PIC_PROF_FIELD, PIC_PROF_SORT, PIC_PROF_LISTS, PIC_PROF_COULOMB = 0, 1, 2, 3, 4
 
@@ -56,6 +57,8 @@ class pic_config(C.Structure):
         ("xs_E", C.POINTER(C.c_double)), ("xs_e_el", C.POINTER(C.c_double)),
         ("xs_e_ex", C.POINTER(C.c_double)), ("xs_i_cx", C.POINTER(C.c_double)),
         ("xs_i_el", C.POINTER(C.c_double)), ("E_ex_eV", C.c_double),
+        ("cluster_center", C.c_double * 3), ("cluster_radius", C.c_double),
+        ("grain_min_sep", C.c_double),
     ]
 
 
@@ -111,6 +114,10 @@ def lib():
         L.pic_grain_charges.argtypes = [P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.pic_fields.argtypes = [P, C.c_int, C.c_uint, C.POINTER(P), C.c_int]
         L.pic_fields_static.argtypes = [P, C.c_int, C.c_uint, C.POINTER(P), C.c_int]
+        L.pic_grain_positions.argtypes = [P, C.c_int, C.POINTER(C.c_double)]
+        L.pic_energy.argtypes = [P, C.c_int, C.POINTER(C.c_double)]
+        L.pic_save.argtypes = [P, C.c_char_p]
+        L.pic_load.argtypes = [P, C.c_char_p]
         L.pic_destroy.argtypes = [P]
         L.pic_destroy.restype = None
         L.pic_last_error.argtypes = [P]
@@ -132,7 +139,9 @@ def lib():
         for name in ("pic_init", "pic_step", "pic_grain_charges", "pic_fields", "pic_get_state",
                      "pic_set_state", "pic_get_counters", "pic_derived", "pic_profile_enable",
                      "pic_profile_read", "pic_get_tuning", "pic_set_tuning", "pic_autotune",
-                     "pic_average", "pic_average_read", "pic_set_fine_grid", "pic_fields_static"):
+                     "pic_average", "pic_average_read", "pic_set_fine_grid", "pic_fields_static",
+                     "pic_save", "pic_load", "pic_grain_positions",
+           "pic_energy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -146,11 +155,19 @@ def _check(rc, ctx=None):
 
 def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 3):
     """pic_config from a workload dict; returns (config, keep-alive arrays)."""
-    g = np.ascontiguousarray(np.asarray(wl.get("grain_pos", np.zeros((0, 3))), np.float64).reshape(-1, 3))
+    cluster = wl.get("cluster") if wl.get("grain_pos") is None else None
+    g = np.ascontiguousarray(np.asarray(np.zeros((0, 3)) if wl.get("grain_pos") is None
+                                        else wl["grain_pos"], np.float64).reshape(-1, 3))
     c = pic_config()
     c.nx, c.ny, c.nz = int(wl["nx"]), int(wl["ny"]), int(wl["nz"])
     c.ppc = int(wl["ppc"])
-    c.n_grains = g.shape[0]
+    c.n_grains = int(cluster["n"]) if cluster else g.shape[0]
+    if cluster:
+        # the library places the grains (seeded; pic_grain_positions reads them)
+        for a in range(3):
+            c.cluster_center[a] = float(cluster["center"][a])
+        c.cluster_radius = float(cluster["radius"])
+        c.grain_min_sep = float(cluster.get("min_sep", 0.0))
     c.pp_cutoff_cells = int(wl.get("cutoff", 3))
     c.md_subcycles = int(wl.get("md_sub", 40))
     prec = wl.get("precision", "fp64")
@@ -166,7 +183,7 @@ def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 3):
     c.E_cap_eV = float(wl["E_cap_eV"])
     c.refine_tol = float(wl.get("refine_tol", 1e-10))
     c.seed = int(wl.get("seed", 0))
-    c.grain_pos = g.ctypes.data_as(C.POINTER(C.c_double))
+    c.grain_pos = g.ctypes.data_as(C.POINTER(C.c_double)) if not cluster else None
     c.coulomb_interval = int(wl.get("coulomb_interval", 0))
     c.coulomb_lnL = float(wl.get("coulomb_lnL", 10.0))
     keep = [g]
@@ -228,6 +245,26 @@ def pic_fields_static(ctx, replica, what, outs, out_on_device=False):
     for i, o in enumerate(outs):
         ptrs[i] = o.data_ptr() if hasattr(o, "data_ptr") else o.ctypes.data
     _check(lib().pic_fields_static(ctx, replica, what, ptrs, 1 if out_on_device else 0), ctx)
+
+
+def pic_grain_positions(ctx, replica, n_grains):
+    out = np.zeros((max(n_grains, 1), 3))
+    _check(lib().pic_grain_positions(ctx, replica, out.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+    return out[:n_grains].copy()
+
+
+def pic_energy(ctx, replica):
+    out = (C.c_double * 4)()
+    _check(lib().pic_energy(ctx, replica, out), ctx)
+    return dict(kinetic_e=out[0], kinetic_i=out[1], field=out[2], total=out[3])
+
+
+def pic_save(ctx, path):
+    _check(lib().pic_save(ctx, os.fsencode(path)), ctx)
+
+
+def pic_load(ctx, path):
+    _check(lib().pic_load(ctx, os.fsencode(path)), ctx)
 
 
 def pic_average(ctx, interval, phase_bins=1):
@@ -385,7 +422,7 @@ class Simulation:
         self.ctx = pic_init([m[0] for m in made], len(made),
                             stream if stream is not None else current_stream())
         self.n_nodes = [w["nx"] * w["ny"] * (w["nz"] + 1) for w in self.wls]
-        self.n_grains = [m[1][0].shape[0] for m in made]
+        self.n_grains = [int(m[0].n_grains) for m in made]
         self.capacity = [w["nx"] * w["ny"] * w["nz"] * w["ppc"] for w in self.wls]
         self.fine_nodes = [0] * len(self.wls)
 
@@ -442,6 +479,22 @@ class Simulation:
 
     def set_state(self, state, replica=0):
         pic_set_state(self.ctx, replica, state, self.n_grains[replica])
+
+    def grain_positions(self, replica=0):
+        """The replica's grains [n][3] in cell units (given or placed by the library)."""
+        return pic_grain_positions(self.ctx, replica, self.n_grains[replica])
+
+    def energy(self, replica=0):
+        """FP64 kinetic (per species), field and total energy (J) at this step."""
+        return pic_energy(self.ctx, replica)
+
+    def save(self, path):
+        """Checkpoint every replica (pic_save)."""
+        pic_save(self.ctx, path)
+
+    def load(self, path):
+        """Resume from a checkpoint written by a context of the same workloads."""
+        pic_load(self.ctx, path)
 
     def counters(self, replica=0):
         return pic_get_counters(self.ctx, replica)

@@ -126,6 +126,17 @@ def ensemble(n_replicas: int = 16, seed: int = 4) -> list:
     return out
 
 
+def column(seed: int = 0, precision: str = "fp64") -> dict:
+    """16x16x128 cells of 50 um (0.8 x 0.8 x 6.4 mm), 4 ppc (262,144
+    particles), two grains one above the other in the rf sheath at (8, 8,
+    100) and (8, 8, 108): a narrow column tall enough for a bulk plasma
+    between the two sheaths, for long statistical runs over many seeds."""
+    wl = dict(_BASE, nx=16, ny=16, nz=128, ppc=4, steps=2000, cutoff=3, seed=seed,
+              grain_pos=np.array([[8.0, 8.0, 100.0], [8.0, 8.0, 108.0]]), precision=precision)
+    wl["name"] = f"column_{precision}_16x16x128_ppc4_2grains"
+    return wl
+
+
 def small_ensemble() -> list:
     """Three uneven small FP32-refined replicas (a quick form of the ensemble)."""
     out = []
