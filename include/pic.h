@@ -152,6 +152,25 @@ typedef struct pic_config {
   double cluster_center[3];
   double cluster_radius;
   double grain_min_sep;
+  /* electron-impact ionisation (Table I: e + Ar -> Ar+ + 2e), in the
+   * null-collision method with the tables above (xs_n > 0): sigma on the same
+   * energy grid (m^2; NULL: no ionisation) and the ionisation energy E_iz_eV.
+   * An electron whose centre-of-mass energy exceeds E_iz can ionise (the third
+   * electron process after elastic and excitation); the energy left,
+   * (mu/2) g^2 - E_iz, is shared: a fraction s, uniform from Philox(id, k, 8,
+   * 0) word 0, goes to a new electron (isotropic, words 1 and 2), 1 - s to the
+   * scattered one (isotropic, as for elastic scattering), both in the
+   * centre-of-mass frame with the neutral at rest; a new ion takes a
+   * Maxwellian velocity of T_gas_K (Philox(id, k, 8, 1), Box-Muller).  Both
+   * new particles start at the parent's position x_{k+1} with these as
+   * v_{k+1/2}; the ionisations of a step take new ids in the order of their
+   * parents' ids (from the loaded count, or max id + 1 after pic_set_state).
+   * max_particles: slots per species (0: the loaded count, plus a quarter
+   * with ionisation); ionisations that find no room are counted in
+   * pic_counters.iz_dropped (a run with drops is not valid). */
+  const double* xs_e_iz;
+  double E_iz_eV;
+  int64_t max_particles;
 } pic_config;
 #define PIC_MAX_XS 4096
 
@@ -187,6 +206,8 @@ typedef struct pic_counters {
                                  pp_cutoff_cells dx: moves long enough to reach a grain from
                                  outside its MD cube, where no grain test is made (0 without
                                  grains) */
+  int64_t n_ionizations;      /* electron-ion pairs created by ionisation */
+  int64_t iz_dropped;         /* ionisations that found no room (0 in a valid run) */
 } pic_counters;
 
 /*

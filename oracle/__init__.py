@@ -67,6 +67,7 @@ class _Config(C.Structure):
         ("xs_i_el", C.POINTER(C.c_double)), ("E_ex_eV", C.c_double),
         ("seed", C.c_uint64),
         ("grain_pos", C.POINTER(C.c_double)),
+        ("xs_e_iz", C.POINTER(C.c_double)), ("E_iz_eV", C.c_double),
     ]
 
 
@@ -94,6 +95,9 @@ class _State(C.Structure):
         ("step", C.c_uint32),
         ("pad0", C.c_uint32),
         ("md_margin", C.c_int64 * 2),
+        ("cap", C.c_int64 * 2),
+        ("next_id", C.c_uint32 * 2),
+        ("n_ionizations", C.c_int64),
     ]
 
 
@@ -187,7 +191,7 @@ class Oracle:
         xs = wl.get("xs")
         self._xs = {}
         if xs:
-            for k in ("E", "e_el", "e_ex", "i_cx", "i_el"):
+            for k in ("E", "e_el", "e_ex", "i_cx", "i_el", "e_iz"):
                 if xs.get(k) is not None:
                     self._xs[k] = np.ascontiguousarray(xs[k], np.float64)
             cfg.xs_n = len(self._xs["E"])
@@ -197,6 +201,8 @@ class Oracle:
             cfg.xs_i_cx = _ptr(self._xs["i_cx"], C.c_double)
             cfg.xs_i_el = _ptr(self._xs.get("i_el"), C.c_double)
             cfg.E_ex_eV = float(xs.get("E_ex", 0.0))
+            cfg.xs_e_iz = _ptr(self._xs.get("e_iz"), C.c_double)
+            cfg.E_iz_eV = float(xs.get("E_iz", 0.0))
         cfg.seed = int(wl.get("seed", 0))
         cfg.grain_pos = _ptr(self.grain_pos, C.c_double)
         self.cfg = cfg
@@ -217,7 +223,7 @@ class Oracle:
     # ---- state plumbing ------------------------------------------------
     def _bind(self):
         for s in range(2):
-            self.st.n[s] = self.pos[s].shape[0]
+            self.st.n[s] = self.st.cap[s] = self.pos[s].shape[0]
             self.st.pos[s] = _ptr(self.pos[s], C.c_double)
             self.st.vel[s] = _ptr(self.vel[s], C.c_double)
             self.st.id[s] = _ptr(self.id[s], C.c_uint32)
@@ -225,12 +231,19 @@ class Oracle:
             self.st.margin[s] = _ptr(self.margin[s], C.c_double)
 
     def set_particles(self, species: int, pos, vel, ids):
+        """Load one species (positions in cell units: x and y are periodic, z
+        must lie between the electrodes, 0 <= z < nz).  The arrays are copied:
+        stepping the oracle never changes the caller's."""
         n = len(ids)
-        self.pos[species] = np.ascontiguousarray(np.asarray(pos, np.float64).reshape(n, 3))
-        self.vel[species] = np.ascontiguousarray(np.asarray(vel, np.float64).reshape(n, 3))
-        self.id[species] = np.ascontiguousarray(np.asarray(ids, np.uint32))
+        pos = np.array(pos, np.float64, order="C", copy=True).reshape(n, 3)
+        if n and not (np.isfinite(pos).all() and (pos[:, 2] >= 0).all() and (pos[:, 2] < self.nz).all()):
+            raise ValueError("set_particles: a position is not finite or has z outside [0, nz)")
+        self.pos[species] = pos
+        self.vel[species] = np.array(vel, np.float64, order="C", copy=True).reshape(n, 3)
+        self.id[species] = np.array(ids, np.uint32, order="C", copy=True)
         self.alive[species] = np.ones(n, np.uint8)
         self.margin[species] = np.full(n, np.inf)
+        self.st.next_id[species] = int(self.id[species].max()) + 1 if n else 0
         self._bind()
 
     def set_counts(self, grain_count=None, wall_count=None, step=None):
@@ -259,6 +272,40 @@ class Oracle:
     @property
     def n_collisions(self):
         return [int(self.st.n_collisions[s]) for s in range(2)]
+
+    @property
+    def n_ionizations(self) -> int:
+        return int(self.st.n_ionizations)
+
+    @property
+    def next_id(self):
+        return [int(self.st.next_id[s]) for s in range(2)]
+
+    def _grow(self):
+        """Room for the particles that this step's ionisations may create (at
+        most one electron and one ion per electron)."""
+        if self._xs.get("e_iz") is None or self.flags & NO_MCC:
+            return False
+        extra = self.pos[0].shape[0]
+        used = [self.pos[s].shape[0] for s in range(2)]
+        for s in range(2):
+            self.pos[s] = np.concatenate([self.pos[s], np.zeros((extra, 3))])
+            self.vel[s] = np.concatenate([self.vel[s], np.zeros((extra, 3))])
+            self.id[s] = np.concatenate([self.id[s], np.zeros(extra, np.uint32)])
+            self.alive[s] = np.concatenate([self.alive[s], np.zeros(extra, np.uint8)])
+            self.margin[s] = np.concatenate([self.margin[s], np.full(extra, np.inf)])
+        self._bind()
+        for s in range(2):
+            self.st.n[s] = used[s]
+        return True
+
+    def _trim(self):
+        for s in range(2):
+            n = int(self.st.n[s])
+            for name in ("pos", "vel", "id", "alive", "margin"):
+                arr = getattr(self, name)
+                arr[s] = np.ascontiguousarray(arr[s][:n])
+        self._bind()
 
     @property
     def md_margin(self):
@@ -482,7 +529,10 @@ class Oracle:
     def step(self, n: int = 1):
         U = self._units()
         for _ in range(n):
+            grown = self._grow()
             rc = lib().orc_step(C.byref(self.cfg), C.byref(self.st), _ptr(U, C.c_double))
+            if grown:
+                self._trim()
             if rc:
                 raise RuntimeError(f"orc_step failed ({rc})")
 
@@ -490,8 +540,11 @@ class Oracle:
         E = None if E is None else np.ascontiguousarray(E, np.float64).reshape(-1)
         U = self._units()
         for _ in range(n):
+            grown = self._grow()
             rc = lib().orc_step_in_field(C.byref(self.cfg), C.byref(self.st),
                                          _ptr(E, C.c_double), _ptr(U, C.c_double))
+            if grown:
+                self._trim()
             if rc:
                 raise RuntimeError(f"orc_step_in_field failed ({rc})")
 

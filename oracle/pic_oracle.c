@@ -25,7 +25,7 @@
 
 /* Philox counter word 2: what a draw is for */
 enum { PUR_INIT_POS = 1, PUR_INIT_VEL = 2, PUR_COLL = 3, PUR_NEUTRAL = 4, PUR_CORDER = 5,
-       PUR_CPAIR = 6, PUR_GRAIN = 7 };
+       PUR_CPAIR = 6, PUR_GRAIN = 7, PUR_IONIZE = 8 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32  */
@@ -161,7 +161,8 @@ double orc_xs_at(const orc_config* c, const double* table, double E)
 /* total cross section of a species at E */
 static double xs_total(const orc_config* c, int sp, double E)
 {
-  if (sp == 0) return orc_xs_at(c, c->xs_e_el, E) + orc_xs_at(c, c->xs_e_ex, E);
+  if (sp == 0)
+    return orc_xs_at(c, c->xs_e_el, E) + orc_xs_at(c, c->xs_e_ex, E) + orc_xs_at(c, c->xs_e_iz, E);
   return orc_xs_at(c, c->xs_i_cx, E) + orc_xs_at(c, c->xs_i_el, E);
 }
 
@@ -254,6 +255,7 @@ int orc_init_particles(const orc_config* c, orc_state* s)
       s->alive[sp][p] = 1;
     }
   }
+  for (int sp = 0; sp < 2; ++sp) s->next_id[sp] = (uint32_t)s->n[sp];
   return 0;
 }
 
@@ -909,33 +911,52 @@ static int move_md(const orc_config* c, const double* E, const double* U, const 
 /* energy drops by E_ex, isotropic scattering); ions: charge exchange, then */
 /* isotropic elastic scattering in the CM frame of ion and neutral.  Above  */
 /* the bound (a cap violation) the collision happens and u1 splits sigma.   */
-static void collide_xs(const orc_config* c, const orc_derived* d, int sp, const uint32_t r[4],
-                       const double* vn, double* v, double* margin, int64_t* cap_viol,
-                       int64_t* ncoll)
+/* an electron-impact ionisation of one step, applied after every particle has
+   moved: the parent's index and id, its velocity before the collision and
+   the squared relative speed left to share, g^2 - 2 E_iz / mu */
+typedef struct iz_event {
+  int64_t p;
+  uint32_t id;
+  double v[3];
+  double gsq;
+} iz_event;
+
+typedef struct iz_sink {
+  iz_event* ev;
+  int64_t n, cap;
+} iz_sink;
+
+static void collide_xs(const orc_config* c, const orc_derived* d, int sp, uint32_t id, uint32_t k,
+                       const uint32_t r[4], const double* vn, double* v, double* margin,
+                       int64_t* cap_viol, int64_t* ncoll, int64_t p, iz_sink* iz)
 {
   double gv[3] = {v[0] - vn[0], v[1] - vn[1], v[2] - vn[2]};
   double g2 = gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2];
   double g = sqrt(g2);
   double E = 0.5 * d->m[sp] * g2 / O_ECHARGE;
-  double s1, s2;
+  double mu = d->m[0] * d->m[1] / (d->m[0] + d->m[1]);
+  double s1, s2, s3 = 0.0;
   if (sp == 0) {
-    double mu = d->m[0] * d->m[1] / (d->m[0] + d->m[1]);
     s1 = orc_xs_at(c, c->xs_e_el, E);
     s2 = 0.5 * mu * g2 > c->E_ex_eV * O_ECHARGE ? orc_xs_at(c, c->xs_e_ex, E) : 0.0;
+    s3 = 0.5 * mu * g2 > c->E_iz_eV * O_ECHARGE ? orc_xs_at(c, c->xs_e_iz, E) : 0.0;
   } else {
     s1 = orc_xs_at(c, c->xs_i_cx, E);
     s2 = orc_xs_at(c, c->xs_i_el, E);
   }
   double a1 = g * s1 / d->sg_max[sp], a2 = g * (s1 + s2) / d->sg_max[sp];
+  double a3 = g * (s1 + s2 + s3) / d->sg_max[sp];
   double u1 = unif_open(r[1]);
-  int proc; /* 0 none, 1 first process, 2 second */
-  if (a2 > 1.0) {
+  int proc; /* 0 none, 1 first process, 2 second, 3 ionisation */
+  if (a3 > 1.0) {
 #pragma omp atomic
     cap_viol[sp] += 1;
-    proc = u1 * (s1 + s2) < s1 ? 1 : 2;
+    double x = u1 * (s1 + s2 + s3);
+    proc = x < s1 ? 1 : (x < s1 + s2 ? 2 : 3);
   } else {
     *margin = dmin(*margin, dmin(fabs(u1 - a1), fabs(u1 - a2)));
-    proc = u1 < a1 ? 1 : (u1 < a2 ? 2 : 0);
+    if (s3 > 0.0) *margin = dmin(*margin, fabs(u1 - a3));
+    proc = u1 < a1 ? 1 : (u1 < a2 ? 2 : (u1 < a3 ? 3 : 0));
   }
   if (proc == 0) return;
 #pragma omp atomic
@@ -952,9 +973,26 @@ static void collide_xs(const orc_config* c, const orc_derived* d, int sp, const 
   if (sp == 0) {
     /* neutral at rest: v' = (m v + M 0) / (m + M) + M / (m + M) g' n */
     double gp = g;
-    if (proc == 2) {
-      double mu = d->m[0] * d->m[1] / mt;
-      gp = sqrt(g2 - 2.0 * c->E_ex_eV * O_ECHARGE / mu);
+    if (proc == 2) gp = sqrt(g2 - 2.0 * c->E_ex_eV * O_ECHARGE / mu);
+    if (proc == 3) {
+      /* ionisation: the centre-of-mass energy less E_iz is shared, a fraction
+         s (uniform, Philox(id, k, IONIZE, 0) word 0) to the ejected electron,
+         1 - s to the scattered one; the ejected electron and the new ion are
+         made after the step (ionize_apply) */
+      double gsq = g2 - 2.0 * c->E_iz_eV * O_ECHARGE / mu;
+      uint32_t w[4];
+      draw(c, id, k, PUR_IONIZE, 0u, w);
+      double share = unif_open(w[0]);
+      int64_t slot;
+#pragma omp atomic capture
+      slot = iz->n++;
+      if (slot < iz->cap) {
+        iz->ev[slot].p = p;
+        iz->ev[slot].id = id;
+        for (int a = 0; a < 3; ++a) iz->ev[slot].v[a] = v[a];
+        iz->ev[slot].gsq = gsq;
+      }
+      gp = sqrt((1.0 - share) * gsq);
     }
     for (int a = 0; a < 3; ++a) v[a] = (d->m[0] / mt) * v[a] + (d->m[1] / mt) * gp * nh[a];
   } else {
@@ -965,7 +1003,8 @@ static void collide_xs(const orc_config* c, const orc_derived* d, int sp, const 
 
 /* binary collision with a neutral drawn from the reservoir, null-collision form */
 static void collide(const orc_config* c, const orc_derived* d, int sp, uint32_t id, uint32_t k,
-                    double* v, double* margin, int64_t* cap_viol, int64_t* ncoll)
+                    double* v, double* margin, int64_t* cap_viol, int64_t* ncoll, int64_t p,
+                    iz_sink* iz)
 {
   uint32_t r[4];
   draw(c, id, k, PUR_COLL, (uint32_t)sp, r);
@@ -980,7 +1019,7 @@ static void collide(const orc_config* c, const orc_derived* d, int sp, uint32_t 
     for (int a = 0; a < 3; ++a) vn[a] *= d->vth_gas;
   }
   if (c->xs_n > 0) {
-    collide_xs(c, d, sp, r, vn, v, margin, cap_viol, ncoll);
+    collide_xs(c, d, sp, id, k, r, vn, v, margin, cap_viol, ncoll, p, iz);
     return;
   }
   double gv[3] = {v[0] - vn[0], v[1] - vn[1], v[2] - vn[2]};
@@ -1179,6 +1218,62 @@ int64_t orc_coulomb(const orc_config* c, orc_state* s)
   return ncoll;
 }
 
+static int cmp_iz(const void* a, const void* b)
+{
+  uint32_t x = ((const iz_event*)a)->id, y = ((const iz_event*)b)->id;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* The ionisations of step k, in order of the parent electron's id: each makes
+   an electron and an ion at the parent's new position x_{k+1}, with ids
+   next_id[s]++ (s: species).  The ejected electron takes the share s of the
+   available centre-of-mass energy: relative speed g_e = sqrt(s gsq), an
+   isotropic direction from Philox(id, k, IONIZE, 0) words 1 and 2, and
+   v = V_cm + M / (m + M) g_e n with V_cm = m v_parent / (m + M) (the neutral
+   at rest, as for the other electron collisions); the ion takes a Maxwellian
+   velocity of the gas temperature from Philox(id, k, IONIZE, 1) (Box-Muller,
+   cosine branch first).  Both join the next step with these as v_{k+1/2}. */
+static int ionize_apply(const orc_config* c, const orc_derived* d, orc_state* s, uint32_t k,
+                        iz_sink* iz)
+{
+  if (iz->n == 0) return 0;
+  if (iz->n > iz->cap) return -7;
+  qsort(iz->ev, (size_t)iz->n, sizeof(iz_event), cmp_iz);
+  if (s->n[0] + iz->n > s->cap[0] || s->n[1] + iz->n > s->cap[1]) return -8;
+  double mt = d->m[0] + d->m[1];
+  for (int64_t q = 0; q < iz->n; ++q) {
+    const iz_event* e = &iz->ev[q];
+    uint32_t w0[4], w1[4];
+    draw(c, e->id, k, PUR_IONIZE, 0u, w0);
+    draw(c, e->id, k, PUR_IONIZE, 1u, w1);
+    double share = unif_open(w0[0]);
+    double ge = sqrt(share * e->gsq);
+    double cost = 1.0 - 2.0 * unif_open(w0[1]);
+    double sint = sqrt(fmax(0.0, 1.0 - cost * cost));
+    double ph = 2.0 * O_PI * unif_open(w0[2]);
+    double nh[3] = {sint * cos(ph), sint * sin(ph), cost};
+    int64_t pe = s->n[0]++, pi = s->n[1]++;
+    for (int a = 0; a < 3; ++a) {
+      s->pos[0][3 * pe + a] = s->pos[0][3 * e->p + a];
+      s->pos[1][3 * pi + a] = s->pos[0][3 * e->p + a];
+      s->vel[0][3 * pe + a] = (d->m[0] / mt) * e->v[a] + (d->m[1] / mt) * ge * nh[a];
+    }
+    double n0, n1, n2, unused;
+    box_muller(w1[0], w1[1], &n0, &n1);
+    box_muller(w1[2], w1[3], &n2, &unused);
+    s->vel[1][3 * pi + 0] = d->vth_gas * n0;
+    s->vel[1][3 * pi + 1] = d->vth_gas * n1;
+    s->vel[1][3 * pi + 2] = d->vth_gas * n2;
+    s->id[0][pe] = s->next_id[0]++;
+    s->id[1][pi] = s->next_id[1]++;
+    s->alive[0][pe] = s->alive[1][pi] = 1;
+    if (s->margin[0]) s->margin[0][pe] = INFINITY;
+    if (s->margin[1]) s->margin[1][pi] = INFINITY;
+  }
+  s->n_ionizations += iz->n;
+  return 0;
+}
+
 static int move_all(const orc_config* c, orc_state* s, const double* E, const double* U)
 {
   orc_derived d;
@@ -1195,6 +1290,13 @@ static int move_all(const orc_config* c, orc_state* s, const double* E, const do
   /* a plain push at least this fast crosses cutoff cells in one step: it could
      reach a grain from outside the grain's MD cube, where no grain test is made */
   const double vfast = c->cutoff * c->dx / c->dt;
+  /* ionisation events of this step (at most one per electron) */
+  iz_sink iz = {NULL, 0, 0};
+  if (c->xs_n > 0 && c->xs_e_iz && !(c->flags & ORC_NO_MCC) && s->n[0] > 0) {
+    iz.cap = s->n[0];
+    iz.ev = (iz_event*)malloc(sizeof(iz_event) * (size_t)iz.cap);
+    if (!iz.ev) return -2;
+  }
   for (int sp = 0; sp < 2; ++sp) {
     double qm = d.q[sp] / d.m[sp];
     int64_t wall[2] = {0, 0}, fast = 0;
@@ -1225,7 +1327,7 @@ static int move_all(const orc_config* c, orc_state* s, const double* E, const do
         s->grain_count[2 * hit + sp] += 1;
         s->alive[sp][p] = 0;
       } else if (!(c->flags & ORC_NO_MCC)) {
-        collide(c, &d, sp, s->id[sp][p], k, v, &margin, s->cap_violation, s->n_collisions);
+        collide(c, &d, sp, s->id[sp][p], k, v, &margin, s->cap_violation, s->n_collisions, p, &iz);
       }
       if (s->margin[sp]) s->margin[sp][p] = margin;
     }
@@ -1233,6 +1335,9 @@ static int move_all(const orc_config* c, orc_state* s, const double* E, const do
     s->wall_count[1][sp] += wall[1];
     s->md_margin[sp] += fast;
   }
+  int rc = ionize_apply(c, &d, s, k, &iz);
+  free(iz.ev);
+  if (rc) return rc;
   s->step = k + 1;
   return 0;
 }

@@ -74,6 +74,10 @@ typedef struct orc_config {
   double E_ex_eV;            /* excitation energy */
   uint64_t seed;             /* Philox key */
   const double* grain_pos;   /* [n_grains][3], cell units */
+  /* electron-impact ionisation (Table I: e + Ar -> Ar+ + 2e), with the tables
+     above: sigma on the same energy grid (nullable: none) and the threshold */
+  const double* xs_e_iz;     /* [xs_n] m^2, nullable */
+  double E_iz_eV;            /* ionisation energy */
 } orc_config;
 
 typedef struct orc_derived {
@@ -103,6 +107,9 @@ typedef struct orc_state {
   uint32_t step;             /* k: the state holds x_k and v_{k-1/2} */
   uint32_t pad0;
   int64_t md_margin[2];      /* plain pushes with |v_{k+1/2}| dt >= cutoff dx (with grains) */
+  int64_t cap[2];            /* array capacity per species (>= n): room for new particles */
+  uint32_t next_id[2];       /* id of the next particle an ionisation creates, per species */
+  int64_t n_ionizations;     /* ionisations (pairs created) */
 } orc_state;
 
 /* ---- building blocks (exposed for the pins) ---- */

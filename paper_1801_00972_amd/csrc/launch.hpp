@@ -24,10 +24,11 @@ struct FftPlanHost {
 // particles: arrays binned by 4x4x4-cell tile and updated in place (see
 // WorkLists); one push block per tile or pair of tiles, the grid padded to a
 // multiple of 16
-int tile_grid(int nx, int ny, int nz);      // tiles rounded up to a multiple of 16
+// tiles (plus `extra` padding tiles) rounded up to a multiple of 16
+int tile_grid(int nx, int ny, int nz, int extra);
 // blocks of the MD kernel; each owns a tally row after the ngrid tile rows
 constexpr int kMdTallyRows = 4096;
-long sort_keys(int nx, int ny, int nz);     // ints of sort workspace (tile counts and cursors)
+long sort_keys(int ngrid);                  // ints of sort workspace (tile counts and cursors)
 // the streaming kernel of one species (gather, push, walls, candidate test, deposit)
 void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
                      const SpeciesStep& S, const WorkLists& L, hipStream_t st);
@@ -121,6 +122,12 @@ void launch_sort_f64(const PartF64& src, const PartF64& dst, const WorkLists& L,
 void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const WorkLists& L, int* hist,
                       int* sums, long capacity, hipStream_t st);
 void launch_fill_int(int* a, long n, int v, hipStream_t st);
+// the step's ionisations made into particles (one block; see ionize_kernel):
+// exactly one of the FP64 and FP32R pointer pairs is non-null
+void launch_ionize(const PartF64* Pe64, const PartF64* Pi64, const PartF32R* Pe32,
+                   const PartF32R* Pi32, const WorkLists& Le, const WorkLists& Li,
+                   const SpeciesStep& Se, uint32_t* next_id, long room_e, long room_i,
+                   unsigned long long* dropped, hipStream_t st);
 // FP64 energy diagnostic: per-block sums (energy_blocks() of them) of |v|^2
 // over a species' live particles, and of |E|^2 times each node's share of a
 // cell volume over the mesh (E as stored: double pairs if e_f64, else float4)

@@ -375,34 +375,40 @@ __device__ inline double xs_at(const SpeciesStep& S, int col, double E) {
 // both forms): the process is picked by u1 against the cumulative
 // g sigma_k(E) / (g sigma)_max, E the projectile's energy with the target at
 // rest.  Electrons: elastic, then excitation (CM energy above E_ex; the CM
-// energy drops by E_ex, isotropic scattering); ions: charge exchange, then
-// isotropic elastic scattering in the CM frame of ion and neutral (equal
-// masses).  Above the bound the collision happens (counted) and u1 splits
-// the cross section.
+// energy drops by E_ex, isotropic scattering), then ionisation (CM energy
+// above E_iz; what is left is shared, a uniform fraction s from
+// Philox(id, k, IONIZE, 0) word 0 to the ejected electron, 1 - s to this one,
+// which scatters isotropically; the event is recorded for ionize_kernel);
+// ions: charge exchange, then isotropic elastic scattering in the CM frame of
+// ion and neutral (equal masses).  Above the bound the collision happens
+// (counted) and u1 splits the cross section.
 template <typename T>
 __device__ void collide_xs(const SpeciesStep& S, const uint4& r, const T vn[3], T v[3], bool& coll,
-                           bool& capv) {
+                           bool& capv, uint32_t id, long slot) {
   const double gx = (double)v[0] - (double)vn[0], gy = (double)v[1] - (double)vn[1],
                gz = (double)v[2] - (double)vn[2];
   const double g2 = gx * gx + gy * gy + gz * gz;
   const double g = sqrt(g2);
   const double E = 0.5 * g2 / fabs(S.qm);  // m g^2 / 2 in eV (|q| = e)
-  double s1, s2;
+  double s1, s2, s3 = 0.0;
   if (S.sp == 0) {
     s1 = xs_at(S, 1, E);
     s2 = g2 > S.ex_g2 ? xs_at(S, 2, E) : 0.0;
+    if (S.iz_ev && g2 > S.iz_g2) s3 = xs_at(S, 5, E);
   } else {
     s1 = xs_at(S, 3, E);
     s2 = xs_at(S, 4, E);
   }
   const double a1 = g * s1 / S.sg_max, a2 = g * (s1 + s2) / S.sg_max;
+  const double a3 = g * (s1 + s2 + s3) / S.sg_max;
   const double u1 = u01_open(r.y);
   int proc;
-  if (a2 > 1.0) {
+  if (a3 > 1.0) {
     capv = true;
-    proc = u1 * (s1 + s2) < s1 ? 1 : 2;
+    const double x = u1 * (s1 + s2 + s3);
+    proc = x < s1 ? 1 : (x < s1 + s2 ? 2 : 3);
   } else {
-    proc = u1 < a1 ? 1 : (u1 < a2 ? 2 : 0);
+    proc = u1 < a1 ? 1 : (u1 < a2 ? 2 : (u1 < a3 ? 3 : 0));
   }
   if (proc == 0) return;
   coll = true;
@@ -418,7 +424,20 @@ __device__ void collide_xs(const SpeciesStep& S, const uint4& r, const T vn[3], 
   sincos(2.0 * kPi * u01_open(r.w), &sp, &cp);
   const double nh[3] = {sint * cp, sint * sp, cost};
   if (S.sp == 0) {
-    const double gp = proc == 2 ? sqrt(g2 - S.ex_g2) : g;
+    double gp = proc == 2 ? sqrt(g2 - S.ex_g2) : g;
+    if (proc == 3) {
+      const double gsq = g2 - S.iz_g2;
+      const uint4 w = philox4x32_10(id, *S.step, kIonize, 0u, S.key0, S.key1);
+      gp = sqrt((1.0 - u01_open(w.x)) * gsq);
+      const int e = atomicAdd(S.iz_cnt, 1);
+      if (e < S.iz_cap) {
+        IzEvent& ev = S.iz_ev[e];
+        ev.id = id;
+        ev.slot = (int32_t)slot;
+        for (int a = 0; a < 3; ++a) ev.v[a] = (double)v[a];
+        ev.gsq = gsq;
+      }
+    }
     for (int a = 0; a < 3; ++a) v[a] = (T)(S.mass_ratio_e * (double)v[a] + S.mass_ratio_n * gp * nh[a]);
   } else {
     for (int a = 0; a < 3; ++a) v[a] = (T)(0.5 * ((double)v[a] + (double)vn[a]) + 0.5 * g * nh[a]);
@@ -427,13 +446,13 @@ __device__ void collide_xs(const SpeciesStep& S, const uint4& r, const T vn[3], 
 
 template <typename T>
 __device__ __forceinline__ void collide(const SpeciesStep& S, uint32_t id, T v[3], bool& coll,
-                                        bool& capv) {
+                                        bool& capv, long slot) {
   if constexpr (sizeof(T) == 4) {
     // FP32R records: the collision in FP64 (2 % of the particles per step),
     // rounded once; a 24-bit uniform in the Box-Muller radius or the
     // scattering angle could put a tail draw 1e-4 off
     double vd[3] = {v[0], v[1], v[2]};
-    collide<double>(S, id, vd, coll, capv);
+    collide<double>(S, id, vd, coll, capv, slot);
     if (coll) {
       v[0] = (T)vd[0];
       v[1] = (T)vd[1];
@@ -455,7 +474,7 @@ __device__ __forceinline__ void collide(const SpeciesStep& S, uint32_t id, T v[3
     vn[2] = vg * n2;
   }
   if (S.xs_n > 0) {
-    collide_xs<T>(S, r, vn, v, coll, capv);
+    collide_xs<T>(S, r, vn, v, coll, capv, id, slot);
     return;
   }
   const T gx = v[0] - vn[0], gy = v[1] - vn[1], gz = v[2] - vn[2];
@@ -633,6 +652,10 @@ __device__ __forceinline__ Tile make_tile(int t, const WorkLists& L, int nx, int
   w.on = false;
   w.x0 = w.y0 = w.k0 = 0;
   w.tx = w.ty = w.tz = 0;
+  // a padding tile of the grid (its slots, if any, hold particles made by
+  // ionisation since the last re-binning): no window, every particle takes
+  // the global-memory paths
+  if (t >= L.ntx * L.nty * L.ntz) return w;
   const int ti = t % L.ntx, tj = (t / L.ntx) % L.nty, tk = t / (L.ntx * L.nty);
   const int i0 = 4 * ti, ni = min(4 * span, nx - i0), j0 = 4 * tj, nj = min(4, ny - j0);
   const int k0 = 4 * tk, nk = min(4, nz - k0);
@@ -1727,7 +1750,7 @@ __global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> 
     if (!slot_alive(P, p)) continue;
     bool coll = false, capv = false;
     typename VelOf<PT>::type v[3] = {P.vx[p], P.vy[p], P.vz[p]};
-    collide(S, P.id[p], v, coll, capv);
+    collide(S, P.id[p], v, coll, capv, p);
     if (coll) {
       P.vx[p] = v[0];
       P.vy[p] = v[1];
@@ -1786,7 +1809,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> 
       if (do_mcc) {
         const uint32_t id = P.id[p];
         const uint4 r = philox4x32_10(id, *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
-        if ((uint64_t)r.x < S.T_null) collide(S, id, v, coll, capv);
+        if ((uint64_t)r.x < S.T_null) collide(S, id, v, coll, capv, p);
       }
       t_coll += coll;
       t_cap += capv;
@@ -1849,7 +1872,7 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(SpeciesPair<PartF64> pr
       if (do_mcc) {
         const uint32_t id = P.id[p];
         const uint4 r = philox4x32_10(id, *S.step, kColl, (uint32_t)S.sp, S.key0, S.key1);
-        if ((uint64_t)r.x < S.T_null) collide(S, id, v, coll, capv);
+        if ((uint64_t)r.x < S.T_null) collide(S, id, v, coll, capv, p);
       }
       t_coll += coll;
       t_cap += capv;
@@ -1899,7 +1922,7 @@ __global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLi
     const long p = seg[idx];
     bool coll = false, capv = false;
     typename VelOf<PT>::type v[3] = {P.vx[p], P.vy[p], P.vz[p]};
-    collide(S, P.id[p], v, coll, capv);
+    collide(S, P.id[p], v, coll, capv, p);
     if (coll) {
       P.vx[p] = v[0];
       P.vy[p] = v[1];
@@ -2379,6 +2402,112 @@ __global__ void advance_step_kernel(uint32_t* step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1u;
 }
 
+// ---------------------------------------------------------------- ionisation
+// The ionisations of the step, after every particle has moved and collided
+// and before any re-binning: in the order of the parent electrons' ids (an
+// event's rank is the number of events with a smaller id), each makes an
+// electron and an ion at the parent's new position, in the slots after the
+// last tile's -- the range of the grid's last padding tile, whose push block
+// takes them through the global-memory paths until the next re-binning puts
+// them in their tiles -- with ids next_id[s] + rank.  The ejected electron
+// takes the fraction s (Philox(id, k, IONIZE, 0) word 0) of the shared
+// centre-of-mass energy, an isotropic direction (words 1 and 2), the neutral
+// at rest; the ion a Maxwellian velocity of the gas temperature
+// (Philox(id, k, IONIZE, 1), Box-Muller, cosine branch first).  Their charges
+// cancel on the mesh (same position), so rho_{k+1} is left as it is.  If the
+// new particles do not fit (room_* slots in use at most, so that the next
+// re-binning fits too) or events exceeded the list, they are counted in
+// *dropped.  One block.
+constexpr int kIzThreads = 1024;
+constexpr int kIzChunk = 4096;
+__device__ __forceinline__ void copy_pos(const PartF64& s, long p, const PartF64& d, long q) {
+  d.x[q] = s.x[p];
+  d.y[q] = s.y[p];
+  d.z[q] = s.z[p];
+}
+__device__ __forceinline__ void copy_pos(const PartF32R& s, long p, const PartF32R& d, long q) {
+  d.cell[q] = s.cell[p];
+  d.ox[q] = s.ox[p];
+  d.oy[q] = s.oy[p];
+  d.oz[q] = s.oz[p];
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kIzThreads) void ionize_kernel(PT Pe, PT Pi, WorkLists Le,
+                                                            WorkLists Li, SpeciesStep Se,
+                                                            uint32_t* __restrict__ next_id,
+                                                            long room_e, long room_i,
+                                                            unsigned long long* dropped) {
+  using V = typename VelOf<PT>::type;
+  __shared__ uint32_t s_id[kIzChunk];
+  const int total = *Se.iz_cnt;
+  const int n = min(total, Se.iz_cap);
+  const int ng = Le.ngrid;
+  const long be = Le.tstart[ng], bi = Li.tstart[ng];
+  // the tail stays a multiple of 4 slots long (a push thread streams four
+  // slots at once): the slots after the new particles up to that are emptied
+  const int n4 = (n + 3) & ~3;
+  const bool fit = be + n4 <= room_e && bi + n4 <= room_i;
+  const uint32_t k = *Se.step;
+  for (int j0 = 0; fit && j0 < n; j0 += kIzThreads) {
+    const int q = j0 + (int)threadIdx.x;
+    const bool mine = q < n;
+    const uint32_t myid = mine ? Se.iz_ev[q].id : 0u;
+    int rank = 0;
+    for (int c0 = 0; c0 < n; c0 += kIzChunk) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < kIzChunk && c0 + t < n; t += kIzThreads) s_id[t] = Se.iz_ev[c0 + t].id;
+      __syncthreads();
+      const int m = min(kIzChunk, n - c0);
+      if (mine)
+        for (int t = 0; t < m; ++t) rank += s_id[t] < myid;
+    }
+    if (!mine) continue;
+    const IzEvent ev = Se.iz_ev[q];
+    const uint4 w0 = philox4x32_10(ev.id, k, kIonize, 0u, Se.key0, Se.key1);
+    const uint4 w1 = philox4x32_10(ev.id, k, kIonize, 1u, Se.key0, Se.key1);
+    const double ge = sqrt(u01_open(w0.x) * ev.gsq);
+    const double cost = 1.0 - 2.0 * u01_open(w0.y);
+    const double sint = sqrt(fmax(0.0, 1.0 - cost * cost));
+    double sp, cp;
+    sincos(2.0 * kPi * u01_open(w0.z), &sp, &cp);
+    const double nh[3] = {sint * cp, sint * sp, cost};
+    const long pe = be + rank, pi = bi + rank;
+    copy_pos(Pe, ev.slot, Pe, pe);
+    copy_pos(Pe, ev.slot, Pi, pi);
+    Pe.vx[pe] = (V)(Se.mass_ratio_e * ev.v[0] + Se.mass_ratio_n * ge * nh[0]);
+    Pe.vy[pe] = (V)(Se.mass_ratio_e * ev.v[1] + Se.mass_ratio_n * ge * nh[1]);
+    Pe.vz[pe] = (V)(Se.mass_ratio_e * ev.v[2] + Se.mass_ratio_n * ge * nh[2]);
+    double n0, n1, n2, n3;
+    normal_pair(w1.x, w1.y, n0, n1);
+    normal_pair(w1.z, w1.w, n2, n3);
+    Pi.vx[pi] = (V)(Se.vth_gas * n0);
+    Pi.vy[pi] = (V)(Se.vth_gas * n1);
+    Pi.vz[pi] = (V)(Se.vth_gas * n2);
+    Pe.id[pe] = next_id[0] + (uint32_t)rank;
+    Pi.id[pi] = next_id[1] + (uint32_t)rank;
+  }
+  if (fit && (int)threadIdx.x < n4 - n) {
+    kill(Pe, be + n + threadIdx.x);
+    kill(Pi, bi + n + threadIdx.x);
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (fit && n > 0) {
+    Le.tstart[ng] = (int32_t)(be + n4);
+    Li.tstart[ng] = (int32_t)(bi + n4);
+    Le.cnt[0] = (int32_t)(be + n4);
+    Li.cnt[0] = (int32_t)(bi + n4);
+    next_id[0] += (uint32_t)n;
+    next_id[1] += (uint32_t)n;
+    Le.tally[TL_BORN] += (unsigned long long)n;
+    Li.tally[TL_BORN] += (unsigned long long)n;
+  }
+  const int lost = fit ? total - n : total;
+  if (lost > 0) *dropped += (unsigned long long)lost;
+  *Se.iz_cnt = 0;
+}
+
 // ---------------------------------------------------------------- energy
 // FP64 energy diagnostic.  Per block: the sum of |v|^2 over the live slots it
 // strides (kinetic), or of |E|^2 times the node's share of a cell volume (half
@@ -2428,8 +2557,8 @@ __global__ __launch_bounds__(kBlock) void field_energy_kernel(const ET* __restri
 // ---------------------------------------------------------------- launchers
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
-int tile_grid(int nx, int ny, int nz) {
-  return (((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) + 15) / 16 * 16;
+int tile_grid(int nx, int ny, int nz, int extra) {
+  return (((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4) + extra + 15) / 16 * 16;
 }
 
 
@@ -2576,6 +2705,18 @@ void launch_fine_moments(const PartF64* P64, const PartF32R* P32, const WorkList
                        mom, avg);
 }
 
+void launch_ionize(const PartF64* Pe64, const PartF64* Pi64, const PartF32R* Pe32,
+                   const PartF32R* Pi32, const WorkLists& Le, const WorkLists& Li,
+                   const SpeciesStep& Se, uint32_t* next_id, long room_e, long room_i,
+                   unsigned long long* dropped, hipStream_t st) {
+  if (Pe64)
+    hipLaunchKernelGGL(ionize_kernel<PartF64>, dim3(1), dim3(kIzThreads), 0, st, *Pe64, *Pi64, Le,
+                       Li, Se, next_id, room_e, room_i, dropped);
+  else
+    hipLaunchKernelGGL(ionize_kernel<PartF32R>, dim3(1), dim3(kIzThreads), 0, st, *Pe32, *Pi32, Le,
+                       Li, Se, next_id, room_e, room_i, dropped);
+}
+
 int energy_blocks() { return kEnergyBlocks; }
 
 void launch_energy(const PartF64* P64, const PartF32R* P32, const WorkLists& L, double* out,
@@ -2602,7 +2743,7 @@ void launch_fill_int(int* a, long n, int v, hipStream_t st) {
   hipLaunchKernelGGL(fill_int_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a, n, v);
 }
 
-long sort_keys(int nx, int ny, int nz) { return 2L * tile_grid(nx, ny, nz) + 1; }
+long sort_keys(int ngrid) { return 2L * ngrid + 1; }
 
 template <typename PT>
 static void sort_impl(const PT& src, const PT& dst, const WorkLists& L, int* hist, int* sums,

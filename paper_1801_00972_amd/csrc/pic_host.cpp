@@ -44,6 +44,15 @@ struct Replica {
   // e excitation, ion charge exchange, ion elastic), device copy, the bounds
   std::vector<double> xs;
   double* d_xs = nullptr;
+  // electron-impact ionisation (an ionisation table given): the step's
+  // events, their count, the next ids per species, events lost (no room)
+  bool ionize = false;
+  IzEvent* d_iz = nullptr;
+  int* d_iz_cnt = nullptr;
+  int iz_cap = 0;
+  uint32_t* d_next_id = nullptr;
+  unsigned long long* d_iz_drop = nullptr;
+  int64_t iz_base = 0;  // ionisations before the last pic_set_state / pic_load
   double sg_max[2]{};
   double vth_gas = 0;
   long n_load = 0;     // particles per species at load
@@ -363,10 +372,14 @@ int validate(const pic_config& c, std::string& why) {
     for (int i = 0; i < c.xs_n; ++i) {
       if (!(std::isfinite(c.xs_E[i]) && c.xs_E[i] >= 0) || (i > 0 && !(c.xs_E[i] > c.xs_E[i - 1])))
         return bad("xs_E must be finite, >= 0 and increasing");
-      for (const double* t : {c.xs_e_el, c.xs_e_ex, c.xs_i_cx, c.xs_i_el})
+      for (const double* t : {c.xs_e_el, c.xs_e_ex, c.xs_i_cx, c.xs_i_el, c.xs_e_iz})
         if (t && !(std::isfinite(t[i]) && t[i] >= 0)) return bad("cross sections must be >= 0");
     }
   }
+  if (c.xs_e_iz && (c.xs_n == 0 || !(std::isfinite(c.E_iz_eV) && c.E_iz_eV > 0)))
+    return bad("ionisation needs the cross-section tables and E_iz_eV > 0");
+  if (c.max_particles < 0 || c.max_particles > 2147483647L - 4L * 1048576L)
+    return bad("max_particles out of range");
   if (c.coulomb_interval < 0) return bad("coulomb_interval must be >= 0");
   if (c.coulomb_interval > 0 && !(std::isfinite(c.coulomb_lnL) && c.coulomb_lnL > 0))
     return bad("coulomb_lnL must be > 0");
@@ -530,6 +543,12 @@ SpeciesStep species_step(const Replica& R, int sp) {
   S.xs_n = c.xs_n;
   S.sg_max = R.sg_max[sp];
   S.ex_g2 = 2.0 * c.E_ex_eV * kCharge / (R.m[0] * R.m[1] / (R.m[0] + R.m[1]));
+  if (sp == 0 && R.ionize) {
+    S.iz_g2 = 2.0 * c.E_iz_eV * kCharge / (R.m[0] * R.m[1] / (R.m[0] + R.m[1]));
+    S.iz_ev = R.d_iz;
+    S.iz_cnt = R.d_iz_cnt;
+    S.iz_cap = R.iz_cap;
+  }
   S.key0 = (uint32_t)(c.seed & 0xffffffffu);
   S.key1 = (uint32_t)(c.seed >> 32);
   S.step = R.d_step;
@@ -769,6 +788,10 @@ int enqueue_sample(pic_ctx* ctx, Replica& R) {
   return PIC_OK;
 }
 
+// slots in use a species may reach with the particles of ionisation, so that
+// the next re-binning (each tile padded to a multiple of 4) still fits
+long iz_room(const Replica& R) { return R.cap[0] - 4L * R.ngrid; }
+
 // launches one step of a replica on ctx->stream from the host state at the
 // start of the step (buffer phases); advance_host then moves the host mirrors
 int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
@@ -799,6 +822,9 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
     hipEvent_t b = prof_event(ctx);
     launch_lists_f64(P, (const double*)R.E, (double*)R.rho[rnx], R.md, S, R.d_gc, R.lists, do_mcc,
                      st);
+    if (R.ionize)
+      launch_ionize(&P[0], &P[1], nullptr, nullptr, R.lists[0], R.lists[1], S[0], R.d_next_id,
+                    iz_room(R), iz_room(R), R.d_iz_drop, st);
     prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
   } else {
     launch_zero_i64((long long*)R.rho[rnx], R.nn, st);
@@ -815,6 +841,9 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
     hipEvent_t b = prof_event(ctx);
     launch_lists_f32r(P, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc, R.lists,
                       do_mcc, st);
+    if (R.ionize)
+      launch_ionize(nullptr, nullptr, &P[0], &P[1], R.lists[0], R.lists[1], S[0], R.d_next_id,
+                    iz_room(R), iz_room(R), R.d_iz_drop, st);
     prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
   }
   launch_advance_step(R.d_step, st);
@@ -895,6 +924,9 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
     for (int sp = 0; sp < 2; ++sp) launch_collide_f32r(P[sp], S[sp], R.lists[sp], ws);
     launch_lists_f32r(P, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc, R.lists, 1,
                       ws);
+    if (R.ionize)
+      launch_ionize(nullptr, nullptr, &P[0], &P[1], R.lists[0], R.lists[1], S[0], R.d_next_id,
+                    iz_room(R), iz_room(R), R.d_iz_drop, ws);
     launch_advance_step(R.d_step, ws);
     return PIC_OK;
   }));
@@ -1149,7 +1181,9 @@ double xs_value(const std::vector<double>& xs, int n, int k, double E) {
 // grid points, E_cap and those stationary points.
 double xs_bound(const std::vector<double>& xs, int n, int sp, double E_cap, double m) {
   const int c0 = sp == 0 ? 1 : 3;
-  auto total = [&](double E) { return xs_value(xs, n, c0, E) + xs_value(xs, n, c0 + 1, E); };
+  auto total = [&](double E) {
+    return xs_value(xs, n, c0, E) + xs_value(xs, n, c0 + 1, E) + (sp == 0 ? xs_value(xs, n, 5, E) : 0.0);
+  };
   auto f = [&](double E) { return total(E) * std::sqrt(2.0 * E * kCharge / m); };
   std::vector<double> cand{0.0, E_cap};
   for (int i = 0; i < n; ++i)
@@ -1202,12 +1236,13 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   const double sigma[2] = {c.sigma_e_el, c.sigma_i_cx};
   if (c.xs_n > 0) {
     const int n = c.xs_n;
-    R.xs.assign(5L * n, 0.0);
-    const double* cols[5] = {c.xs_E, c.xs_e_el, c.xs_e_ex, c.xs_i_cx, c.xs_i_el};
-    for (int k = 0; k < 5; ++k)
+    R.xs.assign(6L * n, 0.0);
+    const double* cols[6] = {c.xs_E, c.xs_e_el, c.xs_e_ex, c.xs_i_cx, c.xs_i_el, c.xs_e_iz};
+    R.ionize = c.xs_e_iz != nullptr;
+    for (int k = 0; k < 6; ++k)
       if (cols[k]) std::copy(cols[k], cols[k] + n, R.xs.begin() + (long)k * n);
     // the caller's arrays are not kept
-    c.xs_E = c.xs_e_el = c.xs_e_ex = c.xs_i_cx = c.xs_i_el = nullptr;
+    c.xs_E = c.xs_e_el = c.xs_e_ex = c.xs_i_cx = c.xs_i_el = c.xs_e_iz = nullptr;
   }
   for (int s = 0; s < 2; ++s) {
     R.g_cap[s] = std::sqrt(2.0 * c.E_cap_eV * kCharge / R.m[s]);
@@ -1218,6 +1253,18 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
     R.T_null[s] = (uint64_t)std::floor(R.P_null[s] * 4294967296.0);
   }
   R.vth_gas = std::sqrt(kBoltz * c.T_gas_K / kMassAr);
+  if (R.ionize) {
+    R.iz_cap = (int)std::min<long>(std::max<long>(4096, (long)c.nx * c.ny * c.nz * c.ppc / 64), 1L << 24);
+    TRY(dalloc(ctx, R, &R.d_iz, R.iz_cap));
+    TRY(dalloc(ctx, R, &R.d_iz_cnt, 1));
+    TRY(dalloc(ctx, R, &R.d_next_id, 2));
+    TRY(dalloc(ctx, R, &R.d_iz_drop, 1));
+    HIPCHK(ctx, hipMemsetAsync(R.d_iz_cnt, 0, 4, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(R.d_iz_drop, 0, 8, ctx->stream));
+    const uint32_t nid[2] = {(uint32_t)((long)c.nx * c.ny * c.nz * c.ppc),
+                             (uint32_t)((long)c.nx * c.ny * c.nz * c.ppc)};
+    HIPCHK(ctx, hipMemcpyAsync(R.d_next_id, nid, 8, hipMemcpyHostToDevice, ctx->stream));
+  }
   if (c.xs_n > 0) {
     TRY(dalloc(ctx, R, &R.d_xs, R.xs.size()));
     HIPCHK(ctx, hipMemcpyAsync(R.d_xs, R.xs.data(), R.xs.size() * sizeof(double),
@@ -1226,8 +1273,15 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   R.n_load = R.ncell * c.ppc;
   // tiles of 4x4x4 cells; each tile's slot range is padded to a multiple of 4
   R.ntiles = ((R.nx + 3) / 4) * ((R.ny + 3) / 4) * ((R.nz + 3) / 4);
-  R.ngrid = tile_grid(R.nx, R.ny, R.nz);
-  R.cap[0] = R.cap[1] = (R.n_load + 4L * R.ntiles + 1023) / 1024 * 1024;
+  // with ionisation the grid keeps a padding tile at its end, whose slot range
+  // takes the particles made since the last re-binning
+  R.ngrid = tile_grid(R.nx, R.ny, R.nz, R.ionize ? 1 : 0);
+  {
+    long most = R.n_load;
+    if (c.max_particles > 0) most = std::max<long>(most, (long)c.max_particles);
+    else if (R.ionize) most = R.n_load + R.n_load / 4;
+    R.cap[0] = R.cap[1] = (most + 4L * R.ngrid + 1023) / 1024 * 1024;
+  }
   if (!factor_len(R.nx, R.fft.fac_x, &R.fft.nfac_x) || !factor_len(R.ny, R.fft.fac_y, &R.fft.nfac_y))
     return fail(ctx, PIC_EINVAL, "FFT length not supported");
   R.fft.L_x = lines_per_block(R.nx, R.ny);
@@ -1270,7 +1324,7 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
   // two sums and a partial pair per residual block (blocks of 256 nodes per plane)
   TRY(dalloc(ctx, R, &R.norms, 2 + 2 * ((R.nxy + 255) / 256) * (R.nz - 1)));
   TRY(dalloc(ctx, R, &R.d_gc, 2 * std::max(c.n_grains, 1)));
-  const long nkey = sort_keys(R.nx, R.ny, R.nz);
+  const long nkey = sort_keys(R.ngrid);
   TRY(dalloc(ctx, R, &R.d_hist, nkey));
   TRY(dalloc(ctx, R, &R.d_sums, (nkey + 1023) / 1024 + 1));
   HIPCHK(ctx, hipMemsetAsync(R.d_gc, 0, 16 * std::max(c.n_grains, 1), st));
@@ -1469,8 +1523,9 @@ struct CkptConfig {
   int32_t nx, ny, nz, ppc, n_grains, cutoff, md_sub, precision, max_refine, coulomb_interval,
       xs_n, pad;
   double dx, dt, n0, Te, Ti, p_gas, T_gas, sig_e, sig_i, V_dc, V_rf, f_rf, radius, E_cap,
-      refine_tol, lnL, E_ex;
+      refine_tol, lnL, E_ex, E_iz;
   uint64_t seed;
+  int64_t max_particles;
 };
 
 CkptConfig ckpt_config(const Replica& R) {
@@ -1505,11 +1560,13 @@ CkptConfig ckpt_config(const Replica& R) {
   k.refine_tol = c.refine_tol;
   k.lnL = c.coulomb_lnL;
   k.E_ex = c.E_ex_eV;
+  k.E_iz = R.ionize ? c.E_iz_eV : 0.0;
   k.seed = c.seed;
+  k.max_particles = c.max_particles;
   return k;
 }
 
-constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '1'};
+constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '2'};
 constexpr int kCkptTallies[] = {TL_MD, TL_FALL, TL_COLL, TL_CAP, TL_BAD, TL_FAST};
 
 struct File {
@@ -1991,6 +2048,16 @@ int pic_set_state(pic_ctx* ctx, int replica, const pic_state_view* v) {
   }
   R->step = v->step;
   HIPCHK(ctx, hipMemcpy(R->d_step, &v->step, 4, hipMemcpyHostToDevice));
+  if (R->ionize) {
+    // ionisations continue with the ids after the largest given
+    uint32_t nid[2] = {0u, 0u};
+    for (int sp = 0; sp < 2; ++sp)
+      for (long i = 0; i < v->n[sp]; ++i) nid[sp] = std::max(nid[sp], v->id[sp][i] + 1u);
+    HIPCHK(ctx, hipMemcpy(R->d_next_id, nid, 8, hipMemcpyHostToDevice));
+    const int zero = 0;
+    HIPCHK(ctx, hipMemcpy(R->d_iz_cnt, &zero, 4, hipMemcpyHostToDevice));
+    R->iz_base = 0;
+  }
   TRY(resort(ctx, *R));
   TRY(deposit_current(ctx, *R));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -2045,6 +2112,18 @@ int pic_save(pic_ctx* ctx, const char* path) {
       int ctl[4] = {0, 0, 0, 0};
       HIPCHK(ctx, hipMemcpy(ctl, R.refine_ctl, sizeof(ctl), hipMemcpyDeviceToHost));
       ok = ok && put(out.f, &n_coul, 1) && put(out.f, &ctl[2], 1);
+      // ionisation: the next ids, the pairs made, the ones dropped
+      uint32_t nid[2] = {0u, 0u};
+      unsigned long long drop = 0;
+      int64_t n_iz = 0;
+      if (R.ionize) {
+        HIPCHK(ctx, hipMemcpy(nid, R.d_next_id, 8, hipMemcpyDeviceToHost));
+        HIPCHK(ctx, hipMemcpy(&drop, R.d_iz_drop, 8, hipMemcpyDeviceToHost));
+        pic_counters cn;
+        TRY(pic_get_counters(ctx, (int)r, &cn));
+        n_iz = cn.n_ionizations;
+      }
+      ok = ok && put(out.f, nid, 2) && put(out.f, &n_iz, 1) && put(out.f, &drop, 1);
       for (int sp = 0; ok && sp < 2; ++sp) {
         const int64_t n = v.n[sp];
         ok = put(out.f, &n, 1) && put(out.f, pos[sp].data(), 3 * (size_t)n) &&
@@ -2087,6 +2166,9 @@ int pic_load(pic_ctx* ctx, const char* path) {
     unsigned long long t[2][6];
     unsigned long long n_coul = 0;
     int unconverged = 0;
+    uint32_t next_id[2] = {0u, 0u};
+    int64_t n_iz = 0;
+    unsigned long long drop = 0;
   };
   std::vector<Saved> saved(nrep);
   const std::string trunc = "checkpoint truncated";
@@ -2111,7 +2193,8 @@ int pic_load(pic_ctx* ctx, const char* path) {
     S.gc.assign(2 * (size_t)std::max(ng, 1), 0);
     if (!get(in.f, &v.step, 1) || !get(in.f, S.gc.data(), 2 * (size_t)ng) ||
         !get(in.f, &v.wall_count[0][0], 4) || !get(in.f, &S.t[0][0], 12) ||
-        !get(in.f, &S.n_coul, 1) || !get(in.f, &S.unconverged, 1))
+        !get(in.f, &S.n_coul, 1) || !get(in.f, &S.unconverged, 1) ||
+        !get(in.f, S.next_id, 2) || !get(in.f, &S.n_iz, 1) || !get(in.f, &S.drop, 1))
       return fail(ctx, PIC_EINVAL, trunc);
     for (int sp = 0; sp < 2; ++sp) {
       int64_t n = 0;
@@ -2157,6 +2240,11 @@ int pic_load(pic_ctx* ctx, const char* path) {
     HIPCHK(ctx, hipMemcpy(R.refine_ctl, ctl, sizeof(ctl), hipMemcpyHostToDevice));
     if (!S.psi.empty())
       HIPCHK(ctx, hipMemcpy(R.psi, S.psi.data(), S.psi.size() * 8, hipMemcpyHostToDevice));
+    if (R.ionize) {
+      HIPCHK(ctx, hipMemcpy(R.d_next_id, S.next_id, 8, hipMemcpyHostToDevice));
+      HIPCHK(ctx, hipMemcpy(R.d_iz_drop, &S.drop, 8, hipMemcpyHostToDevice));
+      R.iz_base = S.n_iz;
+    }
   }
   return PIC_OK;
 }
@@ -2175,7 +2263,8 @@ int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out) {
   for (int sp = 0; sp < 2; ++sp) {
     unsigned long long t[TL_N];
     TRY(read_tallies(ctx, *R, sp, t));
-    out->n_alive[sp] = R->n_base[sp] - (int64_t)t[TL_DEAD];
+    out->n_alive[sp] = R->n_base[sp] - (int64_t)t[TL_DEAD] + (int64_t)t[TL_BORN];
+    if (sp == 0) out->n_ionizations = R->iz_base + (int64_t)t[TL_BORN];
     out->cap_violation[sp] = (int64_t)t[TL_CAP];
     out->n_collisions[sp] = (int64_t)t[TL_COLL];
     out->md_particles[sp] = (int64_t)t[TL_MD];
@@ -2188,6 +2277,11 @@ int pic_get_counters(pic_ctx* ctx, int replica, pic_counters* out) {
   out->step = R->step;
   out->refine_sweeps = R->prec == PIC_FP32R ? ctl[1] : 0;
   out->refine_unconverged = R->prec == PIC_FP32R ? ctl[2] : 0;
+  if (R->d_iz_drop) {
+    unsigned long long dr = 0;
+    HIPCHK(ctx, hipMemcpy(&dr, R->d_iz_drop, 8, hipMemcpyDeviceToHost));
+    out->iz_dropped = (int64_t)dr;
+  }
   out->refine_residual = norms[1] > 0 ? std::sqrt(norms[0] / norms[1]) : std::sqrt(norms[0]);
   if (R->coul.count) {
     unsigned long long nc = 0;

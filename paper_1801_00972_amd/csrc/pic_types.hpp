@@ -15,7 +15,20 @@ constexpr double kMassAr = 39.948 * kAmu;
 constexpr double kPi = 3.14159265358979323846;
 
 // Philox counter word 2: what a draw is for
-enum Purpose : uint32_t { kInitPos = 1, kInitVel = 2, kColl = 3, kNeutral = 4, kGrain = 7 };
+enum Purpose : uint32_t {
+  kInitPos = 1, kInitVel = 2, kColl = 3, kNeutral = 4, kGrain = 7, kIonize = 8
+};
+
+// an electron-impact ionisation of the current step, made into particles after
+// every particle has moved: the parent's id and slot, its velocity before the
+// collision (m/s) and the squared relative speed left to share,
+// g^2 - 2 E_iz / mu (m^2/s^2)
+struct IzEvent {
+  uint32_t id;
+  int32_t slot;
+  double v[3];
+  double gsq;
+};
 
 // particle arrays of one species, structure of arrays
 struct PartF64 {
@@ -59,7 +72,10 @@ struct WorkLists {
 
 // per-tile event counts, accumulated since loading; TL_DEAD counts removed
 // particles; TL_FAST counts plain (not sub-cycled) pushes with |v| dt >= cutoff dx
-enum TallyKind { TL_W0 = 0, TL_W1, TL_BAD, TL_MD, TL_FALL, TL_COLL, TL_CAP, TL_DEAD, TL_FAST, TL_N };
+// TL_BORN particles created by ionisation (first tile row; one writer)
+enum TallyKind {
+  TL_W0 = 0, TL_W1, TL_BAD, TL_MD, TL_FALL, TL_COLL, TL_CAP, TL_DEAD, TL_FAST, TL_BORN, TL_N
+};
 
 // near-grain (MD) tables of one replica
 struct MdTables {
@@ -102,14 +118,21 @@ struct SpeciesStep {
   double vth_gas;
   double mass_ratio_e;     // m_e / (m_e + M)
   double mass_ratio_n;     // M / (m_e + M)
-  // energy-dependent cross sections (xs_n > 0): [5][xs_n] doubles: energy
+  // energy-dependent cross sections (xs_n > 0): [6][xs_n] doubles: energy
   // grid (eV), e-Ar elastic, e-Ar excitation, Ar+-Ar charge exchange, Ar+-Ar
-  // elastic (m^2); sg_max bounds g sigma_total; an excitation needs
-  // g^2 > ex_g2 = 2 E_ex / mu and leaves g'^2 = g^2 - ex_g2
+  // elastic, e-Ar ionisation (m^2); sg_max bounds g sigma_total; an
+  // excitation needs g^2 > ex_g2 = 2 E_ex / mu and leaves g'^2 = g^2 - ex_g2
   const double* xs;
   int xs_n;
   double sg_max;
   double ex_g2;
+  // ionisation (electrons with an ionisation table): needs g^2 > iz_g2 =
+  // 2 E_iz / mu; events go to iz_ev (iz_cap entries, iz_cnt counts them,
+  // including those beyond the capacity); iz_ev == nullptr: none
+  double iz_g2;
+  IzEvent* iz_ev;
+  int* iz_cnt;
+  int iz_cap;
   uint32_t key0, key1;
   const uint32_t* step;    // device: the step index k of the replica
   // deposit

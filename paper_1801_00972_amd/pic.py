@@ -59,6 +59,7 @@ class pic_config(C.Structure):
         ("xs_i_el", C.POINTER(C.c_double)), ("E_ex_eV", C.c_double),
         ("cluster_center", C.c_double * 3), ("cluster_radius", C.c_double),
         ("grain_min_sep", C.c_double),
+        ("xs_e_iz", C.POINTER(C.c_double)), ("E_iz_eV", C.c_double), ("max_particles", C.c_int64),
     ]
 
 
@@ -81,6 +82,7 @@ class pic_counters(C.Structure):
         ("step", C.c_uint32), ("refine_sweeps", C.c_int32), ("refine_residual", C.c_double),
         ("numeric_bad", C.c_int64), ("tile_fallback", C.c_int64), ("n_coulomb", C.c_int64),
         ("refine_unconverged", C.c_int64), ("md_margin", C.c_int64 * 2),
+        ("n_ionizations", C.c_int64), ("iz_dropped", C.c_int64),
     ]
 
 
@@ -190,15 +192,17 @@ def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 3):
     xs = wl.get("xs")
     if xs:
         # cross-section tables: a dict of E (eV) and e_el, e_ex, i_cx, i_el (m^2), E_ex (eV)
-        arrays = {k: np.ascontiguousarray(xs[k], np.float64) for k in ("E", "e_el", "e_ex", "i_cx", "i_el")
-                  if xs.get(k) is not None}
+        arrays = {k: np.ascontiguousarray(xs[k], np.float64)
+                  for k in ("E", "e_el", "e_ex", "i_cx", "i_el", "e_iz") if xs.get(k) is not None}
         keep.append(arrays)
         c.xs_n = len(arrays["E"])
         for k, field in (("E", "xs_E"), ("e_el", "xs_e_el"), ("e_ex", "xs_e_ex"), ("i_cx", "xs_i_cx"),
-                         ("i_el", "xs_i_el")):
+                         ("i_el", "xs_i_el"), ("e_iz", "xs_e_iz")):
             if k in arrays:
                 setattr(c, field, arrays[k].ctypes.data_as(C.POINTER(C.c_double)))
         c.E_ex_eV = float(xs.get("E_ex", 0.0))
+        c.E_iz_eV = float(xs.get("E_iz", 0.0))
+    c.max_particles = int(wl.get("max_particles", 0))
     return c, keep
 
 
@@ -361,7 +365,8 @@ def pic_get_counters(ctx, replica):
                 refine_sweeps=int(c.refine_sweeps), refine_residual=float(c.refine_residual),
                 numeric_bad=int(c.numeric_bad), tile_fallback=int(c.tile_fallback),
                 n_coulomb=int(c.n_coulomb), refine_unconverged=int(c.refine_unconverged),
-                md_margin=list(c.md_margin))
+                md_margin=list(c.md_margin), n_ionizations=int(c.n_ionizations),
+                iz_dropped=int(c.iz_dropped))
 
 
 def pic_derived(ctx, replica):
@@ -423,8 +428,20 @@ class Simulation:
                             stream if stream is not None else current_stream())
         self.n_nodes = [w["nx"] * w["ny"] * (w["nz"] + 1) for w in self.wls]
         self.n_grains = [int(m[0].n_grains) for m in made]
-        self.capacity = [w["nx"] * w["ny"] * w["nz"] * w["ppc"] for w in self.wls]
+        self.capacity = [self._slots(w) for w in self.wls]
         self.fine_nodes = [0] * len(self.wls)
+
+    @staticmethod
+    def _slots(w):
+        """Host room per species for pic_get_state: at most the library's
+        particles per species (the loaded count, max_particles, or a quarter
+        more with ionisation)."""
+        n = w["nx"] * w["ny"] * w["nz"] * w["ppc"]
+        if int(w.get("max_particles", 0)) > 0:
+            return max(n, int(w["max_particles"]))
+        if (w.get("xs") or {}).get("e_iz") is not None:
+            return n + n // 4
+        return n
 
     def step(self, n=1):
         pic_step(self.ctx, n)

@@ -159,14 +159,21 @@ def tiny(nx=8, ny=8, nz=12, ppc=2, grains=None, **kw) -> dict:
     return wl
 
 
-def stand_in_xs() -> dict:
+def stand_in_xs(ionization: bool = False) -> dict:
     """Synthetic cross-section tables for the energy-dependent collision path:
     smooth analytic shapes of roughly argon-like magnitude (NOT measured data),
-    on one grid of projectile energies (eV), for timing and tests."""
+    on one grid of projectile energies (eV), for timing and tests; with
+    `ionization`, also an ionisation table above a 15.76 eV threshold."""
     E = np.concatenate([[0.0], np.geomspace(1e-2, 1e3, 63)])
     e_el = 1.0e-19 * (0.4 + 0.6 * E / (1.0 + E)) / np.sqrt(1.0 + E / 200.0)
     E_ex = 11.5
     e_ex = np.where(E > E_ex, 3.0e-20 * (1.0 - E_ex / np.maximum(E, E_ex)), 0.0)
     i_cx = 5.0e-19 / (1.0 + E) ** 0.1
     i_el = 3.0e-19 / (1.0 + E) ** 0.2
-    return dict(E=E, e_el=e_el, e_ex=e_ex, i_cx=i_cx, i_el=i_el, E_ex=E_ex)
+    out = dict(E=E, e_el=e_el, e_ex=e_ex, i_cx=i_cx, i_el=i_el, E_ex=E_ex)
+    if ionization:
+        E_iz = 15.76
+        out["e_iz"] = np.where(E > E_iz, 2.5e-20 * np.log(np.maximum(E, E_iz) / E_iz)
+                               / (1.0 + np.log(np.maximum(E, E_iz) / E_iz)), 0.0)
+        out["E_iz"] = E_iz
+    return out
