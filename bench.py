@@ -98,9 +98,13 @@ def fine_box(wl, h=0.08, cells=200):
 
 
 def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None, average=0,
-             fine=False):
+             fine=False, keep_state=False, persistent=False):
     """Times one arithmetic form on one context (a list of replica workloads:
-    one for the single-run forms, several for the batched ensemble)."""
+    one for the single-run forms, several for the batched ensemble).
+    keep_state: also return the state after the timed windows, its fields and
+    the state one more step later (for the CPU baseline's comparison).
+    persistent: for an ensemble whose tuner did not choose the persistent
+    push, also time the steps with it (batch_push = 1)."""
     import torch
 
     from paper_1801_00972_amd.pic import (PIC_PROF_COULOMB, PIC_PROF_FIELD, PIC_PROF_LISTS,
@@ -194,6 +198,40 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None, ave
         md_particle_steps=md1 - md0,
         collisions=coll1 - coll0,
     )
+    res["push_form"] = ("one persistent launch for every replica and species"
+                        if tuning.get("batch_push") else
+                        "one launch per replica and species" if len(wls) > 1 else
+                        "one launch per species")
+    if persistent and len(wls) > 1 and not tuning.get("batch_push"):
+        # the persistent one-launch push, timed on the same live run
+        sim.set_tuning(batch_push=1)
+        pic_profile_enable(sim.ctx, True)
+        n0p = _alive(sim)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        n1p = _alive(sim)
+        pms, pn = pic_profile_read(sim.ctx, PIC_PROF_PUSH)
+        pic_profile_enable(sim.ctx, False)
+        pps = 0.5 * (n0p + n1p) * steps
+        pbytes = pps * 2 * RECORD_BYTES[prec] + steps * nn * NODE_BYTES[prec]
+        pach = pbytes / (pms * 1e-3) / 1e9 if pms > 0 else 0.0
+        res["persistent_launch"] = dict(
+            value=pps / (t5 - t4), ms_per_step=1e3 * (t5 - t4) / steps,
+            note="direct launches with kernel events, batch_push = 1",
+            push_ms_per_launch=pms / max(pn, 1),
+            roofline=dict(bound="hbm", achieved=round(pach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=round(pach / HBM_PEAK_GBS, 4), kernel="push_batch_f32r"))
+        log(f"[bench] {label}: persistent push {res['persistent_launch']['value']:.3e} "
+            f"particle-steps/s, {res['persistent_launch']['ms_per_step']:.3f} ms/step")
+    if keep_state:
+        from paper_1801_00972_amd.pic import PIC_E, PIC_PHI, PIC_RHO_FIXED
+        before = sim.get_state()
+        flds = sim.fields(0, PIC_PHI | PIC_E | (PIC_RHO_FIXED if prec == "fp32r" else 0))
+        sim.step(1)
+        res["_snapshot"] = dict(before=before, fields=flds, after=sim.get_state())
     if average:
         res["averages"] = dict(interval=average, phase_bins=4,
                                fine_nodes=sim.fine_nodes if fine else None,
@@ -238,26 +276,87 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
     return dict(bytes_per_copy=2 * nbytes, ms=ms, GBs=2 * nbytes / (ms * 1e-3) / 1e9)
 
 
-def cpu_baseline(wl, steps=6):
-    """The oracle, as it stands, on the same workload: loading untimed, then a
-    bounded number of full steps timed on the host cores."""
-    import oracle
+def _native_oracle():
+    """The oracle built for this host (-O3 -march=native, OpenMP, no fast-math),
+    with the threads bound close (read when its OpenMP runtime loads)."""
+    import tempfile
 
+    import oracle
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    out = os.path.join(tempfile.mkdtemp(prefix="oracle_native_"), "liboracle_native.so")
+    oracle.build(native=True, out=out)
+    oracle.use_library(out)
+    return oracle
+
+
+def fp32r_error(wl, snap, o):
+    """Per-quantity error of the FP32R form against the FP64 oracle: the
+    fields of one state and one step of every particle from it (the oracle
+    `o` holds that state and moves it in its own field)."""
+    import numpy as np
+
+    from tests.parity_util import compare_step_all
+    f_o = o.fields(fixed_point=True)
+    g = snap["fields"]
+    V = max(abs(o.rf_voltage(snap["before"]["step"])), 1e-300)
+    err = dict(
+        rho_fixed_bit_exact=bool(np.array_equal(g["rho_fixed"], f_o["rho_fixed"])),
+        phi=float(np.abs(g["phi"] - f_o["phi"]).max() / max(np.abs(f_o["phi"]).max(), V)),
+        E=float(np.abs(g["E"] - f_o["E"]).max() / np.abs(f_o["E"]).max()),
+    )
+    o.step_in_field(f_o["E"])
+    after = snap["after"]
+    rep = compare_step_all(wl, after, o, 1.0, 1.0, 1e-5)
+    err.update(position_cells=rep["max_dpos"], velocity=rep["max_dvel"],
+               discrete_flips=rep["flips"], particles=rep["n"],
+               grain_count_diff=int(np.abs(after["grain_count"] - o.grain_count).sum()),
+               grain_counts=after["grain_count"].tolist())
+    return err
+
+
+def cpu_baseline(wl, snap=None, steps=12):
+    """The oracle, as it stands, timed on the host cores on the benchmark's own
+    state (the FP32R state after the timed windows, read back exactly), a
+    bounded number of full steps; with that state also the per-quantity error
+    of the FP32R form's step against the oracle's."""
+    import numpy as np
+    oracle = _native_oracle()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log(f"[bench] cpu baseline: oracle, {steps} steps of {wl['name']} on {threads} threads")
-    o = oracle.Oracle(dict(wl, precision="fp64"))
-    o.init_particles()
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    wl64 = dict(wl, precision="fp64")
+    res = dict(unit="particle-steps/s", cores=threads, kind="oracle", cpu_model=_cpu_model(),
+               nproc=nproc, omp_proc_bind=os.environ.get("OMP_PROC_BIND"),
+               build="gcc -O3 -march=native -fopenmp -ffp-contract=off (no fast-math)")
+    if snap is not None:
+        log(f"[bench] cpu baseline: FP32R error of one step against the oracle")
+        o = oracle.Oracle(wl64)
+        st = snap["before"]
+        for s in range(2):
+            o.set_particles(s, st[s]["pos"], st[s]["vel"], st[s]["id"])
+        o.set_counts(grain_count=st["grain_count"], wall_count=st["wall_count"], step=st["step"])
+        res["fp32r_error"] = fp32r_error(wl, snap, o)
+        log(f"[bench] FP32R error: {res['fp32r_error']}")
+        src = ("the benchmark's FP32R state after its timed steps, read back exactly "
+               f"(step {st['step']})")
+        o = oracle.Oracle(wl64)
+        for s in range(2):
+            o.set_particles(s, st[s]["pos"], st[s]["vel"], st[s]["id"])
+        o.set_counts(grain_count=st["grain_count"], wall_count=st["wall_count"], step=st["step"])
+        o.compact()
+    else:
+        o = oracle.Oracle(wl64)
+        o.init_particles()
+        src = "the oracle's own loading"
     o._units()
+    log(f"[bench] cpu baseline: oracle, {steps} steps of {wl['name']} on {threads} threads")
     n0 = o.n_alive(0) + o.n_alive(1)
     t0 = time.perf_counter()
     o.step(steps)
     t1 = time.perf_counter()
     n1 = o.n_alive(0) + o.n_alive(1)
-    ps = 0.5 * (n0 + n1) * steps
-    res = dict(value=ps / (t1 - t0), unit="particle-steps/s", cores=threads, kind="oracle",
-               sample=f"{steps} full FP64 oracle steps of {wl['name']} ({n0} particles) "
-                      f"from the oracle's own loading, {t1 - t0:.1f} s",
-               cpu_model=_cpu_model())
+    res["value"] = 0.5 * (n0 + n1) * steps / (t1 - t0)
+    res["sample"] = (f"{steps} full FP64 oracle steps of {wl['name']} ({n0} particles) from "
+                     f"{src}, {t1 - t0:.1f} s")
     # the same oracle on one thread, one more step of the same run
     try:
         import ctypes
@@ -273,10 +372,20 @@ def cpu_baseline(wl, steps=6):
                                     sample=f"step {steps + 1} of the same run, {t3 - t2:.1f} s")
     except OSError:
         res["single_thread"] = None
+    del np
     return res
 
 
 def _cpu_model():
+    """The host CPU's model name, as lscpu gives it (else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
@@ -344,15 +453,26 @@ def main():
     if args.workload == "large":
         forms = ["fp32r"]
     results = {}
+    head = "fp32r" if "fp32r" in forms else forms[0]
+    want_cpu = not args.no_cpu_baseline and args.workload != "large"
     for form in forms:
         wls = form_workloads(form, args.workload, args.coulomb, args.xs)
         results[form] = run_form(wls, args.steps, args.warmup, args.sort_interval,
                                  autotune=not args.no_autotune, average=args.average,
                                  fine=args.fine and args.average > 0,
+                                 keep_state=want_cpu and form == "fp32r" and form == head,
+                                 persistent=form == "batched",
                                  label=f"{form} {wls[0]['name']}" if len(wls) == 1 else
                                  f"batched ensemble of {len(wls)}")
-    head = "fp32r" if "fp32r" in results else forms[0]
+        if form == "batched":
+            # the plain FP64 form on the same replicas, for the batched form's speedup
+            wls64 = [dict(w, precision="fp64") for w in wls]
+            r64 = run_form(wls64, args.steps, args.warmup, args.sort_interval, autotune=False,
+                           label=f"fp64 ensemble of {len(wls64)}")
+            results["batched"]["fp64_same_replicas"] = {
+                k: r64[k] for k in ("value", "ms_per_step", "push_ms_per_launch", "settings")}
     wl = form_workloads(head, args.workload)[0]
+    snap = results.get(head, {}).pop("_snapshot", None)
     R = results[head]
     line = {
         "metric": METRIC,
@@ -388,8 +508,10 @@ def main():
     }
     if "fp64" in results and "fp32r" in results:
         line["speedup_fp32r_vs_fp64"] = results["fp32r"]["value"] / results["fp64"]["value"]
-    if "fp64" in results and "batched" in results:
-        line["speedup_batched_vs_fp64"] = results["batched"]["value"] / results["fp64"]["value"]
+    if "batched" in results:
+        # the same 16 replicas stepped in the plain FP64 form
+        line["speedup_batched_vs_fp64"] = (results["batched"]["value"] /
+                                           results["batched"]["fp64_same_replicas"]["value"])
     cb = copy_bandwidth()
     line["copy_bandwidth"] = cb
     line["roofline"]["frac_of_measured_copy"] = round(R["roofline"]["achieved"] / cb["GBs"], 4)
@@ -397,8 +519,9 @@ def main():
         # 2.7e8 FP64 oracle particles take ~15 GB and minutes per step: not a bounded sample
         line["cpu_baseline"] = None
     elif not args.no_cpu_baseline:
-        cb = cpu_baseline(W.full_fp64("fp64") if args.workload == "full" else W.small_fp64())
-        line["cpu_baseline"] = cb
+        line["cpu_baseline"] = cpu_baseline(wl, snap)
+        if "fp32r_error" in line["cpu_baseline"]:
+            line["fp32r_error"] = line["cpu_baseline"]["fp32r_error"]
     print(json.dumps(line), flush=True)
 
 
