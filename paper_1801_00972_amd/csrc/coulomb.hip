@@ -10,14 +10,16 @@
 //     key is the particle's Philox word (id, k, order purpose, species) above
 //     its id, so the order inside a cell does not depend on the scatter's
 //     atomics;
-//  3. one wave per block strides over pairs of cells, a half-wave per cell:
-//     each half stages its cell's keys, slots, ids and velocities in LDS,
-//     ranks each species by key, then runs the like items (e-e and Ar+-Ar+
-//     pairs, an odd count's triplet as one item) over its 32 lanes, a
-//     barrier, and the unlike pairs (one lane per particle of the less
-//     numerous species, its partners in order), all in FP64, and writes the
-//     velocities back once; a pair of cells with a species above the stage's
-//     64 runs both cells in turn through global memory with the whole wave.
+//  3. a block of 256 threads strides over groups of 8 consecutive cells (a
+//     contiguous range of the key / slot arrays): it stages the group's keys
+//     and slots in LDS in one sweep, ranks each particle inside its cell by
+//     key and gathers ids and velocities in that order, then 32 lanes per
+//     cell run the like items (e-e and Ar+-Ar+ pairs, an odd count's triplet
+//     as one item), a barrier, and the unlike pairs (one lane per particle of
+//     the less numerous species, its partners in order), and the velocities
+//     go back once; the arithmetic is in the velocities' precision (FP64 or
+//     FP32); a group with a cell above 64 particles of a species runs its
+//     cells in turn through global memory with the whole block.
 // Counting and scattering go a block per tile of the particle bins: an LDS
 // histogram and one global atomic per cell, one more per particle that has
 // left its tile since the last binning.
@@ -57,12 +59,19 @@ __device__ __forceinline__ int coul_cell(const PartF32R& P, long p, int ntx, int
   return tiled_cell(c & 1023, (c >> 10) & 1023, c >> 20, ntx, nty);
 }
 
+// The collision arithmetic runs in the precision the velocities are stored
+// in: FP64 for the FP64 records, FP32 for the FP32R records (whose velocities
+// are FP32 already; the pass's rounding is then of the order of the FP32
+// velocities' own).
+template <typename PT> struct CoulReal { using T = double; };
+template <> struct CoulReal<PartF32R> { using T = float; };
+
 __device__ __forceinline__ void load_v(const PartF64& P, long p, double v[3]) {
   v[0] = P.vx[p];
   v[1] = P.vy[p];
   v[2] = P.vz[p];
 }
-__device__ __forceinline__ void load_v(const PartF32R& P, long p, double v[3]) {
+__device__ __forceinline__ void load_v(const PartF32R& P, long p, float v[3]) {
   v[0] = P.vx[p];
   v[1] = P.vy[p];
   v[2] = P.vz[p];
@@ -72,10 +81,10 @@ __device__ __forceinline__ void store_v(const PartF64& P, long p, const double v
   P.vy[p] = v[1];
   P.vz[p] = v[2];
 }
-__device__ __forceinline__ void store_v(const PartF32R& P, long p, const double v[3]) {
-  P.vx[p] = (float)v[0];
-  P.vy[p] = (float)v[1];
-  P.vz[p] = (float)v[2];
+__device__ __forceinline__ void store_v(const PartF32R& P, long p, const float v[3]) {
+  P.vx[p] = v[0];
+  P.vy[p] = v[1];
+  P.vz[p] = v[2];
 }
 
 // Runs of equal cells in consecutive lanes of a wave (the slots of a tile are
@@ -239,25 +248,59 @@ __global__ __launch_bounds__(256) void coul_scatter_kernel(PT P, WorkLists L, Co
 // (Box-Muller cosine branch of words 0, 1) with variance cv n_L / |u|^3, the
 // azimuth 2 pi u(word 2); the relative velocity u = va - vb turns by
 // theta = 2 atan(delta) about itself, va += fa du, vb -= fb du.
-__device__ void coul_collide(const CoulombConst& C, uint32_t k, uint32_t word, double cv,
-                             double fa, double fb, double* va, double* vb, uint32_t id) {
-  const double u0 = va[0] - vb[0], u1 = va[1] - vb[1], u2 = va[2] - vb[2];
-  const double um = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
-  if (!(um > 0.0)) return;
+// The draws' three functions of the uniforms, per precision: the normal
+// deviate sqrt(-2 ln u1) cos(2 pi u2) and cos, sin of 2 pi u3.
+struct CoulDraw64 {
+  __device__ static double normal(uint32_t a, uint32_t b) {
+    // cospi / sincospi take the angle in half turns: no range reduction by pi
+    return sqrt(-2.0 * log(u01_open(a))) * cospi(2.0 * u01_open(b));
+  }
+  __device__ static void azimuth(uint32_t c, double* s, double* co) {
+    sincospi(2.0 * u01_open(c), s, co);
+  }
+};
+struct CoulDraw32 {
+  // (w + 1/2) 2^-32 in FP32: w rounded to 24 bits, relative error <= 2^-24
+  __device__ static float u01(uint32_t w) {
+    return __builtin_fmaf((float)w, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
+  }
+  // the hardware log2, and cos / sin of 2 pi x taken in turns (x in (0, 1))
+  __device__ static float normal(uint32_t a, uint32_t b) {
+    const float ln_u = __builtin_amdgcn_logf(u01(a)) * 0.69314718055994531f;
+    return __builtin_amdgcn_sqrtf(-2.0f * ln_u) * __builtin_amdgcn_cosf(u01(b));
+  }
+  __device__ static void azimuth(uint32_t c, float* s, float* co) {
+    const float x = u01(c);
+    *s = __builtin_amdgcn_sinf(x);
+    *co = __builtin_amdgcn_cosf(x);
+  }
+};
+template <typename R> struct CoulDraw;
+template <> struct CoulDraw<double> : CoulDraw64 {};
+template <> struct CoulDraw<float> : CoulDraw32 {};
+__device__ __forceinline__ double coul_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float coul_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double coul_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float coul_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <typename R>
+__device__ void coul_collide(const CoulombConst& C, uint32_t k, uint32_t word, R cv, R fa, R fb,
+                             R* va, R* vb, uint32_t id) {
+  const R u0 = va[0] - vb[0], u1 = va[1] - vb[1], u2 = va[2] - vb[2];
+  const R um2 = u0 * u0 + u1 * u1 + u2 * u2;
+  if (!(um2 > (R)0)) return;
+  const R um = coul_sqrt(um2);
   const uint4 r = philox4x32_10(id, k, kCPair, word, C.key0, C.key1);
-  // Box-Muller, cosine branch: sqrt(-2 ln u1) cos(2 pi u2); cospi / sincospi
-  // take the angle in half turns, which needs no range reduction by pi
-  const double n0 = sqrt(-2.0 * log(u01_open(r.x))) * cospi(2.0 * u01_open(r.y));
-  const double delta = sqrt(cv / (um * um * um)) * n0;
-  double sp, cp;
-  sincospi(2.0 * u01_open(r.z), &sp, &cp);
-  const double inv = 1.0 / (1.0 + delta * delta);
-  const double sn = 2.0 * delta * inv;
-  const double omc = 2.0 * delta * delta * inv;
-  const double up = sqrt(u0 * u0 + u1 * u1);
-  double du[3];
-  if (up > 0.0) {
-    const double iu = 1.0 / up;
+  const R delta = coul_sqrt(cv * coul_rcp(um2 * um)) * CoulDraw<R>::normal(r.x, r.y);
+  R sp, cp;
+  CoulDraw<R>::azimuth(r.z, &sp, &cp);
+  const R inv = coul_rcp((R)1 + delta * delta);
+  const R sn = (R)2 * delta * inv;
+  const R omc = (R)2 * delta * delta * inv;
+  const R up = coul_sqrt(u0 * u0 + u1 * u1);
+  R du[3];
+  if (up > (R)0) {
+    const R iu = coul_rcp(up);
     du[0] = (u0 * iu) * u2 * sn * cp - (u1 * iu) * um * sn * sp - u0 * omc;
     du[1] = (u1 * iu) * u2 * sn * cp + (u0 * iu) * um * sn * sp - u1 * omc;
     du[2] = -up * sn * cp - u2 * omc;
@@ -290,51 +333,58 @@ __device__ void coul_collide(const CoulombConst& C, uint32_t k, uint32_t word, d
       const int s = it < items[0] ? 0 : 1;                                                  \
       const int i = it - (s ? items[0] : 0);                                                \
       const int N = n[s];                                                                   \
-      const double cv = C.c_var[s] * (double)N * C.w_vol;                                   \
-      const double f = C.frac[s][s];                                                        \
+      const R cv = (R)(C.c_var[s] * (double)N * C.w_vol);                                   \
+      const R f = (R)C.frac[s][s];                                                          \
       if ((N & 1) && i == 0) {                                                              \
-        coul_collide(C, k, (uint32_t)s, 0.5 * cv, f, f, V(s, 0), V(s, 1), ID(s, 0));        \
-        coul_collide(C, k, (uint32_t)s, 0.5 * cv, f, f, V(s, 1), V(s, 2), ID(s, 1));        \
-        coul_collide(C, k, (uint32_t)s, 0.5 * cv, f, f, V(s, 2), V(s, 0), ID(s, 2));        \
+        coul_collide<R>(C, k, (uint32_t)s, (R)0.5 * cv, f, f, V(s, 0), V(s, 1), ID(s, 0));  \
+        coul_collide<R>(C, k, (uint32_t)s, (R)0.5 * cv, f, f, V(s, 1), V(s, 2), ID(s, 1));  \
+        coul_collide<R>(C, k, (uint32_t)s, (R)0.5 * cv, f, f, V(s, 2), V(s, 0), ID(s, 2));  \
       } else {                                                                              \
         const int q = (N & 1) ? 3 + 2 * (i - 1) : 2 * i;                                     \
-        coul_collide(C, k, (uint32_t)s, cv, f, f, V(s, q), V(s, q + 1), ID(s, q));          \
+        coul_collide<R>(C, k, (uint32_t)s, cv, f, f, V(s, q), V(s, q + 1), ID(s, q));       \
       }                                                                                     \
     }                                                                                       \
     __syncthreads();                                                                        \
     if (n[0] > 0 && n[1] > 0) {                                                             \
       const int sa = n[0] >= n[1] ? 0 : 1, sb = 1 - sa;                                     \
       const int Na = n[sa], Nb = n[sb];                                                     \
-      const double cv = C.c_var[2] * (double)Nb * C.w_vol;                                  \
+      const R cv = (R)(C.c_var[2] * (double)Nb * C.w_vol);                                  \
       for (int r = (LANE); r < Nb; r += (W))                                                \
         for (int j = r; j < Na; j += Nb)                                                    \
-          coul_collide(C, k, 2u + (uint32_t)sa, cv, C.frac[2][sa], C.frac[2][sb], V(sa, j), \
-                       V(sb, r), ID(sa, j));                                                \
+          coul_collide<R>(C, k, 2u + (uint32_t)sa, cv, (R)C.frac[2][sa], (R)C.frac[2][sb],  \
+                          V(sa, j), V(sb, r), ID(sa, j));                                   \
     }                                                                                       \
     __syncthreads();                                                                        \
   }
 
 // cells whose species each hold at most kCellCap particles go through LDS
 constexpr int kCellCap = 64;
-struct CellStage {
-  unsigned long long key[2][kCellCap];
-  int slot_in[2][kCellCap];
-  int slot[2][kCellCap];  // in key order
-  uint32_t id[2][kCellCap];
-  double v[2][kCellCap][3];
+constexpr int kPairThreads = 256;  // threads of a pair block: 32 lanes per cell of a group
+constexpr int kGroup = kPairThreads / 32;  // consecutive cells staged together
+constexpr int kGroupCap = 512;     // staged particles of a species per group
+template <typename R>
+struct GroupStage {
+  unsigned long long key[2][kGroupCap];
+  int slot_in[2][kGroupCap];
+  int slot[2][kGroupCap];  // in key order inside each cell
+  uint32_t id[2][kGroupCap];
+  R v[2][kGroupCap][3];
+  int cs[2][kGroup + 1];   // the cells' starts in the key / slot arrays
 };
 
 // cells above the LDS capacity: the rule through global memory, the slots
-// ranked into the order array, one cell at a time with the whole wave
+// ranked into the order array, one cell at a time with the whole block
 template <typename PT>
 __device__ void global_collide(const PT P[2], const int* const ord[2], const CoulombConst& C,
-                               uint32_t k, uint32_t word, double cv, double fa, double fb, int sa,
+                               uint32_t k, uint32_t word, typename CoulReal<PT>::T cv,
+                               typename CoulReal<PT>::T fa, typename CoulReal<PT>::T fb, int sa,
                                int qa, int sb, int qb, uint32_t id) {
+  using R = typename CoulReal<PT>::T;
   const long pa = ord[sa][qa], pb = ord[sb][qb];
-  double va[3], vb[3];
+  R va[3], vb[3];
   load_v(P[sa], pa, va);
   load_v(P[sb], pb, vb);
-  coul_collide(C, k, word, cv, fa, fb, va, vb, id);
+  coul_collide<R>(C, k, word, cv, fa, fb, va, vb, id);
   store_v(P[sa], pa, va);
   store_v(P[sb], pb, vb);
 }
@@ -342,6 +392,7 @@ __device__ void global_collide(const PT P[2], const int* const ord[2], const Cou
 template <typename PT>
 __device__ void cell_global(const PT P[2], const CoulombBufs& B, const CoulombConst& C, uint32_t k,
                             int c, int lane) {
+  using R = typename CoulReal<PT>::T;
   int r0[2], n[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -352,7 +403,7 @@ __device__ void cell_global(const PT P[2], const CoulombBufs& B, const CoulombCo
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const unsigned long long* key = B.key[s] + r0[s];
-    for (int q = lane; q < n[s]; q += 64) {
+    for (int q = lane; q < n[s]; q += kPairThreads) {
       const unsigned long long kq = key[q];
       int rank = 0;
       for (int t = 0; t < n[s]; ++t) rank += key[t] < kq;
@@ -365,35 +416,35 @@ __device__ void cell_global(const PT P[2], const CoulombBufs& B, const CoulombCo
   for (int s = 0; s < 2; ++s) {
     const int N = n[s];
     if (N < 2) continue;
-    const double cv = C.c_var[s] * (double)N * C.w_vol;
-    const double f = C.frac[s][s];
+    const R cv = (R)(C.c_var[s] * (double)N * C.w_vol);
+    const R f = (R)C.frac[s][s];
     int first = 0;
     if (N & 1) {
       if (lane == 0) {
-        global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 0, s, 1, P[s].id[ord[s][0]]);
-        global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 1, s, 2, P[s].id[ord[s][1]]);
-        global_collide(P, ord, C, k, (uint32_t)s, 0.5 * cv, f, f, s, 2, s, 0, P[s].id[ord[s][2]]);
+        global_collide(P, ord, C, k, (uint32_t)s, (R)0.5 * cv, f, f, s, 0, s, 1, P[s].id[ord[s][0]]);
+        global_collide(P, ord, C, k, (uint32_t)s, (R)0.5 * cv, f, f, s, 1, s, 2, P[s].id[ord[s][1]]);
+        global_collide(P, ord, C, k, (uint32_t)s, (R)0.5 * cv, f, f, s, 2, s, 0, P[s].id[ord[s][2]]);
       }
       first = 3;
     }
-    for (int q = first + 2 * lane; q + 1 < N; q += 128)
+    for (int q = first + 2 * lane; q + 1 < N; q += 2 * kPairThreads)
       global_collide(P, ord, C, k, (uint32_t)s, cv, f, f, s, q, s, q + 1, P[s].id[ord[s][q]]);
   }
   __syncthreads();
   if (n[0] > 0 && n[1] > 0) {
     const int sa = n[0] >= n[1] ? 0 : 1, sb = 1 - sa;
     const int Na = n[sa], Nb = n[sb];
-    const double cv = C.c_var[2] * (double)Nb * C.w_vol;
-    for (int r = lane; r < Nb; r += 64) {
+    const R cv = (R)(C.c_var[2] * (double)Nb * C.w_vol);
+    const R fa = (R)C.frac[2][sa], fb = (R)C.frac[2][sb];
+    for (int r = lane; r < Nb; r += kPairThreads) {
       const long pb = ord[sb][r];
-      double vb[3];
+      R vb[3];
       load_v(P[sb], pb, vb);
       for (int j = r; j < Na; j += Nb) {
         const long pa = ord[sa][j];
-        double va[3];
+        R va[3];
         load_v(P[sa], pa, va);
-        coul_collide(C, k, 2u + (uint32_t)sa, cv, C.frac[2][sa], C.frac[2][sb], va, vb,
-                     P[sa].id[pa]);
+        coul_collide<R>(C, k, 2u + (uint32_t)sa, cv, fa, fb, va, vb, P[sa].id[pa]);
         store_v(P[sa], pa, va);
       }
       store_v(P[sb], pb, vb);
@@ -402,68 +453,91 @@ __device__ void cell_global(const PT P[2], const CoulombBufs& B, const CoulombCo
   __syncthreads();
 }
 
-// One wave per block strides over pairs of cells: each half-wave stages its
-// cell in LDS and runs the rule there (the two cells side by side, their
-// barriers shared); a pair with a cell above the stage's capacity runs both
-// cells in turn through global memory with the whole wave.
+// A block takes groups of kGroup consecutive cells in turn.  Their key / slot
+// ranges are contiguous, so the block stages a group's keys and slots in one
+// coalesced sweep, ranks each particle inside its cell by key, gathers ids and
+// velocities in that order, runs the pairing rule with 32 lanes per cell and
+// writes the velocities back.  A group with a cell above kCellCap particles of
+// a species, or with more than kGroupCap of a species, runs its cells one by
+// one through global memory with the whole block.
 template <typename PT>
-__global__ __launch_bounds__(64) void coul_pair_kernel(PT Pe, PT Pi, CoulombBufs B,
-                                                       CoulombConst C) {
-  __shared__ CellStage stage[2];
-  const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
+__global__ __launch_bounds__(kPairThreads) void coul_pair_kernel(PT Pe, PT Pi, CoulombBufs B,
+                                                                 CoulombConst C) {
+  using R = typename CoulReal<PT>::T;
+  __shared__ GroupStage<R> sm;
+  const int tid = threadIdx.x, cl = tid >> 5, hl = tid & 31;
   const PT P[2] = {Pe, Pi};
   const uint32_t k = *C.step;
-  CellStage& sm = stage[half];
-  unsigned long long pairings = 0;  // this half's cells, added to the counter once
-  for (int c0 = 2 * (int)blockIdx.x; c0 < C.ncell; c0 += 2 * (int)gridDim.x) {
-    const int c = c0 + half;
-    int r0[2] = {0, 0}, n[2] = {0, 0};
-    if (c < C.ncell) {
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        r0[s] = B.start[s][c];
-        n[s] = B.start[s][c + 1] - r0[s];
-      }
+  unsigned long long pairings = 0;  // this half-wave's cells, added to the counter once
+  // each block takes a contiguous run of whole tiles (64 cells, 8 groups):
+  // a tile's particle records are then gathered and written by one block,
+  // through one XCD's L2
+  const int ngroup = (C.ncell + kGroup - 1) / kGroup;
+  constexpr int kTileGroups = 64 / kGroup;
+  const int per = ((ngroup + (int)gridDim.x - 1) / (int)gridDim.x + kTileGroups - 1) /
+                  kTileGroups * kTileGroups;
+  const int g_end = min(ngroup, ((int)blockIdx.x + 1) * per);
+  for (int g = (int)blockIdx.x * per; g < g_end; ++g) {
+    const int c0 = g * kGroup;
+    if (tid < 2 * (kGroup + 1)) {
+      const int s = tid / (kGroup + 1), j = tid % (kGroup + 1);
+      sm.cs[s][j] = B.start[s][min(c0 + j, C.ncell)];
     }
+    __syncthreads();
+    const int b[2] = {sm.cs[0][0], sm.cs[1][0]};
+    const int N[2] = {sm.cs[0][kGroup] - b[0], sm.cs[1][kGroup] - b[1]};
+    bool fits = N[0] <= kGroupCap && N[1] <= kGroupCap;
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
-      if (n[s] >= 2) pairings += (n[s] & 1) ? 3 + (n[s] - 3) / 2 : n[s] / 2;
-    if (n[0] > 0 && n[1] > 0) pairings += n[0] > n[1] ? n[0] : n[1];
-    const bool fits = n[0] <= kCellCap && n[1] <= kCellCap;
-    if (__ballot(!fits) != 0ull) {
-      cell_global(P, B, C, k, c0, lane);
-      if (c0 + 1 < C.ncell) cell_global(P, B, C, k, c0 + 1, lane);
+    for (int j = 0; j < kGroup; ++j)
+      fits = fits && sm.cs[0][j + 1] - sm.cs[0][j] <= kCellCap &&
+             sm.cs[1][j + 1] - sm.cs[1][j] <= kCellCap;
+    int n[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) n[s] = sm.cs[s][cl + 1] - sm.cs[s][cl];
+    if (hl == 0) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        if (n[s] >= 2) pairings += (n[s] & 1) ? 3 + (n[s] - 3) / 2 : n[s] / 2;
+      if (n[0] > 0 && n[1] > 0) pairings += n[0] > n[1] ? n[0] : n[1];
+    }
+    if (!fits) {  // (block-uniform)
+      for (int j = 0; j < kGroup && c0 + j < C.ncell; ++j) cell_global(P, B, C, k, c0 + j, tid);
+      __syncthreads();
       continue;
     }
-    if (__ballot(n[0] + n[1] >= 2) == 0ull) continue;
-    // stage: keys and slots, then rank, gathering ids and velocities in key order
+    // stage the group's keys and slots
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      for (int q = hl; q < n[s]; q += 32) {
-        sm.key[s][q] = B.key[s][r0[s] + q];
-        sm.slot_in[s][q] = B.slot[s][r0[s] + q];
+      for (int i = tid; i < N[s]; i += kPairThreads) {
+        sm.key[s][i] = B.key[s][b[s] + i];
+        sm.slot_in[s][i] = B.slot[s][b[s] + i];
       }
     __syncthreads();
+    // rank inside the cell, gather id and velocity into the ranked position
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      for (int q = hl; q < n[s]; q += 32) {
-        const unsigned long long kq = sm.key[s][q];
-        int rank = 0;
-        for (int t = 0; t < n[s]; ++t) rank += sm.key[s][t] < kq;
-        const int p = sm.slot_in[s][q];
+      for (int i = tid; i < N[s]; i += kPairThreads) {
+        int j = 0;
+        while (j + 1 < kGroup && sm.cs[s][j + 1] - b[s] <= i) ++j;
+        const int lo = sm.cs[s][j] - b[s], hi = sm.cs[s][j + 1] - b[s];
+        const unsigned long long kq = sm.key[s][i];
+        int rank = lo;
+        for (int t = lo; t < hi; ++t) rank += sm.key[s][t] < kq;
+        const int p = sm.slot_in[s][i];
         sm.slot[s][rank] = p;
         sm.id[s][rank] = P[s].id[p];
         load_v(P[s], p, sm.v[s][rank]);
       }
     __syncthreads();
-#define LDS_V(s, q) (sm.v[s][q])
-#define LDS_ID(s, q) (sm.id[s][q])
-    COUL_PAIRS(LDS_V, LDS_ID, hl, 32)
-#undef LDS_V
-#undef LDS_ID
+    const int o0 = sm.cs[0][cl] - b[0], o1 = sm.cs[1][cl] - b[1];
+#define GRP_V(s, q) (sm.v[s][((s) ? o1 : o0) + (q)])
+#define GRP_ID(s, q) (sm.id[s][((s) ? o1 : o0) + (q)])
+    COUL_PAIRS(GRP_V, GRP_ID, hl, 32)
+#undef GRP_V
+#undef GRP_ID
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      for (int q = hl; q < n[s]; q += 32) store_v(P[s], sm.slot[s][q], sm.v[s][q]);
+      for (int i = tid; i < N[s]; i += kPairThreads) store_v(P[s], sm.slot[s][i], sm.v[s][i]);
     __syncthreads();
   }
   if (hl == 0 && pairings) atomicAdd(B.count, pairings);
@@ -488,8 +562,9 @@ void coulomb_impl(const PT P[2], const WorkLists L[2], const CoulombBufs& B, con
       hipLaunchKernelGGL(coul_scatter_kernel<PT>, dim3(g), dim3(256), 0, st, P[s], L[s], C, s,
                          B.start[s], B.fill[s], B.key[s], B.slot[s]);
   }
-  const int grid = (int)std::min<long>((ncell + 1) / 2, 32768);
-  hipLaunchKernelGGL(coul_pair_kernel<PT>, dim3(grid), dim3(64), 0, st, P[0], P[1], B, C);
+  const int grid = (int)std::min<long>((ncell + kGroup - 1) / kGroup, 8192);
+  hipLaunchKernelGGL(coul_pair_kernel<PT>, dim3(grid), dim3(kPairThreads), 0, st, P[0], P[1], B,
+                     C);
 }
 
 }  // namespace
