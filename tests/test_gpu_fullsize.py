@@ -115,8 +115,8 @@ def test_fullsize_fields_and_step(prec):
 
 def test_fullsize_fields_after_sheath_formation():
     """The FP32R fields on a developed state (1,300 steps: sheaths formed, grains
-    charged, the refinement residual near 2e-10 after its two sweeps) against the
-    oracle's fields of that state."""
+    charged; the refinement sweeps until the residual is below its tolerance)
+    against the oracle's fields of that state."""
     from paper_1801_00972_amd.pic import PIC_E, PIC_PHI, PIC_RHO_FIXED, Simulation
     wl = W.full_fp64("fp32r")
     print(f"[case] {wl['name']} after 1300 steps", flush=True)
