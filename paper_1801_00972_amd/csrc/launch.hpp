@@ -35,9 +35,10 @@ void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTab
 void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const MdTables& md,
                       const SpeciesStep& S, const WorkLists& L, hipStream_t st);
 // the push of every (replica, species) of an FP32R ensemble in one persistent launch;
-// start[d] is the first work item (tile) of descriptor d, start[ndesc] the total
+// start[d] is the first work item (tile) of descriptor d, start[ndesc] the total;
+// queue: 8 ints of device scratch, cleared by the launcher (items dealt per XCD)
 void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int ndesc, int grid,
-                            hipStream_t st);
+                            int* queue, hipStream_t st);
 // the collisions of one species' push candidates (right after its push)
 void launch_collide_f64(const PartF64& P, const SpeciesStep& S, const WorkLists& L,
                         hipStream_t st);
@@ -143,7 +144,7 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
                       hipStream_t st);
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
-                          const void* tw_y32, const void* inv32, double* phi, RfDrive rf,
+                          const void* tw_y32, const void* inv, double* phi, RfDrive rf,
                           int sweeps, double tol, double* norms, int* ctl, hipStream_t st);
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
                     hipStream_t st);

@@ -286,14 +286,17 @@ __global__ __launch_bounds__(kPlaneThreads) void fft_plane_kernel(Fft2Geom g, co
 constexpr int kTriChunks = 16;
 constexpr int kTriModes = 16;  // modes per block (16 x 16 = 256 threads)
 
-template <typename T, int kTriMaxLen>  // rows per chunk held in registers
+// d is stored in T; the recurrences run in TC with the factorisation in TC
+// (the FP32 correction solves use TC = double: the lowest modes' tridiagonal
+// systems are the worst conditioned part of the solve)
+template <typename T, typename TC, int kTriMaxLen>  // rows per chunk held in registers
 __global__ __launch_bounds__(256) void thomas_chunked_kernel(cplx<T>* __restrict__ d,
-                                                             const T* __restrict__ inv, int K,
+                                                             const TC* __restrict__ inv, int K,
                                                              long modes,
                                                              const int* __restrict__ skip) {
-  using C = cplx<T>;
+  using C = cplx<TC>;
   if (skip && *skip) return;  // a refinement sweep after convergence
-  __shared__ T s_A[kTriChunks][kTriModes];
+  __shared__ TC s_A[kTriChunks][kTriModes];
   __shared__ C s_B[kTriChunks][kTriModes];
   const int lm = threadIdx.x % kTriModes, c = threadIdx.x / kTriModes;
   const long mn = (long)blockIdx.x * kTriModes + lm;
@@ -302,18 +305,20 @@ __global__ __launch_bounds__(256) void thomas_chunked_kernel(cplx<T>* __restrict
   const int k0 = c * len;
   const int k1 = min(K, k0 + len);
   C v[kTriMaxLen];
-  T f[kTriMaxLen];
+  TC f[kTriMaxLen];
 #pragma unroll
   for (int i = 0; i < kTriMaxLen; ++i) {
     if (on && i < k1 - k0) {
-      v[i] = d[(long)(k0 + i) * modes + mn];
+      const cplx<T> a = d[(long)(k0 + i) * modes + mn];
+      v[i].x = (TC)a.x;
+      v[i].y = (TC)a.y;
       f[i] = inv[(long)(k0 + i) * modes + mn];
     }
   }
   // forward sweep: the chunk's map y_out = A y_in + B
-  T A = (T)1;
+  TC A = (TC)1;
   C B;
-  B.x = B.y = (T)0;
+  B.x = B.y = (TC)0;
 #pragma unroll
   for (int i = 0; i < kTriMaxLen; ++i) {
     if (i < k1 - k0) {
@@ -326,9 +331,9 @@ __global__ __launch_bounds__(256) void thomas_chunked_kernel(cplx<T>* __restrict
   s_B[c][lm] = B;
   __syncthreads();
   C y;
-  y.x = y.y = (T)0;
+  y.x = y.y = (TC)0;
   for (int cc = 0; cc < c; ++cc) {
-    const T a = s_A[cc][lm];
+    const TC a = s_A[cc][lm];
     const C b = s_B[cc][lm];
     y.x = a * y.x + b.x;
     y.y = a * y.y + b.y;
@@ -343,8 +348,8 @@ __global__ __launch_bounds__(256) void thomas_chunked_kernel(cplx<T>* __restrict
   }
   __syncthreads();
   // backward sweep from the chunk's end: x_start = A x_next + B
-  A = (T)1;
-  B.x = B.y = (T)0;
+  A = (TC)1;
+  B.x = B.y = (TC)0;
 #pragma unroll
   for (int i = kTriMaxLen - 1; i >= 0; --i) {
     if (i < k1 - k0) {
@@ -357,9 +362,9 @@ __global__ __launch_bounds__(256) void thomas_chunked_kernel(cplx<T>* __restrict
   s_B[c][lm] = B;
   __syncthreads();
   C x;
-  x.x = x.y = (T)0;
+  x.x = x.y = (TC)0;
   for (int cc = kTriChunks - 1; cc > c; --cc) {
-    const T a = s_A[cc][lm];
+    const TC a = s_A[cc][lm];
     const C b = s_B[cc][lm];
     x.x = a * x.x + b.x;
     x.y = a * x.y + b.y;
@@ -369,33 +374,50 @@ __global__ __launch_bounds__(256) void thomas_chunked_kernel(cplx<T>* __restrict
     if (i < k1 - k0) {
       x.x = v[i].x - f[i] * x.x;
       x.y = v[i].y - f[i] * x.y;
-      if (on) d[(long)(k0 + i) * modes + mn] = x;
+      cplx<T> o;
+      o.x = (T)x.x;
+      o.y = (T)x.y;
+      if (on) d[(long)(k0 + i) * modes + mn] = o;
     }
   }
 }
 
 // ---------------------------------------------------------------- tridiagonal
 // one thread per Fourier mode; inv[k][mode] = 1 / (diag - inv[k-1][mode]) is
-// the factorisation, computed once per run
-template <typename T>
-__global__ void thomas_kernel(cplx<T>* __restrict__ d, const T* __restrict__ inv, int K,
+// the factorisation, computed once per run (for more than 16 x 32 planes; the
+// arithmetic is in TC, the forward sweep's intermediates are stored in T)
+template <typename T, typename TC>
+__global__ void thomas_kernel(cplx<T>* __restrict__ d, const TC* __restrict__ inv, int K,
                               long modes, const int* __restrict__ skip) {
   if (skip && *skip) return;  // a refinement sweep after convergence
   // the loads of a batch of planes are issued together: the recursion only
   // waits on arithmetic, not on one memory round trip per plane
-  using C = cplx<T>;
+  using C = cplx<TC>;
   constexpr int B = 8;
   const long mn = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (mn >= modes) return;
+  auto ld = [&](long i) {
+    const cplx<T> a = d[i];
+    C r;
+    r.x = (TC)a.x;
+    r.y = (TC)a.y;
+    return r;
+  };
+  auto st = [&](long i, const C& v) {
+    cplx<T> o;
+    o.x = (T)v.x;
+    o.y = (T)v.y;
+    d[i] = o;
+  };
   C prev;
-  prev.x = prev.y = (T)0;
+  prev.x = prev.y = (TC)0;
   for (int k0 = 0; k0 < K; k0 += B) {
     C cur[B];
-    T f[B];
+    TC f[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       if (k0 + b < K) {
-        cur[b] = d[(long)(k0 + b) * modes + mn];
+        cur[b] = ld((long)(k0 + b) * modes + mn);
         f[b] = inv[(long)(k0 + b) * modes + mn];
       }
     }
@@ -405,20 +427,20 @@ __global__ void thomas_kernel(cplx<T>* __restrict__ d, const T* __restrict__ inv
         cur[b].x = (cur[b].x - prev.x) * f[b];
         cur[b].y = (cur[b].y - prev.y) * f[b];
         prev = cur[b];
-        d[(long)(k0 + b) * modes + mn] = cur[b];
+        st((long)(k0 + b) * modes + mn, cur[b]);
       }
     }
   }
   // back substitution from the last plane: x_k = d'_k - inv_k x_{k+1}
   C next;
-  next.x = next.y = (T)0;
+  next.x = next.y = (TC)0;
   for (int k1 = K - 1; k1 >= 0; k1 -= B) {
     C cur[B];
-    T f[B];
+    TC f[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       if (k1 - b >= 0) {
-        cur[b] = d[(long)(k1 - b) * modes + mn];
+        cur[b] = ld((long)(k1 - b) * modes + mn);
         f[b] = inv[(long)(k1 - b) * modes + mn];
       }
     }
@@ -428,7 +450,7 @@ __global__ void thomas_kernel(cplx<T>* __restrict__ d, const T* __restrict__ inv
         cur[b].x -= f[b] * next.x;
         cur[b].y -= f[b] * next.y;
         next = cur[b];
-        d[(long)(k1 - b) * modes + mn] = cur[b];
+        st((long)(k1 - b) * modes + mn, cur[b]);
       }
     }
   }
@@ -1012,6 +1034,8 @@ static void fft_plane_launch(const FftPlanHost& P, int nx, int ny, int planes, c
                        dim3(kPlaneThreads), lds, st, g, tx, ty, forward, w, rin, 1.0, rout, out_scale, rf, nz, skip);
 }
 
+// the tridiagonal solves of every mode: work in T, the factorisation inv and
+// the arithmetic in double (both forms)
 template <typename T>
 static void tridiag_launch(void* work, const void* inv, int K, long modes, hipStream_t st,
                            const int* skip = nullptr) {
@@ -1019,14 +1043,14 @@ static void tridiag_launch(void* work, const void* inv, int K, long modes, hipSt
   const int len = (K + kTriChunks - 1) / kTriChunks;
   const int blocks = (int)((modes + kTriModes - 1) / kTriModes);
   if (len <= 16)
-    hipLaunchKernelGGL((thomas_chunked_kernel<T, 16>), dim3(blocks), dim3(256), 0, st, (C*)work,
-                       (const T*)inv, K, modes, skip);
+    hipLaunchKernelGGL((thomas_chunked_kernel<T, double, 16>), dim3(blocks), dim3(256), 0, st,
+                       (C*)work, (const double*)inv, K, modes, skip);
   else if (len <= 32)
-    hipLaunchKernelGGL((thomas_chunked_kernel<T, 32>), dim3(blocks), dim3(256), 0, st, (C*)work,
-                       (const T*)inv, K, modes, skip);
+    hipLaunchKernelGGL((thomas_chunked_kernel<T, double, 32>), dim3(blocks), dim3(256), 0, st,
+                       (C*)work, (const double*)inv, K, modes, skip);
   else
-    hipLaunchKernelGGL(thomas_kernel<T>, dim3(nb256(modes)), dim3(256), 0, st, (C*)work,
-                       (const T*)inv, K, modes, skip);
+    hipLaunchKernelGGL((thomas_kernel<T, double>), dim3(nb256(modes)), dim3(256), 0, st, (C*)work,
+                       (const double*)inv, K, modes, skip);
 }
 
 // one FFT + tridiagonal + inverse FFT solve of A psi = b (T = double or float);
@@ -1069,15 +1093,17 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
 // (zero after loading): r = b - A psi; then up to `sweeps` times
 // { psi += solve32(r); r = b - A psi }, stopping once ||r|| <= tol ||b||;
 // phi = psi + lift.  The charge moves little in one step, so the previous
-// potential is a close guess and each FP32 sweep gains its ~1e-7 on a small
-// correction.  Every sweep is launched (a captured step replays the same
+// potential is a close guess and each sweep gains the FP32 transforms'
+// ~1e-6 on a small correction (the tridiagonal solves inside run in FP64:
+// in FP32 the lowest modes, conditioned like (nz / pi)^2, would limit a sweep
+// to ~1e-3).  Every sweep is launched (a captured step replays the same
 // kernels); the kernels of a sweep after convergence return at once on
 // ctl[0].  norms[0..1] receive ||r||^2, ||b||^2 of the last residual formed;
 // norms[2..] hold 2 partials per residual block: ceil(nx ny / 256) blocks per
 // interior plane; ctl as in norm_reduce_kernel.
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
-                          const void* tw_y32, const void* inv32, double* phi, RfDrive rf,
+                          const void* tw_y32, const void* inv, double* phi, RfDrive rf,
                           int sweeps, double tol, double* norms, int* ctl, hipStream_t st) {
   const long plane = (long)nx * ny;
   const int nb = (int)(nb256(plane) * (nz - 1));
@@ -1086,7 +1112,7 @@ void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const do
   hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb, norms, ctl,
                      tol * tol, 0, 0);
   for (int it = 1; it <= sweeps; ++it) {
-    solve_once<float>(P, nx, ny, nz, r, work32, tw_x32, tw_y32, inv32, OUT_REAL_ACCUM, psi, rf, st,
+    solve_once<float>(P, nx, ny, nz, r, work32, tw_x32, tw_y32, inv, OUT_REAL_ACCUM, psi, rf, st,
                       ctl);
     hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi,
                        b, r, nx, ny, nz - 1, norms + 2, ctl);

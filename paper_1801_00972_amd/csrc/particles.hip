@@ -213,37 +213,51 @@ __device__ int md_move(const ET* __restrict__ E, const MdTables& md, const Grain
       if (u == t) g = gl[u];
     return t < kMdCache ? g : md.grain_idx[(cl >> 8) + t];
   };
-  for (int sub = 0; sub < S.md_sub; ++sub) {
-    int i0 = (int)floor(x[0]), j0 = (int)floor(x[1]), k0 = (int)floor(x[2]);
+  // the field at x: the mesh part from the cell's corrected node fields,
+  // then the grains' Coulomb fields (their mesh parts are in the corrected
+  // nodes): Q r / (4 pi eps0 |r|^3) with r in cells and Q qscale = Q / (4 pi eps0 dx^2)
+  auto mesh_field = [&](double Ep[3]) {
+    const int i0 = (int)floor(x[0]), j0 = (int)floor(x[1]), k0 = (int)floor(x[2]);
     const double fx = x[0] - i0, fy = x[1] - j0, fz = x[2] - k0;
-    int cell = pack_cell(i0, j0, k0);
-    load_cell(cell, i0, j0, k0);
-    double Ep[3] = {0.0, 0.0, 0.0};
-    {
-      const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+    load_cell(pack_cell(i0, j0, k0), i0, j0, k0);
+    const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+    Ep[0] = Ep[1] = Ep[2] = 0.0;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const double wt = wx[c & 1] * wy[(c >> 1) & 1] * wz[c >> 2];
-        Ep[0] += wt * ec[c][0];
-        Ep[1] += wt * ec[c][1];
-        Ep[2] += wt * ec[c][2];
-      }
+    for (int c = 0; c < 8; ++c) {
+      const double wt = wx[c & 1] * wy[(c >> 1) & 1] * wz[c >> 2];
+      Ep[0] += wt * ec[c][0];
+      Ep[1] += wt * ec[c][1];
+      Ep[2] += wt * ec[c][2];
     }
-    // the grains' Coulomb fields (their mesh parts are in the corrected
-    // nodes): Q r / (4 pi eps0 |r|^3) with r in cells and Q qscale = Q / (4 pi eps0 dx^2)
+  };
+  auto grain_field = [&](int g, const double r[3], double Ep[3]) {
+    const double Qc = G.Q[g] * G.qscale;
+    if (Qc == 0.0) return;
+    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double rs = rsqrt_refined(r2);
+    const double inv = Qc * rs * rs * rs;
+    Ep[0] += r[0] * inv;
+    Ep[1] += r[1] * inv;
+    Ep[2] += r[2] * inv;
+  };
+  // position x_s, s = 0 .. md_sub: after a drift (s > 0) the hit test, in list
+  // order (the first grain that holds the particle wins), and, before the
+  // next kick, the field, from one walk over the cell's grains
+  double Ep[3];
+  for (int sub = 0;; ++sub) {
+    mesh_field(Ep);
     for (int t = 0; t < cnt; ++t) {
       const int g = grain_at(t);
-      const double Qc = G.Q[g] * G.qscale;
-      if (Qc == 0.0) continue;
       double r[3];
       grain_sep(G, S, g, x, r);
-      const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-      const double rs = rsqrt_refined(r2);
-      const double inv = Qc * rs * rs * rs;
-      Ep[0] += r[0] * inv;
-      Ep[1] += r[1] * inv;
-      Ep[2] += r[2] * inv;
+      const double d0 = r[0] * S.dx, d1 = r[1] * S.dx, d2 = r[2] * S.dx;
+      if (sub > 0 && d0 * d0 + d1 * d1 + d2 * d2 <= md.a2) {
+        hit = g;
+        return ST_GRAIN;
+      }
+      grain_field(g, r, Ep);
     }
+    if (sub == S.md_sub) break;
     v[0] += S.qm_h * Ep[0];
     v[1] += S.qm_h * Ep[1];
     v[2] += S.qm_h * Ep[2];
@@ -252,23 +266,6 @@ __device__ int md_move(const ET* __restrict__ E, const MdTables& md, const Grain
     x[2] += v[2] * S.h_dx;
     const int zs = z_status(x, S);
     if (zs != ST_ALIVE) return zs;
-    i0 = (int)floor(x[0]);
-    j0 = (int)floor(x[1]);
-    k0 = (int)floor(x[2]);
-    cell = pack_cell(i0, j0, k0);
-    load_cell(cell, i0, j0, k0);
-    for (int t = 0; t < cnt; ++t) {
-      const int g = grain_at(t);
-      double r[3];
-      grain_sep(G, S, g, x, r);
-      r[0] *= S.dx;
-      r[1] *= S.dx;
-      r[2] *= S.dx;
-      if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] <= md.a2) {
-        hit = g;
-        return ST_GRAIN;
-      }
-    }
   }
   return ST_ALIVE;
 }
@@ -1153,21 +1150,26 @@ __global__ __launch_bounds__(kBlock, 4) void push_f32r_kernel(PartF32R P,
 // ---------------------------------------------------------------- push, ensemble
 // One persistent launch over the tile spans of every (replica, species) of an
 // ensemble: work item i belongs to descriptor d with start[d] <= i < start[d+1]
-// (each descriptor has a multiple of 8 items, so the XCD remapping stays a
-// permutation per descriptor); blocks stride over the items (a grid that is
-// a multiple of 8 keeps item i on XCD i % 8).
+// (each descriptor has a multiple of 8 items).  Items are dealt dynamically
+// from eight queues, one per residue of the item index modulo 8: block b takes
+// the next item of queue b % 8 (one atomic per item), so item i still runs on
+// XCD i % 8 as the tile interleave expects, and blocks that drew light tiles
+// take more of them.  A queue's items come in increasing order, so a block
+// finds its descriptor by walking forward.  queue[0..7] are zero at launch.
 __global__ __launch_bounds__(kBlock, 4) void push_batch_f32r_kernel(const PushDescF32* __restrict__ descs,
                                                                  const int32_t* __restrict__ start,
-                                                                 int ndesc) {
+                                                                 int ndesc, int* __restrict__ queue) {
   __shared__ PushSmemF32 sm;
+  __shared__ int s_item;
   const int total = start[ndesc];
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    int lo = 0, hi = ndesc;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (start[mid] <= item) lo = mid;
-      else hi = mid;
-    }
+  const int x = (int)(blockIdx.x & 7u);
+  int lo = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = x + 8 * atomicAdd(&queue[x], 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= total) break;
+    while (lo + 1 < ndesc && start[lo + 1] <= item) ++lo;
     const int local = item - start[lo];
     const PushDescF32& d = descs[lo];
     push_tile_f32r<true>(d.P, d.E, d.rho, d.md, d.S, d.L,
@@ -2582,9 +2584,11 @@ void launch_push_f32r(const PartF32R& P, const float* E, long long* rho, const M
 }
 
 void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int ndesc, int grid,
-                            hipStream_t st) {
+                            int* queue, hipStream_t st) {
   if (ndesc <= 0 || grid <= 0) return;
-  hipLaunchKernelGGL(push_batch_f32r_kernel, dim3(grid), dim3(kBlock), 0, st, descs, start, ndesc);
+  launch_zero_i32(queue, 8, st);
+  hipLaunchKernelGGL(push_batch_f32r_kernel, dim3(grid), dim3(kBlock), 0, st, descs, start, ndesc,
+                     queue);
 }
 
 constexpr int kMdBlocks = kMdTallyRows;

@@ -153,6 +153,7 @@ struct pic_ctx {
   int ndesc = 0;
   PushDescF32* d_desc = nullptr;
   int32_t* d_start = nullptr;
+  int* d_queue = nullptr;  // the persistent push's 8 work queues
   int n_cu = 256;
   // device of the context, and whether the fixed scratch array of
   // pic_fields_static has its address resolved there
@@ -177,6 +178,7 @@ struct pic_ctx {
     for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
     if (d_desc) (void)hipFree(d_desc);
     if (d_start) (void)hipFree(d_start);
+    if (d_queue) (void)hipFree(d_queue);
   }
 };
 
@@ -470,7 +472,8 @@ int setup_md(pic_ctx* ctx, Replica& R) {
   return PIC_OK;
 }
 
-// FFT twiddles and tridiagonal factors of one precision
+// FFT twiddles in T and the tridiagonal factors in double (the tridiagonal
+// solves run in double in both forms)
 template <typename T>
 int setup_solver_tables(pic_ctx* ctx, Replica& R, void** tw_x, void** tw_y, void** inv) {
   auto twiddles = [&](int N, void** out) -> int {
@@ -489,7 +492,7 @@ int setup_solver_tables(pic_ctx* ctx, Replica& R, void** tw_x, void** tw_y, void
   TRY(twiddles(R.nx, tw_x));
   TRY(twiddles(R.ny, tw_y));
   const int K = R.nz - 1;
-  std::vector<T> h((size_t)K * R.nxy);
+  std::vector<double> h((size_t)K * R.nxy);
   for (long mn = 0; mn < R.nxy; ++mn) {
     const int m = (int)(mn % R.nx), n = (int)(mn / R.nx);
     const double sx = std::sin(kPi * m / R.nx), sy = std::sin(kPi * n / R.ny);
@@ -497,13 +500,13 @@ int setup_solver_tables(pic_ctx* ctx, Replica& R, void** tw_x, void** tw_y, void
     double cprev = 0.0;
     for (int k = 0; k < K; ++k) {
       const double f = 1.0 / (diag - cprev);
-      h[(size_t)k * R.nxy + mn] = (T)f;
+      h[(size_t)k * R.nxy + mn] = f;
       cprev = f;
     }
   }
-  T* d;
+  double* d;
   TRY(dalloc(ctx, R, &d, h.size()));
-  HIPCHK(ctx, hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
   *inv = d;
   return PIC_OK;
 }
@@ -913,7 +916,7 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
   hipEvent_t a = prof_event(ctx);
   launch_push_batch_f32r(ctx->d_desc + (size_t)phase_of(R0) * ctx->ndesc, ctx->d_start, ctx->ndesc,
-                         ctx->tune.batch_blocks, st);
+                         ctx->tune.batch_blocks, ctx->d_queue, st);
   CHECK_LAUNCH(ctx);
   hipEvent_t b = prof_event(ctx);
   TRY(for_replicas(ctx, [&](Replica& R) -> int {
@@ -992,6 +995,7 @@ int build_batch(pic_ctx* ctx) {
   if (!ctx->d_desc) {
     HIPCHK(ctx, hipMalloc(&ctx->d_desc, h.size() * sizeof(PushDescF32)));
     HIPCHK(ctx, hipMalloc(&ctx->d_start, start.size() * sizeof(int32_t)));
+    HIPCHK(ctx, hipMalloc(&ctx->d_queue, 8 * sizeof(int)));
   }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   HIPCHK(ctx, hipMemcpy(ctx->d_desc, h.data(), h.size() * sizeof(PushDescF32),

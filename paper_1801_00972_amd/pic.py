@@ -155,7 +155,7 @@ def _check(rc, ctx=None):
         raise PicError(rc, msg.decode() if msg else "error")
 
 
-def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 3):
+def make_config(wl: dict, sort_interval: int = 8, max_refine: int = 2):
     """pic_config from a workload dict; returns (config, keep-alive arrays)."""
     cluster = wl.get("cluster") if wl.get("grain_pos") is None else None
     g = np.ascontiguousarray(np.asarray(np.zeros((0, 3)) if wl.get("grain_pos") is None
@@ -418,7 +418,7 @@ def pic_autotune(ctx, trial_steps=48, capacity=64):
 class Simulation:
     """One context over one or more replicas (workload dicts)."""
 
-    def __init__(self, workloads, stream=None, sort_interval=8, max_refine=3):
+    def __init__(self, workloads, stream=None, sort_interval=8, max_refine=2):
         if isinstance(workloads, dict):
             workloads = [workloads]
         self.wls = list(workloads)
