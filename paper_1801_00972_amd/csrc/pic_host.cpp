@@ -136,6 +136,10 @@ struct pic_ctx {
   int since_sort[2]{};
   // captured steps, by phase (see step_all)
   hipStream_t capture_stream = nullptr;
+  // a second stream for the ions' push and collisions in a one-replica step
+  // (fork and join events around them on the step's stream)
+  hipStream_t species_stream = nullptr;
+  hipEvent_t species_fork = nullptr, species_join = nullptr;
   // replicas stepped one by one are spread over worker streams (default
   // priority), forked from and joined back into the caller's stream
   std::vector<hipStream_t> workers;
@@ -173,6 +177,9 @@ struct pic_ctx {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     drop_graphs();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    if (species_stream) (void)hipStreamDestroy(species_stream);
+    if (species_fork) (void)hipEventDestroy(species_fork);
+    if (species_join) (void)hipEventDestroy(species_join);
     for (hipStream_t w : workers) (void)hipStreamDestroy(w);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
@@ -795,6 +802,31 @@ int enqueue_sample(pic_ctx* ctx, Replica& R) {
 // the next re-binning (each tile padded to a multiple of 4) still fits
 long iz_room(const Replica& R) { return R.cap[0] - 4L * R.ngrid; }
 
+// The two species' push and collision kernels depend on each other only
+// through the atomically summed charge: in a one-replica context (and not
+// while kernels are timed one by one) the ions' go to a second stream,
+// forked after the field solve and joined before the list kernels, so that
+// one species' latency-bound kernels and launch tails overlap the other's
+// streaming.  *forked tells whether the ions' kernels go to ctx->species_stream.
+int species_fork(pic_ctx* ctx, bool* forked) {
+  *forked = ctx->reps.size() == 1 && !ctx->prof;
+  if (!*forked) return PIC_OK;
+  if (!ctx->species_stream) {
+    HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->species_stream, hipStreamNonBlocking));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->species_fork, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->species_join, hipEventDisableTiming));
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->species_fork, ctx->stream));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->species_stream, ctx->species_fork, 0));
+  return PIC_OK;
+}
+int species_join(pic_ctx* ctx, bool forked) {
+  if (!forked) return PIC_OK;
+  HIPCHK(ctx, hipEventRecord(ctx->species_join, ctx->species_stream));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->species_join, 0));
+  return PIC_OK;
+}
+
 // launches one step of a replica on ctx->stream from the host state at the
 // start of the step (buffer phases); advance_host then moves the host mirrors
 int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
@@ -811,17 +843,21 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   const int rnx = 1 - R.rho_cur;
   const int do_mcc = 1;
   const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
+  bool forked = false;
   if (R.prec == PIC_FP64) {
     launch_zero_f64((double*)R.rho[rnx], R.nn, st);
     const PartF64 P[2] = {R.p64[0][R.cur[0]], R.p64[1][R.cur[1]]};
+    TRY(species_fork(ctx, &forked));
     for (int sp = 0; sp < 2; ++sp) {
+      hipStream_t ss = forked && sp == 1 ? ctx->species_stream : st;
       hipEvent_t a = prof_event(ctx);
-      launch_push_f64(P[sp], (const double*)R.E, (double*)R.rho[rnx], R.md, S[sp], R.lists[sp], st);
+      launch_push_f64(P[sp], (const double*)R.E, (double*)R.rho[rnx], R.md, S[sp], R.lists[sp], ss);
       hipEvent_t b = prof_event(ctx);
-      launch_collide_f64(P[sp], S[sp], R.lists[sp], st);
+      launch_collide_f64(P[sp], S[sp], R.lists[sp], ss);
       prof_pair(ctx, PIC_PROF_PUSH, a, b);
       prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
+    TRY(species_join(ctx, forked));
     hipEvent_t b = prof_event(ctx);
     launch_lists_f64(P, (const double*)R.E, (double*)R.rho[rnx], R.md, S, R.d_gc, R.lists, do_mcc,
                      st);
@@ -832,15 +868,18 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   } else {
     launch_zero_i64((long long*)R.rho[rnx], R.nn, st);
     const PartF32R P[2] = {R.p32[0][R.cur[0]], R.p32[1][R.cur[1]]};
+    TRY(species_fork(ctx, &forked));
     for (int sp = 0; sp < 2; ++sp) {
+      hipStream_t ss = forked && sp == 1 ? ctx->species_stream : st;
       hipEvent_t a = prof_event(ctx);
       launch_push_f32r(P[sp], (const float*)R.E, (long long*)R.rho[rnx], R.md, S[sp], R.lists[sp],
-                       st);
+                       ss);
       hipEvent_t b = prof_event(ctx);
-      launch_collide_f32r(P[sp], S[sp], R.lists[sp], st);
+      launch_collide_f32r(P[sp], S[sp], R.lists[sp], ss);
       prof_pair(ctx, PIC_PROF_PUSH, a, b);
       prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
+    TRY(species_join(ctx, forked));
     hipEvent_t b = prof_event(ctx);
     launch_lists_f32r(P, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc, R.lists,
                       do_mcc, st);
