@@ -314,6 +314,56 @@ def fp32r_error(wl, snap, o):
     return err
 
 
+def divergence(wl, steps, warmup):
+    """How far the FP32R form drifts from the FP64 form over `steps` steps: the
+    FP32R state after `warmup` steps is loaded exactly into an FP64 context,
+    both step on, and particles, potential and grain counts are compared."""
+    import numpy as np
+
+    from paper_1801_00972_amd.pic import PIC_PHI, Simulation
+    a = Simulation(dict(wl, precision="fp32r"))
+    a.step(warmup)
+    b = Simulation(dict(wl, precision="fp64"))
+    b.set_state(a.get_state())
+    out = dict(start_step=warmup, steps=steps, checkpoints=[])
+    done = 0
+    for k in sorted({1, 10, 100, steps}):
+        if k > steps:
+            continue
+        a.step(k - done)
+        b.step(k - done)
+        done = k
+        sa, sb = a.get_state(), b.get_state()
+        row = dict(after=k)
+        for s, name in ((0, "electrons"), (1, "ions")):
+            ia, ib = sa[s]["id"], sb[s]["id"]
+            common, ka, kb = np.intersect1d(ia, ib, assume_unique=True, return_indices=True)
+            d = sa[s]["pos"][ka] - sb[s]["pos"][kb]
+            for ax, n in ((0, wl["nx"]), (1, wl["ny"])):
+                d[:, ax] -= n * np.round(d[:, ax] / n)
+            dist = np.sqrt((d * d).sum(axis=1))
+            dv = np.abs(sa[s]["vel"][ka] - sb[s]["vel"][kb]).max(axis=1)
+            vs = np.abs(sb[s]["vel"][kb]).max(axis=1)
+            row[name] = dict(alive_fp32r=int(len(ia)), alive_fp64=int(len(ib)),
+                             only_one_form=int(len(ia) + len(ib) - 2 * len(common)),
+                             pos_cells_median=float(np.median(dist)),
+                             pos_cells_p99=float(np.quantile(dist, 0.99)),
+                             pos_cells_max=float(dist.max()),
+                             vel_rel_median=float(np.median(dv / vs)),
+                             vel_rel_p99=float(np.quantile(dv / vs, 0.99)))
+        fa, fb = a.fields(0, PIC_PHI), b.fields(0, PIC_PHI)
+        row["phi_rel"] = float(np.abs(fa["phi"] - fb["phi"]).max() / np.abs(fb["phi"]).max())
+        ga, gb = a.grain_charges()[0], b.grain_charges()[0]
+        row["grain_net_fp32r"] = (ga[:, 1] - ga[:, 0]).tolist()
+        row["grain_net_fp64"] = (gb[:, 1] - gb[:, 0]).tolist()
+        log(f"[bench] divergence after {k} steps: {row}")
+        out["checkpoints"].append(row)
+    a.close()
+    b.close()
+    del np
+    return out
+
+
 def cpu_baseline(wl, snap=None, steps=12):
     """The oracle, as it stands, timed on the host cores on the benchmark's own
     state (the FP32R state after the timed windows, read back exactly), a
@@ -436,6 +486,9 @@ def main():
                     help="energy-dependent cross sections (synthetic stand-in tables)")
     ap.add_argument("--coulomb", type=int, default=0,
                     help="Coulomb collisions every N steps (0: off, the default workloads)")
+    ap.add_argument("--divergence", type=int, default=0,
+                    help="only measure how far FP32R drifts from FP64 over N steps "
+                         "(from the state after --warmup FP32R steps) and print it as JSON")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -449,6 +502,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.divergence > 0:
+        wl = W.full_fp64("fp32r") if args.workload == "full" else W.small_fp64()
+        print(json.dumps(dict(metric="fp32r_vs_fp64_divergence", workload=wl["name"],
+                              **divergence(wl, args.divergence, args.warmup))), flush=True)
+        return
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     if args.workload == "large":
         forms = ["fp32r"]
