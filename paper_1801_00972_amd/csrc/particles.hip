@@ -611,6 +611,12 @@ __device__ __forceinline__ int push_one_f32(const SpeciesStep& S, const float ec
   ci += d[0];
   cj += d[1];
   ck += d[2];
+  // periodic wrap: one box length covers any move below it (the general
+  // remainder only past that)
+  if (ci < 0) ci += S.nx;
+  else if (ci >= S.nx) ci -= S.nx;
+  if (cj < 0) cj += S.ny;
+  else if (cj >= S.ny) cj -= S.ny;
   if (ci < 0 || ci >= S.nx) ci = ((ci % S.nx) + S.nx) % S.nx;
   if (cj < 0 || cj >= S.ny) cj = ((cj % S.ny) + S.ny) % S.ny;
   return !ok ? ST_BAD : (ck < 0 ? ST_WALL0 : (ck >= S.nz ? ST_WALL1 : ST_ALIVE));
@@ -638,6 +644,7 @@ struct Tile {
   int x0, y0, k0;  // first node (x0, y0 may be negative: periodic)
   int tx, ty, tz;  // nodes per edge
   bool on;
+  bool wraps;      // the window crosses the periodic seam in x or y
 };
 
 // the window of tiles t .. t + span - 1 (consecutive along x): their cells
@@ -647,6 +654,7 @@ __device__ __forceinline__ Tile make_tile(int t, const WorkLists& L, int nx, int
                                           int margin, int cap, int span = 1) {
   Tile w;
   w.on = false;
+  w.wraps = false;
   w.x0 = w.y0 = w.k0 = 0;
   w.tx = w.ty = w.tz = 0;
   // a padding tile of the grid (its slots, if any, hold particles made by
@@ -677,6 +685,7 @@ __device__ __forceinline__ Tile make_tile(int t, const WorkLists& L, int nx, int
       w.ty = ty;
       w.tz = tz;
       w.on = true;
+      w.wraps = x0 < 0 || x0 + tx - 1 >= nx || y0 < 0 || y0 + ty - 1 >= ny;
       return w;
     }
   }
@@ -688,13 +697,18 @@ __device__ __forceinline__ Tile make_tile(int t, const WorkLists& L, int nx, int
 __device__ __forceinline__ int tile_cell(const Tile& t, int i, int j, int k, int nx, int ny) {
   if (!t.on) return -1;
   int lx = i - t.x0;
-  if (lx >= nx) lx -= nx;
-  else if (lx < 0) lx += nx;
   int ly = j - t.y0;
-  if (ly >= ny) ly -= ny;
-  else if (ly < 0) ly += ny;
+  if (t.wraps) {  // (block-uniform)
+    if (lx >= nx) lx -= nx;
+    else if (lx < 0) lx += nx;
+    if (ly >= ny) ly -= ny;
+    else if (ly < 0) ly += ny;
+  }
   const int lz = k - t.k0;
-  if (lx > t.tx - 2 || ly > t.ty - 2 || lz < 0 || lz > t.tz - 2) return -1;
+  // (unsigned: a negative index, possible without the wrap, is out too)
+  if ((unsigned)lx > (unsigned)(t.tx - 2) || (unsigned)ly > (unsigned)(t.ty - 2) ||
+      (unsigned)lz > (unsigned)(t.tz - 2))
+    return -1;
   return (lz * t.ty + ly) * t.tx + lx;
 }
 
