@@ -952,6 +952,14 @@ template <typename V, typename T>
 __device__ __forceinline__ void nt_store4(T* p, long g4, V v) {
   __builtin_nontemporal_store(v, reinterpret_cast<V*>(p) + g4);
 }
+// the kPPT consecutive values of one field at group g (FP32R push records)
+typedef int viP __attribute__((ext_vector_type(kPPT)));
+typedef float vfP __attribute__((ext_vector_type(kPPT)));
+typedef unsigned vuP __attribute__((ext_vector_type(kPPT)));
+template <typename V, typename T>
+__device__ __forceinline__ V nt_loadP(const T* p, long g) {
+  return __builtin_nontemporal_load(reinterpret_cast<const V*>(p) + g);
+}
 
 // LDS of one push block (FP32R)
 struct PushSmemF32 {
@@ -996,28 +1004,40 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
   unsigned long long packed = 0ull;
   int n_w0 = 0, n_w1 = 0, n_bad = 0, n_md = 0, n_out = 0, n_fast = 0;
   for (int base = beg, pass = 0; base < end; base += kChunk, ++pass) {
-    // tile ranges are multiples of 4 slots: a thread's four slots are all in
+    // tile ranges are multiples of 4 slots: a thread's kPPT slots are all in
     // the tile or all beyond it
     const int p0 = base + kPPT * (int)threadIdx.x;
     const bool have = p0 < end;
     const long g4 = p0 / kPPT;
-    int4 c4 = make_int4(-1, -1, -1, -1);
-    float4 X4{}, Y4{}, Z4{}, U4{}, V4{}, W4{};
-    uint4 I4{};
-    if (have) {
-      c4 = nt_load4<int4, vi4>(P.cell, g4);
-      X4 = nt_load4<float4, vf4>(P.ox, g4);
-      Y4 = nt_load4<float4, vf4>(P.oy, g4);
-      Z4 = nt_load4<float4, vf4>(P.oz, g4);
-      U4 = nt_load4<float4, vf4>(P.vx, g4);
-      V4 = nt_load4<float4, vf4>(P.vy, g4);
-      W4 = nt_load4<float4, vf4>(P.vz, g4);
-      I4 = nt_load4<uint4, vu4>(P.id, g4);
+    int cell[kPPT];
+    float o[kPPT][3], v[kPPT][3];
+    uint32_t id[kPPT];
+    {
+      viP c4 = -1;
+      vfP X4 = 0.0f, Y4 = 0.0f, Z4 = 0.0f, U4 = 0.0f, V4 = 0.0f, W4 = 0.0f;
+      vuP I4 = 0u;
+      if (have) {
+        c4 = nt_loadP<viP>(P.cell, g4);
+        X4 = nt_loadP<vfP>(P.ox, g4);
+        Y4 = nt_loadP<vfP>(P.oy, g4);
+        Z4 = nt_loadP<vfP>(P.oz, g4);
+        U4 = nt_loadP<vfP>(P.vx, g4);
+        V4 = nt_loadP<vfP>(P.vy, g4);
+        W4 = nt_loadP<vfP>(P.vz, g4);
+        I4 = nt_loadP<vuP>(P.id, g4);
+      }
+#pragma unroll
+      for (int q = 0; q < kPPT; ++q) {
+        cell[q] = c4[q];
+        o[q][0] = X4[q];
+        o[q][1] = Y4[q];
+        o[q][2] = Z4[q];
+        v[q][0] = U4[q];
+        v[q][1] = V4[q];
+        v[q][2] = W4[q];
+        id[q] = I4[q];
+      }
     }
-    int cell[kPPT] = {c4.x, c4.y, c4.z, c4.w};
-    float o[kPPT][3] = {{X4.x, Y4.x, Z4.x}, {X4.y, Y4.y, Z4.y}, {X4.z, Y4.z, Z4.z}, {X4.w, Y4.w, Z4.w}};
-    float v[kPPT][3] = {{U4.x, V4.x, W4.x}, {U4.y, V4.y, W4.y}, {U4.z, V4.z, W4.z}, {U4.w, V4.w, W4.w}};
-    const uint32_t id[kPPT] = {I4.x, I4.y, I4.z, I4.w};
     int st[kPPT];
     bool cand[kPPT];
     int cached = -1;
@@ -1081,13 +1101,25 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
         packed = 0ull;
       }
       if (have) {
-        nt_store4<vi4>(P.cell, g4, vi4{cell[0], cell[1], cell[2], cell[3]});
-        nt_store4<vf4>(P.ox, g4, vf4{o[0][0], o[1][0], o[2][0], o[3][0]});
-        nt_store4<vf4>(P.oy, g4, vf4{o[0][1], o[1][1], o[2][1], o[3][1]});
-        nt_store4<vf4>(P.oz, g4, vf4{o[0][2], o[1][2], o[2][2], o[3][2]});
-        nt_store4<vf4>(P.vx, g4, vf4{v[0][0], v[1][0], v[2][0], v[3][0]});
-        nt_store4<vf4>(P.vy, g4, vf4{v[0][1], v[1][1], v[2][1], v[3][1]});
-        nt_store4<vf4>(P.vz, g4, vf4{v[0][2], v[1][2], v[2][2], v[3][2]});
+        viP c;
+        vfP a0, a1, a2, b0, b1, b2;
+#pragma unroll
+        for (int q = 0; q < kPPT; ++q) {
+          c[q] = cell[q];
+          a0[q] = o[q][0];
+          a1[q] = o[q][1];
+          a2[q] = o[q][2];
+          b0[q] = v[q][0];
+          b1[q] = v[q][1];
+          b2[q] = v[q][2];
+        }
+        nt_store4<viP>(P.cell, g4, c);
+        nt_store4<vfP>(P.ox, g4, a0);
+        nt_store4<vfP>(P.oy, g4, a1);
+        nt_store4<vfP>(P.oz, g4, a2);
+        nt_store4<vfP>(P.vx, g4, b0);
+        nt_store4<vfP>(P.vy, g4, b1);
+        nt_store4<vfP>(P.vz, g4, b2);
       }
     }
 
@@ -1240,7 +1272,7 @@ __global__ __launch_bounds__(kBlock, 3) void push_f64_kernel(PartF64 P, const do
     const bool have = p0 < end;  // four slots in the tile, or none
     const long g4 = p0 / kPPT;
     double x[kPPT][3], v[kPPT][3];
-    uint32_t id[kPPT] = {0u, 0u, 0u, 0u};
+    uint32_t id[kPPT] = {};
 #pragma unroll
     for (int q = 0; q < kPPT; ++q) {
       x[q][0] = x[q][1] = v[q][0] = v[q][1] = v[q][2] = 0.0;
