@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 METRIC = "particle-steps/s + % HBM roofline, FP32-refined/batched vs FP64 at stated err"
 HBM_PEAK_GBS = 8000.0
 RECORD_BYTES = {"fp32r": 32, "fp64": 52}      # per particle: read once, written once
+RECORD_WRITTEN = {"fp32r": 28, "fp64": 48}    # of which the push writes back (not the id)
 NODE_BYTES = {"fp32r": 16 + 8, "fp64": 32 + 8}  # per node and step: E read, rho written
 # one Coulomb-collision pass, per alive particle: cell read to count and to
 # scatter, id read, order key and slot written, then read, id read, velocity
@@ -171,6 +172,7 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None, ave
     nn = sum(w["nx"] * w["ny"] * (w["nz"] + 1) for w in wls)
     alg_bytes = particle_steps * 2 * RECORD_BYTES[prec] + steps * nn * NODE_BYTES[prec]
     achieved = alg_bytes / (push_ms * 1e-3) / 1e9 if push_ms > 0 else 0.0
+    moved = alg_bytes - particle_steps * (RECORD_BYTES[prec] - RECORD_WRITTEN[prec])
     kernel = "push_batch_f32r" if tuning.get("batch_push") else "push_" + prec
     tpps = traffic_per_particle_step(kernel, wls[0]["name"] if len(wls) == 1 else "ensemble")
     traffic = tpps * particle_steps / max(push_n, 1) if tpps else None
@@ -192,7 +194,11 @@ def run_form(wls, steps, warmup, sort_interval=8, autotune=True, label=None, ave
                       frac=round(achieved / HBM_PEAK_GBS, 4),
                       traffic=round(traffic) if traffic else None,
                       traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, calibrated)",
-                      kernel=kernel, bytes_per_launch=alg_bytes / max(push_n, 1)),
+                      kernel=kernel, bytes_per_launch=alg_bytes / max(push_n, 1),
+                      frac_of_bytes_written=round(moved / (push_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                      if push_ms > 0 else 0.0,
+                      note="frac_of_bytes_written: the same time against the bytes the "
+                           "kernel must move (the id is read, never written back)"),
         refine_residual=sim.counters(0)["refine_residual"] if prec == "fp32r" else None,
         tile_fallback_blocks=fall1 - fall0,
         md_particle_steps=md1 - md0,
