@@ -10,10 +10,11 @@
 //     key is the particle's Philox word (id, k, order purpose, species) above
 //     its id, so the order inside a cell does not depend on the scatter's
 //     atomics;
-//  3. a block of 256 threads strides over groups of 8 consecutive cells (a
-//     contiguous range of the key / slot arrays): it stages the group's keys
-//     and slots in LDS in one sweep, ranks each particle inside its cell by
-//     key and gathers ids and velocities in that order, then 32 lanes per
+//  3. a block of 256 threads takes 16 groups of 8 consecutive cells in turn
+//     (each a contiguous range of the key / slot arrays): it stages a group's
+//     keys in LDS (the next group's keys and slots already load meanwhile),
+//     ranks each particle inside its cell by key and puts the id (the key's
+//     low word) and the velocity in that order, then 32 lanes per
 //     cell run the like items (e-e and Ar+-Ar+ pairs, an odd count's triplet
 //     as one item), a barrier, and the unlike pairs (one lane per particle of
 //     the less numerous species, its partners in order), and the velocities
@@ -362,14 +363,15 @@ constexpr int kCellCap = 64;
 constexpr int kPairThreads = 256;  // threads of a pair block: 32 lanes per cell of a group
 constexpr int kGroup = kPairThreads / 32;  // consecutive cells staged together
 constexpr int kGroupCap = 512;     // staged particles of a species per group
+constexpr int kStagePer = kGroupCap / kPairThreads;  // staged particles per thread and species
+constexpr int kRunGroups = 16;     // groups of one block: two tiles of 64 cells
 template <typename R>
 struct GroupStage {
   unsigned long long key[2][kGroupCap];
-  int slot_in[2][kGroupCap];
   int slot[2][kGroupCap];  // in key order inside each cell
   uint32_t id[2][kGroupCap];
   R v[2][kGroupCap][3];
-  int cs[2][kGroup + 1];   // the cells' starts in the key / slot arrays
+  int start[2][kRunGroups * kGroup + 1];  // the block's cells' starts in the key / slot arrays
 };
 
 // cells above the LDS capacity: the rule through global memory, the slots
@@ -453,83 +455,134 @@ __device__ void cell_global(const PT P[2], const CoulombBufs& B, const CoulombCo
   __syncthreads();
 }
 
-// A block takes groups of kGroup consecutive cells in turn.  Their key / slot
-// ranges are contiguous, so the block stages a group's keys and slots in one
-// coalesced sweep, ranks each particle inside its cell by key, gathers ids and
-// velocities in that order, runs the pairing rule with 32 lanes per cell and
-// writes the velocities back.  A group with a cell above kCellCap particles of
-// a species, or with more than kGroupCap of a species, runs its cells one by
-// one through global memory with the whole block.
+// A block takes a run of kRunGroups groups of kGroup consecutive cells (two
+// tiles: their key / slot ranges are contiguous, and a tile's particle records
+// are gathered and written by one block, through one XCD's L2).  The run's
+// cell starts are staged once.  For each group the block stages the keys in
+// LDS (a key's low word is the particle's id), ranks each particle inside its
+// cell by key, puts slot, id and velocity at the ranked place, runs the pairing
+// rule with 32 lanes per cell and writes the velocities back.  The next
+// group's keys and slots are loaded into registers while the current group is
+// worked on, and the FP32 velocities are gathered before the ranking, so the
+// loads overlap the arithmetic instead of waiting in turn.  A group with a
+// cell above kCellCap particles of a species, or with more than kGroupCap of a
+// species, runs its cells one by one through global memory with the whole
+// block.
 template <typename PT>
 __global__ __launch_bounds__(kPairThreads) void coul_pair_kernel(PT Pe, PT Pi, CoulombBufs B,
                                                                  CoulombConst C) {
   using R = typename CoulReal<PT>::T;
+  // FP32 velocities are gathered in registers before the ranking; the FP64
+  // ones after it, straight into LDS (their registers would cost occupancy)
+  constexpr bool kEarlyV = std::is_same<R, float>::value;
   __shared__ GroupStage<R> sm;
   const int tid = threadIdx.x, cl = tid >> 5, hl = tid & 31;
   const PT P[2] = {Pe, Pi};
   const uint32_t k = *C.step;
   unsigned long long pairings = 0;  // this half-wave's cells, added to the counter once
-  // each block takes a contiguous run of whole tiles (64 cells, 8 groups):
-  // a tile's particle records are then gathered and written by one block,
-  // through one XCD's L2
   const int ngroup = (C.ncell + kGroup - 1) / kGroup;
-  constexpr int kTileGroups = 64 / kGroup;
-  const int per = ((ngroup + (int)gridDim.x - 1) / (int)gridDim.x + kTileGroups - 1) /
-                  kTileGroups * kTileGroups;
-  const int g_end = min(ngroup, ((int)blockIdx.x + 1) * per);
-  for (int g = (int)blockIdx.x * per; g < g_end; ++g) {
-    const int c0 = g * kGroup;
-    if (tid < 2 * (kGroup + 1)) {
-      const int s = tid / (kGroup + 1), j = tid % (kGroup + 1);
-      sm.cs[s][j] = B.start[s][min(c0 + j, C.ncell)];
+  const int g_beg = (int)blockIdx.x * kRunGroups;
+  const int g_end = min(ngroup, g_beg + kRunGroups);
+  if (g_beg >= g_end) return;
+  const int c_beg = g_beg * kGroup;
+  const int nst = min(C.ncell, g_end * kGroup) - c_beg + 1;  // starts staged per species
+  for (int i = tid; i < 2 * nst; i += kPairThreads) {
+    const int s = i >= nst ? 1 : 0, j = i - s * nst;
+    sm.start[s][j] = B.start[s][c_beg + j];
+  }
+  __syncthreads();
+  // start of cell j of the run (cells past the box are empty)
+  auto st_at = [&](int s, int j) { return sm.start[s][min(j, nst - 1)]; };
+  unsigned long long pk[2][kStagePer];
+  int ps[2][kStagePer];
+  auto prefetch = [&](int g) {
+    const int j0 = (g - g_beg) * kGroup;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int b = st_at(s, j0), N = min(st_at(s, j0 + kGroup) - b, kGroupCap);
+#pragma unroll
+      for (int u = 0; u < kStagePer; ++u) {
+        const int i = tid + u * kPairThreads;
+        if (i < N) {
+          pk[s][u] = B.key[s][b + i];
+          ps[s][u] = B.slot[s][b + i];
+        }
+      }
     }
-    __syncthreads();
-    const int b[2] = {sm.cs[0][0], sm.cs[1][0]};
-    const int N[2] = {sm.cs[0][kGroup] - b[0], sm.cs[1][kGroup] - b[1]};
+  };
+  prefetch(g_beg);
+  for (int g = g_beg; g < g_end; ++g) {
+    const int c0 = g * kGroup, j0 = (g - g_beg) * kGroup;
+    int b[2], N[2], n[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      b[s] = st_at(s, j0);
+      N[s] = st_at(s, j0 + kGroup) - b[s];
+      n[s] = st_at(s, j0 + cl + 1) - st_at(s, j0 + cl);
+    }
     bool fits = N[0] <= kGroupCap && N[1] <= kGroupCap;
 #pragma unroll
     for (int j = 0; j < kGroup; ++j)
-      fits = fits && sm.cs[0][j + 1] - sm.cs[0][j] <= kCellCap &&
-             sm.cs[1][j + 1] - sm.cs[1][j] <= kCellCap;
-    int n[2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) n[s] = sm.cs[s][cl + 1] - sm.cs[s][cl];
+      fits = fits && st_at(0, j0 + j + 1) - st_at(0, j0 + j) <= kCellCap &&
+             st_at(1, j0 + j + 1) - st_at(1, j0 + j) <= kCellCap;
     if (hl == 0) {
 #pragma unroll
       for (int s = 0; s < 2; ++s)
         if (n[s] >= 2) pairings += (n[s] & 1) ? 3 + (n[s] - 3) / 2 : n[s] / 2;
       if (n[0] > 0 && n[1] > 0) pairings += n[0] > n[1] ? n[0] : n[1];
     }
+    // this group's keys and slots; the next group's start loading
+    unsigned long long kk[2][kStagePer];
+    int sl[2][kStagePer];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int u = 0; u < kStagePer; ++u) {
+        kk[s][u] = pk[s][u];
+        sl[s][u] = ps[s][u];
+      }
+    if (g + 1 < g_end) prefetch(g + 1);
     if (!fits) {  // (block-uniform)
       for (int j = 0; j < kGroup && c0 + j < C.ncell; ++j) cell_global(P, B, C, k, c0 + j, tid);
       __syncthreads();
       continue;
     }
-    // stage the group's keys and slots
+    R vv[2][kStagePer][3];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      for (int i = tid; i < N[s]; i += kPairThreads) {
-        sm.key[s][i] = B.key[s][b[s] + i];
-        sm.slot_in[s][i] = B.slot[s][b[s] + i];
+#pragma unroll
+      for (int u = 0; u < kStagePer; ++u) {
+        const int i = tid + u * kPairThreads;
+        if (i < N[s]) {
+          sm.key[s][i] = kk[s][u];
+          if (kEarlyV) load_v(P[s], sl[s][u], vv[s][u]);
+        }
       }
     __syncthreads();
-    // rank inside the cell, gather id and velocity into the ranked position
+    // rank inside the cell; slot, id and velocity to the ranked place
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      for (int i = tid; i < N[s]; i += kPairThreads) {
+#pragma unroll
+      for (int u = 0; u < kStagePer; ++u) {
+        const int i = tid + u * kPairThreads;
+        if (i >= N[s]) continue;
         int j = 0;
-        while (j + 1 < kGroup && sm.cs[s][j + 1] - b[s] <= i) ++j;
-        const int lo = sm.cs[s][j] - b[s], hi = sm.cs[s][j + 1] - b[s];
-        const unsigned long long kq = sm.key[s][i];
+        while (j + 1 < kGroup && st_at(s, j0 + j + 1) - b[s] <= i) ++j;
+        const int lo = st_at(s, j0 + j) - b[s], hi = st_at(s, j0 + j + 1) - b[s];
+        const unsigned long long kq = kk[s][u];
         int rank = lo;
         for (int t = lo; t < hi; ++t) rank += sm.key[s][t] < kq;
-        const int p = sm.slot_in[s][i];
-        sm.slot[s][rank] = p;
-        sm.id[s][rank] = P[s].id[p];
-        load_v(P[s], p, sm.v[s][rank]);
+        sm.slot[s][rank] = sl[s][u];
+        sm.id[s][rank] = (uint32_t)kq;
+        if (kEarlyV) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) sm.v[s][rank][a] = vv[s][u][a];
+        } else {
+          load_v(P[s], sl[s][u], sm.v[s][rank]);
+        }
       }
     __syncthreads();
-    const int o0 = sm.cs[0][cl] - b[0], o1 = sm.cs[1][cl] - b[1];
+    const int o0 = st_at(0, j0 + cl) - b[0], o1 = st_at(1, j0 + cl) - b[1];
 #define GRP_V(s, q) (sm.v[s][((s) ? o1 : o0) + (q)])
 #define GRP_ID(s, q) (sm.id[s][((s) ? o1 : o0) + (q)])
     COUL_PAIRS(GRP_V, GRP_ID, hl, 32)
@@ -562,7 +615,8 @@ void coulomb_impl(const PT P[2], const WorkLists L[2], const CoulombBufs& B, con
       hipLaunchKernelGGL(coul_scatter_kernel<PT>, dim3(g), dim3(256), 0, st, P[s], L[s], C, s,
                          B.start[s], B.fill[s], B.key[s], B.slot[s]);
   }
-  const int grid = (int)std::min<long>((ncell + kGroup - 1) / kGroup, 8192);
+  const long ngroup = (ncell + kGroup - 1) / kGroup;
+  const int grid = (int)((ngroup + kRunGroups - 1) / kRunGroups);
   hipLaunchKernelGGL(coul_pair_kernel<PT>, dim3(grid), dim3(kPairThreads), 0, st, P[0], P[1], B,
                      C);
 }
