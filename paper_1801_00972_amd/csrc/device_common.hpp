@@ -95,6 +95,46 @@ __device__ __forceinline__ int phase_bin(uint32_t k, double f_rf, double dt, int
   return b < 0 ? 0 : (b >= nbins ? nbins - 1 : b);
 }
 
+// phi at node (pn, k) (pn the node's index in its plane): stored (kLift
+// false), or lifted from the interior potential psi of the refined solve:
+// 0 and V on the electrodes, psi + V k / nz inside
+template <bool kLift>
+__device__ __forceinline__ double phi_node(const double* __restrict__ src, long plane, long pn,
+                                           int k, int nz, double V) {
+  if (!kLift) return src[(long)k * plane + pn];
+  if (k == 0) return 0.0;
+  if (k == nz) return V;
+  return src[(long)(k - 1) * plane + pn] + V * (double)k / (double)nz;
+}
+
+// E = -grad phi at node (x, y, k): central differences, periodic in x, y;
+// one-sided along z on the electrode planes
+template <bool kLift>
+__device__ __forceinline__ void node_field(const double* __restrict__ src, int nx, int ny, int nz,
+                                           double dx, double V, int x, int y, int k, double& ex,
+                                           double& ey, double& ez) {
+  const long plane = (long)nx * ny, row = (long)y * nx, pn = row + x;
+  const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+  const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+  ex = -(phi_node<kLift>(src, plane, row + xp, k, nz, V) -
+         phi_node<kLift>(src, plane, row + xm, k, nz, V)) /
+       (2.0 * dx);
+  ey = -(phi_node<kLift>(src, plane, (long)yp * nx + x, k, nz, V) -
+         phi_node<kLift>(src, plane, (long)ym * nx + x, k, nz, V)) /
+       (2.0 * dx);
+  if (k == 0)
+    ez = -(phi_node<kLift>(src, plane, pn, 1, nz, V) - phi_node<kLift>(src, plane, pn, 0, nz, V)) /
+         dx;
+  else if (k == nz)
+    ez = -(phi_node<kLift>(src, plane, pn, nz, nz, V) -
+           phi_node<kLift>(src, plane, pn, nz - 1, nz, V)) /
+         dx;
+  else
+    ez = -(phi_node<kLift>(src, plane, pn, k + 1, nz, V) -
+           phi_node<kLift>(src, plane, pn, k - 1, nz, V)) /
+         (2.0 * dx);
+}
+
 // wrap an index that is at most one period outside [0, n)
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 

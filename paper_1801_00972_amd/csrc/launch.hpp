@@ -54,7 +54,14 @@ void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, cons
                        const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
                        int do_mcc, hipStream_t st);
 // the corrected node fields of the MD cells (after E_k and the grain charges)
-void launch_md_field(const void* E, int e_f64, const MdTables& md, int nx, int ny, hipStream_t st);
+// The fields of a step in one launch: phi (from the refined solve's psi,
+// lifted with the electrode voltages, when psi is given; otherwise phi is read
+// as stored), E = -grad phi into E (FP64 double2 pairs or FP32 float4), the
+// MD cells' corrected node fields, and zero_next (nn 8-byte words, may be
+// null) cleared for the next deposit.
+void launch_field_out(const double* psi, double* phi, void* E, int e_f64,
+                      unsigned long long* zero_next, const MdTables& md, int nx, int ny, int nz,
+                      double dx, RfDrive rf, hipStream_t st);
 void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
                      uint32_t k1, double vth, hipStream_t st);
 void launch_init_f32r(const PartF32R& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,
@@ -136,7 +143,9 @@ int energy_blocks();
 void launch_energy(const PartF64* P64, const PartF32R* P32, const WorkLists& L, double* out,
                    hipStream_t st);
 void launch_field_energy(const void* E, int e_f64, long nxy, int nz, double* out, hipStream_t st);
-void launch_advance_step(uint32_t* step, hipStream_t st);
+// the step counter advances and the dense MD lists of both species start
+// empty for the next step
+void launch_advance_step(uint32_t* step, int32_t* cnt0, int32_t* cnt1, hipStream_t st);
 
 // mesh
 void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double* b, void* work,
@@ -144,8 +153,8 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
                       hipStream_t st);
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
-                          const void* tw_y32, const void* inv, double* phi, RfDrive rf,
-                          int sweeps, double tol, double* norms, int* ctl, hipStream_t st);
+                          const void* tw_y32, const void* inv, RfDrive rf, int sweeps,
+                          double tol, double* norms, int* ctl, hipStream_t st);
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
                     hipStream_t st);
 void launch_rhs_fixed(const long long* rho, double scale, double* b, int nx, int ny, int nz,
@@ -166,8 +175,6 @@ void launch_fine_phi(const double* phi, const MdTables& md, const double* Uphi, 
                      int nx, int ny, int nz, double dx, double radius, double* out,
                      const AvgBins& avg, hipStream_t st);
 void launch_efield_f64(const double* phi, double* E, int nx, int ny, int nz, double dx,
-                       hipStream_t st);
-void launch_efield_f32(const double* phi, float* E, int nx, int ny, int nz, double dx,
                        hipStream_t st);
 void launch_e_out(const double* E64, const float* E32, double* out, long nn, hipStream_t st);
 void launch_rho_total(const double* acc64, const long long* accfx, double* tot64, long long* totfx,

@@ -710,19 +710,6 @@ __global__ __launch_bounds__(1024) void norm_reduce_kernel(const double* __restr
   }
 }
 
-// phi = psi + V k / nz on the interior, 0 and V on the electrodes
-__global__ void lift_kernel(const double* __restrict__ psi, double* __restrict__ phi, int nx,
-                            int ny, int nz, RfDrive rf) {
-  const double V = rf_voltage(rf);
-  const long plane = (long)nx * ny;
-  const int pn = (int)(blockIdx.x * blockDim.x + threadIdx.x), k = (int)blockIdx.y;
-  if (pn >= plane) return;
-  const long n = (long)k * plane + pn;
-  if (k == 0) phi[n] = 0.0;
-  else if (k == nz) phi[n] = V;
-  else phi[n] = psi[n - plane] + V * (double)k / (double)nz;
-}
-
 __global__ void walls_kernel(double* __restrict__ phi, long plane, int nz, RfDrive rf) {
   const double V = rf_voltage(rf);
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -732,9 +719,9 @@ __global__ void walls_kernel(double* __restrict__ phi, long plane, int nz, RfDri
 }
 
 // ---------------------------------------------------------------- field
-// E = -grad phi: central differences, periodic in x,y; one-sided along z on
-// the electrode planes.  Stored interleaved per node: FP64 as two double pairs
-// (Ex,Ey),(Ez,0); FP32 as one float4 (Ex,Ey,Ez,0).
+// E = -grad phi from a stored phi (field readouts; the step's fields come
+// from field_out_kernel).  Stored interleaved per node: FP64 as two double
+// pairs (Ex,Ey),(Ez,0); FP32 as one float4 (Ex,Ey,Ez,0).
 template <typename OutT>
 __global__ void efield_kernel(const double* __restrict__ phi, OutT* __restrict__ E, int nx, int ny,
                               int nz, double dx) {
@@ -744,16 +731,8 @@ __global__ void efield_kernel(const double* __restrict__ phi, OutT* __restrict__
   if (pn >= plane) return;
   const long n = (long)k * plane + pn;
   const int y = pn / nx, x = pn - y * nx;
-  const long row = n - x, pl = n - (long)y * nx - x;
-  const double ex = -(phi[row + (x + 1 == nx ? 0 : x + 1)] - phi[row + (x == 0 ? nx - 1 : x - 1)]) /
-                    (2.0 * dx);
-  const double ey = -(phi[pl + (long)(y + 1 == ny ? 0 : y + 1) * nx + x] -
-                      phi[pl + (long)(y == 0 ? ny - 1 : y - 1) * nx + x]) /
-                    (2.0 * dx);
-  double ez;
-  if (k == 0) ez = -(phi[n + plane] - phi[n]) / dx;
-  else if (k == nz) ez = -(phi[n] - phi[n - plane]) / dx;
-  else ez = -(phi[n + plane] - phi[n - plane]) / (2.0 * dx);
+  double ex, ey, ez;
+  node_field<false>(phi, nx, ny, nz, dx, 0.0, x, y, k, ex, ey, ez);
   if constexpr (std::is_same<OutT, double2>::value) {
     E[2 * n] = make_double2(ex, ey);
     E[2 * n + 1] = make_double2(ez, 0.0);
@@ -1091,8 +1070,8 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
 
 // FP32 solves refined in FP64, starting from the psi the previous solve left
 // (zero after loading): r = b - A psi; then up to `sweeps` times
-// { psi += solve32(r); r = b - A psi }, stopping once ||r|| <= tol ||b||;
-// phi = psi + lift.  The charge moves little in one step, so the previous
+// { psi += solve32(r); r = b - A psi }, stopping once ||r|| <= tol ||b||
+// (phi = psi + lift is formed with the field, field_out_kernel).  The charge moves little in one step, so the previous
 // potential is a close guess and each sweep gains the FP32 transforms'
 // ~1e-6 on a small correction (the tridiagonal solves inside run in FP64:
 // in FP32 the lowest modes, conditioned like (nz / pi)^2, would limit a sweep
@@ -1103,8 +1082,8 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
 // interior plane; ctl as in norm_reduce_kernel.
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
-                          const void* tw_y32, const void* inv, double* phi, RfDrive rf,
-                          int sweeps, double tol, double* norms, int* ctl, hipStream_t st) {
+                          const void* tw_y32, const void* inv, RfDrive rf, int sweeps,
+                          double tol, double* norms, int* ctl, hipStream_t st) {
   const long plane = (long)nx * ny;
   const int nb = (int)(nb256(plane) * (nz - 1));
   hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi, b,
@@ -1119,8 +1098,6 @@ void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const do
     hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb, norms, ctl,
                        tol * tol, it, it == sweeps ? 1 : 0);
   }
-  hipLaunchKernelGGL(lift_kernel, dim3(nb256(plane), nz + 1), dim3(256), 0, st, psi, phi, nx, ny, nz,
-                     rf);
 }
 
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
@@ -1164,11 +1141,6 @@ void launch_efield_f64(const double* phi, double* E, int nx, int ny, int nz, dou
                        hipStream_t st) {
   hipLaunchKernelGGL(efield_kernel<double2>, dim3(nb256((long)nx * ny), nz + 1), dim3(256), 0, st,
                      phi, (double2*)E, nx, ny, nz, dx);
-}
-void launch_efield_f32(const double* phi, float* E, int nx, int ny, int nz, double dx,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(efield_kernel<float4>, dim3(nb256((long)nx * ny), nz + 1), dim3(256), 0, st,
-                     phi, (float4*)E, nx, ny, nz, dx);
 }
 
 void launch_e_out(const double* E64, const float* E32, double* out, long nn, hipStream_t st) {

@@ -270,27 +270,12 @@ __device__ int md_move(const ET* __restrict__ E, const MdTables& md, const Grain
   return ST_ALIVE;
 }
 
-// The corrected node fields of Eq. (5) for every cell of the MD box that lies
-// in a cube, once per step after E_k and the grain charges: for corner t of
-// the cell, E_k(node) - sum_g Q_g U_g(node) over the cell's grains, in list
-// order.  One thread per (cell, corner).
-template <typename ET>
-__global__ void md_field_kernel(const ET* __restrict__ E, MdTables md, int nx, int ny, int nxy) {
-  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long nbox = (long)md.bsx * md.bsy * md.bsz;
-  if (gid >= 8 * nbox) return;
-  const long bi = gid >> 3;
-  const int t = (int)(gid & 7);
-  const uint32_t cl = md.cell_list[bi];
+// The corrected node field of Eq. (5) at corner (ta, tb, tc) of MD box cell
+// bi, whose lowest node is (i0, j0, k0): E_k(node) - sum_g Q_g U_g(node) over
+// the cell's grains (cl: its list entry), in list order; E holds E_k(node).
+__device__ __forceinline__ void md_corner(const MdTables& md, int nx, int ny, uint32_t cl, int i0,
+                                          int j0, int k0, int ta, int tb, int tc, double E[3]) {
   const int cnt = (int)(cl & 255u);
-  if (cnt == 0) return;
-  const int a = (int)(bi % md.bsx), b = (int)((bi / md.bsx) % md.bsy);
-  const int c = (int)(bi / ((long)md.bsx * md.bsy));
-  const int i0 = (md.bx0 + a) % nx, j0 = (md.by0 + b) % ny, k0 = md.bz0 + c;
-  const int ta = t & 1, tb = (t >> 1) & 1, tc = t >> 2;
-  const int in = i0 + ta == nx ? 0 : i0 + ta, jn = j0 + tb == ny ? 0 : j0 + tb;
-  double ex, ey, ez;
-  load_node(E, in + (long)nx * jn + (long)nxy * (k0 + tc), ex, ey, ez);
   const int side = md.side;
   const long cube = (long)side * side * side;
   for (int u = 0; u < cnt; ++u) {
@@ -304,14 +289,69 @@ __global__ void md_field_kernel(const ET* __restrict__ E, MdTables md, int nx, i
     const int lz = k0 - (md.gcell[3 * g + 2] - md.cutoff);
     const long l = ((long)(lz + tc) * side + (ly + tb)) * side + (lx + ta);
     const double* U = md.U + (long)g * 3 * cube;
-    ex -= Q * U[l];
-    ey -= Q * U[cube + l];
-    ez -= Q * U[2 * cube + l];
+    E[0] -= Q * U[l];
+    E[1] -= Q * U[cube + l];
+    E[2] -= Q * U[2 * cube + l];
   }
+}
+
+// The fields of a step in one launch.  Blocks [0, nbm): one thread per (MD box
+// cell in a cube, corner) forms the corrected node field; E at the node is
+// formed from phi and rounded to the storage type first, so it is what a read
+// of E returns (these blocks come first: their dependent table loads then
+// overlap the node blocks' streaming).  Blocks from nbm on: one thread per
+// node writes phi (kLift: from the refined solve's interior potential psi and
+// the electrode voltages; otherwise phi is the stored src), E = -grad phi in
+// the storage type, and clears the next step's charge accumulator.
+template <typename ET, bool kLift>
+__global__ __launch_bounds__(256) void field_out_kernel(const double* __restrict__ src,
+                                                        double* __restrict__ phi,
+                                                        ET* __restrict__ E,
+                                                        unsigned long long* __restrict__ zero_next,
+                                                        MdTables md, int nx, int ny, int nz,
+                                                        double dx, RfDrive rf, int nbm) {
+  const double V = kLift ? rf_voltage(rf) : 0.0;
+  if ((int)blockIdx.x >= nbm) {
+    const int plane = nx * ny;
+    const int n = ((int)blockIdx.x - nbm) * (int)blockDim.x + (int)threadIdx.x;
+    if (n >= plane * (nz + 1)) return;
+    const int k = n / plane, pn = n - k * plane;
+    const int y = pn / nx, x = pn - y * nx;
+    if (kLift) phi[n] = phi_node<true>(src, plane, pn, k, nz, V);
+    double ex, ey, ez;
+    node_field<kLift>(src, nx, ny, nz, dx, V, x, y, k, ex, ey, ez);
+    if constexpr (std::is_same<ET, double2>::value) {
+      E[2 * (long)n] = make_double2(ex, ey);
+      E[2 * (long)n + 1] = make_double2(ez, 0.0);
+    } else {
+      E[n] = make_float4((float)ex, (float)ey, (float)ez, 0.0f);
+    }
+    if (zero_next) zero_next[n] = 0ull;
+    return;
+  }
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nbox = (long)md.bsx * md.bsy * md.bsz;
+  if (gid >= 8 * nbox) return;
+  const long bi = gid >> 3;
+  const int t = (int)(gid & 7);
+  const uint32_t cl = md.cell_list[bi];
+  if ((cl & 255u) == 0u) return;
+  const int a = (int)(bi % md.bsx), b = (int)((bi / md.bsx) % md.bsy);
+  const int c = (int)(bi / ((long)md.bsx * md.bsy));
+  const int i0 = (md.bx0 + a) % nx, j0 = (md.by0 + b) % ny, k0 = md.bz0 + c;
+  const int ta = t & 1, tb = (t >> 1) & 1, tc = t >> 2;
+  const int in = i0 + ta == nx ? 0 : i0 + ta, jn = j0 + tb == ny ? 0 : j0 + tb;
+  double En[3];
+  node_field<kLift>(src, nx, ny, nz, dx, V, in, jn, k0 + tc, En[0], En[1], En[2]);
+  if constexpr (!std::is_same<ET, double2>::value) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) En[q] = (double)(float)En[q];
+  }
+  md_corner(md, nx, ny, cl, i0, j0, k0, ta, tb, tc, En);
   double* dst = md.ecorr + bi * 24 + 3 * t;
-  dst[0] = ex;
-  dst[1] = ey;
-  dst[2] = ez;
+  dst[0] = En[0];
+  dst[1] = En[1];
+  dst[2] = En[2];
 }
 
 // ---------------------------------------------------------------- collisions
@@ -1614,14 +1654,6 @@ __global__ __launch_bounds__(kMdThreads) void md_kernel(SpeciesPair<PT> pr, cons
     if (s_hits[t]) atomicAdd(&grain_count[2 * t + S.sp], (unsigned long long)s_hits[t]);
 }
 
-// the dense MD list starts empty for the next step
-__global__ void md_reset_kernel(int32_t* cnt0, int32_t* cnt1) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    cnt0[2] = 0;
-    cnt1[2] = 0;
-  }
-}
-
 // ---------------------------------------------------------------- moments
 // Density and flux moments of one species on the mesh nodes (the densities
 // and fluxes of Sec. IV): per node the sums over the particles of W and of
@@ -2446,8 +2478,14 @@ __global__ void fill_int_kernel(int* a, long n, int v) {
 }
 
 // k -> k + 1 at the end of a step
-__global__ void advance_step_kernel(uint32_t* step) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1u;
+// the end of a step: the step counter advances and the dense MD lists start
+// empty for the next step
+__global__ void advance_step_kernel(uint32_t* step, int32_t* cnt0, int32_t* cnt1) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *step += 1u;
+    cnt0[2] = 0;
+    cnt1[2] = 0;
+  }
 }
 
 // ---------------------------------------------------------------- ionisation
@@ -2610,8 +2648,8 @@ int tile_grid(int nx, int ny, int nz, int extra) {
 }
 
 
-void launch_advance_step(uint32_t* step, hipStream_t st) {
-  hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, step);
+void launch_advance_step(uint32_t* step, int32_t* cnt0, int32_t* cnt1, hipStream_t st) {
+  hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, step, cnt0, cnt1);
 }
 
 void launch_push_f64(const PartF64& P, const double* E, double* rho, const MdTables& md,
@@ -2639,16 +2677,28 @@ void launch_push_batch_f32r(const PushDescF32* descs, const int32_t* start, int 
 
 constexpr int kMdBlocks = kMdTallyRows;
 
-void launch_md_field(const void* E, int e_f64, const MdTables& md, int nx, int ny,
-                     hipStream_t st) {
-  if (md.n_grains == 0) return;
-  const long n = 8L * md.bsx * md.bsy * md.bsz;
-  if (e_f64)
-    hipLaunchKernelGGL(md_field_kernel<double2>, dim3(nblk(n, 256)), dim3(256), 0, st,
-                       (const double2*)E, md, nx, ny, nx * ny);
-  else
-    hipLaunchKernelGGL(md_field_kernel<float4>, dim3(nblk(n, 256)), dim3(256), 0, st,
-                       (const float4*)E, md, nx, ny, nx * ny);
+void launch_field_out(const double* psi, double* phi, void* E, int e_f64,
+                      unsigned long long* zero_next, const MdTables& md, int nx, int ny, int nz,
+                      double dx, RfDrive rf, hipStream_t st) {
+  const long nn = (long)nx * ny * (nz + 1);
+  const int nbe = nblk(nn, 256);
+  const int nbm = md.n_grains > 0 ? nblk(8L * md.bsx * md.bsy * md.bsz, 256) : 0;
+  const double* src = psi ? psi : phi;
+  if (e_f64) {
+    if (psi)
+      hipLaunchKernelGGL((field_out_kernel<double2, true>), dim3(nbe + nbm), dim3(256), 0, st, src,
+                         phi, (double2*)E, zero_next, md, nx, ny, nz, dx, rf, nbm);
+    else
+      hipLaunchKernelGGL((field_out_kernel<double2, false>), dim3(nbe + nbm), dim3(256), 0, st,
+                         src, phi, (double2*)E, zero_next, md, nx, ny, nz, dx, rf, nbm);
+  } else {
+    if (psi)
+      hipLaunchKernelGGL((field_out_kernel<float4, true>), dim3(nbe + nbm), dim3(256), 0, st, src,
+                         phi, (float4*)E, zero_next, md, nx, ny, nz, dx, rf, nbm);
+    else
+      hipLaunchKernelGGL((field_out_kernel<float4, false>), dim3(nbe + nbm), dim3(256), 0, st, src,
+                         phi, (float4*)E, zero_next, md, nx, ny, nz, dx, rf, nbm);
+  }
 }
 
 void launch_collide_f64(const PartF64& P, const SpeciesStep& S, const WorkLists& L,
@@ -2679,7 +2729,6 @@ void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const Md
       hipLaunchKernelGGL(md_collide_kernel<PartF64>, dim3(2 * kMdBlocks), dim3(kMdThreads), 0, st,
                          pr);
   }
-  hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L[0].cnt, L[1].cnt);
 }
 
 void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, const MdTables& md,
@@ -2698,7 +2747,6 @@ void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, cons
       hipLaunchKernelGGL(md_collide_kernel<PartF32R>, dim3(2 * kMdBlocks), dim3(kMdThreads), 0, st,
                          pr);
   }
-  hipLaunchKernelGGL(md_reset_kernel, dim3(1), dim3(64), 0, st, L[0].cnt, L[1].cnt);
 }
 
 void launch_init_f64(const PartF64& P, int n, int ppc, int nx, int ny, int sp, uint32_t k0,

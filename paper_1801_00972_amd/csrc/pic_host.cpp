@@ -651,29 +651,31 @@ int deposit_current(pic_ctx* ctx, Replica& R) {
   return PIC_OK;
 }
 
-// phi_k and E_k from rho_k, the grains' charges and V(t_k); also freezes Q_g
-int solve_fields(pic_ctx* ctx, Replica& R) {
+// phi_k and E_k from rho_k, the grains' charges and V(t_k); also freezes Q_g.
+// zero_next: the same launch clears the other charge accumulator for the
+// step's deposit of rho_{k+1}
+int solve_fields(pic_ctx* ctx, Replica& R, bool zero_next = false) {
   hipStream_t st = ctx->stream;
   const pic_config& c = R.cfg;
   const RfDrive rf{c.V_dc, c.V_rf, c.f_rf, c.dt, R.d_step};
   const double vol = c.dx * c.dx * c.dx;
+  unsigned long long* next =
+      zero_next ? (unsigned long long*)R.rho[1 - R.rho_cur] : nullptr;  // 8-byte words, 0 = 0.0
   if (R.prec == PIC_FP64) {
     const double scale = -c.dx * c.dx / kEps0 * (R.we / vol);
     launch_rhs_f64((const double*)R.rho[R.rho_cur], scale, R.b, R.nx, R.ny, R.nz, st);
     launch_grain_rhs(R.d_gc, R.md.gpos, c.n_grains, R.nx, R.ny, R.nz, R.we, R.d_Q, R.b, scale, 0,
                      R.Qp, st);
     launch_solve_f64(R.fft, R.nx, R.ny, R.nz, R.b, R.work, R.tw_x, R.tw_y, R.inv, R.phi, rf, st);
-    launch_efield_f64(R.phi, (double*)R.E, R.nx, R.ny, R.nz, c.dx, st);
-    launch_md_field(R.E, 1, R.md, R.nx, R.ny, st);
+    launch_field_out(nullptr, R.phi, R.E, 1, next, R.md, R.nx, R.ny, R.nz, c.dx, rf, st);
   } else {
     const double scale = -c.dx * c.dx / kEps0 * (kCharge / 4294967296.0 / vol);
     launch_rhs_fixed((const long long*)R.rho[R.rho_cur], scale, R.b, R.nx, R.ny, R.nz, st);
     launch_grain_rhs(R.d_gc, R.md.gpos, c.n_grains, R.nx, R.ny, R.nz, R.we, R.d_Q, R.b, scale, 1,
                      R.Qp, st);
     launch_solve_refined(R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y, R.inv,
-                         R.phi, rf, c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st);
-    launch_efield_f32(R.phi, (float*)R.E, R.nx, R.ny, R.nz, c.dx, st);
-    launch_md_field(R.E, 0, R.md, R.nx, R.ny, st);
+                         rf, c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st);
+    launch_field_out(R.psi, R.phi, R.E, 0, next, R.md, R.nx, R.ny, R.nz, c.dx, rf, st);
   }
   CHECK_LAUNCH(ctx);
   return PIC_OK;
@@ -832,7 +834,7 @@ int species_join(pic_ctx* ctx, bool forked) {
 int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   hipStream_t st = ctx->stream;
   hipEvent_t f0 = prof_event(ctx);
-  TRY(solve_fields(ctx, R));
+  TRY(solve_fields(ctx, R, true));
   if (sample) TRY(enqueue_sample(ctx, R));
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
   if (coulomb_due(R)) {
@@ -845,7 +847,6 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
   bool forked = false;
   if (R.prec == PIC_FP64) {
-    launch_zero_f64((double*)R.rho[rnx], R.nn, st);
     const PartF64 P[2] = {R.p64[0][R.cur[0]], R.p64[1][R.cur[1]]};
     TRY(species_fork(ctx, &forked));
     for (int sp = 0; sp < 2; ++sp) {
@@ -866,7 +867,6 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
                     iz_room(R), iz_room(R), R.d_iz_drop, st);
     prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
   } else {
-    launch_zero_i64((long long*)R.rho[rnx], R.nn, st);
     const PartF32R P[2] = {R.p32[0][R.cur[0]], R.p32[1][R.cur[1]]};
     TRY(species_fork(ctx, &forked));
     for (int sp = 0; sp < 2; ++sp) {
@@ -888,7 +888,7 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
                     iz_room(R), iz_room(R), R.d_iz_drop, st);
     prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
   }
-  launch_advance_step(R.d_step, st);
+  launch_advance_step(R.d_step, R.lists[0].cnt, R.lists[1].cnt, st);
   CHECK_LAUNCH(ctx);
   if (sorts) {
     hipEvent_t s0 = prof_event(ctx);
@@ -945,10 +945,9 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   const Replica& R0 = *ctx->reps[0];
   hipEvent_t f0 = prof_event(ctx);
   TRY(for_replicas(ctx, [&](Replica& R) -> int {
-    TRY(solve_fields(ctx, R));
+    TRY(solve_fields(ctx, R, true));
     if (sample) TRY(enqueue_sample(ctx, R));
     if (coulomb_due(R)) TRY(enqueue_coulomb(ctx, R));
-    launch_zero_i64((long long*)R.rho[1 - R.rho_cur], R.nn, ctx->stream);
     return PIC_OK;
   }));
   CHECK_LAUNCH(ctx);
@@ -969,7 +968,7 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
     if (R.ionize)
       launch_ionize(nullptr, nullptr, &P[0], &P[1], R.lists[0], R.lists[1], S[0], R.d_next_id,
                     iz_room(R), iz_room(R), R.d_iz_drop, ws);
-    launch_advance_step(R.d_step, ws);
+    launch_advance_step(R.d_step, R.lists[0].cnt, R.lists[1].cnt, ws);
     return PIC_OK;
   }));
   CHECK_LAUNCH(ctx);
