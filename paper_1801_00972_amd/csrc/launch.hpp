@@ -44,16 +44,24 @@ void launch_collide_f64(const PartF64& P, const SpeciesStep& S, const WorkLists&
                         hipStream_t st);
 void launch_collide_f32r(const PartF32R& P, const SpeciesStep& S, const WorkLists& L,
                          hipStream_t st);
-// the listed particles of both species of a replica, after both pushes:
-// outliers and sub-cycled MD motion (each with its collision and deposit);
-// each kernel covers both species in one launch
+// the listed particles of both species of an FP64 replica, after both
+// pushes: outliers and sub-cycled MD motion (each with its collision and
+// deposit); each kernel covers both species in one launch
 void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const MdTables& md,
                       const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
                       int do_mcc, hipStream_t st);
-void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, const MdTables& md,
-                       const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
+// FP32R MD particles: their list (before the push, md_scan_kernel), their
+// sub-cycled motion from P into the other record buffers D (beside the push),
+// then, with the outliers, their states copied back into P and their
+// collisions (after the push)
+void launch_md_scan_f32r(const PartF32R P[2], const WorkLists L[2], const MdTables& md, int nx,
+                         int ny, const long cap[2], hipStream_t st);
+void launch_md_move_f32r(const PartF32R P[2], const PartF32R D[2], const float* E,
+                         long long* rho, const MdTables& md, const SpeciesStep S[2],
+                         unsigned long long* gc, const WorkLists L[2], hipStream_t st);
+void launch_lists_f32r(const PartF32R P[2], const PartF32R D[2], const float* E, long long* rho,
+                       const MdTables& md, const SpeciesStep S[2], const WorkLists L[2],
                        int do_mcc, hipStream_t st);
-// the corrected node fields of the MD cells (after E_k and the grain charges)
 // The fields of a step in one launch: phi (from the refined solve's psi,
 // lifted with the electrode voltages, when psi is given; otherwise phi is read
 // as stored), E = -grad phi into E (FP64 double2 pairs or FP32 float4), the

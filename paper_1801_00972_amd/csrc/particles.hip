@@ -964,9 +964,11 @@ __device__ __forceinline__ bool window_meets_md(const Tile& w, const MdTables& m
 // offset form, periodic wrap, electrode absorption, collision candidate test;
 // the new positions are deposited into the LDS window (per-thread sums over a
 // run of particles in one cell first), whose occupied nodes are then added to
-// rho.  Particles starting inside an MD cube are left untouched and listed for
-// the sub-cycled kernel; candidates are listed for the collision kernel, which
-// runs right after the push while the records it wrote are still in cache.
+// rho.  Particles starting inside an MD cube are left untouched (their list
+// is formed before the push, md_scan_kernel, and the sub-cycled kernel moves
+// them meanwhile into the other record buffer); candidates are listed for the
+// collision kernel, which runs right after the push while the records it
+// wrote are still in cache.
 constexpr int kWinF32 = 1331;  // window capacity (nodes): a tile with a 3-cell margin
 
 // The FP32R push streams the particle records once per step in each direction
@@ -1006,8 +1008,7 @@ struct PushSmemF32 {
   float4 E[kWinF32];
   long long rho[kWinF32];
   unsigned tally[TL_N];
-  int nmd, ncoll, nout, mdbase;
-  int32_t md[2 * kChunk];  // MD slots of up to two passes
+  int ncoll, nout;
 };
 
 // A block takes `span` tiles that are consecutive along x (1 or 2): their
@@ -1033,7 +1034,6 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
   }
   if (threadIdx.x < TL_N) sm.tally[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
-    sm.nmd = 0;
     sm.ncoll = 0;
     sm.nout = 0;
   }
@@ -1131,7 +1131,6 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
         chunk_append(st[q] == ST_OUT, L.out + beg, &sm.nout, p0 + q);
         packed += 1ull << (8 * st[q]);
       }
-      append_slot_order(st, ST_MD, sm.md, &sm.nmd, p0);
       if ((pass & 31) == 31) {
         n_w0 += (int)((packed >> (8 * ST_WALL0)) & 255u);
         n_w1 += (int)((packed >> (8 * ST_WALL1)) & 255u);
@@ -1182,12 +1181,6 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
       }
     }
     if (acc_cell >= 0) deposit_run(tile, sm.rho, rho, S, acc_cell, acc);
-    // the MD stage holds two passes: flush after every second pass (a
-    // block-uniform decision) and after the last
-    if (kMove && (pass & 1) && base + kChunk < end) {
-      __syncthreads();
-      md_flush(sm.md, &sm.nmd, &sm.mdbase, L);
-    }
   }
   if (kMove) {
     n_w0 += (int)((packed >> (8 * ST_WALL0)) & 255u);
@@ -1217,7 +1210,6 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
       L.out_cnt[tidx] = sm.nout;
     }
     tally_store(sm.tally, L.tally + (long)TL_N * tidx);
-    md_flush(sm.md, &sm.nmd, &sm.mdbase, L);
   }
 }
 
@@ -1582,19 +1574,45 @@ __device__ __forceinline__ void deposit_wave(A* __restrict__ rho, const SpeciesS
 
 __device__ __forceinline__ void kill(const PartF64& P, long p) { P.z[p] = -1.0; }
 __device__ __forceinline__ void kill(const PartF32R& P, long p) { P.cell[p] = -1; }
+// slot p of src into slot p of dst (an empty src slot empties dst's)
+__device__ __forceinline__ void copy_rec(const PartF64& src, const PartF64& dst, long p) {
+  dst.x[p] = src.x[p];
+  dst.y[p] = src.y[p];
+  dst.z[p] = src.z[p];
+  dst.vx[p] = src.vx[p];
+  dst.vy[p] = src.vy[p];
+  dst.vz[p] = src.vz[p];
+}
+__device__ __forceinline__ void copy_rec(const PartF32R& src, const PartF32R& dst, long p) {
+  const int c = src.cell[p];
+  dst.cell[p] = c;
+  if (c < 0) return;
+  dst.ox[p] = src.ox[p];
+  dst.oy[p] = src.oy[p];
+  dst.oz[p] = src.oz[p];
+  dst.vx[p] = src.vx[p];
+  dst.vy[p] = src.vy[p];
+  dst.vz[p] = src.vz[p];
+}
 
 // one thread per MD particle of the dense list of this step, both species in
 // one launch (blocks [0, nb) electrons, [nb, 2 nb) ions); events go to the
-// block's own tally row, grain hits to LDS counters first.  The survivors'
+// block's own tally row, grain hits to LDS counters first.  The particles are
+// read from P and their new states written to the same slots of D: D = P for
+// the FP64 records (in place, after the push); the FP32R step runs this kernel
+// beside the push with D the species' other record buffer, and
+// md_collide_kernel copies the states back afterwards.  The survivors'
 // collisions follow in md_collide_kernel (kept out of this kernel so that its
 // registers allow three waves per SIMD).
 constexpr int kMdThreads = 64;
 template <typename PT, typename ET, typename RT>
-__global__ __launch_bounds__(kMdThreads) void md_kernel(SpeciesPair<PT> pr, const ET* __restrict__ E,
+__global__ __launch_bounds__(kMdThreads) void md_kernel(SpeciesPair<PT> pr, PT D0, PT D1,
+                                                        const ET* __restrict__ E,
                                                         RT* __restrict__ rho, MdTables md,
                                                         unsigned long long* __restrict__ grain_count) {
   const int sp = (int)blockIdx.x >= pr.nb;
   const PT P = pr.P[sp];
+  const PT D = sp ? D1 : D0;
   const SpeciesStep S = pr.S[sp];
   const WorkLists L = pr.L[sp];
   const int bid = (int)blockIdx.x - sp * pr.nb;
@@ -1627,10 +1645,10 @@ __global__ __launch_bounds__(kMdThreads) void md_kernel(SpeciesPair<PT> pr, cons
         else atomicAdd(&grain_count[2 * hit + S.sp], 1ull);
       }
       if (st == ST_ALIVE) {
-        cell = store_d(P, p, x, v, S, part);
+        cell = store_d(D, p, x, v, S, part);
         if (cell < 0) st = ST_WALL1;
       } else {
-        kill(P, p);
+        kill(D, p);
       }
     }
     deposit_wave<RT>(rho, S, cell, part);
@@ -1815,9 +1833,11 @@ __global__ __launch_bounds__(256) void fine_moments_kernel(PT P, WorkLists L, Fi
 // The collisions of the MD particles that survived their sub-cycled motion,
 // from their stored velocities (same list, blocks and tally rows as md_kernel).
 template <typename PT>
-__global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> pr) {
+__global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> pr, PT D0, PT D1,
+                                                                int commit, int mcc) {
   const int sp = (int)blockIdx.x >= pr.nb;
   const PT P = pr.P[sp];
+  const PT D = sp ? D1 : D0;
   const SpeciesStep S = pr.S[sp];
   const WorkLists L = pr.L[sp];
   const int bid = (int)blockIdx.x - sp * pr.nb;
@@ -1827,7 +1847,8 @@ __global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> 
   for (long idx = (long)bid * kMdThreads + threadIdx.x; idx < total;
        idx += (long)pr.nb * kMdThreads) {
     const long p = L.md[idx];
-    if (!slot_alive(P, p)) continue;
+    if (commit) copy_rec(D, P, p);  // the sub-cycled kernel's result
+    if (!mcc || !slot_alive(P, p)) continue;
     bool coll = false, capv = false;
     typename VelOf<PT>::type v[3] = {P.vx[p], P.vy[p], P.vz[p]};
     collide(S, P.id[p], v, coll, capv, p);
@@ -1846,6 +1867,65 @@ __global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> 
     if (n_coll) tally[TL_COLL] += (unsigned long long)n_coll;
     if (n_cap) tally[TL_CAP] += (unsigned long long)n_cap;
   }
+}
+
+// ---------------------------------------------------------------- MD list
+// The dense MD list of an FP32R step, formed before the push: every slot
+// whose particle starts the step in a cell of an MD cube (the push leaves
+// those to the sub-cycled kernel; the same test as the push's).  A block takes
+// kMdScanSlots consecutive slots of one species (blocks [0, nb0) electrons,
+// the rest ions), compacts its hits in slot order and reserves their place in
+// the list with one atomic; L.cnt[2] is zero at the start of a step.
+constexpr int kMdScanPer = 8;  // slots per thread (two 16-byte loads)
+constexpr int kMdScanSlots = 256 * kMdScanPer;
+__global__ __launch_bounds__(256) void md_scan_kernel(PartF32R P0, PartF32R P1, WorkLists L0,
+                                                      WorkLists L1, MdTables md, int nx, int ny,
+                                                      int nb0) {
+  __shared__ int s_wave[4];
+  __shared__ int s_base;
+  const int sp = (int)blockIdx.x >= nb0 ? 1 : 0;
+  const PartF32R P = sp ? P1 : P0;
+  const WorkLists L = sp ? L1 : L0;
+  const int n = L.tstart[L.ngrid];  // slots in use (a multiple of 4)
+  const int s0 = ((int)blockIdx.x - sp * nb0) * kMdScanSlots;
+  if (s0 >= n) return;
+  const int p0 = s0 + kMdScanPer * (int)threadIdx.x;
+  int c[kMdScanPer];
+#pragma unroll
+  for (int h = 0; h < kMdScanPer / 4; ++h) {
+    int4 v = make_int4(-1, -1, -1, -1);
+    if (p0 + 4 * h < n) v = reinterpret_cast<const int4*>(P.cell)[(p0 >> 2) + h];
+    c[4 * h] = v.x;
+    c[4 * h + 1] = v.y;
+    c[4 * h + 2] = v.z;
+    c[4 * h + 3] = v.w;
+  }
+  bool hit[kMdScanPer];
+  int cnt = 0;
+#pragma unroll
+  for (int q = 0; q < kMdScanPer; ++q) {
+    hit[q] = c[q] >= 0 && md_lookup(md, nx, ny, cell_i(c[q]), cell_j(c[q]), cell_k(c[q])) != 0u;
+    cnt += hit[q];
+  }
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+  int incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    s_base = total ? atomicAdd(&L.cnt[2], total) : 0;
+  }
+  __syncthreads();
+  int at = s_base + incl - cnt;
+  for (int w = 0; w < wave; ++w) at += s_wave[w];
+#pragma unroll
+  for (int q = 0; q < kMdScanPer; ++q)
+    if (hit[q]) L.md[at++] = p0 + q;
 }
 
 // ---------------------------------------------------------------- outliers
@@ -2724,15 +2804,33 @@ void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const Md
   if (md.n_grains > 0) {
     pr.nb = kMdBlocks;
     hipLaunchKernelGGL((md_kernel<PartF64, double2, double>), dim3(2 * kMdBlocks), dim3(kMdThreads),
-                       0, st, pr, (const double2*)E, rho, md, gc);
+                       0, st, pr, P[0], P[1], (const double2*)E, rho, md, gc);
     if (do_mcc)
       hipLaunchKernelGGL(md_collide_kernel<PartF64>, dim3(2 * kMdBlocks), dim3(kMdThreads), 0, st,
-                         pr);
+                         pr, P[0], P[1], 0, 1);
   }
 }
 
-void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, const MdTables& md,
-                       const SpeciesStep S[2], unsigned long long* gc, const WorkLists L[2],
+void launch_md_scan_f32r(const PartF32R P[2], const WorkLists L[2], const MdTables& md, int nx,
+                         int ny, const long cap[2], hipStream_t st) {
+  if (md.n_grains == 0 || L[0].ngrid <= 0) return;
+  const int nb0 = nblk(cap[0], kMdScanSlots), nb1 = nblk(cap[1], kMdScanSlots);
+  if (nb0 + nb1 > 0)
+    hipLaunchKernelGGL(md_scan_kernel, dim3(nb0 + nb1), dim3(256), 0, st, P[0], P[1], L[0], L[1],
+                       md, nx, ny, nb0);
+}
+
+void launch_md_move_f32r(const PartF32R P[2], const PartF32R D[2], const float* E,
+                         long long* rho, const MdTables& md, const SpeciesStep S[2],
+                         unsigned long long* gc, const WorkLists L[2], hipStream_t st) {
+  if (md.n_grains == 0 || L[0].ngrid <= 0) return;
+  SpeciesPair<PartF32R> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, kMdBlocks, push_span(L[0])};
+  hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(2 * kMdBlocks),
+                     dim3(kMdThreads), 0, st, pr, D[0], D[1], (const float4*)E, rho, md, gc);
+}
+
+void launch_lists_f32r(const PartF32R P[2], const PartF32R D[2], const float* E, long long* rho,
+                       const MdTables& md, const SpeciesStep S[2], const WorkLists L[2],
                        int do_mcc, hipStream_t st) {
   if (L[0].ngrid <= 0) return;
   const int span = push_span(L[0]);
@@ -2741,11 +2839,8 @@ void launch_lists_f32r(const PartF32R P[2], const float* E, long long* rho, cons
                      rho, do_mcc);
   if (md.n_grains > 0) {
     pr.nb = kMdBlocks;
-    hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(2 * kMdBlocks),
-                       dim3(kMdThreads), 0, st, pr, (const float4*)E, rho, md, gc);
-    if (do_mcc)
-      hipLaunchKernelGGL(md_collide_kernel<PartF32R>, dim3(2 * kMdBlocks), dim3(kMdThreads), 0, st,
-                         pr);
+    hipLaunchKernelGGL(md_collide_kernel<PartF32R>, dim3(2 * kMdBlocks), dim3(kMdThreads), 0, st,
+                       pr, D[0], D[1], 1, do_mcc);
   }
 }
 

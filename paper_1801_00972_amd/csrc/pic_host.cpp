@@ -140,6 +140,9 @@ struct pic_ctx {
   // (fork and join events around them on the step's stream)
   hipStream_t species_stream = nullptr;
   hipEvent_t species_fork = nullptr, species_join = nullptr;
+  // FP32R MD particles beside the field solve and the push (one replica)
+  hipStream_t md_stream = nullptr;
+  hipEvent_t md_fork = nullptr, md_join = nullptr;
   // replicas stepped one by one are spread over worker streams (default
   // priority), forked from and joined back into the caller's stream
   std::vector<hipStream_t> workers;
@@ -180,6 +183,9 @@ struct pic_ctx {
     if (species_stream) (void)hipStreamDestroy(species_stream);
     if (species_fork) (void)hipEventDestroy(species_fork);
     if (species_join) (void)hipEventDestroy(species_join);
+    if (md_stream) (void)hipStreamDestroy(md_stream);
+    if (md_fork) (void)hipEventDestroy(md_fork);
+    if (md_join) (void)hipEventDestroy(md_join);
     for (hipStream_t w : workers) (void)hipStreamDestroy(w);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
@@ -829,6 +835,40 @@ int species_join(pic_ctx* ctx, bool forked) {
   return PIC_OK;
 }
 
+// The FP32R MD particles of a one-replica step on a stream of their own:
+// md_fork once the fields (and any Coulomb pass) are in place, so their list
+// forms and their sub-cycled motion runs beside the pushes; md_join before the
+// lists kernels copy their states back.  (The list's scan of every slot, run
+// beside the latency-bound field kernels instead, slowed those by more than
+// it costs the streaming pushes.)  *forked tells whether ctx->md_stream is
+// used.
+int md_fork(pic_ctx* ctx, bool* forked) {
+  *forked = ctx->reps.size() == 1 && !ctx->prof;
+  if (!*forked) return PIC_OK;
+  if (!ctx->md_stream) {
+    HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->md_stream, hipStreamNonBlocking));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->md_fork, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->md_join, hipEventDisableTiming));
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->md_fork, ctx->stream));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->md_stream, ctx->md_fork, 0));
+  return PIC_OK;
+}
+int md_join(pic_ctx* ctx, bool forked) {
+  if (!forked) return PIC_OK;
+  HIPCHK(ctx, hipEventRecord(ctx->md_join, ctx->md_stream));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->md_join, 0));
+  return PIC_OK;
+}
+
+// the species' current and other record buffers of an FP32R replica
+static void f32_buffers(const Replica& R, PartF32R P[2], PartF32R D[2]) {
+  for (int sp = 0; sp < 2; ++sp) {
+    P[sp] = R.p32[sp][R.cur[sp]];
+    D[sp] = R.p32[sp][1 - R.cur[sp]];
+  }
+}
+
 // launches one step of a replica on ctx->stream from the host state at the
 // start of the step (buffer phases); advance_host then moves the host mirrors
 int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
@@ -867,7 +907,18 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
                     iz_room(R), iz_room(R), R.d_iz_drop, st);
     prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
   } else {
-    const PartF32R P[2] = {R.p32[0][R.cur[0]], R.p32[1][R.cur[1]]};
+    PartF32R P[2], D[2];
+    f32_buffers(R, P, D);
+    bool mdf = false;
+    TRY(md_fork(ctx, &mdf));
+    {
+      hipStream_t ms = mdf ? ctx->md_stream : st;
+      hipEvent_t m0 = prof_event(ctx);
+      launch_md_scan_f32r(P, R.lists, R.md, R.nx, R.ny, R.cap, ms);
+      launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc,
+                          R.lists, ms);
+      prof_pair(ctx, PIC_PROF_LISTS, m0, prof_event(ctx));
+    }
     TRY(species_fork(ctx, &forked));
     for (int sp = 0; sp < 2; ++sp) {
       hipStream_t ss = forked && sp == 1 ? ctx->species_stream : st;
@@ -880,9 +931,10 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
       prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
     TRY(species_join(ctx, forked));
+    TRY(md_join(ctx, mdf));
     hipEvent_t b = prof_event(ctx);
-    launch_lists_f32r(P, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc, R.lists,
-                      do_mcc, st);
+    launch_lists_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.lists, do_mcc,
+                      st);
     if (R.ionize)
       launch_ionize(nullptr, nullptr, &P[0], &P[1], R.lists[0], R.lists[1], S[0], R.d_next_id,
                     iz_room(R), iz_room(R), R.d_iz_drop, st);
@@ -945,9 +997,15 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   const Replica& R0 = *ctx->reps[0];
   hipEvent_t f0 = prof_event(ctx);
   TRY(for_replicas(ctx, [&](Replica& R) -> int {
+    PartF32R P[2], D[2];
+    f32_buffers(R, P, D);
+    launch_md_scan_f32r(P, R.lists, R.md, R.nx, R.ny, R.cap, ctx->stream);
     TRY(solve_fields(ctx, R, true));
     if (sample) TRY(enqueue_sample(ctx, R));
     if (coulomb_due(R)) TRY(enqueue_coulomb(ctx, R));
+    const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
+    launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[1 - R.rho_cur], R.md, S,
+                        R.d_gc, R.lists, ctx->stream);
     return PIC_OK;
   }));
   CHECK_LAUNCH(ctx);
@@ -960,11 +1018,11 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   TRY(for_replicas(ctx, [&](Replica& R) -> int {
     hipStream_t ws = ctx->stream;
     const int rnx = 1 - R.rho_cur;
-    const PartF32R P[2] = {R.p32[0][R.cur[0]], R.p32[1][R.cur[1]]};
+    PartF32R P[2], D[2];
+    f32_buffers(R, P, D);
     const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
     for (int sp = 0; sp < 2; ++sp) launch_collide_f32r(P[sp], S[sp], R.lists[sp], ws);
-    launch_lists_f32r(P, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc, R.lists, 1,
-                      ws);
+    launch_lists_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.lists, 1, ws);
     if (R.ionize)
       launch_ionize(nullptr, nullptr, &P[0], &P[1], R.lists[0], R.lists[1], S[0], R.d_next_id,
                     iz_room(R), iz_room(R), R.d_iz_drop, ws);
