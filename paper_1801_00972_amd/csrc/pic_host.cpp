@@ -953,13 +953,27 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
 
 constexpr int kWorkers = 4;  // worker streams for the replicas of an ensemble
 
+// the caller's stream waits for every worker stream (after for_replicas)
+int join_replicas(pic_ctx* ctx) {
+  const int nw = std::min<int>(kWorkers, (int)ctx->reps.size());
+  if (nw <= 1 || ctx->prof) return PIC_OK;
+  for (int w = 0; w < nw; ++w) {
+    HIPCHK(ctx, hipEventRecord(ctx->join_ev[w], ctx->workers[w]));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->join_ev[w], 0));
+  }
+  return PIC_OK;
+}
+
 // Runs fn(R) for every replica: replica r on worker stream r % kWorkers, after
 // an event on the caller's stream, which then waits for every worker (a fork
 // and join that graph capture records as dependencies).  The replicas share
 // no memory, so their kernels may overlap.  With kernel timing on, or one
 // replica, everything stays on the caller's stream.
+// With join false the caller's stream does not wait yet: join_replicas()
+// does it later, so that work enqueued on the caller's stream meanwhile runs
+// beside the replicas' kernels.
 template <typename Fn>
-int for_replicas(pic_ctx* ctx, Fn fn) {
+int for_replicas(pic_ctx* ctx, Fn fn, bool join = true) {
   const int nw = std::min<int>(kWorkers, (int)ctx->reps.size());
   if (nw <= 1 || ctx->prof) {
     for (auto& R : ctx->reps) TRY(fn(*R));
@@ -983,10 +997,7 @@ int for_replicas(pic_ctx* ctx, Fn fn) {
     rc = fn(*ctx->reps[r]);
   }
   ctx->stream = caller;
-  for (int w = 0; w < nw; ++w) {
-    HIPCHK(ctx, hipEventRecord(ctx->join_ev[w], ctx->workers[w]));
-    HIPCHK(ctx, hipStreamWaitEvent(caller, ctx->join_ev[w], 0));
-  }
+  if (rc == PIC_OK && join) rc = join_replicas(ctx);
   return rc;
 }
 
@@ -997,24 +1008,34 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   const Replica& R0 = *ctx->reps[0];
   hipEvent_t f0 = prof_event(ctx);
   TRY(for_replicas(ctx, [&](Replica& R) -> int {
-    PartF32R P[2], D[2];
-    f32_buffers(R, P, D);
-    launch_md_scan_f32r(P, R.lists, R.md, R.nx, R.ny, R.cap, ctx->stream);
     TRY(solve_fields(ctx, R, true));
     if (sample) TRY(enqueue_sample(ctx, R));
     if (coulomb_due(R)) TRY(enqueue_coulomb(ctx, R));
-    const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
-    launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[1 - R.rho_cur], R.md, S,
-                        R.d_gc, R.lists, ctx->stream);
     return PIC_OK;
   }));
   CHECK_LAUNCH(ctx);
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
+  // every replica's MD particles on the worker streams beside the one push
+  // launch (enqueued first, so their waves are resident before the push's
+  // blocks fill the rest; the push's items are dealt dynamically)
+  TRY(for_replicas(
+      ctx,
+      [&](Replica& R) -> int {
+        PartF32R P[2], D[2];
+        f32_buffers(R, P, D);
+        const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
+        launch_md_scan_f32r(P, R.lists, R.md, R.nx, R.ny, R.cap, ctx->stream);
+        launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[1 - R.rho_cur], R.md, S,
+                            R.d_gc, R.lists, ctx->stream);
+        return PIC_OK;
+      },
+      false));
   hipEvent_t a = prof_event(ctx);
   launch_push_batch_f32r(ctx->d_desc + (size_t)phase_of(R0) * ctx->ndesc, ctx->d_start, ctx->ndesc,
                          ctx->tune.batch_blocks, ctx->d_queue, st);
   CHECK_LAUNCH(ctx);
   hipEvent_t b = prof_event(ctx);
+  TRY(join_replicas(ctx));
   TRY(for_replicas(ctx, [&](Replica& R) -> int {
     hipStream_t ws = ctx->stream;
     const int rnx = 1 - R.rho_cur;
