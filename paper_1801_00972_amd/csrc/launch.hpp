@@ -54,8 +54,8 @@ void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const Md
 // sub-cycled motion from P into the other record buffers D (beside the push),
 // then, with the outliers, their states copied back into P and their
 // collisions (after the push)
-void launch_md_scan_f32r(const PartF32R P[2], const WorkLists L[2], const MdTables& md, int nx,
-                         int ny, const long cap[2], hipStream_t st);
+void launch_md_scan_f32r(const PartF32R P[2], const WorkLists L[2], const MdTables& md,
+                         const SpeciesStep S[2], int nx, int ny, int nz, hipStream_t st);
 void launch_md_move_f32r(const PartF32R P[2], const PartF32R D[2], const float* E,
                          long long* rho, const MdTables& md, const SpeciesStep S[2],
                          unsigned long long* gc, const WorkLists L[2], hipStream_t st);

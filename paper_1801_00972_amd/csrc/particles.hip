@@ -927,12 +927,14 @@ __device__ __forceinline__ void md_flush(int32_t* s_md, int* s_nmd, int* s_mdbas
 }
 
 // one run of same-cell charge parts (magnitudes) into the window, or, outside
-// it, with the species' sign straight to the global mesh
+// it, with the species' sign straight to the global mesh (and the block's
+// stray flag set)
 __device__ __forceinline__ void deposit_run(const Tile& tile, long long* s_rho,
                                             long long* __restrict__ rho, const SpeciesStep& S,
-                                            int c, long long acc[8]) {
+                                            int c, long long acc[8], int* s_stray) {
   const int ai = cell_i(c), aj = cell_j(c), ak = cell_k(c);
   const int lb = tile_cell(tile, ai, aj, ak, S.nx, S.ny);
+  if (lb < 0) *s_stray = 1;  // the run ends the push outside the window
   if (lb < 0 && S.isign < 0) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) acc[t] = -acc[t];
@@ -1008,7 +1010,7 @@ struct PushSmemF32 {
   float4 E[kWinF32];
   long long rho[kWinF32];
   unsigned tally[TL_N];
-  int ncoll, nout;
+  int ncoll, nout, stray;
 };
 
 // A block takes `span` tiles that are consecutive along x (1 or 2): their
@@ -1036,6 +1038,7 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
   if (threadIdx.x == 0) {
     sm.ncoll = 0;
     sm.nout = 0;
+    sm.stray = 0;
   }
   // MD cubes near the window: only then does every particle need the lookup
   const bool md_near = window_meets_md(tile, md, S.nx, S.ny);
@@ -1174,13 +1177,13 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
 #pragma unroll
         for (int t = 0; t < 8; ++t) acc[t] += part[t];
       } else {
-        if (acc_cell >= 0) deposit_run(tile, sm.rho, rho, S, acc_cell, acc);
+        if (acc_cell >= 0) deposit_run(tile, sm.rho, rho, S, acc_cell, acc, &sm.stray);
         acc_cell = cell[q];
 #pragma unroll
         for (int t = 0; t < 8; ++t) acc[t] = part[t];
       }
     }
-    if (acc_cell >= 0) deposit_run(tile, sm.rho, rho, S, acc_cell, acc);
+    if (acc_cell >= 0) deposit_run(tile, sm.rho, rho, S, acc_cell, acc, &sm.stray);
   }
   if (kMove) {
     n_w0 += (int)((packed >> (8 * ST_WALL0)) & 255u);
@@ -1208,6 +1211,7 @@ __device__ __forceinline__ void push_tile_f32r(const PartF32R& P, const float4* 
     if (threadIdx.x == 0) {
       L.coll_cnt[tidx] = sm.ncoll;
       L.out_cnt[tidx] = sm.nout;
+      if (sm.stray) L.stray[tidx] = 1;
     }
     tally_store(sm.tally, L.tally + (long)TL_N * tidx);
   }
@@ -1872,60 +1876,71 @@ __global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> 
 // ---------------------------------------------------------------- MD list
 // The dense MD list of an FP32R step, formed before the push: every slot
 // whose particle starts the step in a cell of an MD cube (the push leaves
-// those to the sub-cycled kernel; the same test as the push's).  A block takes
-// kMdScanSlots consecutive slots of one species (blocks [0, nb0) electrons,
-// the rest ions), compacts its hits in slot order and reserves their place in
-// the list with one atomic; L.cnt[2] is zero at the start of a step.
-constexpr int kMdScanPer = 8;  // slots per thread (two 16-byte loads)
+// those to the sub-cycled kernel; the same test as the push's).  A particle
+// in an MD cube either lies inside its push block's window, which then meets
+// the MD cubes' bounding box, or has left that window since the last sort,
+// which set the block's stray flag; the grid's padding tiles (new particles of
+// ionisation) have no window.  So one block per push block (blocks [0, npb)
+// electrons, the rest ions) scans the block's slots only in those cases, in
+// chunks of kMdScanSlots, compacting a chunk's hits in slot order and
+// reserving their place in the list with one atomic; L.cnt[2] is zero at the
+// start of a step.
+constexpr int kMdScanPer = 8;  // slots per thread and chunk (two 16-byte loads)
 constexpr int kMdScanSlots = 256 * kMdScanPer;
 __global__ __launch_bounds__(256) void md_scan_kernel(PartF32R P0, PartF32R P1, WorkLists L0,
                                                       WorkLists L1, MdTables md, int nx, int ny,
-                                                      int nb0) {
+                                                      int nz, int m0, int m1, int span, int npb) {
   __shared__ int s_wave[4];
   __shared__ int s_base;
-  const int sp = (int)blockIdx.x >= nb0 ? 1 : 0;
+  const int sp = (int)blockIdx.x >= npb ? 1 : 0;
   const PartF32R P = sp ? P1 : P0;
   const WorkLists L = sp ? L1 : L0;
-  const int n = L.tstart[L.ngrid];  // slots in use (a multiple of 4)
-  const int s0 = ((int)blockIdx.x - sp * nb0) * kMdScanSlots;
-  if (s0 >= n) return;
-  const int p0 = s0 + kMdScanPer * (int)threadIdx.x;
-  int c[kMdScanPer];
-#pragma unroll
-  for (int h = 0; h < kMdScanPer / 4; ++h) {
-    int4 v = make_int4(-1, -1, -1, -1);
-    if (p0 + 4 * h < n) v = reinterpret_cast<const int4*>(P.cell)[(p0 >> 2) + h];
-    c[4 * h] = v.x;
-    c[4 * h + 1] = v.y;
-    c[4 * h + 2] = v.z;
-    c[4 * h + 3] = v.w;
-  }
-  bool hit[kMdScanPer];
-  int cnt = 0;
-#pragma unroll
-  for (int q = 0; q < kMdScanPer; ++q) {
-    hit[q] = c[q] >= 0 && md_lookup(md, nx, ny, cell_i(c[q]), cell_j(c[q]), cell_k(c[q])) != 0u;
-    cnt += hit[q];
-  }
+  const int t0 = ((int)blockIdx.x - sp * npb) * span;
+  const int beg = L.tstart[t0], end = L.tstart[t0 + span];  // multiples of 4
+  if (beg >= end) return;
+  if (!L.stray[t0] &&
+      !window_meets_md(make_tile(t0, L, nx, ny, nz, sp ? m1 : m0, kWinF32, span), md, nx, ny))
+    return;
   const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
-  int incl = cnt;
+  for (int s0 = beg; s0 < end; s0 += kMdScanSlots) {
+    const int p0 = s0 + kMdScanPer * (int)threadIdx.x;
+    int c[kMdScanPer];
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += t;
-  }
-  if (lane == 63) s_wave[wave] = incl;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-    s_base = total ? atomicAdd(&L.cnt[2], total) : 0;
-  }
-  __syncthreads();
-  int at = s_base + incl - cnt;
-  for (int w = 0; w < wave; ++w) at += s_wave[w];
+    for (int h = 0; h < kMdScanPer / 4; ++h) {
+      int4 v = make_int4(-1, -1, -1, -1);
+      if (p0 + 4 * h < end) v = reinterpret_cast<const int4*>(P.cell)[(p0 >> 2) + h];
+      c[4 * h] = v.x;
+      c[4 * h + 1] = v.y;
+      c[4 * h + 2] = v.z;
+      c[4 * h + 3] = v.w;
+    }
+    bool hit[kMdScanPer];
+    int cnt = 0;
 #pragma unroll
-  for (int q = 0; q < kMdScanPer; ++q)
-    if (hit[q]) L.md[at++] = p0 + q;
+    for (int q = 0; q < kMdScanPer; ++q) {
+      hit[q] = c[q] >= 0 && md_lookup(md, nx, ny, cell_i(c[q]), cell_j(c[q]), cell_k(c[q])) != 0u;
+      cnt += hit[q];
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += t;
+    }
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+      s_base = total ? atomicAdd(&L.cnt[2], total) : 0;
+    }
+    __syncthreads();
+    int at = s_base + incl - cnt;
+    for (int w = 0; w < wave; ++w) at += s_wave[w];
+#pragma unroll
+    for (int q = 0; q < kMdScanPer; ++q)
+      if (hit[q]) L.md[at++] = p0 + q;
+    __syncthreads();  // s_wave and s_base are reused by the next chunk
+  }
 }
 
 // ---------------------------------------------------------------- outliers
@@ -1943,6 +1958,7 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> 
   const int tidx = ((int)blockIdx.x - sp * pr.nb) * pr.span;
   const int count = L.out_cnt[tidx];
   if (count == 0) return;
+  if (threadIdx.x == 0) L.stray[tidx] = 1;  // (already set when these left the window)
   const int32_t* seg = L.out + L.tstart[tidx];
   int t_w0 = 0, t_w1 = 0, t_bad = 0, t_coll = 0, t_cap = 0, t_fast = 0;
   for (int idx = threadIdx.x; idx < count; idx += 64) {
@@ -2811,13 +2827,12 @@ void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const Md
   }
 }
 
-void launch_md_scan_f32r(const PartF32R P[2], const WorkLists L[2], const MdTables& md, int nx,
-                         int ny, const long cap[2], hipStream_t st) {
+void launch_md_scan_f32r(const PartF32R P[2], const WorkLists L[2], const MdTables& md,
+                         const SpeciesStep S[2], int nx, int ny, int nz, hipStream_t st) {
   if (md.n_grains == 0 || L[0].ngrid <= 0) return;
-  const int nb0 = nblk(cap[0], kMdScanSlots), nb1 = nblk(cap[1], kMdScanSlots);
-  if (nb0 + nb1 > 0)
-    hipLaunchKernelGGL(md_scan_kernel, dim3(nb0 + nb1), dim3(256), 0, st, P[0], P[1], L[0], L[1],
-                       md, nx, ny, nb0);
+  const int span = push_span(L[0]), npb = L[0].ngrid / span;
+  hipLaunchKernelGGL(md_scan_kernel, dim3(2 * npb), dim3(256), 0, st, P[0], P[1], L[0], L[1], md,
+                     nx, ny, nz, S[0].margin, S[1].margin, span, npb);
 }
 
 void launch_md_move_f32r(const PartF32R P[2], const PartF32R D[2], const float* E,
@@ -2972,6 +2987,7 @@ void launch_sort_f32r(const PartF32R& src, const PartF32R& dst, const WorkLists&
                       int* sums, long capacity, hipStream_t st) {
   if (capacity <= 0) return;
   sort_impl(src, dst, L, hist, sums, capacity, st);
+  launch_zero_i32(L.stray, L.ngrid, st);  // every particle is in its own tile again
 }
 
 }  // namespace pic

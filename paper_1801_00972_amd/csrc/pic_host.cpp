@@ -615,9 +615,11 @@ int alloc_particles(pic_ctx* ctx, Replica& R) {
     TRY(dalloc(ctx, R, &L.out_cnt, R.ngrid));
     TRY(dalloc(ctx, R, &L.tstart, R.ngrid + 1));
     TRY(dalloc(ctx, R, &L.tally, TL_N * (R.ngrid + kMdTallyRows)));
+    TRY(dalloc(ctx, R, &L.stray, R.ngrid));
     L.cnt = R.d_cnt + 8 * sp;
     HIPCHK(ctx, hipMemsetAsync(L.tally, 0, 8 * TL_N * (R.ngrid + kMdTallyRows), ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(L.tstart, 0, 4 * (R.ngrid + 1), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(L.stray, 0, 4 * R.ngrid, ctx->stream));
   }
   return PIC_OK;
 }
@@ -914,7 +916,7 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
     {
       hipStream_t ms = mdf ? ctx->md_stream : st;
       hipEvent_t m0 = prof_event(ctx);
-      launch_md_scan_f32r(P, R.lists, R.md, R.nx, R.ny, R.cap, ms);
+      launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ms);
       launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc,
                           R.lists, ms);
       prof_pair(ctx, PIC_PROF_LISTS, m0, prof_event(ctx));
@@ -1024,7 +1026,7 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
         PartF32R P[2], D[2];
         f32_buffers(R, P, D);
         const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
-        launch_md_scan_f32r(P, R.lists, R.md, R.nx, R.ny, R.cap, ctx->stream);
+        launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ctx->stream);
         launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[1 - R.rho_cur], R.md, S,
                             R.d_gc, R.lists, ctx->stream);
         return PIC_OK;
@@ -1244,6 +1246,10 @@ int apply_tuning(pic_ctx* ctx, const pic_tuning& t) {
   for (auto& R : ctx->reps) {
     R->margin[0] = t.tile_margin;
     R->margin[1] = t.ion_tile_margin;
+    // the stray flags refer to the old windows: every push block counts as
+    // stray until the next sort (the MD list's scan then covers all slots)
+    if (margin_changed && R->prec != PIC_FP64)
+      for (int sp = 0; sp < 2; ++sp) launch_fill_int(R->lists[sp].stray, R->ngrid, 1, ctx->stream);
   }
   if (margin_changed && ctx->batchable) TRY(build_batch(ctx));
   ctx->drop_graphs();

@@ -66,6 +66,9 @@ struct WorkLists {
   unsigned long long* tally;  // [ngrid + MD blocks][TL_N] accumulated event counts (see
                               // TallyKind); one row per tile, then one per MD block
   int32_t* cnt;       // [0] slots in use, [2] entries in md, [4] scan total of the sort
+  int32_t* stray;     // [ngrid] per push block (at its first tile), FP32R: nonzero once a
+                      // particle of the block's slots has ended a push outside the block's
+                      // window since the last sort (cleared by the sort)
   int ntx, nty, ntz;  // tiles along x, y, z
   int ngrid;          // tiles rounded up to a multiple of 8
 };
