@@ -53,7 +53,7 @@ void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const Md
 // FP32R MD particles: their list (before the push, md_scan_kernel), their
 // sub-cycled motion from P into the other record buffers D (beside the push),
 // then, with the outliers, their states copied back into P and their
-// collisions (after the push)
+// collisions (after the push): of both species (sp_only -1) or of one
 void launch_md_scan_f32r(const PartF32R P[2], const WorkLists L[2], const MdTables& md,
                          const SpeciesStep S[2], int nx, int ny, int nz, hipStream_t st);
 void launch_md_move_f32r(const PartF32R P[2], const PartF32R D[2], const float* E,
@@ -61,7 +61,7 @@ void launch_md_move_f32r(const PartF32R P[2], const PartF32R D[2], const float* 
                          unsigned long long* gc, const WorkLists L[2], hipStream_t st);
 void launch_lists_f32r(const PartF32R P[2], const PartF32R D[2], const float* E, long long* rho,
                        const MdTables& md, const SpeciesStep S[2], const WorkLists L[2],
-                       int do_mcc, hipStream_t st);
+                       int do_mcc, int sp_only, hipStream_t st);
 // The fields of a step in one launch: phi (from the refined solve's psi,
 // lifted with the electrode voltages, when psi is given; otherwise phi is read
 // as stored), E = -grad phi into E (FP64 double2 pairs or FP32 float4), the

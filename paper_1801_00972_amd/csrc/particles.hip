@@ -1838,13 +1838,15 @@ __global__ __launch_bounds__(256) void fine_moments_kernel(PT P, WorkLists L, Fi
 // from their stored velocities (same list, blocks and tally rows as md_kernel).
 template <typename PT>
 __global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> pr, PT D0, PT D1,
-                                                                int commit, int mcc) {
-  const int sp = (int)blockIdx.x >= pr.nb;
+                                                                int commit, int mcc,
+                                                                int sp_only) {
+  // both species (blocks [0, nb) electrons) or species sp_only alone
+  const int sp = sp_only >= 0 ? sp_only : ((int)blockIdx.x >= pr.nb ? 1 : 0);
   const PT P = pr.P[sp];
   const PT D = sp ? D1 : D0;
   const SpeciesStep S = pr.S[sp];
   const WorkLists L = pr.L[sp];
-  const int bid = (int)blockIdx.x - sp * pr.nb;
+  const int bid = (int)blockIdx.x - (sp_only >= 0 ? 0 : sp * pr.nb);
   const int total = L.cnt[2];
   if ((long)bid * kMdThreads >= total) return;
   int n_coll = 0, n_cap = 0;
@@ -1950,12 +1952,14 @@ __global__ __launch_bounds__(256) void md_scan_kernel(PartF32R P0, PartF32R P1, 
 // per tile segment.
 __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> pr,
                                                           const float4* __restrict__ E,
-                                                          long long* __restrict__ rho, int do_mcc) {
-  const int sp = (int)blockIdx.x >= pr.nb;
+                                                          long long* __restrict__ rho, int do_mcc,
+                                                          int sp_only) {
+  // both species (blocks [0, nb) electrons) or species sp_only alone
+  const int sp = sp_only >= 0 ? sp_only : ((int)blockIdx.x >= pr.nb ? 1 : 0);
   const PartF32R P = pr.P[sp];
   const SpeciesStep S = pr.S[sp];
   const WorkLists L = pr.L[sp];
-  const int tidx = ((int)blockIdx.x - sp * pr.nb) * pr.span;
+  const int tidx = ((int)blockIdx.x - (sp_only >= 0 ? 0 : sp * pr.nb)) * pr.span;
   const int count = L.out_cnt[tidx];
   if (count == 0) return;
   if (threadIdx.x == 0) L.stray[tidx] = 1;  // (already set when these left the window)
@@ -2823,7 +2827,7 @@ void launch_lists_f64(const PartF64 P[2], const double* E, double* rho, const Md
                        0, st, pr, P[0], P[1], (const double2*)E, rho, md, gc);
     if (do_mcc)
       hipLaunchKernelGGL(md_collide_kernel<PartF64>, dim3(2 * kMdBlocks), dim3(kMdThreads), 0, st,
-                         pr, P[0], P[1], 0, 1);
+                         pr, P[0], P[1], 0, 1, -1);
   }
 }
 
@@ -2846,16 +2850,17 @@ void launch_md_move_f32r(const PartF32R P[2], const PartF32R D[2], const float* 
 
 void launch_lists_f32r(const PartF32R P[2], const PartF32R D[2], const float* E, long long* rho,
                        const MdTables& md, const SpeciesStep S[2], const WorkLists L[2],
-                       int do_mcc, hipStream_t st) {
+                       int do_mcc, int sp_only, hipStream_t st) {
   if (L[0].ngrid <= 0) return;
   const int span = push_span(L[0]);
+  const int ns = sp_only >= 0 ? 1 : 2;
   SpeciesPair<PartF32R> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, L[0].ngrid / span, span};
-  hipLaunchKernelGGL(outlier_f32r_kernel, dim3(2 * pr.nb), dim3(64), 0, st, pr, (const float4*)E,
-                     rho, do_mcc);
+  hipLaunchKernelGGL(outlier_f32r_kernel, dim3(ns * pr.nb), dim3(64), 0, st, pr, (const float4*)E,
+                     rho, do_mcc, sp_only);
   if (md.n_grains > 0) {
     pr.nb = kMdBlocks;
-    hipLaunchKernelGGL(md_collide_kernel<PartF32R>, dim3(2 * kMdBlocks), dim3(kMdThreads), 0, st,
-                       pr, D[0], D[1], 1, do_mcc);
+    hipLaunchKernelGGL(md_collide_kernel<PartF32R>, dim3(ns * kMdBlocks), dim3(kMdThreads), 0, st,
+                       pr, D[0], D[1], 1, do_mcc, sp_only);
   }
 }
 

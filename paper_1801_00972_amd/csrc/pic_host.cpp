@@ -839,11 +839,11 @@ int species_join(pic_ctx* ctx, bool forked) {
 
 // The FP32R MD particles of a one-replica step on a stream of their own:
 // md_fork once the fields (and any Coulomb pass) are in place, so their list
-// forms and their sub-cycled motion runs beside the pushes; md_join before the
-// lists kernels copy their states back.  (The list's scan of every slot, run
-// beside the latency-bound field kernels instead, slowed those by more than
-// it costs the streaming pushes.)  *forked tells whether ctx->md_stream is
-// used.
+// forms and their sub-cycled motion runs beside the pushes; md_done marks the
+// end of that work, which each species' stream waits for before its lists
+// kernels copy the states back.  (The list's scan, run beside the
+// latency-bound field kernels instead, slowed those by more than it costs the
+// streaming pushes.)  *forked tells whether ctx->md_stream is used.
 int md_fork(pic_ctx* ctx, bool* forked) {
   *forked = ctx->reps.size() == 1 && !ctx->prof;
   if (!*forked) return PIC_OK;
@@ -856,10 +856,14 @@ int md_fork(pic_ctx* ctx, bool* forked) {
   HIPCHK(ctx, hipStreamWaitEvent(ctx->md_stream, ctx->md_fork, 0));
   return PIC_OK;
 }
-int md_join(pic_ctx* ctx, bool forked) {
+int md_done(pic_ctx* ctx, bool forked) {
   if (!forked) return PIC_OK;
   HIPCHK(ctx, hipEventRecord(ctx->md_join, ctx->md_stream));
-  HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->md_join, 0));
+  return PIC_OK;
+}
+int md_wait(pic_ctx* ctx, bool forked, hipStream_t s) {
+  if (!forked) return PIC_OK;
+  HIPCHK(ctx, hipStreamWaitEvent(s, ctx->md_join, 0));
   return PIC_OK;
 }
 
@@ -919,6 +923,7 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
       launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ms);
       launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc,
                           R.lists, ms);
+      TRY(md_done(ctx, mdf));
       prof_pair(ctx, PIC_PROF_LISTS, m0, prof_event(ctx));
     }
     TRY(species_fork(ctx, &forked));
@@ -929,14 +934,16 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
                        ss);
       hipEvent_t b = prof_event(ctx);
       launch_collide_f32r(P[sp], S[sp], R.lists[sp], ss);
+      // this species' outliers, and its MD particles' states back (once the
+      // MD kernel is done), while the other species may still stream
+      TRY(md_wait(ctx, mdf, ss));
+      launch_lists_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.lists,
+                        do_mcc, sp, ss);
       prof_pair(ctx, PIC_PROF_PUSH, a, b);
       prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
     TRY(species_join(ctx, forked));
-    TRY(md_join(ctx, mdf));
     hipEvent_t b = prof_event(ctx);
-    launch_lists_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.lists, do_mcc,
-                      st);
     if (R.ionize)
       launch_ionize(nullptr, nullptr, &P[0], &P[1], R.lists[0], R.lists[1], S[0], R.d_next_id,
                     iz_room(R), iz_room(R), R.d_iz_drop, st);
@@ -1045,7 +1052,8 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
     f32_buffers(R, P, D);
     const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
     for (int sp = 0; sp < 2; ++sp) launch_collide_f32r(P[sp], S[sp], R.lists[sp], ws);
-    launch_lists_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.lists, 1, ws);
+    launch_lists_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.lists, 1, -1,
+                      ws);
     if (R.ionize)
       launch_ionize(nullptr, nullptr, &P[0], &P[1], R.lists[0], R.lists[1], S[0], R.d_next_id,
                     iz_room(R), iz_room(R), R.d_iz_drop, ws);
