@@ -339,6 +339,40 @@ def test_md_margin_counter_matches_oracle(prec):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32r"])
+def test_md_particles_that_left_their_windows(prec):
+    """Near-grain particles found wherever they are: hot electrons and a 20 ps
+    step move about a cell per step, there is no re-binning, so after a few
+    steps many particles sit outside their push block's window, and some of
+    those inside an MD cube (the FP32R list scan finds them through the
+    blocks' stray flags).  Every step is compared with the oracle (a particle
+    left out of the MD list would not move), and a change of window margin in
+    the middle (every block then counts as stray) changes nothing."""
+    wl = W.tiny(nx=16, ny=16, nz=16, ppc=2, grains=[[5.5, 6.5, 8.0], [12.0, 11.0, 7.5]], cutoff=2,
+                Te_eV=30.0, dt=2e-11, precision=prec)
+    sim = _sim(wl, sort_interval=0)
+    sim.set_tuning(ion_sort_interval=0)
+    sim.set_state(_random_state(wl, 6000, 1500, seed=23, near_grain=600))
+    tol = TOL[prec]
+    md = 0
+    for k in range(8):
+        if k == 4:
+            sim.set_tuning(tile_margin=1)
+        st = sim.get_state()
+        orc = oracle_from_state(wl, st)
+        c0 = sim.counters()["md_particles"]
+        sim.step(1)
+        orc.step(1)
+        rep = compare_step(wl, sim.get_state(), orc, tol["pos"], tol["vel"], tol["margin"])
+        d = [a - b for a, b in zip(sim.counters()["md_particles"], c0)]
+        md += sum(d)
+        print(f"  step {k}: MD particles {d}, flips {rep['flips']}, dpos {rep['max_dpos']:.1e}",
+              flush=True)
+        assert rep["flips"] <= 3
+    assert md > 500
+    sim.close()
+
+
 def test_weight_just_below_the_fixed_point_bound_runs():
     """w = n0 dx^3 / ppc just under 128 (macro charge just under 2^39 in
     2^-32 e): accepted, and the fixed-point deposit stays exact."""
