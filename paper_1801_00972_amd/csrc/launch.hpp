@@ -162,11 +162,25 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
                           const void* tw_y32, const void* inv, RfDrive rf, int sweeps,
-                          double tol, double* norms, int* ctl, hipStream_t st);
+                          double tol, double* norms, int* ctl, hipStream_t st,
+                          bool have_r0 = false);
+// one grain's share of the FP32R right-hand side: interior node `node` (the
+// index into b), grain g, the fixed-point part of its charge quantum at that
+// corner; a replica's table is sorted by node, then by grain and corner
+struct GrainShare {
+  long long part;
+  int node;
+  int g;
+};
+// the FP32R right-hand side (fixed-point rho and the grains' shares, tab)
+// and the first residual with its norm partials (partials = norms + 2 of the
+// refined solve, which then runs with have_r0); also freezes Q_g
+void launch_rhs_residual(const long long* rho, double scale, const GrainShare* tab, int ntab,
+                         const unsigned long long* counts, int ng, double we, double* Q,
+                         double* b, const double* psi, double* r, int nx, int ny, int nz,
+                         double* partials, hipStream_t st);
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
                     hipStream_t st);
-void launch_rhs_fixed(const long long* rho, double scale, double* b, int nx, int ny, int nz,
-                      hipStream_t st);
 void launch_grain_rhs(const unsigned long long* counts, const double* gpos, int ng, int nx, int ny,
                       int nz, double we, double* Q, double* b, double scale, int mode,
                       long long Qp, hipStream_t st);

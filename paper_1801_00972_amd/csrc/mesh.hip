@@ -463,11 +463,6 @@ __global__ void rhs_f64_kernel(const double* __restrict__ rho, double scale, dou
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_int) b[i] = scale * rho[i + plane];
 }
-__global__ void rhs_fixed_kernel(const long long* __restrict__ rho, double scale,
-                                 double* __restrict__ b, long plane, long n_int) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_int) b[i] = scale * (double)rho[i + plane];
-}
 
 // CIC nodes and weights of a grain (its position is at least one cell inside)
 __device__ __forceinline__ void grain_nodes(const double* gpos, int g, int nx, int ny, long n[8],
@@ -657,6 +652,79 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
     bb = bi * bi;
   }
   if (!NORMS) return;
+  s_r[threadIdx.x] = rr;
+  s_b[threadIdx.x] = bb;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s_r[threadIdx.x] += s_r[threadIdx.x + off];
+      s_b[threadIdx.x] += s_b[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const long blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
+    partials[2 * blk] = s_r[0];
+    partials[2 * blk + 1] = s_b[0];
+  }
+}
+
+// The FP32R right-hand side and the first residual of the refinement in one
+// pass: b = scale rho on the interior nodes plus, at the grains' CIC nodes,
+// scale (net_g part) for each share in the table's order (the order of the
+// separate grain kernels: by grain, then corner), then r = b - A psi and the
+// block's norm partials, as residual_kernel.  Block (0, 0) also freezes the
+// grains' charges Q_g = net_g w e for the step.  net_g = C_i - C_e.
+__global__ __launch_bounds__(256) void rhs_residual_kernel(
+    const long long* __restrict__ rho, double scale, const GrainShare* __restrict__ tab, int ntab,
+    const unsigned long long* __restrict__ counts, int ng, double we, double* __restrict__ Q,
+    double* __restrict__ b, const double* __restrict__ psi, double* __restrict__ r, int nx,
+    int ny, int K, double* __restrict__ partials) {
+  __shared__ double s_r[256], s_b[256];
+  __shared__ int s_e[2];
+  const long plane = (long)nx * ny;
+  const int pn0 = (int)(blockIdx.x * blockDim.x), k = (int)blockIdx.y;
+  const int pn = pn0 + (int)threadIdx.x;
+  const long i = (long)k * plane + pn;
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int g = (int)threadIdx.x; g < ng; g += (int)blockDim.x)
+      Q[g] = (double)((long long)counts[2 * g + 1] - (long long)counts[2 * g]) * we;
+  if (threadIdx.x < 2) {  // the table's entries of this block's node range
+    const long key = (long)k * plane + pn0 + (threadIdx.x ? (long)blockDim.x : 0);
+    int lo = 0, hi = ntab;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((long)tab[mid].node < key) lo = mid + 1;
+      else hi = mid;
+    }
+    s_e[threadIdx.x] = lo;
+  }
+  __syncthreads();
+  double rr = 0.0, bb = 0.0;
+  if (pn < plane && k < K) {
+    double bi = scale * (double)rho[i + plane];
+    for (int e = s_e[0]; e < s_e[1]; ++e) {
+      const GrainShare t = tab[e];
+      if (t.node != i) continue;
+      const long long net = (long long)counts[2 * t.g + 1] - (long long)counts[2 * t.g];
+      if (net != 0) bi += scale * (double)(net * t.part);
+    }
+    b[i] = bi;
+    const int y = pn / nx, x = pn - y * nx;
+    const long row = i - x, pl = i - (long)y * nx - x;
+    const double c = psi[i];
+    const double xp = psi[row + (x + 1 == nx ? 0 : x + 1)];
+    const double xm = psi[row + (x == 0 ? nx - 1 : x - 1)];
+    const double yp = psi[pl + (long)(y + 1 == ny ? 0 : y + 1) * nx + x];
+    const double ym = psi[pl + (long)(y == 0 ? ny - 1 : y - 1) * nx + x];
+    const double zp = k + 1 < K ? psi[i + plane] : 0.0;
+    const double zm = k > 0 ? psi[i - plane] : 0.0;
+    const double Ax = xp + xm + yp + ym + zp + zm - 6.0 * c;
+    const double ri = bi - Ax;
+    r[i] = ri;
+    rr = ri * ri;
+    bb = bi * bi;
+  }
   s_r[threadIdx.x] = rr;
   s_b[threadIdx.x] = bb;
   __syncthreads();
@@ -1083,11 +1151,12 @@ void launch_solve_f64(const FftPlanHost& P, int nx, int ny, int nz, const double
 void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const double* b,
                           double* psi, double* r, void* work32, const void* tw_x32,
                           const void* tw_y32, const void* inv, RfDrive rf, int sweeps,
-                          double tol, double* norms, int* ctl, hipStream_t st) {
+                          double tol, double* norms, int* ctl, hipStream_t st, bool have_r0) {
   const long plane = (long)nx * ny;
   const int nb = (int)(nb256(plane) * (nz - 1));
-  hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi, b,
-                     r, nx, ny, nz - 1, norms + 2, nullptr);
+  if (!have_r0)
+    hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), nz - 1), dim3(256), 0, st, psi,
+                       b, r, nx, ny, nz - 1, norms + 2, nullptr);
   hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb, norms, ctl,
                      tol * tol, 0, 0);
   for (int it = 1; it <= sweeps; ++it) {
@@ -1100,16 +1169,19 @@ void launch_solve_refined(const FftPlanHost& P, int nx, int ny, int nz, const do
   }
 }
 
+void launch_rhs_residual(const long long* rho, double scale, const GrainShare* tab, int ntab,
+                         const unsigned long long* counts, int ng, double we, double* Q,
+                         double* b, const double* psi, double* r, int nx, int ny, int nz,
+                         double* partials, hipStream_t st) {
+  const long plane = (long)nx * ny;
+  hipLaunchKernelGGL(rhs_residual_kernel, dim3(nb256(plane), nz - 1), dim3(256), 0, st, rho, scale,
+                     tab, ntab, counts, ng, we, Q, b, psi, r, nx, ny, nz - 1, partials);
+}
+
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
                     hipStream_t st) {
   const long plane = (long)nx * ny, n_int = plane * (nz - 1);
   hipLaunchKernelGGL(rhs_f64_kernel, dim3(nb256(n_int)), dim3(256), 0, st, rho, scale, b, plane,
-                     n_int);
-}
-void launch_rhs_fixed(const long long* rho, double scale, double* b, int nx, int ny, int nz,
-                      hipStream_t st) {
-  const long plane = (long)nx * ny, n_int = plane * (nz - 1);
-  hipLaunchKernelGGL(rhs_fixed_kernel, dim3(nb256(n_int)), dim3(256), 0, st, rho, scale, b, plane,
                      n_int);
 }
 

@@ -107,6 +107,8 @@ struct Replica {
   // near-grain tables
   MdTables md{};
   double* d_Q = nullptr;
+  GrainShare* d_gtab = nullptr;  // FP32R: the grains' right-hand-side shares (sorted)
+  int n_gtab = 0;
   // grain counts; event tallies live per chunk in lists[sp].tally
   unsigned long long* d_gc = nullptr;
   int64_t wall_base[2][2]{};  // electrode counts handed over by pic_set_state
@@ -408,6 +410,55 @@ int validate(const pic_config& c, std::string& why) {
   return PIC_OK;
 }
 
+// The FP32R grains' shares of the right-hand side: for each grain its 8 CIC
+// nodes (those on interior planes) and the exact fixed-point split of one
+// macro charge Qp at its offsets, the split the particle deposit makes, sorted
+// by node and then by (grain, corner), the order in which the separate grain
+// kernel adds them.  Each step adds scale (net_g part) at the node.
+std::vector<GrainShare> grain_shares(const Replica& R) {
+  struct Key {
+    long node;
+    int p;
+    GrainShare s;
+  };
+  std::vector<Key> v;
+  const long plane = (long)R.nx * R.ny;
+  for (int g = 0; g < R.cfg.n_grains; ++g) {
+    const double X = R.gpos[3 * g], Y = R.gpos[3 * g + 1], Z = R.gpos[3 * g + 2];
+    const int i0 = (int)std::floor(X), j0 = (int)std::floor(Y), k0 = (int)std::floor(Z);
+    const int i1 = i0 + 1 == R.nx ? 0 : i0 + 1, j1 = j0 + 1 == R.ny ? 0 : j0 + 1;
+    const int ii[2] = {i0, i1}, jj[2] = {j0, j1};
+    const long long qx = (long long)std::floor((X - std::floor(X)) * 16777216.0);
+    const long long qy = (long long)std::floor((Y - std::floor(Y)) * 16777216.0);
+    const long long qz = (long long)std::floor((Z - std::floor(Z)) * 16777216.0);
+    long long part[8], ax[2];
+    ax[1] = (R.Qp * qx) >> 24;
+    ax[0] = R.Qp - ax[1];
+    for (int a = 0; a < 2; ++a) {
+      const long long y1 = (ax[a] * qy) >> 24;
+      const long long yy[2] = {ax[a] - y1, y1};
+      for (int b = 0; b < 2; ++b) {
+        const long long z1 = (yy[b] * qz) >> 24;
+        part[a + 2 * b] = yy[b] - z1;
+        part[a + 2 * b + 4] = z1;
+      }
+    }
+    for (int t = 0; t < 8; ++t) {
+      const int a = t & 1, b = (t >> 1) & 1, c = t >> 2;
+      const long n = ii[a] + (long)R.nx * (jj[b] + (long)R.ny * (k0 + c));
+      const long k = n / plane;
+      if (k < 1 || k > R.nz - 1) continue;
+      v.push_back(Key{n - plane, 8 * g + t, GrainShare{part[t], (int)(n - plane), g}});
+    }
+  }
+  std::sort(v.begin(), v.end(), [](const Key& x, const Key& y) {
+    return x.node != y.node ? x.node < y.node : x.p < y.p;
+  });
+  std::vector<GrainShare> out;
+  for (const Key& k : v) out.push_back(k.s);
+  return out;
+}
+
 int setup_md(pic_ctx* ctx, Replica& R) {
   const pic_config& c = R.cfg;
   const int ng = c.n_grains, cc = c.pp_cutoff_cells;
@@ -482,6 +533,14 @@ int setup_md(pic_ctx* ctx, Replica& R) {
   md.gpos = d_gpos;
   md.gcell = d_gcell;
   md.U = d_U;
+  if (R.prec != PIC_FP64) {
+    const std::vector<GrainShare> tab = grain_shares(R);
+    R.n_gtab = (int)tab.size();
+    TRY(dalloc(ctx, R, &R.d_gtab, std::max<size_t>(tab.size(), 1)));
+    if (!tab.empty())
+      HIPCHK(ctx, hipMemcpy(R.d_gtab, tab.data(), tab.size() * sizeof(GrainShare),
+                            hipMemcpyHostToDevice));
+  }
   return PIC_OK;
 }
 
@@ -678,11 +737,11 @@ int solve_fields(pic_ctx* ctx, Replica& R, bool zero_next = false) {
     launch_field_out(nullptr, R.phi, R.E, 1, next, R.md, R.nx, R.ny, R.nz, c.dx, rf, st);
   } else {
     const double scale = -c.dx * c.dx / kEps0 * (kCharge / 4294967296.0 / vol);
-    launch_rhs_fixed((const long long*)R.rho[R.rho_cur], scale, R.b, R.nx, R.ny, R.nz, st);
-    launch_grain_rhs(R.d_gc, R.md.gpos, c.n_grains, R.nx, R.ny, R.nz, R.we, R.d_Q, R.b, scale, 1,
-                     R.Qp, st);
+    launch_rhs_residual((const long long*)R.rho[R.rho_cur], scale, R.d_gtab, R.n_gtab, R.d_gc,
+                        c.n_grains, R.we, R.d_Q, R.b, R.psi, R.r, R.nx, R.ny, R.nz, R.norms + 2,
+                        st);
     launch_solve_refined(R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y, R.inv,
-                         rf, c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st);
+                         rf, c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st, true);
     launch_field_out(R.psi, R.phi, R.E, 0, next, R.md, R.nx, R.ny, R.nz, c.dx, rf, st);
   }
   CHECK_LAUNCH(ctx);
