@@ -62,6 +62,11 @@ void launch_md_move_f32r(const PartF32R P[2], const PartF32R D[2], const float* 
 void launch_lists_f32r(const PartF32R P[2], const PartF32R D[2], const float* E, long long* rho,
                        const MdTables& md, const SpeciesStep S[2], const WorkLists L[2],
                        int do_mcc, int sp_only, hipStream_t st);
+// all of that for species sp in one launch, its collision candidates included
+// (in place of launch_collide_f32r and launch_lists_f32r for that species)
+void launch_species_lists_f32r(const PartF32R P[2], const PartF32R D[2], const float* E,
+                               long long* rho, const MdTables& md, const SpeciesStep S[2],
+                               const WorkLists L[2], int do_mcc, int sp, hipStream_t st);
 // The fields of a step in one launch: phi (from the refined solve's psi,
 // lifted with the electrode voltages, when psi is given; otherwise phi is read
 // as stored), E = -grad phi into E (FP64 double2 pairs or FP32 float4), the

@@ -1837,16 +1837,11 @@ __global__ __launch_bounds__(256) void fine_moments_kernel(PT P, WorkLists L, Fi
 // The collisions of the MD particles that survived their sub-cycled motion,
 // from their stored velocities (same list, blocks and tally rows as md_kernel).
 template <typename PT>
-__global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> pr, PT D0, PT D1,
-                                                                int commit, int mcc,
-                                                                int sp_only) {
-  // both species (blocks [0, nb) electrons) or species sp_only alone
-  const int sp = sp_only >= 0 ? sp_only : ((int)blockIdx.x >= pr.nb ? 1 : 0);
+__device__ __forceinline__ void md_collide_block(const SpeciesPair<PT>& pr, const PT& D, int sp,
+                                                 int bid, int commit, int mcc) {
   const PT P = pr.P[sp];
-  const PT D = sp ? D1 : D0;
   const SpeciesStep S = pr.S[sp];
   const WorkLists L = pr.L[sp];
-  const int bid = (int)blockIdx.x - (sp_only >= 0 ? 0 : sp * pr.nb);
   const int total = L.cnt[2];
   if ((long)bid * kMdThreads >= total) return;
   int n_coll = 0, n_cap = 0;
@@ -1873,6 +1868,15 @@ __global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> 
     if (n_coll) tally[TL_COLL] += (unsigned long long)n_coll;
     if (n_cap) tally[TL_CAP] += (unsigned long long)n_cap;
   }
+}
+template <typename PT>
+__global__ __launch_bounds__(kMdThreads) void md_collide_kernel(SpeciesPair<PT> pr, PT D0, PT D1,
+                                                                int commit, int mcc,
+                                                                int sp_only) {
+  // both species (blocks [0, nb) electrons) or species sp_only alone
+  const int sp = sp_only >= 0 ? sp_only : ((int)blockIdx.x >= pr.nb ? 1 : 0);
+  const int bid = (int)blockIdx.x - (sp_only >= 0 ? 0 : sp * pr.nb);
+  md_collide_block(pr, sp ? D1 : D0, sp, bid, commit, mcc);
 }
 
 // ---------------------------------------------------------------- MD list
@@ -1950,16 +1954,15 @@ __global__ __launch_bounds__(256) void md_scan_kernel(PartF32R P0, PartF32R P1, 
 // last sort): the same push with the field gathered from global memory and the
 // charge deposited with global atomics, the collision done in place.  One wave
 // per tile segment.
-__global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> pr,
-                                                          const float4* __restrict__ E,
-                                                          long long* __restrict__ rho, int do_mcc,
-                                                          int sp_only) {
-  // both species (blocks [0, nb) electrons) or species sp_only alone
-  const int sp = sp_only >= 0 ? sp_only : ((int)blockIdx.x >= pr.nb ? 1 : 0);
+// the outliers of push block bid of species sp
+__device__ __forceinline__ void outlier_block(const SpeciesPair<PartF32R>& pr,
+                                              const float4* __restrict__ E,
+                                              long long* __restrict__ rho, int do_mcc, int sp,
+                                              int bid) {
   const PartF32R P = pr.P[sp];
   const SpeciesStep S = pr.S[sp];
   const WorkLists L = pr.L[sp];
-  const int tidx = ((int)blockIdx.x - (sp_only >= 0 ? 0 : sp * pr.nb)) * pr.span;
+  const int tidx = bid * pr.span;
   const int count = L.out_cnt[tidx];
   if (count == 0) return;
   if (threadIdx.x == 0) L.stray[tidx] = 1;  // (already set when these left the window)
@@ -2024,6 +2027,14 @@ __global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> 
     tl[TL_DEAD] += t_w0 + t_w1 + t_bad;
     tl[TL_FAST] += t_fast;
   }
+}
+__global__ __launch_bounds__(64) void outlier_f32r_kernel(SpeciesPair<PartF32R> pr,
+                                                          const float4* __restrict__ E,
+                                                          long long* __restrict__ rho, int do_mcc,
+                                                          int sp_only) {
+  // both species (blocks [0, nb) electrons) or species sp_only alone
+  const int sp = sp_only >= 0 ? sp_only : ((int)blockIdx.x >= pr.nb ? 1 : 0);
+  outlier_block(pr, E, rho, do_mcc, sp, (int)blockIdx.x - (sp_only >= 0 ? 0 : sp * pr.nb));
 }
 
 __global__ __launch_bounds__(64) void outlier_f64_kernel(SpeciesPair<PartF64> pr,
@@ -2092,8 +2103,8 @@ __global__ __launch_bounds__(64) void outlier_f64_kernel(SpeciesPair<PartF64> pr
 // One wave per push block's segment of collision candidates (the push block
 // of `span` tiles lists them at its first tile).
 template <typename PT>
-__global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLists L, int span) {
-  const int tidx = (int)blockIdx.x * span;
+__device__ __forceinline__ void collide_block(const PT& P, const SpeciesStep& S, const WorkLists& L,
+                                              int tidx) {
   const int count = L.coll_cnt[tidx];
   if (count == 0) return;
   const int32_t* seg = L.coll + L.tstart[tidx];
@@ -2114,8 +2125,33 @@ __global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLi
   n_coll = wave_sum(n_coll);
   n_cap = wave_sum(n_cap);
   if (threadIdx.x == 0) {
-    L.tally[(long)TL_N * tidx + TL_COLL] += (unsigned long long)n_coll;
-    L.tally[(long)TL_N * tidx + TL_CAP] += (unsigned long long)n_cap;
+    unsigned long long* tl = L.tally + (long)TL_N * tidx;
+    tl[TL_COLL] += (unsigned long long)n_coll;
+    tl[TL_CAP] += (unsigned long long)n_cap;
+  }
+}
+template <typename PT>
+__global__ __launch_bounds__(64) void collide_kernel(PT P, SpeciesStep S, WorkLists L, int span) {
+  collide_block(P, S, L, (int)blockIdx.x * span);
+}
+
+// Everything after one FP32R species' push in one launch: block b < npb takes
+// push block b's collision candidates and then its outliers (disjoint sets of
+// particles, one tally row), and the kMdListBlocks blocks after those copy the
+// MD particles' states back and collide them.
+constexpr int kMdListBlocks = 512;
+__global__ __launch_bounds__(64) void species_lists_f32r_kernel(SpeciesPair<PartF32R> pr,
+                                                                PartF32R D, const float4* E,
+                                                                long long* rho, int do_mcc, int sp,
+                                                                int npb, int md) {
+  const int b = (int)blockIdx.x;
+  if (b < npb) {
+    collide_block(pr.P[sp], pr.S[sp], pr.L[sp], b * pr.span);
+    outlier_block(pr, E, rho, do_mcc, sp, b);
+  } else if (md) {
+    SpeciesPair<PartF32R> pm = pr;
+    pm.nb = kMdListBlocks;  // the blocks' stride over the MD list (tally rows 0 .. 511)
+    md_collide_block(pm, D, sp, b - npb, 1, do_mcc);
   }
 }
 
@@ -2846,6 +2882,17 @@ void launch_md_move_f32r(const PartF32R P[2], const PartF32R D[2], const float* 
   SpeciesPair<PartF32R> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, kMdBlocks, push_span(L[0])};
   hipLaunchKernelGGL((md_kernel<PartF32R, float4, long long>), dim3(2 * kMdBlocks),
                      dim3(kMdThreads), 0, st, pr, D[0], D[1], (const float4*)E, rho, md, gc);
+}
+
+void launch_species_lists_f32r(const PartF32R P[2], const PartF32R D[2], const float* E,
+                               long long* rho, const MdTables& md, const SpeciesStep S[2],
+                               const WorkLists L[2], int do_mcc, int sp, hipStream_t st) {
+  if (L[0].ngrid <= 0) return;
+  const int span = push_span(L[0]), npb = L[0].ngrid / span;
+  SpeciesPair<PartF32R> pr{{P[0], P[1]}, {S[0], S[1]}, {L[0], L[1]}, npb, span};
+  const int md_on = md.n_grains > 0 ? 1 : 0;
+  hipLaunchKernelGGL(species_lists_f32r_kernel, dim3(npb + md_on * kMdListBlocks), dim3(64), 0,
+                     st, pr, D[sp], (const float4*)E, rho, do_mcc, sp, npb, md_on);
 }
 
 void launch_lists_f32r(const PartF32R P[2], const PartF32R D[2], const float* E, long long* rho,

@@ -992,12 +992,12 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
       launch_push_f32r(P[sp], (const float*)R.E, (long long*)R.rho[rnx], R.md, S[sp], R.lists[sp],
                        ss);
       hipEvent_t b = prof_event(ctx);
-      launch_collide_f32r(P[sp], S[sp], R.lists[sp], ss);
-      // this species' outliers, and its MD particles' states back (once the
-      // MD kernel is done), while the other species may still stream
+      // this species' collisions, outliers, and MD particles' states back
+      // (once the MD kernel is done) in one launch, while the other species
+      // may still stream
       TRY(md_wait(ctx, mdf, ss));
-      launch_lists_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.lists,
-                        do_mcc, sp, ss);
+      launch_species_lists_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.lists,
+                                do_mcc, sp, ss);
       prof_pair(ctx, PIC_PROF_PUSH, a, b);
       prof_pair(ctx, PIC_PROF_LISTS, b, prof_event(ctx));
     }
