@@ -103,12 +103,13 @@ __device__ __forceinline__ void wave_run(int cell, int& head, int& len) {
 }
 
 // A block per tile of the particle bins: an LDS histogram of the tile's cells
-// (one atomic per run of equal cells in a wave), then one global atomic per
-// cell; a run of particles that have left the tile since the last binning
-// adds itself.
+// (one atomic per run of equal cells in a wave), kept in thist for the
+// scatter, then one global atomic per cell; a run of particles that have left
+// the tile since the last binning adds itself.
 template <typename PT>
 __global__ __launch_bounds__(256) void coul_count_kernel(PT P, WorkLists L,
-                                                         int* __restrict__ cnt) {
+                                                         int* __restrict__ cnt,
+                                                         int* __restrict__ thist) {
   __shared__ int h[64];
   for (int t = blockIdx.x; t < L.ngrid; t += gridDim.x) {
     if (threadIdx.x < 64) h[threadIdx.x] = 0;
@@ -127,7 +128,10 @@ __global__ __launch_bounds__(256) void coul_count_kernel(PT P, WorkLists L,
         atomicAdd(&cnt[c], len);
     }
     __syncthreads();
-    if (threadIdx.x < 64 && h[threadIdx.x] > 0) atomicAdd(&cnt[64 * t + threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < 64) {
+      thist[64 * t + threadIdx.x] = h[threadIdx.x];
+      if (h[threadIdx.x] > 0) atomicAdd(&cnt[64 * t + threadIdx.x], h[threadIdx.x]);
+    }
     __syncthreads();
   }
 }
@@ -194,33 +198,24 @@ __global__ __launch_bounds__(256) void coul_scan_add(int* __restrict__ a, long n
 }
 
 // (order key, slot) of every particle into its cell's range, a block per
-// tile: the tile's histogram again, one atomic per cell reserves the tile's
-// run of each cell, LDS atomics (one per run of equal cells in a wave) place
-// the particles in it; particles that have left the tile reserve their own
-// places.
+// tile: the tile's histogram (from the counting kernel), one atomic per cell
+// reserves the tile's run of each cell, LDS atomics (one per run of equal
+// cells in a wave) place the particles in it; particles that have left the
+// tile reserve their own places.
 template <typename PT>
 __global__ __launch_bounds__(256) void coul_scatter_kernel(PT P, WorkLists L, CoulombConst C,
                                                            int sp, const int* __restrict__ start,
                                                            int* __restrict__ fill,
+                                                           const int* __restrict__ thist,
                                                            unsigned long long* __restrict__ key,
                                                            int* __restrict__ slot) {
   __shared__ int h[64], at[64];
   const uint32_t k = *C.step;
   for (int t = blockIdx.x; t < L.ngrid; t += gridDim.x) {
-    if (threadIdx.x < 64) h[threadIdx.x] = 0;
-    __syncthreads();
     const long p0 = L.tstart[t], p1 = L.tstart[t + 1];
     const int lane = (int)(threadIdx.x & 63);
-    for (long base = p0 + (threadIdx.x & ~63); base < p1; base += 256) {
-      const long p = base + lane;
-      const int c = p < p1 ? coul_cell(P, p, L.ntx, L.nty) : -1;
-      int head, len;
-      wave_run(c, head, len);
-      if (head == lane && c >= 0 && (c >> 6) == t) atomicAdd(&h[c & 63], len);
-    }
-    __syncthreads();
     if (threadIdx.x < 64) {
-      const int c = 64 * t + threadIdx.x, n = h[threadIdx.x];
+      const int c = 64 * t + threadIdx.x, n = thist[c];
       at[threadIdx.x] = n > 0 ? start[c] + atomicAdd(&fill[c], n) : 0;
       h[threadIdx.x] = 0;
     }
@@ -605,7 +600,8 @@ void coulomb_impl(const PT P[2], const WorkLists L[2], const CoulombBufs& B, con
     launch_zero_i32(B.fill[s], ncell, st);
     const int g = std::min(L[s].ngrid, 65536);
     if (cap[s] > 0 && g > 0)
-      hipLaunchKernelGGL(coul_count_kernel<PT>, dim3(g), dim3(256), 0, st, P[s], L[s], B.start[s]);
+      hipLaunchKernelGGL(coul_count_kernel<PT>, dim3(g), dim3(256), 0, st, P[s], L[s], B.start[s],
+                         B.thist[s]);
     const long n = ncell + 1;
     const int nb = nblk(n, kScanChunk);
     hipLaunchKernelGGL(coul_scan_local, dim3(nb), dim3(256), 0, st, B.start[s], n, B.sums);
@@ -613,7 +609,7 @@ void coulomb_impl(const PT P[2], const WorkLists L[2], const CoulombBufs& B, con
     hipLaunchKernelGGL(coul_scan_add, dim3(nb), dim3(256), 0, st, B.start[s], n, B.sums);
     if (cap[s] > 0 && g > 0)
       hipLaunchKernelGGL(coul_scatter_kernel<PT>, dim3(g), dim3(256), 0, st, P[s], L[s], C, s,
-                         B.start[s], B.fill[s], B.key[s], B.slot[s]);
+                         B.start[s], B.fill[s], B.thist[s], B.key[s], B.slot[s]);
   }
   const long ngroup = (ncell + kGroup - 1) / kGroup;
   const int grid = (int)((ngroup + kRunGroups - 1) / kRunGroups);

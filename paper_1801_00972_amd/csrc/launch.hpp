@@ -98,12 +98,14 @@ void launch_fine_moments(const PartF64* P64, const PartF32R* P32, const WorkList
                          hipStream_t st);
 // Coulomb collisions (coulomb.hip).  Work buffers of a replica: per species
 // the per-cell counts turned into range starts [ncell + 1], fill cursors
-// [ncell], the (order key, slot) entries [cap] and the slots in key order
-// [cap]; the scan's block sums [coulomb_scan_sums(ncell)]; the pairings
-// performed (accumulated).
+// [ncell], each tile's own particles per cell [ncell] (the counting kernel's
+// histograms, for the scatter), the (order key, slot) entries [cap] and the
+// slots in key order [cap]; the scan's block sums [coulomb_scan_sums(ncell)];
+// the pairings performed (accumulated).
 struct CoulombBufs {
   int* start[2];
   int* fill[2];
+  int* thist[2];
   unsigned long long* key[2];
   int* slot[2];
   int* ord[2];

@@ -1530,6 +1530,7 @@ int init_replica(pic_ctx* ctx, Replica& R, const pic_config& cin) {
       // cells in the tile order of the particle bins, 64 a tile
       TRY(dalloc(ctx, R, &R.coul.start[sp], 64L * R.ngrid + 1));
       TRY(dalloc(ctx, R, &R.coul.fill[sp], 64L * R.ngrid));
+      TRY(dalloc(ctx, R, &R.coul.thist[sp], 64L * R.ngrid));
       TRY(dalloc(ctx, R, &R.coul.key[sp], R.cap[sp]));
       TRY(dalloc(ctx, R, &R.coul.slot[sp], R.cap[sp]));
       TRY(dalloc(ctx, R, &R.coul.ord[sp], R.cap[sp]));
