@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -1243,13 +1244,47 @@ int capture_step(pic_ctx* ctx, int key) {
   return PIC_OK;
 }
 
-// the species whose sort falls due at the end of the next step
-int due_sorts(const pic_ctx* ctx) {
+// the species whose sort falls due at the end of the next step, given the
+// steps since each species' last sort
+int sorts_due(const pic_ctx* ctx, const int since[2]) {
   const int iv[2] = {ctx->tune.sort_interval, ctx->tune.ion_sort_interval};
   int sorts = 0;
   for (int sp = 0; sp < 2; ++sp)
-    if (iv[sp] > 0 && ctx->since_sort[sp] + 1 >= iv[sp]) sorts |= 1 << sp;
+    if (iv[sp] > 0 && since[sp] + 1 >= iv[sp]) sorts |= 1 << sp;
   return sorts;
+}
+int due_sorts(const pic_ctx* ctx) { return sorts_due(ctx, ctx->since_sort); }
+
+// The graph keys of the coming steps in the order they fall due, from the
+// host state as it is: buffer phases, sorts and samples run ahead (as
+// step_all and advance_host move them) over four periods of the schedule,
+// which covers every key it reaches.
+std::vector<int> upcoming_keys(const pic_ctx* ctx) {
+  const Replica& R = *ctx->reps[0];
+  int cur[2] = {R.cur[0], R.cur[1]}, rho = R.rho_cur;
+  int since[2] = {ctx->since_sort[0], ctx->since_sort[1]}, since_avg = ctx->since_avg;
+  long period = 2;
+  for (int v : {ctx->tune.sort_interval, ctx->tune.ion_sort_interval, ctx->avg_interval})
+    if (v > 1 && period < (1L << 20)) period = std::lcm(period, (long)v);
+  const long n = 4 * std::min(period, 1L << 20);
+  std::vector<int> keys;
+  bool seen[64] = {};
+  for (long t = 0; t < n; ++t) {
+    const int sorts = sorts_due(ctx, since);
+    const int sample = ctx->avg_interval > 0 && since_avg == 0;
+    const int key = (cur[0] | (cur[1] << 1) | (rho << 2)) | (sorts << 3) | (sample << 5);
+    if (!seen[key]) {
+      seen[key] = true;
+      keys.push_back(key);
+    }
+    rho = 1 - rho;
+    for (int sp = 0; sp < 2; ++sp) {
+      if (sorts & (1 << sp)) cur[sp] = 1 - cur[sp];
+      since[sp] = (sorts & (1 << sp)) ? 0 : since[sp] + 1;
+    }
+    if (ctx->avg_interval > 0) since_avg = (since_avg + 1) % ctx->avg_interval;
+  }
+  return keys;
 }
 
 // one step of every replica: direct launches when profiling (the events must
@@ -1271,8 +1306,11 @@ int step_all(pic_ctx* ctx) {
     const int key = phase_of(*ctx->reps[0]) | (sorts << 3) | (sample << 5);
     if (!ctx->graph[key]) {
       // the capture stream is not ordered after the caller's stream: the
-      // graph's first launch must not overtake work queued there
+      // graph's first launch must not overtake work queued there.  Every
+      // key the schedule will reach is captured now, so that later steps
+      // neither wait for the stream to drain nor for a capture.
       HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      for (int k : upcoming_keys(ctx)) TRY(capture_step(ctx, k));
       TRY(capture_step(ctx, key));
     }
     if (timed) HIPCHK(ctx, hipEventRecord((*ev)[ctx->step_ev_used], ctx->stream));
