@@ -186,6 +186,24 @@ void launch_rhs_residual(const long long* rho, double scale, const GrainShare* t
                          const unsigned long long* counts, int ng, double we, double* Q,
                          double* b, const double* psi, double* r, int nx, int ny, int nz,
                          double* partials, hipStream_t st);
+// the arguments of the FP32R right-hand side (launch_rhs_residual's)
+struct RhsArgs {
+  const long long* rho;
+  double scale;
+  const GrainShare* tab;
+  int ntab;
+  const unsigned long long* counts;
+  int ng;
+  double we;
+  double* Q;
+};
+// launch_rhs_residual + launch_solve_refined(..., have_r0 = true) in fewer
+// kernels where the plane transforms fit in LDS (same phi, psi and Q; the
+// norms' partial sums are grouped differently)
+void launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, int ny, int nz,
+                              double* b, double* psi, double* r, void* work32,
+                              const void* tw_x32, const void* tw_y32, const void* inv, RfDrive rf,
+                              int sweeps, double tol, double* norms, int* ctl, hipStream_t st);
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
                     hipStream_t st);
 void launch_grain_rhs(const unsigned long long* counts, const double* gpos, int ng, int nx, int ny,

@@ -275,6 +275,106 @@ __global__ __launch_bounds__(kPlaneThreads) void fft_plane_kernel(Fft2Geom g, co
   }
 }
 
+// The refinement's residual r = b - A psi of one interior plane formed where
+// the plane transform loads its input, then the forward 2-D transform of r
+// into work, as fft_plane_kernel<T, IN_REAL, OUT_COMPLEX> does after a
+// separate residual pass (the same r in FP64, the same rounding to T; r is
+// not stored).  The plane's sums of r^2 and b^2 go to partials[2 k],
+// partials[2 k + 1], added in a fixed order (per wave, then the waves in
+// turn).  With kRhs the kernel forms b first, as rhs_residual_kernel does
+// (scale rho plus the grains' shares in the table's order; block 0 freezes
+// Q_g), and stores it; otherwise it reads b.
+template <typename T, bool kRhs>
+__global__ __launch_bounds__(kPlaneThreads) void residual_fft_kernel(
+    Fft2Geom g, const cplx<T>* __restrict__ tw_x, const cplx<T>* __restrict__ tw_y,
+    cplx<T>* __restrict__ work, const double* __restrict__ psi, double* __restrict__ b, RhsArgs a,
+    double* __restrict__ partials, const int* __restrict__ skip) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double s_r[kPlaneThreads / 64], s_b[kPlaneThreads / 64];
+  __shared__ int s_e[2];
+  if (skip && *skip) return;  // a refinement sweep after convergence
+  const int nx = g.nx, ny = g.ny, np = nx * ny;
+  const int K = (int)gridDim.x;
+  C* b0 = reinterpret_cast<C*>(smem_raw);
+  C* b1 = b0 + np;
+  const int k = blockIdx.x;
+  const long pbase = (long)k * np;
+  if (kRhs) {
+    if (k == 0)
+      for (int q = (int)threadIdx.x; q < a.ng; q += (int)blockDim.x)
+        a.Q[q] = (double)((long long)a.counts[2 * q + 1] - (long long)a.counts[2 * q]) * a.we;
+    if (threadIdx.x < 2) {  // the table's entries of this plane
+      const long key = pbase + (threadIdx.x ? (long)np : 0);
+      int lo = 0, hi = a.ntab;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((long)a.tab[mid].node < key) lo = mid + 1;
+        else hi = mid;
+      }
+      s_e[threadIdx.x] = lo;
+    }
+    __syncthreads();
+  }
+  double rr = 0.0, bb = 0.0;
+  for (int pn = (int)threadIdx.x; pn < np; pn += kPlaneThreads) {
+    const long i = pbase + pn;
+    double bi;
+    if (kRhs) {
+      bi = a.scale * (double)a.rho[i + np];
+      for (int e = s_e[0]; e < s_e[1]; ++e) {
+        const GrainShare t = a.tab[e];
+        if (t.node != i) continue;
+        const long long net = (long long)a.counts[2 * t.g + 1] - (long long)a.counts[2 * t.g];
+        if (net != 0) bi += a.scale * (double)(net * t.part);
+      }
+      b[i] = bi;
+    } else {
+      bi = b[i];
+    }
+    const int y = pn / nx, x = pn - y * nx;
+    const long row = i - x, pl = i - (long)y * nx - x;
+    const double c = psi[i];
+    const double xp = psi[row + (x + 1 == nx ? 0 : x + 1)];
+    const double xm = psi[row + (x == 0 ? nx - 1 : x - 1)];
+    const double yp = psi[pl + (long)(y + 1 == ny ? 0 : y + 1) * nx + x];
+    const double ym = psi[pl + (long)(y == 0 ? ny - 1 : y - 1) * nx + x];
+    const double zp = k + 1 < K ? psi[i + np] : 0.0;
+    const double zm = k > 0 ? psi[i - np] : 0.0;
+    const double Ax = xp + xm + yp + ym + zp + zm - 6.0 * c;
+    const double ri = bi - Ax;
+    rr += ri * ri;
+    bb += bi * bi;
+    C v;
+    v.x = (T)ri;
+    v.y = (T)0;
+    b0[pn] = v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    rr += __shfl_xor(rr, off, 64);
+    bb += __shfl_xor(bb, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_r[threadIdx.x >> 6] = rr;
+    s_b[threadIdx.x >> 6] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sr = 0.0, sb = 0.0;
+    for (int w = 0; w < kPlaneThreads / 64; ++w) {
+      sr += s_r[w];
+      sb += s_b[w];
+    }
+    partials[2 * k] = sr;
+    partials[2 * k + 1] = sb;
+  }
+  C* res = fft_stages(b0, b1, nx, ny, nx, 1, g.fx, g.nfx, tw_x, true);
+  C* other = res == b0 ? b1 : b0;
+  res = fft_stages(res, other, ny, nx, 1, nx, g.fy, g.nfy, tw_y, true);
+  for (int i = (int)threadIdx.x; i < np; i += kPlaneThreads) work[pbase + i] = res[i];
+}
+
 // ---------------------------------------------------------------- tridiagonal, chunked
 // The two sweeps of the tridiagonal solve as first-order affine recurrences,
 // each split into kTriChunks chunks along z per mode:
@@ -1176,6 +1276,63 @@ void launch_rhs_residual(const long long* rho, double scale, const GrainShare* t
   const long plane = (long)nx * ny;
   hipLaunchKernelGGL(rhs_residual_kernel, dim3(nb256(plane), nz - 1), dim3(256), 0, st, rho, scale,
                      tab, ntab, counts, ng, we, Q, b, psi, r, nx, ny, nz - 1, partials);
+}
+
+// The FP32R field solve from the fixed-point charge: the right-hand side and
+// the refinement of launch_rhs_residual + launch_solve_refined(have_r0).
+// When two planes fit in LDS the residual before each sweep but the last is
+// formed inside the sweep's forward plane transform (the first one also forms
+// b), so the sweep runs transform, tridiagonal, inverse transform; the
+// residual after the last sweep has its own kernel.  The stopping test is the
+// same, with the per-plane partial sums of those fused kernels.
+void launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, int ny, int nz,
+                              double* b, double* psi, double* r, void* work32,
+                              const void* tw_x32, const void* tw_y32, const void* inv, RfDrive rf,
+                              int sweeps, double tol, double* norms, int* ctl, hipStream_t st) {
+  using C = cplx<float>;
+  const long plane = (long)nx * ny;
+  const int K = nz - 1;
+  if (2 * sizeof(C) * (size_t)plane > kPlaneLds) {
+    launch_rhs_residual(a.rho, a.scale, a.tab, a.ntab, a.counts, a.ng, a.we, a.Q, b, psi, r, nx,
+                        ny, nz, norms + 2, st);
+    launch_solve_refined(P, nx, ny, nz, b, psi, r, work32, tw_x32, tw_y32, inv, rf, sweeps, tol,
+                         norms, ctl, st, true);
+    return;
+  }
+  Fft2Geom g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nfx = P.nfac_x;
+  g.nfy = P.nfac_y;
+  for (int i = 0; i < 12; ++i) {
+    g.fx[i] = P.fac_x[i];
+    g.fy[i] = P.fac_y[i];
+  }
+  const size_t lds = 2 * sizeof(C) * (size_t)plane;
+  const C* tx = (const C*)tw_x32;
+  const C* ty = (const C*)tw_y32;
+  C* w = (C*)work32;
+  const int nb = (int)(nb256(plane) * K);
+  hipLaunchKernelGGL((residual_fft_kernel<float, true>), dim3(K), dim3(kPlaneThreads), lds, st, g,
+                     tx, ty, w, psi, b, a, norms + 2, nullptr);
+  hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, K, norms, ctl,
+                     tol * tol, 0, 0);
+  for (int it = 1; it <= sweeps; ++it) {
+    tridiag_launch<float>(work32, inv, K, plane, st, ctl);
+    fft_plane_launch<float>(P, nx, ny, K, tw_x32, tw_y32, 0, IN_COMPLEX, OUT_REAL_ACCUM, work32,
+                            nullptr, psi, 1.0 / (double)plane, rf, nz, st, ctl);
+    if (it < sweeps) {
+      hipLaunchKernelGGL((residual_fft_kernel<float, false>), dim3(K), dim3(kPlaneThreads), lds,
+                         st, g, tx, ty, w, psi, b, a, norms + 2, ctl);
+      hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, K, norms, ctl,
+                         tol * tol, it, 0);
+    } else {
+      hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), K), dim3(256), 0, st, psi, b,
+                         r, nx, ny, K, norms + 2, ctl);
+      hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb, norms,
+                         ctl, tol * tol, it, 1);
+    }
+  }
 }
 
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,

@@ -738,11 +738,10 @@ int solve_fields(pic_ctx* ctx, Replica& R, bool zero_next = false) {
     launch_field_out(nullptr, R.phi, R.E, 1, next, R.md, R.nx, R.ny, R.nz, c.dx, rf, st);
   } else {
     const double scale = -c.dx * c.dx / kEps0 * (kCharge / 4294967296.0 / vol);
-    launch_rhs_residual((const long long*)R.rho[R.rho_cur], scale, R.d_gtab, R.n_gtab, R.d_gc,
-                        c.n_grains, R.we, R.d_Q, R.b, R.psi, R.r, R.nx, R.ny, R.nz, R.norms + 2,
-                        st);
-    launch_solve_refined(R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y, R.inv,
-                         rf, c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st, true);
+    const RhsArgs ra{(const long long*)R.rho[R.rho_cur], scale, R.d_gtab, R.n_gtab, R.d_gc,
+                     c.n_grains, R.we, R.d_Q};
+    launch_rhs_solve_refined(ra, R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y,
+                             R.inv, rf, c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st);
     launch_field_out(R.psi, R.phi, R.E, 0, next, R.md, R.nx, R.ny, R.nz, c.dx, rf, st);
   }
   CHECK_LAUNCH(ctx);
