@@ -146,6 +146,7 @@ struct pic_ctx {
   // FP32R MD particles beside the field solve and the push (one replica)
   hipStream_t md_stream = nullptr;
   hipEvent_t md_fork = nullptr, md_join = nullptr;
+  hipEvent_t md_scanned = nullptr, md_fields = nullptr;
   // replicas stepped one by one are spread over worker streams (default
   // priority), forked from and joined back into the caller's stream
   std::vector<hipStream_t> workers;
@@ -189,6 +190,8 @@ struct pic_ctx {
     if (md_stream) (void)hipStreamDestroy(md_stream);
     if (md_fork) (void)hipEventDestroy(md_fork);
     if (md_join) (void)hipEventDestroy(md_join);
+    if (md_scanned) (void)hipEventDestroy(md_scanned);
+    if (md_fields) (void)hipEventDestroy(md_fields);
     for (hipStream_t w : workers) (void)hipStreamDestroy(w);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
@@ -897,12 +900,13 @@ int species_join(pic_ctx* ctx, bool forked) {
 }
 
 // The FP32R MD particles of a one-replica step on a stream of their own:
-// md_fork once the fields (and any Coulomb pass) are in place, so their list
-// forms and their sub-cycled motion runs beside the pushes; md_done marks the
-// end of that work, which each species' stream waits for before its lists
-// kernels copy the states back.  (The list's scan, run beside the
-// latency-bound field kernels instead, slowed those by more than it costs the
-// streaming pushes.)  *forked tells whether ctx->md_stream is used.
+// md_fork at the start of the step, where their list is scanned beside the
+// field solve from the cells the previous step left (the pushes, which
+// rewrite the cells in place, wait for the scan: md_scanned); their sub-cycled
+// motion follows once the fields (and any Coulomb pass) are in place
+// (md_fields) and runs beside the pushes; md_done marks the end of that work,
+// which each species' stream waits for before its lists kernels copy the
+// states back.  *forked tells whether ctx->md_stream is used.
 int md_fork(pic_ctx* ctx, bool* forked) {
   *forked = ctx->reps.size() == 1 && !ctx->prof;
   if (!*forked) return PIC_OK;
@@ -910,6 +914,8 @@ int md_fork(pic_ctx* ctx, bool* forked) {
     HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->md_stream, hipStreamNonBlocking));
     HIPCHK(ctx, hipEventCreateWithFlags(&ctx->md_fork, hipEventDisableTiming));
     HIPCHK(ctx, hipEventCreateWithFlags(&ctx->md_join, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->md_scanned, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->md_fields, hipEventDisableTiming));
   }
   HIPCHK(ctx, hipEventRecord(ctx->md_fork, ctx->stream));
   HIPCHK(ctx, hipStreamWaitEvent(ctx->md_stream, ctx->md_fork, 0));
@@ -938,6 +944,21 @@ static void f32_buffers(const Replica& R, PartF32R P[2], PartF32R D[2]) {
 // start of the step (buffer phases); advance_host then moves the host mirrors
 int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   hipStream_t st = ctx->stream;
+  // FP32R: the MD list scan must read the particles' cells as the previous
+  // step left them (the pushes rewrite them in place).  With the MD stream it
+  // runs first, beside the field solve, and the pushes wait for it; otherwise
+  // it runs in line before them.
+  bool mdf = false;
+  if (R.prec != PIC_FP64) {
+    TRY(md_fork(ctx, &mdf));
+    if (mdf) {
+      PartF32R P[2], D[2];
+      f32_buffers(R, P, D);
+      const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
+      launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ctx->md_stream);
+      HIPCHK(ctx, hipEventRecord(ctx->md_scanned, ctx->md_stream));
+    }
+  }
   hipEvent_t f0 = prof_event(ctx);
   TRY(solve_fields(ctx, R, true));
   if (sample) TRY(enqueue_sample(ctx, R));
@@ -974,12 +995,17 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   } else {
     PartF32R P[2], D[2];
     f32_buffers(R, P, D);
-    bool mdf = false;
-    TRY(md_fork(ctx, &mdf));
     {
       hipStream_t ms = mdf ? ctx->md_stream : st;
+      if (mdf) {
+        // the MD kernel needs the fields (and any Coulomb pass); the pushes
+        // need the scan done
+        HIPCHK(ctx, hipEventRecord(ctx->md_fields, st));
+        HIPCHK(ctx, hipStreamWaitEvent(ms, ctx->md_fields, 0));
+        HIPCHK(ctx, hipStreamWaitEvent(st, ctx->md_scanned, 0));
+      }
       hipEvent_t m0 = prof_event(ctx);
-      launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ms);
+      if (!mdf) launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ms);
       launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc,
                           R.lists, ms);
       TRY(md_done(ctx, mdf));
@@ -1076,6 +1102,14 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   const Replica& R0 = *ctx->reps[0];
   hipEvent_t f0 = prof_event(ctx);
   TRY(for_replicas(ctx, [&](Replica& R) -> int {
+    // the MD list scan reads the cells as the previous step left them: on the
+    // replica's worker stream, joined before the push launch
+    {
+      PartF32R P[2], D[2];
+      f32_buffers(R, P, D);
+      const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
+      launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ctx->stream);
+    }
     TRY(solve_fields(ctx, R, true));
     if (sample) TRY(enqueue_sample(ctx, R));
     if (coulomb_due(R)) TRY(enqueue_coulomb(ctx, R));
@@ -1083,7 +1117,7 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
   }));
   CHECK_LAUNCH(ctx);
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
-  // every replica's MD particles on the worker streams beside the one push
+  // every replica's MD kernel on the worker streams beside the one push
   // launch (enqueued first, so their waves are resident before the push's
   // blocks fill the rest; the push's items are dealt dynamically)
   TRY(for_replicas(
@@ -1092,7 +1126,6 @@ int enqueue_batch(pic_ctx* ctx, int sorts, int sample) {
         PartF32R P[2], D[2];
         f32_buffers(R, P, D);
         const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
-        launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ctx->stream);
         launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[1 - R.rho_cur], R.md, S,
                             R.d_gc, R.lists, ctx->stream);
         return PIC_OK;
