@@ -199,11 +199,18 @@ struct RhsArgs {
 };
 // launch_rhs_residual + launch_solve_refined(..., have_r0 = true) in fewer
 // kernels where the plane transforms fit in LDS (same phi, psi and Q; the
-// norms' partial sums are grouped differently)
-void launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, int ny, int nz,
-                              double* b, double* psi, double* r, void* work32,
-                              const void* tw_x32, const void* tw_y32, const void* inv, RfDrive rf,
-                              int sweeps, double tol, double* norms, int* ctl, hipStream_t st);
+// norms' partial sums are grouped differently).  With defer_final the
+// residual after the last sweep and its test are left to the caller where that
+// path applies (returns 1; launch_refine_final), else returns 0.
+int launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, int ny, int nz,
+                             double* b, double* psi, double* r, void* work32,
+                             const void* tw_x32, const void* tw_y32, const void* inv, RfDrive rf,
+                             int sweeps, double tol, double* norms, int* ctl, hipStream_t st,
+                             bool defer_final);
+// the residual after the last of `sweeps` refinement sweeps and its stopping
+// test (norms, ctl as launch_solve_refined); psi and b unchanged since the solve
+void launch_refine_final(int nx, int ny, int nz, const double* b, const double* psi, double* r,
+                         int sweeps, double tol, double* norms, int* ctl, hipStream_t st);
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,
                     hipStream_t st);
 void launch_grain_rhs(const unsigned long long* counts, const double* gpos, int ng, int nx, int ny,

@@ -1278,17 +1278,22 @@ void launch_rhs_residual(const long long* rho, double scale, const GrainShare* t
                      tab, ntab, counts, ng, we, Q, b, psi, r, nx, ny, nz - 1, partials);
 }
 
+void launch_refine_final(int nx, int ny, int nz, const double* b, const double* psi, double* r,
+                         int sweeps, double tol, double* norms, int* ctl, hipStream_t st);
+
 // The FP32R field solve from the fixed-point charge: the right-hand side and
 // the refinement of launch_rhs_residual + launch_solve_refined(have_r0).
 // When two planes fit in LDS the residual before each sweep but the last is
 // formed inside the sweep's forward plane transform (the first one also forms
 // b), so the sweep runs transform, tridiagonal, inverse transform; the
-// residual after the last sweep has its own kernel.  The stopping test is the
-// same, with the per-plane partial sums of those fused kernels.
-void launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, int ny, int nz,
-                              double* b, double* psi, double* r, void* work32,
-                              const void* tw_x32, const void* tw_y32, const void* inv, RfDrive rf,
-                              int sweeps, double tol, double* norms, int* ctl, hipStream_t st) {
+// residual after the last sweep has its own kernel (launch_refine_final; with
+// defer_final the caller launches it, and 1 is returned).  The stopping test
+// is the same, with the per-plane partial sums of those fused kernels.
+int launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, int ny, int nz,
+                             double* b, double* psi, double* r, void* work32,
+                             const void* tw_x32, const void* tw_y32, const void* inv, RfDrive rf,
+                             int sweeps, double tol, double* norms, int* ctl, hipStream_t st,
+                             bool defer_final) {
   using C = cplx<float>;
   const long plane = (long)nx * ny;
   const int K = nz - 1;
@@ -1297,7 +1302,7 @@ void launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, in
                         ny, nz, norms + 2, st);
     launch_solve_refined(P, nx, ny, nz, b, psi, r, work32, tw_x32, tw_y32, inv, rf, sweeps, tol,
                          norms, ctl, st, true);
-    return;
+    return 0;
   }
   Fft2Geom g{};
   g.nx = nx;
@@ -1312,7 +1317,6 @@ void launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, in
   const C* tx = (const C*)tw_x32;
   const C* ty = (const C*)tw_y32;
   C* w = (C*)work32;
-  const int nb = (int)(nb256(plane) * K);
   hipLaunchKernelGGL((residual_fft_kernel<float, true>), dim3(K), dim3(kPlaneThreads), lds, st, g,
                      tx, ty, w, psi, b, a, norms + 2, nullptr);
   hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, K, norms, ctl,
@@ -1326,13 +1330,26 @@ void launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, in
                          st, g, tx, ty, w, psi, b, a, norms + 2, ctl);
       hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, K, norms, ctl,
                          tol * tol, it, 0);
-    } else {
-      hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), K), dim3(256), 0, st, psi, b,
-                         r, nx, ny, K, norms + 2, ctl);
-      hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb, norms,
-                         ctl, tol * tol, it, 1);
+    } else if (!defer_final) {
+      launch_refine_final(nx, ny, nz, b, psi, r, sweeps, tol, norms, ctl, st);
     }
   }
+  return defer_final ? 1 : 0;
+}
+
+// the residual after the last sweep and its stopping test (the reported
+// residual and the count of solves that ended above the tolerance); psi and b
+// stay as the solve left them until the next solve, so this may run on
+// another stream beside the work that follows the solve
+void launch_refine_final(int nx, int ny, int nz, const double* b, const double* psi, double* r,
+                         int sweeps, double tol, double* norms, int* ctl, hipStream_t st) {
+  const long plane = (long)nx * ny;
+  const int K = nz - 1;
+  const int nb = (int)(nb256(plane) * K);
+  hipLaunchKernelGGL(residual_kernel<true>, dim3(nb256(plane), K), dim3(256), 0, st, psi, b, r,
+                     nx, ny, K, norms + 2, ctl);
+  hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, nb, norms, ctl,
+                     tol * tol, sweeps, 1);
 }
 
 void launch_rhs_f64(const double* rho, double scale, double* b, int nx, int ny, int nz,

@@ -725,7 +725,11 @@ int deposit_current(pic_ctx* ctx, Replica& R) {
 // phi_k and E_k from rho_k, the grains' charges and V(t_k); also freezes Q_g.
 // zero_next: the same launch clears the other charge accumulator for the
 // step's deposit of rho_{k+1}
-int solve_fields(pic_ctx* ctx, Replica& R, bool zero_next = false) {
+// final_pending (FP32R): when given, the residual after the last refinement
+// sweep and its test may be left to the caller (*final_pending tells), who
+// launches them with launch_refine_final on another stream
+int solve_fields(pic_ctx* ctx, Replica& R, bool zero_next = false,
+                 bool* final_pending = nullptr) {
   hipStream_t st = ctx->stream;
   const pic_config& c = R.cfg;
   const RfDrive rf{c.V_dc, c.V_rf, c.f_rf, c.dt, R.d_step};
@@ -743,8 +747,10 @@ int solve_fields(pic_ctx* ctx, Replica& R, bool zero_next = false) {
     const double scale = -c.dx * c.dx / kEps0 * (kCharge / 4294967296.0 / vol);
     const RhsArgs ra{(const long long*)R.rho[R.rho_cur], scale, R.d_gtab, R.n_gtab, R.d_gc,
                      c.n_grains, R.we, R.d_Q};
-    launch_rhs_solve_refined(ra, R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y,
-                             R.inv, rf, c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st);
+    const int deferred = launch_rhs_solve_refined(
+        ra, R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y, R.inv, rf,
+        c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st, final_pending != nullptr);
+    if (final_pending) *final_pending = deferred != 0;
     launch_field_out(R.psi, R.phi, R.E, 0, next, R.md, R.nx, R.ny, R.nz, c.dx, rf, st);
   }
   CHECK_LAUNCH(ctx);
@@ -960,7 +966,10 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
     }
   }
   hipEvent_t f0 = prof_event(ctx);
-  TRY(solve_fields(ctx, R, true));
+  // with the MD stream, the refinement's last residual and test go there too
+  // (nothing in the step reads them), off the path to the pushes
+  bool fin = false;
+  TRY(solve_fields(ctx, R, true, mdf ? &fin : nullptr));
   if (sample) TRY(enqueue_sample(ctx, R));
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
   if (coulomb_due(R)) {
@@ -1004,6 +1013,9 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
         HIPCHK(ctx, hipStreamWaitEvent(ms, ctx->md_fields, 0));
         HIPCHK(ctx, hipStreamWaitEvent(st, ctx->md_scanned, 0));
       }
+      if (fin)
+        launch_refine_final(R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.cfg.max_refine,
+                            R.cfg.refine_tol, R.norms, R.refine_ctl, ms);
       hipEvent_t m0 = prof_event(ctx);
       if (!mdf) launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ms);
       launch_md_move_f32r(P, D, (const float*)R.E, (long long*)R.rho[rnx], R.md, S, R.d_gc,
