@@ -201,12 +201,14 @@ struct RhsArgs {
 // kernels where the plane transforms fit in LDS (same phi, psi and Q; the
 // norms' partial sums are grouped differently).  With defer_final the
 // residual after the last sweep and its test are left to the caller where that
-// path applies (returns 1; launch_refine_final), else returns 0.
+// path applies (returns 1; launch_refine_final), else returns 0.  first_done
+// (may be null) is recorded on st after the right-hand side's kernel; -1 if
+// that record fails.
 int launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, int ny, int nz,
                              double* b, double* psi, double* r, void* work32,
                              const void* tw_x32, const void* tw_y32, const void* inv, RfDrive rf,
                              int sweeps, double tol, double* norms, int* ctl, hipStream_t st,
-                             bool defer_final);
+                             bool defer_final, hipEvent_t first_done);
 // the residual after the last of `sweeps` refinement sweeps and its stopping
 // test (norms, ctl as launch_solve_refined); psi and b unchanged since the solve
 void launch_refine_final(int nx, int ny, int nz, const double* b, const double* psi, double* r,

@@ -1289,17 +1289,20 @@ void launch_refine_final(int nx, int ny, int nz, const double* b, const double* 
 // residual after the last sweep has its own kernel (launch_refine_final; with
 // defer_final the caller launches it, and 1 is returned).  The stopping test
 // is the same, with the per-plane partial sums of those fused kernels.
+// first_done, when given, is recorded on st after the first kernel (the one
+// that reads rho and the grains' counts); -1 if that record fails.
 int launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, int ny, int nz,
                              double* b, double* psi, double* r, void* work32,
                              const void* tw_x32, const void* tw_y32, const void* inv, RfDrive rf,
                              int sweeps, double tol, double* norms, int* ctl, hipStream_t st,
-                             bool defer_final) {
+                             bool defer_final, hipEvent_t first_done) {
   using C = cplx<float>;
   const long plane = (long)nx * ny;
   const int K = nz - 1;
   if (2 * sizeof(C) * (size_t)plane > kPlaneLds) {
     launch_rhs_residual(a.rho, a.scale, a.tab, a.ntab, a.counts, a.ng, a.we, a.Q, b, psi, r, nx,
                         ny, nz, norms + 2, st);
+    if (first_done && hipEventRecord(first_done, st) != hipSuccess) return -1;
     launch_solve_refined(P, nx, ny, nz, b, psi, r, work32, tw_x32, tw_y32, inv, rf, sweeps, tol,
                          norms, ctl, st, true);
     return 0;
@@ -1319,6 +1322,7 @@ int launch_rhs_solve_refined(const RhsArgs& a, const FftPlanHost& P, int nx, int
   C* w = (C*)work32;
   hipLaunchKernelGGL((residual_fft_kernel<float, true>), dim3(K), dim3(kPlaneThreads), lds, st, g,
                      tx, ty, w, psi, b, a, norms + 2, nullptr);
+  if (first_done && hipEventRecord(first_done, st) != hipSuccess) return -1;
   hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(1024), 0, st, norms + 2, K, norms, ctl,
                      tol * tol, 0, 0);
   for (int it = 1; it <= sweeps; ++it) {

@@ -727,9 +727,11 @@ int deposit_current(pic_ctx* ctx, Replica& R) {
 // step's deposit of rho_{k+1}
 // final_pending (FP32R): when given, the residual after the last refinement
 // sweep and its test may be left to the caller (*final_pending tells), who
-// launches them with launch_refine_final on another stream
+// launches them with launch_refine_final on another stream.  first_done
+// (FP32R, may be null): recorded on the stream after the right-hand side's
+// kernel, so that other work can start beside the rest of the solve.
 int solve_fields(pic_ctx* ctx, Replica& R, bool zero_next = false,
-                 bool* final_pending = nullptr) {
+                 bool* final_pending = nullptr, hipEvent_t first_done = nullptr) {
   hipStream_t st = ctx->stream;
   const pic_config& c = R.cfg;
   const RfDrive rf{c.V_dc, c.V_rf, c.f_rf, c.dt, R.d_step};
@@ -749,7 +751,9 @@ int solve_fields(pic_ctx* ctx, Replica& R, bool zero_next = false,
                      c.n_grains, R.we, R.d_Q};
     const int deferred = launch_rhs_solve_refined(
         ra, R.fft, R.nx, R.ny, R.nz, R.b, R.psi, R.r, R.work, R.tw_x, R.tw_y, R.inv, rf,
-        c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st, final_pending != nullptr);
+        c.max_refine, c.refine_tol, R.norms, R.refine_ctl, st, final_pending != nullptr,
+        first_done);
+    if (deferred < 0) return fail(ctx, PIC_EDEVICE, "event record in the field solve failed");
     if (final_pending) *final_pending = deferred != 0;
     launch_field_out(R.psi, R.phi, R.E, 0, next, R.md, R.nx, R.ny, R.nz, c.dx, rf, st);
   }
@@ -905,15 +909,16 @@ int species_join(pic_ctx* ctx, bool forked) {
   return PIC_OK;
 }
 
-// The FP32R MD particles of a one-replica step on a stream of their own:
-// md_fork at the start of the step, where their list is scanned beside the
-// field solve from the cells the previous step left (the pushes, which
-// rewrite the cells in place, wait for the scan: md_scanned); their sub-cycled
-// motion follows once the fields (and any Coulomb pass) are in place
-// (md_fields) and runs beside the pushes; md_done marks the end of that work,
-// which each species' stream waits for before its lists kernels copy the
-// states back.  *forked tells whether ctx->md_stream is used.
-int md_fork(pic_ctx* ctx, bool* forked) {
+// The FP32R MD particles of a one-replica step on a stream of their own
+// (md_streams makes the stream and its events): md_fork, recorded after the
+// field solve's first kernel, starts the scan of their list beside the rest of
+// the solve from the cells the previous step left (the pushes, which rewrite
+// the cells in place, wait for the scan: md_scanned); their sub-cycled motion
+// follows once the fields (and any Coulomb pass) are in place (md_fields) and
+// runs beside the pushes; md_done marks the end of that work, which each
+// species' stream waits for before its lists kernels copy the states back.
+// *forked tells whether ctx->md_stream is used.
+int md_streams(pic_ctx* ctx, bool* forked) {
   *forked = ctx->reps.size() == 1 && !ctx->prof;
   if (!*forked) return PIC_OK;
   if (!ctx->md_stream) {
@@ -923,8 +928,6 @@ int md_fork(pic_ctx* ctx, bool* forked) {
     HIPCHK(ctx, hipEventCreateWithFlags(&ctx->md_scanned, hipEventDisableTiming));
     HIPCHK(ctx, hipEventCreateWithFlags(&ctx->md_fields, hipEventDisableTiming));
   }
-  HIPCHK(ctx, hipEventRecord(ctx->md_fork, ctx->stream));
-  HIPCHK(ctx, hipStreamWaitEvent(ctx->md_stream, ctx->md_fork, 0));
   return PIC_OK;
 }
 int md_done(pic_ctx* ctx, bool forked) {
@@ -955,21 +958,22 @@ int enqueue_step(pic_ctx* ctx, Replica& R, int sorts, int sample) {
   // runs first, beside the field solve, and the pushes wait for it; otherwise
   // it runs in line before them.
   bool mdf = false;
-  if (R.prec != PIC_FP64) {
-    TRY(md_fork(ctx, &mdf));
-    if (mdf) {
-      PartF32R P[2], D[2];
-      f32_buffers(R, P, D);
-      const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
-      launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ctx->md_stream);
-      HIPCHK(ctx, hipEventRecord(ctx->md_scanned, ctx->md_stream));
-    }
-  }
+  if (R.prec != PIC_FP64) TRY(md_streams(ctx, &mdf));
   hipEvent_t f0 = prof_event(ctx);
   // with the MD stream, the refinement's last residual and test go there too
-  // (nothing in the step reads them), off the path to the pushes
+  // (nothing in the step reads them), off the path to the pushes.  The scan
+  // starts once the solve's first kernel is done (md_fork): beside the large
+  // plane-transform blocks of that kernel its blocks slowed it by half.
   bool fin = false;
-  TRY(solve_fields(ctx, R, true, mdf ? &fin : nullptr));
+  TRY(solve_fields(ctx, R, true, mdf ? &fin : nullptr, mdf ? ctx->md_fork : nullptr));
+  if (mdf) {
+    PartF32R P[2], D[2];
+    f32_buffers(R, P, D);
+    const SpeciesStep S[2] = {species_step(R, 0), species_step(R, 1)};
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->md_stream, ctx->md_fork, 0));
+    launch_md_scan_f32r(P, R.lists, R.md, S, R.nx, R.ny, R.nz, ctx->md_stream);
+    HIPCHK(ctx, hipEventRecord(ctx->md_scanned, ctx->md_stream));
+  }
   if (sample) TRY(enqueue_sample(ctx, R));
   prof_pair(ctx, PIC_PROF_FIELD, f0, prof_event(ctx));
   if (coulomb_due(R)) {
